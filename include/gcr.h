@@ -1,0 +1,260 @@
+/*
+ * gcr.h -- C-ABI of the MI355X ghost-cell reconstruction library (libgcr.so).
+ *
+ * The library implements the direct, non-iterative ghost-cell method of
+ * Rapaka, Jagad, Addad & Riahi ("Stable, Compact, and Direct Ghost-Cell
+ * Reconstruction"): it tags ghost cells on a Cartesian grid cut by an
+ * embedded body (classical CGC, extended-stencil CGC_ES and hybrid HGC;
+ * Sec. 3.1 and Sec. 7), orders them by the levels of their dependency graph
+ * (Sec. 3.2), fills them level by level with the analytical Dirichlet and
+ * Neumann relations (Sec. 4 and Sec. 5), and evaluates boundary values,
+ * gradients and forces from the same polynomials (Sec. 6).
+ *
+ * Conventions shared by every call
+ *  - Cells are cell-centred: cell (i,j,k) has centre lo + (idx + 1/2) h per
+ *    axis and linear index i + n[0]*(j + n[1]*k) (x fastest).  A grid holds
+ *    fewer than 2^31 cells.
+ *  - Fields are dense FP64 arrays in that layout, one device pointer per field.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are host memory owned by the caller.  The library keeps no
+ *    reference to caller memory after a call returns.
+ *  - `stream` is a hipStream_t (NULL: the null stream).  Every call that
+ *    launches work is asynchronous on that stream, except gcr_plan_create
+ *    and gcr_batch_create, which synchronise it once to size the plan.
+ *  - Every call returns GCR_OK or an error code; gcr_status_str() names it.
+ *    Geometry and graph errors are detected when a plan is built; apply
+ *    calls fail only on bad arguments or HIP errors.  On error nothing the
+ *    caller owns has been modified, except by already-enqueued work of the
+ *    same call for GCR_E_HIP.
+ *  - Ghost-indexed arrays use the canonical order: level ascending, linear
+ *    index ascending inside a level (Sec. 3.2: cells of one level are
+ *    independent, so the order inside a level is free; this one is fixed).
+ */
+#ifndef GCR_H
+#define GCR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GCR_OK = 0,
+  GCR_E_ARG = 1,         /* invalid argument (null, size, range, dimension) */
+  GCR_E_HIP = 2,         /* a HIP runtime call failed */
+  GCR_E_NOMEM = 3,       /* device or host allocation failed */
+  GCR_E_CYCLE = 4,       /* a coupled unit of the ghost graph is too large */
+  GCR_E_STENCIL = 5,     /* a stencil point leaves the grid or is a solid cell;
+                            or a query point has no ghost within 2 cells */
+  GCR_E_DEGENERATE = 6,  /* zero denominator in a relation */
+  GCR_E_GEOMETRY = 7,    /* closest-point projection did not converge */
+  GCR_E_UNSUPPORTED = 8  /* size or combination not supported */
+} gcr_status;
+
+/* Ghost placement (Sec. 3.1, Sec. 7.2). */
+typedef enum { GCR_CGC = 0, GCR_CGC_ES = 1, GCR_HGC = 2 } gcr_scheme;
+
+/* Boundary-condition kind per field (Sec. 4.1, 5.1).  GCR_MIXED: a per-ghost
+ * uint8 array (0 Dirichlet, 1 Neumann) is supplied. */
+typedef enum { GCR_DIRICHLET = 0, GCR_NEUMANN = 1, GCR_MIXED = 2 } gcr_bc;
+
+/* Body kinds. */
+typedef enum {
+  GCR_SPHERE = 0,   /* circle (2D) or sphere (3D), radius r0 about center */
+  GCR_STAR2D = 1,   /* r(t) = r0 (1 + sum_k A_k cos kt + B_k sin kt);
+                       coef = {A_0,B_0,A_1,B_1,...}, ncoef = number of k     */
+  GCR_SHSTAR = 2,   /* r(w) = r0 (1 + sum_lm a_lm Y_lm(w)), real Schmidt
+                       semi-normalised harmonics, no Condon-Shortley phase;
+                       coef[l*l + l + m], ncoef = (L+1)^2, L <= 8            */
+  GCR_AIRFOIL = 3   /* symmetric four-digit section: thickness ratio
+                       `thickness`, chord `chord`, leading edge at center,
+                       nose-up incidence `incidence` (radians), closed
+                       trailing edge                                         */
+} gcr_shape_kind;
+
+typedef struct {
+  int32_t dim;     /* 2 or 3 */
+  int32_t pad;
+  int64_t n[3];    /* cells per axis (n[2] ignored in 2D) */
+  double lo[3];    /* lower corner */
+  double h[3];     /* uniform spacing per axis, > 0 */
+} gcr_grid;
+
+typedef struct {
+  int32_t kind;            /* gcr_shape_kind */
+  int32_t ncoef;
+  double center[3];
+  double r0;
+  const double* coef;      /* host; copied by the library */
+  double chord, thickness, incidence;
+} gcr_shape;
+
+typedef struct gcr_plan gcr_plan;
+typedef struct gcr_batch gcr_batch;
+
+typedef struct {
+  int32_t dim;
+  int32_t n_levels;            /* depth of the (condensed) dependency graph */
+  int64_t n_cells;
+  int64_t n_interface;         /* cells with a face neighbour of the other class */
+  int64_t n_ghost;
+  int64_t n_ghost_fluid_side;  /* HGC ghosts with fluid centres (tag -2) */
+  int32_t n_units_coupled;     /* strongly connected groups of >1 ghost */
+  int32_t max_unit;            /* their largest size (0 if none) */
+  int32_t max_level_width;     /* largest level */
+  int32_t schedule;            /* fill schedule in use, see gcr_set_schedule */
+  double max_alpha[3];         /* max (x_s - x_1)/(x_2 - x_1) per axis (Sec. 8) */
+} gcr_stats;
+
+/* Builds the plan of one grid + body + scheme: classification (Sec. 3.1,
+ * cell centres, psi >= 0 solid), ghost tags, foot points S = x_c + psi n with
+ * the analytic outward normal at the closest boundary point, stencil
+ * multipliers (Eq. stencil_anisotropic for CGC_ES), the ghost dependency
+ * graph and its Kahn levels (Sec. 3.2).  Where the graph is not acyclic
+ * (concave bodies), each strongly connected group of ghosts forms one unit
+ * whose relations are solved together; units have at most 16 ghosts, else
+ * GCR_E_CYCLE.  grid, shape: host.  Synchronises `stream`.  The plan owns
+ * all its device memory; *out is NULL on error. */
+gcr_status gcr_plan_create(const gcr_grid* grid, const gcr_shape* shape,
+                           int32_t scheme, void* stream, gcr_plan** out);
+void gcr_plan_destroy(gcr_plan* plan);
+
+/* Host copy of the plan's sizes and statistics. */
+gcr_status gcr_plan_stats(const gcr_plan* plan, gcr_stats* out);
+
+/* Level offsets into the canonical ghost order, host array [n_levels + 1]. */
+gcr_status gcr_plan_level_offsets(const gcr_plan* plan, int32_t* out);
+
+/* Device copies of the plan (any pointer may be NULL):
+ *   tags     int8  [n_cells]  0 fluid, 1 solid, +2 / -2 ghost (Sec. 3.1)
+ *   cell     int32 [n_ghost]  linear index of each ghost
+ *   level    int32 [n_ghost]  1-based level
+ *   delta    f64 [dim][n_ghost] x_s - x_c
+ *   normal   f64 [dim][n_ghost] unit normal into the fluid at S
+ *   psi      f64 [n_ghost]    signed distance (Eq. signed_distance)
+ *   r        int32 [dim][n_ghost] stencil multipliers
+ *   unit     int32 [n_ghost]  canonical position of the unit's first ghost,
+ *                             or -1 for a ghost that is its own unit */
+gcr_status gcr_plan_export(const gcr_plan* plan, int8_t* tags, int32_t* cell,
+                           int32_t* level, double* delta, double* normal,
+                           double* psi, int32_t* r, int32_t* unit, void* stream);
+
+/* Fill schedule.  0 = automatic (tuned), 1 = one launch per level,
+ * 2 = one workgroup sweeping all levels, 3 = per-level launches captured in a
+ * HIP graph and replayed.  `param` is reserved (0). */
+gcr_status gcr_set_schedule(gcr_plan* plan, int32_t schedule, int32_t param);
+
+/* Level-by-level ghost fill (Sec. 3.2 with Eqs. phi_G_Dir_2d, phi_G_Neu_2d,
+ * phi_G_Dir_3d, phi_G_Neu_3d).  nf fields, 1 <= nf <= 8:
+ *   fields   host array [nf] of device f64 [n_cells], in/out: ghost slots are
+ *            overwritten; every other cell is read only.
+ *   bc_kind  host int32 [nf]: gcr_bc per field.
+ *   bc_type  host array [nf] of device uint8 [n_ghost] (0/1), read only for
+ *            fields with GCR_MIXED; may be NULL if no field is mixed.
+ *   bc_val   host array [nf] of device f64 [n_ghost]: phi at S (Dirichlet) or
+ *            dphi/dn at S (Neumann), canonical ghost order. */
+gcr_status gcr_fill(const gcr_plan* plan, int32_t nf, double* const* fields,
+                    const int32_t* bc_kind, const uint8_t* const* bc_type,
+                    const double* const* bc_val, void* stream);
+
+/* Value and Cartesian gradient of each ghost's reconstruction polynomial at
+ * its foot point S (Sec. 6; Eqs. derivative_bilinear, derivative_trilinear_*).
+ *   fields   host array [nf] of device f64 [n_cells] (filled)
+ *   val      device f64 [nf][n_ghost]         (may be NULL)
+ *   grad     device f64 [nf][dim][n_ghost]    (may be NULL) */
+gcr_status gcr_surface_ghost(const gcr_plan* plan, int32_t nf,
+                             const double* const* fields, double* val,
+                             double* grad, void* stream);
+
+/* The same at caller points xq (device f64 [dim][nq]): each point is served
+ * by its anchor ghost, the ghost within 2 cells per axis of the point's cell
+ * whose S is nearest (ties: smaller linear index).
+ *   val [nf][nq], grad [nf][dim][nq], anchor int32 [nq] (canonical position);
+ *   any output may be NULL.  GCR_E_STENCIL is not reported for points
+ *   without an anchor: their outputs are NaN and anchor -1. */
+gcr_status gcr_surface(const gcr_plan* plan, int64_t nq, const double* xq,
+                       int32_t nf, const double* const* fields, double* val,
+                       double* grad, int32_t* anchor, void* stream);
+
+/* Force on the body, F = sum_q w_q (-p n_q + mu (grad u + grad u^T) n_q)
+ * (Sec. 6: pressure and wall stress from the boundary values and gradients).
+ *   xq, nrm  device f64 [dim][nq]: points and outward unit normals
+ *   wq       device f64 [nq]: quadrature weights
+ *   p        device f64 [n_cells] (filled); u: host array [dim] of device
+ *            f64 [n_cells] (filled velocity components)
+ *   F        device f64 [dim].  Deterministic (fixed reduction order). */
+gcr_status gcr_forces(const gcr_plan* plan, int64_t nq, const double* xq,
+                      const double* nrm, const double* wq, const double* p,
+                      const double* const* u, double mu, double* F,
+                      void* stream);
+
+/* Adjoint of gcr_surface: lam[f] (device f64 [n_cells]) += (d outputs /
+ * d filled field)^T (gval [nf][nq], ggrad [nf][dim][nq]; either may be NULL).
+ * Deterministic. */
+gcr_status gcr_surface_adjoint(const gcr_plan* plan, int64_t nq,
+                               const double* xq, int32_t nf,
+                               const double* gval, const double* ggrad,
+                               double* const* lam, void* stream);
+
+/* Adjoint of gcr_forces for the functional J = gF . F (gF device f64 [dim]):
+ * lam_p += dJ/dp, lam_u[i] += dJ/du_i (device f64 [n_cells] each). */
+gcr_status gcr_forces_adjoint(const gcr_plan* plan, int64_t nq,
+                              const double* xq, const double* nrm,
+                              const double* wq, double mu, const double* gF,
+                              double* lam_p, double* const* lam_u,
+                              void* stream);
+
+/* Adjoint of gcr_fill: the levels in reverse.  lam[f] (device f64 [n_cells])
+ * holds dJ/d(filled field) on entry and dJ/d(input field) on return (zero in
+ * ghost slots, whose inputs the fill overwrites); lam_bc[f] (device f64
+ * [n_ghost]) receives dJ/d(bc_val).  bc_kind / bc_type as in gcr_fill.
+ * Deterministic: every cell is written by one thread, sums in fixed order. */
+gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf,
+                            double* const* lam, const int32_t* bc_kind,
+                            const uint8_t* const* bc_type,
+                            double* const* lam_bc, void* stream);
+
+/* Batched plans: ninst instances of uneven size built by shared launches.
+ * grids, shapes, schemes: host arrays [ninst].  Synchronises once. */
+gcr_status gcr_batch_create(int32_t ninst, const gcr_grid* grids,
+                            const gcr_shape* shapes, const int32_t* schemes,
+                            void* stream, gcr_batch** out);
+void gcr_batch_destroy(gcr_batch* batch);
+/* Plan of instance i, owned by the batch (valid until gcr_batch_destroy). */
+gcr_status gcr_batch_plan(const gcr_batch* batch, int32_t i,
+                          const gcr_plan** out);
+
+/* Batched forward in one persistent launch: for every instance, fill its nf
+ * fields, then (if nq != NULL) the force on its body from field p_field
+ * (pressure) and the dim fields u_first.. (velocity).  Host arrays of device
+ * pointers are instance-major, [ninst * nf]:
+ *   fields, bc_val, bc_type (bc_type may be NULL);  bc_kind host [nf].
+ *   nq host int64 [ninst]; xq, nrm, wq host [ninst] device pointers;
+ *   F device f64 [ninst][3] (unused components zero). */
+gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
+                             double* const* fields, const int32_t* bc_kind,
+                             const uint8_t* const* bc_type,
+                             const double* const* bc_val, const int64_t* nq,
+                             const double* const* xq, const double* const* nrm,
+                             const double* const* wq, int32_t p_field,
+                             int32_t u_first, double mu, double* F,
+                             void* stream);
+
+/* Stage timing of plan building.  When on (process-wide), gcr_plan_create
+ * and gcr_batch_create record HIP events on their stream around each stage;
+ * gcr_last_build_times copies the device times in milliseconds of the last
+ * build on the calling thread into ms[8]: [0] classification, [1] interface
+ * scan, [2] interface compaction, [3] geometry and ghost tags, [4] ghost
+ * compaction, [5] stencils and dependencies, [6] levels and canonical order,
+ * [7] finalize.  Off by default (no events recorded). */
+gcr_status gcr_set_profiling(int32_t on);
+gcr_status gcr_last_build_times(float* ms);
+
+const char* gcr_status_str(gcr_status s);
+const char* gcr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCR_H */

@@ -194,6 +194,52 @@ static dual shstar_radius(const orc_shape* s, const double v[3]) {
   return dscale(sum, s->r0);
 }
 
+/* r(omega) alone: the same recurrences in plain doubles (the value parts of
+ * the dual-number operations above are these very operations). */
+static double sh_value(int l, int m, const double v[3]) {
+  int am = m < 0 ? -m : m;
+  double rho = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double t = v[2] / rho, ux = v[0] / rho, uy = v[1] / rho;
+  double dfact = 1.0;
+  for (int i = 1; i <= 2 * am - 1; i += 2) dfact *= (double)i;
+  double p;
+  if (l == am) {
+    p = dfact;
+  } else {
+    double pm1 = (t * dfact) * (double)(2 * am + 1);
+    if (l == am + 1) {
+      p = pm1;
+    } else {
+      double a = dfact, b = pm1;
+      for (int ll = am + 2; ll <= l; ++ll) {
+        double c = ((t * b) * (double)(2 * ll - 1) - a * (double)(ll + am - 1)) *
+                   (1.0 / (double)(ll - am));
+        a = b; b = c;
+      }
+      p = b;
+    }
+  }
+  double re = 1.0, im = 0.0;
+  for (int i = 0; i < am; ++i) {
+    double nre = re * ux - im * uy;
+    double nim = re * uy + im * ux;
+    re = nre; im = nim;
+  }
+  double N = (am == 0) ? 1.0 : sqrt(2.0 * factorial(l - am) / factorial(l + am));
+  return (p * (m >= 0 ? re : im)) * N;
+}
+
+static double shstar_radius_value(const orc_shape* s, const double v[3]) {
+  int L = (int)floor(sqrt((double)s->ncoef) + 1e-9) - 1;
+  double sum = 1.0;
+  for (int l = 0; l <= L; ++l)
+    for (int m = -l; m <= l; ++m) {
+      double a = s->coef[l * l + l + m];
+      if (a != 0.0) sum = sum + sh_value(l, m, v) * a;
+    }
+  return sum * s->r0;
+}
+
 /* 2D star: r(theta), r'(theta), r''(theta). */
 static void star_radius(const orc_shape* s, double th, double* r, double* r1,
                         double* r2) {
@@ -293,7 +339,14 @@ static int inside_q(const orc_shape* s, int dim, const double* x, double* q) {
     star_radius(s, atan2(v[1], v[0]), &r, &r1, &r2);
   } else {
     if (rho == 0.0) { *q = s->r0; return 1; }
-    r = shstar_radius(s, v).v;
+    /* |Y_lm| <= 1 for Schmidt semi-normalised harmonics, so r lies within
+     * r0 (1 -+ sum |a_lm|): far cells are settled without evaluating r */
+    double sa = 0.0;
+    for (int i = 0; i < s->ncoef; ++i) sa += fabs(s->coef[i]);
+    double rmax = s->r0 * (1.0 + sa), rmin = s->r0 * (1.0 - sa);
+    if (rho > rmax) { *q = rmax - rho; return 0; }
+    if (rho < rmin) { *q = rmin - rho; return 1; }
+    r = shstar_radius_value(s, v);
   }
   *q = r - rho;
   return *q >= 0.0;
@@ -461,9 +514,10 @@ int orc_shape_project(const orc_shape* s, int dim, const double* x, int solid,
       nb[0] = b[0] - X[0]; nb[1] = b[1] - X[1];
       if (solid) { nb[0] = -nb[0]; nb[1] = -nb[1]; }
     } else {
-      /* contour runs lower TE -> LE -> upper TE (s increasing), so the
-       * outward normal is the tangent turned clockwise                     */
-      nb[0] = D1[1]; nb[1] = -D1[0];
+      /* the contour runs lower TE -> LE -> upper TE as s increases, i.e.
+       * clockwise, so the outward normal is the tangent turned
+       * counter-clockwise                                                  */
+      nb[0] = -D1[1]; nb[1] = D1[0];
     }
     normalize(nb, 2);
     double w[2], Sb[2] = {X[0], X[1]}, Sw[2];

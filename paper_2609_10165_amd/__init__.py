@@ -1,0 +1,352 @@
+"""Ghost-cell reconstruction on MI355X: Python binding of libgcr.so.
+
+Argument marshalling only -- every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and streams.  The names follow
+the C-ABI in ``include/gcr.h`` (``gcr_plan_create`` -> ``Plan(...)``,
+``gcr_fill`` -> ``Plan.fill`` ...).  There is no fallback: if the library is
+missing, importing works but every call raises ``GcrError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libgcr.so")
+
+CGC, CGC_ES, HGC = 0, 1, 2
+DIRICHLET, NEUMANN, MIXED = 0, 1, 2
+SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
+SCHED_AUTO, SCHED_LEVELS, SCHED_WORKGROUP, SCHED_GRAPH = 0, 1, 2, 3
+SYMBOLS = [
+    "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
+    "gcr_plan_export", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
+    "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
+    "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_forward",
+    "gcr_set_profiling", "gcr_last_build_times", "gcr_status_str", "gcr_version",
+]
+
+
+class GcrError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = _lib.gcr_status_str(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
+                ("h", ctypes.c_double * 3)]
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ncoef", ctypes.c_int32),
+                ("center", ctypes.c_double * 3), ("r0", ctypes.c_double),
+                ("coef", ctypes.POINTER(ctypes.c_double)),
+                ("chord", ctypes.c_double), ("thickness", ctypes.c_double),
+                ("incidence", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("n_cells", ctypes.c_int64), ("n_interface", ctypes.c_int64),
+                ("n_ghost", ctypes.c_int64), ("n_ghost_fluid_side", ctypes.c_int64),
+                ("n_units_coupled", ctypes.c_int32), ("max_unit", ctypes.c_int32),
+                ("max_level_width", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("max_alpha", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgcr.so (raises GcrError-like OSError if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"libgcr.so not built ({LIB_PATH}); run paper_2609_10165_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        L.gcr_status_str.restype = ctypes.c_char_p
+        L.gcr_status_str.argtypes = [ctypes.c_int]
+        L.gcr_version.restype = ctypes.c_char_p
+        L.gcr_plan_create.argtypes = [P(_Grid), P(_Shape), i32, vp, P(vp)]
+        L.gcr_plan_destroy.argtypes = [vp]
+        L.gcr_plan_destroy.restype = None
+        L.gcr_plan_stats.argtypes = [vp, P(_Stats)]
+        L.gcr_plan_level_offsets.argtypes = [vp, vp]
+        L.gcr_plan_export.argtypes = [vp] + [vp] * 8 + [vp]
+        L.gcr_set_schedule.argtypes = [vp, i32, i32]
+        L.gcr_fill.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.gcr_surface_ghost.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.gcr_surface.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp]
+        L.gcr_forces.argtypes = [vp, i64, vp, vp, vp, vp, vp, dbl, vp, vp]
+        L.gcr_surface_adjoint.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp]
+        L.gcr_forces_adjoint.argtypes = [vp, i64, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.gcr_fill_adjoint.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.gcr_batch_create.argtypes = [i32, P(_Grid), P(_Shape), vp, vp, P(vp)]
+        L.gcr_batch_destroy.argtypes = [vp]
+        L.gcr_batch_destroy.restype = None
+        L.gcr_batch_plan.argtypes = [vp, i32, P(vp)]
+        L.gcr_set_profiling.argtypes = [i32]
+        L.gcr_last_build_times.argtypes = [vp]
+        L.gcr_batch_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl,
+                                        vp, vp]
+        for name in SYMBOLS:
+            getattr(L, name)
+            if getattr(L, name).restype is ctypes.c_int and name not in ("gcr_status_str",):
+                pass
+        _lib = L
+    return _lib
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise GcrError(code, what)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t: Optional[torch.Tensor], dtype=torch.float64) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor, got {t.dtype} "
+                         f"on {t.device} (contiguous={t.is_contiguous()})")
+    return t.data_ptr()
+
+
+def _ptr_array(ts, dtype=torch.float64):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _dptr(t, dtype)
+    return arr
+
+
+def make_grid(grid) -> _Grid:
+    g = _Grid()
+    g.dim = int(grid.dim)
+    for i in range(3):
+        g.n[i] = int(grid.n[i]) if i < grid.dim else 1
+        g.lo[i] = float(grid.lo[i]) if i < grid.dim else 0.0
+        g.h[i] = float(grid.h[i]) if i < grid.dim else 1.0
+    return g
+
+
+def make_shape(shape):
+    """Returns the ctypes shape and the coefficient buffer it points into."""
+    s = _Shape()
+    s.kind = int(shape.kind)
+    coef = [float(v) for v in getattr(shape, "coef", [])]
+    buf = (ctypes.c_double * max(1, len(coef)))(*coef) if coef else None
+    s.ncoef = int(getattr(shape, "ncoef", 0))
+    for i in range(3):
+        s.center[i] = float(shape.center[i]) if i < len(shape.center) else 0.0
+    s.r0 = float(getattr(shape, "r0", 0.0))
+    s.coef = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double)) if buf is not None else None
+    s.chord = float(getattr(shape, "chord", 1.0))
+    s.thickness = float(getattr(shape, "thick", getattr(shape, "thickness", 0.12)))
+    s.incidence = float(getattr(shape, "incidence", 0.0))
+    return s, buf
+
+
+class Plan:
+    """gcr_plan_create: ghost tags, levels and geometry of one grid + body."""
+
+    def __init__(self, grid, shape, scheme: int, stream=None, _handle=None, _owner=None):
+        L = lib()
+        self._owner = _owner
+        if _handle is not None:
+            self._h = _handle
+        else:
+            g = make_grid(grid)
+            s, keep = make_shape(shape)
+            h = ctypes.c_void_p()
+            _check(L.gcr_plan_create(ctypes.byref(g), ctypes.byref(s), int(scheme),
+                                     _stream(stream), ctypes.byref(h)), "gcr_plan_create")
+            self._h = h
+        st = _Stats()
+        _check(L.gcr_plan_stats(self._h, ctypes.byref(st)), "gcr_plan_stats")
+        self.dim = st.dim
+        self.n_cells = st.n_cells
+        self.n_ghost = st.n_ghost
+        self.n_levels = st.n_levels
+        self.n_interface = st.n_interface
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and self._owner is None and _lib is not None:
+            _lib.gcr_plan_destroy(h)
+        self._h = None
+
+    def stats(self) -> dict:
+        st = _Stats()
+        _check(lib().gcr_plan_stats(self._h, ctypes.byref(st)), "gcr_plan_stats")
+        return {f: (list(getattr(st, f))[: st.dim] if f == "max_alpha" else getattr(st, f))
+                for f, _ in _Stats._fields_}
+
+    def level_offsets(self):
+        buf = (ctypes.c_int32 * (self.n_levels + 1))()
+        _check(lib().gcr_plan_level_offsets(self._h, buf), "gcr_plan_level_offsets")
+        return list(buf)
+
+    def set_schedule(self, schedule: int):
+        _check(lib().gcr_set_schedule(self._h, int(schedule), 0), "gcr_set_schedule")
+
+    def export(self, stream=None) -> dict:
+        dev = torch.device("cuda")
+        ng, d = self.n_ghost, self.dim
+        out = dict(tags=torch.empty(self.n_cells, dtype=torch.int8, device=dev),
+                   cell=torch.empty(ng, dtype=torch.int32, device=dev),
+                   level=torch.empty(ng, dtype=torch.int32, device=dev),
+                   delta=torch.empty((d, ng), dtype=torch.float64, device=dev),
+                   normal=torch.empty((d, ng), dtype=torch.float64, device=dev),
+                   psi=torch.empty(ng, dtype=torch.float64, device=dev),
+                   r=torch.empty((d, ng), dtype=torch.int32, device=dev),
+                   unit=torch.empty(ng, dtype=torch.int32, device=dev))
+        _check(lib().gcr_plan_export(
+            self._h, _dptr(out["tags"], torch.int8), _dptr(out["cell"], torch.int32),
+            _dptr(out["level"], torch.int32), _dptr(out["delta"]), _dptr(out["normal"]),
+            _dptr(out["psi"]), _dptr(out["r"], torch.int32), _dptr(out["unit"], torch.int32),
+            _stream(stream)), "gcr_plan_export")
+        return out
+
+    def fill(self, fields: Sequence[torch.Tensor], bc_kind: Sequence[int],
+             bc_val: Sequence[torch.Tensor], bc_type: Optional[Sequence] = None, stream=None):
+        nf = len(fields)
+        kinds = (ctypes.c_int32 * nf)(*[int(k) for k in bc_kind])
+        bt = None
+        if bc_type is not None:
+            bt = (ctypes.c_void_p * nf)()
+            for i, t in enumerate(bc_type):
+                bt[i] = _dptr(t, torch.uint8) if t is not None else None
+        _check(lib().gcr_fill(self._h, nf, _ptr_array(fields), kinds, bt, _ptr_array(bc_val),
+                              _stream(stream)), "gcr_fill")
+
+    def surface_ghost(self, fields: Sequence[torch.Tensor], stream=None):
+        nf = len(fields)
+        dev = fields[0].device
+        val = torch.empty((nf, self.n_ghost), dtype=torch.float64, device=dev)
+        grad = torch.empty((nf, self.dim, self.n_ghost), dtype=torch.float64, device=dev)
+        _check(lib().gcr_surface_ghost(self._h, nf, _ptr_array(fields), _dptr(val), _dptr(grad),
+                                       _stream(stream)), "gcr_surface_ghost")
+        return val, grad
+
+    def surface(self, xq: torch.Tensor, fields: Sequence[torch.Tensor], stream=None):
+        nf = len(fields)
+        nq = xq.shape[1]
+        dev = xq.device
+        val = torch.empty((nf, nq), dtype=torch.float64, device=dev)
+        grad = torch.empty((nf, self.dim, nq), dtype=torch.float64, device=dev)
+        anchor = torch.empty(nq, dtype=torch.int32, device=dev)
+        _check(lib().gcr_surface(self._h, nq, _dptr(xq), nf, _ptr_array(fields), _dptr(val),
+                                 _dptr(grad), _dptr(anchor, torch.int32), _stream(stream)),
+               "gcr_surface")
+        return val, grad, anchor
+
+    def forces(self, xq, nrm, wq, p, u: Sequence[torch.Tensor], mu: float, out=None,
+               stream=None):
+        F = out if out is not None else torch.empty(self.dim, dtype=torch.float64,
+                                                    device=xq.device)
+        _check(lib().gcr_forces(self._h, xq.shape[1], _dptr(xq), _dptr(nrm), _dptr(wq), _dptr(p),
+                                _ptr_array(u), float(mu), _dptr(F), _stream(stream)),
+               "gcr_forces")
+        return F
+
+    def surface_adjoint(self, xq, gval, ggrad, lam: Sequence[torch.Tensor], stream=None):
+        _check(lib().gcr_surface_adjoint(self._h, xq.shape[1], _dptr(xq), len(lam), _dptr(gval),
+                                         _dptr(ggrad), _ptr_array(lam), _stream(stream)),
+               "gcr_surface_adjoint")
+
+    def forces_adjoint(self, xq, nrm, wq, mu, gF, lam_p, lam_u, stream=None):
+        _check(lib().gcr_forces_adjoint(self._h, xq.shape[1], _dptr(xq), _dptr(nrm), _dptr(wq),
+                                        float(mu), _dptr(gF), _dptr(lam_p), _ptr_array(lam_u),
+                                        _stream(stream)), "gcr_forces_adjoint")
+
+    def fill_adjoint(self, lam: Sequence[torch.Tensor], bc_kind: Sequence[int],
+                     lam_bc: Sequence[torch.Tensor], bc_type=None, stream=None):
+        nf = len(lam)
+        kinds = (ctypes.c_int32 * nf)(*[int(k) for k in bc_kind])
+        bt = None
+        if bc_type is not None:
+            bt = (ctypes.c_void_p * nf)()
+            for i, t in enumerate(bc_type):
+                bt[i] = _dptr(t, torch.uint8) if t is not None else None
+        _check(lib().gcr_fill_adjoint(self._h, nf, _ptr_array(lam), kinds, bt,
+                                      _ptr_array(lam_bc), _stream(stream)), "gcr_fill_adjoint")
+
+
+class Batch:
+    """gcr_batch_create: plans of many uneven instances built together."""
+
+    def __init__(self, grids, shapes, schemes, stream=None):
+        L = lib()
+        n = len(grids)
+        G = (_Grid * n)(*[make_grid(g) for g in grids])
+        keep = [make_shape(s) for s in shapes]
+        S = (_Shape * n)(*[k[0] for k in keep])
+        sch = (ctypes.c_int32 * n)(*[int(s) for s in schemes])
+        h = ctypes.c_void_p()
+        _check(L.gcr_batch_create(n, G, S, sch, _stream(stream), ctypes.byref(h)),
+               "gcr_batch_create")
+        self._h = h
+        self.n = n
+        self.plans = []
+        for i in range(n):
+            ph = ctypes.c_void_p()
+            _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
+            self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            self.plans = []
+            _lib.gcr_batch_destroy(h)
+        self._h = None
+
+    def forward(self, nf, fields, bc_kind, bc_val, bc_type=None, nq=None, xq=None, nrm=None,
+                wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, stream=None):
+        """gcr_batch_forward; per-instance lists are instance-major [ninst*nf]."""
+        L = lib()
+        kinds = (ctypes.c_int32 * nf)(*[int(k) for k in bc_kind])
+        bt = None
+        if bc_type is not None:
+            bt = (ctypes.c_void_p * len(bc_type))()
+            for i, t in enumerate(bc_type):
+                bt[i] = _dptr(t, torch.uint8) if t is not None else None
+        nqa = xa = na = wa = None
+        if nq is not None:
+            nqa = (ctypes.c_int64 * self.n)(*[int(v) for v in nq])
+            xa, na, wa = _ptr_array(xq), _ptr_array(nrm), _ptr_array(wq)
+        _check(L.gcr_batch_forward(self._h, nf, _ptr_array(fields), kinds, bt,
+                                   _ptr_array(bc_val), nqa, xa, na, wa, int(p_field),
+                                   int(u_first), float(mu), _dptr(F), _stream(stream)),
+               "gcr_batch_forward")
+        return F
+
+
+STAGES = ["classify", "interface_scan", "interface_compact", "geometry_tags",
+          "ghost_compact", "dependencies", "levels_order", "finalize"]
+
+
+def set_profiling(on: bool):
+    _check(lib().gcr_set_profiling(1 if on else 0), "gcr_set_profiling")
+
+
+def last_build_times() -> dict:
+    buf = (ctypes.c_float * 8)()
+    _check(lib().gcr_last_build_times(buf), "gcr_last_build_times")
+    return dict(zip(STAGES, list(buf)))
+
+
+def version() -> str:
+    return lib().gcr_version().decode()

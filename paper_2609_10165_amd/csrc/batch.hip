@@ -1,0 +1,353 @@
+// batch.hip -- batched forward: many uneven instances, several fields each,
+// reconstructed in one persistent launch.
+//
+// Work items are (instance, field) pairs, largest first.  A workgroup takes
+// items round-robin; for each it sweeps the instance's levels for that
+// field (barrier between levels), then evaluates that field at the
+// instance's surface points and reduces its share of the force:
+//   pressure p:      -w p n
+//   velocity u_c:    mu w (e_c (grad u_c . n) + n_c grad u_c)
+// which sum over the fields to w (-p n + mu (grad u + grad u^T) n).  The
+// last item of an instance to finish (device-scope counter, reset after use)
+// adds the shares in field order, so the result does not depend on timing.
+// Workgroup size and grid are picked by timing candidates on first use.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "gcr_fill.hpp"
+#include "gcr_impl.hpp"
+
+namespace gcr {
+
+struct BStatic {
+  const PlanD* plans;        // [ninst]
+  const int32_t* const* lev_off;
+  const int32_t* nlev;
+};
+
+struct BCall {
+  int nf, ninst, p_field, u_first, nitems, pad;
+  double mu;
+  int kind[kMaxFields];
+  double* const* fields;         // [ninst*nf]
+  const double* const* bcv;      // [ninst*nf]
+  const uint8_t* const* bct;     // [ninst*nf] (may hold nulls)
+  const int64_t* nq;             // [ninst] or null (no forces)
+  const double* const* xq;
+  const double* const* nrm;
+  const double* const* wq;
+  const int32_t* order;          // [nitems] items w = i*nf + f
+};
+
+template <int D>
+__global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, double* __restrict__ part,
+                                                        int* __restrict__ counter,
+                                                        double* __restrict__ Fout) {
+  __shared__ double red[1024][3];
+  __shared__ int s_last;
+  const int T = blockDim.x;
+  for (int it = blockIdx.x; it < C.nitems; it += gridDim.x) {
+    const int w = C.order[it];
+    const int i = w / C.nf, f = w % C.nf;
+    const PlanD& P = S.plans[i];
+    double* F = C.fields[w];
+    const double* b = C.bcv[w];
+    const uint8_t* bt = C.bct ? C.bct[w] : nullptr;
+    const int kind = C.kind[f];
+    const int32_t* lo_ = S.lev_off[i];
+    const int nl = S.nlev[i];
+    for (int l = 0; l < nl; ++l) {
+      const int lo = lo_[l], hi = lo_[l + 1];
+      for (int p = lo + (int)threadIdx.x; p < hi; p += T) fill_single<D>(P, p, F, b, bt, kind);
+      __syncthreads();
+    }
+    // share of the force
+    const int vc = f - C.u_first;
+    const bool isp = f == C.p_field, isu = vc >= 0 && vc < D;
+    double t[3] = {0.0, 0.0, 0.0};
+    if (C.nq && (isp || isu)) {
+      const int64_t nq = C.nq[i];
+      const double* xq = C.xq[i];
+      const double* nr = C.nrm[i];
+      const double* wq = C.wq[i];
+      for (int64_t q = threadIdx.x; q < nq; q += T) {
+        double x[3] = {0.0, 0.0, 0.0}, n[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          x[a] = xq[a * nq + q];
+          n[a] = nr[a * nq + q];
+        }
+        const int g = find_anchor<D>(P, x);
+        double val, gr[3];
+        if (g < 0) {
+          val = __longlong_as_double(0x7ff8000000000000LL);
+          gr[0] = gr[1] = gr[2] = val;
+        } else {
+          int ii, jj, kk;
+          unlinear(P.g, P.cell[g], ii, jj, kk);
+          const int ijk[3] = {ii, jj, kk};
+          double rel[3] = {0.0, 0.0, 0.0}, v[8];
+#pragma unroll
+          for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
+          corner_values<D>(P, g, F, v);
+          box_eval<D>(rel, P.code[g], P.g.h, v, val, gr);
+        }
+        const double wt = wq[q];
+        if (isp) {
+#pragma unroll
+          for (int a = 0; a < D; ++a) t[a] += -wt * val * n[a];
+        } else {
+          double gn = 0.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) gn += gr[a] * n[a];
+#pragma unroll
+          for (int a = 0; a < D; ++a) t[a] += C.mu * wt * ((a == vc ? gn : 0.0) + n[vc] * gr[a]);
+        }
+      }
+    }
+    for (int a = 0; a < 3; ++a) red[threadIdx.x][a] = t[a];
+    __syncthreads();
+    for (int s = T / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s)
+        for (int a = 0; a < 3; ++a) red[threadIdx.x][a] += red[threadIdx.x + s][a];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      for (int a = 0; a < 3; ++a) part[(int64_t)w * 3 + a] = red[0][a];
+      __threadfence();
+      const int done = atomicAdd(&counter[i], 1);
+      s_last = (done == C.nf - 1);
+      if (s_last) {
+        __threadfence();
+        double s3[3] = {0.0, 0.0, 0.0};
+        for (int ff = 0; ff < C.nf; ++ff)
+          for (int a = 0; a < 3; ++a)
+            s3[a] += __hip_atomic_load(&part[((int64_t)i * C.nf + ff) * 3 + a], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        for (int a = 0; a < 3; ++a) Fout[(int64_t)i * 3 + a] = s3[a];
+        atomicExch(&counter[i], 0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct BatchFwdState {
+  PlanD* d_plans = nullptr;
+  int32_t** d_levp = nullptr;
+  int32_t* d_nlev = nullptr;
+  int* d_counter = nullptr;
+  double* d_part = nullptr;
+  size_t part_cap = 0;
+  char* d_call = nullptr;
+  size_t call_cap = 0;
+  int threads = 0, grid_mul = 0;   // tuned
+  std::vector<void*> owned;
+  ~BatchFwdState() {
+    for (void* p : owned) pool_free(p);
+  }
+};
+
+}  // namespace gcr
+
+using namespace gcr;
+
+namespace {
+std::mutex g_bfs_mu;
+std::vector<std::pair<const gcr_batch*, std::unique_ptr<BatchFwdState>>> g_bfs;
+
+BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
+  std::lock_guard<std::mutex> lk(g_bfs_mu);
+  for (auto& e : g_bfs)
+    if (e.first == b) return e.second.get();
+  auto S = std::make_unique<BatchFwdState>();
+  const int n = (int)b->plans.size();
+  std::vector<PlanD> pv(n);
+  std::vector<int32_t*> lp(n);
+  std::vector<int32_t> nl(n);
+  for (int i = 0; i < n; ++i) {
+    pv[i] = plan_view(b->plans[i].get());
+    lp[i] = b->plans[i]->d_lev_off;
+    nl[i] = b->plans[i]->nlev;
+  }
+  S->d_plans = static_cast<PlanD*>(pool_alloc(sizeof(PlanD) * n));
+  S->d_levp = static_cast<int32_t**>(pool_alloc(sizeof(int32_t*) * n));
+  S->d_nlev = static_cast<int32_t*>(pool_alloc(sizeof(int32_t) * n));
+  S->d_counter = static_cast<int*>(pool_alloc(sizeof(int) * n));
+  for (void* p : {(void*)S->d_plans, (void*)S->d_levp, (void*)S->d_nlev, (void*)S->d_counter})
+    S->owned.push_back(p);
+  if (!S->d_plans || !S->d_levp || !S->d_nlev || !S->d_counter) {
+    *err = GCR_E_NOMEM;
+    return nullptr;
+  }
+  if (hipMemcpyAsync(S->d_plans, pv.data(), sizeof(PlanD) * n, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(S->d_levp, lp.data(), sizeof(int32_t*) * n, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(S->d_nlev, nl.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) ||
+      hipMemsetAsync(S->d_counter, 0, sizeof(int) * n, st) || hipStreamSynchronize(st)) {
+    *err = GCR_E_HIP;
+    return nullptr;
+  }
+  g_bfs.emplace_back(b, std::move(S));
+  return g_bfs.back().second.get();
+}
+}  // namespace
+
+void gcr_batch_release_state(const gcr_batch* b) {
+  std::lock_guard<std::mutex> lk(g_bfs_mu);
+  for (size_t k = 0; k < g_bfs.size(); ++k)
+    if (g_bfs[k].first == b) {
+      g_bfs.erase(g_bfs.begin() + k);
+      return;
+    }
+}
+
+static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int threads, int grid,
+                               double* F, hipStream_t st) {
+  BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
+  if (dim == 2)
+    k_batch_forward<2><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+  else
+    k_batch_forward<3><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+  GCR_HIP(hipGetLastError());
+  return GCR_OK;
+}
+
+extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* const* fields,
+                                        const int32_t* bc_kind, const uint8_t* const* bc_type,
+                                        const double* const* bc_val, const int64_t* nq,
+                                        const double* const* xq, const double* const* nrm,
+                                        const double* const* wq, int32_t p_field,
+                                        int32_t u_first, double mu, double* F, void* stream) {
+  if (!batch || nf < 1 || nf > kMaxFields || !fields || !bc_kind || !bc_val) return GCR_E_ARG;
+  const int n = (int)batch->plans.size();
+  const int dim = batch->plans[0]->dim;
+  for (int i = 0; i < n; ++i)
+    if (batch->plans[i]->dim != dim) return GCR_E_UNSUPPORTED;
+  for (int f = 0; f < nf; ++f)
+    if (bc_kind[f] < 0 || bc_kind[f] > 2) return GCR_E_ARG;
+  for (int w = 0; w < n * nf; ++w) {
+    if (!fields[w] || !bc_val[w]) return GCR_E_ARG;
+    if (bc_kind[w % nf] == GCR_MIXED && (!bc_type || !bc_type[w])) return GCR_E_ARG;
+  }
+  if (nq) {
+    if (!xq || !nrm || !wq || !F) return GCR_E_ARG;
+    for (int i = 0; i < n; ++i)
+      if (nq[i] < 0 || (nq[i] > 0 && (!xq[i] || !nrm[i] || !wq[i]))) return GCR_E_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  gcr_status err = GCR_OK;
+  BatchFwdState* S = state_of(batch, st, &err);
+  if (!S) return err;
+  // items, largest first: fill work ~ ghosts, latency ~ levels, surface ~ points
+  const int nitems = n * nf;
+  std::vector<double> cost(nitems);
+  for (int w = 0; w < nitems; ++w) {
+    const gcr_plan* p = batch->plans[w / nf].get();
+    cost[w] = (double)p->ng / 256.0 + 4.0 * p->nlev + (nq ? (double)nq[w / nf] / 256.0 : 0.0);
+  }
+  std::vector<int32_t> order(nitems);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  // call table: one upload
+  const size_t np = (size_t)nitems;
+  const size_t bytes = sizeof(void*) * (3 * np + 3 * n) + sizeof(int64_t) * n +
+                       sizeof(int32_t) * np + 64;
+  std::vector<char> host(bytes, 0);
+  char* h = host.data();
+  size_t o = 0;
+  auto put = [&](const void* src, size_t sz) {
+    std::memcpy(h + o, src, sz);
+    size_t at = o;
+    o += (sz + 7) & ~size_t(7);
+    return at;
+  };
+  std::vector<const void*> bt(np, nullptr);
+  if (bc_type)
+    for (size_t w = 0; w < np; ++w) bt[w] = bc_type[w];
+  const size_t o_fields = put(fields, sizeof(void*) * np);
+  const size_t o_bcv = put(bc_val, sizeof(void*) * np);
+  const size_t o_bct = put(bt.data(), sizeof(void*) * np);
+  size_t o_nq = 0, o_xq = 0, o_nrm = 0, o_wq = 0;
+  if (nq) {
+    o_nq = put(nq, sizeof(int64_t) * n);
+    o_xq = put(xq, sizeof(void*) * n);
+    o_nrm = put(nrm, sizeof(void*) * n);
+    o_wq = put(wq, sizeof(void*) * n);
+  }
+  const size_t o_order = put(order.data(), sizeof(int32_t) * np);
+  if (S->call_cap < o) {
+    if (S->d_call) pool_free(S->d_call);
+    S->d_call = static_cast<char*>(pool_alloc(o));
+    S->call_cap = S->d_call ? o : 0;
+    if (!S->d_call) return GCR_E_NOMEM;
+  }
+  if (S->part_cap < np * 3) {
+    if (S->d_part) pool_free(S->d_part);
+    S->d_part = static_cast<double*>(pool_alloc(sizeof(double) * np * 3));
+    S->part_cap = S->d_part ? np * 3 : 0;
+    if (!S->d_part) return GCR_E_NOMEM;
+  }
+  GCR_HIP(hipMemcpyAsync(S->d_call, h, o, hipMemcpyHostToDevice, st));
+  char* d = S->d_call;
+  BCall C;
+  std::memset(&C, 0, sizeof(C));
+  C.nf = nf;
+  C.ninst = n;
+  C.p_field = nq ? p_field : -1;
+  C.u_first = nq ? u_first : -1000;
+  C.nitems = nitems;
+  C.mu = mu;
+  for (int f = 0; f < nf; ++f) C.kind[f] = bc_kind[f];
+  C.fields = reinterpret_cast<double* const*>(d + o_fields);
+  C.bcv = reinterpret_cast<const double* const*>(d + o_bcv);
+  C.bct = bc_type ? reinterpret_cast<const uint8_t* const*>(d + o_bct) : nullptr;
+  C.nq = nq ? reinterpret_cast<const int64_t*>(d + o_nq) : nullptr;
+  C.xq = nq ? reinterpret_cast<const double* const*>(d + o_xq) : nullptr;
+  C.nrm = nq ? reinterpret_cast<const double* const*>(d + o_nrm) : nullptr;
+  C.wq = nq ? reinterpret_cast<const double* const*>(d + o_wq) : nullptr;
+  C.order = reinterpret_cast<const int32_t*>(d + o_order);
+  double* Fo = F;
+  double* Fdummy = nullptr;
+  if (!nq) {
+    Fdummy = static_cast<double*>(plan_scratch(batch->plans[0].get(), 5, sizeof(double) * 3 * n));
+    if (!Fdummy) return GCR_E_NOMEM;
+    Fo = Fdummy;
+  }
+  if (S->threads == 0) {
+    // tuner: workgroup size x grid size, timed on the caller's data (the
+    // forward is idempotent)
+    hipEvent_t e0, e1;
+    GCR_HIP(hipEventCreate(&e0));
+    GCR_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bt_ = 256, bg = 1;
+    const int cand_t[3] = {256, 512, 1024};
+    const int cand_g[2] = {1, 4};
+    for (int tt : cand_t)
+      for (int gm : cand_g) {
+        const int grid = std::min(nitems, 256 * gm);
+        gcr_status s = launch_batch(S, C, dim, tt, grid, Fo, st);
+        if (s != GCR_OK) return s;
+        GCR_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) launch_batch(S, C, dim, tt, grid, Fo, st);
+        GCR_HIP(hipEventRecord(e1, st));
+        GCR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        GCR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          bt_ = tt;
+          bg = gm;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    S->threads = bt_;
+    S->grid_mul = bg;
+  }
+  return launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
+}

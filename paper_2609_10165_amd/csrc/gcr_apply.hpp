@@ -1,0 +1,135 @@
+// gcr_apply.hpp -- argument blocks of the apply kernels and their launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/gcr.h"
+#include "gcr_device.hpp"
+
+namespace gcr {
+
+// Device view of one plan (canonical ghost order).
+struct PlanD {
+  GridD g;
+  int ng;
+  const int8_t* tags;
+  const int32_t* cell;
+  const double* dl[3];      // x_s - x_c
+  const double* nn[3];      // unit normal into the fluid
+  const uint32_t* code;
+  const int32_t* blk;       // coupled-unit slot or -1
+  const int32_t* unit_mem;  // [slot][kMaxUnit] canonical positions
+  const int32_t* unit_cnt;
+  const int32_t* sorted_cell;  // ghost cells in linear-index order
+  const int32_t* sorted_pos;   // their canonical positions
+  int rmax[3];                 // largest stencil multiplier per axis
+};
+
+// canonical position of the ghost in cell c, or -1
+__device__ __forceinline__ int ghost_at(const PlanD& P, int c) {
+  int lo = 0, hi = P.ng;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (P.sorted_cell[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return (lo < P.ng && P.sorted_cell[lo] == c) ? P.sorted_pos[lo] : -1;
+}
+
+struct FillArgs {
+  PlanD P;
+  int nf;
+  int kind[kMaxFields];            // 0 Dirichlet, 1 Neumann, 2 per-ghost
+  double* f[kMaxFields];
+  const double* b[kMaxFields];
+  const uint8_t* bt[kMaxFields];
+};
+
+struct SurfArgs {
+  PlanD P;
+  int nf;
+  const double* f[kMaxFields];
+  double* val;
+  double* grad;
+  int32_t* anchor;
+};
+
+struct ForceArgs {
+  int64_t nq;
+  const double* xq;
+  const double* nrm;
+  const double* wq;
+  const double* p;
+  const double* u[3];
+  double mu;
+};
+
+PlanD plan_view(const gcr_plan* p);
+
+void launch_fill_range(const FillArgs& A, int lo, int hi, hipStream_t st);
+void launch_fill_wg(const FillArgs& A, const int32_t* d_lev_off, int nlev, int threads,
+                    hipStream_t st);
+void launch_fill_batch(int dim_mask, const FillArgs* d_args, const int32_t* d_order, int nitems,
+                       const int32_t* const* d_lev_offs, const int32_t* d_nlevs, int grid,
+                       int threads, hipStream_t st);
+void launch_surface_ghost(const SurfArgs& S, hipStream_t st);
+void launch_surface_query(const SurfArgs& S, int64_t nq, const double* xq, hipStream_t st);
+void launch_forces(const PlanD& P, const ForceArgs& F, double* part, double* out,
+                   hipStream_t st);
+
+}  // namespace gcr
+
+namespace gcr {
+
+// Corner values of ghost p's stencil box; corners outside the grid read NaN.
+template <int D>
+__device__ __forceinline__ void corner_values(const PlanD& P, int p, const double* F, double v[8]) {
+  const int c = P.cell[p];
+  const uint32_t code = P.code[p];
+  int i, j, k;
+  unlinear(P.g, c, i, j, k);
+#pragma unroll
+  for (int m = 0; m < (1 << D); ++m)
+    v[m] = corner_in_grid(P.g, code, i, j, k, m) ? F[c + corner_offset(P.g, code, m)]
+                                                 : __longlong_as_double(0x7ff8000000000000LL);
+}
+
+// Anchor of a point: among ghosts within 2 cells per axis of the point's
+// cell, the one whose foot point is nearest; ties go to the smaller linear
+// index (cells are visited in ascending linear index, strict comparison).
+template <int D>
+__device__ __forceinline__ int find_anchor(const PlanD& P, const double x[3]) {
+  int qi[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) qi[a] = (int)floor((x[a] - P.g.lo[a]) / P.g.h[a]);
+  int best = -1;
+  double bd = 1e300;
+  const int z0 = D == 3 ? qi[2] - 2 : 0, z1 = D == 3 ? qi[2] + 2 : 0;
+  for (int kz = z0; kz <= z1; ++kz) {
+    if (D == 3 && (kz < 0 || kz >= P.g.n[2])) continue;
+    for (int jy = qi[1] - 2; jy <= qi[1] + 2; ++jy) {
+      if (jy < 0 || jy >= P.g.n[1]) continue;
+      for (int ix = qi[0] - 2; ix <= qi[0] + 2; ++ix) {
+        if (ix < 0 || ix >= P.g.n[0]) continue;
+        const int c = linear(P.g, ix, jy, kz);
+        const int8_t t = P.tags[c];
+        if (t != 2 && t != -2) continue;
+        const int g = ghost_at(P, c);
+        if (g < 0) continue;
+        const int q[3] = {ix, jy, kz};
+        double d2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = centre(P.g, a, q[a]) + P.dl[a][g];
+          d2 += (x[a] - s) * (x[a] - s);
+        }
+        if (d2 < bd) {
+          bd = d2;
+          best = g;
+        }
+      }
+    }
+  }
+  return best;
+}
+
+}  // namespace gcr

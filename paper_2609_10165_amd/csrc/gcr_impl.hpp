@@ -1,0 +1,163 @@
+// gcr_impl.hpp -- host-side internals shared by the library's translation
+// units: the plan and batch objects, the device memory pool, error helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/gcr.h"
+#include "gcr_device.hpp"
+
+namespace gcr {
+
+// Per-instance results of plan building, written by the device.
+struct InstInfo {
+  uint32_t err;
+  int32_t nlev;
+  int32_t nunits;
+  int32_t maxunit;
+  int32_t maxwidth;
+  int32_t nfluid;
+  int32_t rmax[3];      // largest stencil multiplier per axis
+  int32_t pad;
+  unsigned long long max_alpha_bits[3];
+};
+
+// Device memory pool: power-of-two size classes, blocks are kept for reuse
+// until the process ends, so rebuilding plans does not call hipMalloc.
+void* pool_alloc(size_t bytes);
+void pool_free(void* p);
+
+template <class T>
+T* palloc(size_t n) {
+  return static_cast<T*>(pool_alloc(sizeof(T) * (n ? n : 1)));
+}
+
+// Owner of every device array of one batch of plans (a single plan is a
+// batch of one).  Ghost-indexed arrays are concatenated over instances and
+// structure-of-arrays with stride `cap`.
+struct BatchData {
+  int ninst = 0;
+  int64_t ncells_total = 0, nchunks = 0, nif = 0, cap = 0, ng_total = 0;
+  std::vector<Inst> inst;            // host copies
+  std::vector<int64_t> if_off, g_off;  // host [ninst+1]
+  std::vector<InstInfo> info;        // host [ninst]
+  std::vector<int32_t> lev_off;      // host [ninst][kMaxLevels+1]
+  // device
+  Inst* d_inst = nullptr;
+  int8_t* d_tags = nullptr;
+  int64_t* d_chunk_start = nullptr;  // [ninst+1]
+  int32_t* d_chunk_cnt = nullptr;
+  int64_t* d_chunk_excl = nullptr;
+  int64_t* d_if_off = nullptr;       // [ninst+1]
+  int64_t* d_g_off = nullptr;        // [ninst+1]
+  InstInfo* d_info = nullptr;
+  int32_t* d_lev_off = nullptr;      // [ninst][kMaxLevels+1]
+  // interface cells
+  int32_t* d_if_cell = nullptr;
+  double* d_if_psi = nullptr;
+  double* d_if_n = nullptr;          // [3][cap]
+  uint8_t* d_if_flag = nullptr;
+  int32_t* d_blkcnt = nullptr;
+  int64_t* d_blkexcl = nullptr;
+  // ghosts, linear-index order
+  int32_t* d_g_cell = nullptr;
+  double* d_g_psi = nullptr;
+  double* d_g_n = nullptr;           // [3][cap]
+  uint32_t* d_g_code = nullptr;
+  int32_t* d_deps = nullptr;         // [7][cap]
+  int32_t* d_lev = nullptr;
+  int32_t* d_blk_idx = nullptr;
+  int32_t* d_perm = nullptr;         // linear-order position -> canonical (instance-local)
+  // ghosts, canonical order
+  int32_t* d_cell = nullptr;
+  double* d_delta = nullptr;         // [3][cap]
+  double* d_nrm = nullptr;           // [3][cap]
+  double* d_psi = nullptr;
+  uint32_t* d_code = nullptr;
+  int32_t* d_level = nullptr;
+  int32_t* d_blk = nullptr;
+  int32_t* d_unit_mem = nullptr;     // [ninst][kMaxUnits][kMaxUnit]
+  int32_t* d_unit_cnt = nullptr;     // [ninst][kMaxUnits]
+  std::vector<void*> owned;
+  ~BatchData();
+};
+
+// Schedule of the fill.
+enum { kSchedAuto = 0, kSchedLevels = 1, kSchedWorkgroup = 2, kSchedGraph = 3 };
+constexpr int kScratchSlots = 6;
+
+struct GraphCache;
+
+}  // namespace gcr
+
+// A plan: a view of one instance of a BatchData.
+struct gcr_plan {
+  std::shared_ptr<gcr::BatchData> batch;
+  int index = 0;
+  gcr::Inst inst;          // host copy
+  int dim = 0;
+  int64_t ncell = 0, ng = 0, nif = 0, stride = 0, goff = 0;
+  int32_t nlev = 0;
+  gcr::InstInfo info{};
+  std::vector<int32_t> lev_off;   // host [nlev+1]
+  // device views
+  int8_t* tags = nullptr;
+  int32_t* cell = nullptr;
+  double* delta[3] = {nullptr, nullptr, nullptr};
+  double* nrm[3] = {nullptr, nullptr, nullptr};
+  double* psi = nullptr;
+  uint32_t* code = nullptr;
+  int32_t* level = nullptr;
+  int32_t* blk = nullptr;
+  int32_t* unit_mem = nullptr;
+  int32_t* unit_cnt = nullptr;
+  int32_t* sorted_cell = nullptr;   // ghost cells in linear-index order
+  int32_t* sorted_pos = nullptr;    // their canonical positions
+  int32_t* d_lev_off = nullptr;
+  int schedule = gcr::kSchedAuto;
+  int tuned = -1;                   // schedule picked by the tuner
+  // scratch buffers owned by the plan (forces partials, adjoint state);
+  // calls that use them must not overlap on one plan
+  void* scr[gcr::kScratchSlots] = {};
+  size_t scr_bytes[gcr::kScratchSlots] = {};
+  std::unique_ptr<gcr::GraphCache> graph;
+  ~gcr_plan();
+};
+
+struct gcr_batch {
+  std::shared_ptr<gcr::BatchData> data;
+  std::vector<std::unique_ptr<gcr_plan>> plans;
+  void* fwd_args = nullptr;         // device table for the batched forward
+  size_t fwd_args_bytes = 0;
+  ~gcr_batch();
+};
+
+namespace gcr {
+
+gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes,
+                       const int32_t* schemes, hipStream_t st, std::shared_ptr<BatchData>* out);
+void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p);
+void set_profiling(int on);
+void* plan_scratch(gcr_plan* p, int slot, size_t bytes);
+void last_build_times(float* ms);
+gcr_status status_from_err(uint32_t err);
+
+extern thread_local hipError_t g_last_hip_error;
+
+}  // namespace gcr
+
+// drops the batched-forward tables of a batch (defined with the batched kernel)
+void gcr_batch_release_state(const gcr_batch* b);
+
+#define GCR_HIP(x)                                  \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) {                         \
+      gcr::g_last_hip_error = e_;                   \
+      return GCR_E_HIP;                             \
+    }                                               \
+  } while (0)

@@ -1,0 +1,1215 @@
+// plan.hip -- building ghost-cell plans on the GPU.
+//
+// Pipeline (one launch per stage, all instances of a batch together):
+//   classify      every cell: inside test at its centre (Sec. 3.1), and
+//                 whether a face neighbour has the other class; far-field
+//                 segments are settled by a radial bound and written as
+//                 16-byte constant stores
+//   scan/compact  interface cells in linear-index order
+//   geometry      closest point, analytic normal, psi; ghost tags for CGC,
+//                 CGC_ES and HGC (Eq. HGC_criterion with Eq. delta_n)
+//   ghosts        order-preserving compaction of the ghost cells
+//   deps          stencil code (e = sgn n, multipliers r), validation, and
+//                 ghost-to-ghost dependencies (Sec. 3.2)
+//   levels        Kahn layering per instance, emitting the canonical order
+//                 (level, linear index) as it goes; a stall means a cycle:
+//                 its strongly connected groups become coupled units
+//   finalize      canonical structure-of-arrays for the apply kernels
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+
+#include "gcr_impl.hpp"
+
+namespace gcr {
+
+// --------------------------------------------------------------------------
+// small device helpers
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ int find_inst(const int64_t* off, int ninst, int64_t x) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// --------------------------------------------------------------------------
+// closest point and normal
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ void naca_point(double t, double s, double C[2], double D[2]) {
+  double s2 = s * s, sg = s < 0.0 ? -1.0 : 1.0;
+  double poly = 0.1260 * s2 + 0.3516 * s2 * s2 - 0.2843 * s2 * s2 * s2 + 0.1036 * s2 * s2 * s2 * s2;
+  double dpoly = s * (2.0 * 0.1260 + s2 * (4.0 * 0.3516 + s2 * (-6.0 * 0.2843 + s2 * 8.0 * 0.1036)));
+  C[0] = s2;
+  C[1] = 5.0 * t * (0.2969 * s - sg * poly);
+  D[0] = 2.0 * s;
+  D[1] = 5.0 * t * (0.2969 - sg * dpoly);
+}
+
+__device__ bool project(const ShapeD& s, int dim, const double x[3], bool solid, double n[3],
+                        double& psi) {
+  double v[3] = {x[0] - s.c[0], x[1] - s.c[1], dim == 3 ? x[2] - s.c[2] : 0.0};
+  n[2] = 0.0;
+  if (s.kind == kSphere) {
+    double rho2 = v[0] * v[0] + v[1] * v[1];
+    if (dim == 3) rho2 += v[2] * v[2];
+    double rho = sqrt(rho2);
+    if (rho == 0.0) return false;
+    for (int i = 0; i < dim; ++i) n[i] = v[i] / rho;
+    psi = s.r0 - rho;
+    return true;
+  }
+  double S[3] = {0.0, 0.0, 0.0};
+  bool ok = false;
+  if (s.kind == kStar2D) {
+    // Gauss-Newton on a fixed chart of directions u(a) ~ w0 + a t0
+    double rho = sqrt(v[0] * v[0] + v[1] * v[1]);
+    if (rho == 0.0) return false;
+    double w0[2] = {v[0] / rho, v[1] / rho}, t0[2] = {-w0[1], w0[0]};
+    double a = 0.0, last = 1.0;
+    int good = 0;
+    for (int it = 0; it < 80 && good < 2; ++it) {
+      double q0 = w0[0] + a * t0[0], q1 = w0[1] + a * t0[1];
+      double nv = sqrt(q0 * q0 + q1 * q1);
+      double u0 = q0 / nv, u1 = q1 / nv, r, r1;
+      star_r(s, u0, u1, r, r1);
+      double fac = (-u1 * t0[0] + u0 * t0[1]) / nv;
+      double J0 = fac * (r1 * u0 - r * u1), J1 = fac * (r1 * u1 + r * u0);
+      double R0 = s.c[0] + r * u0 - x[0], R1 = s.c[1] + r * u1 - x[1];
+      double da = -(J0 * R0 + J1 * R1) / (J0 * J0 + J1 * J1);
+      a += da;
+      last = fabs(da);
+      good = last < 1e-15 ? good + 1 : 0;
+    }
+    ok = good >= 2 || last < 1e-13;
+    double q0 = w0[0] + a * t0[0], q1 = w0[1] + a * t0[1];
+    double nv = sqrt(q0 * q0 + q1 * q1);
+    double u0 = q0 / nv, u1 = q1 / nv, r, r1;
+    star_r(s, u0, u1, r, r1);
+    S[0] = s.c[0] + r * u0;
+    S[1] = s.c[1] + r * u1;
+    // tangent dX/dtheta = r' u + r u_perp; outward normal = tangent turned clockwise
+    double T0 = r1 * u0 - r * u1, T1 = r1 * u1 + r * u0;
+    double tn = sqrt(T0 * T0 + T1 * T1);
+    n[0] = T1 / tn;
+    n[1] = -T0 / tn;
+  } else if (s.kind == kShStar) {
+    double rho = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (rho == 0.0) return false;
+    double w0[3] = {v[0] / rho, v[1] / rho, v[2] / rho};
+    int ax = 0;
+    if (fabs(w0[1]) < fabs(w0[ax])) ax = 1;
+    if (fabs(w0[2]) < fabs(w0[ax])) ax = 2;
+    double t1[3] = {0.0, 0.0, 0.0};
+    t1[ax] = 1.0;
+    double dd = w0[ax];
+    for (int i = 0; i < 3; ++i) t1[i] -= dd * w0[i];
+    double tl = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    for (int i = 0; i < 3; ++i) t1[i] /= tl;
+    double t2[3] = {w0[1] * t1[2] - w0[2] * t1[1], w0[2] * t1[0] - w0[0] * t1[2],
+                    w0[0] * t1[1] - w0[1] * t1[0]};
+    double p1 = 0.0, p2 = 0.0, last = 1.0;
+    int good = 0;
+    for (int it = 0; it < 80 && good < 2; ++it) {
+      double q[3], u[3], r, g[3];
+      for (int i = 0; i < 3; ++i) q[i] = w0[i] + p1 * t1[i] + p2 * t2[i];
+      double nv = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+      for (int i = 0; i < 3; ++i) u[i] = q[i] / nv;
+      sh_r(s, u, r, g);
+      double ut1 = u[0] * t1[0] + u[1] * t1[1] + u[2] * t1[2];
+      double ut2 = u[0] * t2[0] + u[1] * t2[1] + u[2] * t2[2];
+      double J1[3], J2[3], R[3];
+      double du1[3], du2[3];
+      for (int i = 0; i < 3; ++i) {
+        du1[i] = (t1[i] - ut1 * u[i]) / nv;
+        du2[i] = (t2[i] - ut2 * u[i]) / nv;
+      }
+      double dr1 = g[0] * du1[0] + g[1] * du1[1] + g[2] * du1[2];
+      double dr2 = g[0] * du2[0] + g[1] * du2[1] + g[2] * du2[2];
+      for (int i = 0; i < 3; ++i) {
+        J1[i] = dr1 * u[i] + r * du1[i];
+        J2[i] = dr2 * u[i] + r * du2[i];
+        R[i] = s.c[i] + r * u[i] - x[i];
+      }
+      double a11 = 0, a12 = 0, a22 = 0, b1 = 0, b2 = 0;
+      for (int i = 0; i < 3; ++i) {
+        a11 += J1[i] * J1[i];
+        a12 += J1[i] * J2[i];
+        a22 += J2[i] * J2[i];
+        b1 -= J1[i] * R[i];
+        b2 -= J2[i] * R[i];
+      }
+      double det = a11 * a22 - a12 * a12;
+      double d1 = (b1 * a22 - b2 * a12) / det, d2 = (a11 * b2 - a12 * b1) / det;
+      p1 += d1;
+      p2 += d2;
+      last = fabs(d1) + fabs(d2);
+      good = last < 1e-15 ? good + 1 : 0;
+    }
+    ok = good >= 2 || last < 1e-13;
+    double q[3], u[3], r, g[3];
+    for (int i = 0; i < 3; ++i) q[i] = w0[i] + p1 * t1[i] + p2 * t2[i];
+    double nv = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    for (int i = 0; i < 3; ++i) u[i] = q[i] / nv;
+    sh_r(s, u, r, g);
+    for (int i = 0; i < 3; ++i) {
+      S[i] = s.c[i] + r * u[i];
+      n[i] = u[i] - g[i] / r;   // gradient of |y - c| - r(direction)
+    }
+    double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int i = 0; i < 3; ++i) n[i] /= nl;
+  } else if (s.kind == kAirfoil) {
+    double dx = (x[0] - s.c[0]) / s.chord, dy = (x[1] - s.c[1]) / s.chord;
+    double b0 = s.ca * dx - s.sa * dy, b1 = s.sa * dx + s.ca * dy;
+    double xc = b0 < 0.0 ? 0.0 : (b0 > 1.0 ? 1.0 : b0);
+    double sp = sqrt(xc);
+    double best = 1e300, bs = 0.0;
+    ok = true;
+    for (int br = 0; br < 2; ++br) {
+      double lo = br == 0 ? 0.0 : -1.0, hi = br == 0 ? 1.0 : 0.0;
+      double sv = br == 0 ? sp : -sp;
+      if (sv == 0.0) sv = br == 0 ? 1e-3 : -1e-3;
+      double last = 1.0;
+      // Gauss-Newton on the contour parameter, clamped to the branch
+      for (int it = 0; it < 200 && last > 1e-15; ++it) {
+        double C[2], D[2];
+        naca_point(s.thick, sv, C, D);
+        double ds = -((C[0] - b0) * D[0] + (C[1] - b1) * D[1]) / (D[0] * D[0] + D[1] * D[1]);
+        double ns = sv + ds;
+        ns = ns < lo ? lo : (ns > hi ? hi : ns);
+        last = fabs(ns - sv);
+        sv = ns;
+      }
+      if (last > 1e-12) ok = false;
+      double C[2], D[2];
+      naca_point(s.thick, sv, C, D);
+      double d2 = (C[0] - b0) * (C[0] - b0) + (C[1] - b1) * (C[1] - b1);
+      if (d2 < best) {
+        best = d2;
+        bs = sv;
+      }
+    }
+    double C[2], D[2], nb[2];
+    naca_point(s.thick, bs, C, D);
+    if (fabs(bs) >= 1.0) {
+      // trailing-edge corner: the normal is the direction from the corner
+      double e0 = b0 - C[0], e1 = b1 - C[1];
+      double el = sqrt(e0 * e0 + e1 * e1);
+      nb[0] = (solid ? -e0 : e0) / el;
+      nb[1] = (solid ? -e1 : e1) / el;
+    } else {
+      // contour is clockwise in s: outward normal = tangent turned counter-clockwise
+      double dl = sqrt(D[0] * D[0] + D[1] * D[1]);
+      nb[0] = -D[1] / dl;
+      nb[1] = D[0] / dl;
+    }
+    n[0] = s.ca * nb[0] + s.sa * nb[1];
+    n[1] = -s.sa * nb[0] + s.ca * nb[1];
+    S[0] = s.c[0] + s.chord * (s.ca * C[0] + s.sa * C[1]);
+    S[1] = s.c[1] + s.chord * (-s.sa * C[0] + s.ca * C[1]);
+  } else {
+    return false;
+  }
+  double d2 = 0.0;
+  for (int i = 0; i < dim; ++i) d2 += (x[i] - S[i]) * (x[i] - S[i]);
+  psi = solid ? sqrt(d2) : -sqrt(d2);
+  return ok;
+}
+
+// --------------------------------------------------------------------------
+// 1. classification
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ bool cell_solid(const Inst& I, int i, int j, int k) {
+  double x[3] = {centre(I.g, 0, i), centre(I.g, 1, j), I.g.dim == 3 ? centre(I.g, 2, k) : 0.0};
+  return inside(I.s, I.g.dim, x);
+}
+
+// 16 solid bits of row (j,k) from i0; a row outside the grid returns `self`
+__device__ __forceinline__ uint32_t row_bits(const Inst& I, int i0, int j, int k, uint32_t self) {
+  if (j < 0 || j >= I.g.n[1] || k < 0 || (I.g.dim == 3 && k >= I.g.n[2])) return self;
+  uint32_t b = 0;
+  for (int t = 0; t < kSeg; ++t) b |= (uint32_t)cell_solid(I, i0 + t, j, k) << t;
+  return b;
+}
+
+__global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts, int ninst,
+                                                  const int64_t* __restrict__ chunk_start,
+                                                  int8_t* __restrict__ tags,
+                                                  int32_t* __restrict__ chunk_cnt) {
+  const int64_t chunk = blockIdx.x;
+  const int ii = find_inst(chunk_start, ninst, chunk);
+  const Inst& I = insts[ii];
+  const GridD& g = I.g;
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const int64_t base64 = (chunk - I.chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
+  int cnt = 0;
+  if (base64 < g.ncell) {
+    const int base = (int)base64;
+    const int nvalid = (int)min((int64_t)kSeg, g.ncell - base64);
+    uint8_t t[kSeg];
+    int i0, j, k;
+    unlinear(g, base, i0, j, k);
+    if (nvalid == kSeg && i0 + kSeg - 1 < g.n[0]) {
+      // one row segment: radial culling on its box (face neighbours included)
+      double lo[3], hi[3];
+      lo[0] = centre(g, 0, i0) - g.h[0];
+      hi[0] = centre(g, 0, i0 + kSeg - 1) + g.h[0];
+      lo[1] = centre(g, 1, j) - g.h[1];
+      hi[1] = centre(g, 1, j) + g.h[1];
+      lo[2] = hi[2] = 0.0;
+      if (g.dim == 3) {
+        lo[2] = centre(g, 2, k) - g.h[2];
+        hi[2] = centre(g, 2, k) + g.h[2];
+      }
+      double dmin2 = 0.0, dmax2 = 0.0;
+      for (int a = 0; a < g.dim; ++a) {
+        double c = I.s.cull_c[a];
+        double dl = c < lo[a] ? lo[a] - c : (c > hi[a] ? c - hi[a] : 0.0);
+        double df = fmax(fabs(c - lo[a]), fabs(hi[a] - c));
+        dmin2 += dl * dl;
+        dmax2 += df * df;
+      }
+      int settled = -1;
+      if (sqrt(dmin2) > I.s.rmax * (1.0 + 1e-9) + 1e-300) settled = 0;
+      else if (sqrt(dmax2) < I.s.rmin * (1.0 - 1e-9)) settled = 1;
+      if (settled >= 0) {
+        for (int b = 0; b < kSeg; ++b) t[b] = (uint8_t)settled;
+      } else {
+        uint32_t row = 0;   // bits for i0-1 .. i0+16
+        for (int b = 0; b < kSeg + 2; ++b) {
+          int i = i0 - 1 + b;
+          if (i >= 0 && i < g.n[0]) row |= (uint32_t)cell_solid(I, i, j, k) << b;
+        }
+        if (i0 == 0) row = (row & ~1u) | ((row >> 1) & 1u);
+        if (i0 + kSeg >= g.n[0]) row = (row & ~(1u << (kSeg + 1))) | (((row >> kSeg) & 1u) << (kSeg + 1));
+        const uint32_t M = (1u << kSeg) - 1;
+        uint32_t self = (row >> 1) & M;
+        uint32_t diff = (self ^ (row & M)) | (self ^ ((row >> 2) & M));
+        diff |= self ^ row_bits(I, i0, j - 1, k, self);
+        diff |= self ^ row_bits(I, i0, j + 1, k, self);
+        if (g.dim == 3) {
+          diff |= self ^ row_bits(I, i0, j, k - 1, self);
+          diff |= self ^ row_bits(I, i0, j, k + 1, self);
+        }
+        cnt = __popc(diff);
+        for (int b = 0; b < kSeg; ++b)
+          t[b] = (uint8_t)(((self >> b) & 1u) | (((diff >> b) & 1u) << 6));
+      }
+    } else {
+      // segment crossing a row end or the grid end: cell by cell
+      for (int b = 0; b < nvalid; ++b) {
+        int c = base + b, i, jj, kk;
+        unlinear(g, c, i, jj, kk);
+        bool sd = cell_solid(I, i, jj, kk);
+        bool iface = false;
+        int q[3] = {i, jj, kk};
+        for (int a = 0; a < g.dim && !iface; ++a)
+          for (int sg = -1; sg <= 1; sg += 2) {
+            int qq[3] = {q[0], q[1], q[2]};
+            qq[a] += sg;
+            if (qq[a] < 0 || qq[a] >= g.n[a]) continue;
+            if (cell_solid(I, qq[0], qq[1], qq[2]) != sd) {
+              iface = true;
+              break;
+            }
+          }
+        t[b] = (uint8_t)((sd ? 1 : 0) | (iface ? 0x40 : 0));
+        cnt += iface;
+      }
+    }
+    int8_t* dst = tags + I.cell_off + base;
+    if (nvalid == kSeg) {
+      uint4 w;
+      w.x = t[0] | (t[1] << 8) | (t[2] << 16) | ((uint32_t)t[3] << 24);
+      w.y = t[4] | (t[5] << 8) | (t[6] << 16) | ((uint32_t)t[7] << 24);
+      w.z = t[8] | (t[9] << 8) | (t[10] << 16) | ((uint32_t)t[11] << 24);
+      w.w = t[12] | (t[13] << 8) | (t[14] << 16) | ((uint32_t)t[15] << 24);
+      *reinterpret_cast<uint4*>(dst) = w;
+    } else {
+      for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)t[b];
+    }
+  }
+  if (cnt) atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_cnt[chunk] = s_cnt;
+}
+
+// --------------------------------------------------------------------------
+// 2. scans and compactions
+// --------------------------------------------------------------------------
+
+// excl[i] = sum cnt[0..i), excl[n] = total; one workgroup.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ cnt, int64_t n,
+                                               int64_t* __restrict__ excl) {
+  __shared__ int64_t sh[17];
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = threadIdx.x * per, e = min(n, b + per);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += cnt[i];
+  int64_t tot;
+  int64_t run = block_excl_scan<1024>(s, &tot, sh);
+  for (int64_t i = b; i < e; ++i) {
+    excl[i] = run;
+    run += cnt[i];
+  }
+  if (threadIdx.x == 0) excl[n] = tot;
+}
+
+// off[i] = excl[start[i]] for the instance boundaries
+__global__ void k_gather_off(const int64_t* __restrict__ excl, const int64_t* __restrict__ start,
+                             int n, int64_t* __restrict__ off) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) off[i] = excl[start[i]];
+}
+
+__global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ insts, int ninst,
+                                                       const int64_t* __restrict__ chunk_start,
+                                                       const int8_t* __restrict__ tags,
+                                                       const int32_t* __restrict__ chunk_cnt,
+                                                       const int64_t* __restrict__ chunk_excl,
+                                                       int32_t* __restrict__ if_cell) {
+  const int64_t chunk = blockIdx.x;
+  if (chunk_cnt[chunk] == 0) return;
+  __shared__ int64_t sh[5];
+  const int ii = find_inst(chunk_start, ninst, chunk);
+  const Inst& I = insts[ii];
+  const int64_t base64 = (chunk - I.chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
+  uint32_t mask = 0;
+  int base = 0;
+  if (base64 < I.g.ncell) {
+    base = (int)base64;
+    const int nvalid = (int)min((int64_t)kSeg, I.g.ncell - base64);
+    const int8_t* src = tags + I.cell_off + base;
+    for (int b = 0; b < nvalid; ++b)
+      if (src[b] & 0x40) mask |= 1u << b;
+  }
+  int64_t tot;
+  int64_t pos = chunk_excl[chunk] + block_excl_scan<256>(__popc(mask), &tot, sh);
+  while (mask) {
+    int b = __ffs(mask) - 1;
+    mask &= mask - 1;
+    if_cell[pos++] = base + b;
+  }
+}
+
+// --------------------------------------------------------------------------
+// 3. geometry and ghost tags
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_geometry(const Inst* __restrict__ insts, int ninst,
+                                                  const int64_t* __restrict__ if_off,
+                                                  const int32_t* __restrict__ if_cell,
+                                                  int8_t* __restrict__ tags,
+                                                  double* __restrict__ if_psi,
+                                                  double* __restrict__ if_n, int64_t cap,
+                                                  uint8_t* __restrict__ if_flag,
+                                                  InstInfo* __restrict__ info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= if_off[ninst]) return;
+  const int ii = find_inst(if_off, ninst, e);
+  const Inst& I = insts[ii];
+  const GridD& g = I.g;
+  const int c = if_cell[e];
+  int8_t* tp = tags + I.cell_off + c;
+  const bool solid = (*tp & 1) != 0;
+  int i, j, k;
+  unlinear(g, c, i, j, k);
+  double x[3] = {centre(g, 0, i), centre(g, 1, j), g.dim == 3 ? centre(g, 2, k) : 0.0};
+  double n[3] = {0.0, 0.0, 0.0}, psi = 0.0;
+  bool ok = project(I.s, g.dim, x, solid, n, psi);
+  if (!ok) atomicOr(&info[ii].err, kErrGeometry);
+  double sum = 0.0;
+  for (int a = 0; a < g.dim; ++a) sum += (n[a] / g.h[a]) * (n[a] / g.h[a]);
+  double dn = 1.0 / sqrt(sum);
+  bool ghost;
+  if (I.scheme == kHGC) ghost = solid ? (psi <= dn / 2.0) : (-psi < dn / 2.0);
+  else ghost = solid;
+  *tp = ghost ? (solid ? 2 : -2) : (solid ? 1 : 0);
+  if_psi[e] = psi;
+  for (int a = 0; a < 3; ++a) if_n[a * cap + e] = n[a];
+  if_flag[e] = ghost ? 1 : 0;
+}
+
+// per 1024-entry block counts of flags
+__global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ flag, int64_t n,
+                                                     int32_t* __restrict__ cnt) {
+  __shared__ int s;
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  int c = 0;
+  for (int t = 0; t < 4; ++t) {
+    int64_t e = (int64_t)blockIdx.x * 1024 + t * 256 + threadIdx.x;
+    if (e < n) c += flag[e];
+  }
+  if (c) atomicAdd(&s, c);
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_scatter_ghosts(
+    const uint8_t* __restrict__ flag, int64_t n, const int64_t* __restrict__ blk_excl,
+    const int32_t* __restrict__ if_cell, const double* __restrict__ if_psi,
+    const double* __restrict__ if_n, int64_t cap, int32_t* __restrict__ g_cell,
+    double* __restrict__ g_psi, double* __restrict__ g_n) {
+  __shared__ int64_t sh[5];
+  int64_t run = blk_excl[blockIdx.x];
+  for (int t = 0; t < 4; ++t) {
+    int64_t e = (int64_t)blockIdx.x * 1024 + t * 256 + threadIdx.x;
+    int f = (e < n) ? flag[e] : 0;
+    int64_t tot;
+    int64_t pos = run + block_excl_scan<256>(f, &tot, sh);
+    if (f) {
+      g_cell[pos] = if_cell[e];
+      g_psi[pos] = if_psi[e];
+      for (int a = 0; a < 3; ++a) g_n[a * cap + pos] = if_n[a * cap + e];
+    }
+    run += tot;
+  }
+}
+
+// ghost offsets of the instances: ghosts before interface entry if_off[i]
+__global__ void k_ghost_off(const uint8_t* __restrict__ flag, const int64_t* __restrict__ blk_excl,
+                            const int64_t* __restrict__ if_off, int ninst,
+                            int64_t* __restrict__ g_off) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > ninst) return;
+  int64_t e = if_off[i];
+  int64_t b = e / 1024;
+  int64_t s = blk_excl[b];
+  for (int64_t q = b * 1024; q < e; ++q) s += flag[q];
+  g_off[i] = s;
+}
+
+// --------------------------------------------------------------------------
+// 4. stencils and dependencies
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t find_cell(const int32_t* cells, int64_t lo, int64_t hi, int c) {
+  // cells[lo..hi) ascending; returns index or -1
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    int v = cells[mid];
+    if (v == c) return mid;
+    if (v < c) lo = mid + 1; else hi = mid;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, int ninst,
+                                              const int64_t* __restrict__ g_off,
+                                              const int32_t* __restrict__ g_cell,
+                                              const double* __restrict__ g_psi,
+                                              const double* __restrict__ g_n, int64_t cap,
+                                              const int8_t* __restrict__ tags,
+                                              uint32_t* __restrict__ g_code,
+                                              int32_t* __restrict__ deps,
+                                              InstInfo* __restrict__ info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g_off[ninst]) return;
+  const int ii = find_inst(g_off, ninst, e);
+  const Inst& I = insts[ii];
+  const GridD& g = I.g;
+  const int c = g_cell[e];
+  const double psi = g_psi[e];
+  double n[3];
+  int r[3] = {1, 1, 1};
+  for (int a = 0; a < 3; ++a) n[a] = g_n[a * cap + e];
+  if (I.scheme == kCGC_ES) {
+    // Eq. stencil_anisotropic: r_i = max(1, ceil(2 |x_1 - x_s|_i / dx_i))
+    for (int a = 0; a < g.dim; ++a) {
+      double d = psi * n[a];
+      double q = 2.0 * fabs(d) / g.h[a];
+      int ri = (int)ceil(q);
+      r[a] = ri < 1 ? 1 : ri;
+      if (r[a] > 15) {
+        atomicOr(&info[ii].err, kErrUnsupported);
+        r[a] = 15;
+      }
+    }
+  }
+  const uint32_t code = make_code(n, r, g.dim);
+  g_code[e] = code;
+  int i, j, k;
+  unlinear(g, c, i, j, k);
+  const int8_t* T = tags + I.cell_off;
+  const int np = (1 << g.dim) - 1;
+  const uint32_t skip = code_skip(code);
+  for (int m = 1; m <= np; ++m) {
+    int32_t d = -1;
+    if (!(m & skip)) {
+      if (!corner_in_grid(g, code, i, j, k, m)) {
+        atomicOr(&info[ii].err, kErrStencil);
+      } else {
+        int q = c + corner_offset(g, code, m);
+        int8_t t = T[q];
+        if (t == 1) atomicOr(&info[ii].err, kErrStencil);
+        else if (t == 2 || t == -2) d = (int32_t)find_cell(g_cell, g_off[ii], g_off[ii + 1], q);
+      }
+    }
+    deps[(int64_t)(m - 1) * cap + e] = d;
+  }
+}
+
+// --------------------------------------------------------------------------
+// 5. levels and canonical order (one workgroup per instance)
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_levels_order(
+    const Inst* __restrict__ insts, const int64_t* __restrict__ g_off,
+    const int32_t* __restrict__ deps, int64_t cap, int32_t* __restrict__ lev,
+    int32_t* __restrict__ blk_idx, int32_t* __restrict__ perm, int32_t* __restrict__ lev_off_all,
+    int32_t* __restrict__ unit_mem_all, int32_t* __restrict__ unit_cnt_all,
+    InstInfo* __restrict__ info) {
+  const int ii = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int np = (1 << insts[ii].g.dim) - 1;
+  const int64_t lo = g_off[ii];
+  const int n = (int)(g_off[ii + 1] - lo);
+  int32_t* lev_off = lev_off_all + (int64_t)ii * (kMaxLevels + 1);
+  int32_t* unit_mem = unit_mem_all + (int64_t)ii * kMaxUnits * kMaxUnit;
+  int32_t* unit_cnt = unit_cnt_all + (int64_t)ii * kMaxUnits;
+
+  __shared__ int64_t sh[17];
+  __shared__ int s_flag, s_m, s_units, s_maxunit;
+  __shared__ int32_t res[kMaxResidual];
+  __shared__ int32_t rep[kMaxResidual];
+  __shared__ int32_t slot[kMaxResidual];
+  __shared__ uint32_t reach[kMaxResidual * (kMaxResidual / 32)];
+
+  for (int g = tid; g < n; g += 1024) {
+    lev[lo + g] = 0;
+    blk_idx[lo + g] = -1;
+    perm[lo + g] = -1;
+  }
+  if (tid == 0) {
+    lev_off[0] = 0;
+    s_units = 0;
+    s_maxunit = 0;
+  }
+  __syncthreads();
+
+  int placed = 0, k = 0, maxwidth = 0;
+  bool units = false;
+  uint32_t err = 0;
+  while (placed < n) {
+    ++k;
+    if (k > kMaxLevels) {
+      err |= kErrUnsupported;
+      break;
+    }
+    int newly = 0;
+    for (int base = 0; base < n; base += 1024) {
+      const int g = base + tid;
+      bool ready = false;
+      if (g < n && lev[lo + g] == 0) {
+        const int u = units ? blk_idx[lo + g] : -1;
+        ready = true;
+        if (u < 0) {
+          for (int m = 0; m < np && ready; ++m) {
+            int32_t d = deps[(int64_t)m * cap + lo + g];
+            if (d >= 0) {
+              int ld = lev[d];
+              if (ld == 0 || ld >= k) ready = false;
+            }
+          }
+        } else {
+          // a coupled unit is ready when every ghost it needs outside the unit is placed
+          const int cntu = unit_cnt[u];
+          for (int q = 0; q < cntu && ready; ++q) {
+            int32_t w = unit_mem[u * kMaxUnit + q];
+            for (int m = 0; m < np && ready; ++m) {
+              int32_t d = deps[(int64_t)m * cap + w];
+              if (d >= 0 && blk_idx[d] != u) {
+                int ld = lev[d];
+                if (ld == 0 || ld >= k) ready = false;
+              }
+            }
+          }
+        }
+      }
+      int64_t tot;
+      int64_t pre = block_excl_scan<1024>(ready ? 1 : 0, &tot, sh);
+      if (ready) {
+        lev[lo + g] = k;
+        perm[lo + g] = placed + newly + (int)pre;
+      }
+      newly += (int)tot;
+      __syncthreads();
+    }
+    if (newly == 0) {
+      if (units) {
+        err |= kErrCycle;
+        break;
+      }
+      // Kahn stalled: the rest holds cycles.  Find their strongly connected
+      // groups from the transitive closure of the residual graph.
+      --k;
+      int64_t tot;
+      for (int base = 0, off = 0; base < n; base += 1024) {
+        const int g = base + tid;
+        const bool r = g < n && lev[lo + g] == 0;
+        int64_t pre = block_excl_scan<1024>(r ? 1 : 0, &tot, sh);
+        if (r && off + pre < kMaxResidual) res[off + pre] = g;
+        off += (int)tot;
+        if (base + 1024 >= n && tid == 0) s_m = off;
+      }
+      __syncthreads();
+      const int m = s_m;
+      if (m > kMaxResidual) {
+        err |= kErrCycle;
+        break;
+      }
+      const int W = (m + 31) / 32;
+      for (int t = tid; t < m * W; t += 1024) reach[t] = 0;
+      __syncthreads();
+      for (int u = tid; u < m; u += 1024) {
+        for (int q = 0; q < np; ++q) {
+          int32_t d = deps[(int64_t)q * cap + lo + res[u]];
+          if (d >= 0 && lev[d] == 0) {
+            int v = (int)find_cell(res, 0, m, (int)(d - lo));
+            if (v >= 0) reach[u * W + (v >> 5)] |= 1u << (v & 31);
+          }
+        }
+      }
+      __syncthreads();
+      do {
+        if (tid == 0) s_flag = 0;
+        __syncthreads();
+        int changed = 0;
+        for (int u = tid; u < m; u += 1024) {
+          for (int q = 0; q < np; ++q) {
+            int32_t d = deps[(int64_t)q * cap + lo + res[u]];
+            if (d < 0 || lev[d] != 0) continue;
+            int v = (int)find_cell(res, 0, m, (int)(d - lo));
+            if (v < 0) continue;
+            for (int w = 0; w < W; ++w) {
+              uint32_t o = reach[u * W + w], nw = o | reach[v * W + w];
+              if (nw != o) {
+                reach[u * W + w] = nw;
+                changed = 1;
+              }
+            }
+          }
+        }
+        if (changed) s_flag = 1;
+        __syncthreads();
+      } while (s_flag);
+      // representative = smallest member of the group; -1 off cycles
+      for (int u = tid; u < m; u += 1024) {
+        int rp = -1;
+        if ((reach[u * W + (u >> 5)] >> (u & 31)) & 1u) {
+          for (int v = 0; v < m; ++v)
+            if (((reach[u * W + (v >> 5)] >> (v & 31)) & 1u) &&
+                ((reach[v * W + (u >> 5)] >> (u & 31)) & 1u)) {
+              rp = v;
+              break;
+            }
+        }
+        rep[u] = rp;
+      }
+      __syncthreads();
+      // slots in residual order
+      {
+        int off = 0;
+        for (int base = 0; base < m; base += 1024) {
+          int u = base + tid;
+          bool isrep = u < m && rep[u] == u;
+          int64_t pre = block_excl_scan<1024>(isrep ? 1 : 0, &tot, sh);
+          if (isrep) slot[u] = off + (int)pre;
+          off += (int)tot;
+        }
+        if (tid == 0) s_units = off;
+      }
+      __syncthreads();
+      if (s_units > kMaxUnits) {
+        err |= kErrCycle;
+        break;
+      }
+      for (int u = tid; u < m; u += 1024) {
+        int rp = rep[u];
+        if (rp < 0) continue;
+        int sl = slot[rp], rank = 0, size = 0;
+        for (int v = 0; v < m; ++v)
+          if (rep[v] == rp) {
+            if (v < u) ++rank;
+            ++size;
+          }
+        if (size > kMaxUnit) {
+          atomicOr(&info[ii].err, kErrCycle);
+          continue;
+        }
+        unit_mem[sl * kMaxUnit + rank] = (int32_t)(lo + res[u]);
+        blk_idx[lo + res[u]] = sl;
+        if (u == rp) {
+          unit_cnt[sl] = size;
+          atomicMax(&s_maxunit, size);
+        }
+      }
+      // restart the layering with the units: a unit's level is one more than
+      // the deepest level it needs, as if it had been known from the start
+      for (int g = tid; g < n; g += 1024) {
+        lev[lo + g] = 0;
+        perm[lo + g] = -1;
+      }
+      __syncthreads();
+      units = true;
+      placed = 0;
+      k = 0;
+      maxwidth = 0;
+      continue;
+    }
+    placed += newly;
+    maxwidth = max(maxwidth, newly);
+    if (tid == 0) lev_off[k] = placed;
+  }
+  if (tid == 0) {
+    if (err) atomicOr(&info[ii].err, err);
+    info[ii].nlev = k;
+    info[ii].maxwidth = maxwidth;
+    info[ii].nunits = units ? s_units : 0;
+    info[ii].maxunit = s_maxunit;
+  }
+}
+
+// --------------------------------------------------------------------------
+// 6. canonical arrays
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* a, double v) {
+  if (v > 0.0) atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(256) void k_finalize(
+    const Inst* __restrict__ insts, int ninst, const int64_t* __restrict__ g_off, int64_t cap,
+    const int32_t* __restrict__ g_cell, const double* __restrict__ g_psi,
+    const double* __restrict__ g_n, const uint32_t* __restrict__ g_code,
+    const int32_t* __restrict__ lev, const int32_t* __restrict__ blk_idx,
+    const int32_t* __restrict__ perm, int32_t* __restrict__ cell, double* __restrict__ delta,
+    double* __restrict__ nrm, double* __restrict__ psi, uint32_t* __restrict__ code,
+    int32_t* __restrict__ level, int32_t* __restrict__ blk, InstInfo* __restrict__ info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ng_all = g_off[ninst];
+  // per-thread statistics: max alpha and multiplier per axis, fluid-side count
+  double am[3] = {0.0, 0.0, 0.0};
+  int rm[3] = {0, 0, 0}, fl = 0, ii = -1;
+  if (e < ng_all) {
+    ii = find_inst(g_off, ninst, e);
+    const GridD& g = insts[ii].g;
+    const int pl = perm[e];
+    if (pl >= 0 && pl < g_off[ii + 1] - g_off[ii]) {   // else the build failed earlier
+      const int64_t p = g_off[ii] + pl;
+      const double ps = g_psi[e];
+      const uint32_t cd = g_code[e];
+      cell[p] = g_cell[e];
+      psi[p] = ps;
+      code[p] = cd;
+      level[p] = lev[e];
+      blk[p] = blk_idx[e];
+      for (int a = 0; a < 3; ++a) {
+        double na = g_n[a * cap + e];
+        double da = ps * na;
+        nrm[a * cap + p] = na;
+        delta[a * cap + p] = da;
+        if (a < g.dim) {
+          double X = (double)(code_e(cd, a) * code_r(cd, a)) * g.h[a];
+          am[a] = fmax(0.0, da / X);
+          rm[a] = code_r(cd, a);
+        }
+      }
+      fl = ps < 0.0 ? 1 : 0;
+    }
+  }
+  // one instance in the whole workgroup: reduce there, one atomic per value
+  __shared__ int s_i0;
+  __shared__ double s_am[3][256];
+  __shared__ int s_rm[3][256], s_fl[256];
+  if (threadIdx.x == 0) s_i0 = ii;
+  __syncthreads();
+  const bool uniform = __syncthreads_and(ii == s_i0 || ii < 0) && s_i0 >= 0;
+  if (!uniform) {
+    if (ii >= 0) {
+      for (int a = 0; a < 3; ++a) {
+        atomic_max_nonneg(&info[ii].max_alpha_bits[a], am[a]);
+        if (rm[a]) atomicMax(&info[ii].rmax[a], rm[a]);
+      }
+      if (fl) atomicAdd(&info[ii].nfluid, 1);
+    }
+    return;
+  }
+  for (int a = 0; a < 3; ++a) {
+    s_am[a][threadIdx.x] = am[a];
+    s_rm[a][threadIdx.x] = rm[a];
+  }
+  s_fl[threadIdx.x] = fl;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int a = 0; a < 3; ++a) {
+        s_am[a][threadIdx.x] = fmax(s_am[a][threadIdx.x], s_am[a][threadIdx.x + s]);
+        s_rm[a][threadIdx.x] = max(s_rm[a][threadIdx.x], s_rm[a][threadIdx.x + s]);
+      }
+      s_fl[threadIdx.x] += s_fl[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int i0 = s_i0;
+    for (int a = 0; a < 3; ++a) {
+      atomic_max_nonneg(&info[i0].max_alpha_bits[a], s_am[a][0]);
+      if (s_rm[a][0]) atomicMax(&info[i0].rmax[a], s_rm[a][0]);
+    }
+    if (s_fl[0]) atomicAdd(&info[i0].nfluid, s_fl[0]);
+  }
+}
+
+// unit members: linear-order positions -> instance-local canonical positions
+__global__ void k_units_canonical(const int32_t* __restrict__ perm,
+                                  const InstInfo* __restrict__ info,
+                                  int32_t* __restrict__ unit_mem_all,
+                                  const int32_t* __restrict__ unit_cnt_all) {
+  const int ii = blockIdx.x;
+  const int nu = info[ii].nunits;
+  int32_t* um = unit_mem_all + (int64_t)ii * kMaxUnits * kMaxUnit;
+  const int32_t* uc = unit_cnt_all + (int64_t)ii * kMaxUnits;
+  for (int t = threadIdx.x; t < nu * kMaxUnit; t += blockDim.x) {
+    int u = t / kMaxUnit, q = t % kMaxUnit;
+    if (q < uc[u]) um[t] = perm[um[t]];
+  }
+}
+
+// --------------------------------------------------------------------------
+// host orchestration
+// --------------------------------------------------------------------------
+
+static double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= (double)i;
+  return f;
+}
+
+static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme, Inst* I) {
+  std::memset(I, 0, sizeof(Inst));
+  if (gg.dim != 2 && gg.dim != 3) return GCR_E_ARG;
+  if (scheme < 0 || scheme > 2) return GCR_E_ARG;
+  int64_t ncell = 1;
+  for (int a = 0; a < gg.dim; ++a) {
+    if (gg.n[a] < 1 || !(gg.h[a] > 0.0) || !std::isfinite(gg.lo[a])) return GCR_E_ARG;
+    ncell *= gg.n[a];
+    if (ncell >= (int64_t(1) << 31)) return GCR_E_UNSUPPORTED;
+  }
+  I->g.dim = gg.dim;
+  for (int a = 0; a < 3; ++a) {
+    I->g.n[a] = a < gg.dim ? (int)gg.n[a] : 1;
+    I->g.lo[a] = a < gg.dim ? gg.lo[a] : 0.0;
+    I->g.h[a] = a < gg.dim ? gg.h[a] : 1.0;
+  }
+  I->g.ncell = ncell;
+  I->scheme = scheme;
+  ShapeD& s = I->s;
+  s.kind = gs.kind;
+  for (int a = 0; a < 3; ++a) s.c[a] = a < gg.dim ? gs.center[a] : 0.0;
+  s.r0 = gs.r0;
+  if (gs.kind == kSphere) {
+    if (!(gs.r0 > 0.0)) return GCR_E_ARG;
+    for (int a = 0; a < 3; ++a) s.cull_c[a] = s.c[a];
+    s.rmin = s.rmax = gs.r0;
+  } else if (gs.kind == kStar2D) {
+    if (gg.dim != 2 || !(gs.r0 > 0.0) || gs.ncoef < 0 || 2 * gs.ncoef > kMaxCoef) return GCR_E_ARG;
+    if (gs.ncoef > 0 && !gs.coef) return GCR_E_ARG;
+    s.ncoef = gs.ncoef;
+    double sa = 0.0;
+    for (int q = 0; q < 2 * gs.ncoef; ++q) {
+      s.coef[q] = gs.coef[q];
+      sa += std::fabs(gs.coef[q]);
+    }
+    for (int a = 0; a < 3; ++a) s.cull_c[a] = s.c[a];
+    s.rmin = std::max(0.0, gs.r0 * (1.0 - sa));
+    s.rmax = gs.r0 * (1.0 + sa);
+  } else if (gs.kind == kShStar) {
+    int L = (int)std::lround(std::sqrt((double)gs.ncoef)) - 1;
+    if (gg.dim != 3 || !(gs.r0 > 0.0) || L < 0 || (L + 1) * (L + 1) != gs.ncoef || L > 8 ||
+        !gs.coef)
+      return GCR_E_ARG;
+    s.ncoef = gs.ncoef;
+    s.L = L;
+    double sa = 0.0;
+    for (int l = 0; l <= L; ++l)
+      for (int m = -l; m <= l; ++m) {
+        int am = m < 0 ? -m : m;
+        double N = am == 0 ? 1.0 : std::sqrt(2.0 * factorial(l - am) / factorial(l + am));
+        s.coef[l * l + l + m] = gs.coef[l * l + l + m] * N;
+        sa += std::fabs(gs.coef[l * l + l + m]);   // |Y_lm| <= 1 (Schmidt)
+      }
+    for (int a = 0; a < 3; ++a) s.cull_c[a] = s.c[a];
+    s.rmin = std::max(0.0, gs.r0 * (1.0 - sa));
+    s.rmax = gs.r0 * (1.0 + sa);
+  } else if (gs.kind == kAirfoil) {
+    if (gg.dim != 2 || !(gs.chord > 0.0) || !(gs.thickness > 0.0) || gs.thickness > 0.5)
+      return GCR_E_ARG;
+    s.chord = gs.chord;
+    s.thick = gs.thickness;
+    s.ca = std::cos(gs.incidence);
+    s.sa = std::sin(gs.incidence);
+    // mid-chord in world coordinates; the section lies within 0.51 chords of it
+    s.cull_c[0] = s.c[0] + gs.chord * (s.ca * 0.5);
+    s.cull_c[1] = s.c[1] + gs.chord * (-s.sa * 0.5);
+    s.rmin = 0.0;
+    s.rmax = 0.51 * gs.chord;
+  } else {
+    return GCR_E_ARG;
+  }
+  return GCR_OK;
+}
+
+BatchData::~BatchData() {
+  for (void* p : owned) pool_free(p);
+}
+
+template <class T>
+static T* own(BatchData& B, size_t n) {
+  T* p = palloc<T>(n);
+  if (p) B.owned.push_back(p);
+  return p;
+}
+
+gcr_status status_from_err(uint32_t err) {
+  if (err & kErrGeometry) return GCR_E_GEOMETRY;
+  if (err & kErrCycle) return GCR_E_CYCLE;
+  if (err & kErrStencil) return GCR_E_STENCIL;
+  if (err & kErrDegenerate) return GCR_E_DEGENERATE;
+  if (err & kErrUnsupported) return GCR_E_UNSUPPORTED;
+  return GCR_OK;
+}
+
+static inline unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// stage timing (process-wide switch, per-thread results)
+static std::atomic<int> g_profiling{0};
+static thread_local float g_stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+struct StageEvents {
+  hipEvent_t ev[10] = {};
+  bool on = false;
+  explicit StageEvents(bool enable) : on(enable) {
+    if (on)
+      for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) on = false;
+  }
+  void mark(int i, hipStream_t st) {
+    if (on) (void)hipEventRecord(ev[i], st);
+  }
+  void collect() {
+    if (!on) return;
+    const int a[8] = {0, 1, 3, 4, 5, 6, 7, 8}, b[8] = {1, 2, 4, 5, 6, 7, 8, 9};
+    for (int s = 0; s < 8; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[a[s]], ev[b[s]]) != hipSuccess) ms = -1.f;
+      g_stage_ms[s] = ms;
+    }
+  }
+  ~StageEvents() {
+    if (on)
+      for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+void set_profiling(int on) { g_profiling.store(on ? 1 : 0); }
+void last_build_times(float* ms) {
+  for (int s = 0; s < 8; ++s) ms[s] = g_stage_ms[s];
+}
+
+gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes,
+                       const int32_t* schemes, hipStream_t st, std::shared_ptr<BatchData>* out) {
+  if (ninst < 1 || !grids || !shapes || !schemes || !out) return GCR_E_ARG;
+  auto B = std::make_shared<BatchData>();
+  B->ninst = ninst;
+  B->inst.resize(ninst);
+  std::vector<int64_t> chunk_start(ninst + 1);
+  int64_t cells = 0, chunks = 0;
+  for (int i = 0; i < ninst; ++i) {
+    gcr_status s = make_inst(grids[i], shapes[i], schemes[i], &B->inst[i]);
+    if (s != GCR_OK) return s;
+    Inst& I = B->inst[i];
+    I.cell_off = cells;
+    cells += (I.g.ncell + 255) / 256 * 256;
+    I.chunk_off = chunks;
+    I.nchunk = (I.g.ncell + kChunk - 1) / kChunk;
+    chunk_start[i] = chunks;
+    chunks += I.nchunk;
+  }
+  chunk_start[ninst] = chunks;
+  B->ncells_total = cells;
+  B->nchunks = chunks;
+
+  BatchData& D = *B;
+  D.d_inst = own<Inst>(D, ninst);
+  D.d_tags = own<int8_t>(D, cells);
+  D.d_chunk_start = own<int64_t>(D, ninst + 1);
+  D.d_chunk_cnt = own<int32_t>(D, chunks);
+  D.d_chunk_excl = own<int64_t>(D, chunks + 1);
+  D.d_if_off = own<int64_t>(D, ninst + 1);
+  D.d_g_off = own<int64_t>(D, ninst + 1);
+  D.d_info = own<InstInfo>(D, ninst);
+  D.d_lev_off = own<int32_t>(D, (size_t)ninst * (kMaxLevels + 1));
+  D.d_unit_mem = own<int32_t>(D, (size_t)ninst * kMaxUnits * kMaxUnit);
+  D.d_unit_cnt = own<int32_t>(D, (size_t)ninst * kMaxUnits);
+  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl ||
+      !D.d_if_off || !D.d_g_off || !D.d_info || !D.d_lev_off || !D.d_unit_mem || !D.d_unit_cnt)
+    return GCR_E_NOMEM;
+  GCR_HIP(hipMemcpyAsync(D.d_inst, D.inst.data(), sizeof(Inst) * ninst, hipMemcpyHostToDevice, st));
+  GCR_HIP(hipMemcpyAsync(D.d_chunk_start, chunk_start.data(), sizeof(int64_t) * (ninst + 1),
+                         hipMemcpyHostToDevice, st));
+  GCR_HIP(hipMemsetAsync(D.d_info, 0, sizeof(InstInfo) * ninst, st));
+
+  StageEvents T(g_profiling.load() != 0);
+  T.mark(0, st);
+  k_classify<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
+                                                D.d_chunk_cnt);
+  T.mark(1, st);
+  k_scan<<<1, 1024, 0, st>>>(D.d_chunk_cnt, chunks, D.d_chunk_excl);
+  k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
+                                                     D.d_if_off);
+  T.mark(2, st);
+  GCR_HIP(hipGetLastError());
+  D.if_off.resize(ninst + 1);
+  GCR_HIP(hipMemcpyAsync(D.if_off.data(), D.d_if_off, sizeof(int64_t) * (ninst + 1),
+                         hipMemcpyDeviceToHost, st));
+  GCR_HIP(hipStreamSynchronize(st));
+  const int64_t nif = D.if_off[ninst];
+  const int64_t cap = std::max<int64_t>(nif, 1);
+  D.nif = nif;
+  D.cap = cap;
+  const int64_t nblk = (nif + 1023) / 1024;
+  D.d_if_cell = own<int32_t>(D, cap);
+  D.d_if_psi = own<double>(D, cap);
+  D.d_if_n = own<double>(D, 3 * cap);
+  D.d_if_flag = own<uint8_t>(D, cap);
+  D.d_blkcnt = own<int32_t>(D, nblk + 1);
+  D.d_blkexcl = own<int64_t>(D, nblk + 2);
+  D.d_g_cell = own<int32_t>(D, cap);
+  D.d_g_psi = own<double>(D, cap);
+  D.d_g_n = own<double>(D, 3 * cap);
+  D.d_g_code = own<uint32_t>(D, cap);
+  D.d_deps = own<int32_t>(D, 7 * cap);
+  D.d_lev = own<int32_t>(D, cap);
+  D.d_blk_idx = own<int32_t>(D, cap);
+  D.d_perm = own<int32_t>(D, cap);
+  D.d_cell = own<int32_t>(D, cap);
+  D.d_delta = own<double>(D, 3 * cap);
+  D.d_nrm = own<double>(D, 3 * cap);
+  D.d_psi = own<double>(D, cap);
+  D.d_code = own<uint32_t>(D, cap);
+  D.d_level = own<int32_t>(D, cap);
+  D.d_blk = own<int32_t>(D, cap);
+  if (!D.d_if_cell || !D.d_if_psi || !D.d_if_n || !D.d_if_flag || !D.d_blkcnt || !D.d_blkexcl ||
+      !D.d_g_cell || !D.d_g_psi || !D.d_g_n || !D.d_g_code || !D.d_deps || !D.d_lev ||
+      !D.d_blk_idx || !D.d_perm || !D.d_cell || !D.d_delta || !D.d_nrm || !D.d_psi ||
+      !D.d_code || !D.d_level || !D.d_blk)
+    return GCR_E_NOMEM;
+  // the third normal component of 2D ghosts stays zero
+  GCR_HIP(hipMemsetAsync(D.d_if_n + 2 * cap, 0, sizeof(double) * cap, st));
+
+  T.mark(3, st);
+  if (nif > 0) {
+    k_compact_iface<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
+                                                      D.d_chunk_cnt, D.d_chunk_excl, D.d_if_cell);
+    T.mark(4, st);
+    k_geometry<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_if_off, D.d_if_cell,
+                                                  D.d_tags, D.d_if_psi, D.d_if_n, cap,
+                                                  D.d_if_flag, D.d_info);
+    T.mark(5, st);
+    k_count_flags<<<(unsigned)nblk, 256, 0, st>>>(D.d_if_flag, nif, D.d_blkcnt);
+    k_scan<<<1, 1024, 0, st>>>(D.d_blkcnt, nblk, D.d_blkexcl);
+    k_scatter_ghosts<<<(unsigned)nblk, 256, 0, st>>>(D.d_if_flag, nif, D.d_blkexcl, D.d_if_cell,
+                                                     D.d_if_psi, D.d_if_n, cap, D.d_g_cell,
+                                                     D.d_g_psi, D.d_g_n);
+    k_ghost_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_if_flag, D.d_blkexcl, D.d_if_off, ninst,
+                                                      D.d_g_off);
+    T.mark(6, st);
+    // ghost count unknown on the host: launch over the interface capacity
+    k_deps<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_g_off, D.d_g_cell, D.d_g_psi,
+                                              D.d_g_n, cap, D.d_tags, D.d_g_code, D.d_deps,
+                                              D.d_info);
+    T.mark(7, st);
+    k_levels_order<<<ninst, 1024, 0, st>>>(D.d_inst, D.d_g_off, D.d_deps, cap, D.d_lev,
+                                            D.d_blk_idx, D.d_perm, D.d_lev_off, D.d_unit_mem,
+                                            D.d_unit_cnt, D.d_info);
+    T.mark(8, st);
+    k_finalize<<<blocks(nif, 256), 256, 0, st>>>(
+        D.d_inst, ninst, D.d_g_off, cap, D.d_g_cell, D.d_g_psi, D.d_g_n, D.d_g_code, D.d_lev,
+        D.d_blk_idx, D.d_perm, D.d_cell, D.d_delta, D.d_nrm, D.d_psi, D.d_code, D.d_level,
+        D.d_blk, D.d_info);
+    k_units_canonical<<<ninst, 256, 0, st>>>(D.d_perm, D.d_info, D.d_unit_mem, D.d_unit_cnt);
+    T.mark(9, st);
+  } else {
+    for (int i = 4; i <= 9; ++i) T.mark(i, st);
+    GCR_HIP(hipMemsetAsync(D.d_g_off, 0, sizeof(int64_t) * (ninst + 1), st));
+    GCR_HIP(hipMemsetAsync(D.d_lev_off, 0, sizeof(int32_t) * ninst * (kMaxLevels + 1), st));
+  }
+  GCR_HIP(hipGetLastError());
+  D.g_off.resize(ninst + 1);
+  D.info.resize(ninst);
+  D.lev_off.resize((size_t)ninst * (kMaxLevels + 1));
+  GCR_HIP(hipMemcpyAsync(D.g_off.data(), D.d_g_off, sizeof(int64_t) * (ninst + 1),
+                         hipMemcpyDeviceToHost, st));
+  GCR_HIP(hipMemcpyAsync(D.info.data(), D.d_info, sizeof(InstInfo) * ninst, hipMemcpyDeviceToHost,
+                         st));
+  GCR_HIP(hipMemcpyAsync(D.lev_off.data(), D.d_lev_off,
+                         sizeof(int32_t) * ninst * (kMaxLevels + 1), hipMemcpyDeviceToHost, st));
+  GCR_HIP(hipStreamSynchronize(st));
+  T.collect();
+  D.ng_total = D.g_off[ninst];
+  for (int i = 0; i < ninst; ++i) {
+    gcr_status s = status_from_err(D.info[i].err);
+    if (s != GCR_OK) return s;
+  }
+  *out = B;
+  return GCR_OK;
+}
+
+void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p) {
+  const BatchData& D = *B;
+  p->batch = B;
+  p->index = i;
+  p->inst = D.inst[i];
+  p->dim = p->inst.g.dim;
+  p->ncell = p->inst.g.ncell;
+  p->goff = D.g_off[i];
+  p->ng = D.g_off[i + 1] - D.g_off[i];
+  p->nif = D.if_off[i + 1] - D.if_off[i];
+  p->stride = D.cap;
+  p->info = D.info[i];
+  p->nlev = p->info.nlev;
+  p->lev_off.assign(D.lev_off.begin() + (size_t)i * (kMaxLevels + 1),
+                    D.lev_off.begin() + (size_t)i * (kMaxLevels + 1) + p->nlev + 1);
+  p->tags = D.d_tags + p->inst.cell_off;
+  const int64_t o = p->goff;
+  if (D.d_cell) {
+    p->cell = D.d_cell + o;
+    for (int a = 0; a < 3; ++a) {
+      p->delta[a] = D.d_delta + a * D.cap + o;
+      p->nrm[a] = D.d_nrm + a * D.cap + o;
+    }
+    p->psi = D.d_psi + o;
+    p->code = D.d_code + o;
+    p->level = D.d_level + o;
+    p->blk = D.d_blk + o;
+    p->sorted_cell = D.d_g_cell + o;
+    p->sorted_pos = D.d_perm + o;
+  }
+  p->unit_mem = D.d_unit_mem + (int64_t)i * kMaxUnits * kMaxUnit;
+  p->unit_cnt = D.d_unit_cnt + (int64_t)i * kMaxUnits;
+  p->d_lev_off = D.d_lev_off + (int64_t)i * (kMaxLevels + 1);
+}
+
+}  // namespace gcr

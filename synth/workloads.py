@@ -399,7 +399,7 @@ def airfoil_queries(shape: Shape, m=1024):
     x = np.stack([shape.center[0] + ch * (ca * bx + sa * by), shape.center[1] + ch * (-sa * bx + ca * by)])
     T = np.stack([ca * tx + sa * ty, -sa * tx + ca * ty]) * ch
     ds = np.hypot(T[0], T[1])
-    n = np.stack([T[1], -T[0]]) / ds
+    n = np.stack([-T[1], T[0]]) / ds   # contour is clockwise in s
     w = ds * (2.0 / (2 * m))
     return Queries(x, n, w)
 

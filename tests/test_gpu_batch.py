@@ -1,0 +1,146 @@
+"""GPU parity of the batched path: plans of many uneven instances built by
+shared launches, and the persistent batched forward (fill of several fields
+with mixed Dirichlet/Neumann data + force), against the oracle per instance
+and against the single-instance path."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import HGC
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gcr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_10165_amd as g
+    g.lib()
+    return g
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def ghost_centres(op):
+    g = op.grid
+    c = op.ghost_cell
+    return np.stack([g.lo[0] + (c % g.n[0] + 0.5) * g.h[0],
+                     g.lo[1] + (c // g.n[0] + 0.5) * g.h[1]])
+
+
+def run_batch(gcr, insts, with_forces=True):
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
+    nf = 3
+    ops, fields, bcv, bct, host_in, wants = [], [], [], [], [], []
+    for inst, plan in zip(insts, B.plans):
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        ops.append(op)
+        S = ghost_centres(op) + op.delta
+        kinds = [synth.mixed_kinds(S, inst.shape.center, b) for b in inst.mixed_beta]
+        vals = np.stack([synth.sample(f, inst.grid) for f in inst.fields])
+        vals[:, op.tags != 0] = np.nan
+        b = np.stack([synth.bc_values(f, S, op.normal, k) for f, k in zip(inst.fields, kinds)])
+        want = op.fill(vals.copy(), np.stack(kinds), b)
+        sc = op.fill_scale(np.nan_to_num(vals), np.stack(kinds), b)
+        wants.append((want, sc))
+        host_in.append(vals)
+        for f in range(nf):
+            fields.append(dev(vals[f]))
+            bcv.append(dev(b[f]))
+            bct.append(dev(kinds[f], torch.uint8))
+    kw = {}
+    F = None
+    if with_forces:
+        nq = [i.queries.x.shape[1] for i in insts]
+        xq = [dev(i.queries.x) for i in insts]
+        nr = [dev(i.queries.n) for i in insts]
+        wq = [dev(i.queries.w) for i in insts]
+        F = torch.zeros((len(insts), 3), dtype=torch.float64, device="cuda")
+        kw = dict(nq=nq, xq=xq, nrm=nr, wq=wq, p_field=2, u_first=0, mu=0.9, F=F)
+    B.forward(nf, fields, [2, 2, 2], bcv, bc_type=bct, **kw)
+    torch.cuda.synchronize()
+    return B, ops, fields, wants, F
+
+
+def test_batch_plans_match_single_plans(gcr):
+    insts = synth.stars64(seed=5, ninst=6, nmin=96, nmax=600)
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
+    for inst, bp in zip(insts, B.plans):
+        sp = gcr.Plan(inst.grid, inst.shape, HGC)
+        a, b = bp.export(), sp.export()
+        torch.cuda.synchronize()
+        for k in ("tags", "cell", "level", "r", "unit"):
+            assert torch.equal(a[k], b[k]), k
+        for k in ("delta", "normal", "psi"):
+            assert torch.equal(a[k], b[k]), k
+        assert bp.level_offsets() == sp.level_offsets()
+
+
+def test_batch_forward_matches_oracle(gcr):
+    insts = synth.stars64(seed=6, ninst=8, nmin=96, nmax=500)
+    B, ops, fields, wants, F = run_batch(gcr, insts)
+    nf = 3
+    for i, (op, (want, sc)) in enumerate(zip(ops, wants)):
+        for f in range(nf):
+            got = host(fields[i * nf + f])
+            err = np.abs(got[op.ghost_cell] - want[f][op.ghost_cell])
+            assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][op.ghost_cell]), sc[f])), (i, f)
+        inst = insts[i]
+        q = inst.queries
+        Fo = op.forces(q.x, q.n, q.w, want[2], want[:2], 0.9)
+        s = np.abs(q.w).sum() * (np.nanmax(np.abs(want)) * 50 / inst.grid.h[0])
+        assert np.all(np.abs(host(F[i])[:2] - Fo) <= 1e-12 * np.maximum(np.abs(Fo), s)), (i, F[i], Fo)
+
+
+def test_batch_forward_full_size_sampled(gcr):
+    """64 instances, n ~ U{128..2048}: the whole batch runs; 4 instances are
+    checked against the oracle."""
+    insts = synth.stars64(seed=0)
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
+    nf = 3
+    rng = np.random.default_rng(0)
+    check = set(rng.choice(len(insts), 4, replace=False).tolist())
+    fields, bcv, bct, ref = [], [], [], {}
+    for k, (inst, plan) in enumerate(zip(insts, B.plans)):
+        ex = plan.export()
+        c = ex["cell"].to(torch.int64)
+        g = inst.grid
+        S = torch.stack([g.lo[0] + (c % g.n[0] + 0.5) * g.h[0],
+                         g.lo[1] + (c // g.n[0] + 0.5) * g.h[1]]) + ex["delta"]
+        Sh, nh = host(S), host(ex["normal"])
+        kinds = [synth.mixed_kinds(Sh, inst.shape.center, b) for b in inst.mixed_beta]
+        vals = np.stack([synth.sample(f, g) for f in inst.fields])
+        b = np.stack([synth.bc_values(f, Sh, nh, kk) for f, kk in zip(inst.fields, kinds)])
+        for f in range(nf):
+            fields.append(dev(vals[f]))
+            bcv.append(dev(b[f]))
+            bct.append(dev(kinds[f], torch.uint8))
+        if k in check:
+            ref[k] = (vals, b, np.stack(kinds))
+    nq = [i.queries.x.shape[1] for i in insts]
+    F = torch.zeros((len(insts), 3), dtype=torch.float64, device="cuda")
+    B.forward(nf, fields, [2, 2, 2], bcv, bc_type=bct, nq=nq,
+              xq=[dev(i.queries.x) for i in insts], nrm=[dev(i.queries.n) for i in insts],
+              wq=[dev(i.queries.w) for i in insts], p_field=2, u_first=0, mu=1.0, F=F)
+    torch.cuda.synchronize()
+    assert torch.isfinite(F).all()
+    for k in sorted(check):
+        inst = insts[k]
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        assert op.n_ghost == B.plans[k].n_ghost
+        vals, b, kinds = ref[k]
+        want = op.fill(vals.copy(), kinds, b)
+        sc = op.fill_scale(vals, kinds, b)
+        for f in range(nf):
+            got = host(fields[k * nf + f])
+            err = np.abs(got[op.ghost_cell] - want[f][op.ghost_cell])
+            assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][op.ghost_cell]), sc[f]))

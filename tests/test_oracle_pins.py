@@ -643,3 +643,28 @@ def test_margins_of_standard_seeds():
         inst = synth.circle128(seed=seed)
         for scheme in (CGC, CGC_ES, HGC):
             assert oracle.OraclePlan(inst.grid, inst.shape, scheme).min_margin > 1e-9
+
+
+@pytest.mark.parametrize("which", ["circle", "star", "shstar", "airfoil"])
+def test_normals_point_into_fluid(which):
+    """n is the unit normal pointing into the fluid (Sec. 3.1): a step along
+    +n from S leaves the body, a step along -n enters it."""
+    if which == "circle":
+        inst = synth.circle128(seed=0)
+    elif which == "star":
+        inst = synth.stars64(seed=3, ninst=1, nmin=300, nmax=300)[0]
+    elif which == "shstar":
+        inst = synth.shstar384(seed=0, n=48, nt=4, nph=8)
+    else:
+        inst = synth.airfoil4096(seed=0, n=512, m=64)
+    p = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+    S = ghost_centres(p) + p.delta
+    eps = 1e-7
+    for g in range(0, p.n_ghost, max(1, p.n_ghost // 100)):
+        assert not oracle.inside(inst.shape, p.dim, S[:, g] + eps * p.normal[:, g])
+        assert oracle.inside(inst.shape, p.dim, S[:, g] - eps * p.normal[:, g])
+        assert abs(np.linalg.norm(p.normal[:, g]) - 1) < 1e-14
+    if which in ("circle", "star", "airfoil"):
+        q = inst.queries
+        for k in range(0, q.x.shape[1], max(1, q.x.shape[1] // 50)):
+            assert not oracle.inside(inst.shape, p.dim, q.x[:, k] + 1e-6 * q.n[:, k])
