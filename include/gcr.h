@@ -113,7 +113,7 @@ typedef struct {
  * multipliers (Eq. stencil_anisotropic for CGC_ES), the ghost dependency
  * graph and its Kahn levels (Sec. 3.2).  Where the graph is not acyclic
  * (concave bodies), each strongly connected group of ghosts forms one unit
- * whose relations are solved together; units have at most 16 ghosts, else
+ * whose relations are solved together; units have at most 8 ghosts, else
  * GCR_E_CYCLE.  grid, shape: host.  Synchronises `stream`.  The plan owns
  * all its device memory; *out is NULL on error. */
 gcr_status gcr_plan_create(const gcr_grid* grid, const gcr_shape* shape,

@@ -57,7 +57,7 @@ struct orc_plan {
   double margins[7];
 };
 
-#define ORC_MAX_BLOCK 16
+#define ORC_MAX_BLOCK 8
 
 /* ------------------------------------------------------------------------- */
 /* grid helpers                                                              */

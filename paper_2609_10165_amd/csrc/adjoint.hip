@@ -85,109 +85,88 @@ __device__ __forceinline__ void for_each_reader(const PlanD& P, int c, Fn fn) {
   }
 }
 
-// Adjoint of a coupled unit: (I - W_int)^T mu = lam + external pulls.
+// Adjoint of coupled unit u at level `level`: (I - W_int)^T mu = lam +
+// external pulls, solved in an LDS workspace (one unit per thread).
 template <int D>
-__device__ __noinline__ void adj_unit(const AdjArgs& A, int u) {
+__device__ __forceinline__ void adj_unit(const AdjArgs& A, int u, UnitWS& ws) {
   const PlanD& P = A.P;
   const int k = P.unit_cnt[u];
-  int mem[kMaxUnit], cel[kMaxUnit];
   for (int i = 0; i < k; ++i) {
-    mem[i] = P.unit_mem[u * kMaxUnit + i];
-    cel[i] = P.cell[mem[i]];
+    ws.mem[i] = P.unit_mem[u * kMaxUnit + i];
+    ws.cel[i] = P.cell[ws.mem[i]];
   }
   for (int f = 0; f < A.nf; ++f) {
-    double M[kMaxUnit * kMaxUnit], rhs[kMaxUnit];
-    for (int i = 0; i < k * k; ++i) M[i] = 0.0;
+    // transposed matrix directly: M[t][i] = delta - w(i reads t)
+    for (int i = 0; i < k * k; ++i) ws.M[i] = 0.0;
     for (int i = 0; i < k; ++i) {
-      M[i * k + i] = 1.0;
-      double acc = A.lam[f][cel[i]];
-      for_each_reader<D>(P, cel[i], [&](int g, int mask) {
+      ws.M[i * k + i] = 1.0;
+      double acc = A.lam[f][ws.cel[i]];
+      for_each_reader<D>(P, ws.cel[i], [&](int g, int mask) {
         if (P.blk[g] == u) return true;   // inside the unit: handled by the solve
         double w[8];
         weights_of<D>(P, g, field_bc(A, f, g), w);
         acc += w[mask] * A.Lam[(int64_t)f * P.ng + g];
         return true;
       });
-      rhs[i] = acc;
-      // row i of W_int: member i reads member t with weight w
+      ws.rhs[i] = acc;
+    }
+    for (int i = 0; i < k; ++i) {
       double w[8];
-      weights_of<D>(P, mem[i], field_bc(A, f, mem[i]), w);
-      const uint32_t code = P.code[mem[i]];
+      weights_of<D>(P, ws.mem[i], field_bc(A, f, ws.mem[i]), w);
+      const uint32_t code = P.code[ws.mem[i]];
       for (int c = 1; c < (1 << D); ++c) {
         if (c & code_skip(code)) continue;
-        const int q = cel[i] + corner_offset(P.g, code, c);
+        const int q = ws.cel[i] + corner_offset(P.g, code, c);
         for (int t = 0; t < k; ++t)
-          if (cel[t] == q) M[i * k + t] -= w[c];
+          if (ws.cel[t] == q) ws.M[t * k + i] -= w[c];
       }
     }
-    // solve M^T mu = rhs (Gaussian elimination with partial pivoting on M^T)
-    double T[kMaxUnit * kMaxUnit];
-    for (int i = 0; i < k; ++i)
-      for (int t = 0; t < k; ++t) T[i * k + t] = M[t * k + i];
-    for (int c = 0; c < k; ++c) {
-      int piv = c;
-      for (int r = c + 1; r < k; ++r)
-        if (fabs(T[r * k + c]) > fabs(T[piv * k + c])) piv = r;
-      if (piv != c) {
-        for (int t = 0; t < k; ++t) {
-          double x = T[c * k + t];
-          T[c * k + t] = T[piv * k + t];
-          T[piv * k + t] = x;
-        }
-        double x = rhs[c];
-        rhs[c] = rhs[piv];
-        rhs[piv] = x;
-      }
-      for (int r = c + 1; r < k; ++r) {
-        double fct = T[r * k + c] / T[c * k + c];
-        for (int t = c; t < k; ++t) T[r * k + t] -= fct * T[c * k + t];
-        rhs[r] -= fct * rhs[c];
-      }
-    }
-    for (int c = k - 1; c >= 0; --c) {
-      double v = rhs[c];
-      for (int t = c + 1; t < k; ++t) v -= T[c * k + t] * rhs[t];
-      rhs[c] = v / T[c * k + c];
-    }
-    for (int i = 0; i < k; ++i) A.Lam[(int64_t)f * P.ng + mem[i]] = rhs[i];
+    ws_solve(ws, k);
+    for (int i = 0; i < k; ++i) A.Lam[(int64_t)f * P.ng + ws.mem[i]] = ws.rhs[i];
   }
+}
+
+template <int D>
+__device__ __forceinline__ void adj_units_of_level(const AdjArgs& A, int level, UnitWS* ws,
+                                                   int tid, int nthreads) {
+  for (int s = tid; s < A.P.nunits; s += nthreads)
+    if (A.P.unit_lev[s] == level) adj_unit<D>(A, s, ws[tid]);
 }
 
 template <int D>
 __device__ __forceinline__ void adj_ghost(const AdjArgs& A, int p) {
   const PlanD& P = A.P;
-  const int u = P.blk[p];
-  if (u >= 0) {
-    if (P.unit_mem[u * kMaxUnit] == p) adj_unit<D>(A, u);
-    return;
-  }
+  if (P.blk[p] >= 0) return;   // coupled units: adj_units_of_level
   const int c = P.cell[p];
+  // fully unrolled over the field slots so the accumulators stay in registers
   double acc[kMaxFields];
-  for (int f = 0; f < A.nf; ++f) acc[f] = A.lam[f][c];
+#pragma unroll
+  for (int f = 0; f < kMaxFields; ++f) acc[f] = f < A.nf ? A.lam[f][c] : 0.0;
   for_each_reader<D>(P, c, [&](int g, int mask) {
     double wD[8], wN[8];
     bool hD = false, hN = false;
-    for (int f = 0; f < A.nf; ++f) {
+#pragma unroll
+    for (int f = 0; f < kMaxFields; ++f) {
+      if (f >= A.nf) break;
       const int bc = field_bc(A, f, g);
-      const double* w;
-      if (bc == 0) {
-        if (!hD) {
-          weights_of<D>(P, g, 0, wD);
-          hD = true;
-        }
-        w = wD;
-      } else {
-        if (!hN) {
-          weights_of<D>(P, g, 1, wN);
-          hN = true;
-        }
-        w = wN;
+      if (bc == 0 && !hD) {
+        weights_of<D>(P, g, 0, wD);
+        hD = true;
+      } else if (bc != 0 && !hN) {
+        weights_of<D>(P, g, 1, wN);
+        hN = true;
       }
-      acc[f] += w[mask] * A.Lam[(int64_t)f * P.ng + g];
+      double wm = 0.0;
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k)
+        if (k == mask) wm = bc == 0 ? wD[k] : wN[k];
+      acc[f] += wm * A.Lam[(int64_t)f * P.ng + g];
     }
     return true;
   });
-  for (int f = 0; f < A.nf; ++f) A.Lam[(int64_t)f * P.ng + p] = acc[f];
+#pragma unroll
+  for (int f = 0; f < kMaxFields; ++f)
+    if (f < A.nf) A.Lam[(int64_t)f * P.ng + p] = acc[f];
 }
 
 template <int D>
@@ -199,11 +178,22 @@ __global__ __launch_bounds__(256) void k_adj_range(AdjArgs A, int lo, int hi) {
 template <int D>
 __global__ __launch_bounds__(1024) void k_adj_wg(AdjArgs A, const int32_t* __restrict__ lev_off,
                                                  int nlev) {
+  __shared__ UnitWS ws[64];
   for (int l = nlev - 1; l >= 0; --l) {
     for (int p = lev_off[l] + (int)threadIdx.x; p < lev_off[l + 1]; p += blockDim.x)
       adj_ghost<D>(A, p);
     __syncthreads();
+    if (A.P.nunits) {
+      if (threadIdx.x < 64) adj_units_of_level<D>(A, l + 1, ws, threadIdx.x, 64);
+      __syncthreads();
+    }
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void k_adj_units(AdjArgs A, int level) {
+  __shared__ UnitWS ws[64];
+  adj_units_of_level<D>(A, level, ws, threadIdx.x, 64);
 }
 
 // Boundary-data sensitivities, non-ghost cells (owner rule), ghost slots zeroed.
@@ -335,28 +325,34 @@ __global__ __launch_bounds__(256) void k_sadj_seed(SurfAdjArgs S) {
   int i, j, k;
   unlinear(P.g, P.cell[g], i, j, k);
   const int ijk[3] = {i, j, k};
-  double acc[kMaxFields][8];
-  for (int f = 0; f < S.nf; ++f)
-    for (int m = 0; m < 8; ++m) acc[f][m] = 0.0;
-  for (int t = b; t < e; ++t) {
-    const int64_t q = S.bucket[t];
-    double rel[3] = {0.0, 0.0, 0.0};
+  // one field at a time keeps the 2^D corner sums in registers
+  for (int f = 0; f < S.nf; ++f) {
+    double acc[8];
 #pragma unroll
-    for (int a = 0; a < D; ++a) rel[a] = S.xq[a * S.nq + q] - centre(P.g, a, ijk[a]);
-    for (int m = 0; m < (1 << D); ++m) {
-      double cv, cg[3];
-      box_coeffs<D>(rel, code, P.g.h, m, cv, cg);
-      for (int f = 0; f < S.nf; ++f) {
-        double s = S.gval ? cv * S.gval[(int64_t)f * S.nq + q] : 0.0;
-        if (S.ggrad)
+    for (int m = 0; m < 8; ++m) acc[m] = 0.0;
+    for (int t = b; t < e; ++t) {
+      const int64_t q = S.bucket[t];
+      double rel[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-          for (int a = 0; a < D; ++a) s += cg[a] * S.ggrad[((int64_t)f * D + a) * S.nq + q];
-        acc[f][m] += s;
+      for (int a = 0; a < D; ++a) rel[a] = S.xq[a * S.nq + q] - centre(P.g, a, ijk[a]);
+      const double gv = S.gval ? S.gval[(int64_t)f * S.nq + q] : 0.0;
+      double gg[3] = {0.0, 0.0, 0.0};
+      if (S.ggrad)
+#pragma unroll
+        for (int a = 0; a < D; ++a) gg[a] = S.ggrad[((int64_t)f * D + a) * S.nq + q];
+#pragma unroll
+      for (int m = 0; m < (1 << D); ++m) {
+        double cv, cg[3];
+        box_coeffs<D>(rel, code, P.g.h, m, cv, cg);
+        double s = cv * gv;
+#pragma unroll
+        for (int a = 0; a < D; ++a) s += cg[a] * gg[a];
+        acc[m] += s;
       }
     }
+#pragma unroll
+    for (int m = 0; m < (1 << D); ++m) S.seed[((int64_t)f * 8 + m) * P.ng + g] = acc[m];
   }
-  for (int f = 0; f < S.nf; ++f)
-    for (int m = 0; m < (1 << D); ++m) S.seed[((int64_t)f * 8 + m) * P.ng + g] = acc[f][m];
 }
 
 // each box corner of each anchor: the first anchor (fixed search order) whose
@@ -568,6 +564,12 @@ gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf, double* const* lam
       const int lo = p->lev_off[l], hi = p->lev_off[l + 1];
       if (p->dim == 2) k_adj_range<2><<<nblk(hi - lo, 256), 256, 0, st>>>(A, lo, hi);
       else k_adj_range<3><<<nblk(hi - lo, 256), 256, 0, st>>>(A, lo, hi);
+      for (int32_t ul : p->unit_lev_host)
+        if (ul == l + 1) {
+          if (p->dim == 2) k_adj_units<2><<<1, 64, 0, st>>>(A, l + 1);
+          else k_adj_units<3><<<1, 64, 0, st>>>(A, l + 1);
+          break;
+        }
     }
   }
   if (p->dim == 2) k_adj_support<2><<<nblk(ng, 256), 256, 0, st>>>(A);

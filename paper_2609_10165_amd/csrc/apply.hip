@@ -21,35 +21,28 @@ __global__ __launch_bounds__(256) void k_fill_range(FillArgs A, int lo, int hi) 
   if (p < hi) fill_ghost<D>(A, p);
 }
 
-// one workgroup sweeps every level; a barrier separates levels
+// one workgroup sweeps every level; a barrier separates levels, and the
+// coupled units of a level are solved (first 64 threads) before the next
 template <int D>
 __global__ __launch_bounds__(1024) void k_fill_wg(FillArgs A, const int32_t* __restrict__ lev_off,
                                                   int nlev) {
+  __shared__ UnitWS ws[64];
   for (int l = 0; l < nlev; ++l) {
     const int lo = lev_off[l], hi = lev_off[l + 1];
     for (int p = lo + (int)threadIdx.x; p < hi; p += blockDim.x) fill_ghost<D>(A, p);
     __syncthreads();
-  }
-}
-
-// batched: one workgroup per (instance, field group) work item
-template <int D>
-__global__ __launch_bounds__(1024) void k_fill_batch(const FillArgs* __restrict__ args,
-                                                     const int32_t* __restrict__ order, int nitems,
-                                                     const int32_t* const* __restrict__ lev_offs,
-                                                     const int32_t* __restrict__ nlevs) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int w = order[it];
-    const FillArgs& A = args[w];
-    if (A.P.g.dim != D) continue;
-    const int32_t* lo_ = lev_offs[w];
-    const int nl = nlevs[w];
-    for (int l = 0; l < nl; ++l) {
-      const int lo = lo_[l], hi = lo_[l + 1];
-      for (int p = lo + (int)threadIdx.x; p < hi; p += blockDim.x) fill_ghost<D>(A, p);
+    if (A.P.nunits) {
+      if (threadIdx.x < 64) fill_units_of_level<D>(A, l + 1, ws, threadIdx.x, 64);
       __syncthreads();
     }
   }
+}
+
+// coupled units of one level
+template <int D>
+__global__ __launch_bounds__(64) void k_fill_units(FillArgs A, int level) {
+  __shared__ UnitWS ws[64];
+  fill_units_of_level<D>(A, level, ws, threadIdx.x, 64);
 }
 
 void launch_fill_range(const FillArgs& A, int lo, int hi, hipStream_t st) {
@@ -59,20 +52,16 @@ void launch_fill_range(const FillArgs& A, int lo, int hi, hipStream_t st) {
   else k_fill_range<3><<<nb, 256, 0, st>>>(A, lo, hi);
 }
 
+void launch_fill_units(const FillArgs& A, int level, hipStream_t st) {
+  if (A.P.g.dim == 2) k_fill_units<2><<<1, 64, 0, st>>>(A, level);
+  else k_fill_units<3><<<1, 64, 0, st>>>(A, level);
+}
+
 void launch_fill_wg(const FillArgs& A, const int32_t* d_lev_off, int nlev, int threads,
                     hipStream_t st) {
   if (nlev <= 0) return;
   if (A.P.g.dim == 2) k_fill_wg<2><<<1, threads, 0, st>>>(A, d_lev_off, nlev);
   else k_fill_wg<3><<<1, threads, 0, st>>>(A, d_lev_off, nlev);
-}
-
-void launch_fill_batch(int dim_mask, const FillArgs* d_args, const int32_t* d_order, int nitems,
-                       const int32_t* const* d_lev_offs, const int32_t* d_nlevs, int grid,
-                       int threads, hipStream_t st) {
-  if (dim_mask & 1)
-    k_fill_batch<2><<<grid, threads, 0, st>>>(d_args, d_order, nitems, d_lev_offs, d_nlevs);
-  if (dim_mask & 2)
-    k_fill_batch<3><<<grid, threads, 0, st>>>(d_args, d_order, nitems, d_lev_offs, d_nlevs);
 }
 
 // --------------------------------------------------------------------------

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
                                                         int* __restrict__ counter,
                                                         double* __restrict__ Fout) {
   __shared__ double red[1024][3];
-  __shared__ int s_last;
+  __shared__ UnitWS ws[64];
   const int T = blockDim.x;
   for (int it = blockIdx.x; it < C.nitems; it += gridDim.x) {
     const int w = C.order[it];
@@ -64,6 +64,12 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
       const int lo = lo_[l], hi = lo_[l + 1];
       for (int p = lo + (int)threadIdx.x; p < hi; p += T) fill_single<D>(P, p, F, b, bt, kind);
       __syncthreads();
+      if (P.nunits) {
+        if (threadIdx.x < 64)
+          for (int s = threadIdx.x; s < P.nunits; s += 64)
+            if (P.unit_lev[s] == l + 1) fill_unit_field<D>(P, s, F, b, bt, kind, ws[threadIdx.x]);
+        __syncthreads();
+      }
     }
     // share of the force
     const int vc = f - C.u_first;
@@ -120,8 +126,7 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
       for (int a = 0; a < 3; ++a) part[(int64_t)w * 3 + a] = red[0][a];
       __threadfence();
       const int done = atomicAdd(&counter[i], 1);
-      s_last = (done == C.nf - 1);
-      if (s_last) {
+      if (done == C.nf - 1) {
         __threadfence();
         double s3[3] = {0.0, 0.0, 0.0};
         for (int ff = 0; ff < C.nf; ++ff)

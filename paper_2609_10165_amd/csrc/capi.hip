@@ -89,6 +89,10 @@ PlanD plan_view(const gcr_plan* p) {
   P.sorted_cell = p->sorted_cell;
   P.sorted_pos = p->sorted_pos;
   for (int a = 0; a < 3; ++a) P.rmax[a] = a < p->dim ? std::max(1, p->info.rmax[a]) : 0;
+  P.htab = p->htab;
+  P.hmask = p->hmask;
+  P.nunits = p->info.nunits;
+  P.unit_lev = p->unit_lev;
   return P;
 }
 
@@ -101,8 +105,21 @@ struct GraphCache {
   }
 };
 
+// per-level launches; a level holding coupled units gets a second, small
+// launch that solves them
+static void launch_levels_fill(const gcr_plan* p, const FillArgs& A, hipStream_t st) {
+  for (int l = 0; l < p->nlev; ++l) {
+    launch_fill_range(A, p->lev_off[l], p->lev_off[l + 1], st);
+    for (int32_t ul : p->unit_lev_host)
+      if (ul == l + 1) {
+        launch_fill_units(A, l + 1, st);
+        break;
+      }
+  }
+}
+
 static gcr_status fill_levels(const gcr_plan* p, const FillArgs& A, hipStream_t st) {
-  for (int l = 0; l < p->nlev; ++l) launch_fill_range(A, p->lev_off[l], p->lev_off[l + 1], st);
+  launch_levels_fill(p, A, st);
   GCR_HIP(hipGetLastError());
   return GCR_OK;
 }
@@ -124,7 +141,7 @@ static gcr_status fill_graph(gcr_plan* p, const FillArgs& A, hipStream_t st) {
   if (!G.cap) GCR_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   GCR_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
-  for (int l = 0; l < p->nlev; ++l) launch_fill_range(A, p->lev_off[l], p->lev_off[l + 1], G.cap);
+  launch_levels_fill(p, A, G.cap);
   GCR_HIP(hipStreamEndCapture(G.cap, &graph));
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

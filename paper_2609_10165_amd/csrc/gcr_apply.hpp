@@ -23,16 +23,68 @@ struct PlanD {
   const int32_t* sorted_cell;  // ghost cells in linear-index order
   const int32_t* sorted_pos;   // their canonical positions
   int rmax[3];                 // largest stencil multiplier per axis
+  const unsigned long long* htab;  // open-addressing table cell -> canonical position
+  unsigned hmask;
+  int nunits;                  // coupled units
+  const int32_t* unit_lev;     // their levels (1-based)
 };
 
-// canonical position of the ghost in cell c, or -1
+constexpr unsigned long long kHashEmpty = ~0ull;
+
+__device__ __forceinline__ unsigned cell_hash(int c) {
+  unsigned h = (unsigned)c * 2654435761u;
+  return h ^ (h >> 15);
+}
+
+// canonical position of the ghost in cell c, or -1 (linear probing; the
+// table is at most half full, so every probe sequence reaches an empty slot)
 __device__ __forceinline__ int ghost_at(const PlanD& P, int c) {
-  int lo = 0, hi = P.ng;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (P.sorted_cell[mid] < c) lo = mid + 1; else hi = mid;
+  unsigned h = cell_hash(c) & P.hmask;
+  for (;;) {
+    const unsigned long long e = P.htab[h];
+    if (e == kHashEmpty) return -1;
+    if ((int)(e >> 32) == c) return (int)(e & 0xffffffffu);
+    h = (h + 1) & P.hmask;
   }
-  return (lo < P.ng && P.sorted_cell[lo] == c) ? P.sorted_pos[lo] : -1;
+}
+
+// LDS workspace of one coupled-unit solve
+struct UnitWS {
+  double M[kMaxUnit * kMaxUnit];
+  double rhs[kMaxUnit];
+  int cel[kMaxUnit];
+  int mem[kMaxUnit];
+};
+
+// Gaussian elimination with partial pivoting on ws.M (k x k) ws.rhs, in place
+__device__ __forceinline__ void ws_solve(UnitWS& ws, int k) {
+  double* M = ws.M;
+  double* rhs = ws.rhs;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (fabs(M[r * k + c]) > fabs(M[piv * k + c])) piv = r;
+    if (piv != c) {
+      for (int t = 0; t < k; ++t) {
+        double x = M[c * k + t];
+        M[c * k + t] = M[piv * k + t];
+        M[piv * k + t] = x;
+      }
+      double x = rhs[c];
+      rhs[c] = rhs[piv];
+      rhs[piv] = x;
+    }
+    for (int r = c + 1; r < k; ++r) {
+      double fct = M[r * k + c] / M[c * k + c];
+      for (int t = c; t < k; ++t) M[r * k + t] -= fct * M[c * k + t];
+      rhs[r] -= fct * rhs[c];
+    }
+  }
+  for (int c = k - 1; c >= 0; --c) {
+    double v = rhs[c];
+    for (int t = c + 1; t < k; ++t) v -= M[c * k + t] * rhs[t];
+    rhs[c] = v / M[c * k + c];
+  }
 }
 
 struct FillArgs {
@@ -68,9 +120,7 @@ PlanD plan_view(const gcr_plan* p);
 void launch_fill_range(const FillArgs& A, int lo, int hi, hipStream_t st);
 void launch_fill_wg(const FillArgs& A, const int32_t* d_lev_off, int nlev, int threads,
                     hipStream_t st);
-void launch_fill_batch(int dim_mask, const FillArgs* d_args, const int32_t* d_order, int nitems,
-                       const int32_t* const* d_lev_offs, const int32_t* d_nlevs, int grid,
-                       int threads, hipStream_t st);
+void launch_fill_units(const FillArgs& A, int level, hipStream_t st);
 void launch_surface_ghost(const SurfArgs& S, hipStream_t st);
 void launch_surface_query(const SurfArgs& S, int64_t nq, const double* xq, hipStream_t st);
 void launch_forces(const PlanD& P, const ForceArgs& F, double* part, double* out,

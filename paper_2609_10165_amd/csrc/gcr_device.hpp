@@ -11,7 +11,7 @@ namespace gcr {
 
 constexpr int kMaxCoef = 128;     // star: 2 * 64 harmonics; SH: (L+1)^2, L <= 8
 constexpr int kMaxFields = 8;
-constexpr int kMaxUnit = 16;      // largest coupled unit (strongly connected group)
+constexpr int kMaxUnit = 8;       // largest coupled unit (strongly connected group)
 constexpr int kMaxUnits = 1024;   // coupled units per instance
 constexpr int kMaxLevels = 1024;  // levels per instance
 constexpr int kChunk = 4096;      // cells per classification workgroup
@@ -364,6 +364,11 @@ __device__ __forceinline__ bool inside(const ShapeD& s, int dim, const double x[
   double dx = x[0] - s.c[0], dy = x[1] - s.c[1], dz = dim == 3 ? x[2] - s.c[2] : 0.0;
   double rho2 = dx * dx + dy * dy;
   if (dim == 3) rho2 += dz * dz;
+  // rho^2 clearly below rmin^2 or above rmax^2 settles the test without a
+  // square root; the 1e-10 relative margin dwarfs every rounding involved,
+  // so the decision equals that of r - sqrt(rho^2) >= 0
+  if (rho2 < s.rmin * s.rmin * (1.0 - 1e-10)) return true;
+  if (rho2 > s.rmax * s.rmax * (1.0 + 1e-10)) return false;
   double rho = sqrt(rho2);
   double r;
   if (s.kind == kSphere) {

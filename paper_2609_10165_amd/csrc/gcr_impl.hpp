@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -82,9 +83,40 @@ struct BatchData {
   int32_t* d_blk = nullptr;
   int32_t* d_unit_mem = nullptr;     // [ninst][kMaxUnits][kMaxUnit]
   int32_t* d_unit_cnt = nullptr;     // [ninst][kMaxUnits]
+  int32_t* d_unit_lev = nullptr;     // [ninst][kMaxUnits] level of each unit
+  uint32_t* d_reach = nullptr;       // [ninst] residual closure bitsets (cyclic graphs)
+  int32_t* d_listA = nullptr;        // [cap] frontier lists of the layering
+  int32_t* d_listB = nullptr;
+  std::vector<int32_t> unit_lev;     // host copy
+  // cell -> ghost hash tables, concatenated per instance
+  unsigned long long* d_htab = nullptr;
+  int64_t* d_hoff = nullptr;
+  uint32_t* d_hmask = nullptr;
+  std::vector<int64_t> hoff;
+  std::vector<uint32_t> hmask;
   std::vector<void*> owned;
   ~BatchData();
 };
+
+// Arguments of the layering kernel (levels.hip).
+struct LevelsArgs {
+  const Inst* insts;
+  const int64_t* g_off;
+  const int32_t* deps;
+  int64_t cap;
+  int32_t* lev;
+  int32_t* blk_idx;
+  int32_t* perm;
+  int32_t* lev_off;
+  int32_t* unit_mem;
+  int32_t* unit_cnt;
+  int32_t* unit_lev;
+  uint32_t* reach;
+  int32_t* listA;
+  int32_t* listB;
+  InstInfo* info;
+};
+void launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
 
 // Schedule of the fill.
 enum { kSchedAuto = 0, kSchedLevels = 1, kSchedWorkgroup = 2, kSchedGraph = 3 };
@@ -118,6 +150,10 @@ struct gcr_plan {
   int32_t* sorted_cell = nullptr;   // ghost cells in linear-index order
   int32_t* sorted_pos = nullptr;    // their canonical positions
   int32_t* d_lev_off = nullptr;
+  int32_t* unit_lev = nullptr;      // device [nunits]
+  std::vector<int32_t> unit_lev_host;
+  unsigned long long* htab = nullptr;
+  uint32_t hmask = 0;
   int schedule = gcr::kSchedAuto;
   int tuned = -1;                   // schedule picked by the tuner
   // scratch buffers owned by the plan (forces partials, adjoint state);

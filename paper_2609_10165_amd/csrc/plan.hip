@@ -561,227 +561,6 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
 }
 
 // --------------------------------------------------------------------------
-// 5. levels and canonical order (one workgroup per instance)
-// --------------------------------------------------------------------------
-
-__global__ __launch_bounds__(1024) void k_levels_order(
-    const Inst* __restrict__ insts, const int64_t* __restrict__ g_off,
-    const int32_t* __restrict__ deps, int64_t cap, int32_t* __restrict__ lev,
-    int32_t* __restrict__ blk_idx, int32_t* __restrict__ perm, int32_t* __restrict__ lev_off_all,
-    int32_t* __restrict__ unit_mem_all, int32_t* __restrict__ unit_cnt_all,
-    InstInfo* __restrict__ info) {
-  const int ii = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int np = (1 << insts[ii].g.dim) - 1;
-  const int64_t lo = g_off[ii];
-  const int n = (int)(g_off[ii + 1] - lo);
-  int32_t* lev_off = lev_off_all + (int64_t)ii * (kMaxLevels + 1);
-  int32_t* unit_mem = unit_mem_all + (int64_t)ii * kMaxUnits * kMaxUnit;
-  int32_t* unit_cnt = unit_cnt_all + (int64_t)ii * kMaxUnits;
-
-  __shared__ int64_t sh[17];
-  __shared__ int s_flag, s_m, s_units, s_maxunit;
-  __shared__ int32_t res[kMaxResidual];
-  __shared__ int32_t rep[kMaxResidual];
-  __shared__ int32_t slot[kMaxResidual];
-  __shared__ uint32_t reach[kMaxResidual * (kMaxResidual / 32)];
-
-  for (int g = tid; g < n; g += 1024) {
-    lev[lo + g] = 0;
-    blk_idx[lo + g] = -1;
-    perm[lo + g] = -1;
-  }
-  if (tid == 0) {
-    lev_off[0] = 0;
-    s_units = 0;
-    s_maxunit = 0;
-  }
-  __syncthreads();
-
-  int placed = 0, k = 0, maxwidth = 0;
-  bool units = false;
-  uint32_t err = 0;
-  while (placed < n) {
-    ++k;
-    if (k > kMaxLevels) {
-      err |= kErrUnsupported;
-      break;
-    }
-    int newly = 0;
-    for (int base = 0; base < n; base += 1024) {
-      const int g = base + tid;
-      bool ready = false;
-      if (g < n && lev[lo + g] == 0) {
-        const int u = units ? blk_idx[lo + g] : -1;
-        ready = true;
-        if (u < 0) {
-          for (int m = 0; m < np && ready; ++m) {
-            int32_t d = deps[(int64_t)m * cap + lo + g];
-            if (d >= 0) {
-              int ld = lev[d];
-              if (ld == 0 || ld >= k) ready = false;
-            }
-          }
-        } else {
-          // a coupled unit is ready when every ghost it needs outside the unit is placed
-          const int cntu = unit_cnt[u];
-          for (int q = 0; q < cntu && ready; ++q) {
-            int32_t w = unit_mem[u * kMaxUnit + q];
-            for (int m = 0; m < np && ready; ++m) {
-              int32_t d = deps[(int64_t)m * cap + w];
-              if (d >= 0 && blk_idx[d] != u) {
-                int ld = lev[d];
-                if (ld == 0 || ld >= k) ready = false;
-              }
-            }
-          }
-        }
-      }
-      int64_t tot;
-      int64_t pre = block_excl_scan<1024>(ready ? 1 : 0, &tot, sh);
-      if (ready) {
-        lev[lo + g] = k;
-        perm[lo + g] = placed + newly + (int)pre;
-      }
-      newly += (int)tot;
-      __syncthreads();
-    }
-    if (newly == 0) {
-      if (units) {
-        err |= kErrCycle;
-        break;
-      }
-      // Kahn stalled: the rest holds cycles.  Find their strongly connected
-      // groups from the transitive closure of the residual graph.
-      --k;
-      int64_t tot;
-      for (int base = 0, off = 0; base < n; base += 1024) {
-        const int g = base + tid;
-        const bool r = g < n && lev[lo + g] == 0;
-        int64_t pre = block_excl_scan<1024>(r ? 1 : 0, &tot, sh);
-        if (r && off + pre < kMaxResidual) res[off + pre] = g;
-        off += (int)tot;
-        if (base + 1024 >= n && tid == 0) s_m = off;
-      }
-      __syncthreads();
-      const int m = s_m;
-      if (m > kMaxResidual) {
-        err |= kErrCycle;
-        break;
-      }
-      const int W = (m + 31) / 32;
-      for (int t = tid; t < m * W; t += 1024) reach[t] = 0;
-      __syncthreads();
-      for (int u = tid; u < m; u += 1024) {
-        for (int q = 0; q < np; ++q) {
-          int32_t d = deps[(int64_t)q * cap + lo + res[u]];
-          if (d >= 0 && lev[d] == 0) {
-            int v = (int)find_cell(res, 0, m, (int)(d - lo));
-            if (v >= 0) reach[u * W + (v >> 5)] |= 1u << (v & 31);
-          }
-        }
-      }
-      __syncthreads();
-      do {
-        if (tid == 0) s_flag = 0;
-        __syncthreads();
-        int changed = 0;
-        for (int u = tid; u < m; u += 1024) {
-          for (int q = 0; q < np; ++q) {
-            int32_t d = deps[(int64_t)q * cap + lo + res[u]];
-            if (d < 0 || lev[d] != 0) continue;
-            int v = (int)find_cell(res, 0, m, (int)(d - lo));
-            if (v < 0) continue;
-            for (int w = 0; w < W; ++w) {
-              uint32_t o = reach[u * W + w], nw = o | reach[v * W + w];
-              if (nw != o) {
-                reach[u * W + w] = nw;
-                changed = 1;
-              }
-            }
-          }
-        }
-        if (changed) s_flag = 1;
-        __syncthreads();
-      } while (s_flag);
-      // representative = smallest member of the group; -1 off cycles
-      for (int u = tid; u < m; u += 1024) {
-        int rp = -1;
-        if ((reach[u * W + (u >> 5)] >> (u & 31)) & 1u) {
-          for (int v = 0; v < m; ++v)
-            if (((reach[u * W + (v >> 5)] >> (v & 31)) & 1u) &&
-                ((reach[v * W + (u >> 5)] >> (u & 31)) & 1u)) {
-              rp = v;
-              break;
-            }
-        }
-        rep[u] = rp;
-      }
-      __syncthreads();
-      // slots in residual order
-      {
-        int off = 0;
-        for (int base = 0; base < m; base += 1024) {
-          int u = base + tid;
-          bool isrep = u < m && rep[u] == u;
-          int64_t pre = block_excl_scan<1024>(isrep ? 1 : 0, &tot, sh);
-          if (isrep) slot[u] = off + (int)pre;
-          off += (int)tot;
-        }
-        if (tid == 0) s_units = off;
-      }
-      __syncthreads();
-      if (s_units > kMaxUnits) {
-        err |= kErrCycle;
-        break;
-      }
-      for (int u = tid; u < m; u += 1024) {
-        int rp = rep[u];
-        if (rp < 0) continue;
-        int sl = slot[rp], rank = 0, size = 0;
-        for (int v = 0; v < m; ++v)
-          if (rep[v] == rp) {
-            if (v < u) ++rank;
-            ++size;
-          }
-        if (size > kMaxUnit) {
-          atomicOr(&info[ii].err, kErrCycle);
-          continue;
-        }
-        unit_mem[sl * kMaxUnit + rank] = (int32_t)(lo + res[u]);
-        blk_idx[lo + res[u]] = sl;
-        if (u == rp) {
-          unit_cnt[sl] = size;
-          atomicMax(&s_maxunit, size);
-        }
-      }
-      // restart the layering with the units: a unit's level is one more than
-      // the deepest level it needs, as if it had been known from the start
-      for (int g = tid; g < n; g += 1024) {
-        lev[lo + g] = 0;
-        perm[lo + g] = -1;
-      }
-      __syncthreads();
-      units = true;
-      placed = 0;
-      k = 0;
-      maxwidth = 0;
-      continue;
-    }
-    placed += newly;
-    maxwidth = max(maxwidth, newly);
-    if (tid == 0) lev_off[k] = placed;
-  }
-  if (tid == 0) {
-    if (err) atomicOr(&info[ii].err, err);
-    info[ii].nlev = k;
-    info[ii].maxwidth = maxwidth;
-    info[ii].nunits = units ? s_units : 0;
-    info[ii].maxunit = s_maxunit;
-  }
-}
-
-// --------------------------------------------------------------------------
 // 6. canonical arrays
 // --------------------------------------------------------------------------
 
@@ -885,6 +664,33 @@ __global__ void k_units_canonical(const int32_t* __restrict__ perm,
     int u = t / kMaxUnit, q = t % kMaxUnit;
     if (q < uc[u]) um[t] = perm[um[t]];
   }
+}
+
+// --------------------------------------------------------------------------
+// 7. cell -> ghost hash tables (open addressing, at most half full)
+// --------------------------------------------------------------------------
+
+__global__ void k_hash_clear(unsigned long long* __restrict__ t, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = ~0ull;
+}
+
+__global__ void k_hash_build(const int64_t* __restrict__ g_off, int ninst,
+                             const int32_t* __restrict__ cell,
+                             const int64_t* __restrict__ hoff,
+                             const uint32_t* __restrict__ hmask,
+                             unsigned long long* __restrict__ htab) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g_off[ninst]) return;
+  const int ii = find_inst(g_off, ninst, e);
+  const int c = cell[e];
+  const unsigned long long entry =
+      ((unsigned long long)(uint32_t)c << 32) | (uint32_t)(e - g_off[ii]);
+  unsigned long long* t = htab + hoff[ii];
+  const uint32_t mask = hmask[ii];
+  uint32_t h = (uint32_t)c * 2654435761u;
+  h = (h ^ (h >> 15)) & mask;
+  while (atomicCAS(&t[h], ~0ull, entry) != ~0ull) h = (h + 1) & mask;
 }
 
 // --------------------------------------------------------------------------
@@ -1063,6 +869,9 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_lev_off = own<int32_t>(D, (size_t)ninst * (kMaxLevels + 1));
   D.d_unit_mem = own<int32_t>(D, (size_t)ninst * kMaxUnits * kMaxUnit);
   D.d_unit_cnt = own<int32_t>(D, (size_t)ninst * kMaxUnits);
+  D.d_unit_lev = own<int32_t>(D, (size_t)ninst * kMaxUnits);
+  D.d_reach = own<uint32_t>(D, (size_t)ninst * kMaxResidual * (kMaxResidual / 32));
+  if (!D.d_unit_lev || !D.d_reach) return GCR_E_NOMEM;
   if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl ||
       !D.d_if_off || !D.d_g_off || !D.d_info || !D.d_lev_off || !D.d_unit_mem || !D.d_unit_cnt)
     return GCR_E_NOMEM;
@@ -1111,6 +920,9 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_code = own<uint32_t>(D, cap);
   D.d_level = own<int32_t>(D, cap);
   D.d_blk = own<int32_t>(D, cap);
+  D.d_listA = own<int32_t>(D, cap);
+  D.d_listB = own<int32_t>(D, cap);
+  if (!D.d_listA || !D.d_listB) return GCR_E_NOMEM;
   if (!D.d_if_cell || !D.d_if_psi || !D.d_if_n || !D.d_if_flag || !D.d_blkcnt || !D.d_blkexcl ||
       !D.d_g_cell || !D.d_g_psi || !D.d_g_n || !D.d_g_code || !D.d_deps || !D.d_lev ||
       !D.d_blk_idx || !D.d_perm || !D.d_cell || !D.d_delta || !D.d_nrm || !D.d_psi ||
@@ -1141,9 +953,27 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                                               D.d_g_n, cap, D.d_tags, D.d_g_code, D.d_deps,
                                               D.d_info);
     T.mark(7, st);
-    k_levels_order<<<ninst, 1024, 0, st>>>(D.d_inst, D.d_g_off, D.d_deps, cap, D.d_lev,
-                                            D.d_blk_idx, D.d_perm, D.d_lev_off, D.d_unit_mem,
-                                            D.d_unit_cnt, D.d_info);
+    {
+      LevelsArgs L;
+      L.insts = D.d_inst;
+      L.g_off = D.d_g_off;
+      L.deps = D.d_deps;
+      L.cap = cap;
+      L.lev = D.d_lev;
+      L.blk_idx = D.d_blk_idx;
+      L.perm = D.d_perm;
+      L.lev_off = D.d_lev_off;
+      L.unit_mem = D.d_unit_mem;
+      L.unit_cnt = D.d_unit_cnt;
+      L.unit_lev = D.d_unit_lev;
+      L.reach = D.d_reach;
+      L.listA = D.d_listA;
+      L.listB = D.d_listB;
+      L.info = D.d_info;
+      int64_t max_if = 0;
+      for (int i = 0; i < ninst; ++i) max_if = std::max(max_if, D.if_off[i + 1] - D.if_off[i]);
+      launch_levels(L, ninst, max_if, st);
+    }
     T.mark(8, st);
     k_finalize<<<blocks(nif, 256), 256, 0, st>>>(
         D.d_inst, ninst, D.d_g_off, cap, D.d_g_cell, D.d_g_psi, D.d_g_n, D.d_g_code, D.d_lev,
@@ -1166,6 +996,9 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                          st));
   GCR_HIP(hipMemcpyAsync(D.lev_off.data(), D.d_lev_off,
                          sizeof(int32_t) * ninst * (kMaxLevels + 1), hipMemcpyDeviceToHost, st));
+  D.unit_lev.resize((size_t)ninst * kMaxUnits);
+  GCR_HIP(hipMemcpyAsync(D.unit_lev.data(), D.d_unit_lev, sizeof(int32_t) * ninst * kMaxUnits,
+                         hipMemcpyDeviceToHost, st));
   GCR_HIP(hipStreamSynchronize(st));
   T.collect();
   D.ng_total = D.g_off[ninst];
@@ -1173,6 +1006,28 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
     gcr_status s = status_from_err(D.info[i].err);
     if (s != GCR_OK) return s;
   }
+  // cell -> ghost tables, built on the stream (used by later calls only)
+  D.hoff.assign(ninst + 1, 0);
+  D.hmask.assign(ninst, 0);
+  for (int i = 0; i < ninst; ++i) {
+    int64_t size = 64;
+    while (size < 2 * (D.g_off[i + 1] - D.g_off[i])) size <<= 1;
+    D.hmask[i] = (uint32_t)(size - 1);
+    D.hoff[i + 1] = D.hoff[i] + size;
+  }
+  D.d_htab = own<unsigned long long>(D, D.hoff[ninst]);
+  D.d_hoff = own<int64_t>(D, ninst + 1);
+  D.d_hmask = own<uint32_t>(D, ninst);
+  if (!D.d_htab || !D.d_hoff || !D.d_hmask) return GCR_E_NOMEM;
+  GCR_HIP(hipMemcpyAsync(D.d_hoff, D.hoff.data(), sizeof(int64_t) * (ninst + 1),
+                         hipMemcpyHostToDevice, st));
+  GCR_HIP(hipMemcpyAsync(D.d_hmask, D.hmask.data(), sizeof(uint32_t) * ninst,
+                         hipMemcpyHostToDevice, st));
+  k_hash_clear<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_htab, D.hoff[ninst]);
+  if (D.ng_total > 0)
+    k_hash_build<<<blocks(D.ng_total, 256), 256, 0, st>>>(D.d_g_off, ninst, D.d_cell, D.d_hoff,
+                                                          D.d_hmask, D.d_htab);
+  GCR_HIP(hipGetLastError());
   *out = B;
   return GCR_OK;
 }
@@ -1210,6 +1065,11 @@ void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p) {
   p->unit_mem = D.d_unit_mem + (int64_t)i * kMaxUnits * kMaxUnit;
   p->unit_cnt = D.d_unit_cnt + (int64_t)i * kMaxUnits;
   p->d_lev_off = D.d_lev_off + (int64_t)i * (kMaxLevels + 1);
+  p->unit_lev = D.d_unit_lev + (int64_t)i * kMaxUnits;
+  p->unit_lev_host.assign(D.unit_lev.begin() + (size_t)i * kMaxUnits,
+                          D.unit_lev.begin() + (size_t)i * kMaxUnits + p->info.nunits);
+  p->htab = D.d_htab + D.hoff[i];
+  p->hmask = D.hmask[i];
 }
 
 }  // namespace gcr
