@@ -140,6 +140,14 @@ gcr_status gcr_plan_export(const gcr_plan* plan, int8_t* tags, int32_t* cell,
                            int32_t* level, double* delta, double* normal,
                            double* psi, int32_t* r, int32_t* unit, void* stream);
 
+/* Where the caller evaluates boundary data (Sec. 3: the Dirichlet value or
+ * normal derivative is prescribed at the foot point S of each ghost):
+ *   S        device f64 [dim][n_ghost]  S = x_c + delta, canonical order
+ *   normal   device f64 [dim][n_ghost]  unit normal into the fluid at S
+ * Either may be NULL.  One kernel on `stream`. */
+gcr_status gcr_plan_foot_points(const gcr_plan* plan, double* S, double* normal,
+                                void* stream);
+
 /* Fill schedule.  0 = automatic (tuned), 1 = one launch per level,
  * 2 = one workgroup sweeping all levels, 3 = per-level launches captured in a
  * HIP graph and replayed.  `param` is reserved (0). */

@@ -23,7 +23,7 @@ SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
 SCHED_AUTO, SCHED_LEVELS, SCHED_WORKGROUP, SCHED_GRAPH = 0, 1, 2, 3
 SYMBOLS = [
     "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
-    "gcr_plan_export", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
+    "gcr_plan_export", "gcr_plan_foot_points", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_forward",
     "gcr_set_profiling", "gcr_last_build_times", "gcr_status_str", "gcr_version",
@@ -81,6 +81,7 @@ def lib():
         L.gcr_plan_stats.argtypes = [vp, P(_Stats)]
         L.gcr_plan_level_offsets.argtypes = [vp, vp]
         L.gcr_plan_export.argtypes = [vp] + [vp] * 8 + [vp]
+        L.gcr_plan_foot_points.argtypes = [vp, vp, vp, vp]
         L.gcr_set_schedule.argtypes = [vp, i32, i32]
         L.gcr_fill.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.gcr_surface_ghost.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -202,23 +203,34 @@ class Plan:
     def set_schedule(self, schedule: int):
         _check(lib().gcr_set_schedule(self._h, int(schedule), 0), "gcr_set_schedule")
 
-    def export(self, stream=None) -> dict:
+    EXPORTS = ("tags", "cell", "level", "delta", "normal", "psi", "r", "unit")
+
+    def export(self, which: Sequence[str] = EXPORTS, stream=None) -> dict:
+        """Device copies of the plan arrays named in `which`."""
         dev = torch.device("cuda")
         ng, d = self.n_ghost, self.dim
-        out = dict(tags=torch.empty(self.n_cells, dtype=torch.int8, device=dev),
-                   cell=torch.empty(ng, dtype=torch.int32, device=dev),
-                   level=torch.empty(ng, dtype=torch.int32, device=dev),
-                   delta=torch.empty((d, ng), dtype=torch.float64, device=dev),
-                   normal=torch.empty((d, ng), dtype=torch.float64, device=dev),
-                   psi=torch.empty(ng, dtype=torch.float64, device=dev),
-                   r=torch.empty((d, ng), dtype=torch.int32, device=dev),
-                   unit=torch.empty(ng, dtype=torch.int32, device=dev))
-        _check(lib().gcr_plan_export(
-            self._h, _dptr(out["tags"], torch.int8), _dptr(out["cell"], torch.int32),
-            _dptr(out["level"], torch.int32), _dptr(out["delta"]), _dptr(out["normal"]),
-            _dptr(out["psi"]), _dptr(out["r"], torch.int32), _dptr(out["unit"], torch.int32),
-            _stream(stream)), "gcr_plan_export")
+        shapes = dict(tags=(self.n_cells, torch.int8), cell=(ng, torch.int32),
+                      level=(ng, torch.int32), delta=((d, ng), torch.float64),
+                      normal=((d, ng), torch.float64), psi=(ng, torch.float64),
+                      r=((d, ng), torch.int32), unit=(ng, torch.int32))
+        out = {}
+        for k in which:
+            if k not in shapes:
+                raise KeyError(f"unknown plan array {k!r}")
+            shp, dt = shapes[k]
+            out[k] = torch.empty(shp, dtype=dt, device=dev)
+        ptr = [_dptr(out.get(k), shapes[k][1]) for k in self.EXPORTS]
+        _check(lib().gcr_plan_export(self._h, *ptr, _stream(stream)), "gcr_plan_export")
         return out
+
+    def foot_points(self, stream=None):
+        """(S, normal), each f64 [dim][n_ghost]: where boundary data is due."""
+        dev = torch.device("cuda")
+        S = torch.empty((self.dim, self.n_ghost), dtype=torch.float64, device=dev)
+        n = torch.empty((self.dim, self.n_ghost), dtype=torch.float64, device=dev)
+        _check(lib().gcr_plan_foot_points(self._h, _dptr(S), _dptr(n), _stream(stream)),
+               "gcr_plan_foot_points")
+        return S, n
 
     def fill(self, fields: Sequence[torch.Tensor], bc_kind: Sequence[int],
              bc_val: Sequence[torch.Tensor], bc_type: Optional[Sequence] = None, stream=None):

@@ -223,6 +223,24 @@ __global__ void k_export_r(const uint32_t* __restrict__ code, int ng, int dim,
     for (int a = 0; a < dim; ++a) r[(int64_t)a * ng + p] = code_r(code[p], a);
 }
 
+// Foot points S = x_c + delta and the normals, [dim][ng] each
+__global__ void k_foot_points(GridD g, const int32_t* __restrict__ cell, const double* d0,
+                              const double* d1, const double* d2, const double* n0,
+                              const double* n1, const double* n2, int ng,
+                              double* __restrict__ S, double* __restrict__ nrm) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ng) return;
+  int i, j, k;
+  unlinear(g, cell[p], i, j, k);
+  const double* dl[3] = {d0, d1, d2};
+  const double* nn[3] = {n0, n1, n2};
+  const int q[3] = {i, j, k};
+  for (int a = 0; a < g.dim; ++a) {
+    if (S) S[(int64_t)a * ng + p] = centre(g, a, q[a]) + dl[a][p];
+    if (nrm) nrm[(int64_t)a * ng + p] = nn[a][p];
+  }
+}
+
 __global__ void k_export_unit(const int32_t* __restrict__ blk,
                               const int32_t* __restrict__ unit_mem, int ng,
                               int32_t* __restrict__ unit) {
@@ -375,6 +393,18 @@ gcr_status gcr_plan_export(const gcr_plan* p, int8_t* tags, int32_t* cell, int32
     if (unit) k_export_unit<<<nb, 256, 0, st>>>(p->blk, p->unit_mem, (int)ng, unit);
     GCR_HIP(hipGetLastError());
   }
+  return GCR_OK;
+}
+
+gcr_status gcr_plan_foot_points(const gcr_plan* p, double* S, double* normal, void* stream) {
+  if (!p) return GCR_E_ARG;
+  if (p->ng == 0 || (!S && !normal)) return GCR_OK;
+  const int ng = (int)p->ng;
+  const double* d2 = p->dim == 3 ? p->delta[2] : p->delta[0];
+  const double* n2 = p->dim == 3 ? p->nrm[2] : p->nrm[0];
+  k_foot_points<<<(unsigned)((ng + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+      p->inst.g, p->cell, p->delta[0], p->delta[1], d2, p->nrm[0], p->nrm[1], n2, ng, S, normal);
+  GCR_HIP(hipGetLastError());
   return GCR_OK;
 }
 

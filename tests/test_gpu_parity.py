@@ -346,3 +346,19 @@ def test_zero_normal_components(gcr):
     assert (op.normal == 0).any()
     check_plan(op, gp, strict_geometry=True)
     run_fill(gcr, op, gp, inst, inst.fields * 2, [DIRICHLET, NEUMANN])
+
+
+@pytest.mark.parametrize("which", ["circle128", "sphere64"])
+def test_foot_points(gcr, which):
+    """gcr_plan_foot_points: S = x_c + delta and the normals, against the
+    oracle's foot points (1e-12 of a cell width) and the exported arrays."""
+    inst = synth.circle128(seed=3) if which == "circle128" else synth.sphere256(seed=1, n=64)
+    op, gp = plan_pair(gcr, inst, HGC)
+    S, n = gp.foot_points()
+    ex = gp.export(which=("normal",))
+    torch.cuda.synchronize()
+    h = min(op.grid.h[: op.dim])
+    want = ghost_centres(op) + op.delta
+    check_close(host(S), want, np.full(want.shape, h), "foot points")
+    assert np.array_equal(host(n), host(ex["normal"]))
+    assert S.shape == (op.dim, op.n_ghost)

@@ -471,6 +471,40 @@ def test_star_closest_point_bruteforce():
         assert abs(v[0] * p.normal[1, g] - v[1] * p.normal[0, g]) < 1e-13
 
 
+def test_airfoil_closest_point_bruteforce():
+    """Four-digit closed-trailing-edge contour (x = s^2 parametrisation):
+    no dense contour sample is nearer than |psi|, S lies on the contour,
+    and away from the trailing-edge corner (x - S) is along the normal."""
+    inst = synth.airfoil4096(seed=1, n=512, m=64)
+    sh = inst.shape
+    p = oracle.OraclePlan(inst.grid, sh, HGC)
+    s = np.linspace(-1.0, 1.0, 2_000_001)
+    s2 = s * s
+    yt = 5 * sh.thick * (0.2969 * np.abs(s) - (0.1260 * s2 + 0.3516 * s2 ** 2
+                                                - 0.2843 * s2 ** 3 + 0.1036 * s2 ** 4))
+    bx, by = s2, np.sign(s) * yt
+    ca, sa = math.cos(sh.incidence), math.sin(sh.incidence)
+    le = sh.center
+    curve = np.stack([le[0] + sh.chord * (ca * bx + sa * by),
+                      le[1] + sh.chord * (-sa * bx + ca * by)])
+    ds = np.hypot(*np.diff(curve, axis=1)).max()
+    xc = ghost_centres(p)
+    S = xc + p.delta
+    te = curve[:, -1]
+    for g in range(0, p.n_ghost, max(1, p.n_ghost // 80)):
+        d = np.sqrt(((curve - xc[:, g:g + 1]) ** 2).sum(0)).min()
+        assert abs(p.psi[g]) <= d + 1e-14
+        assert d * d <= p.psi[g] ** 2 + 1.01 * (ds / 2) ** 2
+        dx, dy = (S[0, g] - le[0]) / sh.chord, (S[1, g] - le[1]) / sh.chord
+        b0, b1 = ca * dx - sa * dy, sa * dx + ca * dy
+        yb = 5 * sh.thick * (0.2969 * math.sqrt(max(b0, 0.0)) - 0.1260 * b0 - 0.3516 * b0 ** 2
+                             + 0.2843 * b0 ** 3 - 0.1036 * b0 ** 4)
+        assert abs(abs(b1) - yb) < 1e-12
+        if np.hypot(*(S[:, g] - te)) > 1e-12:
+            v = xc[:, g] - S[:, g]
+            assert abs(v[0] * p.normal[1, g] - v[1] * p.normal[0, g]) < 1e-13
+
+
 def test_sh_basis_matches_scipy():
     rng = np.random.default_rng(0)
     for _ in range(20):
