@@ -4,19 +4,27 @@ One step = the whole path on a 256^3 grid cut by a sphere (R = 0.3,
 sub-cell offset) with four FP64 fields (u, v, w Dirichlet; p Neumann), for
 each of the three ghost schemes (CGC, CGC_ES, HGC):
   plan (classification, tags, geometry, dependency levels, canonical order)
-  -> boundary data at the foot points (caller side, torch)
+  -> foot points and boundary data there (caller side, torch)
   -> level-by-level fill of the 4 fields
   -> boundary values and gradients at 2048 surface points
   -> pressure + viscous force.
 Metric: ghost cells per second (sum of the three plans' ghosts per step).
+
+Side measurements on the same GPU (reported beside the headline, never as
+`value`):
+  batched  64 2D star instances, n ~ U{128..2048}, 3 fields with mixed
+           Dirichlet/Neumann data, HGC: one persistent launch (fill + force)
+           against the plain per-instance forward (per-level launches);
+  fwd_bwd  384^3 grid, spherical-harmonic star, u, v, w, p, HGC: fill + drag
+           forward, then the reverse-level adjoint, against the forward alone.
 
 Prints one JSON line.  Only N=1 is supported (one GPU).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -29,6 +37,7 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 SCHEMES = (0, 1, 2)
+DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 
 
 def parse():
@@ -37,22 +46,55 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="oracle time budget of the CPU baseline sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and forward+adjoint side measurements")
+    ap.add_argument("--extra-reps", type=int, default=10)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first "
+                         "(reference kernel for byte counters)")
     return ap.parse_args()
 
 
-def bc_eval_torch(fields_fn, S, n, kinds):
-    """Boundary data at the foot points, evaluated by the caller (torch)."""
-    x, y, z = S[0], S[1], S[2]
+def bc_sphere_fields(S, n):
+    """Boundary data of the u, v, w, p fields at the foot points: values of
+    u = sin z + cos y, v = sin x + cos z, w = sin y + cos x and the normal
+    derivative of p = cos x cos y cos z (caller side, torch)."""
     import torch
-    u = torch.sin(z) + torch.cos(y)
-    v = torch.sin(x) + torch.cos(z)
-    w = torch.sin(y) + torch.cos(x)
-    dpx = -torch.sin(x) * torch.cos(y) * torch.cos(z)
-    dpy = -torch.cos(x) * torch.sin(y) * torch.cos(z)
-    dpz = -torch.cos(x) * torch.cos(y) * torch.sin(z)
-    dp = dpx * n[0] + dpy * n[1] + dpz * n[2]
-    return [u.contiguous(), v.contiguous(), w.contiguous(), dp.contiguous()]
+    s, c = torch.sin(S), torch.cos(S)
+    out = torch.empty((4, S.shape[1]), dtype=torch.float64, device=S.device)
+    torch.add(s[2], c[1], out=out[0])
+    torch.add(s[0], c[2], out=out[1])
+    torch.add(s[1], c[0], out=out[2])
+    # dp/dn = -(s0 c1 c2 n0 + c0 s1 c2 n1 + c0 c1 s2 n2)
+    t = torch.stack([s[0] * c[1] * c[2], c[0] * s[1] * c[2], c[0] * c[1] * s[2]])
+    torch.sum(t * n, dim=0, out=out[3])
+    out[3].neg_()
+    return out
+
+
+def _dev(torch, a, dtype=None):
+    """Contiguous device copy of a host array (inputs resident in HBM)."""
+    a = np.ascontiguousarray(a)
+    return torch.tensor(a, dtype=dtype, device="cuda")
+
+
+def kernel_traffic(name):
+    """HBM bytes per launch of `name` from the committed byte-counter summary,
+    or None when the summary is absent or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for rel in rec.get("sources", []):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -66,19 +108,21 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        a = torch.ones(nb, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     inst = synth.sphere256(seed=0)
     grid, shape = inst.grid, inst.shape
-    kinds = [0, 0, 0, 1]
+    kinds = [DIRICHLET, DIRICHLET, DIRICHLET, NEUMANN]
     # inputs resident in HBM before timing
-    fields = [torch.tensor(synth.sample(f, grid), dtype=torch.float64, device=dev)
-              for f in inst.fields]
+    fields = [_dev(torch, synth.sample(f, grid), torch.float64) for f in inst.fields]
     q = inst.queries
-    xq = torch.tensor(q.x, device=dev)
-    nq = torch.tensor(q.n, device=dev)
-    wq = torch.tensor(q.w, device=dev)
-    h = torch.tensor(grid.h[:3], dtype=torch.float64, device=dev)
-    lo = torch.tensor(grid.lo[:3], dtype=torch.float64, device=dev)
-    n0, n1 = grid.n[0], grid.n[1]
+    xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
     F = torch.empty(3, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -88,12 +132,9 @@ def main():
             plan = gcr.Plan(grid, shape, sch)
             if record is not None:
                 record.append(gcr.last_build_times())
-            ex = plan.export()
-            c = ex["cell"].to(torch.int64)
-            idx = torch.stack([c % n0, (c // n0) % n1, c // (n0 * n1)]).to(torch.float64)
-            S = lo[:, None] + (idx + 0.5) * h[:, None] + ex["delta"]
-            bc = bc_eval_torch(None, S, ex["normal"], kinds)
-            plan.fill(fields, kinds, bc)
+            S, nrm = plan.foot_points()
+            bc = bc_sphere_fields(S, nrm)
+            plan.fill(fields, kinds, list(bc))
             plan.surface(xq, fields)
             plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
             ng_total += plan.n_ghost
@@ -119,20 +160,27 @@ def main():
     ms_total = t0.elapsed_time(t1)
     ms_step = ms_total / args.steps
     value = ng_step / (ms_step * 1e-3)
+    gcr.set_profiling(False)
 
     # dominant HBM-bound kernel: classification writes the dense tag array
-    # (1 byte per cell) -- its duration from HIP events on the build stream
+    # (1 byte per cell); its duration from HIP events on the build stream
     cls_ms = float(np.mean([r["classify"] for r in rec]))
     stage_ms = {k: float(np.mean([r[k] for r in rec])) for k in rec[0]}
     ncell = grid.n[0] * grid.n[1] * grid.n[2]
     achieved = ncell / (cls_ms * 1e-3) / 1e9
+    traffic = kernel_traffic("k_classify")
     roofline = {"bound": "hbm", "kernel": "k_classify", "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "algorithmic_bytes": ncell, "avg_ms": round(cls_ms, 5)}
+                "traffic": traffic, "algorithmic_bytes": ncell, "avg_ms": round(cls_ms, 5)}
+
+    extras = {}
+    if not args.no_extras:
+        extras["batched"] = bench_batched(gcr, torch, synth, args.extra_reps)
+        extras["fwd_bwd"] = bench_fwd_bwd(gcr, torch, synth, args.extra_reps)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inst, args.cpu_reps)
+        cpu = cpu_baseline(inst, args.cpu_seconds)
 
     out = {
         "metric": "ghost cells/s (plan + fill + surface + forces, all 3 schemes)",
@@ -149,24 +197,161 @@ def main():
         "roofline": roofline,
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "wall_s": round(wall, 3),
+        **extras,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(inst, reps):
-    """The oracle, as it stands, on the same workload (full size), `reps`
-    passes; threads = OpenMP threads of the classification loop."""
+def _time(torch, fn, reps):
+    """Median and mean ms of `fn` over `reps` calls, HIP events on the
+    current stream, one untimed call first."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), float(np.mean(ts))
+
+
+def bench_batched(gcr, torch, synth, reps):
+    """64 uneven 2D instances: the persistent batched forward against the
+    plain per-instance forward (one launch per level, uncaptured)."""
+    insts = synth.stars64(seed=0)
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [2] * len(insts))
+    nf = 3
+    fields, bcv, bct, xq, nr, wq, nqs = [], [], [], [], [], [], []
+    ng = 0
+    ncell = 0
+    for inst, plan in zip(insts, B.plans):
+        S, n = plan.foot_points()
+        Sh, nh = S.cpu().numpy(), n.cpu().numpy()
+        kk = [synth.mixed_kinds(Sh, inst.shape.center, b) for b in inst.mixed_beta]
+        for f, k in zip(inst.fields, kk):
+            fields.append(_dev(torch, synth.sample(f, inst.grid), torch.float64))
+            bcv.append(_dev(torch, synth.bc_values(f, Sh, nh, k), torch.float64))
+            bct.append(_dev(torch, k.astype(np.uint8)))
+        q = inst.queries
+        xq.append(_dev(torch, q.x))
+        nr.append(_dev(torch, q.n))
+        wq.append(_dev(torch, q.w))
+        nqs.append(q.x.shape[1])
+        ng += plan.n_ghost
+        ncell += plan.n_cells
+    F = torch.zeros((len(insts), 3), dtype=torch.float64, device="cuda")
+
+    def batched():
+        B.forward(nf, fields, [MIXED] * nf, bcv, bc_type=bct, nq=nqs, xq=xq, nrm=nr, wq=wq,
+                  p_field=2, u_first=0, mu=1.0, F=F)
+
+    for _ in range(3):          # the tuner settles on its first calls
+        batched()
+    torch.cuda.synchronize()
+    tb, _ = _time(torch, batched, reps)
+    for p in B.plans:
+        p.set_schedule(1)
+
+    def plain():
+        for i, p in enumerate(B.plans):
+            fs = fields[i * nf:(i + 1) * nf]
+            p.fill(fs, [MIXED] * nf, bcv[i * nf:(i + 1) * nf], bc_type=bct[i * nf:(i + 1) * nf])
+            p.forces(xq[i], nr[i], wq[i], fs[2], fs[:2], 1.0, out=F[i])
+
+    tp, _ = _time(torch, plain, reps)
+    return {"workload": "stars64: 64 2D star bodies, n ~ U{128..2048}, 3 fields mixed BC, HGC, "
+                        "fill + force per instance",
+            "instances": len(insts), "cells": ncell, "ghosts": ng, "fields": nf,
+            "batched_ms": round(tb, 4), "plain_ms": round(tp, 4),
+            "batched_ghost_cells_per_s": round(ng / (tb * 1e-3), 1),
+            "plain_ghost_cells_per_s": round(ng / (tp * 1e-3), 1),
+            "speedup_vs_plain": round(tp / tb, 3)}
+
+
+def bench_fwd_bwd(gcr, torch, synth, reps):
+    """384^3 spherical-harmonic star, HGC, u, v, w, p: forward (fill + drag)
+    and forward + reverse-level adjoint (d drag / d interior field and
+    boundary data).  The dense zero-fill of the gradient buffers is timed
+    on its own and kept out of the adjoint figure."""
+    inst = synth.shstar384(seed=0)
+    plan = gcr.Plan(inst.grid, inst.shape, 2)
+    kinds = [f.bc for f in inst.fields]
+    nf = len(kinds)
+    S, n = plan.foot_points()
+    Sh, nh = S.cpu().numpy(), n.cpu().numpy()
+    fields = [_dev(torch, synth.sample(f, inst.grid), torch.float64) for f in inst.fields]
+    bcv = [_dev(torch, synth.bc_values(f, Sh, nh, k), torch.float64)
+           for f, k in zip(inst.fields, kinds)]
+    q = inst.queries
+    xq, nr, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
+    F = torch.empty(3, dtype=torch.float64, device="cuda")
+    gF = torch.tensor([1.0, 0.0, 0.0], dtype=torch.float64, device="cuda")
+    lam = [torch.zeros(plan.n_cells, dtype=torch.float64, device="cuda") for _ in range(nf)]
+    lam_bc = [torch.empty(plan.n_ghost, dtype=torch.float64, device="cuda") for _ in range(nf)]
+
+    def fwd():
+        plan.fill(fields, kinds, bcv)
+        plan.forces(xq, nr, wq, fields[3], fields[:3], 1.0, out=F)
+
+    def bwd():
+        plan.forces_adjoint(xq, nr, wq, 1.0, gF, lam[3], lam[:3])
+        plan.fill_adjoint(lam, kinds, lam_bc)
+
+    def zero():
+        for t in lam:
+            t.zero_()
+
+    def fwd_bwd():
+        fwd()
+        bwd()
+
+    tf, _ = _time(torch, fwd, reps)
+    # the adjoint accumulates into lam: zero it between timed calls, outside
+    # the timed region
+    ts = []
+    for _ in range(reps + 1):
+        zero()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fwd_bwd()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    tfb = float(np.median(ts[1:]))
+    tz, _ = _time(torch, zero, reps)
+    ng = plan.n_ghost
+    return {"workload": "shstar384: 384^3 grid on [-1,1]^3, SH star (l=2..4), u,v,w Dirichlet + "
+                        "p Neumann, HGC, fill + drag, then adjoint of drag",
+            "cells": plan.n_cells, "ghosts": ng, "fields": nf, "levels": plan.n_levels,
+            "fwd_ms": round(tf, 4), "fwd_bwd_ms": round(tfb, 4),
+            "fwd_bwd_over_fwd": round(tfb / tf, 3),
+            "fwd_ghost_cells_per_s": round(ng / (tf * 1e-3), 1),
+            "fwd_bwd_ghost_cells_per_s": round(ng / (tfb * 1e-3), 1),
+            "dense_grad_zero_ms": round(tz, 4)}
+
+
+def cpu_baseline(inst, seconds):
+    """The oracle, as it stands, on the same workload (full size): passes
+    over the three schemes until `seconds` of oracle time are spent (at
+    least one); threads = OpenMP threads of its per-cell loops."""
     import oracle
     import synth
 
     grid = inst.grid
     vals = np.stack([synth.sample(f, grid) for f in inst.fields])
-    kinds = [0, 0, 0, 1]
+    kinds = [DIRICHLET, DIRICHLET, DIRICHLET, NEUMANN]
     q = inst.queries
     ng_total = 0
     t = 0.0
-    for _ in range(reps):
+    passes = 0
+    while passes == 0 or t < seconds:
         for sch in SCHEMES:
             t0 = time.perf_counter()
             p = oracle.OraclePlan(grid, inst.shape, sch)
@@ -181,9 +366,10 @@ def cpu_baseline(inst, reps):
             p.forces(q.x, q.n, q.w, out[3], out[:3], 1.0)
             t += time.perf_counter() - t0
             ng_total += p.n_ghost
+        passes += 1
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(ng_total / t, 1), "unit": "ghost cells/s", "cores": cores,
-            "kind": "oracle", "sample": f"full sphere256 workload, {reps} passes x 3 schemes "
+            "kind": "oracle", "sample": f"full sphere256 workload, {passes} passes x 3 schemes "
                                         f"({t:.1f} s of oracle time)"}
 
 

@@ -2,15 +2,17 @@
 //
 // The fill is affine: phi_G = ws b_G + sum_k w_k phi_{P_k}.  Its adjoint runs
 // the levels in reverse.  Every value is produced by exactly one thread and
-// every sum is taken in a fixed order, so results are bitwise reproducible:
-//   * a ghost pulls from the ghosts that read it (found by a fixed-order
-//     search of the cells within the largest stencil multiplier, checking
-//     each candidate's own stencil code) -- they sit in higher levels;
-//   * a non-ghost cell read by several ghosts is updated by its first reader
-//     in that search order (its "owner"), which sums all readers;
-//   * a coupled unit solves its transposed system.
-// The surface adjoint groups caller points by anchor ghost (sorted buckets)
-// and pulls each box corner the same way.
+// every sum is taken in a fixed order, so results are bitwise reproducible.
+// Both adjoints pull through the transposed stencil ("support"), built on
+// the first adjoint call of a plan and kept with it: every cell that some
+// ghost's stencil box touches gets a slot holding its readers (ghost,
+// corner), sorted by (canonical ghost position, corner).  Then
+//   * a ghost pulls w * lambda from the ghosts that read it (higher levels);
+//   * a non-ghost cell sums all its readers once, in its own slot;
+//   * a coupled unit solves its transposed system;
+//   * the surface adjoint groups caller points by anchor ghost (sorted
+//     buckets), forms per-corner seeds, and each slot sums the seeds of the
+//     anchors whose box holds it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +23,208 @@
 
 namespace gcr {
 
+// Transposed stencil.  Entry = (reader << 4) | (corner << 1) | fill, with
+// fill = 1 when the fill reads that corner (corner > 0, not skipped);
+// corner 0 (the ghost's own cell) and skipped corners belong to the box the
+// surface evaluation uses.
+struct SupView {
+  const int32_t* off;    // [bound + 1] slot -> first entry
+  const int32_t* ent;    // [bound]
+  const int32_t* cell;   // [bound] slot -> cell
+  const int32_t* ghost;  // [bound] slot -> canonical ghost position or -1
+  const int32_t* gslot;  // [ng] ghost -> slot of its own cell
+  const int32_t* nslot;  // device count of slots
+  int64_t bound;         // ng << dim
+};
+
+constexpr uint32_t kSupEmpty = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t sup_hash(uint32_t c) {
+  uint32_t h = c * 2654435761u;
+  return h ^ (h >> 15);
+}
+
+struct SupBuild {
+  PlanD P;
+  uint32_t* key;
+  int32_t* val;
+  uint32_t hmask;
+  int32_t* nslot;
+  int32_t* cnt;
+  int32_t* off;
+  int32_t* fillc;
+  int32_t* ent;
+  int32_t* cell;
+  int32_t* ghost;
+  int32_t* gslot;
+  int64_t bound;
+};
+
+__device__ __forceinline__ int sup_find(const SupBuild& B, uint32_t q) {
+  uint32_t h = sup_hash(q) & B.hmask;
+  for (;;) {
+    const uint32_t k = B.key[h];
+    if (k == q) return B.val[h];
+    if (k == kSupEmpty) return -1;
+    h = (h + 1) & B.hmask;
+  }
+}
+
+// corner m of ghost p, or -1 off the grid
+template <int D>
+__device__ __forceinline__ int sup_corner(const PlanD& P, int p, int m, uint32_t& code) {
+  code = P.code[p];
+  const int c = P.cell[p];
+  int i, j, k;
+  unlinear(P.g, c, i, j, k);
+  if (!corner_in_grid(P.g, code, i, j, k, m)) return -1;
+  return c + corner_offset(P.g, code, m);
+}
+
+__global__ void k_sup_clear(SupBuild B) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= (int64_t)B.hmask) B.key[t] = kSupEmpty;
+  if (t < B.bound) {
+    B.cnt[t] = 0;
+    B.fillc[t] = 0;
+    B.ghost[t] = -1;
+  }
+  if (t == 0) B.nslot[0] = 0;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_sup_insert(SupBuild B) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B.bound) return;
+  const int p = (int)(t >> D), m = (int)(t & ((1 << D) - 1));
+  uint32_t code;
+  const int q = sup_corner<D>(B.P, p, m, code);
+  if (q < 0) return;
+  // the table holds at most `bound` keys in >= 2 * bound entries: a free
+  // entry is always reached
+  uint32_t h = sup_hash((uint32_t)q) & B.hmask;
+  for (;;) {
+    const uint32_t prev = atomicCAS(&B.key[h], kSupEmpty, (uint32_t)q);
+    if (prev == kSupEmpty) {
+      B.val[h] = atomicAdd(B.nslot, 1);
+      return;
+    }
+    if (prev == (uint32_t)q) return;
+    h = (h + 1) & B.hmask;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_sup_count(SupBuild B) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B.bound) return;
+  const int p = (int)(t >> D), m = (int)(t & ((1 << D) - 1));
+  uint32_t code;
+  const int q = sup_corner<D>(B.P, p, m, code);
+  if (q < 0) return;
+  const int s = sup_find(B, (uint32_t)q);
+  if (s < 0) return;
+  atomicAdd(&B.cnt[s], 1);
+  B.cell[s] = q;
+  if (m == 0) {
+    B.ghost[s] = p;
+    B.gslot[p] = s;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_sup_fill(SupBuild B) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B.bound) return;
+  const int p = (int)(t >> D), m = (int)(t & ((1 << D) - 1));
+  uint32_t code;
+  const int q = sup_corner<D>(B.P, p, m, code);
+  if (q < 0) return;
+  const int s = sup_find(B, (uint32_t)q);
+  if (s < 0) return;
+  const int fill = (m != 0 && !(m & code_skip(code))) ? 1 : 0;
+  B.ent[B.off[s] + atomicAdd(&B.fillc[s], 1)] = (p << 4) | (m << 1) | fill;
+}
+
+// each slot's readers in ascending (ghost, corner) order
+__global__ __launch_bounds__(256) void k_sup_sort(SupBuild B) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B.bound || s >= B.nslot[0]) return;
+  const int b = B.off[s], e = B.off[s + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int v = B.ent[i];
+    int j = i - 1;
+    while (j >= b && B.ent[j] > v) {
+      B.ent[j + 1] = B.ent[j];
+      --j;
+    }
+    B.ent[j + 1] = v;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_sadj_scan(const int32_t* __restrict__ cnt, int n,
+                                                    int32_t* __restrict__ off);
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+// Builds the transposed stencil of plan p on `st` (once; later calls reuse it).
+static gcr_status plan_support(gcr_plan* p, hipStream_t st, SupView* out) {
+  const int D = p->dim;
+  const int64_t bound = p->ng << D;
+  uint32_t H = 1;
+  while ((int64_t)H < 2 * bound) H <<= 1;
+  const size_t n32 = 2 * (size_t)H + 6 * (size_t)bound + 2 + (size_t)p->ng + 1;
+  char* base = (char*)p->sup;
+  if (!base) {
+    base = (char*)pool_alloc(sizeof(int32_t) * n32);
+    if (!base) return GCR_E_NOMEM;
+    SupBuild B;
+    std::memset(&B, 0, sizeof(B));
+    B.P = plan_view(p);
+    B.key = (uint32_t*)base;
+    B.val = (int32_t*)(B.key + H);
+    B.cnt = B.val + H;
+    B.off = B.cnt + bound + 1;
+    B.fillc = B.off + bound + 1;
+    B.ent = B.fillc + bound;
+    B.cell = B.ent + bound;
+    B.ghost = B.cell + bound;
+    B.gslot = B.ghost + bound;
+    B.nslot = B.gslot + p->ng;
+    B.hmask = H - 1;
+    B.bound = bound;
+    const int64_t nt = std::max<int64_t>((int64_t)H, bound);
+    k_sup_clear<<<nblk(nt, 256), 256, 0, st>>>(B);
+    if (D == 2) {
+      k_sup_insert<2><<<nblk(bound, 256), 256, 0, st>>>(B);
+      k_sup_count<2><<<nblk(bound, 256), 256, 0, st>>>(B);
+    } else {
+      k_sup_insert<3><<<nblk(bound, 256), 256, 0, st>>>(B);
+      k_sup_count<3><<<nblk(bound, 256), 256, 0, st>>>(B);
+    }
+    k_sadj_scan<<<1, 1024, 0, st>>>(B.cnt, (int)bound, B.off);
+    if (D == 2) k_sup_fill<2><<<nblk(bound, 256), 256, 0, st>>>(B);
+    else k_sup_fill<3><<<nblk(bound, 256), 256, 0, st>>>(B);
+    k_sup_sort<<<nblk(bound, 256), 256, 0, st>>>(B);
+    GCR_HIP(hipGetLastError());
+    p->sup = base;
+    p->sup_bound = bound;
+    p->sup_hmask = H - 1;
+  }
+  const uint32_t* key = (const uint32_t*)base;
+  const int32_t* val = (const int32_t*)(key + (p->sup_hmask + 1));
+  const int32_t* cnt = val + (p->sup_hmask + 1);
+  out->off = cnt + bound + 1;
+  const int32_t* fillc = out->off + bound + 1;
+  out->ent = fillc + bound;
+  out->cell = out->ent + bound;
+  out->ghost = out->cell + bound;
+  out->gslot = out->ghost + bound;
+  out->nslot = out->gslot + p->ng;
+  out->bound = bound;
+  return GCR_OK;
+}
+
 struct AdjArgs {
   PlanD P;
   int nf;
@@ -29,6 +233,7 @@ struct AdjArgs {
   double* lam[kMaxFields];     // dense, in/out
   double* lam_bc[kMaxFields];  // [ng]
   double* Lam;                 // [nf][ng] adjoint of each filled ghost value
+  SupView S;
 };
 
 template <int D>
@@ -46,47 +251,42 @@ __device__ __forceinline__ int field_bc(const AdjArgs& A, int f, int g) {
   return A.kind[f] == 2 ? (int)A.bt[f][g] : A.kind[f];
 }
 
-// Ghosts whose (non-skipped) stencil contains cell c, in a fixed order;
-// fn(g, corner) may return false to stop.
-template <int D, class Fn>
-__device__ __forceinline__ void for_each_reader(const PlanD& P, int c, Fn fn) {
-  int i, j, k;
-  unlinear(P.g, c, i, j, k);
-  const int rx = P.rmax[0], ry = P.rmax[1], rz = D == 3 ? P.rmax[2] : 0;
-  for (int oz = -rz; oz <= rz; ++oz) {
-    const int qk = k - oz;
-    if (D == 3 && (qk < 0 || qk >= P.g.n[2])) continue;
-    for (int oy = -ry; oy <= ry; ++oy) {
-      const int qj = j - oy;
-      if (qj < 0 || qj >= P.g.n[1]) continue;
-      for (int ox = -rx; ox <= rx; ++ox) {
-        if (ox == 0 && oy == 0 && oz == 0) continue;
-        const int qi = i - ox;
-        if (qi < 0 || qi >= P.g.n[0]) continue;
-        const int q = linear(P.g, qi, qj, qk);
-        const int8_t t = P.tags[q];
-        if (t != 2 && t != -2) continue;
-        const int g = ghost_at(P, q);
-        if (g < 0) continue;
-        const uint32_t code = P.code[g];
-        const int o[3] = {ox, oy, oz};
-        int mask = 0;
-        bool ok = true;
+// w[corner] * Lam of each fill reader of slot s, summed in entry order into
+// acc[f]; readers inside unit `skip_unit` (>= 0) are left out.
+template <int D>
+__device__ __forceinline__ void pull_readers(const AdjArgs& A, int s, int skip_unit,
+                                             double acc[kMaxFields]) {
+  const PlanD& P = A.P;
+  const int b = A.S.off[s], e = A.S.off[s + 1];
+  for (int t = b; t < e; ++t) {
+    const int en = A.S.ent[t];
+    if (!(en & 1)) continue;
+    const int r = en >> 4, m = (en >> 1) & 7;
+    if (skip_unit >= 0 && P.blk[r] == skip_unit) continue;
+    double wD[8], wN[8];
+    bool hD = false, hN = false;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          if (o[a] == 0) continue;
-          if (o[a] == code_e(code, a) * code_r(code, a)) mask |= 1 << a;
-          else ok = false;
-        }
-        if (!ok || (mask & code_skip(code))) continue;
-        if (!fn(g, mask)) return;
+    for (int f = 0; f < kMaxFields; ++f) {
+      if (f >= A.nf) break;
+      const int bc = field_bc(A, f, r);
+      if (bc == 0 && !hD) {
+        weights_of<D>(P, r, 0, wD);
+        hD = true;
+      } else if (bc != 0 && !hN) {
+        weights_of<D>(P, r, 1, wN);
+        hN = true;
       }
+      double wm = 0.0;
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k)
+        if (k == m) wm = bc == 0 ? wD[k] : wN[k];
+      acc[f] += wm * A.Lam[(int64_t)f * P.ng + r];
     }
   }
 }
 
-// Adjoint of coupled unit u at level `level`: (I - W_int)^T mu = lam +
-// external pulls, solved in an LDS workspace (one unit per thread).
+// Adjoint of coupled unit u: (I - W_int)^T mu = lam + external pulls,
+// solved in an LDS workspace (one unit per thread).
 template <int D>
 __device__ __forceinline__ void adj_unit(const AdjArgs& A, int u, UnitWS& ws) {
   const PlanD& P = A.P;
@@ -100,15 +300,15 @@ __device__ __forceinline__ void adj_unit(const AdjArgs& A, int u, UnitWS& ws) {
     for (int i = 0; i < k * k; ++i) ws.M[i] = 0.0;
     for (int i = 0; i < k; ++i) {
       ws.M[i * k + i] = 1.0;
-      double acc = A.lam[f][ws.cel[i]];
-      for_each_reader<D>(P, ws.cel[i], [&](int g, int mask) {
-        if (P.blk[g] == u) return true;   // inside the unit: handled by the solve
-        double w[8];
-        weights_of<D>(P, g, field_bc(A, f, g), w);
-        acc += w[mask] * A.Lam[(int64_t)f * P.ng + g];
-        return true;
-      });
-      ws.rhs[i] = acc;
+      double acc[kMaxFields];
+#pragma unroll
+      for (int g = 0; g < kMaxFields; ++g) acc[g] = 0.0;
+      pull_readers<D>(A, A.S.gslot[ws.mem[i]], u, acc);
+      double a = A.lam[f][ws.cel[i]];
+#pragma unroll
+      for (int g = 0; g < kMaxFields; ++g)
+        if (g == f) a += acc[g];
+      ws.rhs[i] = a;
     }
     for (int i = 0; i < k; ++i) {
       double w[8];
@@ -136,34 +336,14 @@ __device__ __forceinline__ void adj_units_of_level(const AdjArgs& A, int level, 
 template <int D>
 __device__ __forceinline__ void adj_ghost(const AdjArgs& A, int p) {
   const PlanD& P = A.P;
-  if (P.blk[p] >= 0) return;   // coupled units: adj_units_of_level
+  const int blk = P.blk[p];
   const int c = P.cell[p];
-  // fully unrolled over the field slots so the accumulators stay in registers
+  const int s = A.S.gslot[p];
+  if (blk >= 0) return;   // coupled units: adj_units_of_level
   double acc[kMaxFields];
 #pragma unroll
   for (int f = 0; f < kMaxFields; ++f) acc[f] = f < A.nf ? A.lam[f][c] : 0.0;
-  for_each_reader<D>(P, c, [&](int g, int mask) {
-    double wD[8], wN[8];
-    bool hD = false, hN = false;
-#pragma unroll
-    for (int f = 0; f < kMaxFields; ++f) {
-      if (f >= A.nf) break;
-      const int bc = field_bc(A, f, g);
-      if (bc == 0 && !hD) {
-        weights_of<D>(P, g, 0, wD);
-        hD = true;
-      } else if (bc != 0 && !hN) {
-        weights_of<D>(P, g, 1, wN);
-        hN = true;
-      }
-      double wm = 0.0;
-#pragma unroll
-      for (int k = 1; k < (1 << D); ++k)
-        if (k == mask) wm = bc == 0 ? wD[k] : wN[k];
-      acc[f] += wm * A.Lam[(int64_t)f * P.ng + g];
-    }
-    return true;
-  });
+  pull_readers<D>(A, s, -1, acc);
 #pragma unroll
   for (int f = 0; f < kMaxFields; ++f)
     if (f < A.nf) A.Lam[(int64_t)f * P.ng + p] = acc[f];
@@ -176,7 +356,7 @@ __global__ __launch_bounds__(256) void k_adj_range(AdjArgs A, int lo, int hi) {
 }
 
 template <int D>
-__global__ __launch_bounds__(1024) void k_adj_wg(AdjArgs A, const int32_t* __restrict__ lev_off,
+__global__ __launch_bounds__(256) void k_adj_wg(AdjArgs A, const int32_t* __restrict__ lev_off,
                                                  int nlev) {
   __shared__ UnitWS ws[64];
   for (int l = nlev - 1; l >= 0; --l) {
@@ -196,46 +376,34 @@ __global__ __launch_bounds__(64) void k_adj_units(AdjArgs A, int level) {
   adj_units_of_level<D>(A, level, ws, threadIdx.x, 64);
 }
 
-// Boundary-data sensitivities, non-ghost cells (owner rule), ghost slots zeroed.
+// Per slot: a ghost's own cell gives its boundary-data sensitivity and is
+// zeroed (the fill overwrites it); a non-ghost cell sums its readers once.
 template <int D>
 __global__ __launch_bounds__(256) void k_adj_support(AdjArgs A) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.S.bound || s >= A.S.nslot[0]) return;
   const PlanD& P = A.P;
-  if (p >= P.ng) return;
-  const int c = P.cell[p];
-  const uint32_t code = P.code[p];
-  for (int f = 0; f < A.nf; ++f) {
-    double w[8];
-    weights_of<D>(P, p, field_bc(A, f, p), w);
-    A.lam_bc[f][p] = w[0] * A.Lam[(int64_t)f * P.ng + p];
+  const int q = A.S.cell[s];
+  const int p = A.S.ghost[s];
+  if (p >= 0) {
+    for (int f = 0; f < A.nf; ++f) {
+      double w[8];
+      weights_of<D>(P, p, field_bc(A, f, p), w);
+      A.lam_bc[f][p] = w[0] * A.Lam[(int64_t)f * P.ng + p];
+      A.lam[f][q] = 0.0;
+    }
+    return;
   }
-  for (int m = 1; m < (1 << D); ++m) {
-    if (m & code_skip(code)) continue;
-    const int q = c + corner_offset(P.g, code, m);
-    const int8_t t = P.tags[q];
-    if (t == 2 || t == -2) continue;   // ghosts pulled their readers already
-    bool owner = true, first = true;
-    double acc[kMaxFields];
-    for (int f = 0; f < A.nf; ++f) acc[f] = 0.0;
-    for_each_reader<D>(P, q, [&](int g, int mask) {
-      if (first) {
-        first = false;
-        if (g != p) {
-          owner = false;
-          return false;
-        }
-      }
-      for (int f = 0; f < A.nf; ++f) {
-        double w[8];
-        weights_of<D>(P, g, field_bc(A, f, g), w);
-        acc[f] += w[mask] * A.Lam[(int64_t)f * P.ng + g];
-      }
-      return true;
-    });
-    if (owner)
-      for (int f = 0; f < A.nf; ++f) A.lam[f][q] += acc[f];
-  }
-  for (int f = 0; f < A.nf; ++f) A.lam[f][c] = 0.0;
+  bool any = false;
+  for (int t = A.S.off[s]; t < A.S.off[s + 1]; ++t) any |= (A.S.ent[t] & 1) != 0;
+  if (!any) return;
+  double acc[kMaxFields];
+#pragma unroll
+  for (int f = 0; f < kMaxFields; ++f) acc[f] = 0.0;
+  pull_readers<D>(A, (int)s, -1, acc);
+#pragma unroll
+  for (int f = 0; f < kMaxFields; ++f)
+    if (f < A.nf) A.lam[f][q] += acc[f];
 }
 
 // --------------------------------------------------------------------------
@@ -256,6 +424,7 @@ struct SurfAdjArgs {
   int32_t* fillc;        // [ng]
   int32_t* bucket;       // [nq]
   double* seed;          // [nf][8][ng]
+  SupView Sp;
 };
 
 __global__ void k_zero_i32(int32_t* __restrict__ a, int64_t n) {
@@ -270,12 +439,16 @@ __global__ void k_zero_f64(double* __restrict__ a, int64_t n) {
 
 template <int D>
 __global__ __launch_bounds__(256) void k_sadj_anchor(SurfAdjArgs S) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= S.nq) return;
+  constexpr int NL = anchor_lanes<D>();
+  const int sub = (int)threadIdx.x % NL;
+  const int64_t q = (int64_t)blockIdx.x * (256 / NL) + threadIdx.x / NL;
+  const bool active = q < S.nq;
   double x[3] = {0.0, 0.0, 0.0};
+  if (active)
 #pragma unroll
-  for (int a = 0; a < D; ++a) x[a] = S.xq[a * S.nq + q];
-  const int g = find_anchor<D>(S.P, x);
+    for (int a = 0; a < D; ++a) x[a] = S.xq[a * S.nq + q];
+  const int g = find_anchor_group<D, NL>(S.P, x, sub, active);
+  if (!active || sub != 0) return;
   S.anchor[q] = g;
   if (g >= 0) atomicAdd(&S.cnt[g], 1);
 }
@@ -355,66 +528,30 @@ __global__ __launch_bounds__(256) void k_sadj_seed(SurfAdjArgs S) {
   }
 }
 
-// each box corner of each anchor: the first anchor (fixed search order) whose
-// box holds the cell adds every anchor's seed for it
-template <int D>
+// each slot: the seeds of every anchor whose box holds its cell, in entry
+// order (ghosts that anchor no point have no seeds)
 __global__ __launch_bounds__(256) void k_sadj_pull(SurfAdjArgs S) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const PlanD& P = S.P;
-  if (g >= P.ng) return;
-  if (S.off[g] == S.off[g + 1]) return;
-  const uint32_t code = P.code[g];
-  int gi, gj, gk;
-  unlinear(P.g, P.cell[g], gi, gj, gk);
-  for (int m = 0; m < (1 << D); ++m) {
-    if (!corner_in_grid(P.g, code, gi, gj, gk, m)) continue;
-    const int c = P.cell[g] + corner_offset(P.g, code, m);
-    int i, j, k;
-    unlinear(P.g, c, i, j, k);
-    const int rx = P.rmax[0], ry = P.rmax[1], rz = D == 3 ? P.rmax[2] : 0;
-    bool owner = true, first = true, stop = false;
-    double acc[kMaxFields];
-    for (int f = 0; f < S.nf; ++f) acc[f] = 0.0;
-    for (int oz = -rz; oz <= rz && !stop; ++oz) {
-      const int qk = k - oz;
-      if (D == 3 && (qk < 0 || qk >= P.g.n[2])) continue;
-      for (int oy = -ry; oy <= ry && !stop; ++oy) {
-        const int qj = j - oy;
-        if (qj < 0 || qj >= P.g.n[1]) continue;
-        for (int ox = -rx; ox <= rx && !stop; ++ox) {
-          const int qi = i - ox;
-          if (qi < 0 || qi >= P.g.n[0]) continue;
-          const int q = linear(P.g, qi, qj, qk);
-          const int8_t t = P.tags[q];
-          if (t != 2 && t != -2) continue;
-          const int a2 = ghost_at(P, q);
-          if (a2 < 0 || S.off[a2] == S.off[a2 + 1]) continue;
-          const uint32_t c2 = P.code[a2];
-          const int o[3] = {ox, oy, oz};
-          int mask = 0;
-          bool ok = true;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S.Sp.bound || s >= S.Sp.nslot[0]) return;
+  const int ng = S.P.ng;
+  double acc[kMaxFields];
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            if (o[a] == 0) continue;
-            if (o[a] == code_e(c2, a) * code_r(c2, a)) mask |= 1 << a;
-            else ok = false;
-          }
-          if (!ok) continue;
-          if (first) {
-            first = false;
-            if (a2 != g) {
-              owner = false;
-              stop = true;
-              break;
-            }
-          }
-          for (int f = 0; f < S.nf; ++f) acc[f] += S.seed[((int64_t)f * 8 + mask) * P.ng + a2];
-        }
-      }
-    }
-    if (owner && !first)
-      for (int f = 0; f < S.nf; ++f) S.lam[f][c] += acc[f];
+  for (int f = 0; f < kMaxFields; ++f) acc[f] = 0.0;
+  bool any = false;
+  for (int t = S.Sp.off[s]; t < S.Sp.off[s + 1]; ++t) {
+    const int en = S.Sp.ent[t];
+    const int r = en >> 4, m = (en >> 1) & 7;
+    if (S.off[r] == S.off[r + 1]) continue;
+    any = true;
+#pragma unroll
+    for (int f = 0; f < kMaxFields; ++f)
+      if (f < S.nf) acc[f] += S.seed[((int64_t)f * 8 + m) * ng + r];
   }
+  if (!any) return;
+  const int q = S.Sp.cell[s];
+#pragma unroll
+  for (int f = 0; f < kMaxFields; ++f)
+    if (f < S.nf) S.lam[f][q] += acc[f];
 }
 
 // forces adjoint: J = gF . F gives, per point, d J / d p = -w (gF . n) and
@@ -441,8 +578,6 @@ __global__ void k_forces_seed(int64_t nq, int dim, const double* __restrict__ nr
       ggrad[((int64_t)(1 + i) * dim + j) * nq + q] = mu * w * (g[i] * n[j] + g[j] * n[i]);
 }
 
-static inline unsigned nblk(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
-
 static gcr_status surface_adjoint_impl(gcr_plan* p, int64_t nq, const double* xq, int nf,
                                        const double* gval, const double* ggrad,
                                        double* const* lam, hipStream_t st) {
@@ -457,6 +592,10 @@ static gcr_status surface_adjoint_impl(gcr_plan* p, int64_t nq, const double* xq
   S.gval = gval;
   S.ggrad = ggrad;
   for (int f = 0; f < nf; ++f) S.lam[f] = lam[f];
+  {
+    const gcr_status ss = plan_support(p, st, &S.Sp);
+    if (ss != GCR_OK) return ss;
+  }
   char* ib = (char*)plan_scratch(p, 1, sizeof(int32_t) * (2 * nq + 3 * (ng + 1)));
   double* sb = (double*)plan_scratch(p, 2, sizeof(double) * (size_t)nf * 8 * ng);
   if (!ib || !sb) return GCR_E_NOMEM;
@@ -469,17 +608,14 @@ static gcr_status surface_adjoint_impl(gcr_plan* p, int64_t nq, const double* xq
   k_zero_i32<<<nblk(ng + 1, 256), 256, 0, st>>>(S.cnt, ng + 1);
   k_zero_i32<<<nblk(ng + 1, 256), 256, 0, st>>>(S.fillc, ng + 1);
   const int D = p->dim;
-  if (D == 2) k_sadj_anchor<2><<<nblk(nq, 256), 256, 0, st>>>(S);
-  else k_sadj_anchor<3><<<nblk(nq, 256), 256, 0, st>>>(S);
+  const unsigned nba = (unsigned)force_blocks(D, nq);
+  if (D == 2) k_sadj_anchor<2><<<nba, 256, 0, st>>>(S);
+  else k_sadj_anchor<3><<<nba, 256, 0, st>>>(S);
   k_sadj_scan<<<1, 1024, 0, st>>>(S.cnt, (int)ng, S.off);
   k_sadj_bucket<<<nblk(nq, 256), 256, 0, st>>>(S);
-  if (D == 2) {
-    k_sadj_seed<2><<<nblk(ng, 256), 256, 0, st>>>(S);
-    k_sadj_pull<2><<<nblk(ng, 256), 256, 0, st>>>(S);
-  } else {
-    k_sadj_seed<3><<<nblk(ng, 256), 256, 0, st>>>(S);
-    k_sadj_pull<3><<<nblk(ng, 256), 256, 0, st>>>(S);
-  }
+  if (D == 2) k_sadj_seed<2><<<nblk(ng, 256), 256, 0, st>>>(S);
+  else k_sadj_seed<3><<<nblk(ng, 256), 256, 0, st>>>(S);
+  k_sadj_pull<<<nblk(S.Sp.bound, 256), 256, 0, st>>>(S);
   GCR_HIP(hipGetLastError());
   return GCR_OK;
 }
@@ -553,12 +689,16 @@ gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf, double* const* lam
   A.Lam = (double*)plan_scratch(p, 4, sizeof(double) * (size_t)nf * ng);
   if (!A.Lam) return GCR_E_NOMEM;
   hipStream_t st = (hipStream_t)stream;
+  {
+    const gcr_status ss = plan_support(p, st, &A.S);
+    if (ss != GCR_OK) return ss;
+  }
   // the same schedule family as the fill: one workgroup, or one launch per level
   const bool wg = (p->schedule == kSchedWorkgroup) ||
                   (p->schedule == kSchedAuto && p->tuned == kSchedWorkgroup);
   if (wg) {
-    if (p->dim == 2) k_adj_wg<2><<<1, 1024, 0, st>>>(A, p->d_lev_off, p->nlev);
-    else k_adj_wg<3><<<1, 1024, 0, st>>>(A, p->d_lev_off, p->nlev);
+    if (p->dim == 2) k_adj_wg<2><<<1, 256, 0, st>>>(A, p->d_lev_off, p->nlev);
+    else k_adj_wg<3><<<1, 256, 0, st>>>(A, p->d_lev_off, p->nlev);
   } else {
     for (int l = p->nlev - 1; l >= 0; --l) {
       const int lo = p->lev_off[l], hi = p->lev_off[l + 1];
@@ -572,8 +712,8 @@ gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf, double* const* lam
         }
     }
   }
-  if (p->dim == 2) k_adj_support<2><<<nblk(ng, 256), 256, 0, st>>>(A);
-  else k_adj_support<3><<<nblk(ng, 256), 256, 0, st>>>(A);
+  if (p->dim == 2) k_adj_support<2><<<nblk(A.S.bound, 256), 256, 0, st>>>(A);
+  else k_adj_support<3><<<nblk(A.S.bound, 256), 256, 0, st>>>(A);
   GCR_HIP(hipGetLastError());
   return GCR_OK;
 }

@@ -88,40 +88,43 @@ __global__ __launch_bounds__(256) void k_surface_ghost(SurfArgs S) {
   }
 }
 
+// One group of anchor_lanes<D>() lanes per point: the group finds the
+// anchor, then lane f evaluates field f.
 template <int D>
 __global__ __launch_bounds__(256) void k_surface_query(SurfArgs S, int64_t nq,
                                                        const double* __restrict__ xq) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+  constexpr int NL = anchor_lanes<D>();
+  const int sub = (int)threadIdx.x % NL;
+  const int64_t q = (int64_t)blockIdx.x * (256 / NL) + threadIdx.x / NL;
+  const bool active = q < nq;
   const PlanD& P = S.P;
   double x[3] = {0.0, 0.0, 0.0};
+  if (active)
 #pragma unroll
-  for (int a = 0; a < D; ++a) x[a] = xq[a * nq + q];
-  const int g = find_anchor<D>(P, x);
-  if (S.anchor) S.anchor[q] = g;
-  double rel[3] = {0.0, 0.0, 0.0};
-  uint32_t code = 0;
+    for (int a = 0; a < D; ++a) x[a] = xq[a * nq + q];
+  const int g = find_anchor_group<D, NL>(P, x, sub, active);
+  if (!active) return;
+  if (sub == 0 && S.anchor) S.anchor[q] = g;
+  if (sub >= S.nf) return;
+  const int f = sub;
+  const double nanv = __longlong_as_double(0x7ff8000000000000LL);
+  double val = nanv, grad[3] = {nanv, nanv, nanv};
   if (g >= 0) {
-    code = P.code[g];
+    const uint32_t code = P.code[g];
     int i, j, k;
     unlinear(P.g, P.cell[g], i, j, k);
     const int ijk[3] = {i, j, k};
+    double rel[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
+    double v[8];
+    corner_values<D>(P, g, S.f[f], v);
+    box_eval<D>(rel, code, P.g.h, v, val, grad);
   }
-  const double nanv = __longlong_as_double(0x7ff8000000000000LL);
-  for (int f = 0; f < S.nf; ++f) {
-    double val = nanv, grad[3] = {nanv, nanv, nanv};
-    if (g >= 0) {
-      double v[8];
-      corner_values<D>(P, g, S.f[f], v);
-      box_eval<D>(rel, code, P.g.h, v, val, grad);
-    }
-    if (S.val) S.val[(int64_t)f * nq + q] = val;
-    if (S.grad)
+  if (S.val) S.val[(int64_t)f * nq + q] = val;
+  if (S.grad)
 #pragma unroll
-      for (int a = 0; a < D; ++a) S.grad[((int64_t)f * D + a) * nq + q] = grad[a];
-  }
+    for (int a = 0; a < D; ++a) S.grad[((int64_t)f * D + a) * nq + q] = grad[a];
 }
 
 void launch_surface_ghost(const SurfArgs& S, hipStream_t st) {
@@ -133,7 +136,7 @@ void launch_surface_ghost(const SurfArgs& S, hipStream_t st) {
 
 void launch_surface_query(const SurfArgs& S, int64_t nq, const double* xq, hipStream_t st) {
   if (nq <= 0) return;
-  const unsigned nb = (unsigned)((nq + 255) / 256);
+  const unsigned nb = (unsigned)force_blocks(S.P.g.dim, nq);
   if (S.P.g.dim == 2) k_surface_query<2><<<nb, 256, 0, st>>>(S, nq, xq);
   else k_surface_query<3><<<nb, 256, 0, st>>>(S, nq, xq);
 }
@@ -143,62 +146,76 @@ void launch_surface_query(const SurfArgs& S, int64_t nq, const double* xq, hipSt
 // fixed tree order (per-block partials, then one block in block order)
 // --------------------------------------------------------------------------
 
-template <int D>
-__device__ __forceinline__ void traction(const PlanD& P, const ForceArgs& F, int64_t q,
-                                         double t[3]) {
-  t[0] = t[1] = t[2] = 0.0;
-  double x[3] = {0.0, 0.0, 0.0}, n[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    x[a] = F.xq[a * F.nq + q];
-    n[a] = F.nrm[a * F.nq + q];
-  }
-  const int g = find_anchor<D>(P, x);
-  if (g < 0) {
-    t[0] = t[1] = t[2] = __longlong_as_double(0x7ff8000000000000LL);
-    return;
-  }
-  const uint32_t code = P.code[g];
-  int i, j, k;
-  unlinear(P.g, P.cell[g], i, j, k);
-  const int ijk[3] = {i, j, k};
-  double rel[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
-  double v[8], pv, pg[3], gu[3][3];
-  corner_values<D>(P, g, F.p, v);
-  box_eval<D>(rel, code, P.g.h, v, pv, pg);
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    double uv;
-    corner_values<D>(P, g, F.u[c], v);
-    box_eval<D>(rel, code, P.g.h, v, uv, gu[c]);   // gu[c][a] = d u_c / d x_a
-  }
-  const double w = F.wq[q];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    double s = -pv * n[a];
-#pragma unroll
-    for (int b = 0; b < D; ++b) s += F.mu * (gu[a][b] + gu[b][a]) * n[b];
-    t[a] = w * s;
-  }
-}
-
+// One group per point: the group finds the anchor, lane 0 evaluates p and
+// lane 1 + c the velocity component u_c; lane 0 gathers the gradients and
+// forms the weighted traction.  Per-block partials are summed in point
+// order by one thread, so the reduction order is fixed.
 template <int D>
 __global__ __launch_bounds__(256) void k_forces(PlanD P, ForceArgs F, double* __restrict__ part) {
-  __shared__ double sh[256][3];
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double t[3] = {0.0, 0.0, 0.0};
-  if (q < F.nq) traction<D>(P, F, q, t);
-  for (int a = 0; a < 3; ++a) sh[threadIdx.x][a] = t[a];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int a = 0; a < 3; ++a) sh[threadIdx.x][a] += sh[threadIdx.x + s][a];
-    __syncthreads();
+  constexpr int NL = anchor_lanes<D>();
+  constexpr int PPB = 256 / NL;
+  __shared__ double sh[PPB][3];
+  const int sub = (int)threadIdx.x % NL;
+  const int grp = (int)threadIdx.x / NL;
+  const int64_t q = (int64_t)blockIdx.x * PPB + grp;
+  const bool active = q < F.nq;
+  double x[3] = {0.0, 0.0, 0.0};
+  if (active)
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = F.xq[a * F.nq + q];
+  const int g = find_anchor_group<D, NL>(P, x, sub, active);
+  // field of this lane: 0 = p, 1 + c = u_c
+  double val = 0.0, grad[3] = {0.0, 0.0, 0.0};
+  if (active && g >= 0 && sub <= D) {
+    const uint32_t code = P.code[g];
+    int i, j, k;
+    unlinear(P.g, P.cell[g], i, j, k);
+    const int ijk[3] = {i, j, k};
+    double rel[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
+    double v[8];
+    corner_values<D>(P, g, sub == 0 ? F.p : F.u[sub - 1], v);
+    box_eval<D>(rel, code, P.g.h, v, val, grad);
   }
-  if (threadIdx.x == 0)
-    for (int a = 0; a < 3; ++a) part[blockIdx.x * 3 + a] = sh[0][a];
+  // gu[c][a] = d u_c / d x_a, from lane 1 + c of this group
+  double gu[3][3];
+  const int base = grp * NL;
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int a = 0; a < D; ++a) gu[c][a] = __shfl(grad[a], base + 1 + c, 64);
+  if (sub == 0) {
+    double t[3] = {0.0, 0.0, 0.0};
+    if (active) {
+      if (g < 0) {
+        t[0] = t[1] = t[2] = __longlong_as_double(0x7ff8000000000000LL);
+      } else {
+        const double w = F.wq[q];
+        double n[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) n[a] = F.nrm[a * F.nq + q];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = -val * n[a];
+#pragma unroll
+          for (int b = 0; b < D; ++b) s += F.mu * (gu[a][b] + gu[b][a]) * n[b];
+          t[a] = w * s;
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sh[grp][a] = t[a];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < PPB; ++i)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) s[a] += sh[i][a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) part[blockIdx.x * 3 + a] = s[a];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nb,
@@ -222,7 +239,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 
 void launch_forces(const PlanD& P, const ForceArgs& F, double* part, double* out,
                    hipStream_t st) {
-  const int nb = (int)std::max<int64_t>(1, (F.nq + 255) / 256);
+  const int nb = (int)force_blocks(P.g.dim, F.nq);
   if (P.g.dim == 2) k_forces<2><<<nb, 256, 0, st>>>(P, F, part);
   else k_forces<3><<<nb, 256, 0, st>>>(P, F, part);
   k_sum_partials<<<1, 256, 0, st>>>(part, nb, P.g.dim, out);

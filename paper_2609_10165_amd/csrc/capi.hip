@@ -177,6 +177,8 @@ int bucket(int64_t v) {
 }
 }  // namespace
 
+constexpr int64_t kWgMaxGhosts = 8192;
+
 static gcr_status tuned_fill(gcr_plan* p, const FillArgs& A, hipStream_t st) {
   if (p->tuned < 0) {
     auto key = std::make_tuple(p->dim, bucket(p->ng), bucket(p->nlev), A.nf);
@@ -193,6 +195,8 @@ static gcr_status tuned_fill(gcr_plan* p, const FillArgs& A, hipStream_t st) {
       int pick = kSchedLevels;
       const int cands[3] = {kSchedLevels, kSchedWorkgroup, kSchedGraph};
       for (int c : cands) {
+        // one workgroup cannot keep up once a level spans many rounds of it
+        if (c == kSchedWorkgroup && p->ng > kWgMaxGhosts) continue;
         gcr_status s = run_fill(p, A, c, st);  // warm (and graph capture)
         if (s != GCR_OK) continue;
         GCR_HIP(hipEventRecord(e0, st));
@@ -286,6 +290,7 @@ using namespace gcr;
 gcr_plan::~gcr_plan() {
   for (int i = 0; i < kScratchSlots; ++i)
     if (scr[i]) pool_free(scr[i]);
+  if (sup) pool_free(sup);
 }
 
 gcr_batch::~gcr_batch() {
@@ -479,7 +484,7 @@ gcr_status gcr_forces(const gcr_plan* p, int64_t nq, const double* xq, const dou
   A.p = pf;
   for (int a = 0; a < p->dim; ++a) A.u[a] = u[a];
   A.mu = mu;
-  const int64_t nb = std::max<int64_t>(1, (nq + 255) / 256);
+  const int64_t nb = force_blocks(p->dim, nq);
   double* part = (double*)plan_scratch(const_cast<gcr_plan*>(p), 0, sizeof(double) * 3 * nb);
   if (!part) return GCR_E_NOMEM;
   launch_forces(plan_view(p), A, part, F, (hipStream_t)stream);

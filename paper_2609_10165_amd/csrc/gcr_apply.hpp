@@ -182,4 +182,68 @@ __device__ __forceinline__ int find_anchor(const PlanD& P, const double x[3]) {
   return best;
 }
 
+// The same anchor found by NL cooperating lanes (NL a power of two, the
+// lanes sub = 0..NL-1 of one aligned group of a wave, all of them calling):
+// each lane scans every NL-th cell of the 5^D neighbourhood, then the group
+// reduces (d2, linear index) lexicographically, which picks the cell the
+// serial scan picks.  `active` false makes a lane scan nothing (it still
+// takes part in the reduction).
+template <int D>
+constexpr int anchor_lanes() { return D == 3 ? 64 : 32; }
+
+template <int D, int NL>
+__device__ __forceinline__ int find_anchor_group(const PlanD& P, const double x[3], int sub,
+                                                 bool active) {
+  constexpr int NC = D == 3 ? 125 : 25;
+  int qi[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) qi[a] = (int)floor((x[a] - P.g.lo[a]) / P.g.h[a]);
+  double bd = 1e300;
+  int bc = 0x7fffffff, bg = -1;
+  if (active) {
+    for (int t = sub; t < NC; t += NL) {
+      const int ix = qi[0] - 2 + t % 5;
+      const int jy = qi[1] - 2 + (t / 5) % 5;
+      const int kz = D == 3 ? qi[2] - 2 + t / 25 : 0;
+      if (ix < 0 || ix >= P.g.n[0] || jy < 0 || jy >= P.g.n[1]) continue;
+      if (D == 3 && (kz < 0 || kz >= P.g.n[2])) continue;
+      const int c = linear(P.g, ix, jy, kz);
+      const int8_t tg = P.tags[c];
+      if (tg != 2 && tg != -2) continue;
+      const int g = ghost_at(P, c);
+      if (g < 0) continue;
+      const int q[3] = {ix, jy, kz};
+      double d2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double s = centre(P.g, a, q[a]) + P.dl[a][g];
+        d2 += (x[a] - s) * (x[a] - s);
+      }
+      if (d2 < bd || (d2 == bd && c < bc)) {
+        bd = d2;
+        bc = c;
+        bg = g;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = NL / 2; o > 0; o >>= 1) {
+    const double od = __shfl_xor(bd, o, NL);
+    const int oc = __shfl_xor(bc, o, NL);
+    const int og = __shfl_xor(bg, o, NL);
+    if (od < bd || (od == bd && oc < bc)) {
+      bd = od;
+      bc = oc;
+      bg = og;
+    }
+  }
+  return bg;
+}
+
+// Blocks (and per-block force partials) of the force kernel for nq points.
+inline int64_t force_blocks(int dim, int64_t nq) {
+  const int ppb = 256 / (dim == 3 ? anchor_lanes<3>() : anchor_lanes<2>());
+  return std::max<int64_t>(1, (nq + ppb - 1) / ppb);
+}
+
 }  // namespace gcr

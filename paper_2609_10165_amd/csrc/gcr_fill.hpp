@@ -49,39 +49,63 @@ __device__ __forceinline__ void fill_unit_field(const PlanD& P, int u, double* F
   for (int i = 0; i < k; ++i) F[ws.cel[i]] = ws.rhs[i];
 }
 
+// Fields are gathered before any store: a ghost of level k reads only
+// fluid cells and ghosts of lower levels, never a slot that this launch
+// writes, so every load of every field may be issued first.  (The compiler
+// cannot prove that on its own: the field arrays could alias.)
+constexpr int kFieldGroup = 4;
+
 template <int D>
 __device__ __forceinline__ void fill_ghost(const FillArgs& A, int p) {
   const PlanD& P = A.P;
-  if (P.blk[p] >= 0) return;   // coupled unit: solved by fill_units_of_level
+  const int blk = P.blk[p];
   const int c = P.cell[p];
   const uint32_t code = P.code[p];
-  const uint32_t skip = code_skip(code);
   double dl[3], nn[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     dl[a] = a < D ? P.dl[a][p] : 0.0;
     nn[a] = a < D ? P.nn[a][p] : 0.0;
   }
+  if (blk >= 0) return;   // coupled unit: solved by fill_units_of_level
+  const uint32_t skip = code_skip(code);
   int off[8];
 #pragma unroll
   for (int k = 1; k < (1 << D); ++k) off[k] = c + corner_offset(P.g, code, k);
-  double wD[8], wN[8];
-  bool haveD = false, haveN = false;
-  for (int f = 0; f < A.nf; ++f) {
-    const int bc = A.kind[f] == 2 ? (int)A.bt[f][p] : A.kind[f];
-    if (bc == 0 && !haveD) {
-      ghost_weights<D>(dl, nn, code, P.g.h, 0, wD);
-      haveD = true;
-    } else if (bc != 0 && !haveN) {
-      ghost_weights<D>(dl, nn, code, P.g.h, 1, wN);
-      haveN = true;
-    }
-    double* F = A.f[f];
-    double v = (bc == 0 ? wD[0] : wN[0]) * A.b[f][p];
+  for (int f0 = 0; f0 < A.nf; f0 += kFieldGroup) {
+    double val[kFieldGroup][8], bv[kFieldGroup];
+    int bc[kFieldGroup];
 #pragma unroll
-    for (int k = 1; k < (1 << D); ++k)
-      if (!(k & skip)) v += (bc == 0 ? wD[k] : wN[k]) * F[off[k]];
-    F[c] = v;
+    for (int j = 0; j < kFieldGroup; ++j) {
+      const int f = f0 + j;
+      if (f >= A.nf) break;
+      bc[j] = A.kind[f] == 2 ? (int)A.bt[f][p] : A.kind[f];
+      bv[j] = A.b[f][p];
+      const double* F = A.f[f];
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k) val[j][k] = (k & skip) ? 0.0 : F[off[k]];
+    }
+    bool anyD = false, anyN = false;
+#pragma unroll
+    for (int j = 0; j < kFieldGroup; ++j) {
+      if (f0 + j >= A.nf) break;
+      anyD |= bc[j] == 0;
+      anyN |= bc[j] != 0;
+    }
+    double wD[8], wN[8];
+    if (anyD) ghost_weights<D>(dl, nn, code, P.g.h, 0, wD);
+    if (anyN) ghost_weights<D>(dl, nn, code, P.g.h, 1, wN);
+#pragma unroll
+    for (int j = 0; j < kFieldGroup; ++j) {
+      const int f = f0 + j;
+      if (f >= A.nf) break;
+      const bool dir = bc[j] == 0;
+      double v = (dir ? wD[0] : wN[0]) * bv[j];
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k)
+        if (!(k & skip)) v += (dir ? wD[k] : wN[k]) * val[j][k];
+      A.f[f][c] = v;
+    }
   }
 }
 
@@ -101,22 +125,27 @@ __device__ __forceinline__ void fill_units_of_level(const FillArgs& A, int level
 template <int D>
 __device__ __forceinline__ void fill_single(const PlanD& P, int p, double* F, const double* b,
                                             const uint8_t* bt, int kind) {
-  if (P.blk[p] >= 0) return;
+  const int blk = P.blk[p];
   const int c = P.cell[p];
   const uint32_t code = P.code[p];
-  const uint32_t skip = code_skip(code);
-  double dl[3], nn[3], w[8];
+  double dl[3], nn[3], w[8], val[8];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     dl[a] = a < D ? P.dl[a][p] : 0.0;
     nn[a] = a < D ? P.nn[a][p] : 0.0;
   }
   const int bc = kind == 2 ? (int)bt[p] : kind;
-  ghost_weights<D>(dl, nn, code, P.g.h, bc, w);
-  double v = w[0] * b[p];
+  const double bv = b[p];
+  if (blk >= 0) return;
+  const uint32_t skip = code_skip(code);
 #pragma unroll
   for (int k = 1; k < (1 << D); ++k)
-    if (!(k & skip)) v += w[k] * F[c + corner_offset(P.g, code, k)];
+    val[k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
+  ghost_weights<D>(dl, nn, code, P.g.h, bc, w);
+  double v = w[0] * bv;
+#pragma unroll
+  for (int k = 1; k < (1 << D); ++k)
+    if (!(k & skip)) v += w[k] * val[k];
   F[c] = v;
 }
 

@@ -85,8 +85,12 @@ struct BatchData {
   int32_t* d_unit_cnt = nullptr;     // [ninst][kMaxUnits]
   int32_t* d_unit_lev = nullptr;     // [ninst][kMaxUnits] level of each unit
   uint32_t* d_reach = nullptr;       // [ninst] residual closure bitsets (cyclic graphs)
-  int32_t* d_listA = nullptr;        // [cap] frontier lists of the layering
-  int32_t* d_listB = nullptr;
+  int32_t* d_listA = nullptr;        // [cap] level lists of the layering
+  int32_t* d_rcnt = nullptr;         // [cap] reverse-edge counts / fill pointers
+  int32_t* d_roff = nullptr;         // [cap] reverse-edge offsets (instance-local)
+  int32_t* d_radj = nullptr;         // [7][cap] reverse edges (instance-local ids)
+  uint32_t* d_cnt = nullptr;         // byte counters in HBM (instances beyond LDS)
+  uint32_t* d_bits = nullptr;        // level bitmaps in HBM (instances beyond LDS)
   std::vector<int32_t> unit_lev;     // host copy
   // cell -> ghost hash tables, concatenated per instance
   unsigned long long* d_htab = nullptr;
@@ -113,10 +117,14 @@ struct LevelsArgs {
   int32_t* unit_lev;
   uint32_t* reach;
   int32_t* listA;
-  int32_t* listB;
+  int32_t* rcnt;
+  int32_t* roff;
+  int32_t* radj;
+  uint32_t* cnt;
+  uint32_t* bits;
   InstInfo* info;
 };
-void launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
+gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
 
 // Schedule of the fill.
 enum { kSchedAuto = 0, kSchedLevels = 1, kSchedWorkgroup = 2, kSchedGraph = 3 };
@@ -160,6 +168,10 @@ struct gcr_plan {
   // calls that use them must not overlap on one plan
   void* scr[gcr::kScratchSlots] = {};
   size_t scr_bytes[gcr::kScratchSlots] = {};
+  // transposed stencil of the adjoints, built on first use (adjoint.hip)
+  void* sup = nullptr;
+  int64_t sup_bound = 0;
+  uint32_t sup_hmask = 0;
   std::unique_ptr<gcr::GraphCache> graph;
   ~gcr_plan();
 };

@@ -1,16 +1,20 @@
 // levels.hip -- Kahn layering of the ghost dependency graph (Sec. 3.2) and
 // the canonical order (level, linear index), one workgroup per instance.
 //
-// Iteration k examines only the ghosts not yet placed, kept in linear-index
-// order in a list; one packed workgroup scan per 1024 ghosts gives both the
-// canonical positions of the ghosts placed at level k and the next list (so
-// the work is the sum of the list lengths, not levels x ghosts).  Levels
-// live in LDS when the instance fits.  A ghost is ready at k when every
-// ghost it reads has a level in 1..k-1, so decisions do not depend on the
-// order threads run in.  If an iteration places nothing, the remaining
-// ghosts hold cycles: their strongly connected groups (from the transitive
-// closure of the remaining graph) become coupled units and the layering
-// restarts with them, so each unit sits one level above the deepest level it
+// The reverse edges (ghost -> ghosts that read it) are built once as a CSR
+// list.  Each ghost (or coupled unit) holds a byte counter of unplaced ghosts
+// it reads, packed four to a word and kept in LDS when the instance fits.
+// Level k is formed from the dependants of level k-1 whose counter drops to
+// zero: they set their bit in a bitmap over the linear ghost order, and one
+// workgroup scan over the bitmap words emits them in linear-index order with
+// their canonical positions.  The work is O(ghosts + edges) plus one bitmap
+// scan per level; the level of a ghost is the longest dependency path from a
+// ghost that reads no ghost, independent of the order threads run in.
+//
+// If a level comes out empty while ghosts remain, the remaining ghosts hold
+// cycles: their strongly connected groups (from the transitive closure of
+// the remaining graph) become coupled units, and the layering restarts with
+// each unit as one node, so a unit sits one level above the deepest level it
 // needs.
 #include <hip/hip_runtime.h>
 
@@ -28,45 +32,59 @@ __device__ __forceinline__ int64_t find_sorted(const int32_t* a, int64_t lo, int
   return -1;
 }
 
+// byte counters packed four per 32-bit word; a counter never goes below
+// zero (one decrement per counted edge) and never exceeds 8 * 7, so no carry
+// or borrow crosses into a neighbour
+__device__ __forceinline__ void cnt_add(uint32_t* c, int i, uint32_t v) {
+  atomicAdd(&c[i >> 2], v << ((i & 3) * 8));
+}
+__device__ __forceinline__ uint32_t cnt_dec(uint32_t* c, int i) {
+  const uint32_t old = atomicSub(&c[i >> 2], 1u << ((i & 3) * 8));
+  return (old >> ((i & 3) * 8)) & 0xffu;
+}
+__device__ __forceinline__ uint32_t cnt_get(const uint32_t* c, int i) {
+  return (c[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+}
+
 template <bool InLds>
 __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
-  extern __shared__ uint16_t s_lev[];
+  extern __shared__ uint32_t s_dyn[];
   const int ii = blockIdx.x;
   const int tid = threadIdx.x;
   const int np = (1 << L.insts[ii].g.dim) - 1;
   const int64_t lo = L.g_off[ii];
   const int n = (int)(L.g_off[ii + 1] - lo);
+  const int W = (n + 31) >> 5;   // bitmap words
+  const int C = (n + 3) >> 2;    // counter words
   const int64_t cap = L.cap;
   const int32_t* __restrict__ deps = L.deps;
   int32_t* __restrict__ lev = L.lev;
   int32_t* __restrict__ blk_idx = L.blk_idx;
   int32_t* __restrict__ perm = L.perm;
+  int32_t* __restrict__ rcnt = L.rcnt;
+  int32_t* __restrict__ roff = L.roff + lo;
+  int32_t* __restrict__ radj = L.radj + 7 * lo;
   int32_t* lev_off = L.lev_off + (int64_t)ii * (kMaxLevels + 1);
   int32_t* unit_mem = L.unit_mem + (int64_t)ii * kMaxUnits * kMaxUnit;
   int32_t* unit_cnt = L.unit_cnt + (int64_t)ii * kMaxUnits;
   int32_t* unit_lev = L.unit_lev + (int64_t)ii * kMaxUnits;
   uint32_t* reach = L.reach + (int64_t)ii * kMaxResidual * (kMaxResidual / 32);
-  int32_t* listA = L.listA + lo;
-  int32_t* listB = L.listB + lo;
-
-  // level of ghost d (global linear-order position); 0 = not placed
-  auto LEV = [&](int64_t d) -> int { return InLds ? (int)s_lev[d - lo] : lev[d]; };
-  auto SET = [&](int g, int v) {
-    if (InLds) s_lev[g] = (uint16_t)v;
-    lev[lo + g] = v;
-  };
+  int32_t* cur = L.listA + lo;
+  // instance ii owns words [(lo >> 2) + ii, + C) and [(lo >> 5) + ii, + W):
+  // the next instance starts at ((lo + n) >> 2) + ii + 1 >= that end
+  uint32_t* cnt = InLds ? s_dyn : L.cnt + (lo >> 2) + ii;
+  uint32_t* bits = InLds ? s_dyn + C : L.bits + (lo >> 5) + ii;
 
   __shared__ int64_t sh[17];
-  __shared__ int s_flag, s_units, s_maxunit;
+  __shared__ int s_flag, s_units, s_maxunit, s_E;
   __shared__ int32_t res[kMaxResidual];
   __shared__ int32_t rep[kMaxResidual];
   __shared__ int32_t slot[kMaxResidual];
 
+  // ---- reverse edges: count, scan, fill
   for (int g = tid; g < n; g += 1024) {
-    SET(g, 0);
+    rcnt[lo + g] = 0;
     blk_idx[lo + g] = -1;
-    perm[lo + g] = -1;
-    listA[g] = g;
   }
   if (tid == 0) {
     lev_off[0] = 0;
@@ -74,187 +92,252 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
     s_maxunit = 0;
   }
   __syncthreads();
-
-  int32_t* cur = listA;
-  int32_t* nxt = listB;
-  int nrem = n, placed = 0, k = 0, maxwidth = 0;
-  bool units = false;
-  uint32_t err = 0;
-  while (nrem > 0) {
-    ++k;
-    if (k > kMaxLevels) {
-      err |= kErrUnsupported;
-      break;
+  for (int g = tid; g < n; g += 1024)
+    for (int m = 0; m < np; ++m) {
+      const int32_t d = deps[(int64_t)m * cap + lo + g];
+      if (d >= 0) atomicAdd(&rcnt[d], 1);
     }
-    int newly = 0, kept = 0;
-    for (int base = 0; base < nrem; base += 1024) {
-      const int idx = base + tid;
-      const int g = idx < nrem ? cur[idx] : -1;
-      bool ready = false;
-      if (g >= 0) {
-        const int u = units ? blk_idx[lo + g] : -1;
-        ready = true;
-        if (u < 0) {
-          for (int m = 0; m < np && ready; ++m) {
-            const int32_t d = deps[(int64_t)m * cap + lo + g];
-            if (d >= 0) {
-              const int ld = LEV(d);
-              if (ld == 0 || ld >= k) ready = false;
-            }
-          }
-        } else {
-          const int cntu = unit_cnt[u];
-          for (int q = 0; q < cntu && ready; ++q) {
-            const int32_t w = unit_mem[u * kMaxUnit + q];
-            for (int m = 0; m < np && ready; ++m) {
-              const int32_t d = deps[(int64_t)m * cap + w];
-              if (d >= 0 && blk_idx[d] != u) {
-                const int ld = LEV(d);
-                if (ld == 0 || ld >= k) ready = false;
-              }
-            }
-          }
-          if (ready) unit_lev[u] = k;
-        }
-      }
-      const int64_t packed = ready ? 1 : (g >= 0 ? (int64_t(1) << 32) : 0);
+  __syncthreads();
+  {
+    int64_t carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+      const int g = base + tid;
+      const int c = g < n ? rcnt[lo + g] : 0;
       int64_t tot;
-      const int64_t pre = block_excl_scan<1024>(packed, &tot, sh);
-      if (ready) {
-        perm[lo + g] = placed + newly + (int)(pre & 0xffffffff);
-        SET(g, k);
-      } else if (g >= 0) {
-        nxt[kept + (int)(pre >> 32)] = g;
+      const int64_t pre = block_excl_scan<1024>(c, &tot, sh);
+      if (g < n) {
+        roff[g] = (int32_t)(carry + pre);
+        rcnt[lo + g] = 0;
       }
-      newly += (int)(tot & 0xffffffff);
-      kept += (int)(tot >> 32);
+      carry += tot;
+    }
+    if (tid == 0) s_E = (int)carry;
+  }
+  __syncthreads();
+  for (int g = tid; g < n; g += 1024)
+    for (int m = 0; m < np; ++m) {
+      const int32_t d = deps[(int64_t)m * cap + lo + g];
+      if (d >= 0) {
+        const int p = atomicAdd(&rcnt[d], 1);
+        radj[roff[d - lo] + p] = g;
+      }
+    }
+  __syncthreads();
+  const int E = s_E;
+
+  bool units = false;
+  int k = 0, placed = 0, maxwidth = 0;
+  uint32_t err = 0;
+  for (;;) {
+    // ---- counters of unplaced ghosts read (per ghost, or per unit on its
+    // first member), internal edges of a unit excluded
+    for (int w = tid; w < C; w += 1024) cnt[w] = 0;
+    for (int w = tid; w < W; w += 1024) bits[w] = 0;
+    for (int g = tid; g < n; g += 1024) {
+      lev[lo + g] = 0;
+      perm[lo + g] = -1;
     }
     __syncthreads();
-    if (newly == 0) {
-      if (units) {
-        err |= kErrCycle;
+    for (int g = tid; g < n; g += 1024) {
+      const int u = units ? blk_idx[lo + g] : -1;
+      const int tgt = u >= 0 ? (int)(unit_mem[u * kMaxUnit] - lo) : g;
+      uint32_t c = 0;
+      for (int m = 0; m < np; ++m) {
+        const int32_t d = deps[(int64_t)m * cap + lo + g];
+        if (d >= 0 && !(u >= 0 && blk_idx[d] == u)) ++c;
+      }
+      if (c) cnt_add(cnt, tgt, c);
+    }
+    __syncthreads();
+    // level 1: nodes that read no unplaced ghost
+    for (int g = tid; g < n; g += 1024) {
+      const int u = units ? blk_idx[lo + g] : -1;
+      if (u >= 0 && unit_mem[u * kMaxUnit] - lo != g) continue;
+      if (cnt_get(cnt, g) != 0) continue;
+      if (u >= 0) {
+        unit_lev[u] = 1;
+        for (int q = 0; q < unit_cnt[u]; ++q) {
+          const int v = (int)(unit_mem[u * kMaxUnit + q] - lo);
+          atomicOr(&bits[v >> 5], 1u << (v & 31));
+        }
+      } else {
+        atomicOr(&bits[g >> 5], 1u << (g & 31));
+      }
+    }
+    __syncthreads();
+
+    k = 0;
+    placed = 0;
+    maxwidth = 0;
+    for (;;) {
+      // ---- emit the next level from the bitmap, in linear-index order
+      int newly = 0;
+      for (int base = 0; base < W; base += 1024) {
+        const int w = base + tid;
+        uint32_t word = w < W ? bits[w] : 0u;
+        int64_t tot;
+        const int64_t pre = block_excl_scan<1024>(__popc(word), &tot, sh);
+        if (word) {
+          bits[w] = 0u;
+          int pos = newly + (int)pre;
+          while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1;
+            const int g = w * 32 + b;
+            cur[pos] = g;
+            perm[lo + g] = placed + pos;
+            lev[lo + g] = k + 1;
+            ++pos;
+          }
+        }
+        newly += (int)tot;
+      }
+      if (newly == 0) break;
+      ++k;
+      if (k > kMaxLevels) {
+        err |= kErrUnsupported;
         break;
       }
-      // the remaining ghosts (ascending, in cur) hold cycles
-      const int m = nrem;
-      if (m > kMaxResidual) {
-        err |= kErrCycle;
-        break;
-      }
-      for (int u = tid; u < m; u += 1024) res[u] = cur[u];
-      const int W = (m + 31) / 32;
-      for (int t = tid; t < m * W; t += 1024) reach[t] = 0;
+      placed += newly;
+      maxwidth = max(maxwidth, newly);
+      if (tid == 0) lev_off[k] = placed;
       __syncthreads();
+      // ---- dependants of level k: the last edge into a node releases it
+      for (int i = tid; i < newly; i += 1024) {
+        const int g = cur[i];
+        const int ug = units ? blk_idx[lo + g] : -1;
+        const int e1 = g + 1 < n ? roff[g + 1] : E;
+        for (int e = roff[g]; e < e1; ++e) {
+          const int r = radj[e];
+          const int ur = units ? blk_idx[lo + r] : -1;
+          if (ur >= 0 && ur == ug) continue;
+          const int tgt = ur >= 0 ? (int)(unit_mem[ur * kMaxUnit] - lo) : r;
+          if (cnt_dec(cnt, tgt) != 1u) continue;
+          if (ur >= 0) {
+            unit_lev[ur] = k + 1;
+            for (int q = 0; q < unit_cnt[ur]; ++q) {
+              const int v = (int)(unit_mem[ur * kMaxUnit + q] - lo);
+              atomicOr(&bits[v >> 5], 1u << (v & 31));
+            }
+          } else {
+            atomicOr(&bits[r >> 5], 1u << (r & 31));
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (err || placed == n) break;
+    if (units) {
+      err |= kErrCycle;
+      break;
+    }
+
+    // ---- the unplaced ghosts (ascending) hold cycles
+    int m = 0;
+    for (int base = 0; base < n; base += 1024) {
+      const int g = base + tid;
+      const bool left = g < n && lev[lo + g] == 0;
+      int64_t tot;
+      const int64_t pre = block_excl_scan<1024>(left ? 1 : 0, &tot, sh);
+      if (left && m + pre < kMaxResidual) res[m + pre] = g;
+      m += (int)tot;
+    }
+    if (m > kMaxResidual) {
+      err |= kErrCycle;
+      break;
+    }
+    const int RW = (m + 31) / 32;
+    for (int t = tid; t < m * RW; t += 1024) reach[t] = 0;
+    __syncthreads();
+    for (int u = tid; u < m; u += 1024) {
+      for (int q = 0; q < np; ++q) {
+        const int32_t d = deps[(int64_t)q * cap + lo + res[u]];
+        if (d >= 0 && lev[d] == 0) {
+          const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
+          if (v >= 0) reach[u * RW + (v >> 5)] |= 1u << (v & 31);
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    do {
+      if (tid == 0) s_flag = 0;
+      __syncthreads();
+      int changed = 0;
       for (int u = tid; u < m; u += 1024) {
         for (int q = 0; q < np; ++q) {
           const int32_t d = deps[(int64_t)q * cap + lo + res[u]];
-          if (d >= 0 && LEV(d) == 0) {
-            const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
-            if (v >= 0) reach[u * W + (v >> 5)] |= 1u << (v & 31);
+          if (d < 0 || lev[d] != 0) continue;
+          const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
+          if (v < 0) continue;
+          for (int w = 0; w < RW; ++w) {
+            const uint32_t o = reach[u * RW + w], nw = o | reach[v * RW + w];
+            if (nw != o) {
+              reach[u * RW + w] = nw;
+              changed = 1;
+            }
           }
         }
       }
+      if (changed) s_flag = 1;
       __threadfence_block();
       __syncthreads();
-      do {
-        if (tid == 0) s_flag = 0;
-        __syncthreads();
-        int changed = 0;
-        for (int u = tid; u < m; u += 1024) {
-          for (int q = 0; q < np; ++q) {
-            const int32_t d = deps[(int64_t)q * cap + lo + res[u]];
-            if (d < 0 || LEV(d) != 0) continue;
-            const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
-            if (v < 0) continue;
-            for (int w = 0; w < W; ++w) {
-              const uint32_t o = reach[u * W + w], nw = o | reach[v * W + w];
-              if (nw != o) {
-                reach[u * W + w] = nw;
-                changed = 1;
-              }
-            }
-          }
-        }
-        if (changed) s_flag = 1;
-        __threadfence_block();
-        __syncthreads();
-      } while (s_flag);
-      // representative = smallest member of the group; -1 off cycles
-      for (int u = tid; u < m; u += 1024) {
-        int rp = -1;
-        if ((reach[u * W + (u >> 5)] >> (u & 31)) & 1u) {
-          for (int v = 0; v < m; ++v)
-            if (((reach[u * W + (v >> 5)] >> (v & 31)) & 1u) &&
-                ((reach[v * W + (u >> 5)] >> (u & 31)) & 1u)) {
-              rp = v;
-              break;
-            }
-        }
-        rep[u] = rp;
-      }
-      __syncthreads();
-      {
-        int off = 0;
-        for (int base = 0; base < m; base += 1024) {
-          const int u = base + tid;
-          const bool isrep = u < m && rep[u] == u;
-          int64_t tot;
-          const int64_t pre = block_excl_scan<1024>(isrep ? 1 : 0, &tot, sh);
-          if (isrep) slot[u] = off + (int)pre;
-          off += (int)tot;
-        }
-        if (tid == 0) s_units = off;
-      }
-      __syncthreads();
-      if (s_units > kMaxUnits) {
-        err |= kErrCycle;
-        break;
-      }
-      for (int u = tid; u < m; u += 1024) {
-        const int rp = rep[u];
-        if (rp < 0) continue;
-        int rank = 0, size = 0;
+    } while (s_flag);
+    // representative = smallest member of the group; -1 off cycles
+    for (int u = tid; u < m; u += 1024) {
+      int rp = -1;
+      if ((reach[u * RW + (u >> 5)] >> (u & 31)) & 1u) {
         for (int v = 0; v < m; ++v)
-          if (rep[v] == rp) {
-            if (v < u) ++rank;
-            ++size;
+          if (((reach[u * RW + (v >> 5)] >> (v & 31)) & 1u) &&
+              ((reach[v * RW + (u >> 5)] >> (u & 31)) & 1u)) {
+            rp = v;
+            break;
           }
-        if (size > kMaxUnit) {
-          atomicOr(&L.info[ii].err, kErrCycle);
-          continue;
-        }
-        const int sl = slot[rp];
-        unit_mem[sl * kMaxUnit + rank] = (int32_t)(lo + res[u]);
-        blk_idx[lo + res[u]] = sl;
-        if (u == rp) {
-          unit_cnt[sl] = size;
-          atomicMax(&s_maxunit, size);
-        }
       }
-      __syncthreads();
-      // restart the layering with the units
-      for (int g = tid; g < n; g += 1024) {
-        SET(g, 0);
-        perm[lo + g] = -1;
-        listA[g] = g;
-      }
-      __syncthreads();
-      cur = listA;
-      nxt = listB;
-      units = true;
-      nrem = n;
-      placed = 0;
-      k = 0;
-      maxwidth = 0;
-      continue;
+      rep[u] = rp;
     }
-    placed += newly;
-    maxwidth = max(maxwidth, newly);
-    if (tid == 0) lev_off[k] = placed;
-    int32_t* t = cur;
-    cur = nxt;
-    nxt = t;
-    nrem = kept;
+    __syncthreads();
+    {
+      int off = 0;
+      for (int base = 0; base < m; base += 1024) {
+        const int u = base + tid;
+        const bool isrep = u < m && rep[u] == u;
+        int64_t tot;
+        const int64_t pre = block_excl_scan<1024>(isrep ? 1 : 0, &tot, sh);
+        if (isrep) slot[u] = off + (int)pre;
+        off += (int)tot;
+      }
+      if (tid == 0) s_units = off;
+    }
+    __syncthreads();
+    if (s_units > kMaxUnits) {
+      err |= kErrCycle;
+      break;
+    }
+    for (int u = tid; u < m; u += 1024) {
+      const int rp = rep[u];
+      if (rp < 0) continue;
+      int rank = 0, size = 0;
+      for (int v = 0; v < m; ++v)
+        if (rep[v] == rp) {
+          if (v < u) ++rank;
+          ++size;
+        }
+      if (size > kMaxUnit) {
+        atomicOr(&L.info[ii].err, kErrCycle);
+        continue;
+      }
+      const int sl = slot[rp];
+      unit_mem[sl * kMaxUnit + rank] = (int32_t)(lo + res[u]);
+      blk_idx[lo + res[u]] = sl;
+      if (u == rp) {
+        unit_cnt[sl] = size;
+        atomicMax(&s_maxunit, size);
+      }
+    }
+    __syncthreads();
+    if (L.info[ii].err & kErrCycle) break;
+    units = true;   // restart the layering with the units as nodes
   }
   if (tid == 0) {
     if (err) atomicOr(&L.info[ii].err, err);
@@ -265,23 +348,39 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   }
 }
 
-// Levels in LDS when the largest instance fits (uint16 per ghost).
-constexpr int kLdsLevelCap = 64 * 1024;
-
-void launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st) {
-  if (max_n <= kLdsLevelCap) {
-    static bool attr = false;
-    const size_t bytes = (size_t)std::max<int64_t>(max_n, 1) * sizeof(uint16_t);
-    if (!attr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kLdsLevelCap * (int)sizeof(uint16_t));
-      attr = true;
+// Counters and bitmap in LDS when the largest instance fits, else in HBM.
+gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st) {
+  static int lds_max = -1;
+  if (lds_max < 0) {
+    int dev = 0, a = 0, b = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      a = 0;
+    if (hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
+      b = 0;
+    (void)hipGetLastError();
+    hipFuncAttributes fa{};
+    int stat = 8192;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_levels<true>)) == hipSuccess)
+      stat = (int)fa.sharedSizeBytes;
+    (void)hipGetLastError();
+    lds_max = std::max(0, std::max(a, b) - stat - 256);
+  }
+  const int64_t nn = std::max<int64_t>(max_n, 1);
+  const int64_t bytes = 4 * (((nn + 3) >> 2) + ((nn + 31) >> 5));
+  if (bytes <= lds_max) {
+    static int64_t attr = 0;
+    if (bytes > attr) {
+      GCR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+      attr = bytes;
     }
-    k_levels<true><<<ninst, 1024, bytes, st>>>(L);
+    k_levels<true><<<ninst, 1024, (size_t)bytes, st>>>(L);
   } else {
     k_levels<false><<<ninst, 1024, 0, st>>>(L);
   }
+  GCR_HIP(hipGetLastError());
+  return GCR_OK;
 }
 
 }  // namespace gcr

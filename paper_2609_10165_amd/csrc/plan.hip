@@ -921,8 +921,13 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_level = own<int32_t>(D, cap);
   D.d_blk = own<int32_t>(D, cap);
   D.d_listA = own<int32_t>(D, cap);
-  D.d_listB = own<int32_t>(D, cap);
-  if (!D.d_listA || !D.d_listB) return GCR_E_NOMEM;
+  D.d_rcnt = own<int32_t>(D, cap);
+  D.d_roff = own<int32_t>(D, cap);
+  D.d_radj = own<int32_t>(D, 7 * cap);
+  D.d_cnt = own<uint32_t>(D, (cap >> 2) + ninst + 2);
+  D.d_bits = own<uint32_t>(D, (cap >> 5) + ninst + 2);
+  if (!D.d_listA || !D.d_rcnt || !D.d_roff || !D.d_radj || !D.d_cnt || !D.d_bits)
+    return GCR_E_NOMEM;
   if (!D.d_if_cell || !D.d_if_psi || !D.d_if_n || !D.d_if_flag || !D.d_blkcnt || !D.d_blkexcl ||
       !D.d_g_cell || !D.d_g_psi || !D.d_g_n || !D.d_g_code || !D.d_deps || !D.d_lev ||
       !D.d_blk_idx || !D.d_perm || !D.d_cell || !D.d_delta || !D.d_nrm || !D.d_psi ||
@@ -968,11 +973,16 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
       L.unit_lev = D.d_unit_lev;
       L.reach = D.d_reach;
       L.listA = D.d_listA;
-      L.listB = D.d_listB;
+      L.rcnt = D.d_rcnt;
+      L.roff = D.d_roff;
+      L.radj = D.d_radj;
+      L.cnt = D.d_cnt;
+      L.bits = D.d_bits;
       L.info = D.d_info;
       int64_t max_if = 0;
       for (int i = 0; i < ninst; ++i) max_if = std::max(max_if, D.if_off[i + 1] - D.if_off[i]);
-      launch_levels(L, ninst, max_if, st);
+      const gcr_status ls = launch_levels(L, ninst, max_if, st);
+      if (ls != GCR_OK) return ls;
     }
     T.mark(8, st);
     k_finalize<<<blocks(nif, 256), 256, 0, st>>>(
