@@ -44,6 +44,7 @@ struct ShapeD {
   double r0;
   double cull_c[3];     // centre of the radial culling bounds
   double rmin, rmax;    // every boundary point lies at rmin <= |x - cull_c| <= rmax
+  double lip;           // star / SH: |r(w) - r(w')| <= lip * angle(w, w')
   double chord, thick, ca, sa;   // airfoil: chord, thickness ratio, cos/sin incidence
   double coef[kMaxCoef];         // star: A_k, B_k pairs; SH: a_lm * N_lm at l*l+l+m
 };

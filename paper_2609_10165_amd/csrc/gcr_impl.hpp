@@ -86,9 +86,10 @@ struct BatchData {
   int32_t* d_unit_lev = nullptr;     // [ninst][kMaxUnits] level of each unit
   uint32_t* d_reach = nullptr;       // [ninst] residual closure bitsets (cyclic graphs)
   int32_t* d_listA = nullptr;        // [cap] level lists of the layering
-  int32_t* d_rcnt = nullptr;         // [cap] reverse-edge counts / fill pointers
-  int32_t* d_roff = nullptr;         // [cap] reverse-edge offsets (instance-local)
-  int32_t* d_radj = nullptr;         // [7][cap] reverse edges (instance-local ids)
+  int32_t* d_rcnt = nullptr;         // [2][cap] reverse-edge counts, fill pointers
+  int32_t* d_roff = nullptr;         // [cap+1] reverse-edge offsets (all ghosts)
+  int32_t* d_radj = nullptr;         // [7][cap] reverse edges (linear-order ghost ids)
+  uint8_t* d_dcnt = nullptr;         // [cap] ghost dependencies per ghost
   uint32_t* d_cnt = nullptr;         // byte counters in HBM (instances beyond LDS)
   uint32_t* d_bits = nullptr;        // level bitmaps in HBM (instances beyond LDS)
   std::vector<int32_t> unit_lev;     // host copy
@@ -117,9 +118,9 @@ struct LevelsArgs {
   int32_t* unit_lev;
   uint32_t* reach;
   int32_t* listA;
-  int32_t* rcnt;
-  int32_t* roff;
-  int32_t* radj;
+  const uint8_t* dcnt;
+  const int32_t* roff;
+  const int32_t* radj;
   uint32_t* cnt;
   uint32_t* bits;
   InstInfo* info;

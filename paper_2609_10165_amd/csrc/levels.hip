@@ -1,9 +1,11 @@
 // levels.hip -- Kahn layering of the ghost dependency graph (Sec. 3.2) and
 // the canonical order (level, linear index), one workgroup per instance.
 //
-// The reverse edges (ghost -> ghosts that read it) are built once as a CSR
-// list.  Each ghost (or coupled unit) holds a byte counter of unplaced ghosts
-// it reads, packed four to a word and kept in LDS when the instance fits.
+// The reverse edges (ghost -> ghosts that read it) arrive as a CSR list and
+// the number of ghosts each ghost reads as a byte per ghost, both built by
+// grid-wide kernels.  Each ghost (or coupled unit) holds a byte counter of
+// unplaced ghosts it reads, packed four to a word and kept in LDS when the
+// instance fits.
 // Level k is formed from the dependants of level k-1 whose counter drops to
 // zero: they set their bit in a bitmap over the linear ghost order, and one
 // workgroup scan over the bitmap words emits them in linear-index order with
@@ -61,9 +63,9 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   int32_t* __restrict__ lev = L.lev;
   int32_t* __restrict__ blk_idx = L.blk_idx;
   int32_t* __restrict__ perm = L.perm;
-  int32_t* __restrict__ rcnt = L.rcnt;
-  int32_t* __restrict__ roff = L.roff + lo;
-  int32_t* __restrict__ radj = L.radj + 7 * lo;
+  const uint8_t* __restrict__ dcnt = L.dcnt + lo;
+  const int32_t* __restrict__ roff = L.roff + lo;   // global ids in radj
+  const int32_t* __restrict__ radj = L.radj;
   int32_t* lev_off = L.lev_off + (int64_t)ii * (kMaxLevels + 1);
   int32_t* unit_mem = L.unit_mem + (int64_t)ii * kMaxUnits * kMaxUnit;
   int32_t* unit_cnt = L.unit_cnt + (int64_t)ii * kMaxUnits;
@@ -76,54 +78,18 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   uint32_t* bits = InLds ? s_dyn + C : L.bits + (lo >> 5) + ii;
 
   __shared__ int64_t sh[17];
-  __shared__ int s_flag, s_units, s_maxunit, s_E;
+  __shared__ int s_flag, s_units, s_maxunit;
   __shared__ int32_t res[kMaxResidual];
   __shared__ int32_t rep[kMaxResidual];
   __shared__ int32_t slot[kMaxResidual];
 
-  // ---- reverse edges: count, scan, fill
-  for (int g = tid; g < n; g += 1024) {
-    rcnt[lo + g] = 0;
-    blk_idx[lo + g] = -1;
-  }
+  for (int g = tid; g < n; g += 1024) blk_idx[lo + g] = -1;
   if (tid == 0) {
     lev_off[0] = 0;
     s_units = 0;
     s_maxunit = 0;
   }
   __syncthreads();
-  for (int g = tid; g < n; g += 1024)
-    for (int m = 0; m < np; ++m) {
-      const int32_t d = deps[(int64_t)m * cap + lo + g];
-      if (d >= 0) atomicAdd(&rcnt[d], 1);
-    }
-  __syncthreads();
-  {
-    int64_t carry = 0;
-    for (int base = 0; base < n; base += 1024) {
-      const int g = base + tid;
-      const int c = g < n ? rcnt[lo + g] : 0;
-      int64_t tot;
-      const int64_t pre = block_excl_scan<1024>(c, &tot, sh);
-      if (g < n) {
-        roff[g] = (int32_t)(carry + pre);
-        rcnt[lo + g] = 0;
-      }
-      carry += tot;
-    }
-    if (tid == 0) s_E = (int)carry;
-  }
-  __syncthreads();
-  for (int g = tid; g < n; g += 1024)
-    for (int m = 0; m < np; ++m) {
-      const int32_t d = deps[(int64_t)m * cap + lo + g];
-      if (d >= 0) {
-        const int p = atomicAdd(&rcnt[d], 1);
-        radj[roff[d - lo] + p] = g;
-      }
-    }
-  __syncthreads();
-  const int E = s_E;
 
   bool units = false;
   int k = 0, placed = 0, maxwidth = 0;
@@ -131,40 +97,57 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   for (;;) {
     // ---- counters of unplaced ghosts read (per ghost, or per unit on its
     // first member), internal edges of a unit excluded
-    for (int w = tid; w < C; w += 1024) cnt[w] = 0;
-    for (int w = tid; w < W; w += 1024) bits[w] = 0;
     for (int g = tid; g < n; g += 1024) {
       lev[lo + g] = 0;
       perm[lo + g] = -1;
     }
-    __syncthreads();
-    for (int g = tid; g < n; g += 1024) {
-      const int u = units ? blk_idx[lo + g] : -1;
-      const int tgt = u >= 0 ? (int)(unit_mem[u * kMaxUnit] - lo) : g;
-      uint32_t c = 0;
-      for (int m = 0; m < np; ++m) {
-        const int32_t d = deps[(int64_t)m * cap + lo + g];
-        if (d >= 0 && !(u >= 0 && blk_idx[d] == u)) ++c;
+    if (!units) {
+      // four counters per word, and level 1 = ghosts that read no ghost
+      for (int w = tid; w < C; w += 1024) {
+        uint32_t v = 0;
+        for (int q = 0; q < 4; ++q)
+          if (4 * w + q < n) v |= (uint32_t)dcnt[4 * w + q] << (8 * q);
+        cnt[w] = v;
       }
-      if (c) cnt_add(cnt, tgt, c);
-    }
-    __syncthreads();
-    // level 1: nodes that read no unplaced ghost
-    for (int g = tid; g < n; g += 1024) {
-      const int u = units ? blk_idx[lo + g] : -1;
-      if (u >= 0 && unit_mem[u * kMaxUnit] - lo != g) continue;
-      if (cnt_get(cnt, g) != 0) continue;
-      if (u >= 0) {
-        unit_lev[u] = 1;
-        for (int q = 0; q < unit_cnt[u]; ++q) {
-          const int v = (int)(unit_mem[u * kMaxUnit + q] - lo);
-          atomicOr(&bits[v >> 5], 1u << (v & 31));
+      for (int w = tid; w < W; w += 1024) {
+        uint32_t b = 0;
+        for (int q = 0; q < 32; ++q)
+          if (32 * w + q < n && dcnt[32 * w + q] == 0) b |= 1u << q;
+        bits[w] = b;
+      }
+      __syncthreads();
+    } else {
+      for (int w = tid; w < C; w += 1024) cnt[w] = 0;
+      for (int w = tid; w < W; w += 1024) bits[w] = 0;
+      __syncthreads();
+      for (int g = tid; g < n; g += 1024) {
+        const int u = blk_idx[lo + g];
+        const int tgt = u >= 0 ? (int)(unit_mem[u * kMaxUnit] - lo) : g;
+        uint32_t c = 0;
+        for (int m = 0; m < np; ++m) {
+          const int32_t d = deps[(int64_t)m * cap + lo + g];
+          if (d >= 0 && !(u >= 0 && blk_idx[d] == u)) ++c;
         }
-      } else {
-        atomicOr(&bits[g >> 5], 1u << (g & 31));
+        if (c) cnt_add(cnt, tgt, c);
       }
+      __syncthreads();
+      // level 1: nodes that read no unplaced ghost
+      for (int g = tid; g < n; g += 1024) {
+        const int u = blk_idx[lo + g];
+        if (u >= 0 && unit_mem[u * kMaxUnit] - lo != g) continue;
+        if (cnt_get(cnt, g) != 0) continue;
+        if (u >= 0) {
+          unit_lev[u] = 1;
+          for (int q = 0; q < unit_cnt[u]; ++q) {
+            const int v = (int)(unit_mem[u * kMaxUnit + q] - lo);
+            atomicOr(&bits[v >> 5], 1u << (v & 31));
+          }
+        } else {
+          atomicOr(&bits[g >> 5], 1u << (g & 31));
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
 
     k = 0;
     placed = 0;
@@ -206,9 +189,9 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
       for (int i = tid; i < newly; i += 1024) {
         const int g = cur[i];
         const int ug = units ? blk_idx[lo + g] : -1;
-        const int e1 = g + 1 < n ? roff[g + 1] : E;
+        const int e1 = roff[g + 1];
         for (int e = roff[g]; e < e1; ++e) {
-          const int r = radj[e];
+          const int r = (int)(radj[e] - lo);
           const int ur = units ? blk_idx[lo + r] : -1;
           if (ur >= 0 && ur == ug) continue;
           const int tgt = ur >= 0 ? (int)(unit_mem[ur * kMaxUnit] - lo) : r;

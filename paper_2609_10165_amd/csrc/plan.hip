@@ -227,6 +227,37 @@ __device__ bool project(const ShapeD& s, int dim, const double x[3], bool solid,
 // 1. classification
 // --------------------------------------------------------------------------
 
+// Star and SH bodies: r over the directions a box subtends from the centre
+// lies within r(w_c) +- lip * D, D the box's angular radius, so a box whose
+// distances from the centre all exceed (or all stay below) that range is
+// fluid (solid) throughout.  Returns 0 / 1, or -1 if the box may straddle.
+__device__ __forceinline__ int star_box(const ShapeD& s, int dim, const double lo[3],
+                                        const double hi[3]) {
+  double xc[3] = {0.0, 0.0, 0.0}, rc2 = 0.0, hd2 = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    xc[a] = 0.5 * (lo[a] + hi[a]) - s.c[a];
+    const double e = 0.5 * (hi[a] - lo[a]);
+    rc2 += xc[a] * xc[a];
+    hd2 += e * e;
+  }
+  const double rc = sqrt(rc2), hd = sqrt(hd2);
+  if (!(rc > 2.0 * hd)) return -1;
+  const double D = asin(hd / rc) * (1.0 + 1e-12) + 1e-15;
+  double r;
+  if (s.kind == kStar2D) {
+    double r1;
+    star_r(s, xc[0] / rc, xc[1] / rc, r, r1);
+  } else {
+    const double u[3] = {xc[0] / rc, xc[1] / rc, xc[2] / rc};
+    double gr[3];
+    sh_r(s, u, r, gr);
+  }
+  const double spread = s.lip * D;
+  if (rc - hd > (r + spread) * (1.0 + 1e-9) + 1e-300) return 0;
+  if (rc + hd < (r - spread) * (1.0 - 1e-9)) return 1;
+  return -1;
+}
+
 __device__ __forceinline__ bool cell_solid(const Inst& I, int i, int j, int k) {
   double x[3] = {centre(I.g, 0, i), centre(I.g, 1, j), I.g.dim == 3 ? centre(I.g, 2, k) : 0.0};
   return inside(I.s, I.g.dim, x);
@@ -282,6 +313,7 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
       int settled = -1;
       if (sqrt(dmin2) > I.s.rmax * (1.0 + 1e-9) + 1e-300) settled = 0;
       else if (sqrt(dmax2) < I.s.rmin * (1.0 - 1e-9)) settled = 1;
+      else if (I.s.kind == kStar2D || I.s.kind == kShStar) settled = star_box(I.s, g.dim, lo, hi);
       if (settled >= 0) {
         for (int b = 0; b < kSeg; ++b) t[b] = (uint8_t)settled;
       } else {
@@ -513,6 +545,8 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
                                               const int8_t* __restrict__ tags,
                                               uint32_t* __restrict__ g_code,
                                               int32_t* __restrict__ deps,
+                                              int32_t* __restrict__ rcnt,
+                                              uint8_t* __restrict__ dcnt,
                                               InstInfo* __restrict__ info) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g_off[ninst]) return;
@@ -544,6 +578,7 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
   const int8_t* T = tags + I.cell_off;
   const int np = (1 << g.dim) - 1;
   const uint32_t skip = code_skip(code);
+  int nd = 0;
   for (int m = 1; m <= np; ++m) {
     int32_t d = -1;
     if (!(m & skip)) {
@@ -557,7 +592,54 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
       }
     }
     deps[(int64_t)(m - 1) * cap + e] = d;
+    if (d >= 0) {
+      atomicAdd(&rcnt[d], 1);   // reverse edge d -> e
+      ++nd;
+    }
   }
+  dcnt[e] = (uint8_t)nd;
+}
+
+// Reverse edges of the dependency graph as CSR over all ghosts (linear
+// order): off[e] = first reader of ghost e, off[ng] = number of edges.
+// One workgroup; the ghost count is read on the device.
+__global__ __launch_bounds__(1024) void k_rscan(const int32_t* __restrict__ cnt,
+                                                const int64_t* __restrict__ g_off, int ninst,
+                                                int32_t* __restrict__ off) {
+  __shared__ int64_t sh[17];
+  const int64_t n = g_off[ninst];
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = threadIdx.x * per, e = min(n, b + per);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += cnt[i];
+  int64_t tot;
+  int64_t run = block_excl_scan<1024>(s, &tot, sh);
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = (int32_t)run;
+    run += cnt[i];
+  }
+  if (threadIdx.x == 0) off[n] = (int32_t)tot;
+}
+
+__global__ __launch_bounds__(256) void k_rfill(const Inst* __restrict__ insts,
+                                               const int64_t* __restrict__ g_off, int ninst,
+                                               int64_t cap, const int32_t* __restrict__ deps,
+                                               const int32_t* __restrict__ off,
+                                               int32_t* __restrict__ fillc,
+                                               int32_t* __restrict__ radj) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g_off[ninst]) return;
+  const int ii = find_inst(g_off, ninst, e);
+  const int np = (1 << insts[ii].g.dim) - 1;
+  for (int m = 0; m < np; ++m) {
+    const int32_t d = deps[(int64_t)m * cap + e];
+    if (d >= 0) radj[off[d] + atomicAdd(&fillc[d], 1)] = (int32_t)e;
+  }
+}
+
+__global__ void k_zero32(int32_t* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
 }
 
 // --------------------------------------------------------------------------
@@ -741,6 +823,11 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
     for (int a = 0; a < 3; ++a) s.cull_c[a] = s.c[a];
     s.rmin = std::max(0.0, gs.r0 * (1.0 - sa));
     s.rmax = gs.r0 * (1.0 + sa);
+    // |d/dt (A cos kt + B sin kt)| <= k sqrt(A^2 + B^2)
+    double lip = 0.0;
+    for (int k = 0; k < gs.ncoef; ++k)
+      lip += (double)k * std::hypot(gs.coef[2 * k], gs.coef[2 * k + 1]);
+    s.lip = gs.r0 * lip;
   } else if (gs.kind == kShStar) {
     int L = (int)std::lround(std::sqrt((double)gs.ncoef)) - 1;
     if (gg.dim != 3 || !(gs.r0 > 0.0) || L < 0 || (L + 1) * (L + 1) != gs.ncoef || L > 8 ||
@@ -759,6 +846,12 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
     for (int a = 0; a < 3; ++a) s.cull_c[a] = s.c[a];
     s.rmin = std::max(0.0, gs.r0 * (1.0 - sa));
     s.rmax = gs.r0 * (1.0 + sa);
+    // on a great circle Y_lm is a trigonometric polynomial of degree <= l
+    // with |Y_lm| <= 1, so (Bernstein) its derivative is at most l
+    double lip = 0.0;
+    for (int l = 1; l <= L; ++l)
+      for (int m = -l; m <= l; ++m) lip += (double)l * std::fabs(gs.coef[l * l + l + m]);
+    s.lip = gs.r0 * lip;
   } else if (gs.kind == kAirfoil) {
     if (gg.dim != 2 || !(gs.chord > 0.0) || !(gs.thickness > 0.0) || gs.thickness > 0.5)
       return GCR_E_ARG;
@@ -921,12 +1014,13 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_level = own<int32_t>(D, cap);
   D.d_blk = own<int32_t>(D, cap);
   D.d_listA = own<int32_t>(D, cap);
-  D.d_rcnt = own<int32_t>(D, cap);
-  D.d_roff = own<int32_t>(D, cap);
+  D.d_rcnt = own<int32_t>(D, 2 * cap);   // counts, then fill pointers
+  D.d_roff = own<int32_t>(D, cap + 1);
+  D.d_dcnt = own<uint8_t>(D, cap);
   D.d_radj = own<int32_t>(D, 7 * cap);
   D.d_cnt = own<uint32_t>(D, (cap >> 2) + ninst + 2);
   D.d_bits = own<uint32_t>(D, (cap >> 5) + ninst + 2);
-  if (!D.d_listA || !D.d_rcnt || !D.d_roff || !D.d_radj || !D.d_cnt || !D.d_bits)
+  if (!D.d_listA || !D.d_rcnt || !D.d_roff || !D.d_radj || !D.d_cnt || !D.d_bits || !D.d_dcnt)
     return GCR_E_NOMEM;
   if (!D.d_if_cell || !D.d_if_psi || !D.d_if_n || !D.d_if_flag || !D.d_blkcnt || !D.d_blkexcl ||
       !D.d_g_cell || !D.d_g_psi || !D.d_g_n || !D.d_g_code || !D.d_deps || !D.d_lev ||
@@ -954,9 +1048,13 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                                                       D.d_g_off);
     T.mark(6, st);
     // ghost count unknown on the host: launch over the interface capacity
+    k_zero32<<<blocks(2 * cap, 256), 256, 0, st>>>(D.d_rcnt, 2 * cap);   // rcnt + rfill
     k_deps<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_g_off, D.d_g_cell, D.d_g_psi,
                                               D.d_g_n, cap, D.d_tags, D.d_g_code, D.d_deps,
-                                              D.d_info);
+                                              D.d_rcnt, D.d_dcnt, D.d_info);
+    k_rscan<<<1, 1024, 0, st>>>(D.d_rcnt, D.d_g_off, ninst, D.d_roff);
+    k_rfill<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, D.d_g_off, ninst, cap, D.d_deps,
+                                               D.d_roff, D.d_rcnt + cap, D.d_radj);
     T.mark(7, st);
     {
       LevelsArgs L;
@@ -973,7 +1071,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
       L.unit_lev = D.d_unit_lev;
       L.reach = D.d_reach;
       L.listA = D.d_listA;
-      L.rcnt = D.d_rcnt;
+      L.dcnt = D.d_dcnt;
       L.roff = D.d_roff;
       L.radj = D.d_radj;
       L.cnt = D.d_cnt;
