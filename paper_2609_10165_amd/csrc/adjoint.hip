@@ -233,6 +233,7 @@ struct AdjArgs {
   double* lam[kMaxFields];     // dense, in/out
   double* lam_bc[kMaxFields];  // [ng]
   double* Lam;                 // [nf][ng] adjoint of each filled ghost value
+  const double* w[2];          // the plan's cached weights per kind, [2^D][ng]
   SupView S;
 };
 
@@ -263,23 +264,12 @@ __device__ __forceinline__ void pull_readers(const AdjArgs& A, int s, int skip_u
     if (!(en & 1)) continue;
     const int r = en >> 4, m = (en >> 1) & 7;
     if (skip_unit >= 0 && P.blk[r] == skip_unit) continue;
-    double wD[8], wN[8];
-    bool hD = false, hN = false;
+    const double* const W0 = A.w[0];
+    const double* const W1 = A.w[1];
 #pragma unroll
     for (int f = 0; f < kMaxFields; ++f) {
       if (f >= A.nf) break;
-      const int bc = field_bc(A, f, r);
-      if (bc == 0 && !hD) {
-        weights_of<D>(P, r, 0, wD);
-        hD = true;
-      } else if (bc != 0 && !hN) {
-        weights_of<D>(P, r, 1, wN);
-        hN = true;
-      }
-      double wm = 0.0;
-#pragma unroll
-      for (int k = 1; k < (1 << D); ++k)
-        if (k == m) wm = bc == 0 ? wD[k] : wN[k];
+      const double wm = (field_bc(A, f, r) == 0 ? W0 : W1)[(int64_t)m * P.ng + r];
       acc[f] += wm * A.Lam[(int64_t)f * P.ng + r];
     }
   }
@@ -387,9 +377,8 @@ __global__ __launch_bounds__(256) void k_adj_support(AdjArgs A) {
   const int p = A.S.ghost[s];
   if (p >= 0) {
     for (int f = 0; f < A.nf; ++f) {
-      double w[8];
-      weights_of<D>(P, p, field_bc(A, f, p), w);
-      A.lam_bc[f][p] = w[0] * A.Lam[(int64_t)f * P.ng + p];
+      const double w0 = (field_bc(A, f, p) == 0 ? A.w[0] : A.w[1])[p];
+      A.lam_bc[f][p] = w0 * A.Lam[(int64_t)f * P.ng + p];
       A.lam[f][q] = 0.0;
     }
     return;
@@ -689,6 +678,10 @@ gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf, double* const* lam
   A.Lam = (double*)plan_scratch(p, 4, sizeof(double) * (size_t)nf * ng);
   if (!A.Lam) return GCR_E_NOMEM;
   hipStream_t st = (hipStream_t)stream;
+  {
+    const gcr_status ws = plan_weights(p, nf, A.kind, A.w, st);
+    if (ws != GCR_OK) return ws;
+  }
   {
     const gcr_status ss = plan_support(p, st, &A.S);
     if (ss != GCR_OK) return ss;

@@ -15,6 +15,32 @@ namespace gcr {
 // fill
 // --------------------------------------------------------------------------
 
+// Weights of every ghost for one boundary-condition kind (Sec. 4.1 / 5.1
+// relations solved for the ghost value), w[k][p], k = 0 the datum.  They
+// depend on the plan only, so a plan computes them once per kind.
+template <int D>
+__global__ __launch_bounds__(256) void k_weights(PlanD P, int bc, double* __restrict__ w,
+                                                 uint8_t* __restrict__ kinds) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < 2) kinds[p] = (uint8_t)p;   // the {0, 1} table of uniform kinds
+  if (p >= P.ng) return;
+  double dl[3], nn[3], wk[8];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dl[a] = a < D ? P.dl[a][p] : 0.0;
+    nn[a] = a < D ? P.nn[a][p] : 0.0;
+  }
+  ghost_weights<D>(dl, nn, P.code[p], P.g.h, bc, wk);
+#pragma unroll
+  for (int k = 0; k < (1 << D); ++k) w[(int64_t)k * P.ng + p] = wk[k];
+}
+
+void launch_weights(const PlanD& P, int bc, double* w, uint8_t* kinds, hipStream_t st) {
+  const unsigned nb = (unsigned)std::max(1, (P.ng + 255) / 256);
+  if (P.g.dim == 2) k_weights<2><<<nb, 256, 0, st>>>(P, bc, w, kinds);
+  else k_weights<3><<<nb, 256, 0, st>>>(P, bc, w, kinds);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_fill_range(FillArgs A, int lo, int hi) {
   const int p = lo + blockIdx.x * blockDim.x + threadIdx.x;

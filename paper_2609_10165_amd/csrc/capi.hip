@@ -67,6 +67,46 @@ void pool_free(void* p) {
   g_live_blocks.erase(it);
 }
 
+// Pinned host staging blocks (hipHostMalloc), pooled like the device blocks:
+// copies from and to them are asynchronous, so a plan build does not wait
+// for earlier work on its stream when it uploads its tables.
+namespace {
+std::mutex g_pin_mu;
+std::map<size_t, std::vector<void*>> g_pin_free;
+std::unordered_map<void*, size_t> g_pin_live;
+}  // namespace
+
+void* pinned_alloc(size_t bytes) {
+  const size_t c = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto& v = g_pin_free[c];
+    if (!v.empty()) {
+      void* p = v.back();
+      v.pop_back();
+      g_pin_live[p] = c;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_live[p] = c;
+  return p;
+}
+
+void pinned_free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  auto it = g_pin_live.find(p);
+  if (it == g_pin_live.end()) return;
+  g_pin_free[it->second].push_back(p);
+  g_pin_live.erase(it);
+}
+
 // --------------------------------------------------------------------------
 // helpers
 // --------------------------------------------------------------------------
@@ -279,6 +319,34 @@ static gcr_status make_fill_args(const gcr_plan* p, int32_t nf, double* const* f
   return GCR_OK;
 }
 
+// The plan's cached weights for the kinds in kind[0..nf) (computed on
+// `st` the first time a kind is used); w[b] receives kind b's array.
+gcr_status plan_weights(gcr_plan* p, int nf, const int* kind, const double* w[2],
+                        hipStream_t st) {
+  bool need[2] = {false, false};
+  for (int f = 0; f < nf; ++f) {
+    if (kind[f] == 0 || kind[f] == 2) need[0] = true;
+    if (kind[f] == 1 || kind[f] == 2) need[1] = true;
+  }
+  const size_t nw = 16 * (size_t)std::max<int64_t>(p->ng, 1);
+  if (!p->wts) {
+    // the weights, then the {0, 1} kind table read by uniform-kind fields
+    p->wts = (double*)pool_alloc(sizeof(double) * (nw + 1));
+    if (!p->wts) return GCR_E_NOMEM;
+  }
+  uint8_t* kinds = reinterpret_cast<uint8_t*>(p->wts + nw);
+  for (int b = 0; b < 2; ++b) {
+    double* wb = p->wts + (size_t)b * 8 * p->ng;
+    if (need[b] && !p->wts_ok[b]) {
+      launch_weights(plan_view(p), b, wb, kinds, st);
+      GCR_HIP(hipGetLastError());
+      p->wts_ok[b] = true;
+    }
+    w[b] = wb;
+  }
+  return GCR_OK;
+}
+
 }  // namespace gcr
 
 using namespace gcr;
@@ -291,6 +359,7 @@ gcr_plan::~gcr_plan() {
   for (int i = 0; i < kScratchSlots; ++i)
     if (scr[i]) pool_free(scr[i]);
   if (sup) pool_free(sup);
+  if (wts) pool_free(wts);
 }
 
 gcr_batch::~gcr_batch() {
@@ -429,6 +498,18 @@ gcr_status gcr_fill(const gcr_plan* plan, int32_t nf, double* const* fields,
   if (plan->ng == 0) return GCR_OK;
   gcr_plan* p = const_cast<gcr_plan*>(plan);
   hipStream_t st = (hipStream_t)stream;
+  s = plan_weights(p, A.nf, A.kind, A.w, st);
+  if (s != GCR_OK) return s;
+  {
+    const uint8_t* kinds = reinterpret_cast<const uint8_t*>(p->wts + 16 * p->ng);
+    for (int f = 0; f < nf; ++f)
+      if (A.kind[f] != GCR_MIXED) {
+        A.bt[f] = kinds + A.kind[f];
+        A.bts[f] = 0;
+      } else {
+        A.bts[f] = 1;
+      }
+  }
   if (p->schedule == kSchedAuto) return tuned_fill(p, A, st);
   return run_fill(p, A, p->schedule, st);
 }

@@ -93,7 +93,9 @@ struct FillArgs {
   int kind[kMaxFields];            // 0 Dirichlet, 1 Neumann, 2 per-ghost
   double* f[kMaxFields];
   const double* b[kMaxFields];
-  const uint8_t* bt[kMaxFields];
+  const uint8_t* bt[kMaxFields];   // kind of ghost p: bt[f][p * bts[f]] (per-ghost array,
+  int bts[kMaxFields];             // stride 1, or the plan's {0, 1} table, stride 0)
+  const double* w[2];              // cached weights per kind, [2^D][ng]
 };
 
 struct SurfArgs {
@@ -118,6 +120,7 @@ struct ForceArgs {
 PlanD plan_view(const gcr_plan* p);
 
 void launch_fill_range(const FillArgs& A, int lo, int hi, hipStream_t st);
+void launch_weights(const PlanD& P, int bc, double* w, uint8_t* kinds, hipStream_t st);
 void launch_fill_wg(const FillArgs& A, const int32_t* d_lev_off, int nlev, int threads,
                     hipStream_t st);
 void launch_fill_units(const FillArgs& A, int level, hipStream_t st);

@@ -49,64 +49,75 @@ __device__ __forceinline__ void fill_unit_field(const PlanD& P, int u, double* F
   for (int i = 0; i < k; ++i) F[ws.cel[i]] = ws.rhs[i];
 }
 
-// Fields are gathered before any store: a ghost of level k reads only
-// fluid cells and ghosts of lower levels, never a slot that this launch
-// writes, so every load of every field may be issued first.  (The compiler
-// cannot prove that on its own: the field arrays could alias.)
+// Loads are ordered so that each ghost costs two dependent round trips:
+// first its metadata, boundary data and cached weights (none depends on
+// another load), then its stencil corners; all stores come last.  A ghost of
+// level k reads only fluid cells and ghosts of lower levels, never a slot
+// that this launch writes, so this order is exact.  (The compiler cannot
+// prove that on its own, since field and weight arrays could alias.)
+// Ghosts of coupled units compute but do not store (their unit solve does).
 constexpr int kFieldGroup = 4;
+
+// Fields f0 .. f0 + kFieldGroup - 1 of ghost p (metadata already loaded).
+template <int D>
+__device__ __forceinline__ void fill_group(const FillArgs& A, int p, int f0, bool live, int c,
+                                           uint32_t code) {
+  const PlanD& P = A.P;
+  const int ng = P.ng;
+  const double* const W0 = A.w[0];
+  const double* const W1 = A.w[1];
+  int bc[kFieldGroup];
+  double bv[kFieldGroup];
+  // slots past nf load field nf - 1 again (never stored): no branches here
+#pragma unroll
+  for (int j = 0; j < kFieldGroup; ++j) {
+    const int f = min(f0 + j, A.nf - 1);
+    bc[j] = (int)A.bt[f][(int64_t)p * A.bts[f]];
+    bv[j] = A.b[f][p];
+  }
+  // both kinds' arrays are always allocated (a kind no field uses holds
+  // unused values), so the loads need not wait for the kinds
+  double wD[8], wN[8];
+#pragma unroll
+  for (int k = 0; k < (1 << D); ++k) {
+    wD[k] = W0[(int64_t)k * ng + p];
+    wN[k] = W1[(int64_t)k * ng + p];
+  }
+  const uint32_t skip = code_skip(code);
+  double val[kFieldGroup][8];
+#pragma unroll
+  for (int j = 0; j < kFieldGroup; ++j) {
+    const double* F = A.f[min(f0 + j, A.nf - 1)];
+#pragma unroll
+    for (int k = 1; k < (1 << D); ++k)
+      val[j][k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
+  }
+  double v[kFieldGroup];
+#pragma unroll
+  for (int j = 0; j < kFieldGroup; ++j) {
+    const bool dir = bc[j] == 0;
+    double sum = (dir ? wD[0] : wN[0]) * bv[j];
+#pragma unroll
+    for (int k = 1; k < (1 << D); ++k)
+      if (!(k & skip)) sum += (dir ? wD[k] : wN[k]) * val[j][k];
+    v[j] = sum;
+  }
+  if (live)
+#pragma unroll
+    for (int j = 0; j < kFieldGroup; ++j)
+      if (f0 + j < A.nf) A.f[f0 + j][c] = v[j];
+}
 
 template <int D>
 __device__ __forceinline__ void fill_ghost(const FillArgs& A, int p) {
   const PlanD& P = A.P;
-  const int blk = P.blk[p];
+  const bool live = P.blk[p] < 0;
   const int c = P.cell[p];
   const uint32_t code = P.code[p];
-  double dl[3], nn[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    dl[a] = a < D ? P.dl[a][p] : 0.0;
-    nn[a] = a < D ? P.nn[a][p] : 0.0;
-  }
-  if (blk >= 0) return;   // coupled unit: solved by fill_units_of_level
-  const uint32_t skip = code_skip(code);
-  int off[8];
-#pragma unroll
-  for (int k = 1; k < (1 << D); ++k) off[k] = c + corner_offset(P.g, code, k);
-  for (int f0 = 0; f0 < A.nf; f0 += kFieldGroup) {
-    double val[kFieldGroup][8], bv[kFieldGroup];
-    int bc[kFieldGroup];
-#pragma unroll
-    for (int j = 0; j < kFieldGroup; ++j) {
-      const int f = f0 + j;
-      if (f >= A.nf) break;
-      bc[j] = A.kind[f] == 2 ? (int)A.bt[f][p] : A.kind[f];
-      bv[j] = A.b[f][p];
-      const double* F = A.f[f];
-#pragma unroll
-      for (int k = 1; k < (1 << D); ++k) val[j][k] = (k & skip) ? 0.0 : F[off[k]];
-    }
-    bool anyD = false, anyN = false;
-#pragma unroll
-    for (int j = 0; j < kFieldGroup; ++j) {
-      if (f0 + j >= A.nf) break;
-      anyD |= bc[j] == 0;
-      anyN |= bc[j] != 0;
-    }
-    double wD[8], wN[8];
-    if (anyD) ghost_weights<D>(dl, nn, code, P.g.h, 0, wD);
-    if (anyN) ghost_weights<D>(dl, nn, code, P.g.h, 1, wN);
-#pragma unroll
-    for (int j = 0; j < kFieldGroup; ++j) {
-      const int f = f0 + j;
-      if (f >= A.nf) break;
-      const bool dir = bc[j] == 0;
-      double v = (dir ? wD[0] : wN[0]) * bv[j];
-#pragma unroll
-      for (int k = 1; k < (1 << D); ++k)
-        if (!(k & skip)) v += (dir ? wD[k] : wN[k]) * val[j][k];
-      A.f[f][c] = v;
-    }
-  }
+  // straight-line groups (kMaxFields = 2 * kFieldGroup), so the first
+  // group's independent loads issue together with the metadata loads
+  fill_group<D>(A, p, 0, live, c, code);
+  if (A.nf > kFieldGroup) fill_group<D>(A, p, kFieldGroup, live, c, code);
 }
 
 // Units of level `level` (1-based), every field; threads tid < nthreads each

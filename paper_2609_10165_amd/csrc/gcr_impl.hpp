@@ -30,6 +30,21 @@ struct InstInfo {
 // Device memory pool: power-of-two size classes, blocks are kept for reuse
 // until the process ends, so rebuilding plans does not call hipMalloc.
 void* pool_alloc(size_t bytes);
+void* pinned_alloc(size_t bytes);
+void pinned_free(void* p);
+
+// Pinned staging block of one plan build.  Until `pending` is cleared, an
+// exit synchronises the stream first, so no queued copy still uses the block
+// when it returns to the pool.
+struct PinnedStage {
+  char* p = nullptr;
+  hipStream_t st = nullptr;
+  bool pending = false;
+  ~PinnedStage() {
+    if (pending) (void)hipStreamSynchronize(st);
+    pinned_free(p);
+  }
+};
 void pool_free(void* p);
 
 template <class T>
@@ -52,6 +67,9 @@ struct BatchData {
   int8_t* d_tags = nullptr;
   int64_t* d_chunk_start = nullptr;  // [ninst+1]
   int32_t* d_chunk_cnt = nullptr;
+  int8_t* d_span = nullptr;          // [chunks * 4] settled flag of each wave's span
+  int32_t* d_band = nullptr;         // near-boundary row segments (k_band)
+  int32_t* d_nband = nullptr;        // their number
   int64_t* d_chunk_excl = nullptr;
   int64_t* d_if_off = nullptr;       // [ninst+1]
   int64_t* d_g_off = nullptr;        // [ninst+1]
@@ -169,6 +187,9 @@ struct gcr_plan {
   // calls that use them must not overlap on one plan
   void* scr[gcr::kScratchSlots] = {};
   size_t scr_bytes[gcr::kScratchSlots] = {};
+  // ghost weights per boundary-condition kind, [2][8][ng], computed on first use
+  double* wts = nullptr;
+  bool wts_ok[2] = {false, false};
   // transposed stencil of the adjoints, built on first use (adjoint.hip)
   void* sup = nullptr;
   int64_t sup_bound = 0;
@@ -176,6 +197,12 @@ struct gcr_plan {
   std::unique_ptr<gcr::GraphCache> graph;
   ~gcr_plan();
 };
+
+namespace gcr {
+// Cached ghost weights of plan p for the kinds used (capi.hip).
+gcr_status plan_weights(gcr_plan* p, int nf, const int* kind, const double* w[2],
+                        hipStream_t st);
+}  // namespace gcr
 
 struct gcr_batch {
   std::shared_ptr<gcr::BatchData> data;

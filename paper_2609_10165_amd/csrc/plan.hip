@@ -258,122 +258,327 @@ __device__ __forceinline__ int star_box(const ShapeD& s, int dim, const double l
   return -1;
 }
 
-__device__ __forceinline__ bool cell_solid(const Inst& I, int i, int j, int k) {
-  double x[3] = {centre(I.g, 0, i), centre(I.g, 1, j), I.g.dim == 3 ? centre(I.g, 2, k) : 0.0};
-  return inside(I.s, I.g.dim, x);
+// Whether every point of the box [lo, hi] lies on one side of the boundary:
+// 0 fluid, 1 solid, -1 undecided (radial bounds, then the Lipschitz test).
+__device__ __forceinline__ int box_settled(const ShapeD& s, int dim, const double lo[3],
+                                           const double hi[3]) {
+  double dmin2 = 0.0, dmax2 = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    const double c = s.cull_c[a];
+    const double dl = c < lo[a] ? lo[a] - c : (c > hi[a] ? c - hi[a] : 0.0);
+    const double df = fmax(fabs(c - lo[a]), fabs(hi[a] - c));
+    dmin2 += dl * dl;
+    dmax2 += df * df;
+  }
+  if (sqrt(dmin2) > s.rmax * (1.0 + 1e-9) + 1e-300) return 0;
+  if (sqrt(dmax2) < s.rmin * (1.0 - 1e-9)) return 1;
+  if (s.kind == kStar2D || s.kind == kShStar) return star_box(s, dim, lo, hi);
+  return -1;
 }
 
-// 16 solid bits of row (j,k) from i0; a row outside the grid returns `self`
-__device__ __forceinline__ uint32_t row_bits(const Inst& I, int i0, int j, int k, uint32_t self) {
-  if (j < 0 || j >= I.g.n[1] || k < 0 || (I.g.dim == 3 && k >= I.g.n[2])) return self;
-  uint32_t b = 0;
-  for (int t = 0; t < kSeg; ++t) b |= (uint32_t)cell_solid(I, i0 + t, j, k) << t;
-  return b;
+// Solid test of cell (i, j, k); g and s come from registers and LDS (the
+// caller copies them once per workgroup: read through the instance table,
+// every field would be a dependent scalar load).
+__device__ __forceinline__ bool cell_solid(const GridD& g, const ShapeD& s, int i, int j, int k) {
+  double x[3] = {centre(g, 0, i), centre(g, 1, j), g.dim == 3 ? centre(g, 2, k) : 0.0};
+  return inside(s, g.dim, x);
+}
+
+// One thread per span of 64 * kSeg cells (one classification wave): whether
+// the box of the span's cells and their face neighbours, in index space,
+// lies wholly on one side of the boundary (0 fluid, 1 solid, -1 undecided).
+__global__ __launch_bounds__(256) void k_spans(const Inst* __restrict__ insts, int ninst,
+                                               const int64_t* __restrict__ chunk_start,
+                                               int64_t nspan, int8_t* __restrict__ span) {
+  constexpr int kSpan = 64 * kSeg, kPer = kChunk / kSpan;
+  const int64_t sp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sp >= nspan) return;
+  const int64_t chunk = sp / kPer;
+  const int ii = find_inst(chunk_start, ninst, chunk);
+  const Inst& I = insts[ii];
+  const GridD& g = I.g;
+  const int64_t base = (chunk - I.chunk_off) * kChunk + (sp % kPer) * kSpan;
+  int8_t r = -1;
+  if (base < g.ncell) {
+    int p0[3], p1[3], mn[3], mx[3];
+    unlinear(g, (int)base, p0[0], p0[1], p0[2]);
+    unlinear(g, (int)min(base + kSpan, g.ncell) - 1, p1[0], p1[1], p1[2]);
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = p0[a];
+      mx[a] = p1[a];
+    }
+    if (p0[2] != p1[2]) {
+      mn[0] = mn[1] = 0;
+      mx[0] = g.n[0] - 1;
+      mx[1] = g.n[1] - 1;
+    } else if (p0[1] != p1[1]) {
+      mn[0] = 0;
+      mx[0] = g.n[0] - 1;
+    }
+    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < g.dim; ++a) {
+      lo[a] = centre(g, a, mn[a]) - g.h[a];
+      hi[a] = centre(g, a, mx[a]) + g.h[a];
+    }
+    r = (int8_t)box_settled(I.s, g.dim, lo, hi);
+  }
+  span[sp] = r;
 }
 
 __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts, int ninst,
                                                   const int64_t* __restrict__ chunk_start,
+                                                  const int8_t* __restrict__ span,
                                                   int8_t* __restrict__ tags,
-                                                  int32_t* __restrict__ chunk_cnt) {
+                                                  int32_t* __restrict__ chunk_cnt,
+                                                  int32_t* __restrict__ band,
+                                                  int32_t* __restrict__ nband) {
   const int64_t chunk = blockIdx.x;
   const int ii = find_inst(chunk_start, ninst, chunk);
   const Inst& I = insts[ii];
-  const GridD& g = I.g;
-  __shared__ int s_cnt;
-  if (threadIdx.x == 0) s_cnt = 0;
+  const GridD g = I.g;
+  const int64_t chunk_off = I.chunk_off, cell_off = I.cell_off;
+  __shared__ int s_cnt, s_band, s_base;
+  __shared__ ShapeD sh_s;
+  static_assert(sizeof(ShapeD) % 8 == 0, "ShapeD copied as doubles");
+  constexpr int kSpans = kChunk / (64 * kSeg);
+  // the shape is read only by waves whose span is undecided or partial
+  bool need_shape = false;
+  for (int q = 0; q < kSpans; ++q)
+    need_shape |= (chunk - chunk_off) * kChunk + (int64_t)(q + 1) * 64 * kSeg > g.ncell ||
+                  span[chunk * kSpans + q] < 0;
+  if (need_shape) {
+    const double* src = reinterpret_cast<const double*>(&I.s);
+    double* dst = reinterpret_cast<double*>(&sh_s);
+    for (int q = (int)threadIdx.x; q < (int)(sizeof(ShapeD) / 8); q += 256) dst[q] = src[q];
+  }
+  if (threadIdx.x == 0) {
+    s_cnt = 0;
+    s_band = 0;
+  }
   __syncthreads();
-  const int64_t base64 = (chunk - I.chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
+  const ShapeD& S = sh_s;
+  const int64_t base64 = (chunk - chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
   int cnt = 0;
-  if (base64 < g.ncell) {
-    const int base = (int)base64;
-    const int nvalid = (int)min((int64_t)kSeg, g.ncell - base64);
-    uint8_t t[kSeg];
-    int i0, j, k;
-    unlinear(g, base, i0, j, k);
-    if (nvalid == kSeg && i0 + kSeg - 1 < g.n[0]) {
-      // one row segment: radial culling on its box (face neighbours included)
-      double lo[3], hi[3];
-      lo[0] = centre(g, 0, i0) - g.h[0];
-      hi[0] = centre(g, 0, i0 + kSeg - 1) + g.h[0];
-      lo[1] = centre(g, 1, j) - g.h[1];
-      hi[1] = centre(g, 1, j) + g.h[1];
-      lo[2] = hi[2] = 0.0;
-      if (g.dim == 3) {
-        lo[2] = centre(g, 2, k) - g.h[2];
-        hi[2] = centre(g, 2, k) + g.h[2];
-      }
-      double dmin2 = 0.0, dmax2 = 0.0;
-      for (int a = 0; a < g.dim; ++a) {
-        double c = I.s.cull_c[a];
-        double dl = c < lo[a] ? lo[a] - c : (c > hi[a] ? c - hi[a] : 0.0);
-        double df = fmax(fabs(c - lo[a]), fabs(hi[a] - c));
-        dmin2 += dl * dl;
-        dmax2 += df * df;
-      }
-      int settled = -1;
-      if (sqrt(dmin2) > I.s.rmax * (1.0 + 1e-9) + 1e-300) settled = 0;
-      else if (sqrt(dmax2) < I.s.rmin * (1.0 - 1e-9)) settled = 1;
-      else if (I.s.kind == kStar2D || I.s.kind == kShStar) settled = star_box(I.s, g.dim, lo, hi);
-      if (settled >= 0) {
-        for (int b = 0; b < kSeg; ++b) t[b] = (uint8_t)settled;
-      } else {
-        uint32_t row = 0;   // bits for i0-1 .. i0+16
-        for (int b = 0; b < kSeg + 2; ++b) {
-          int i = i0 - 1 + b;
-          if (i >= 0 && i < g.n[0]) row |= (uint32_t)cell_solid(I, i, j, k) << b;
-        }
-        if (i0 == 0) row = (row & ~1u) | ((row >> 1) & 1u);
-        if (i0 + kSeg >= g.n[0]) row = (row & ~(1u << (kSeg + 1))) | (((row >> kSeg) & 1u) << (kSeg + 1));
-        const uint32_t M = (1u << kSeg) - 1;
-        uint32_t self = (row >> 1) & M;
-        uint32_t diff = (self ^ (row & M)) | (self ^ ((row >> 2) & M));
-        diff |= self ^ row_bits(I, i0, j - 1, k, self);
-        diff |= self ^ row_bits(I, i0, j + 1, k, self);
+  // a wave whose span the pre-pass settled only stores (full spans only:
+  // the last, partial span of an instance takes the per-segment path)
+  const int64_t wbase = base64 - (int64_t)(threadIdx.x & 63) * kSeg;
+  const int wset = wbase + 64 * kSeg <= g.ncell ? (int)span[chunk * (kChunk / (64 * kSeg)) +
+                                                             (threadIdx.x >> 6)]
+                                                : -1;
+  int mode = 0;   // 0 no cells or stored here, 1 settled segment, 2 band, 3 cell by cell
+  if (wset >= 0) {
+    const uint32_t v = wset ? 0x01010101u : 0u;
+    *reinterpret_cast<uint4*>(tags + cell_off + base64) = make_uint4(v, v, v, v);
+  } else {
+    // per lane: 1 row segment settled by its box, 2 row segment near the
+    // boundary (tested by k_band), 3 segment crossing a row end or the grid
+    // end (cell by cell)
+    const bool valid = base64 < g.ncell;
+    const int base = valid ? (int)base64 : 0;
+    const int nvalid = valid ? (int)min((int64_t)kSeg, g.ncell - base64) : 0;
+    int i0 = 0, j = 0, k = 0, settled = -1;
+    if (valid) {
+      unlinear(g, base, i0, j, k);
+      if (nvalid == kSeg && i0 + kSeg - 1 < g.n[0]) {
+        // radial culling on the segment's box (face neighbours included)
+        double lo[3], hi[3];
+        lo[0] = centre(g, 0, i0) - g.h[0];
+        hi[0] = centre(g, 0, i0 + kSeg - 1) + g.h[0];
+        lo[1] = centre(g, 1, j) - g.h[1];
+        hi[1] = centre(g, 1, j) + g.h[1];
+        lo[2] = hi[2] = 0.0;
         if (g.dim == 3) {
-          diff |= self ^ row_bits(I, i0, j, k - 1, self);
-          diff |= self ^ row_bits(I, i0, j, k + 1, self);
+          lo[2] = centre(g, 2, k) - g.h[2];
+          hi[2] = centre(g, 2, k) + g.h[2];
         }
-        cnt = __popc(diff);
-        for (int b = 0; b < kSeg; ++b)
-          t[b] = (uint8_t)(((self >> b) & 1u) | (((diff >> b) & 1u) << 6));
-      }
-    } else {
-      // segment crossing a row end or the grid end: cell by cell
-      for (int b = 0; b < nvalid; ++b) {
-        int c = base + b, i, jj, kk;
-        unlinear(g, c, i, jj, kk);
-        bool sd = cell_solid(I, i, jj, kk);
-        bool iface = false;
-        int q[3] = {i, jj, kk};
-        for (int a = 0; a < g.dim && !iface; ++a)
-          for (int sg = -1; sg <= 1; sg += 2) {
-            int qq[3] = {q[0], q[1], q[2]};
-            qq[a] += sg;
-            if (qq[a] < 0 || qq[a] >= g.n[a]) continue;
-            if (cell_solid(I, qq[0], qq[1], qq[2]) != sd) {
-              iface = true;
-              break;
-            }
+        settled = box_settled(S, g.dim, lo, hi);
+        mode = settled >= 0 ? 1 : 2;
+      } else {
+        // a segment crossing a row end (or cut by the grid end): the tail of
+        // its first row and the head of its second, each boxed with its
+        // face neighbours, usually settle it too (both sides must agree)
+        int p1[3];
+        unlinear(g, base + nvalid - 1, p1[0], p1[1], p1[2]);
+        const bool one_row = p1[1] == j && p1[2] == k;
+        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+        int seg_a[3] = {i0, j, k}, seg_b[3] = {one_row ? p1[0] : g.n[0] - 1, j, k};
+        for (int a = 0; a < g.dim; ++a) {
+          lo[a] = centre(g, a, seg_a[a]) - g.h[a];
+          hi[a] = centre(g, a, seg_b[a]) + g.h[a];
+        }
+        // (with rows of 16 cells or more a segment meets at most two rows)
+        int sa = g.n[0] >= kSeg ? box_settled(S, g.dim, lo, hi) : -1;
+        if (!one_row && sa >= 0) {
+          const int c0[3] = {0, p1[1], p1[2]};
+          for (int a = 0; a < g.dim; ++a) {
+            lo[a] = centre(g, a, c0[a]) - g.h[a];
+            hi[a] = centre(g, a, p1[a]) + g.h[a];
           }
-        t[b] = (uint8_t)((sd ? 1 : 0) | (iface ? 0x40 : 0));
-        cnt += iface;
+          if (box_settled(S, g.dim, lo, hi) != sa) sa = -1;
+        }
+        settled = sa;
+        mode = settled >= 0 ? 1 : 3;
       }
     }
-    int8_t* dst = tags + I.cell_off + base;
-    if (nvalid == kSeg) {
-      uint4 w;
-      w.x = t[0] | (t[1] << 8) | (t[2] << 16) | ((uint32_t)t[3] << 24);
-      w.y = t[4] | (t[5] << 8) | (t[6] << 16) | ((uint32_t)t[7] << 24);
-      w.z = t[8] | (t[9] << 8) | (t[10] << 16) | ((uint32_t)t[11] << 24);
-      w.w = t[12] | (t[13] << 8) | (t[14] << 16) | ((uint32_t)t[15] << 24);
-      *reinterpret_cast<uint4*>(dst) = w;
-    } else {
-      for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)t[b];
+    if (valid) {
+      uint8_t t[kSeg];
+      if (mode == 1) {
+        for (int b = 0; b < nvalid; ++b) t[b] = (uint8_t)settled;
+      } else if (mode == 2) {
+        for (int b = 0; b < kSeg; ++b) t[b] = 0;   // written by k_band
+      } else {
+        for (int b = 0; b < nvalid; ++b) {
+          int c = base + b, i, jj, kk;
+          unlinear(g, c, i, jj, kk);
+          bool sd = cell_solid(g, S, i, jj, kk);
+          bool iface = false;
+          int q[3] = {i, jj, kk};
+          for (int a = 0; a < g.dim && !iface; ++a)
+            for (int sg = -1; sg <= 1; sg += 2) {
+              int qq[3] = {q[0], q[1], q[2]};
+              qq[a] += sg;
+              if (qq[a] < 0 || qq[a] >= g.n[a]) continue;
+              if (cell_solid(g, S, qq[0], qq[1], qq[2]) != sd) {
+                iface = true;
+                break;
+              }
+            }
+          t[b] = (uint8_t)((sd ? 1 : 0) | (iface ? 0x40 : 0));
+          cnt += iface;
+        }
+      }
+      int8_t* dst = tags + cell_off + base;
+      if (mode == 2) {
+        // k_band writes these 16 cells
+      } else if (nvalid == kSeg) {
+        uint4 w;
+        w.x = t[0] | (t[1] << 8) | (t[2] << 16) | ((uint32_t)t[3] << 24);
+        w.y = t[4] | (t[5] << 8) | (t[6] << 16) | ((uint32_t)t[7] << 24);
+        w.z = t[8] | (t[9] << 8) | (t[10] << 16) | ((uint32_t)t[11] << 24);
+        w.w = t[12] | (t[13] << 8) | (t[14] << 16) | ((uint32_t)t[15] << 24);
+        *reinterpret_cast<uint4*>(dst) = w;
+      } else {
+        for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)t[b];
+      }
     }
+  }
+  // near-boundary row segments go to the band list (k_band tests them with
+  // a whole wave each): positions within the workgroup from an LDS counter,
+  // one global atomic per workgroup; every thread reaches the barriers
+  {
+    const uint64_t bm = __ballot(mode == 2);
+    const int lane = (int)(threadIdx.x & 63);
+    int wofs = 0;
+    if (bm && lane == 0) wofs = atomicAdd(&s_band, __popcll(bm));
+    wofs = __shfl(wofs, 0);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_band > 0) s_base = atomicAdd(nband, s_band);
+    __syncthreads();
+    if (mode == 2)
+      band[s_base + wofs + __popcll(bm & ((1ull << lane) - 1))] =
+          (int32_t)(chunk * (kChunk / kSeg) + threadIdx.x);
   }
   if (cnt) atomicAdd(&s_cnt, cnt);
   __syncthreads();
   if (threadIdx.x == 0) chunk_cnt[chunk] = s_cnt;
+}
+
+constexpr unsigned kBandWaves = 16384;   // workgroups of k_band (one wave each)
+
+// Near-boundary row segments listed by k_classify, one wave each: the 82
+// cells a segment needs (own row with both ends, rows j-1, j+1, k-1, k+1)
+// spread over the lanes (t = 0..17 own row from i0 - 1, t = 18 + 16 r + o row
+// r at i0 + o), two ballots, then lane 0 forms the segment's tags and
+// interface marks.  Cells off the grid read as fluid in the own row; a whole
+// neighbour row off the grid stands for the segment itself, since a face
+// without a neighbour cannot make an interface.  Every wave leaves its loop
+// once the list is exhausted.
+__global__ __launch_bounds__(64) void k_band(const Inst* __restrict__ insts, int ninst,
+                                             const int64_t* __restrict__ chunk_start,
+                                             const int32_t* __restrict__ band,
+                                             const int32_t* __restrict__ nband,
+                                             int8_t* __restrict__ tags,
+                                             int32_t* __restrict__ chunk_cnt) {
+  __shared__ ShapeD sh_s;
+  static_assert(sizeof(ShapeD) % 8 == 0, "ShapeD copied as doubles");
+  const int lane = (int)threadIdx.x;
+  const int nb = nband[0];
+  int cached = -1;
+  for (int b = (int)blockIdx.x; b < nb; b += (int)gridDim.x) {
+    const int32_t seg = band[b];
+    const int64_t chunk = seg / (kChunk / kSeg);
+    const int ii = find_inst(chunk_start, ninst, chunk);
+    const Inst& I = insts[ii];
+    if (ii != cached) {   // uniform: one wave per workgroup
+      __syncthreads();
+      const double* src = reinterpret_cast<const double*>(&I.s);
+      double* dst = reinterpret_cast<double*>(&sh_s);
+      for (int q = lane; q < (int)(sizeof(ShapeD) / 8); q += 64) dst[q] = src[q];
+      __syncthreads();
+      cached = ii;
+    }
+    const ShapeD& S = sh_s;
+    const GridD g = I.g;
+    const int64_t cell_off = I.cell_off;
+    const int base = (int)((chunk - I.chunk_off) * kChunk + (int64_t)(seg % (kChunk / kSeg)) * kSeg);
+    int i0, j, k;
+    unlinear(g, base, i0, j, k);
+    bool r[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int t = lane + 64 * q;
+      bool v = false;
+      if (t < kSeg + 2 + 4 * kSeg) {
+        int ci = i0, cj = j, ck = k, rr = -1;
+        if (t < kSeg + 2) {
+          ci = i0 - 1 + t;
+        } else {
+          rr = (t - (kSeg + 2)) / kSeg;
+          ci = i0 + (t - (kSeg + 2)) % kSeg;
+          if (rr == 0) cj = j - 1;
+          else if (rr == 1) cj = j + 1;
+          else if (rr == 2) ck = k - 1;
+          else ck = k + 1;
+        }
+        const bool in = ci >= 0 && ci < g.n[0] && cj >= 0 && cj < g.n[1] &&
+                        (g.dim == 3 ? (ck >= 0 && ck < g.n[2]) : rr < 2);
+        if (in) v = cell_solid(g, S, ci, cj, ck);
+      }
+      r[q] = v;
+    }
+    const uint64_t m0 = __ballot(r[0]), m1 = __ballot(r[1]);
+    if (lane == 0) {
+      constexpr uint32_t M = (1u << kSeg) - 1;
+      uint32_t row = (uint32_t)(m0 & ((1ull << (kSeg + 2)) - 1));   // i0-1 .. i0+16
+      if (i0 == 0) row = (row & ~1u) | ((row >> 1) & 1u);
+      if (i0 + kSeg >= g.n[0]) row = (row & ~(1u << (kSeg + 1))) | (((row >> kSeg) & 1u) << (kSeg + 1));
+      const uint32_t self = (row >> 1) & M;
+      uint32_t diff = (self ^ (row & M)) | (self ^ ((row >> 2) & M));
+      uint32_t rjm = (uint32_t)(m0 >> 18) & M, rjp = (uint32_t)(m0 >> 34) & M;
+      uint32_t rkm = (uint32_t)((m0 >> 50) | (m1 << 14)) & M, rkp = (uint32_t)(m1 >> 2) & M;
+      if (j - 1 < 0) rjm = self;
+      if (j + 1 >= g.n[1]) rjp = self;
+      diff |= (self ^ rjm) | (self ^ rjp);
+      if (g.dim == 3) {
+        if (k - 1 < 0) rkm = self;
+        if (k + 1 >= g.n[2]) rkp = self;
+        diff |= (self ^ rkm) | (self ^ rkp);
+      }
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          const int c = 4 * q + bb;
+          v |= (((self >> c) & 1u) | (((diff >> c) & 1u) << 6)) << (8 * bb);
+        }
+        w[q] = v;
+      }
+      *reinterpret_cast<uint4*>(tags + cell_off + base) = make_uint4(w[0], w[1], w[2], w[3]);
+      if (diff) atomicAdd(&chunk_cnt[chunk], __popc(diff));
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -526,15 +731,17 @@ __global__ void k_ghost_off(const uint8_t* __restrict__ flag, const int64_t* __r
 // 4. stencils and dependencies
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ int64_t find_cell(const int32_t* cells, int64_t lo, int64_t hi, int c) {
-  // cells[lo..hi) ascending; returns index or -1
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    int v = cells[mid];
-    if (v == c) return mid;
-    if (v < c) lo = mid + 1; else hi = mid;
+// value stored for cell c in one instance's table, or -1 (linear probing;
+// the table is at most half full, so an empty slot ends every probe)
+__device__ __forceinline__ int hash_find(const unsigned long long* t, uint32_t mask, int c) {
+  uint32_t h = (uint32_t)c * 2654435761u;
+  h = (h ^ (h >> 15)) & mask;
+  for (;;) {
+    const unsigned long long e = t[h];
+    if (e == ~0ull) return -1;
+    if ((int)(e >> 32) == c) return (int)(e & 0xffffffffu);
+    h = (h + 1) & mask;
   }
-  return -1;
 }
 
 __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, int ninst,
@@ -543,6 +750,9 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
                                               const double* __restrict__ g_psi,
                                               const double* __restrict__ g_n, int64_t cap,
                                               const int8_t* __restrict__ tags,
+                                              const unsigned long long* __restrict__ htab,
+                                              const int64_t* __restrict__ hoff,
+                                              const uint32_t* __restrict__ hmask,
                                               uint32_t* __restrict__ g_code,
                                               int32_t* __restrict__ deps,
                                               int32_t* __restrict__ rcnt,
@@ -588,7 +798,10 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
         int q = c + corner_offset(g, code, m);
         int8_t t = T[q];
         if (t == 1) atomicOr(&info[ii].err, kErrStencil);
-        else if (t == 2 || t == -2) d = (int32_t)find_cell(g_cell, g_off[ii], g_off[ii + 1], q);
+        else if (t == 2 || t == -2) {
+          const int v = hash_find(htab + hoff[ii], hmask[ii], q);
+          if (v >= 0) d = (int32_t)(g_off[ii] + v);
+        }
       }
     }
     deps[(int64_t)(m - 1) * cap + e] = d;
@@ -775,6 +988,19 @@ __global__ void k_hash_build(const int64_t* __restrict__ g_off, int ninst,
   while (atomicCAS(&t[h], ~0ull, entry) != ~0ull) h = (h + 1) & mask;
 }
 
+// linear-order ghost index -> canonical position, in place
+__global__ void k_hash_remap(const int64_t* __restrict__ hoff, int ninst,
+                             const int64_t* __restrict__ g_off, const int32_t* __restrict__ perm,
+                             unsigned long long* __restrict__ htab) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= hoff[ninst]) return;
+  const unsigned long long e = htab[s];
+  if (e == ~0ull) return;
+  const int ii = find_inst(hoff, ninst, s);
+  const int32_t v = (int32_t)(e & 0xffffffffu);
+  htab[s] = (e & 0xffffffff00000000ull) | (uint32_t)perm[g_off[ii] + v];
+}
+
 // --------------------------------------------------------------------------
 // host orchestration
 // --------------------------------------------------------------------------
@@ -955,6 +1181,9 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_tags = own<int8_t>(D, cells);
   D.d_chunk_start = own<int64_t>(D, ninst + 1);
   D.d_chunk_cnt = own<int32_t>(D, chunks);
+  D.d_span = own<int8_t>(D, chunks * (kChunk / (64 * kSeg)));
+  D.d_band = own<int32_t>(D, chunks * (kChunk / kSeg));   // every segment at most once
+  D.d_nband = own<int32_t>(D, 1);
   D.d_chunk_excl = own<int64_t>(D, chunks + 1);
   D.d_if_off = own<int64_t>(D, ninst + 1);
   D.d_g_off = own<int64_t>(D, ninst + 1);
@@ -965,18 +1194,42 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_unit_lev = own<int32_t>(D, (size_t)ninst * kMaxUnits);
   D.d_reach = own<uint32_t>(D, (size_t)ninst * kMaxResidual * (kMaxResidual / 32));
   if (!D.d_unit_lev || !D.d_reach) return GCR_E_NOMEM;
-  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl ||
+  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_span || !D.d_band || !D.d_nband ||
       !D.d_if_off || !D.d_g_off || !D.d_info || !D.d_lev_off || !D.d_unit_mem || !D.d_unit_cnt)
     return GCR_E_NOMEM;
-  GCR_HIP(hipMemcpyAsync(D.d_inst, D.inst.data(), sizeof(Inst) * ninst, hipMemcpyHostToDevice, st));
-  GCR_HIP(hipMemcpyAsync(D.d_chunk_start, chunk_start.data(), sizeof(int64_t) * (ninst + 1),
+  // pinned staging: [instances | chunk starts | if_off | hoff | hmask | g_off |
+  // info | lev_off | unit_lev], each region 256-byte aligned
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_inst = 0, o_cs = o_inst + al(sizeof(Inst) * ninst);
+  const size_t o_if = o_cs + al(8 * (ninst + 1)), o_ho = o_if + al(8 * (ninst + 1));
+  const size_t o_hm = o_ho + al(8 * (ninst + 1)), o_go = o_hm + al(4 * ninst);
+  const size_t o_info = o_go + al(8 * (ninst + 1)), o_lo = o_info + al(sizeof(InstInfo) * ninst);
+  const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
+  const size_t stage_bytes = o_ul + al(4 * (size_t)ninst * kMaxUnits);
+  PinnedStage PS;
+  PS.st = st;
+  PS.p = (char*)pinned_alloc(stage_bytes);
+  if (!PS.p) return GCR_E_NOMEM;
+  std::memcpy(PS.p + o_inst, D.inst.data(), sizeof(Inst) * ninst);
+  std::memcpy(PS.p + o_cs, chunk_start.data(), 8 * (ninst + 1));
+  PS.pending = true;
+  GCR_HIP(hipMemcpyAsync(D.d_inst, PS.p + o_inst, sizeof(Inst) * ninst, hipMemcpyHostToDevice, st));
+  GCR_HIP(hipMemcpyAsync(D.d_chunk_start, PS.p + o_cs, sizeof(int64_t) * (ninst + 1),
                          hipMemcpyHostToDevice, st));
   GCR_HIP(hipMemsetAsync(D.d_info, 0, sizeof(InstInfo) * ninst, st));
 
   StageEvents T(g_profiling.load() != 0);
   T.mark(0, st);
-  k_classify<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
-                                                D.d_chunk_cnt);
+  {
+    const int64_t nspan = chunks * (kChunk / (64 * kSeg));
+    k_spans<<<blocks(nspan, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, nspan,
+                                                 D.d_span);
+  }
+  k_zero32<<<1, 64, 0, st>>>(D.d_nband, 1);
+  k_classify<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_span,
+                                                D.d_tags, D.d_chunk_cnt, D.d_band, D.d_nband);
+  k_band<<<kBandWaves, 64, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_band, D.d_nband,
+                                    D.d_tags, D.d_chunk_cnt);
   T.mark(1, st);
   k_scan<<<1, 1024, 0, st>>>(D.d_chunk_cnt, chunks, D.d_chunk_excl);
   k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
@@ -984,13 +1237,36 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   T.mark(2, st);
   GCR_HIP(hipGetLastError());
   D.if_off.resize(ninst + 1);
-  GCR_HIP(hipMemcpyAsync(D.if_off.data(), D.d_if_off, sizeof(int64_t) * (ninst + 1),
+  GCR_HIP(hipMemcpyAsync(PS.p + o_if, D.d_if_off, sizeof(int64_t) * (ninst + 1),
                          hipMemcpyDeviceToHost, st));
   GCR_HIP(hipStreamSynchronize(st));
+  std::memcpy(D.if_off.data(), PS.p + o_if, 8 * (ninst + 1));
   const int64_t nif = D.if_off[ninst];
   const int64_t cap = std::max<int64_t>(nif, 1);
   D.nif = nif;
   D.cap = cap;
+  // cell -> ghost tables: at most half full (ghosts <= interface cells);
+  // keyed to linear-order ghost indices while the plan is built, remapped
+  // to canonical positions once those are known
+  D.hoff.assign(ninst + 1, 0);
+  D.hmask.assign(ninst, 0);
+  for (int i = 0; i < ninst; ++i) {
+    int64_t size = 64;
+    while (size < 2 * (D.if_off[i + 1] - D.if_off[i])) size <<= 1;
+    D.hmask[i] = (uint32_t)(size - 1);
+    D.hoff[i + 1] = D.hoff[i] + size;
+  }
+  D.d_htab = own<unsigned long long>(D, D.hoff[ninst]);
+  D.d_hoff = own<int64_t>(D, ninst + 1);
+  D.d_hmask = own<uint32_t>(D, ninst);
+  if (!D.d_htab || !D.d_hoff || !D.d_hmask) return GCR_E_NOMEM;
+  std::memcpy(PS.p + o_ho, D.hoff.data(), 8 * (ninst + 1));
+  std::memcpy(PS.p + o_hm, D.hmask.data(), 4 * ninst);
+  GCR_HIP(hipMemcpyAsync(D.d_hoff, PS.p + o_ho, sizeof(int64_t) * (ninst + 1),
+                         hipMemcpyHostToDevice, st));
+  GCR_HIP(hipMemcpyAsync(D.d_hmask, PS.p + o_hm, sizeof(uint32_t) * ninst,
+                         hipMemcpyHostToDevice, st));
+  k_hash_clear<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_htab, D.hoff[ninst]);
   const int64_t nblk = (nif + 1023) / 1024;
   D.d_if_cell = own<int32_t>(D, cap);
   D.d_if_psi = own<double>(D, cap);
@@ -1048,9 +1324,12 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                                                       D.d_g_off);
     T.mark(6, st);
     // ghost count unknown on the host: launch over the interface capacity
+    k_hash_build<<<blocks(nif, 256), 256, 0, st>>>(D.d_g_off, ninst, D.d_g_cell, D.d_hoff,
+                                                    D.d_hmask, D.d_htab);
     k_zero32<<<blocks(2 * cap, 256), 256, 0, st>>>(D.d_rcnt, 2 * cap);   // rcnt + rfill
     k_deps<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_g_off, D.d_g_cell, D.d_g_psi,
-                                              D.d_g_n, cap, D.d_tags, D.d_g_code, D.d_deps,
+                                              D.d_g_n, cap, D.d_tags, D.d_htab, D.d_hoff,
+                                              D.d_hmask, D.d_g_code, D.d_deps,
                                               D.d_rcnt, D.d_dcnt, D.d_info);
     k_rscan<<<1, 1024, 0, st>>>(D.d_rcnt, D.d_g_off, ninst, D.d_roff);
     k_rfill<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, D.d_g_off, ninst, cap, D.d_deps,
@@ -1088,6 +1367,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
         D.d_blk_idx, D.d_perm, D.d_cell, D.d_delta, D.d_nrm, D.d_psi, D.d_code, D.d_level,
         D.d_blk, D.d_info);
     k_units_canonical<<<ninst, 256, 0, st>>>(D.d_perm, D.d_info, D.d_unit_mem, D.d_unit_cnt);
+    k_hash_remap<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_hoff, ninst, D.d_g_off, D.d_perm,
+                                                              D.d_htab);
     T.mark(9, st);
   } else {
     for (int i = 4; i <= 9; ++i) T.mark(i, st);
@@ -1098,43 +1379,27 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.g_off.resize(ninst + 1);
   D.info.resize(ninst);
   D.lev_off.resize((size_t)ninst * (kMaxLevels + 1));
-  GCR_HIP(hipMemcpyAsync(D.g_off.data(), D.d_g_off, sizeof(int64_t) * (ninst + 1),
+  GCR_HIP(hipMemcpyAsync(PS.p + o_go, D.d_g_off, sizeof(int64_t) * (ninst + 1),
                          hipMemcpyDeviceToHost, st));
-  GCR_HIP(hipMemcpyAsync(D.info.data(), D.d_info, sizeof(InstInfo) * ninst, hipMemcpyDeviceToHost,
+  GCR_HIP(hipMemcpyAsync(PS.p + o_info, D.d_info, sizeof(InstInfo) * ninst, hipMemcpyDeviceToHost,
                          st));
-  GCR_HIP(hipMemcpyAsync(D.lev_off.data(), D.d_lev_off,
-                         sizeof(int32_t) * ninst * (kMaxLevels + 1), hipMemcpyDeviceToHost, st));
+  GCR_HIP(hipMemcpyAsync(PS.p + o_lo, D.d_lev_off, sizeof(int32_t) * ninst * (kMaxLevels + 1),
+                         hipMemcpyDeviceToHost, st));
   D.unit_lev.resize((size_t)ninst * kMaxUnits);
-  GCR_HIP(hipMemcpyAsync(D.unit_lev.data(), D.d_unit_lev, sizeof(int32_t) * ninst * kMaxUnits,
+  GCR_HIP(hipMemcpyAsync(PS.p + o_ul, D.d_unit_lev, sizeof(int32_t) * ninst * kMaxUnits,
                          hipMemcpyDeviceToHost, st));
   GCR_HIP(hipStreamSynchronize(st));
+  PS.pending = false;
+  std::memcpy(D.g_off.data(), PS.p + o_go, 8 * (ninst + 1));
+  std::memcpy(D.info.data(), PS.p + o_info, sizeof(InstInfo) * ninst);
+  std::memcpy(D.lev_off.data(), PS.p + o_lo, 4 * (size_t)ninst * (kMaxLevels + 1));
+  std::memcpy(D.unit_lev.data(), PS.p + o_ul, 4 * (size_t)ninst * kMaxUnits);
   T.collect();
   D.ng_total = D.g_off[ninst];
   for (int i = 0; i < ninst; ++i) {
     gcr_status s = status_from_err(D.info[i].err);
     if (s != GCR_OK) return s;
   }
-  // cell -> ghost tables, built on the stream (used by later calls only)
-  D.hoff.assign(ninst + 1, 0);
-  D.hmask.assign(ninst, 0);
-  for (int i = 0; i < ninst; ++i) {
-    int64_t size = 64;
-    while (size < 2 * (D.g_off[i + 1] - D.g_off[i])) size <<= 1;
-    D.hmask[i] = (uint32_t)(size - 1);
-    D.hoff[i + 1] = D.hoff[i] + size;
-  }
-  D.d_htab = own<unsigned long long>(D, D.hoff[ninst]);
-  D.d_hoff = own<int64_t>(D, ninst + 1);
-  D.d_hmask = own<uint32_t>(D, ninst);
-  if (!D.d_htab || !D.d_hoff || !D.d_hmask) return GCR_E_NOMEM;
-  GCR_HIP(hipMemcpyAsync(D.d_hoff, D.hoff.data(), sizeof(int64_t) * (ninst + 1),
-                         hipMemcpyHostToDevice, st));
-  GCR_HIP(hipMemcpyAsync(D.d_hmask, D.hmask.data(), sizeof(uint32_t) * ninst,
-                         hipMemcpyHostToDevice, st));
-  k_hash_clear<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_htab, D.hoff[ninst]);
-  if (D.ng_total > 0)
-    k_hash_build<<<blocks(D.ng_total, 256), 256, 0, st>>>(D.d_g_off, ninst, D.d_cell, D.d_hoff,
-                                                          D.d_hmask, D.d_htab);
   GCR_HIP(hipGetLastError());
   *out = B;
   return GCR_OK;
