@@ -60,18 +60,22 @@ def parse():
 def bc_sphere_fields(S, n):
     """Boundary data of the u, v, w, p fields at the foot points: values of
     u = sin z + cos y, v = sin x + cos z, w = sin y + cos x and the normal
-    derivative of p = cos x cos y cos z (caller side, torch)."""
+    derivative of p = cos x cos y cos z, written dp/dn = -(c_x c_y c_z)
+    sum_i tan(S_i) n_i (cos > 0.5 on the domain) to keep the caller's
+    launches few (caller side, torch)."""
     import torch
     s, c = torch.sin(S), torch.cos(S)
     out = torch.empty((4, S.shape[1]), dtype=torch.float64, device=S.device)
-    torch.add(s[2], c[1], out=out[0])
-    torch.add(s[0], c[2], out=out[1])
-    torch.add(s[1], c[0], out=out[2])
-    # dp/dn = -(s0 c1 c2 n0 + c0 s1 c2 n1 + c0 c1 s2 n2)
-    t = torch.stack([s[0] * c[1] * c[2], c[0] * s[1] * c[2], c[0] * c[1] * s[2]])
-    torch.sum(t * n, dim=0, out=out[3])
-    out[3].neg_()
+    torch.add(s[_IDX_S], c[_IDX_C], out=out[:3])
+    t = s / c
+    t.mul_(n)
+    torch.sum(t, dim=0, out=out[3])
+    out[3].mul_(c.prod(dim=0)).neg_()
     return out
+
+
+_IDX_S = [2, 0, 1]   # u: sin z, v: sin x, w: sin y
+_IDX_C = [1, 2, 0]   #    cos y,    cos z,    cos x
 
 
 def _dev(torch, a, dtype=None):
@@ -177,6 +181,7 @@ def main():
     if not args.no_extras:
         extras["batched"] = bench_batched(gcr, torch, synth, args.extra_reps)
         extras["fwd_bwd"] = bench_fwd_bwd(gcr, torch, synth, args.extra_reps)
+        extras["large"] = bench_large(gcr, torch, synth, max(3, args.extra_reps // 2))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -335,6 +340,66 @@ def bench_fwd_bwd(gcr, torch, synth, reps):
             "fwd_ghost_cells_per_s": round(ng / (tf * 1e-3), 1),
             "fwd_bwd_ghost_cells_per_s": round(ng / (tfb * 1e-3), 1),
             "dense_grad_zero_ms": round(tz, 4)}
+
+
+def bench_large(gcr, torch, synth, reps):
+    """The sphere of the headline workload on a 1024^3 grid (1.07e9 cells):
+    the size at which the classification pass (1 byte per cell written)
+    is bandwidth-scale.  HGC plan, fill of u, v, w, p, force; fields are
+    generated on the device."""
+    inst = synth.sphere256(seed=0, n=1024)
+    g = inst.grid
+    dev = "cuda"
+    ax = [g.lo[a] + (torch.arange(g.n[a], dtype=torch.float64, device=dev) + 0.5) * g.h[a]
+          for a in range(3)]
+    x, y, z = ax[0][None, None, :], ax[1][None, :, None], ax[2][:, None, None]
+    shape = (g.n[2], g.n[1], g.n[0])
+    fields = [(torch.sin(z) + torch.cos(y)).expand(shape).contiguous().view(-1),
+              (torch.sin(x) + torch.cos(z)).expand(shape).contiguous().view(-1),
+              (torch.sin(y) + torch.cos(x)).expand(shape).contiguous().view(-1),
+              (torch.cos(x) * torch.cos(y) * torch.cos(z)).contiguous().view(-1)]
+    kinds = [DIRICHLET, DIRICHLET, DIRICHLET, NEUMANN]
+    q = inst.queries
+    xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
+    F = torch.empty(3, dtype=torch.float64, device=dev)
+
+    def step():
+        plan = gcr.Plan(g, inst.shape, 2)
+        times = gcr.last_build_times()
+        S, nrm = plan.foot_points()
+        plan.fill(fields, kinds, list(bc_sphere_fields(S, nrm)))
+        plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
+        return plan.n_ghost, times
+
+    gcr.set_profiling(True)
+    step()
+    torch.cuda.synchronize()
+    ts, cls = [], []
+    ng = 0
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ng, times = step()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+        cls.append(times["classify"])
+    gcr.set_profiling(False)
+    t = float(np.median(ts))
+    c = float(np.median(cls))
+    ncell = g.n[0] * g.n[1] * g.n[2]
+    del fields
+    torch.cuda.empty_cache()
+    return {"workload": "sphere1024: 1024^3 grid on [-1,1]^3, the headline sphere, HGC, "
+                        "plan + fill of u,v,w,p + force",
+            "cells": ncell, "ghosts": ng, "step_ms": round(t, 4),
+            "ghost_cells_per_s": round(ng / (t * 1e-3), 1),
+            "classify_ms": round(c, 5),
+            "classify_roofline": {"bound": "hbm", "achieved": round(ncell / (c * 1e-3) / 1e9, 2),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(ncell / (c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "algorithmic_bytes": ncell}}
 
 
 def cpu_baseline(inst, seconds):

@@ -446,17 +446,7 @@ __global__ __launch_bounds__(256) void k_sadj_anchor(SurfAdjArgs S) {
 __global__ __launch_bounds__(1024) void k_sadj_scan(const int32_t* __restrict__ cnt, int n,
                                                     int32_t* __restrict__ off) {
   __shared__ int64_t sh[17];
-  const int per = (n + 1023) / 1024;
-  const int b = threadIdx.x * per, e = min(n, b + per);
-  int64_t s = 0;
-  for (int i = b; i < e; ++i) s += cnt[i];
-  int64_t tot;
-  int64_t run = block_excl_scan<1024>(s, &tot, sh);
-  for (int i = b; i < e; ++i) {
-    off[i] = (int32_t)run;
-    run += cnt[i];
-  }
-  if (threadIdx.x == 0) off[n] = (int32_t)tot;
+  block_scan_i32(cnt, n, off, sh);
 }
 
 __global__ __launch_bounds__(256) void k_sadj_bucket(SurfAdjArgs S) {

@@ -87,6 +87,51 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* total, in
   return res;
 }
 
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total, by one
+// workgroup of 1024 threads: tiles of 8 consecutive values per thread
+// (two 16-byte loads when the tile is whole and aligned), a serial scan per
+// thread, one workgroup scan per tile.  Every thread must call it.
+__device__ __forceinline__ void block_scan_i32(const int32_t* __restrict__ in, int64_t n,
+                                               int32_t* __restrict__ out, int64_t* sh) {
+  constexpr int kT = 8, kTile = 1024 * kT;
+  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  int64_t carry = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += kTile) {
+    const int64_t b = t0 + (int64_t)threadIdx.x * kT;
+    int v[kT];
+    if (vec && b + kT <= n) {
+      const int4 a = *reinterpret_cast<const int4*>(in + b);
+      const int4 c = *reinterpret_cast<const int4*>(in + b + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < kT; ++q) v[q] = b + q < n ? in[b + q] : 0;
+    }
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kT; ++q) sum += v[q];
+    int64_t tot;
+    int64_t run = carry + block_excl_scan<1024>(sum, &tot, sh);
+    int o[kT];
+#pragma unroll
+    for (int q = 0; q < kT; ++q) {
+      o[q] = (int32_t)run;
+      run += v[q];
+    }
+    if (vec && b + kT <= n) {
+      *reinterpret_cast<int4*>(out + b) = make_int4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<int4*>(out + b + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kT; ++q)
+        if (b + q < n) out[b + q] = o[q];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = (int32_t)carry;
+}
+
 // --------------------------------------------------------------------------
 // grid helpers
 // --------------------------------------------------------------------------

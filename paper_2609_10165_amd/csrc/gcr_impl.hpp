@@ -68,6 +68,8 @@ struct BatchData {
   int64_t* d_chunk_start = nullptr;  // [ninst+1]
   int32_t* d_chunk_cnt = nullptr;
   int8_t* d_span = nullptr;          // [chunks * 4] settled flag of each wave's span
+  int32_t* d_chunk_list = nullptr;   // chunks holding interface cells, ascending
+  int32_t* d_nchunk_list = nullptr;
   int32_t* d_band = nullptr;         // near-boundary row segments (k_band)
   int32_t* d_nband = nullptr;        // their number
   int64_t* d_chunk_excl = nullptr;
@@ -118,6 +120,8 @@ struct BatchData {
   std::vector<int64_t> hoff;
   std::vector<uint32_t> hmask;
   std::vector<void*> owned;
+  char* arena_cur = nullptr;         // bump allocator over pooled chunks
+  size_t arena_left = 0;
   ~BatchData();
 };
 

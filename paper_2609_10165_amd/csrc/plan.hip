@@ -341,12 +341,24 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
   __shared__ ShapeD sh_s;
   static_assert(sizeof(ShapeD) % 8 == 0, "ShapeD copied as doubles");
   constexpr int kSpans = kChunk / (64 * kSeg);
-  // the shape is read only by waves whose span is undecided or partial
+  // a workgroup whose spans are all whole and settled only stores: one round
+  // of flag loads, no barrier (most workgroups of a large grid)
   bool need_shape = false;
-  for (int q = 0; q < kSpans; ++q)
+  int8_t fl[kSpans];
+  for (int q = 0; q < kSpans; ++q) {
+    fl[q] = span[chunk * kSpans + q];
     need_shape |= (chunk - chunk_off) * kChunk + (int64_t)(q + 1) * 64 * kSeg > g.ncell ||
-                  span[chunk * kSpans + q] < 0;
-  if (need_shape) {
+                  fl[q] < 0;
+  }
+  if (!need_shape) {
+    const int8_t f = fl[threadIdx.x >> 6];
+    const uint32_t v = f ? 0x01010101u : 0u;
+    *reinterpret_cast<uint4*>(tags + cell_off + (chunk - chunk_off) * kChunk +
+                              (int64_t)threadIdx.x * kSeg) = make_uint4(v, v, v, v);
+    if (threadIdx.x == 0) chunk_cnt[chunk] = 0;
+    return;
+  }
+  {
     const double* src = reinterpret_cast<const double*>(&I.s);
     double* dst = reinterpret_cast<double*>(&sh_s);
     for (int q = (int)threadIdx.x; q < (int)(sizeof(ShapeD) / 8); q += 256) dst[q] = src[q];
@@ -585,21 +597,50 @@ __global__ __launch_bounds__(64) void k_band(const Inst* __restrict__ insts, int
 // 2. scans and compactions
 // --------------------------------------------------------------------------
 
-// excl[i] = sum cnt[0..i), excl[n] = total; one workgroup.
+// excl[i] = sum cnt[0..i), excl[n] = total; one workgroup.  If list is
+// given, the indices i with cnt[i] > 0 are written to it in ascending order
+// and their number to nlist[0]: each count carries a flag in bits 40 and up,
+// so one scan yields both (counts stay below 2^40).
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ cnt, int64_t n,
-                                               int64_t* __restrict__ excl) {
+                                               int64_t* __restrict__ excl,
+                                               int32_t* __restrict__ list,
+                                               int32_t* __restrict__ nlist) {
   __shared__ int64_t sh[17];
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = threadIdx.x * per, e = min(n, b + per);
-  int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += cnt[i];
-  int64_t tot;
-  int64_t run = block_excl_scan<1024>(s, &tot, sh);
-  for (int64_t i = b; i < e; ++i) {
-    excl[i] = run;
-    run += cnt[i];
+  constexpr int kT = 8, kTile = 1024 * kT;
+  constexpr int64_t kHi = int64_t(1) << 40;
+  const bool vec = (reinterpret_cast<uintptr_t>(cnt) & 15) == 0;
+  int64_t carry = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += kTile) {
+    const int64_t b = t0 + (int64_t)threadIdx.x * kT;
+    int v[kT];
+    if (vec && b + kT <= n) {
+      const int4 a = *reinterpret_cast<const int4*>(cnt + b);
+      const int4 c = *reinterpret_cast<const int4*>(cnt + b + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < kT; ++q) v[q] = b + q < n ? cnt[b + q] : 0;
+    }
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kT; ++q) sum += v[q] + (v[q] > 0 ? kHi : 0);
+    int64_t tot;
+    int64_t run = carry + block_excl_scan<1024>(sum, &tot, sh);
+#pragma unroll
+    for (int q = 0; q < kT; ++q) {
+      if (b + q < n) {
+        excl[b + q] = run & (kHi - 1);
+        if (list && v[q] > 0) list[run >> 40] = (int32_t)(b + q);
+      }
+      run += v[q] + (v[q] > 0 ? kHi : 0);
+    }
+    carry += tot;
   }
-  if (threadIdx.x == 0) excl[n] = tot;
+  if (threadIdx.x == 0) {
+    excl[n] = carry & (kHi - 1);
+    if (nlist) nlist[0] = (int32_t)(carry >> 40);
+  }
 }
 
 // off[i] = excl[start[i]] for the instance boundaries
@@ -614,9 +655,9 @@ __global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ 
                                                        const int8_t* __restrict__ tags,
                                                        const int32_t* __restrict__ chunk_cnt,
                                                        const int64_t* __restrict__ chunk_excl,
+                                                       const int32_t* __restrict__ chunk_list,
                                                        int32_t* __restrict__ if_cell) {
-  const int64_t chunk = blockIdx.x;
-  if (chunk_cnt[chunk] == 0) return;
+  const int64_t chunk = chunk_list[blockIdx.x];   // chunks holding interface cells
   __shared__ int64_t sh[5];
   const int ii = find_inst(chunk_start, ninst, chunk);
   const Inst& I = insts[ii];
@@ -627,8 +668,16 @@ __global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ 
     base = (int)base64;
     const int nvalid = (int)min((int64_t)kSeg, I.g.ncell - base64);
     const int8_t* src = tags + I.cell_off + base;
-    for (int b = 0; b < nvalid; ++b)
-      if (src[b] & 0x40) mask |= 1u << b;
+    if (nvalid == kSeg) {
+      const uint4 w = *reinterpret_cast<const uint4*>(src);
+      const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int b = 0; b < kSeg; ++b)
+        if ((q[b >> 2] >> (8 * (b & 3))) & 0x40u) mask |= 1u << b;
+    } else {
+      for (int b = 0; b < nvalid; ++b)
+        if (src[b] & 0x40) mask |= 1u << b;
+    }
   }
   int64_t tot;
   int64_t pos = chunk_excl[chunk] + block_excl_scan<256>(__popc(mask), &tot, sh);
@@ -820,18 +869,7 @@ __global__ __launch_bounds__(1024) void k_rscan(const int32_t* __restrict__ cnt,
                                                 const int64_t* __restrict__ g_off, int ninst,
                                                 int32_t* __restrict__ off) {
   __shared__ int64_t sh[17];
-  const int64_t n = g_off[ninst];
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = threadIdx.x * per, e = min(n, b + per);
-  int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += cnt[i];
-  int64_t tot;
-  int64_t run = block_excl_scan<1024>(s, &tot, sh);
-  for (int64_t i = b; i < e; ++i) {
-    off[i] = (int32_t)run;
-    run += cnt[i];
-  }
-  if (threadIdx.x == 0) off[n] = (int32_t)tot;
+  block_scan_i32(cnt, g_off[ninst], off, sh);
 }
 
 __global__ __launch_bounds__(256) void k_rfill(const Inst* __restrict__ insts,
@@ -1102,8 +1140,22 @@ BatchData::~BatchData() {
 
 template <class T>
 static T* own(BatchData& B, size_t n) {
-  T* p = palloc<T>(n);
-  if (p) B.owned.push_back(p);
+  // bump allocation from pooled chunks of at least 4 MiB (a build makes a
+  // few pool calls instead of one per array); 256-byte aligned
+  constexpr size_t kArena = size_t(4) << 20;
+  const size_t bytes = ((sizeof(T) * (n ? n : 1)) + 255) & ~size_t(255);
+  if (bytes > B.arena_left) {
+    const size_t chunk = std::max(bytes, kArena);
+    char* c = static_cast<char*>(pool_alloc(chunk));
+    if (!c) return nullptr;
+    B.owned.push_back(c);
+    if (bytes >= kArena) return reinterpret_cast<T*>(c);   // a chunk of its own
+    B.arena_cur = c;
+    B.arena_left = chunk;
+  }
+  T* p = reinterpret_cast<T*>(B.arena_cur);
+  B.arena_cur += bytes;
+  B.arena_left -= bytes;
   return p;
 }
 
@@ -1182,6 +1234,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_chunk_start = own<int64_t>(D, ninst + 1);
   D.d_chunk_cnt = own<int32_t>(D, chunks);
   D.d_span = own<int8_t>(D, chunks * (kChunk / (64 * kSeg)));
+  D.d_chunk_list = own<int32_t>(D, chunks);
+  D.d_nchunk_list = own<int32_t>(D, 1);
   D.d_band = own<int32_t>(D, chunks * (kChunk / kSeg));   // every segment at most once
   D.d_nband = own<int32_t>(D, 1);
   D.d_chunk_excl = own<int64_t>(D, chunks + 1);
@@ -1194,7 +1248,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_unit_lev = own<int32_t>(D, (size_t)ninst * kMaxUnits);
   D.d_reach = own<uint32_t>(D, (size_t)ninst * kMaxResidual * (kMaxResidual / 32));
   if (!D.d_unit_lev || !D.d_reach) return GCR_E_NOMEM;
-  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_span || !D.d_band || !D.d_nband ||
+  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_span || !D.d_chunk_list || !D.d_nchunk_list || !D.d_band || !D.d_nband ||
       !D.d_if_off || !D.d_g_off || !D.d_info || !D.d_lev_off || !D.d_unit_mem || !D.d_unit_cnt)
     return GCR_E_NOMEM;
   // pinned staging: [instances | chunk starts | if_off | hoff | hmask | g_off |
@@ -1205,7 +1259,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   const size_t o_hm = o_ho + al(8 * (ninst + 1)), o_go = o_hm + al(4 * ninst);
   const size_t o_info = o_go + al(8 * (ninst + 1)), o_lo = o_info + al(sizeof(InstInfo) * ninst);
   const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
-  const size_t stage_bytes = o_ul + al(4 * (size_t)ninst * kMaxUnits);
+  const size_t o_nl = o_ul + al(4 * (size_t)ninst * kMaxUnits);
+  const size_t stage_bytes = o_nl + al(4);
   PinnedStage PS;
   PS.st = st;
   PS.p = (char*)pinned_alloc(stage_bytes);
@@ -1231,7 +1286,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   k_band<<<kBandWaves, 64, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_band, D.d_nband,
                                     D.d_tags, D.d_chunk_cnt);
   T.mark(1, st);
-  k_scan<<<1, 1024, 0, st>>>(D.d_chunk_cnt, chunks, D.d_chunk_excl);
+  k_scan<<<1, 1024, 0, st>>>(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list,
+                             D.d_nchunk_list);
   k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
                                                      D.d_if_off);
   T.mark(2, st);
@@ -1239,8 +1295,12 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.if_off.resize(ninst + 1);
   GCR_HIP(hipMemcpyAsync(PS.p + o_if, D.d_if_off, sizeof(int64_t) * (ninst + 1),
                          hipMemcpyDeviceToHost, st));
+  GCR_HIP(hipMemcpyAsync(PS.p + o_nl, D.d_nchunk_list, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         st));
   GCR_HIP(hipStreamSynchronize(st));
   std::memcpy(D.if_off.data(), PS.p + o_if, 8 * (ninst + 1));
+  int32_t nlist = 0;
+  std::memcpy(&nlist, PS.p + o_nl, sizeof(int32_t));
   const int64_t nif = D.if_off[ninst];
   const int64_t cap = std::max<int64_t>(nif, 1);
   D.nif = nif;
@@ -1308,15 +1368,16 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
 
   T.mark(3, st);
   if (nif > 0) {
-    k_compact_iface<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
-                                                      D.d_chunk_cnt, D.d_chunk_excl, D.d_if_cell);
+    k_compact_iface<<<(unsigned)nlist, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
+                                                     D.d_chunk_cnt, D.d_chunk_excl, D.d_chunk_list,
+                                                     D.d_if_cell);
     T.mark(4, st);
     k_geometry<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_if_off, D.d_if_cell,
                                                   D.d_tags, D.d_if_psi, D.d_if_n, cap,
                                                   D.d_if_flag, D.d_info);
     T.mark(5, st);
     k_count_flags<<<(unsigned)nblk, 256, 0, st>>>(D.d_if_flag, nif, D.d_blkcnt);
-    k_scan<<<1, 1024, 0, st>>>(D.d_blkcnt, nblk, D.d_blkexcl);
+    k_scan<<<1, 1024, 0, st>>>(D.d_blkcnt, nblk, D.d_blkexcl, nullptr, nullptr);
     k_scatter_ghosts<<<(unsigned)nblk, 256, 0, st>>>(D.d_if_flag, nif, D.d_blkexcl, D.d_if_cell,
                                                      D.d_if_psi, D.d_if_n, cap, D.d_g_cell,
                                                      D.d_g_psi, D.d_g_n);
