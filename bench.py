@@ -130,6 +130,8 @@ def main():
     F = torch.empty(3, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
+    seg = []
+
     def step(record=None):
         ng_total = 0
         for sch in SCHEMES:
@@ -142,6 +144,7 @@ def main():
             plan.surface(xq, fields)
             plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
             ng_total += plan.n_ghost
+            seg.append(plan.stats()["n_band_segments"])
             del plan
         return ng_total
 
@@ -165,17 +168,21 @@ def main():
     ms_step = ms_total / args.steps
     value = ng_step / (ms_step * 1e-3)
     gcr.set_profiling(False)
+    band_segments = seg[-1]
 
-    # dominant HBM-bound kernel: classification writes the dense tag array
-    # (1 byte per cell); its duration from HIP events on the build stream
-    cls_ms = float(np.mean([r["classify"] for r in rec]))
+    # HBM-bound kernel: the classification store pass writes the dense tag
+    # array, 1 byte per cell, except the 16-cell row segments near the body
+    # that the band pass writes; its duration from HIP events recorded around
+    # the launch on the build stream
+    cls_ms = float(np.mean([r["classify_store"] for r in rec]))
     stage_ms = {k: float(np.mean([r[k] for r in rec])) for k in rec[0]}
     ncell = grid.n[0] * grid.n[1] * grid.n[2]
-    achieved = ncell / (cls_ms * 1e-3) / 1e9
+    cls_bytes = ncell - 16 * band_segments
+    achieved = cls_bytes / (cls_ms * 1e-3) / 1e9
     traffic = kernel_traffic("k_classify")
     roofline = {"bound": "hbm", "kernel": "k_classify", "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes": ncell, "avg_ms": round(cls_ms, 5)}
+                "traffic": traffic, "algorithmic_bytes": cls_bytes, "avg_ms": round(cls_ms, 5)}
 
     extras = {}
     if not args.no_extras:
@@ -366,6 +373,7 @@ def bench_large(gcr, torch, synth, reps):
     def step():
         plan = gcr.Plan(g, inst.shape, 2)
         times = gcr.last_build_times()
+        times["band_segments"] = plan.stats()["n_band_segments"]
         S, nrm = plan.foot_points()
         plan.fill(fields, kinds, list(bc_sphere_fields(S, nrm)))
         plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
@@ -384,22 +392,25 @@ def bench_large(gcr, torch, synth, reps):
         b.record()
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))
-        cls.append(times["classify"])
+        cls.append(times["classify_store"])
+        nseg = times["band_segments"]
     gcr.set_profiling(False)
     t = float(np.median(ts))
     c = float(np.median(cls))
     ncell = g.n[0] * g.n[1] * g.n[2]
+    cbytes = ncell - 16 * nseg
     del fields
     torch.cuda.empty_cache()
     return {"workload": "sphere1024: 1024^3 grid on [-1,1]^3, the headline sphere, HGC, "
                         "plan + fill of u,v,w,p + force",
             "cells": ncell, "ghosts": ng, "step_ms": round(t, 4),
             "ghost_cells_per_s": round(ng / (t * 1e-3), 1),
-            "classify_ms": round(c, 5),
-            "classify_roofline": {"bound": "hbm", "achieved": round(ncell / (c * 1e-3) / 1e9, 2),
+            "classify_store_ms": round(c, 5),
+            "classify_roofline": {"bound": "hbm", "kernel": "k_classify",
+                                  "achieved": round(cbytes / (c * 1e-3) / 1e9, 2),
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": round(ncell / (c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                  "algorithmic_bytes": ncell}}
+                                  "frac": round(cbytes / (c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "algorithmic_bytes": cbytes}}
 
 
 def cpu_baseline(inst, seconds):

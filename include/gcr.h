@@ -105,6 +105,10 @@ typedef struct {
   int32_t max_level_width;     /* largest level */
   int32_t schedule;            /* fill schedule in use, see gcr_set_schedule */
   double max_alpha[3];         /* max (x_s - x_1)/(x_2 - x_1) per axis (Sec. 8) */
+  int64_t n_band_segments;     /* 16-cell row segments whose classification needed
+                                  the exact test of every cell (near the body), in
+                                  the build that made the plan (a batch: all of its
+                                  instances) */
 } gcr_stats;
 
 /* Builds the plan of one grid + body + scheme: classification (Sec. 3.1,
@@ -252,10 +256,12 @@ gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
 /* Stage timing of plan building.  When on (process-wide), gcr_plan_create
  * and gcr_batch_create record HIP events on their stream around each stage;
  * gcr_last_build_times copies the device times in milliseconds of the last
- * build on the calling thread into ms[8]: [0] classification, [1] interface
+ * build on the calling thread into ms[11]: [0] classification, [1] interface
  * scan, [2] interface compaction, [3] geometry and ghost tags, [4] ghost
  * compaction, [5] stencils and dependencies, [6] levels and canonical order,
- * [7] finalize.  Off by default (no events recorded). */
+ * [7] finalize; [8], [9], [10] split [0] into the span pre-pass, the store
+ * pass and the exact tests near the body.  Off by default (no events
+ * recorded). */
 gcr_status gcr_set_profiling(int32_t on);
 gcr_status gcr_last_build_times(float* ms);
 

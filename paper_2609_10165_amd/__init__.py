@@ -57,7 +57,7 @@ class _Stats(ctypes.Structure):
                 ("n_ghost", ctypes.c_int64), ("n_ghost_fluid_side", ctypes.c_int64),
                 ("n_units_coupled", ctypes.c_int32), ("max_unit", ctypes.c_int32),
                 ("max_level_width", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("max_alpha", ctypes.c_double * 3)]
+                ("max_alpha", ctypes.c_double * 3), ("n_band_segments", ctypes.c_int64)]
 
 
 _lib = None
@@ -347,7 +347,8 @@ class Batch:
 
 
 STAGES = ["classify", "interface_scan", "interface_compact", "geometry_tags",
-          "ghost_compact", "dependencies", "levels_order", "finalize"]
+          "ghost_compact", "dependencies", "levels_order", "finalize",
+          "classify_prepass", "classify_store", "classify_band"]
 
 
 def set_profiling(on: bool):
@@ -355,7 +356,7 @@ def set_profiling(on: bool):
 
 
 def last_build_times() -> dict:
-    buf = (ctypes.c_float * 8)()
+    buf = (ctypes.c_float * len(STAGES))()
     _check(lib().gcr_last_build_times(buf), "gcr_last_build_times")
     return dict(zip(STAGES, list(buf)))
 

@@ -430,6 +430,7 @@ gcr_status gcr_plan_stats(const gcr_plan* p, gcr_stats* out) {
   out->max_unit = p->info.maxunit;
   out->max_level_width = p->info.maxwidth;
   out->schedule = p->schedule != kSchedAuto ? p->schedule : (p->tuned < 0 ? 0 : p->tuned);
+  out->n_band_segments = p->batch ? p->batch->nband : 0;
   for (int a = 0; a < 3; ++a) {
     unsigned long long b = p->info.max_alpha_bits[a];
     double v;

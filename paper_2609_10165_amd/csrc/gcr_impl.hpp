@@ -14,6 +14,9 @@
 
 namespace gcr {
 
+constexpr int kStages = 11;   // plan-build stages timed by gcr_last_build_times
+
+
 // Per-instance results of plan building, written by the device.
 struct InstInfo {
   uint32_t err;
@@ -58,6 +61,7 @@ T* palloc(size_t n) {
 struct BatchData {
   int ninst = 0;
   int64_t ncells_total = 0, nchunks = 0, nif = 0, cap = 0, ng_total = 0;
+  int64_t nband = 0;                 // row segments tested by the band pass
   std::vector<Inst> inst;            // host copies
   std::vector<int64_t> if_off, g_off;  // host [ninst+1]
   std::vector<InstInfo> info;        // host [ninst]

@@ -1172,10 +1172,10 @@ static inline unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1
 
 // stage timing (process-wide switch, per-thread results)
 static std::atomic<int> g_profiling{0};
-static thread_local float g_stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+static thread_local float g_stage_ms[kStages] = {};
 
 struct StageEvents {
-  hipEvent_t ev[10] = {};
+  hipEvent_t ev[12] = {};
   bool on = false;
   explicit StageEvents(bool enable) : on(enable) {
     if (on)
@@ -1187,8 +1187,11 @@ struct StageEvents {
   }
   void collect() {
     if (!on) return;
-    const int a[8] = {0, 1, 3, 4, 5, 6, 7, 8}, b[8] = {1, 2, 4, 5, 6, 7, 8, 9};
-    for (int s = 0; s < 8; ++s) {
+    // stages 0..7 as documented; 8..10 split stage 0 into the span pre-pass,
+    // the store pass (k_classify) and the band tests (k_band)
+    const int a[kStages] = {0, 1, 3, 4, 5, 6, 7, 8, 0, 10, 11};
+    const int b[kStages] = {1, 2, 4, 5, 6, 7, 8, 9, 10, 11, 1};
+    for (int s = 0; s < kStages; ++s) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[a[s]], ev[b[s]]) != hipSuccess) ms = -1.f;
       g_stage_ms[s] = ms;
@@ -1202,7 +1205,7 @@ struct StageEvents {
 
 void set_profiling(int on) { g_profiling.store(on ? 1 : 0); }
 void last_build_times(float* ms) {
-  for (int s = 0; s < 8; ++s) ms[s] = g_stage_ms[s];
+  for (int s = 0; s < kStages; ++s) ms[s] = g_stage_ms[s];
 }
 
 gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes,
@@ -1260,7 +1263,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   const size_t o_info = o_go + al(8 * (ninst + 1)), o_lo = o_info + al(sizeof(InstInfo) * ninst);
   const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
   const size_t o_nl = o_ul + al(4 * (size_t)ninst * kMaxUnits);
-  const size_t stage_bytes = o_nl + al(4);
+  const size_t stage_bytes = o_nl + al(8);
   PinnedStage PS;
   PS.st = st;
   PS.p = (char*)pinned_alloc(stage_bytes);
@@ -1281,8 +1284,10 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                                                  D.d_span);
   }
   k_zero32<<<1, 64, 0, st>>>(D.d_nband, 1);
+  T.mark(10, st);
   k_classify<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_span,
                                                 D.d_tags, D.d_chunk_cnt, D.d_band, D.d_nband);
+  T.mark(11, st);
   k_band<<<kBandWaves, 64, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_band, D.d_nband,
                                     D.d_tags, D.d_chunk_cnt);
   T.mark(1, st);
@@ -1297,10 +1302,13 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                          hipMemcpyDeviceToHost, st));
   GCR_HIP(hipMemcpyAsync(PS.p + o_nl, D.d_nchunk_list, sizeof(int32_t), hipMemcpyDeviceToHost,
                          st));
+  GCR_HIP(hipMemcpyAsync(PS.p + o_nl + 4, D.d_nband, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   GCR_HIP(hipStreamSynchronize(st));
   std::memcpy(D.if_off.data(), PS.p + o_if, 8 * (ninst + 1));
-  int32_t nlist = 0;
+  int32_t nlist = 0, nband = 0;
   std::memcpy(&nlist, PS.p + o_nl, sizeof(int32_t));
+  std::memcpy(&nband, PS.p + o_nl + 4, sizeof(int32_t));
+  D.nband = nband;
   const int64_t nif = D.if_off[ninst];
   const int64_t cap = std::max<int64_t>(nif, 1);
   D.nif = nif;
