@@ -265,6 +265,15 @@ gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
 gcr_status gcr_set_profiling(int32_t on);
 gcr_status gcr_last_build_times(float* ms);
 
+/* Layering (Sec. 3.2) of a plan built alone: an instance with at least
+ * `min_interface` interface cells is layered by the whole GPU (one grid-wide
+ * round per level, then a stable counting sort by level); smaller ones, and
+ * every instance of a batch, by one workgroup.  A cycle or a graph deeper
+ * than 126 levels hands the instance to the one-workgroup layering, so the
+ * result never depends on this setting.  0 restores the default (65536).
+ * Process-wide; applies to plans built afterwards. */
+gcr_status gcr_set_wide_layering(int64_t min_interface);
+
 const char* gcr_status_str(gcr_status s);
 const char* gcr_version(void);
 

@@ -26,7 +26,7 @@ SYMBOLS = [
     "gcr_plan_export", "gcr_plan_foot_points", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_forward",
-    "gcr_set_profiling", "gcr_last_build_times", "gcr_status_str", "gcr_version",
+    "gcr_set_profiling", "gcr_last_build_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
         L.gcr_batch_destroy.restype = None
         L.gcr_batch_plan.argtypes = [vp, i32, P(vp)]
         L.gcr_set_profiling.argtypes = [i32]
+        L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_last_build_times.argtypes = [vp]
         L.gcr_batch_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl,
                                         vp, vp]
@@ -349,6 +350,12 @@ class Batch:
 STAGES = ["classify", "interface_scan", "interface_compact", "geometry_tags",
           "ghost_compact", "dependencies", "levels_order", "finalize",
           "classify_prepass", "classify_store", "classify_band"]
+
+
+def set_wide_layering(min_interface: int = 0):
+    """Interface-cell count from which a plan built alone is layered by the
+    whole GPU (0: the default)."""
+    _check(lib().gcr_set_wide_layering(int(min_interface)), "gcr_set_wide_layering")
 
 
 def set_profiling(on: bool):

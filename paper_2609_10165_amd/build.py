@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libgcr.so")
-SOURCES = ["plan.hip", "levels.hip", "apply.hip", "adjoint.hip", "batch.hip", "capi.hip"]
+SOURCES = ["classify.hip", "plan.hip", "levels.hip", "apply.hip", "adjoint.hip", "batch.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

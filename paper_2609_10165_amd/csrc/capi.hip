@@ -604,6 +604,12 @@ gcr_status gcr_set_profiling(int32_t on) {
   return GCR_OK;
 }
 
+gcr_status gcr_set_wide_layering(int64_t min_interface) {
+  if (min_interface < 0) return GCR_E_ARG;
+  set_wide_layering(min_interface);
+  return GCR_OK;
+}
+
 gcr_status gcr_last_build_times(float* ms) {
   if (!ms) return GCR_E_ARG;
   last_build_times(ms);

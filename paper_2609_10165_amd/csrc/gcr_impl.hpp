@@ -150,8 +150,35 @@ struct LevelsArgs {
   uint32_t* cnt;
   uint32_t* bits;
   InstInfo* info;
+  // wide layering of a single large instance (null: not used)
+  int32_t* listB;        // [cap] second level list
+  int32_t* wide;         // [kWideState] completion flag, sizes of the levels
+  int32_t* hist;         // [kWideLevels][cap / 256 + 1] per-tile level counts
 };
+constexpr int kWideLevels = 128;               // deepest graph the wide layering orders
+constexpr int kWideState = kWideLevels + 8;
+constexpr int64_t kWideMinInterface = 65536;   // default; smaller instances: one workgroup
+void set_wide_layering(int64_t min_interface);   // 0: the default
+int64_t wide_layering_min();
 gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
+
+// Classification of every cell of a batch into tags (0 fluid, 1 solid, 0x40
+// interface mark) and per-chunk interface counts.  ev_prepass / ev_store
+// (either may be null) are recorded after the span pre-pass and after the
+// store pass.
+void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
+                     int8_t* span, int8_t* tags, int32_t* chunk_cnt, int32_t* band,
+                     int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store, hipStream_t st);
+
+// instance holding global index x of a batch: the last i with off[i] <= x
+__device__ __forceinline__ int find_inst(const int64_t* off, int ninst, int64_t x) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Schedule of the fill.
 enum { kSchedAuto = 0, kSchedLevels = 1, kSchedWorkgroup = 2, kSchedGraph = 3 };

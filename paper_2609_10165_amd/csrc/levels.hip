@@ -18,6 +18,15 @@
 // the remaining graph) become coupled units, and the layering restarts with
 // each unit as one node, so a unit sits one level above the deepest level it
 // needs.
+//
+// A single large instance is layered by the whole grid instead
+// (k_levels_wide): one cooperative launch whose rounds each release the next
+// level from the current one through the same counters (in HBM), with a grid
+// barrier between rounds; the canonical order then comes from a stable
+// counting sort of the ghosts by level.  A stall there (a cycle) or a graph
+// deeper than the sort supports hands the instance to the one-workgroup
+// layering, launched right after, which otherwise returns at once.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "gcr_impl.hpp"
@@ -48,9 +57,169 @@ __device__ __forceinline__ uint32_t cnt_get(const uint32_t* c, int i) {
   return (c[i >> 2] >> ((i & 3) * 8)) & 0xffu;
 }
 
+// Appends v to list (size counter *size) for the lanes with p set: one
+// atomic per wave.  Lanes may be diverged; only active lanes take part.
+__device__ __forceinline__ void wave_push(bool p, int v, int32_t* list, int32_t* size) {
+  const unsigned long long m = __ballot(p);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(size, __popcll(m));
+  base = __shfl(base, leader);
+  if (p) list[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+// Wide layering of instance 0.  wide[0] = 1 when it finished (levels,
+// canonical order, level offsets and info final), wide[r] = size of level r.
+__global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const int tid = threadIdx.x;
+  const int G = (int)gridDim.x;
+  const int64_t GT = (int64_t)G * 256;
+  const int64_t gt = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t lo = L.g_off[0];
+  const int n = (int)(L.g_off[1] - lo);
+  const int C = (n + 3) >> 2;
+  uint32_t* __restrict__ cnt = L.cnt;
+  int32_t* __restrict__ lev = L.lev + lo;
+  int32_t* __restrict__ perm = L.perm + lo;
+  const uint8_t* __restrict__ dcnt = L.dcnt + lo;
+  const int32_t* __restrict__ roff = L.roff + lo;
+  const int32_t* __restrict__ radj = L.radj;
+  int32_t* __restrict__ size = L.wide;
+  int32_t* lists[2] = {L.listA + lo, L.listB + lo};
+  __shared__ int64_t sh[8];
+  __shared__ int s_hist[kWideLevels];
+  __shared__ int s_wc[4][kWideLevels];
+
+  // counters of ghosts read, four per word; no ghost is in a unit
+  for (int64_t w = gt; w < C; w += GT) {
+    uint32_t v = 0;
+    for (int q = 0; q < 4; ++q)
+      if (4 * w + q < n) v |= (uint32_t)dcnt[4 * w + q] << (8 * q);
+    cnt[w] = v;
+  }
+  for (int64_t g = gt; g < n; g += GT) L.blk_idx[lo + g] = -1;
+  if (blockIdx.x == 0)
+    for (int r = tid; r < kWideState; r += 256) size[r] = 0;
+  grid.sync();
+  // level 1: ghosts that read no ghost
+  for (int64_t g0 = (int64_t)blockIdx.x * 256; g0 < n; g0 += GT) {
+    const int g = (int)(g0 + tid);
+    const bool p = g < n && dcnt[g] == 0;
+    if (p) lev[g] = 1;
+    wave_push(p, g, lists[1], &size[1]);
+  }
+  grid.sync();
+
+  // round r: the dependants of level r whose last counted edge comes from it
+  // form level r + 1
+  int r = 1, placed = 0, maxw = 0;
+  bool ok = true;
+  for (;;) {
+    const int sz = __hip_atomic_load(&size[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (sz == 0) break;
+    placed += sz;
+    maxw = max(maxw, sz);
+    if (r == kWideLevels - 1) {
+      ok = false;
+      break;
+    }
+    const int32_t* __restrict__ cur = lists[r & 1];
+    int32_t* __restrict__ nxt = lists[(r + 1) & 1];
+    for (int64_t i = gt; i < sz; i += GT) {
+      const int g = cur[i];
+      const int e1 = roff[g + 1];
+      for (int e = roff[g]; e < e1; ++e) {
+        const int q = (int)(radj[e] - lo);
+        const bool rel = cnt_dec(cnt, q) == 1u;
+        if (rel) lev[q] = r + 1;
+        wave_push(rel, q, nxt, &size[r + 1]);
+      }
+    }
+    ++r;
+    grid.sync();
+  }
+  if (!ok || placed != n) return;   // every workgroup leaves here alike
+  const int nlev = r - 1;
+  const int ntiles = (n + 255) >> 8;
+  int32_t* __restrict__ hist = L.hist;   // [level][tile]
+
+  // stable counting sort by level: per-tile counts ...
+  for (int t = blockIdx.x; t < ntiles; t += G) {
+    for (int l = tid; l < nlev; l += 256) s_hist[l] = 0;
+    __syncthreads();
+    const int g = t * 256 + tid;
+    if (g < n) atomicAdd(&s_hist[lev[g] - 1], 1);
+    __syncthreads();
+    for (int l = tid; l < nlev; l += 256) hist[(int64_t)l * ntiles + t] = s_hist[l];
+    __syncthreads();
+  }
+  grid.sync();
+  // ... scanned over the tiles of each level, plus the level offsets ...
+  for (int l = blockIdx.x; l < nlev; l += G) {
+    int32_t* row = hist + (int64_t)l * ntiles;
+    int64_t carry = 0;
+    for (int t0 = 0; t0 < ntiles; t0 += 256) {
+      const int t = t0 + tid;
+      const int v = t < ntiles ? row[t] : 0;
+      int64_t tot;
+      const int64_t pre = block_excl_scan<256>(v, &tot, sh);
+      if (t < ntiles) row[t] = (int32_t)(carry + pre);
+      carry += tot;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    int32_t* lev_off = L.lev_off;
+    int run = 0;
+    lev_off[0] = 0;
+    for (int k = 1; k <= nlev; ++k) {
+      run += size[k];
+      lev_off[k] = run;
+    }
+    L.info[0].nlev = nlev;
+    L.info[0].maxwidth = maxw;
+    L.info[0].nunits = 0;
+    L.info[0].maxunit = 0;
+    size[0] = 1;
+  }
+  grid.sync();
+  // ... and each ghost's rank among the same level's ghosts before it
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int t = blockIdx.x; t < ntiles; t += G) {
+    for (int i = tid; i < 4 * nlev; i += 256) s_wc[i / nlev][i % nlev] = 0;
+    __syncthreads();
+    const int g = t * 256 + tid;
+    const bool valid = g < n;
+    const int l = valid ? lev[g] - 1 : -1;
+    unsigned long long rem = __ballot(valid);
+    int inw = 0;
+    while (rem) {
+      const int leader = __ffsll((long long)rem) - 1;
+      const int l0 = __shfl(l, leader);
+      const bool same = valid && l == l0;
+      const unsigned long long m = __ballot(same);
+      if (same) inw = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == leader) s_wc[wv][l0] = __popcll(m);
+      rem &= ~m;
+    }
+    __syncthreads();
+    if (valid) {
+      int pos = L.lev_off[l] + hist[(int64_t)l * ntiles + t] + inw;
+      for (int w = 0; w < wv; ++w) pos += s_wc[w][l];
+      perm[g] = pos;
+    }
+    __syncthreads();
+  }
+}
+
 template <bool InLds>
 __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   extern __shared__ uint32_t s_dyn[];
+  // after a finished wide layering there is nothing left to do
+  if (L.wide && L.wide[0] == 1) return;
   const int ii = blockIdx.x;
   const int tid = threadIdx.x;
   const int np = (1 << L.insts[ii].g.dim) - 1;
@@ -351,6 +520,31 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
   }
   const int64_t nn = std::max<int64_t>(max_n, 1);
   const int64_t bytes = 4 * (((nn + 3) >> 2) + ((nn + 31) >> 5));
+  LevelsArgs F = L;   // the one-workgroup layering
+  F.wide = nullptr;
+  if (L.wide && ninst == 1) {
+    // grid: as many co-resident workgroups as fit, at most one per tile
+    static int coop = -1;
+    if (coop < 0) {
+      int dev = 0, ncu = 0, per = 0;
+      (void)hipGetDevice(&dev);
+      if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &per, reinterpret_cast<const void*>(&k_levels_wide), 256, 0) != hipSuccess)
+        per = 0;
+      (void)hipGetLastError();
+      coop = std::max(0, std::min(per, 1) * ncu);
+    }
+    const int64_t G = std::min<int64_t>(coop, std::max<int64_t>(1, (nn + 255) >> 8));
+    if (G > 0) {
+      LevelsArgs A = L;
+      void* args[] = {&A};
+      GCR_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_levels_wide),
+                                         dim3((unsigned)G), dim3(256), args, 0, st));
+      F.wide = L.wide;
+    }
+  }
   if (bytes <= lds_max) {
     static int64_t attr = 0;
     if (bytes > attr) {
@@ -358,9 +552,9 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
       attr = bytes;
     }
-    k_levels<true><<<ninst, 1024, (size_t)bytes, st>>>(L);
+    k_levels<true><<<ninst, 1024, (size_t)bytes, st>>>(F);
   } else {
-    k_levels<false><<<ninst, 1024, 0, st>>>(L);
+    k_levels<false><<<ninst, 1024, 0, st>>>(F);
   }
   GCR_HIP(hipGetLastError());
   return GCR_OK;

@@ -186,6 +186,52 @@ def test_plan_airfoil(gcr):
     check_plan(op, gp)
 
 
+@pytest.fixture
+def wide(gcr):
+    gcr.set_wide_layering(1)   # every plan built alone is layered grid-wide
+    yield
+    gcr.set_wide_layering(0)
+
+
+def _layering_case(case):
+    if case == "circle128":
+        return synth.circle128(seed=3), HGC
+    if case == "sphere_ragged":
+        h = 2.0 / 61
+        grid = synth.Grid(3, (61, 53, 47), (-1.0, -0.9, -0.8), (h, h, h))
+        shape = synth.Shape(synth.SPHERE, (0.013, -0.02, 0.007), 0.41)
+        return synth.Instance("sphere_ragged", grid, shape, CGC, synth.abc_fields()), CGC
+    if case == "sphere256":
+        return synth.sphere256(seed=0, scheme=CGC_ES), CGC_ES
+    if case == "star_unit":
+        # a coupled unit: the grid-wide rounds stall and the one-workgroup
+        # layering takes over
+        return synth.stars64(seed=0, ninst=1, nmin=96, nmax=160)[0], CGC
+    if case == "shstar":
+        return synth.shstar384(seed=0, n=96, nt=4, nph=8), HGC
+    return synth.airfoil4096(seed=0, n=1024, m=64), HGC
+
+
+@pytest.mark.parametrize("case", ["circle128", "sphere_ragged", "sphere256", "star_unit",
+                                  "shstar", "airfoil"])
+def test_wide_layering_matches_oracle(gcr, wide, case):
+    inst, scheme = _layering_case(case)
+    op, gp = plan_pair(gcr, inst, scheme)
+    if case == "star_unit":
+        assert op.n_units_coupled >= 1
+    check_plan(op, gp, strict_geometry=case in ("circle128", "sphere_ragged", "sphere256"))
+    run_fill(gcr, op, gp, inst, (list(inst.fields) * 2)[:2], [DIRICHLET, NEUMANN])
+
+
+def test_plan_shstar384_full_size(gcr):
+    # above the default size for grid-wide layering
+    inst = synth.shstar384(seed=0)
+    op, gp = plan_pair(gcr, inst, HGC)
+    assert op.n_interface >= 65536
+    assert op.min_margin > 1e-9
+    check_plan(op, gp)
+
+
 # ---------------------------------------------------------------------------
 # fill
 # ---------------------------------------------------------------------------
