@@ -2,13 +2,15 @@
 
 One step = the whole path on a 256^3 grid cut by a sphere (R = 0.3,
 sub-cell offset) with four FP64 fields (u, v, w Dirichlet; p Neumann), for
-each of the three ghost schemes (CGC, CGC_ES, HGC):
-  plan (classification, tags, geometry, dependency levels, canonical order)
+each of the three ghost schemes (CGC, CGC_ES, HGC), the three built and
+applied as one batch:
+  plans (classification, tags, geometry, dependency levels, canonical order)
   -> foot points and boundary data there (caller side, torch)
-  -> level-by-level fill of the 4 fields
-  -> boundary values and gradients at 2048 surface points
-  -> pressure + viscous force.
+  -> level-by-level fill of the 4 fields and the pressure + viscous force
+     (one persistent launch for all schemes and fields)
+  -> boundary values and gradients at 2048 surface points.
 Metric: ghost cells per second (sum of the three plans' ghosts per step).
+The same step done one plan at a time is timed beside it (plain_step).
 
 Side measurements on the same GPU (reported beside the headline, never as
 `value`):
@@ -84,10 +86,11 @@ def _dev(torch, a, dtype=None):
     return torch.tensor(a, dtype=dtype, device="cuda")
 
 
-def kernel_traffic(name):
-    """HBM bytes per launch of `name` from the committed byte-counter summary,
-    or None when the summary is absent or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+def kernel_traffic(name, workload):
+    """HBM bytes per launch of kernel `name` on `workload` from the committed
+    byte-counter summary, or None when it is absent or the kernel's sources
+    changed since."""
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -123,28 +126,52 @@ def main():
     inst = synth.sphere256(seed=0)
     grid, shape = inst.grid, inst.shape
     kinds = [DIRICHLET, DIRICHLET, DIRICHLET, NEUMANN]
-    # inputs resident in HBM before timing
-    fields = [_dev(torch, synth.sample(f, grid), torch.float64) for f in inst.fields]
+    # inputs resident in HBM before timing: one copy of the 4 fields per
+    # scheme (each scheme overwrites its own ghost cells, and HGC's include
+    # fluid cells that the other schemes read)
+    base = [_dev(torch, synth.sample(f, grid), torch.float64) for f in inst.fields]
+    fieldsets = [[f.clone() for f in base] for _ in SCHEMES]
     q = inst.queries
     xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
+    nqp = xq.shape[1]
+    F3 = torch.zeros((len(SCHEMES), 3), dtype=torch.float64, device=dev)
     F = torch.empty(3, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-
     seg = []
 
     def step(record=None):
+        """The three schemes as one batch: shared build launches, boundary
+        data for all foot points at once, fill + force of every (scheme,
+        field) in one persistent launch, then the surface values."""
+        B = gcr.Batch([grid] * len(SCHEMES), [shape] * len(SCHEMES), list(SCHEMES))
+        if record is not None:
+            record.append(gcr.last_build_times())
+        fp = [p.foot_points() for p in B.plans]
+        bc = bc_sphere_fields(torch.cat([x[0] for x in fp], dim=1),
+                              torch.cat([x[1] for x in fp], dim=1))
+        bcv, off = [], 0
+        for p in B.plans:
+            bcv += [bc[f, off:off + p.n_ghost] for f in range(4)]
+            off += p.n_ghost
+        B.forward(4, [f for fs in fieldsets for f in fs], kinds, bcv, nq=[nqp] * len(SCHEMES),
+                  xq=[xq] * len(SCHEMES), nrm=[nq] * len(SCHEMES), wq=[wq] * len(SCHEMES),
+                  p_field=3, u_first=0, mu=1.0, F=F3)
+        for p, fs in zip(B.plans, fieldsets):
+            p.surface(xq, fs)
+        seg.append(B.plans[0].stats()["n_band_segments"])
+        return off
+
+    def step_plain():
+        """The same work one plan at a time: per-plan build, per-level fill
+        launches, one surface and one force launch per scheme."""
         ng_total = 0
-        for sch in SCHEMES:
+        for sch, fs in zip(SCHEMES, fieldsets):
             plan = gcr.Plan(grid, shape, sch)
-            if record is not None:
-                record.append(gcr.last_build_times())
             S, nrm = plan.foot_points()
-            bc = bc_sphere_fields(S, nrm)
-            plan.fill(fields, kinds, list(bc))
-            plan.surface(xq, fields)
-            plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
+            plan.fill(fs, kinds, list(bc_sphere_fields(S, nrm)))
+            plan.surface(xq, fs)
+            plan.forces(xq, nq, wq, fs[3], fs[:3], 1.0, out=F)
             ng_total += plan.n_ghost
-            seg.append(plan.stats()["n_band_segments"])
             del plan
         return ng_total
 
@@ -170,19 +197,34 @@ def main():
     gcr.set_profiling(False)
     band_segments = seg[-1]
 
+    # plain per-plan form of the same step, for comparison
+    for _ in range(2):
+        step_plain()
+    torch.cuda.synchronize()
+    plain_reps = max(3, args.steps // 2)
+    t0.record(stream)
+    for _ in range(plain_reps):
+        ng_plain = step_plain()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = t0.elapsed_time(t1) / plain_reps
+
     # HBM-bound kernel: the classification store pass writes the dense tag
-    # array, 1 byte per cell, except the 16-cell row segments near the body
-    # that the band pass writes; its duration from HIP events recorded around
-    # the launch on the build stream
+    # array, 1 byte per cell of the three instances, except the 16-cell row
+    # segments near the body that the band pass writes; its duration from
+    # HIP events recorded around the launch on the build stream
     cls_ms = float(np.mean([r["classify_store"] for r in rec]))
     stage_ms = {k: float(np.mean([r[k] for r in rec])) for k in rec[0]}
     ncell = grid.n[0] * grid.n[1] * grid.n[2]
-    cls_bytes = ncell - 16 * band_segments
+    cls_bytes = len(SCHEMES) * ncell - 16 * band_segments
     achieved = cls_bytes / (cls_ms * 1e-3) / 1e9
-    traffic = kernel_traffic("k_classify")
+    traffic = kernel_traffic("k_classify", "sphere256x3")
     roofline = {"bound": "hbm", "kernel": "k_classify", "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes": cls_bytes, "avg_ms": round(cls_ms, 5)}
+    plain = {"ms_per_step": round(ms_plain, 4), "ghosts_per_step": ng_plain,
+             "ghost_cells_per_s": round(ng_plain / (ms_plain * 1e-3), 1),
+             "batched_speedup": round(ms_plain / ms_step, 3)}
 
     extras = {}
     if not args.no_extras:
@@ -204,9 +246,10 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "sphere256: 256^3 grid on [-1,1]^3, sphere R=0.3 at sub-cell "
                                "offset, 4 FP64 fields (u,v,w Dirichlet, p Neumann), "
-                               "CGC + CGC_ES + HGC per step, 2048 surface points",
+                               "CGC + CGC_ES + HGC per step as one batch, 2048 surface points",
                    "ghosts_per_step": ng_step, "cells": ncell},
         "roofline": roofline,
+        "plain_step": plain,
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "wall_s": round(wall, 3),
         **extras,

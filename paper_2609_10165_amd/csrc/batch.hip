@@ -10,11 +10,15 @@
 // which sum over the fields to w (-p n + mu (grad u + grad u^T) n).  The
 // last item of an instance to finish (device-scope counter, reset after use)
 // adds the shares in field order, so the result does not depend on timing.
-// Workgroup size and grid are picked by timing candidates on first use.
+// Workgroup size and grid are picked by timing candidates on the first
+// call for a kind of batch and remembered for the process.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <numeric>
 #include <vector>
 
@@ -41,7 +45,33 @@ struct BCall {
   const double* const* nrm;
   const double* const* wq;
   const int32_t* order;          // [nitems] items w = i*nf + f
+  const int64_t* aoff;           // [ninst + 1] first point of each instance (forces)
+  const int32_t* anchor;         // [aoff[ninst]] anchor ghost of every point
 };
+
+// Anchor ghost of every surface point of every instance, one group of lanes
+// per point (the search is geometry only, so the fields' items share it).
+template <int D>
+__global__ __launch_bounds__(256) void k_batch_anchor(BStatic S, BCall C, int64_t npts,
+                                                      int32_t* __restrict__ anchor) {
+  constexpr int NL = anchor_lanes<D>();
+  constexpr int PPB = 256 / NL;
+  const int sub = (int)threadIdx.x % NL;
+  const int64_t gq = (int64_t)blockIdx.x * PPB + (int)threadIdx.x / NL;
+  const bool active = gq < npts;
+  int i = 0;
+  int64_t q = 0;
+  double x[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    i = find_inst(C.aoff, C.ninst, gq);
+    q = gq - C.aoff[i];
+    const int64_t nq = C.nq[i];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = C.xq[i][a * nq + q];
+  }
+  const int g = find_anchor_group<D, NL>(S.plans[i], x, sub, active);
+  if (active && sub == 0) anchor[gq] = g;
+}
 
 template <int D>
 __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, double* __restrict__ part,
@@ -87,7 +117,7 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
           x[a] = xq[a * nq + q];
           n[a] = nr[a * nq + q];
         }
-        const int g = find_anchor<D>(P, x);
+        const int g = C.anchor[C.aoff[i] + q];
         double val, gr[3];
         if (g < 0) {
           val = __longlong_as_double(0x7ff8000000000000LL);
@@ -150,10 +180,14 @@ struct BatchFwdState {
   size_t part_cap = 0;
   char* d_call = nullptr;
   size_t call_cap = 0;
+  int32_t* d_anchor = nullptr;
+  size_t anchor_cap = 0;
   int threads = 0, grid_mul = 0;   // tuned
   std::vector<void*> owned;
   ~BatchFwdState() {
     for (void* p : owned) pool_free(p);
+    for (void* p : {(void*)d_part, (void*)d_call, (void*)d_anchor})
+      if (p) pool_free(p);
   }
 };
 
@@ -162,6 +196,8 @@ struct BatchFwdState {
 using namespace gcr;
 
 namespace {
+std::mutex g_shape_mu;
+std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_shape;
 std::mutex g_bfs_mu;
 std::vector<std::pair<const gcr_batch*, std::unique_ptr<BatchFwdState>>> g_bfs;
 
@@ -189,10 +225,11 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
     *err = GCR_E_NOMEM;
     return nullptr;
   }
+  // pageable sources: each copy has consumed its source when it returns
   if (hipMemcpyAsync(S->d_plans, pv.data(), sizeof(PlanD) * n, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(S->d_levp, lp.data(), sizeof(int32_t*) * n, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(S->d_nlev, nl.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) ||
-      hipMemsetAsync(S->d_counter, 0, sizeof(int) * n, st) || hipStreamSynchronize(st)) {
+      hipMemsetAsync(S->d_counter, 0, sizeof(int) * n, st)) {
     *err = GCR_E_HIP;
     return nullptr;
   }
@@ -259,7 +296,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   // call table: one upload
   const size_t np = (size_t)nitems;
-  const size_t bytes = sizeof(void*) * (3 * np + 3 * n) + sizeof(int64_t) * n +
+  const size_t bytes = sizeof(void*) * (3 * np + 3 * n) + sizeof(int64_t) * (2 * n + 1) +
                        sizeof(int32_t) * np + 64;
   std::vector<char> host(bytes, 0);
   char* h = host.data();
@@ -276,12 +313,22 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   const size_t o_fields = put(fields, sizeof(void*) * np);
   const size_t o_bcv = put(bc_val, sizeof(void*) * np);
   const size_t o_bct = put(bt.data(), sizeof(void*) * np);
-  size_t o_nq = 0, o_xq = 0, o_nrm = 0, o_wq = 0;
+  size_t o_nq = 0, o_xq = 0, o_nrm = 0, o_wq = 0, o_aoff = 0;
+  std::vector<int64_t> aoff(n + 1, 0);
   if (nq) {
+    for (int i = 0; i < n; ++i) aoff[i + 1] = aoff[i] + nq[i];
     o_nq = put(nq, sizeof(int64_t) * n);
     o_xq = put(xq, sizeof(void*) * n);
     o_nrm = put(nrm, sizeof(void*) * n);
     o_wq = put(wq, sizeof(void*) * n);
+    o_aoff = put(aoff.data(), sizeof(int64_t) * (n + 1));
+  }
+  const int64_t npts = aoff[n];
+  if (npts > 0 && S->anchor_cap < (size_t)npts) {
+    if (S->d_anchor) pool_free(S->d_anchor);
+    S->d_anchor = static_cast<int32_t*>(pool_alloc(sizeof(int32_t) * npts));
+    S->anchor_cap = S->d_anchor ? (size_t)npts : 0;
+    if (!S->d_anchor) return GCR_E_NOMEM;
   }
   const size_t o_order = put(order.data(), sizeof(int32_t) * np);
   if (S->call_cap < o) {
@@ -315,12 +362,50 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   C.nrm = nq ? reinterpret_cast<const double* const*>(d + o_nrm) : nullptr;
   C.wq = nq ? reinterpret_cast<const double* const*>(d + o_wq) : nullptr;
   C.order = reinterpret_cast<const int32_t*>(d + o_order);
+  C.aoff = nq ? reinterpret_cast<const int64_t*>(d + o_aoff) : nullptr;
+  C.anchor = S->d_anchor;
+  if (npts > 0) {
+    BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
+    if (dim == 2) {
+      constexpr int ppb = 256 / anchor_lanes<2>();
+      k_batch_anchor<2><<<(unsigned)((npts + ppb - 1) / ppb), 256, 0, st>>>(bs, C, npts,
+                                                                           S->d_anchor);
+    } else {
+      constexpr int ppb = 256 / anchor_lanes<3>();
+      k_batch_anchor<3><<<(unsigned)((npts + ppb - 1) / ppb), 256, 0, st>>>(bs, C, npts,
+                                                                           S->d_anchor);
+    }
+    GCR_HIP(hipGetLastError());
+  }
   double* Fo = F;
   double* Fdummy = nullptr;
   if (!nq) {
     Fdummy = static_cast<double*>(plan_scratch(batch->plans[0].get(), 5, sizeof(double) * 3 * n));
     if (!Fdummy) return GCR_E_NOMEM;
     Fo = Fdummy;
+  }
+  // the tuned launch shape of batches like this one (dimension, fields,
+  // forces or not, and power-of-two buckets of items, ghosts and levels)
+  int64_t max_ng = 0;
+  int max_lev = 0;
+  for (int i = 0; i < n; ++i) {
+    max_ng = std::max<int64_t>(max_ng, batch->plans[i]->ng);
+    max_lev = std::max(max_lev, batch->plans[i]->nlev);
+  }
+  auto bucket = [](int64_t v) {
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+  };
+  const auto key = std::make_tuple(dim, nf, nq ? 1 : 0, bucket(nitems), bucket(max_ng),
+                                   bucket(max_lev));
+  if (S->threads == 0) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    auto it = g_shape.find(key);
+    if (it != g_shape.end()) {
+      S->threads = it->second.first;
+      S->grid_mul = it->second.second;
+    }
   }
   if (S->threads == 0) {
     // tuner: workgroup size x grid size, timed on the caller's data (the
@@ -335,6 +420,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     for (int tt : cand_t)
       for (int gm : cand_g) {
         const int grid = std::min(nitems, 256 * gm);
+        if (gm > 1 && grid == std::min(nitems, 256 * (gm / 4))) continue;   // same shape
         gcr_status s = launch_batch(S, C, dim, tt, grid, Fo, st);
         if (s != GCR_OK) return s;
         GCR_HIP(hipEventRecord(e0, st));
@@ -353,6 +439,8 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     (void)hipEventDestroy(e1);
     S->threads = bt_;
     S->grid_mul = bg;
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape[key] = {bt_, bg};
   }
   return launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
 }

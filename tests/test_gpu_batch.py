@@ -144,3 +144,69 @@ def test_batch_forward_full_size_sampled(gcr):
             got = host(fields[k * nf + f])
             err = np.abs(got[op.ghost_cell] - want[f][op.ghost_cell])
             assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][op.ghost_cell]), sc[f]))
+
+
+def test_batch_three_schemes_sphere256_full_size(gcr):
+    """The benchmark step's configuration: the 256^3 sphere with CGC, CGC_ES
+    and HGC built as one batch, u, v, w (Dirichlet) and p (Neumann) filled
+    with the force in one persistent launch, then surface values and
+    gradients per plan; every scheme against the oracle at full size."""
+    from synth import CGC, CGC_ES
+    inst = synth.sphere256(seed=0)
+    g = inst.grid
+    schemes = [CGC, CGC_ES, HGC]
+    kinds = [f.bc for f in inst.fields]
+    B = gcr.Batch([g] * 3, [inst.shape] * 3, schemes)
+    ops, fields, bcv, wants, vals_in = [], [], [], [], []
+    for sch, plan in zip(schemes, B.plans):
+        op = oracle.OraclePlan(g, inst.shape, sch)
+        ops.append(op)
+        ex = plan.export(("tags", "cell", "level"))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ex["tags"]), op.tags), sch
+        assert np.array_equal(host(ex["cell"]).astype(np.int64), op.ghost_cell), sch
+        assert np.array_equal(host(ex["level"]), op.level), sch
+        assert plan.level_offsets() == list(op.level_off), sch
+        c = op.ghost_cell
+        xc = np.stack([g.lo[0] + (c % g.n[0] + 0.5) * g.h[0],
+                       g.lo[1] + ((c // g.n[0]) % g.n[1] + 0.5) * g.h[1],
+                       g.lo[2] + (c // (g.n[0] * g.n[1]) + 0.5) * g.h[2]])
+        S = xc + op.delta
+        vals = np.stack([synth.sample(f, g) for f in inst.fields])
+        vals[:, op.tags != 0] = np.nan
+        bt = np.broadcast_to(np.asarray(kinds, np.int8)[:, None], (4, op.n_ghost))
+        b = np.stack([synth.bc_values(f, S, op.normal, k) for f, k in zip(inst.fields, kinds)])
+        wants.append((op.fill(vals.copy(), bt, b), op.fill_scale(np.nan_to_num(vals), bt, b)))
+        vals_in.append(vals)
+        fields += [dev(v) for v in vals]
+        bcv += [dev(x) for x in b]
+    q = inst.queries
+    nq = q.x.shape[1]
+    xq, nr, wq = dev(q.x), dev(q.n), dev(q.w)
+    mu = 0.7
+    F = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    B.forward(4, fields, kinds, bcv, nq=[nq] * 3, xq=[xq] * 3, nrm=[nr] * 3, wq=[wq] * 3,
+              p_field=3, u_first=0, mu=mu, F=F)
+    torch.cuda.synchronize()
+    for i, (op, plan) in enumerate(zip(ops, B.plans)):
+        want, sc = wants[i]
+        got = np.stack([host(fields[4 * i + f]) for f in range(4)])
+        c = op.ghost_cell
+        for f in range(4):
+            err = np.abs(got[f][c] - want[f][c])
+            assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][c]), sc[f])), (i, f)
+            nong = np.ones(op.n_cells, bool)
+            nong[c] = False
+            keep = nong & ~np.isnan(vals_in[i][f])
+            assert np.array_equal(got[f][keep], vals_in[i][f][keep]), (i, f)
+        cs = op.cell_scale(np.nan_to_num(want), sc)
+        Fo = op.forces(q.x, q.n, q.w, want[3], want[:3], mu)
+        _, _, _, ps = op.surface_query(q.x, want[3:4], field_scale=cs[3:4])
+        _, _, _, us = op.surface_query(q.x, want[:3], field_scale=cs[:3])
+        s = np.sum(np.abs(q.w) * (ps[0, 0] + 2 * mu * us[:, 1:].sum(axis=(0, 1))))
+        assert np.all(np.abs(host(F[i]) - Fo) <= 1e-12 * np.maximum(np.abs(Fo), s)), (i, F[i], Fo)
+        v, gr, anc = plan.surface(xq, fields[4 * i:4 * i + 4])
+        ov, og, oanc, osc = op.surface_query(q.x, want, field_scale=cs)
+        assert np.array_equal(host(anc), oanc), i
+        assert np.all(np.abs(host(v) - ov) <= 1e-12 * np.maximum(np.abs(ov), osc[:, 0])), i
+        assert np.all(np.abs(host(gr) - og) <= 1e-12 * np.maximum(np.abs(og), osc[:, 1:])), i
