@@ -20,7 +20,10 @@
  *    reference to caller memory after a call returns.
  *  - `stream` is a hipStream_t (NULL: the null stream).  Every call that
  *    launches work is asynchronous on that stream, except gcr_plan_create
- *    and gcr_batch_create, which synchronise it once to size the plan.
+ *    and gcr_batch_create, which synchronise it twice (to size the band
+ *    arrays, then to read the level offsets), and the first gcr_fill with
+ *    the automatic schedule or gcr_batch_forward for a kind of plan, which
+ *    times candidate schedules once and remembers the winner.
  *  - Every call returns GCR_OK or an error code; gcr_status_str() names it.
  *    Geometry and graph errors are detected when a plan is built; apply
  *    calls fail only on bad arguments or HIP errors.  On error nothing the
@@ -118,7 +121,7 @@ typedef struct {
  * graph and its Kahn levels (Sec. 3.2).  Where the graph is not acyclic
  * (concave bodies), each strongly connected group of ghosts forms one unit
  * whose relations are solved together; units have at most 8 ghosts, else
- * GCR_E_CYCLE.  grid, shape: host.  Synchronises `stream`.  The plan owns
+ * GCR_E_CYCLE.  grid, shape: host.  Synchronises `stream` twice.  The plan owns
  * all its device memory; *out is NULL on error. */
 gcr_status gcr_plan_create(const gcr_grid* grid, const gcr_shape* shape,
                            int32_t scheme, void* stream, gcr_plan** out);
@@ -228,7 +231,7 @@ gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf,
                             double* const* lam_bc, void* stream);
 
 /* Batched plans: ninst instances of uneven size built by shared launches.
- * grids, shapes, schemes: host arrays [ninst].  Synchronises once. */
+ * grids, shapes, schemes: host arrays [ninst].  Synchronises twice. */
 gcr_status gcr_batch_create(int32_t ninst, const gcr_grid* grids,
                             const gcr_shape* shapes, const int32_t* schemes,
                             void* stream, gcr_batch** out);
