@@ -569,6 +569,9 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
                     orc_plan** out) {
   *out = NULL;
   if (!g || !s || (g->dim != 2 && g->dim != 3)) return ORC_E_ARG;
+  /* scheme: CGC, CGC_ES or HGC, optionally with ORC_LAYER2 */
+  const int layer2 = (scheme & ORC_LAYER2) != 0;
+  scheme &= ~ORC_LAYER2;
   if (scheme < 0 || scheme > 2) return ORC_E_ARG;
   int dim = g->dim;
   for (int i = 0; i < dim; ++i)
@@ -636,16 +639,48 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     nif += iface[c];
   }
   p->nif = nif;
+  /* Sec. 7.1 (additional ghost-cell layers): with a second layer, solid
+   * cells with psi <= 1.5 delta n join the ghosts.  Candidates (value 2
+   * here) are the solid cells with a fluid cell within R_i cells along each
+   * axis i: going from x_c through its foot point S by a further half cell
+   * diagonal reaches a point whose cell has a fluid centre (psi is
+   * 1-Lipschitz), at most (1.5 + sqrt(d)/2) h_max away from x_c since
+   * delta n <= h_max; hence R_i = floor((1.5 + sqrt(d)/2) h_max / h_i) + 1.
+   * Their distance to the boundary decides below. */
+  int64_t ncand = nif;
+  if (layer2) {
+    double hmax = G->h[0];
+    for (int i = 1; i < dim; ++i) if (G->h[i] > hmax) hmax = G->h[i];
+    int64_t R[3] = {0, 0, 0};
+    for (int i = 0; i < dim; ++i)
+      R[i] = (int64_t)floor((1.5 + 0.5 * sqrt((double)dim)) * hmax / G->h[i]) + 1;
+    for (int64_t c = 0; c < N; ++c) {
+      if (!solid[c] || iface[c]) continue;
+      int64_t ijk[3];
+      unlinear(G, c, ijk);
+      int found = 0;
+      for (int64_t dk = -R[2]; dk <= R[2] && !found; ++dk)
+        for (int64_t dj = -R[1]; dj <= R[1] && !found; ++dj)
+          for (int64_t di = -R[0]; di <= R[0] && !found; ++di) {
+            int64_t q[3] = {ijk[0] + di, ijk[1] + dj, ijk[2] + dk};
+            int in = 1;
+            for (int i = 0; i < 3; ++i) if (q[i] < 0 || q[i] >= G->n[i]) in = 0;
+            if (in && !solid[linear(G, q)]) found = 1;
+          }
+      if (found) { iface[c] = 2; ++ncand; }
+    }
+  }
 
   /* 3. geometry and ghost tags on those cells */
-  int64_t* ic = (int64_t*)malloc(sizeof(int64_t) * (nif ? nif : 1));
-  double* igeo = (double*)malloc(sizeof(double) * 7 * (nif ? nif : 1));
+  int64_t* ic = (int64_t*)malloc(sizeof(int64_t) * (ncand ? ncand : 1));
+  double* igeo = (double*)malloc(sizeof(double) * 7 * (ncand ? ncand : 1));
+  uint8_t* iext = (uint8_t*)calloc(ncand ? ncand : 1, 1);   /* second-layer ghost */
   int status = ORC_OK;
   {
     int64_t k = 0;
     for (int64_t c = 0; c < N; ++c) if (iface[c]) ic[k++] = c;
   }
-  for (int64_t k = 0; k < nif; ++k) {
+  for (int64_t k = 0; k < ncand; ++k) {
     int64_t c = ic[k], ijk[3];
     unlinear(G, c, ijk);
     double x[3] = {centre(G, 0, ijk[0]), centre(G, 1, ijk[1]),
@@ -670,7 +705,15 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
         if (m < p->margins[1]) p->margins[1] = m;
       }
     } else {
-      if (solid[c]) t = 2;
+      /* CGC / CGC_ES: solid cells with a fluid face neighbour */
+      if (solid[c] && iface[c] == 1) t = 2;
+    }
+    if (layer2 && solid[c] && t != 2) {
+      /* second layer: solid cells with psi <= 1.5 delta n, on the extended
+       * stencil of Eq. stencil_anisotropic */
+      if (psi <= 1.5 * dn) { t = 2; iext[k] = 1; }
+      double m = fabs(psi - 1.5 * dn) / hmin;
+      if (m < p->margins[1]) p->margins[1] = m;
     }
     p->tag[c] = t;
     igeo[7 * k + 0] = psi;
@@ -678,30 +721,32 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     for (int i = 0; i < 3; ++i) { igeo[7 * k + 4 + i] = S[i]; }
   }
   if (status != ORC_OK) {
-    free(solid); free(iface); free(ic); free(igeo); orc_plan_destroy(p);
+    free(solid); free(iface); free(ic); free(igeo); free(iext); orc_plan_destroy(p);
     return status;
   }
 
   /* 4. ghost list in linear-index order */
   int64_t ng = 0;
-  for (int64_t k = 0; k < nif; ++k) if (p->tag[ic[k]] == 2 || p->tag[ic[k]] == -2) ++ng;
+  for (int64_t k = 0; k < ncand; ++k) if (p->tag[ic[k]] == 2 || p->tag[ic[k]] == -2) ++ng;
   p->ng = ng;
   int64_t na = ng ? ng : 1;
   int64_t* gcell = (int64_t*)malloc(sizeof(int64_t) * na);
   double* gpsi = (double*)malloc(sizeof(double) * na);
   double* gn = (double*)malloc(sizeof(double) * 3 * na);
+  uint8_t* gext = (uint8_t*)calloc(na, 1);
   {
     int64_t j = 0;
-    for (int64_t k = 0; k < nif; ++k) {
+    for (int64_t k = 0; k < ncand; ++k) {
       int8_t t = p->tag[ic[k]];
       if (t != 2 && t != -2) continue;
       gcell[j] = ic[k];
+      gext[j] = iext[k];
       gpsi[j] = igeo[7 * k];
       for (int i = 0; i < 3; ++i) gn[3 * j + i] = igeo[7 * k + 1 + i];
       ++j;
     }
   }
-  free(ic); free(igeo);
+  free(ic); free(igeo); free(iext);
 
   /* 5. stencil per ghost: e = sgn(n) with sgn(0) = +1 (Appendix A), r_i = 1
    * or Eq. stencil_anisotropic (CGC_ES), x_s = x_c + psi n (Eq.
@@ -720,7 +765,7 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
       gr[3 * j + i] = 1;
       if (i < dim && ni != 0.0 && fabs(ni) < p->margins[3]) p->margins[3] = fabs(ni);
     }
-    if (scheme == ORC_CGC_ES) {
+    if (scheme == ORC_CGC_ES || gext[j]) {
       for (int i = 0; i < dim; ++i) {
         double q = 2.0 * fabs(gd[3 * j + i]) / G->h[i];
         int ri = (int)ceil(q);
@@ -879,7 +924,7 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
   }
 
   if (status != ORC_OK) {
-    free(solid); free(iface); free(gcell); free(gpsi); free(gn); free(ge); free(gr);
+    free(solid); free(iface); free(gcell); free(gpsi); free(gn); free(gext); free(ge); free(gr);
     free(gd); free(gst); free(dep); free(lev); free(order); free(lev_off); free(comp);
     orc_plan_destroy(p);
     return status;
@@ -943,7 +988,7 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     }
     free(put); free(cid); free(csz);
   }
-  free(solid); free(iface); free(gcell); free(gpsi); free(gn); free(ge); free(gr);
+  free(solid); free(iface); free(gcell); free(gpsi); free(gn); free(gext); free(ge); free(gr);
   free(gd); free(gst); free(dep); free(lev); free(order); free(lev_off); free(comp);
   *out = p;
   return ORC_OK;

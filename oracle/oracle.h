@@ -27,6 +27,9 @@ enum {
 };
 enum { ORC_SPHERE = 0, ORC_STAR2D = 1, ORC_SHSTAR = 2, ORC_AIRFOIL = 3 };
 enum { ORC_CGC = 0, ORC_CGC_ES = 1, ORC_HGC = 2 };
+/* Flag added to a scheme: a second ghost layer (Sec. 7.1), solid cells with
+ * psi <= 1.5 delta n, on the extended stencil of Eq. stencil_anisotropic. */
+enum { ORC_LAYER2 = 4 };
 enum { ORC_DIRICHLET = 0, ORC_NEUMANN = 1 };
 
 typedef struct {
@@ -73,7 +76,8 @@ void orc_export(const orc_plan* p, int8_t* tags, int64_t* ghost_cell,
                 double* normal, double* psi, int32_t* r);
 /* Stencil cells of ghost g (canonical position): [2^d - 1], -1 where skipped. */
 void orc_stencil(const orc_plan* p, int64_t g, int64_t* cells);
-/* Decision margins (in units of h): [0] classification, [1] HGC band,
+/* Decision margins (in units of h): [0] classification, [1] HGC band and
+ * second-layer threshold,
  * [2] CGC_ES multiplier, [3] normal sign, [4] max alpha_x, [5] max alpha_y,
  * [6] max alpha_z. */
 void orc_margins(const orc_plan* p, double* out);

@@ -28,6 +28,7 @@ import numpy as np
 
 SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
 CGC, CGC_ES, HGC = 0, 1, 2
+LAYER2 = 4          # flag: a second ghost layer on top of any scheme
 DIRICHLET, NEUMANN = 0, 1
 
 _M64 = (1 << 64) - 1
