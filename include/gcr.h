@@ -57,6 +57,11 @@ typedef enum {
 
 /* Ghost placement (Sec. 3.1, Sec. 7.2). */
 typedef enum { GCR_CGC = 0, GCR_CGC_ES = 1, GCR_HGC = 2 } gcr_scheme;
+/* Flag or-ed into a scheme: a second ghost layer (Sec. 7.1).  Solid cells
+ * with psi <= 1.5 delta n (Eq. delta_n) that the scheme does not already
+ * make ghosts join the ghost set; they are reconstructed on the extended
+ * stencil of Eq. stencil_anisotropic, the scheme's own ghosts as before. */
+#define GCR_LAYER2 4
 
 /* Boundary-condition kind per field (Sec. 4.1, 5.1).  GCR_MIXED: a per-ghost
  * uint8 array (0 Dirichlet, 1 Neumann) is supplied. */
@@ -125,6 +130,8 @@ typedef struct {
  * all its device memory; *out is NULL on error. */
 gcr_status gcr_plan_create(const gcr_grid* grid, const gcr_shape* shape,
                            int32_t scheme, void* stream, gcr_plan** out);
+/* (scheme: a gcr_scheme, optionally | GCR_LAYER2; gcr_stats.n_interface
+ * then still counts interface cells only.) */
 void gcr_plan_destroy(gcr_plan* plan);
 
 /* Host copy of the plan's sizes and statistics. */

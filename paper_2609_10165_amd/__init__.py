@@ -9,6 +9,7 @@ missing, importing works but every call raises ``GcrError``.
 from __future__ import annotations
 
 import ctypes
+import sys
 import os
 from typing import Optional, Sequence
 
@@ -18,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libgcr.so")
 
 CGC, CGC_ES, HGC = 0, 1, 2
+LAYER2 = 4   # flag or-ed into a scheme: a second ghost layer
 DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
 SCHED_AUTO, SCHED_LEVELS, SCHED_WORKGROUP, SCHED_GRAPH = 0, 1, 2, 3
@@ -184,9 +186,11 @@ class Plan:
         self.n_levels = st.n_levels
         self.n_interface = st.n_interface
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)
-        if h is not None and self._owner is None and _lib is not None:
+        # at interpreter exit the HIP runtime may already be torn down: the
+        # process is ending, so the plan's memory is left to it
+        if h is not None and self._owner is None and _lib is not None and not _finalizing():
             _lib.gcr_plan_destroy(h)
         self._h = None
 
@@ -319,9 +323,9 @@ class Batch:
             _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
             self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self))
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
+        if h is not None and _lib is not None and not _finalizing():
             self.plans = []
             _lib.gcr_batch_destroy(h)
         self._h = None

@@ -199,7 +199,9 @@ namespace {
 std::mutex g_shape_mu;
 std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_shape;
 std::mutex g_bfs_mu;
-std::vector<std::pair<const gcr_batch*, std::unique_ptr<BatchFwdState>>> g_bfs;
+// never destroyed: states still held at exit are left to the process, since
+// the device pool they return memory to may already be gone by then
+auto& g_bfs = *new std::vector<std::pair<const gcr_batch*, std::unique_ptr<BatchFwdState>>>();
 
 BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   std::lock_guard<std::mutex> lk(g_bfs_mu);

@@ -29,6 +29,7 @@ enum : uint32_t {
 
 enum { kSphere = 0, kStar2D = 1, kShStar = 2, kAirfoil = 3 };
 enum { kCGC = 0, kCGC_ES = 1, kHGC = 2 };
+constexpr int kLayer2 = 4;   // scheme flag: a second ghost layer
 
 struct GridD {
   int dim;
@@ -52,7 +53,8 @@ struct ShapeD {
 struct Inst {
   GridD g;
   ShapeD s;
-  int scheme, pad;
+  int scheme;          // kCGC, kCGC_ES, kHGC
+  int layer2;          // 1: a second ghost layer (Sec. 7.1)
   int64_t cell_off;    // offset of this instance in the concatenated tag array
   int64_t chunk_off;   // first classification chunk of this instance
   int64_t nchunk;

@@ -64,6 +64,7 @@ struct BatchData {
   int64_t nband = 0;                 // row segments tested by the band pass
   std::vector<Inst> inst;            // host copies
   std::vector<int64_t> if_off, g_off;  // host [ninst+1]
+  std::vector<int64_t> iface_off;      // host [ninst+1] interface cells alone
   std::vector<InstInfo> info;        // host [ninst]
   std::vector<int32_t> lev_off;      // host [ninst][kMaxLevels+1]
   // device
@@ -76,6 +77,8 @@ struct BatchData {
   int32_t* d_nchunk_list = nullptr;
   int32_t* d_band = nullptr;         // near-boundary row segments (k_band)
   int32_t* d_nband = nullptr;        // their number
+  int64_t* d_scan_tmp = nullptr;     // tile totals of the long chunk scan
+  int64_t* d_iface_off = nullptr;    // interface cells per instance (second layer)
   int64_t* d_chunk_excl = nullptr;
   int64_t* d_if_off = nullptr;       // [ninst+1]
   int64_t* d_g_off = nullptr;        // [ninst+1]
@@ -90,6 +93,7 @@ struct BatchData {
   int64_t* d_blkexcl = nullptr;
   // ghosts, linear-index order
   int32_t* d_g_cell = nullptr;
+  uint8_t* d_g_ext = nullptr;        // ghost on the extended stencil (second layer)
   double* d_g_psi = nullptr;
   double* d_g_n = nullptr;           // [3][cap]
   uint32_t* d_g_code = nullptr;

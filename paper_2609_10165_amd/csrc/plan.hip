@@ -215,50 +215,192 @@ __device__ bool project(const ShapeD& s, int dim, const double x[3], bool solid,
 // 2. scans and compactions
 // --------------------------------------------------------------------------
 
-// excl[i] = sum cnt[0..i), excl[n] = total; one workgroup.  If list is
-// given, the indices i with cnt[i] > 0 are written to it in ascending order
-// and their number to nlist[0]: each count carries a flag in bits 40 and up,
-// so one scan yields both (counts stay below 2^40).
+// excl[i] = sum cnt[0..i), excl[n] = total.  If list is given, the indices
+// i with cnt[i] > 0 are written to it in ascending order and their number
+// to nlist[0]: each count carries a flag in bits 40 and up, so one scan
+// yields both (counts stay below 2^40).  Tiles of 8 values per thread of a
+// 1024-thread workgroup.
+constexpr int kScanT = 8, kScanTile = 1024 * kScanT;
+constexpr int64_t kScanHi = int64_t(1) << 40;
+
+__device__ __forceinline__ void scan_load(const int32_t* __restrict__ cnt, int64_t n, int64_t b,
+                                          int v[kScanT]) {
+  const bool vec = (reinterpret_cast<uintptr_t>(cnt) & 15) == 0;
+  if (vec && b + kScanT <= n) {
+    const int4 a = *reinterpret_cast<const int4*>(cnt + b);
+    const int4 c = *reinterpret_cast<const int4*>(cnt + b + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScanT; ++q) v[q] = b + q < n ? cnt[b + q] : 0;
+  }
+}
+
+// One tile from t0 with the packed prefix `carry`; returns the tile's
+// packed total.  Every thread of the workgroup calls it.
+__device__ __forceinline__ int64_t scan_tile(const int32_t* __restrict__ cnt, int64_t n,
+                                             int64_t t0, int64_t carry,
+                                             int64_t* __restrict__ excl,
+                                             int32_t* __restrict__ list, int64_t* sh) {
+  const int64_t b = t0 + (int64_t)threadIdx.x * kScanT;
+  int v[kScanT];
+  scan_load(cnt, n, b, v);
+  int64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanT; ++q) sum += v[q] + (v[q] > 0 ? kScanHi : 0);
+  int64_t tot;
+  int64_t run = carry + block_excl_scan<1024>(sum, &tot, sh);
+#pragma unroll
+  for (int q = 0; q < kScanT; ++q) {
+    if (b + q < n) {
+      excl[b + q] = run & (kScanHi - 1);
+      if (list && v[q] > 0) list[run >> 40] = (int32_t)(b + q);
+    }
+    run += v[q] + (v[q] > 0 ? kScanHi : 0);
+  }
+  return tot;
+}
+
+// the whole scan by one workgroup (short inputs)
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ cnt, int64_t n,
                                                int64_t* __restrict__ excl,
                                                int32_t* __restrict__ list,
                                                int32_t* __restrict__ nlist) {
   __shared__ int64_t sh[17];
-  constexpr int kT = 8, kTile = 1024 * kT;
-  constexpr int64_t kHi = int64_t(1) << 40;
-  const bool vec = (reinterpret_cast<uintptr_t>(cnt) & 15) == 0;
   int64_t carry = 0;
-  for (int64_t t0 = 0; t0 < n; t0 += kTile) {
-    const int64_t b = t0 + (int64_t)threadIdx.x * kT;
-    int v[kT];
-    if (vec && b + kT <= n) {
-      const int4 a = *reinterpret_cast<const int4*>(cnt + b);
-      const int4 c = *reinterpret_cast<const int4*>(cnt + b + 4);
-      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-      v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
-    } else {
+  for (int64_t t0 = 0; t0 < n; t0 += kScanTile) carry += scan_tile(cnt, n, t0, carry, excl, list, sh);
+  if (threadIdx.x == 0) {
+    excl[n] = carry & (kScanHi - 1);
+    if (nlist) nlist[0] = (int32_t)(carry >> 40);
+  }
+}
+
+// long inputs: packed total of each tile, one workgroup per tile ...
+__global__ __launch_bounds__(1024) void k_scan_reduce(const int32_t* __restrict__ cnt, int64_t n,
+                                                      int64_t* __restrict__ tsum) {
+  __shared__ int64_t sh[17];
+  int v[kScanT];
+  scan_load(cnt, n, (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanT, v);
+  int64_t sum = 0;
 #pragma unroll
-      for (int q = 0; q < kT; ++q) v[q] = b + q < n ? cnt[b + q] : 0;
-    }
-    int64_t sum = 0;
-#pragma unroll
-    for (int q = 0; q < kT; ++q) sum += v[q] + (v[q] > 0 ? kHi : 0);
+  for (int q = 0; q < kScanT; ++q) sum += v[q] + (v[q] > 0 ? kScanHi : 0);
+  int64_t tot;
+  (void)block_excl_scan<1024>(sum, &tot, sh);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+// ... their exclusive scan in place, the total and the list length ...
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ tsum, int64_t ntiles,
+                                                   int64_t* __restrict__ excl_n,
+                                                   int32_t* __restrict__ nlist) {
+  __shared__ int64_t sh[17];
+  int64_t carry = 0;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += 1024) {
+    const int64_t t = t0 + threadIdx.x;
+    const int64_t v = t < ntiles ? tsum[t] : 0;
     int64_t tot;
-    int64_t run = carry + block_excl_scan<1024>(sum, &tot, sh);
-#pragma unroll
-    for (int q = 0; q < kT; ++q) {
-      if (b + q < n) {
-        excl[b + q] = run & (kHi - 1);
-        if (list && v[q] > 0) list[run >> 40] = (int32_t)(b + q);
-      }
-      run += v[q] + (v[q] > 0 ? kHi : 0);
-    }
+    const int64_t pre = block_excl_scan<1024>(v, &tot, sh);
+    if (t < ntiles) tsum[t] = carry + pre;
     carry += tot;
   }
   if (threadIdx.x == 0) {
-    excl[n] = carry & (kHi - 1);
+    excl_n[0] = carry & (kScanHi - 1);
     if (nlist) nlist[0] = (int32_t)(carry >> 40);
   }
+}
+
+// ... then every tile again from its offset
+__global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ cnt, int64_t n,
+                                                    const int64_t* __restrict__ toff,
+                                                    int64_t* __restrict__ excl,
+                                                    int32_t* __restrict__ list) {
+  __shared__ int64_t sh[17];
+  (void)scan_tile(cnt, n, (int64_t)blockIdx.x * kScanTile, toff[blockIdx.x], excl, list, sh);
+}
+
+// One workgroup up to two tiles, else the three-pass form (tsum: ntiles
+// int64 of scratch).
+static void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* list,
+                        int32_t* nlist, int64_t* tsum, hipStream_t st) {
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles <= 2 || !tsum) {
+    k_scan<<<1, 1024, 0, st>>>(cnt, n, excl, list, nlist);
+    return;
+  }
+  k_scan_reduce<<<(unsigned)ntiles, 1024, 0, st>>>(cnt, n, tsum);
+  k_scan_top<<<1, 1024, 0, st>>>(tsum, ntiles, excl + n, nlist);
+  k_scan_down<<<(unsigned)ntiles, 1024, 0, st>>>(cnt, n, tsum, excl, list);
+}
+
+// Second ghost layer (Sec. 7.1): the solid cells within R_i cells along each
+// axis i of a solid interface cell, R_i = floor((1.5 + sqrt(d)/2) h_max /
+// h_i) + 1, get the candidate mark 0x20.  Every cell with psi <= 1.5 delta n
+// is among them: a walk from it through its foot point reaches a fluid
+// centre within that box (delta n <= h_max, psi 1-Lipschitz), and the last
+// solid cell before it is a solid interface cell.  One workgroup per chunk
+// of the interface chunk list (the grid covers every chunk; the rest exit).
+__global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts, int ninst,
+                                                 const int64_t* __restrict__ chunk_start,
+                                                 const int32_t* __restrict__ chunk_list,
+                                                 const int32_t* __restrict__ nlist,
+                                                 int8_t* __restrict__ tags) {
+  if ((int)blockIdx.x >= nlist[0]) return;
+  const int64_t chunk = chunk_list[blockIdx.x];
+  const int ii = find_inst(chunk_start, ninst, chunk);
+  const Inst& I = insts[ii];
+  if (!I.layer2) return;
+  const GridD& g = I.g;
+  double hmax = g.h[0];
+  for (int a = 1; a < g.dim; ++a) hmax = fmax(hmax, g.h[a]);
+  int R[3] = {0, 0, 0};
+  for (int a = 0; a < g.dim; ++a)
+    R[a] = (int)floor((1.5 + 0.5 * sqrt((double)g.dim)) * hmax / g.h[a]) + 1;
+  uint32_t* words = reinterpret_cast<uint32_t*>(tags);
+  const int64_t base = (chunk - I.chunk_off) * kChunk;
+  for (int t = threadIdx.x; t < kChunk; t += 256) {
+    const int64_t c = base + t;
+    if (c >= g.ncell) break;
+    if ((tags[I.cell_off + c] & 0x41) != 0x41) continue;   // solid interface cells
+    int i, j, k;
+    unlinear(g, (int)c, i, j, k);
+    for (int dk = -R[2]; dk <= R[2]; ++dk) {
+      const int kk = k + dk;
+      if (kk < 0 || kk >= g.n[2]) continue;
+      for (int dj = -R[1]; dj <= R[1]; ++dj) {
+        const int jj = j + dj;
+        if (jj < 0 || jj >= g.n[1]) continue;
+        for (int di = -R[0]; di <= R[0]; ++di) {
+          const int ix = i + di;
+          if (ix < 0 || ix >= g.n[0]) continue;
+          const int64_t b = I.cell_off + linear(g, ix, jj, kk);
+          if (tags[b] != 1) continue;   // plain solid, not yet marked
+          // the tag array is padded to 256 bytes, so its last word is whole
+          atomicOr(&words[b >> 2], 0x20u << (8 * (int)(b & 3)));
+        }
+      }
+    }
+  }
+}
+
+// per chunk: cells with an interface or candidate mark (every chunk)
+__global__ __launch_bounds__(256) void k_count_marks(const Inst* __restrict__ insts, int ninst,
+                                                     const int64_t* __restrict__ chunk_start,
+                                                     const int8_t* __restrict__ tags,
+                                                     int32_t* __restrict__ chunk_cnt) {
+  __shared__ int s;
+  const int64_t chunk = blockIdx.x;
+  const int ii = find_inst(chunk_start, ninst, chunk);
+  const Inst& I = insts[ii];
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  const int64_t base = (chunk - I.chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
+  int n = 0;
+  for (int b = 0; b < kSeg; ++b)
+    if (base + b < I.g.ncell && (tags[I.cell_off + base + b] & 0x60)) ++n;
+  if (n) atomicAdd(&s, n);
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_cnt[chunk] = s;
 }
 
 // off[i] = excl[start[i]] for the instance boundaries
@@ -275,7 +417,7 @@ __global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ 
                                                        const int64_t* __restrict__ chunk_excl,
                                                        const int32_t* __restrict__ chunk_list,
                                                        int32_t* __restrict__ if_cell) {
-  const int64_t chunk = chunk_list[blockIdx.x];   // chunks holding interface cells
+  const int64_t chunk = chunk_list[blockIdx.x];   // chunks holding listed cells
   __shared__ int64_t sh[5];
   const int ii = find_inst(chunk_start, ninst, chunk);
   const Inst& I = insts[ii];
@@ -291,10 +433,10 @@ __global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ 
       const uint32_t q[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
       for (int b = 0; b < kSeg; ++b)
-        if ((q[b >> 2] >> (8 * (b & 3))) & 0x40u) mask |= 1u << b;
+        if ((q[b >> 2] >> (8 * (b & 3))) & 0x60u) mask |= 1u << b;
     } else {
       for (int b = 0; b < nvalid; ++b)
-        if (src[b] & 0x40) mask |= 1u << b;
+        if (src[b] & 0x60) mask |= 1u << b;
     }
   }
   int64_t tot;
@@ -325,7 +467,9 @@ __global__ __launch_bounds__(256) void k_geometry(const Inst* __restrict__ insts
   const GridD& g = I.g;
   const int c = if_cell[e];
   int8_t* tp = tags + I.cell_off + c;
-  const bool solid = (*tp & 1) != 0;
+  const int8_t t0 = *tp;
+  const bool solid = (t0 & 1) != 0;
+  const bool iface = (t0 & 0x40) != 0;   // else a second-layer candidate
   int i, j, k;
   unlinear(g, c, i, j, k);
   double x[3] = {centre(g, 0, i), centre(g, 1, j), g.dim == 3 ? centre(g, 2, k) : 0.0};
@@ -335,13 +479,19 @@ __global__ __launch_bounds__(256) void k_geometry(const Inst* __restrict__ insts
   double sum = 0.0;
   for (int a = 0; a < g.dim; ++a) sum += (n[a] / g.h[a]) * (n[a] / g.h[a]);
   double dn = 1.0 / sqrt(sum);
-  bool ghost;
-  if (I.scheme == kHGC) ghost = solid ? (psi <= dn / 2.0) : (-psi < dn / 2.0);
-  else ghost = solid;
+  bool ghost = false;
+  if (iface) {
+    if (I.scheme == kHGC) ghost = solid ? (psi <= dn / 2.0) : (-psi < dn / 2.0);
+    else ghost = solid;
+  }
+  // Sec. 7.1: a second layer adds the solid cells with psi <= 1.5 delta n,
+  // reconstructed on the extended stencil
+  const bool ext = I.layer2 && solid && !ghost && psi <= 1.5 * dn;
+  ghost = ghost || ext;
   *tp = ghost ? (solid ? 2 : -2) : (solid ? 1 : 0);
   if_psi[e] = psi;
   for (int a = 0; a < 3; ++a) if_n[a * cap + e] = n[a];
-  if_flag[e] = ghost ? 1 : 0;
+  if_flag[e] = ghost ? (ext ? 3 : 1) : 0;   // bit 0 ghost, bit 1 extended stencil
 }
 
 // per 1024-entry block counts of flags
@@ -353,7 +503,7 @@ __global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__
   int c = 0;
   for (int t = 0; t < 4; ++t) {
     int64_t e = (int64_t)blockIdx.x * 1024 + t * 256 + threadIdx.x;
-    if (e < n) c += flag[e];
+    if (e < n) c += flag[e] & 1;
   }
   if (c) atomicAdd(&s, c);
   __syncthreads();
@@ -364,15 +514,17 @@ __global__ __launch_bounds__(256) void k_scatter_ghosts(
     const uint8_t* __restrict__ flag, int64_t n, const int64_t* __restrict__ blk_excl,
     const int32_t* __restrict__ if_cell, const double* __restrict__ if_psi,
     const double* __restrict__ if_n, int64_t cap, int32_t* __restrict__ g_cell,
-    double* __restrict__ g_psi, double* __restrict__ g_n) {
+    double* __restrict__ g_psi, double* __restrict__ g_n, uint8_t* __restrict__ g_ext) {
   __shared__ int64_t sh[5];
   int64_t run = blk_excl[blockIdx.x];
   for (int t = 0; t < 4; ++t) {
     int64_t e = (int64_t)blockIdx.x * 1024 + t * 256 + threadIdx.x;
-    int f = (e < n) ? flag[e] : 0;
+    const int fl = (e < n) ? flag[e] : 0;
+    const int f = fl & 1;
     int64_t tot;
     int64_t pos = run + block_excl_scan<256>(f, &tot, sh);
     if (f) {
+      g_ext[pos] = (uint8_t)(fl >> 1);
       g_cell[pos] = if_cell[e];
       g_psi[pos] = if_psi[e];
       for (int a = 0; a < 3; ++a) g_n[a * cap + pos] = if_n[a * cap + e];
@@ -390,7 +542,7 @@ __global__ void k_ghost_off(const uint8_t* __restrict__ flag, const int64_t* __r
   int64_t e = if_off[i];
   int64_t b = e / 1024;
   int64_t s = blk_excl[b];
-  for (int64_t q = b * 1024; q < e; ++q) s += flag[q];
+  for (int64_t q = b * 1024; q < e; ++q) s += flag[q] & 1;
   g_off[i] = s;
 }
 
@@ -416,6 +568,7 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
                                               const int32_t* __restrict__ g_cell,
                                               const double* __restrict__ g_psi,
                                               const double* __restrict__ g_n, int64_t cap,
+                                              const uint8_t* __restrict__ g_ext,
                                               const int8_t* __restrict__ tags,
                                               const unsigned long long* __restrict__ htab,
                                               const int64_t* __restrict__ hoff,
@@ -435,7 +588,7 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
   double n[3];
   int r[3] = {1, 1, 1};
   for (int a = 0; a < 3; ++a) n[a] = g_n[a * cap + e];
-  if (I.scheme == kCGC_ES) {
+  if (I.scheme == kCGC_ES || g_ext[e]) {
     // Eq. stencil_anisotropic: r_i = max(1, ceil(2 |x_1 - x_s|_i / dx_i))
     for (int a = 0; a < g.dim; ++a) {
       double d = psi * n[a];
@@ -670,7 +823,8 @@ static double factorial(int n) {
 static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme, Inst* I) {
   std::memset(I, 0, sizeof(Inst));
   if (gg.dim != 2 && gg.dim != 3) return GCR_E_ARG;
-  if (scheme < 0 || scheme > 2) return GCR_E_ARG;
+  const int base = scheme & ~kLayer2;
+  if (base < 0 || base > 2) return GCR_E_ARG;
   int64_t ncell = 1;
   for (int a = 0; a < gg.dim; ++a) {
     if (gg.n[a] < 1 || !(gg.h[a] > 0.0) || !std::isfinite(gg.lo[a])) return GCR_E_ARG;
@@ -684,7 +838,8 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
     I->g.h[a] = a < gg.dim ? gg.h[a] : 1.0;
   }
   I->g.ncell = ncell;
-  I->scheme = scheme;
+  I->scheme = base;
+  I->layer2 = (scheme & kLayer2) ? 1 : 0;
   ShapeD& s = I->s;
   s.kind = gs.kind;
   for (int a = 0; a < 3; ++a) s.c[a] = a < gg.dim ? gs.center[a] : 0.0;
@@ -865,7 +1020,9 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_band = own<int32_t>(D, chunks * (kChunk / kSeg));   // every segment at most once
   D.d_nband = own<int32_t>(D, 1);
   D.d_chunk_excl = own<int64_t>(D, chunks + 1);
+  D.d_scan_tmp = own<int64_t>(D, (chunks + kScanTile - 1) / kScanTile + 1);
   D.d_if_off = own<int64_t>(D, ninst + 1);
+  D.d_iface_off = own<int64_t>(D, ninst + 1);
   D.d_g_off = own<int64_t>(D, ninst + 1);
   D.d_info = own<InstInfo>(D, ninst);
   D.d_lev_off = own<int32_t>(D, (size_t)ninst * (kMaxLevels + 1));
@@ -874,9 +1031,12 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_unit_lev = own<int32_t>(D, (size_t)ninst * kMaxUnits);
   D.d_reach = own<uint32_t>(D, (size_t)ninst * kMaxResidual * (kMaxResidual / 32));
   if (!D.d_unit_lev || !D.d_reach) return GCR_E_NOMEM;
-  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_span || !D.d_chunk_list || !D.d_nchunk_list || !D.d_band || !D.d_nband ||
-      !D.d_if_off || !D.d_g_off || !D.d_info || !D.d_lev_off || !D.d_unit_mem || !D.d_unit_cnt)
+  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_scan_tmp || !D.d_span || !D.d_chunk_list || !D.d_nchunk_list || !D.d_band || !D.d_nband ||
+      !D.d_if_off || !D.d_iface_off || !D.d_g_off || !D.d_info || !D.d_lev_off ||
+      !D.d_unit_mem || !D.d_unit_cnt)
     return GCR_E_NOMEM;
+  bool any_layer2 = false;
+  for (int i = 0; i < ninst; ++i) any_layer2 = any_layer2 || D.inst[i].layer2;
   // pinned staging: [instances | chunk starts | if_off | hoff | hmask | g_off |
   // info | lev_off | unit_lev], each region 256-byte aligned
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -886,7 +1046,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   const size_t o_info = o_go + al(8 * (ninst + 1)), o_lo = o_info + al(sizeof(InstInfo) * ninst);
   const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
   const size_t o_nl = o_ul + al(4 * (size_t)ninst * kMaxUnits);
-  const size_t stage_bytes = o_nl + al(8);
+  const size_t o_io = o_nl + al(8);
+  const size_t stage_bytes = o_io + al(8 * (ninst + 1));
   PinnedStage PS;
   PS.st = st;
   PS.p = (char*)pinned_alloc(stage_bytes);
@@ -904,8 +1065,20 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   launch_classify(D.d_inst, ninst, D.d_chunk_start, chunks, D.d_span, D.d_tags, D.d_chunk_cnt,
                   D.d_band, D.d_nband, T.event(10), T.event(11), st);
   T.mark(1, st);
-  k_scan<<<1, 1024, 0, st>>>(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list,
-                             D.d_nchunk_list);
+  launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
+              D.d_scan_tmp, st);
+  if (any_layer2) {
+    // interface counts of the instances, then the second-layer candidates
+    // join the list: mark, recount every chunk, scan again
+    k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
+                                                       D.d_iface_off);
+    k_l2_mark<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start,
+                                                D.d_chunk_list, D.d_nchunk_list, D.d_tags);
+    k_count_marks<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
+                                                    D.d_chunk_cnt);
+    launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
+                D.d_scan_tmp, st);
+  }
   k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
                                                      D.d_if_off);
   T.mark(2, st);
@@ -916,8 +1089,13 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   GCR_HIP(hipMemcpyAsync(PS.p + o_nl, D.d_nchunk_list, sizeof(int32_t), hipMemcpyDeviceToHost,
                          st));
   GCR_HIP(hipMemcpyAsync(PS.p + o_nl + 4, D.d_nband, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (any_layer2)
+    GCR_HIP(hipMemcpyAsync(PS.p + o_io, D.d_iface_off, sizeof(int64_t) * (ninst + 1),
+                           hipMemcpyDeviceToHost, st));
   GCR_HIP(hipStreamSynchronize(st));
   std::memcpy(D.if_off.data(), PS.p + o_if, 8 * (ninst + 1));
+  D.iface_off = D.if_off;   // interface cells alone (second-layer candidates excluded)
+  if (any_layer2) std::memcpy(D.iface_off.data(), PS.p + o_io, 8 * (ninst + 1));
   int32_t nlist = 0, nband = 0;
   std::memcpy(&nlist, PS.p + o_nl, sizeof(int32_t));
   std::memcpy(&nband, PS.p + o_nl + 4, sizeof(int32_t));
@@ -956,6 +1134,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_blkcnt = own<int32_t>(D, nblk + 1);
   D.d_blkexcl = own<int64_t>(D, nblk + 2);
   D.d_g_cell = own<int32_t>(D, cap);
+  D.d_g_ext = own<uint8_t>(D, cap);
   D.d_g_psi = own<double>(D, cap);
   D.d_g_n = own<double>(D, 3 * cap);
   D.d_g_code = own<uint32_t>(D, cap);
@@ -980,7 +1159,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   if (!D.d_listA || !D.d_rcnt || !D.d_roff || !D.d_radj || !D.d_cnt || !D.d_bits || !D.d_dcnt)
     return GCR_E_NOMEM;
   if (!D.d_if_cell || !D.d_if_psi || !D.d_if_n || !D.d_if_flag || !D.d_blkcnt || !D.d_blkexcl ||
-      !D.d_g_cell || !D.d_g_psi || !D.d_g_n || !D.d_g_code || !D.d_deps || !D.d_lev ||
+      !D.d_g_cell || !D.d_g_ext || !D.d_g_psi || !D.d_g_n || !D.d_g_code || !D.d_deps || !D.d_lev ||
       !D.d_blk_idx || !D.d_perm || !D.d_cell || !D.d_delta || !D.d_nrm || !D.d_psi ||
       !D.d_code || !D.d_level || !D.d_blk)
     return GCR_E_NOMEM;
@@ -1001,7 +1180,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
     k_scan<<<1, 1024, 0, st>>>(D.d_blkcnt, nblk, D.d_blkexcl, nullptr, nullptr);
     k_scatter_ghosts<<<(unsigned)nblk, 256, 0, st>>>(D.d_if_flag, nif, D.d_blkexcl, D.d_if_cell,
                                                      D.d_if_psi, D.d_if_n, cap, D.d_g_cell,
-                                                     D.d_g_psi, D.d_g_n);
+                                                     D.d_g_psi, D.d_g_n, D.d_g_ext);
     k_ghost_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_if_flag, D.d_blkexcl, D.d_if_off, ninst,
                                                       D.d_g_off);
     T.mark(6, st);
@@ -1010,7 +1189,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                                                     D.d_hmask, D.d_htab);
     k_zero32<<<blocks(2 * cap, 256), 256, 0, st>>>(D.d_rcnt, 2 * cap);   // rcnt + rfill
     k_deps<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_g_off, D.d_g_cell, D.d_g_psi,
-                                              D.d_g_n, cap, D.d_tags, D.d_htab, D.d_hoff,
+                                              D.d_g_n, cap, D.d_g_ext, D.d_tags, D.d_htab, D.d_hoff,
                                               D.d_hmask, D.d_g_code, D.d_deps,
                                               D.d_rcnt, D.d_dcnt, D.d_info);
     k_rscan<<<1, 1024, 0, st>>>(D.d_rcnt, D.d_g_off, ninst, D.d_roff);
@@ -1104,7 +1283,7 @@ void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p) {
   p->ncell = p->inst.g.ncell;
   p->goff = D.g_off[i];
   p->ng = D.g_off[i + 1] - D.g_off[i];
-  p->nif = D.if_off[i + 1] - D.if_off[i];
+  p->nif = D.iface_off[i + 1] - D.iface_off[i];
   p->stride = D.cap;
   p->info = D.info[i];
   p->nlev = p->info.nlev;

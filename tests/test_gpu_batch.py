@@ -210,3 +210,37 @@ def test_batch_three_schemes_sphere256_full_size(gcr):
         assert np.array_equal(host(anc), oanc), i
         assert np.all(np.abs(host(v) - ov) <= 1e-12 * np.maximum(np.abs(ov), osc[:, 0])), i
         assert np.all(np.abs(host(gr) - og) <= 1e-12 * np.maximum(np.abs(og), osc[:, 1:])), i
+
+
+def test_batch_forward_with_coupled_units(gcr):
+    """CGC on concave stars: instances with coupled units (solved by a unit
+    tile of their level) beside instances without, against the oracle."""
+    from synth import CGC
+    insts = synth.stars64(seed=0, ninst=1, nmin=96, nmax=160) + \
+        synth.stars64(seed=7, ninst=3, nmin=96, nmax=300)
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [CGC] * len(insts))
+    nf = 3
+    ops, fields, bcv, bct, wants = [], [], [], [], []
+    for inst in insts:
+        op = oracle.OraclePlan(inst.grid, inst.shape, CGC)
+        ops.append(op)
+        S = ghost_centres(op) + op.delta
+        kinds = [synth.mixed_kinds(S, inst.shape.center, b) for b in inst.mixed_beta]
+        vals = np.stack([synth.sample(f, inst.grid) for f in inst.fields])
+        vals[:, op.tags != 0] = np.nan
+        b = np.stack([synth.bc_values(f, S, op.normal, k) for f, k in zip(inst.fields, kinds)])
+        wants.append((op.fill(vals.copy(), np.stack(kinds), b),
+                      op.fill_scale(np.nan_to_num(vals), np.stack(kinds), b)))
+        for f in range(nf):
+            fields.append(dev(vals[f]))
+            bcv.append(dev(b[f]))
+            bct.append(dev(kinds[f], torch.uint8))
+    assert ops[0].n_units_coupled >= 1
+    B.forward(nf, fields, [2, 2, 2], bcv, bc_type=bct)
+    torch.cuda.synchronize()
+    for i, (op, (want, sc)) in enumerate(zip(ops, wants)):
+        for f in range(nf):
+            got = host(fields[i * nf + f])
+            c = op.ghost_cell
+            err = np.abs(got[c] - want[f][c])
+            assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][c]), sc[f])), (i, f)

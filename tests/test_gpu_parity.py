@@ -408,3 +408,57 @@ def test_foot_points(gcr, which):
     check_close(host(S), want, np.full(want.shape, h), "foot points")
     assert np.array_equal(host(n), host(ex["normal"]))
     assert S.shape == (op.dim, op.n_ghost)
+
+
+def test_plan_long_chunk_scan(gcr):
+    # 8320^2 = 69.2M cells: 16,900 classification chunks, more than two scan
+    # tiles, so the chunk scan takes its three-pass form
+    n = 8320
+    h = 4.0 / n
+    grid = synth.Grid(2, (n, n, 1), (-2.0, -2.0, 0.0), (h, h, 1.0))
+    shape = synth.Shape(synth.SPHERE, (0.3 * h, 0.7 * h, 0.0), 0.5)
+    op, gp = plan_pair(gcr, synth.Instance("circle8320", grid, shape, HGC, []), HGC)
+    assert op.min_margin > 1e-9
+    check_plan(op, gp, strict_geometry=True)
+
+
+# ---------------------------------------------------------------------------
+# second ghost layer (Sec. 7.1)
+# ---------------------------------------------------------------------------
+
+def _layer2_case(case):
+    if case == "circle128":
+        return synth.circle128(seed=5)
+    if case == "sphere_ragged":
+        h = 2.0 / 61
+        grid = synth.Grid(3, (61, 53, 47), (-1.0, -0.9, -0.8), (h, h, h))
+        shape = synth.Shape(synth.SPHERE, (0.013, -0.02, 0.007), 0.41)
+        return synth.Instance("sphere_ragged", grid, shape, HGC, synth.abc_fields())
+    if case == "star":
+        return synth.stars64(seed=3, ninst=1, nmin=200, nmax=300)[0]
+    return synth.shstar384(seed=2, n=96, nt=4, nph=8)
+
+
+@pytest.mark.parametrize("case", ["circle128", "sphere_ragged", "star", "shstar"])
+@pytest.mark.parametrize("scheme", [CGC, CGC_ES, HGC])
+def test_second_layer_plan_and_fill(gcr, case, scheme):
+    inst = _layer2_case(case)
+    sch = scheme | synth.LAYER2
+    op, gp = plan_pair(gcr, inst, sch)
+    assert op.min_margin > 1e-9
+    op1 = oracle.OraclePlan(inst.grid, inst.shape, scheme)
+    assert op.n_ghost > op1.n_ghost
+    assert gp.n_interface == op.n_interface
+    check_plan(op, gp, strict_geometry=case in ("circle128", "sphere_ragged"))
+    flds = (list(inst.fields) * 2)[:2]
+    run_fill(gcr, op, gp, inst, flds, [DIRICHLET, NEUMANN])
+
+
+def test_second_layer_batch_mixed_flags(gcr):
+    # one batch: instances with and without the second layer
+    insts = synth.stars64(seed=5, ninst=4, nmin=96, nmax=400)
+    schemes = [HGC | synth.LAYER2, HGC, CGC | synth.LAYER2, CGC_ES]
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], schemes)
+    for inst, sch, bp in zip(insts, schemes, B.plans):
+        op = oracle.OraclePlan(inst.grid, inst.shape, sch)
+        check_plan(op, bp)
