@@ -18,7 +18,9 @@ Side measurements on the same GPU (reported beside the headline, never as
            Dirichlet/Neumann data, HGC: one persistent launch (fill + force)
            against the plain per-instance forward (per-level launches);
   fwd_bwd  384^3 grid, spherical-harmonic star, u, v, w, p, HGC: fill + drag
-           forward, then the reverse-level adjoint, against the forward alone.
+           forward, then the reverse-level adjoint, against the forward alone;
+  layer2   the headline sphere with a second ghost layer, against HGC alone;
+  large    the headline sphere on 1024^3 (classification at 1.07 GB).
 
 Prints one JSON line.  Only N=1 is supported (one GPU).
 """
@@ -179,6 +181,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    gcr.forward_times()   # drop the warm-up calls' events
     rec = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -194,6 +197,7 @@ def main():
     ms_total = t0.elapsed_time(t1)
     ms_step = ms_total / args.steps
     value = ng_step / (ms_step * 1e-3)
+    fwd_times = gcr.forward_times()   # events recorded around the kernels in the timed loop
     gcr.set_profiling(False)
     band_segments = seg[-1]
 
@@ -219,9 +223,24 @@ def main():
     cls_bytes = len(SCHEMES) * ncell - 16 * band_segments
     achieved = cls_bytes / (cls_ms * 1e-3) / 1e9
     traffic = kernel_traffic("k_classify", "sphere256x3")
-    roofline = {"bound": "hbm", "kernel": "k_classify", "achieved": round(achieved, 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes": cls_bytes, "avg_ms": round(cls_ms, 5)}
+    roofline_classify = {"bound": "hbm", "kernel": "k_classify", "achieved": round(achieved, 2),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "algorithmic_bytes": cls_bytes, "avg_ms": round(cls_ms, 5)}
+    # the step's longest kernel: the persistent fill + force launch.  Bytes
+    # it must move: per ghost and field, 2^d - 1 stencil values, the boundary
+    # datum and the result (72 B in 3D); per ghost, cell, code, unit, delta
+    # and normal once (60 B); per surface point, position, normal, weight
+    # and anchor (60 B) and 2^d values of each of p, u, v, w (256 B).
+    fwd_ms = fwd_times["forward"]
+    fwd_bytes = ng_step * (4 * 72 + 60) + len(SCHEMES) * nqp * (60 + 4 * 64)
+    fwd_gbs = fwd_bytes / (fwd_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_batch_forward", "achieved": round(fwd_gbs, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
+                "traffic": kernel_traffic("k_batch_forward", "sphere256x3"),
+                "algorithmic_bytes": fwd_bytes, "avg_ms": round(fwd_ms, 5),
+                "note": "latency-bound: 11-12 dependent levels, each a pass of dependent "
+                        "loads and a barrier"}
     plain = {"ms_per_step": round(ms_plain, 4), "ghosts_per_step": ng_plain,
              "ghost_cells_per_s": round(ng_plain / (ms_plain * 1e-3), 1),
              "batched_speedup": round(ms_plain / ms_step, 3)}
@@ -230,6 +249,7 @@ def main():
     if not args.no_extras:
         extras["batched"] = bench_batched(gcr, torch, synth, args.extra_reps)
         extras["fwd_bwd"] = bench_fwd_bwd(gcr, torch, synth, args.extra_reps)
+        extras["layer2"] = bench_layer2(gcr, torch, synth, args.extra_reps)
         extras["large"] = bench_large(gcr, torch, synth, max(3, args.extra_reps // 2))
 
     cpu = None
@@ -249,6 +269,7 @@ def main():
                                "CGC + CGC_ES + HGC per step as one batch, 2048 surface points",
                    "ghosts_per_step": ng_step, "cells": ncell},
         "roofline": roofline,
+        "roofline_classify": roofline_classify,
         "plain_step": plain,
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "wall_s": round(wall, 3),
@@ -390,6 +411,36 @@ def bench_fwd_bwd(gcr, torch, synth, reps):
             "fwd_ghost_cells_per_s": round(ng / (tf * 1e-3), 1),
             "fwd_bwd_ghost_cells_per_s": round(ng / (tfb * 1e-3), 1),
             "dense_grad_zero_ms": round(tz, 4)}
+
+
+def bench_layer2(gcr, torch, synth, reps):
+    """The headline sphere with a second ghost layer (HGC | LAYER2): plan,
+    boundary data, fill of u, v, w, p and force, one plan at a time, beside
+    the same step with HGC alone."""
+    inst = synth.sphere256(seed=0)
+    g = inst.grid
+    dev = torch.device("cuda")
+    fields = [_dev(torch, synth.sample(f, g), torch.float64) for f in inst.fields]
+    kinds = [DIRICHLET, DIRICHLET, DIRICHLET, NEUMANN]
+    q = inst.queries
+    xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
+    F = torch.empty(3, dtype=torch.float64, device=dev)
+    out = {"workload": "sphere256, HGC with a second ghost layer (solid cells with "
+                       "psi <= 1.5 delta n, extended stencils): plan + fill of u,v,w,p + force"}
+    for name, sch in (("layer2", 2 | 4), ("hgc", 2)):
+        info = {}
+
+        def step():
+            plan = gcr.Plan(g, inst.shape, sch)
+            S, nrm = plan.foot_points()
+            plan.fill(fields, kinds, list(bc_sphere_fields(S, nrm)))
+            plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
+            info["ghosts"], info["levels"] = plan.n_ghost, plan.n_levels
+
+        t, _ = _time(torch, step, reps)
+        out[name] = {"ghosts": info["ghosts"], "levels": info["levels"], "step_ms": round(t, 4),
+                     "ghost_cells_per_s": round(info["ghosts"] / (t * 1e-3), 1)}
+    return out
 
 
 def bench_large(gcr, torch, synth, reps):

@@ -274,6 +274,12 @@ gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
  * recorded). */
 gcr_status gcr_set_profiling(int32_t on);
 gcr_status gcr_last_build_times(float* ms);
+/* With profiling on, each gcr_batch_forward also records HIP events around
+ * its two kernels (the surface-point anchor search and the persistent fill
+ * + force launch).  This call waits for the recorded work, writes the mean
+ * ms of each over the calls since the last query to out[0] and out[1] and
+ * their number to out[2] (-1, -1, 0 if none), and clears the record. */
+gcr_status gcr_forward_times(float* out);
 
 /* Layering (Sec. 3.2) of a plan built alone: an instance with at least
  * `min_interface` interface cells is layered by the whole GPU (one grid-wide

@@ -28,7 +28,7 @@ SYMBOLS = [
     "gcr_plan_export", "gcr_plan_foot_points", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_forward",
-    "gcr_set_profiling", "gcr_last_build_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
+    "gcr_set_profiling", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
         L.gcr_batch_plan.argtypes = [vp, i32, P(vp)]
         L.gcr_set_profiling.argtypes = [i32]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
+        L.gcr_forward_times.argtypes = [vp]
         L.gcr_last_build_times.argtypes = [vp]
         L.gcr_batch_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl,
                                         vp, vp]
@@ -364,6 +365,14 @@ def set_wide_layering(min_interface: int = 0):
 
 def set_profiling(on: bool):
     _check(lib().gcr_set_profiling(1 if on else 0), "gcr_set_profiling")
+
+
+def forward_times() -> dict:
+    """Mean ms of the batched forward's anchor search and fill + force
+    kernels over the calls made with profiling on since the last query."""
+    buf = (ctypes.c_float * 3)()
+    _check(lib().gcr_forward_times(buf), "gcr_forward_times")
+    return {"anchor": buf[0], "forward": buf[1], "calls": int(buf[2])}
 
 
 def last_build_times() -> dict:

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -249,6 +250,37 @@ void gcr_batch_release_state(const gcr_batch* b) {
     }
 }
 
+// With profiling on, every batched forward records HIP events around its two
+// kernels; gcr_forward_times averages them.
+namespace {
+std::mutex g_fwd_ev_mu;
+std::vector<std::array<hipEvent_t, 3>> g_fwd_ev;
+}  // namespace
+
+extern "C" gcr_status gcr_forward_times(float* out) {
+  if (!out) return GCR_E_ARG;
+  std::lock_guard<std::mutex> lk(g_fwd_ev_mu);
+  double a = 0.0, f = 0.0;
+  int n = 0;
+  for (auto& e : g_fwd_ev) {
+    float ma = 0.f, mf = 0.f;
+    if (hipEventSynchronize(e[2]) == hipSuccess &&
+        hipEventElapsedTime(&ma, e[0], e[1]) == hipSuccess &&
+        hipEventElapsedTime(&mf, e[1], e[2]) == hipSuccess) {
+      a += ma;
+      f += mf;
+      ++n;
+    }
+    for (hipEvent_t x : e) (void)hipEventDestroy(x);
+  }
+  g_fwd_ev.clear();
+  (void)hipGetLastError();
+  out[0] = n ? (float)(a / n) : -1.f;
+  out[1] = n ? (float)(f / n) : -1.f;
+  out[2] = (float)n;
+  return GCR_OK;
+}
+
 static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int threads, int grid,
                                double* F, hipStream_t st) {
   BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
@@ -366,6 +398,11 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   C.order = reinterpret_cast<const int32_t*>(d + o_order);
   C.aoff = nq ? reinterpret_cast<const int64_t*>(d + o_aoff) : nullptr;
   C.anchor = S->d_anchor;
+  std::array<hipEvent_t, 3> ev{};
+  bool timed = profiling_on();
+  for (auto& e : ev)
+    if (timed && hipEventCreate(&e) != hipSuccess) timed = false;
+  if (timed) (void)hipEventRecord(ev[0], st);
   if (npts > 0) {
     BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
     if (dim == 2) {
@@ -444,5 +481,13 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[key] = {bt_, bg};
   }
-  return launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
+  if (timed) (void)hipEventRecord(ev[1], st);
+  const gcr_status rs =
+      launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
+  if (timed) {
+    (void)hipEventRecord(ev[2], st);
+    std::lock_guard<std::mutex> lk(g_fwd_ev_mu);
+    g_fwd_ev.push_back(ev);
+  }
+  return rs;
 }

@@ -339,47 +339,74 @@ static void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* l
 // is among them: a walk from it through its foot point reaches a fluid
 // centre within that box (delta n <= h_max, psi 1-Lipschitz), and the last
 // solid cell before it is a solid interface cell.  One workgroup per chunk
-// of the interface chunk list (the grid covers every chunk; the rest exit).
+// of the interface chunk list (the grid covers every chunk; the rest exit):
+// the chunk's solid interface cells go to an LDS list, then the workgroup
+// walks the (cell, box offset) pairs, eight loads in flight per thread
+// before any mark is set.
 __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts, int ninst,
                                                  const int64_t* __restrict__ chunk_start,
                                                  const int32_t* __restrict__ chunk_list,
                                                  const int32_t* __restrict__ nlist,
                                                  int8_t* __restrict__ tags) {
+  __shared__ int s_cell[kChunk];
+  __shared__ int s_n;
   if ((int)blockIdx.x >= nlist[0]) return;
   const int64_t chunk = chunk_list[blockIdx.x];
   const int ii = find_inst(chunk_start, ninst, chunk);
   const Inst& I = insts[ii];
   if (!I.layer2) return;
-  const GridD& g = I.g;
-  double hmax = g.h[0];
-  for (int a = 1; a < g.dim; ++a) hmax = fmax(hmax, g.h[a]);
-  int R[3] = {0, 0, 0};
-  for (int a = 0; a < g.dim; ++a)
-    R[a] = (int)floor((1.5 + 0.5 * sqrt((double)g.dim)) * hmax / g.h[a]) + 1;
-  uint32_t* words = reinterpret_cast<uint32_t*>(tags);
+  const GridD g = I.g;
+  const int8_t* T = tags + I.cell_off;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
   const int64_t base = (chunk - I.chunk_off) * kChunk;
   for (int t = threadIdx.x; t < kChunk; t += 256) {
     const int64_t c = base + t;
-    if (c >= g.ncell) break;
-    if ((tags[I.cell_off + c] & 0x41) != 0x41) continue;   // solid interface cells
-    int i, j, k;
-    unlinear(g, (int)c, i, j, k);
-    for (int dk = -R[2]; dk <= R[2]; ++dk) {
-      const int kk = k + dk;
-      if (kk < 0 || kk >= g.n[2]) continue;
-      for (int dj = -R[1]; dj <= R[1]; ++dj) {
-        const int jj = j + dj;
-        if (jj < 0 || jj >= g.n[1]) continue;
-        for (int di = -R[0]; di <= R[0]; ++di) {
-          const int ix = i + di;
-          if (ix < 0 || ix >= g.n[0]) continue;
-          const int64_t b = I.cell_off + linear(g, ix, jj, kk);
-          if (tags[b] != 1) continue;   // plain solid, not yet marked
-          // the tag array is padded to 256 bytes, so its last word is whole
-          atomicOr(&words[b >> 2], 0x20u << (8 * (int)(b & 3)));
+    if (c < g.ncell && (T[c] & 0x41) == 0x41) s_cell[atomicAdd(&s_n, 1)] = (int)c;
+  }
+  __syncthreads();
+  double hmax = g.h[0];
+  for (int a = 1; a < g.dim; ++a) hmax = fmax(hmax, g.h[a]);
+  int R[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+  for (int a = 0; a < g.dim; ++a) {
+    R[a] = (int)floor((1.5 + 0.5 * sqrt((double)g.dim)) * hmax / g.h[a]) + 1;
+    W[a] = 2 * R[a] + 1;
+  }
+  const int box = W[0] * W[1] * W[2];
+  const int64_t items = (int64_t)s_n * box;
+  uint32_t* words = reinterpret_cast<uint32_t*>(tags);
+  constexpr int kFly = 8;
+  for (int64_t i0 = threadIdx.x; i0 < items; i0 += 256 * kFly) {
+    int64_t at[kFly];
+    int8_t v[kFly];
+#pragma unroll
+    for (int u = 0; u < kFly; ++u) {
+      const int64_t it = i0 + (int64_t)u * 256;
+      at[u] = -1;
+      v[u] = 0;
+      if (it < items) {
+        const int c = s_cell[it / box];
+        int o = (int)(it % box);
+        const int di = o % W[0] - R[0];
+        o /= W[0];
+        const int dj = o % W[1] - R[1];
+        const int dk = o / W[1] - R[2];
+        int i, j, k;
+        unlinear(g, c, i, j, k);
+        i += di;
+        j += dj;
+        k += dk;
+        if (i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2]) {
+          at[u] = I.cell_off + linear(g, i, j, k);
+          v[u] = tags[at[u]];
         }
       }
     }
+#pragma unroll
+    for (int u = 0; u < kFly; ++u)
+      if (at[u] >= 0 && v[u] == 1)   // plain solid, not yet marked
+        // the tag array is padded to 256 bytes, so its last word is whole
+        atomicOr(&words[at[u] >> 2], 0x20u << (8 * (int)(at[u] & 3)));
   }
 }
 
@@ -396,8 +423,18 @@ __global__ __launch_bounds__(256) void k_count_marks(const Inst* __restrict__ in
   __syncthreads();
   const int64_t base = (chunk - I.chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
   int n = 0;
-  for (int b = 0; b < kSeg; ++b)
-    if (base + b < I.g.ncell && (tags[I.cell_off + base + b] & 0x60)) ++n;
+  if (base + kSeg <= I.g.ncell) {
+    const uint4 w = *reinterpret_cast<const uint4*>(tags + I.cell_off + base);
+    const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t m = q[b] & 0x60606060u;   // per byte: bit 0 set iff 0x20 or 0x40 is
+      n += __popc(((m >> 5) | (m >> 6)) & 0x01010101u);
+    }
+  } else {
+    for (int b = 0; b < kSeg; ++b)
+      if (base + b < I.g.ncell && (tags[I.cell_off + base + b] & 0x60)) ++n;
+  }
   if (n) atomicAdd(&s, n);
   __syncthreads();
   if (threadIdx.x == 0) chunk_cnt[chunk] = s;
@@ -978,6 +1015,7 @@ struct StageEvents {
 };
 
 void set_profiling(int on) { g_profiling.store(on ? 1 : 0); }
+bool profiling_on() { return g_profiling.load() != 0; }
 
 static std::atomic<int64_t> g_wide_min{kWideMinInterface};
 void set_wide_layering(int64_t v) { g_wide_min.store(v > 0 ? v : kWideMinInterface); }
