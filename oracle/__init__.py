@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
-                ("h", ctypes.c_double * 3)]
+                ("h", ctypes.c_double * 3), ("faces", ctypes.c_void_p * 3)]
 
 
 class _Shape(ctypes.Structure):
@@ -109,12 +109,20 @@ def _vp(a):
 
 
 def make_grid(grid) -> _Grid:
+    """The ctypes grid; a stretched grid's face arrays are kept alive on it."""
     g = _Grid()
     g.dim = grid.dim
+    faces = getattr(grid, "faces", None)
+    g._keep = []
     for i in range(3):
         g.n[i] = int(grid.n[i]) if i < grid.dim else 1
         g.lo[i] = float(grid.lo[i]) if i < grid.dim else 0.0
         g.h[i] = float(grid.h[i]) if i < grid.dim else 1.0
+        g.faces[i] = None
+        if faces is not None and i < grid.dim and faces[i] is not None:
+            f = np.ascontiguousarray(faces[i], dtype=np.float64)
+            g._keep.append(f)
+            g.faces[i] = f.ctypes.data
     return g
 
 

@@ -55,6 +55,7 @@ struct orc_plan {
   int32_t* blk_off;     /* [nblk+1] */
   int64_t* blk_mem;     /* members, canonical positions, ascending */
   double margins[7];
+  double* faces[3];     /* owned copies of a stretched grid's faces */
 };
 
 #define ORC_MAX_BLOCK 8
@@ -64,7 +65,39 @@ struct orc_plan {
 /* ------------------------------------------------------------------------- */
 
 static double centre(const orc_grid* g, int ax, int64_t i) {
+  if (g->faces[ax]) return 0.5 * (g->faces[ax][i] + g->faces[ax][i + 1]);
   return g->lo[ax] + ((double)i + 0.5) * g->h[ax];
+}
+
+/* local spacing of cell i along axis ax: its width */
+static double width(const orc_grid* g, int ax, int64_t i) {
+  if (g->faces[ax]) return g->faces[ax][i + 1] - g->faces[ax][i];
+  return g->h[ax];
+}
+
+/* x_2 - x_1 along axis ax for a stencil from cell i displaced by er cells
+ * (stretched: the difference of the two centres; a displacement off the grid,
+ * possible only along an axis the normal does not leave, uses the width) */
+static double span(const orc_grid* g, int ax, int64_t i, int er) {
+  if (!g->faces[ax]) return (double)er * g->h[ax];
+  if (i + er < 0 || i + er >= g->n[ax]) return (double)er * width(g, ax, i);
+  return centre(g, ax, i + er) - centre(g, ax, i);
+}
+
+/* index of the cell holding coordinate x along axis ax (outside the grid:
+ * below 0 or at least n) */
+static int64_t cell_of(const orc_grid* g, int ax, double x) {
+  if (!g->faces[ax]) return (int64_t)floor((x - g->lo[ax]) / g->h[ax]);
+  const double* f = g->faces[ax];
+  const int64_t n = g->n[ax];
+  if (x < f[0]) return -1;
+  if (x >= f[n]) return n;
+  int64_t lo = 0, hi = n - 1;   /* the last i with f[i] <= x */
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) / 2;
+    if (f[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 static void unlinear(const orc_grid* g, int64_t c, int64_t ijk[3]) {
@@ -545,6 +578,7 @@ void orc_plan_destroy(orc_plan* p) {
   free(p->delta); free(p->nrm); free(p->psi); free(p->r); free(p->e);
   free(p->sten); free(p->sorted_cell); free(p->sorted_pos);
   free(p->blk); free(p->blk_off); free(p->blk_mem);
+  for (int i = 0; i < 3; ++i) free(p->faces[i]);
   free(p);
 }
 
@@ -574,15 +608,35 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
   scheme &= ~ORC_LAYER2;
   if (scheme < 0 || scheme > 2) return ORC_E_ARG;
   int dim = g->dim;
-  for (int i = 0; i < dim; ++i)
-    if (g->n[i] < 1 || !(g->h[i] > 0.0)) return ORC_E_ARG;
+  int stretched = 0;
+  for (int i = 0; i < dim; ++i) {
+    if (g->n[i] < 1) return ORC_E_ARG;
+    if (g->faces[i]) {
+      stretched = 1;
+      for (int64_t k = 0; k < g->n[i]; ++k)
+        if (!(g->faces[i][k + 1] > g->faces[i][k]) || !isfinite(g->faces[i][k + 1]))
+          return ORC_E_ARG;
+    } else if (!(g->h[i] > 0.0)) {
+      return ORC_E_ARG;
+    }
+  }
+  if (stretched && layer2) return ORC_E_UNSUPPORTED;
   if (s->kind == ORC_SHSTAR && dim != 3) return ORC_E_ARG;
   if ((s->kind == ORC_STAR2D || s->kind == ORC_AIRFOIL) && dim != 2) return ORC_E_ARG;
 
   orc_plan* p = (orc_plan*)calloc(1, sizeof(orc_plan));
   if (!p) return ORC_E_NOMEM;
   p->g = *g;
-  if (dim == 2) { p->g.n[2] = 1; p->g.lo[2] = 0.0; p->g.h[2] = 1.0; }
+  if (dim == 2) { p->g.n[2] = 1; p->g.lo[2] = 0.0; p->g.h[2] = 1.0; p->g.faces[2] = NULL; }
+  for (int i = 0; i < dim; ++i) {
+    p->faces[i] = NULL;
+    if (!g->faces[i]) continue;
+    p->faces[i] = (double*)malloc(sizeof(double) * (g->n[i] + 1));
+    if (!p->faces[i]) { orc_plan_destroy(p); return ORC_E_NOMEM; }
+    memcpy(p->faces[i], g->faces[i], sizeof(double) * (g->n[i] + 1));
+    p->g.faces[i] = p->faces[i];
+    p->g.lo[i] = p->faces[i][0];
+  }
   p->s = *s;
   if (s->ncoef > 0) {
     int nc = (s->kind == ORC_STAR2D) ? 2 * s->ncoef : s->ncoef;
@@ -596,8 +650,10 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
   int64_t N = G->n[0] * G->n[1] * G->n[2];
   p->ncell = N;
   for (int i = 0; i < 7; ++i) p->margins[i] = (i >= 4) ? 0.0 : INFINITY;
-  double hmin = G->h[0];
-  for (int i = 1; i < dim; ++i) if (G->h[i] < hmin) hmin = G->h[i];
+  double hmin = INFINITY;   /* smallest cell width: the unit of the margins */
+  for (int i = 0; i < dim; ++i)
+    for (int64_t k = 0; k < (G->faces[i] ? G->n[i] : 1); ++k)
+      if (width(G, i, k) < hmin) hmin = width(G, i, k);
 
   /* 1. classification by cell centre: fluid 0, solid 1 (Sec. 3.1) */
   uint8_t* solid = (uint8_t*)malloc(N);
@@ -688,9 +744,12 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     double S[3] = {0, 0, 0}, n[3] = {0, 0, 0}, psi = 0.0;
     int st = orc_shape_project(&p->s, dim, x, solid[c], S, n, &psi);
     if (st != ORC_OK) { status = st; break; }
-    /* Eq. delta_n */
+    /* Eq. delta_n, with the cell's own widths */
     double sum = 0.0;
-    for (int i = 0; i < dim; ++i) sum += (n[i] / G->h[i]) * (n[i] / G->h[i]);
+    for (int i = 0; i < dim; ++i) {
+      const double w = width(G, i, ijk[i]);
+      sum += (n[i] / w) * (n[i] / w);
+    }
     double dn = 1.0 / sqrt(sum);
     int8_t t = (int8_t)solid[c];
     if (scheme == ORC_HGC) {
@@ -758,6 +817,8 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
   int64_t* gst = (int64_t*)malloc(sizeof(int64_t) * 7 * na);
   int64_t* dep = (int64_t*)malloc(sizeof(int64_t) * 7 * na); /* linear-order ghost ids */
   for (int64_t j = 0; j < ng; ++j) {
+    int64_t ijk[3];
+    unlinear(G, gcell[j], ijk);
     for (int i = 0; i < 3; ++i) {
       double ni = gn[3 * j + i];
       gd[3 * j + i] = gpsi[j] * ni;
@@ -767,7 +828,7 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     }
     if (scheme == ORC_CGC_ES || gext[j]) {
       for (int i = 0; i < dim; ++i) {
-        double q = 2.0 * fabs(gd[3 * j + i]) / G->h[i];
+        double q = 2.0 * fabs(gd[3 * j + i]) / width(G, i, ijk[i]);
         int ri = (int)ceil(q);
         if (ri < 1) ri = 1;
         gr[3 * j + i] = ri;
@@ -777,8 +838,6 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
         if (m < p->margins[2]) p->margins[2] = m;
       }
     }
-    int64_t ijk[3];
-    unlinear(G, gcell[j], ijk);
     for (int k = 0; k < np; ++k) {
       const int* sb = subset(dim, k);
       int skip = 0;
@@ -961,9 +1020,13 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     p->sorted_cell[j] = gcell[j];
     p->sorted_pos[j] = pos;
     /* normalised boundary distance alpha_i = (x_s - x_1)/(x_2 - x_1) */
-    for (int i = 0; i < dim; ++i) {
-      double a = gd[3 * j + i] / ((double)ge[3 * j + i] * gr[3 * j + i] * G->h[i]);
-      if (a > p->margins[4 + i]) p->margins[4 + i] = a;
+    {
+      int64_t ijk[3];
+      unlinear(G, gcell[j], ijk);
+      for (int i = 0; i < dim; ++i) {
+        double a = gd[3 * j + i] / span(G, i, ijk[i], ge[3 * j + i] * gr[3 * j + i]);
+        if (a > p->margins[4 + i]) p->margins[4 + i] = a;
+      }
     }
   }
   /* coupled units: members in canonical order */
@@ -1032,9 +1095,11 @@ void orc_margins(const orc_plan* p, double* out) {
 static void local_coords(const orc_plan* p, int64_t g, double x2[3], double xs[3],
                          double n[3]) {
   int64_t ng = p->ng;
+  int64_t ijk[3];
+  unlinear(&p->g, p->cell[g], ijk);
   for (int i = 0; i < 3; ++i) {
     if (i < p->dim) {
-      x2[i] = (double)p->e[i * ng + g] * (double)p->r[i * ng + g] * p->g.h[i];
+      x2[i] = span(&p->g, i, ijk[i], p->e[i * ng + g] * p->r[i * ng + g]);
       xs[i] = p->delta[i * ng + g];
       n[i] = p->nrm[i * ng + g];
     } else {
@@ -1366,7 +1431,7 @@ int orc_surface_ghost(const orc_plan* p, int nf, const double* fields,
 static int64_t find_anchor(const orc_plan* p, const double* x) {
   int dim = p->dim;
   int64_t qi[3] = {0, 0, 0};
-  for (int i = 0; i < dim; ++i) qi[i] = (int64_t)floor((x[i] - p->g.lo[i]) / p->g.h[i]);
+  for (int i = 0; i < dim; ++i) qi[i] = cell_of(&p->g, i, x[i]);
   int64_t best = -1;
   double bd = INFINITY;
   int64_t kz0 = dim == 3 ? qi[2] - 2 : 0, kz1 = dim == 3 ? qi[2] + 2 : 0;

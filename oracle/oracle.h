@@ -32,11 +32,16 @@ enum { ORC_CGC = 0, ORC_CGC_ES = 1, ORC_HGC = 2 };
 enum { ORC_LAYER2 = 4 };
 enum { ORC_DIRICHLET = 0, ORC_NEUMANN = 1 };
 
+/* Uniform spacing h per axis from lo, or, where faces[i] is given, the n[i]
+ * + 1 cell faces of axis i (strictly increasing; lo and h then unused on
+ * that axis): a stretched grid, with cell centres midway between faces and
+ * the local spacing of a cell its width. */
 typedef struct {
   int32_t dim, pad;
   int64_t n[3];
   double lo[3];
   double h[3];
+  const double* faces[3];
 } orc_grid;
 
 /*

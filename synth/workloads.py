@@ -57,17 +57,28 @@ class SplitMix64:
 
 @dataclass
 class Grid:
+    """Uniform spacing h per axis from lo, or, where faces[axis] is given, a
+    stretched axis: its n + 1 cell faces (lo and h then nominal only)."""
     dim: int
     n: tuple
     lo: tuple
     h: tuple
+    faces: tuple = None
 
     @property
     def n_cells(self) -> int:
         return int(np.prod(self.n[: self.dim]))
 
     def centres(self, axis: int) -> np.ndarray:
+        if self.faces is not None and self.faces[axis] is not None:
+            f = np.asarray(self.faces[axis], dtype=np.float64)
+            return 0.5 * (f[:-1] + f[1:])
         return self.lo[axis] + (np.arange(self.n[axis]) + 0.5) * self.h[axis]
+
+    def widths(self, axis: int) -> np.ndarray:
+        if self.faces is not None and self.faces[axis] is not None:
+            return np.diff(np.asarray(self.faces[axis], dtype=np.float64))
+        return np.full(self.n[axis], float(self.h[axis]))
 
     def mesh(self):
         """Cell-centre coordinate arrays, flattened x-fastest."""
@@ -256,6 +267,45 @@ def circle128(seed: int = 0, scheme: int = HGC, nq: int = 256) -> Instance:
     f, g = _trig2d()
     return Instance("circle128", grid, shape, scheme, [Field("u", f, g, DIRICHLET)],
                     circle_queries(c, 0.5, nq))
+
+
+def stretched_faces(n: int, lo: float, hi: float, ratio: float) -> np.ndarray:
+    """n cells on [lo, hi] whose widths grow geometrically by `ratio` per
+    cell from the middle of the axis outward (the paper's grids are
+    stretched by a fixed ratio away from the body)."""
+    k = np.abs(np.arange(n) - (n - 1) / 2.0)
+    w = ratio ** k
+    w *= (hi - lo) / w.sum()
+    f = np.concatenate([[lo], lo + np.cumsum(w)])
+    f[-1] = hi
+    return f
+
+
+def circle_stretched(seed: int = 0, scheme: int = HGC, n: int = 128, ratio: float = 1.02,
+                     nq: int = 256) -> Instance:
+    """The circle of circle128 on a grid stretched by `ratio` per cell."""
+    rng = SplitMix64(0xC1C15700 + seed)
+    fx, fy = stretched_faces(n, -2.0, 2.0, ratio), stretched_faces(n, -2.0, 2.0, ratio * 1.005)
+    h = 4.0 / n
+    grid = Grid(2, (n, n, 1), (-2.0, -2.0, 0.0), (h, h, 1.0), (fx, fy, None))
+    c = (rng.uniform(0, h), rng.uniform(0, h), 0.0)
+    shape = Shape(SPHERE, c, 0.5)
+    f, g = _trig2d()
+    return Instance("circle_stretched", grid, shape, scheme, [Field("u", f, g, DIRICHLET)],
+                    circle_queries(c, 0.5, nq))
+
+
+def sphere_stretched(seed: int = 0, scheme: int = HGC, n: int = 48,
+                     ratio: float = 1.03) -> Instance:
+    """The sphere of sphere256 on an n^3 grid stretched by `ratio` per cell."""
+    rng = SplitMix64(0x5F357000 + seed)
+    h = 2.0 / n
+    faces = tuple(stretched_faces(n, -1.0, 1.0, ratio + 0.004 * a) for a in range(3))
+    grid = Grid(3, (n, n, n), (-1.0, -1.0, -1.0), (h, h, h), faces)
+    c = (rng.uniform(0, h), rng.uniform(0, h), rng.uniform(0, h))
+    shape = Shape(SPHERE, c, 0.3)
+    return Instance(f"sphere_stretched{n}", grid, shape, scheme, abc_fields(),
+                    sphere_queries(c, 0.3))
 
 
 def sphere256(seed: int = 0, scheme: int = HGC, n: int = 256) -> Instance:
