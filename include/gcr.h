@@ -12,8 +12,9 @@
  *
  * Conventions shared by every call
  *  - Cells are cell-centred: cell (i,j,k) has centre lo + (idx + 1/2) h per
- *    axis and linear index i + n[0]*(j + n[1]*k) (x fastest).  A grid holds
- *    fewer than 2^31 cells.
+ *    axis (midway between its faces on a stretched axis) and linear index
+ *    i + n[0]*(j + n[1]*k) (x fastest).  A grid holds fewer than 2^31
+ *    cells.
  *  - Fields are dense FP64 arrays in that layout, one device pointer per field.
  *  - "device" pointers are HIP device memory owned by the caller; "host"
  *    pointers are host memory owned by the caller.  The library keeps no
@@ -87,6 +88,15 @@ typedef struct {
   int64_t n[3];    /* cells per axis (n[2] ignored in 2D) */
   double lo[3];    /* lower corner */
   double h[3];     /* uniform spacing per axis, > 0 */
+  /* Stretched axes (the flows of Secs. 8.1-8.2 run on grids stretched toward
+   * the outer boundaries; Sec. 7.1 takes the local spacing per direction):
+   * faces[a], if not NULL, holds host double [n[a] + 1] cell faces of axis
+   * a, strictly increasing (copied by the library; lo[a], h[a] then
+   * unused).  Cell centres lie midway between faces; Eq. delta_n and Eq.
+   * stencil_anisotropic take the local cell widths; a stencil's x_2 - x_1
+   * is the difference of the two cell centres.  Not combined with
+   * GCR_LAYER2 (GCR_E_UNSUPPORTED). */
+  const double* faces[3];
 } gcr_grid;
 
 typedef struct {

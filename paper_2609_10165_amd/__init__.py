@@ -42,7 +42,7 @@ class GcrError(RuntimeError):
 class _Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
-                ("h", ctypes.c_double * 3)]
+                ("h", ctypes.c_double * 3), ("faces", ctypes.c_void_p * 3)]
 
 
 class _Shape(ctypes.Structure):
@@ -138,12 +138,22 @@ def _ptr_array(ts, dtype=torch.float64):
 
 
 def make_grid(grid) -> _Grid:
+    """The ctypes grid.  A stretched axis (grid.faces[a] not None) passes its
+    n + 1 faces; the arrays are kept alive on the returned object."""
+    import numpy as np
     g = _Grid()
     g.dim = int(grid.dim)
+    faces = getattr(grid, "faces", None)
+    g._keep = []
     for i in range(3):
         g.n[i] = int(grid.n[i]) if i < grid.dim else 1
         g.lo[i] = float(grid.lo[i]) if i < grid.dim else 0.0
         g.h[i] = float(grid.h[i]) if i < grid.dim else 1.0
+        g.faces[i] = None
+        if faces is not None and i < grid.dim and faces[i] is not None:
+            f = np.ascontiguousarray(faces[i], dtype=np.float64)
+            g._keep.append(f)
+            g.faces[i] = f.ctypes.data
     return g
 
 
@@ -309,7 +319,8 @@ class Batch:
     def __init__(self, grids, shapes, schemes, stream=None):
         L = lib()
         n = len(grids)
-        G = (_Grid * n)(*[make_grid(g) for g in grids])
+        gs = [make_grid(g) for g in grids]   # keeps stretched faces alive for the call
+        G = (_Grid * n)(*gs)
         keep = [make_shape(s) for s in shapes]
         S = (_Shape * n)(*[k[0] for k in keep])
         sch = (ctypes.c_int32 * n)(*[int(s) for s in schemes])

@@ -245,7 +245,9 @@ __device__ __forceinline__ void weights_of(const PlanD& P, int g, int bc, double
     dl[a] = a < D ? P.dl[a][g] : 0.0;
     nn[a] = a < D ? P.nn[a][g] : 0.0;
   }
-  ghost_weights<D>(dl, nn, P.code[g], P.g.h, bc, w);
+  double X[3];
+  stencil_span(P.g, P.code[g], P.cell[g], X);
+  ghost_weights<D>(dl, nn, X, bc, w);
 }
 
 __device__ __forceinline__ int field_bc(const AdjArgs& A, int f, int g) {
@@ -477,6 +479,8 @@ __global__ __launch_bounds__(256) void k_sadj_seed(SurfAdjArgs S) {
   int i, j, k;
   unlinear(P.g, P.cell[g], i, j, k);
   const int ijk[3] = {i, j, k};
+  double X[3];
+  stencil_span(P.g, code, P.cell[g], X);
   // one field at a time keeps the 2^D corner sums in registers
   for (int f = 0; f < S.nf; ++f) {
     double acc[8];
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(256) void k_sadj_seed(SurfAdjArgs S) {
 #pragma unroll
       for (int m = 0; m < (1 << D); ++m) {
         double cv, cg[3];
-        box_coeffs<D>(rel, code, P.g.h, m, cv, cg);
+        box_coeffs<D>(rel, X, m, cv, cg);
         double s = cv * gv;
 #pragma unroll
         for (int a = 0; a < D; ++a) s += cg[a] * gg[a];

@@ -30,7 +30,9 @@ __global__ __launch_bounds__(256) void k_weights(PlanD P, int bc, double* __rest
     dl[a] = a < D ? P.dl[a][p] : 0.0;
     nn[a] = a < D ? P.nn[a][p] : 0.0;
   }
-  ghost_weights<D>(dl, nn, P.code[p], P.g.h, bc, wk);
+  double X[3];
+  stencil_span(P.g, P.code[p], P.cell[p], X);
+  ghost_weights<D>(dl, nn, X, bc, wk);
 #pragma unroll
   for (int k = 0; k < (1 << D); ++k) w[(int64_t)k * P.ng + p] = wk[k];
 }
@@ -100,13 +102,14 @@ __global__ __launch_bounds__(256) void k_surface_ghost(SurfArgs S) {
   const PlanD& P = S.P;
   if (p >= P.ng) return;
   const uint32_t code = P.code[p];
-  double rel[3];
+  double rel[3], X[3];
+  stencil_span(P.g, code, P.cell[p], X);
 #pragma unroll
   for (int a = 0; a < 3; ++a) rel[a] = a < D ? P.dl[a][p] : 0.0;
   for (int f = 0; f < S.nf; ++f) {
     double v[8], val, grad[3];
     corner_values<D>(P, p, S.f[f], v);
-    box_eval<D>(rel, code, P.g.h, v, val, grad);
+    box_eval<D>(rel, X, v, val, grad);
     if (S.val) S.val[(int64_t)f * P.ng + p] = val;
     if (S.grad)
 #pragma unroll
@@ -143,9 +146,10 @@ __global__ __launch_bounds__(256) void k_surface_query(SurfArgs S, int64_t nq,
     double rel[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
-    double v[8];
+    double v[8], X[3];
+    stencil_span(P.g, code, P.cell[g], X);
     corner_values<D>(P, g, S.f[f], v);
-    box_eval<D>(rel, code, P.g.h, v, val, grad);
+    box_eval<D>(rel, X, v, val, grad);
   }
   if (S.val) S.val[(int64_t)f * nq + q] = val;
   if (S.grad)
@@ -200,9 +204,10 @@ __global__ __launch_bounds__(256) void k_forces(PlanD P, ForceArgs F, double* __
     double rel[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
-    double v[8];
+    double v[8], X[3];
+    stencil_span(P.g, code, P.cell[g], X);
     corner_values<D>(P, g, sub == 0 ? F.p : F.u[sub - 1], v);
-    box_eval<D>(rel, code, P.g.h, v, val, grad);
+    box_eval<D>(rel, X, v, val, grad);
   }
   // gu[c][a] = d u_c / d x_a, from lane 1 + c of this group
   double gu[3][3];

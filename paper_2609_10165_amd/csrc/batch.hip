@@ -131,7 +131,9 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
 #pragma unroll
           for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
           corner_values<D>(P, g, F, v);
-          box_eval<D>(rel, P.code[g], P.g.h, v, val, gr);
+          double X[3];
+          stencil_span(P.g, P.code[g], P.cell[g], X);
+          box_eval<D>(rel, X, v, val, gr);
         }
         const double wt = wq[q];
         if (isp) {

@@ -108,8 +108,8 @@ __global__ __launch_bounds__(256) void k_spans(const Inst* __restrict__ insts, i
     }
     double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < g.dim; ++a) {
-      lo[a] = centre(g, a, mn[a]) - g.h[a];
-      hi[a] = centre(g, a, mx[a]) + g.h[a];
+      lo[a] = centre_below(g, a, mn[a]);
+      hi[a] = centre_above(g, a, mx[a]);
     }
     r = (int8_t)box_settled(I.s, g.dim, lo, hi);
   }
@@ -185,14 +185,14 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
       if (nvalid == kSeg && i0 + kSeg - 1 < g.n[0]) {
         // radial culling on the segment's box (face neighbours included)
         double lo[3], hi[3];
-        lo[0] = centre(g, 0, i0) - g.h[0];
-        hi[0] = centre(g, 0, i0 + kSeg - 1) + g.h[0];
-        lo[1] = centre(g, 1, j) - g.h[1];
-        hi[1] = centre(g, 1, j) + g.h[1];
+        lo[0] = centre_below(g, 0, i0);
+        hi[0] = centre_above(g, 0, i0 + kSeg - 1);
+        lo[1] = centre_below(g, 1, j);
+        hi[1] = centre_above(g, 1, j);
         lo[2] = hi[2] = 0.0;
         if (g.dim == 3) {
-          lo[2] = centre(g, 2, k) - g.h[2];
-          hi[2] = centre(g, 2, k) + g.h[2];
+          lo[2] = centre_below(g, 2, k);
+          hi[2] = centre_above(g, 2, k);
         }
         settled = box_settled(S, g.dim, lo, hi);
         mode = settled >= 0 ? 1 : 2;
@@ -205,18 +205,23 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
         const bool one_row = p1[1] == j && p1[2] == k;
         double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
         int seg_a[3] = {i0, j, k}, seg_b[3] = {one_row ? p1[0] : g.n[0] - 1, j, k};
-        for (int a = 0; a < g.dim; ++a) {
-          lo[a] = centre(g, a, seg_a[a]) - g.h[a];
-          hi[a] = centre(g, a, seg_b[a]) + g.h[a];
-        }
+        // (axes unrolled: a runtime index into g would move it to scratch)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if (a < g.dim) {
+            lo[a] = centre_below(g, a, seg_a[a]);
+            hi[a] = centre_above(g, a, seg_b[a]);
+          }
         // (with rows of 16 cells or more a segment meets at most two rows)
         int sa = g.n[0] >= kSeg ? box_settled(S, g.dim, lo, hi) : -1;
         if (!one_row && sa >= 0) {
           const int c0[3] = {0, p1[1], p1[2]};
-          for (int a = 0; a < g.dim; ++a) {
-            lo[a] = centre(g, a, c0[a]) - g.h[a];
-            hi[a] = centre(g, a, p1[a]) + g.h[a];
-          }
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            if (a < g.dim) {
+              lo[a] = centre_below(g, a, c0[a]);
+              hi[a] = centre_above(g, a, p1[a]);
+            }
           if (box_settled(S, g.dim, lo, hi) != sa) sa = -1;
         }
         settled = sa;
@@ -236,8 +241,9 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
           bool sd = cell_solid(g, S, i, jj, kk);
           bool iface = false;
           int q[3] = {i, jj, kk};
-          for (int a = 0; a < g.dim && !iface; ++a)
-            for (int sg = -1; sg <= 1; sg += 2) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            for (int sg = -1; sg <= 1 && a < g.dim && !iface; sg += 2) {
               int qq[3] = {q[0], q[1], q[2]};
               qq[a] += sg;
               if (qq[a] < 0 || qq[a] >= g.n[a]) continue;

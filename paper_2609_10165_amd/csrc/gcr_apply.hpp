@@ -153,7 +153,7 @@ template <int D>
 __device__ __forceinline__ int find_anchor(const PlanD& P, const double x[3]) {
   int qi[3] = {0, 0, 0};
 #pragma unroll
-  for (int a = 0; a < D; ++a) qi[a] = (int)floor((x[a] - P.g.lo[a]) / P.g.h[a]);
+  for (int a = 0; a < D; ++a) qi[a] = cell_of(P.g, a, x[a]);
   int best = -1;
   double bd = 1e300;
   const int z0 = D == 3 ? qi[2] - 2 : 0, z1 = D == 3 ? qi[2] + 2 : 0;
@@ -200,7 +200,7 @@ __device__ __forceinline__ int find_anchor_group(const PlanD& P, const double x[
   constexpr int NC = D == 3 ? 125 : 25;
   int qi[3] = {0, 0, 0};
 #pragma unroll
-  for (int a = 0; a < D; ++a) qi[a] = (int)floor((x[a] - P.g.lo[a]) / P.g.h[a]);
+  for (int a = 0; a < D; ++a) qi[a] = cell_of(P.g, a, x[a]);
   double bd = 1e300;
   int bc = 0x7fffffff, bg = -1;
   if (active) {

@@ -37,6 +37,7 @@ struct GridD {
   double lo[3];
   double h[3];
   int64_t ncell;
+  const double* face[3];   // stretched axis: n + 1 cell faces (device), else null
 };
 
 struct ShapeD {
@@ -139,7 +140,41 @@ __device__ __forceinline__ void block_scan_i32(const int32_t* __restrict__ in, i
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ double centre(const GridD& g, int ax, int i) {
+  if (g.face[ax]) return 0.5 * (g.face[ax][i] + g.face[ax][i + 1]);
   return g.lo[ax] + ((double)i + 0.5) * g.h[ax];
+}
+
+// local spacing of cell i along axis ax: its width
+__device__ __forceinline__ double width(const GridD& g, int ax, int i) {
+  if (g.face[ax]) return g.face[ax][i + 1] - g.face[ax][i];
+  return g.h[ax];
+}
+
+// centres of the face neighbours of cell i along ax (beyond the grid: one
+// width further), bounding every point a box test must cover
+__device__ __forceinline__ double centre_below(const GridD& g, int ax, int i) {
+  if (!g.face[ax]) return centre(g, ax, i) - g.h[ax];
+  return i > 0 ? centre(g, ax, i - 1) : centre(g, ax, i) - width(g, ax, i);
+}
+__device__ __forceinline__ double centre_above(const GridD& g, int ax, int i) {
+  if (!g.face[ax]) return centre(g, ax, i) + g.h[ax];
+  return i + 1 < g.n[ax] ? centre(g, ax, i + 1) : centre(g, ax, i) + width(g, ax, i);
+}
+
+// index of the cell holding coordinate x along ax (off the grid: < 0 or
+// >= n, which callers test)
+__device__ __forceinline__ int cell_of(const GridD& g, int ax, double x) {
+  if (!g.face[ax]) return (int)floor((x - g.lo[ax]) / g.h[ax]);
+  const double* f = g.face[ax];
+  const int n = g.n[ax];
+  if (x < f[0]) return -1;
+  if (x >= f[n]) return n;
+  int lo = 0, hi = n - 1;   // the last i with f[i] <= x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (f[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 __device__ __forceinline__ void unlinear(const GridD& g, int c, int& i, int& j, int& k) {
@@ -170,6 +205,27 @@ __device__ __forceinline__ uint32_t make_code(const double n[3], const int r[3],
 }
 __device__ __forceinline__ int code_e(uint32_t code, int i) { return (code >> i) & 1u ? -1 : 1; }
 __device__ __forceinline__ int code_r(uint32_t code, int i) { return (int)((code >> (8 + 4 * i)) & 15u); }
+
+// x_2 - x_1 per axis of the stencil of the ghost in cell c: e_i r_i h_i, or
+// on a stretched axis the difference of the two cell centres (a
+// displacement off the grid, only along an axis the normal does not leave,
+// takes the cell width)
+__device__ __forceinline__ void stencil_span(const GridD& g, uint32_t code, int c,
+                                             double X[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) X[a] = (double)(code_e(code, a) * code_r(code, a)) * g.h[a];
+  if (!g.face[0] && !g.face[1] && !g.face[2]) return;   // uniform: no cell index needed
+  int ijk[3];
+  unlinear(g, c, ijk[0], ijk[1], ijk[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int er = code_e(code, a) * code_r(code, a);
+    if (a >= g.dim || !g.face[a]) continue;
+    const int q = ijk[a] + er;
+    X[a] = (q >= 0 && q < g.n[a]) ? centre(g, a, q) - centre(g, a, ijk[a])
+                                  : (double)er * width(g, a, ijk[a]);
+  }
+}
 __device__ __forceinline__ uint32_t code_skip(uint32_t code) { return (code >> 3) & 7u; }
 
 // Linear offset of stencil corner `k` (bit i set: displaced by e_i r_i along
@@ -226,14 +282,10 @@ __device__ __forceinline__ double lagrange_grad(const double a[3], const double 
 // weight of corner k.  Returns false on a zero denominator.
 template <int D>
 __device__ __forceinline__ bool ghost_weights(const double dl[3], const double nn[3],
-                                              uint32_t code, const double h[3], int bc,
-                                              double w[8]) {
-  double X[3], a[3];
+                                              const double X[3], int bc, double w[8]) {
+  double a[3];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    X[i] = (double)(code_e(code, i) * code_r(code, i)) * h[i];
-    a[i] = dl[i] / X[i];
-  }
+  for (int i = 0; i < D; ++i) a[i] = dl[i] / X[i];
   double c[8];
   if (bc == 0) {
 #pragma unroll
@@ -258,14 +310,11 @@ __device__ __forceinline__ bool ghost_weights(const double dl[3], const double n
 // Value and gradient of the box polynomial at a point whose offset from the
 // ghost centre is rel[], from the 2^D corner values v[].
 template <int D>
-__device__ __forceinline__ void box_eval(const double rel[3], uint32_t code, const double h[3],
+__device__ __forceinline__ void box_eval(const double rel[3], const double X[3],
                                          const double v[8], double& val, double grad[3]) {
-  double X[3], a[3];
+  double a[3];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    X[i] = (double)(code_e(code, i) * code_r(code, i)) * h[i];
-    a[i] = rel[i] / X[i];
-  }
+  for (int i = 0; i < D; ++i) a[i] = rel[i] / X[i];
   val = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) grad[i] = 0.0;
@@ -282,14 +331,11 @@ __device__ __forceinline__ void box_eval(const double rel[3], uint32_t code, con
 // Coefficients of the value and gradient of the box polynomial at rel[] on
 // corner k (for adjoints).
 template <int D>
-__device__ __forceinline__ void box_coeffs(const double rel[3], uint32_t code, const double h[3],
-                                           int k, double& cv, double cg[3]) {
-  double X[3], a[3];
+__device__ __forceinline__ void box_coeffs(const double rel[3], const double X[3], int k,
+                                           double& cv, double cg[3]) {
+  double a[3];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    X[i] = (double)(code_e(code, i) * code_r(code, i)) * h[i];
-    a[i] = rel[i] / X[i];
-  }
+  for (int i = 0; i < D; ++i) a[i] = rel[i] / X[i];
   lagrange<D>(a, k, cv);
 #pragma unroll
   for (int i = 0; i < D; ++i) cg[i] = lagrange_grad<D>(a, X, k, i);

@@ -30,7 +30,9 @@ __device__ __forceinline__ void fill_unit_field(const PlanD& P, int u, double* F
       nn[a] = a < D ? P.nn[a][p] : 0.0;
     }
     const int bc = kind == 2 ? (int)bt[p] : kind;
-    ghost_weights<D>(dl, nn, code, P.g.h, bc, w);
+    double X[3];
+    stencil_span(P.g, code, ws.cel[i], X);
+    ghost_weights<D>(dl, nn, X, bc, w);
     for (int t = 0; t < k; ++t) ws.M[i * k + t] = (t == i) ? 1.0 : 0.0;
     double r = w[0] * b[p];
 #pragma unroll
@@ -152,7 +154,9 @@ __device__ __forceinline__ void fill_single(const PlanD& P, int p, double* F, co
 #pragma unroll
   for (int k = 1; k < (1 << D); ++k)
     val[k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
-  ghost_weights<D>(dl, nn, code, P.g.h, bc, w);
+  double X[3];
+  stencil_span(P.g, code, c, X);
+  ghost_weights<D>(dl, nn, X, bc, w);
   double v = w[0] * bv;
 #pragma unroll
   for (int k = 1; k < (1 << D); ++k)

@@ -365,13 +365,18 @@ __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts,
     if (c < g.ncell && (T[c] & 0x41) == 0x41) s_cell[atomicAdd(&s_n, 1)] = (int)c;
   }
   __syncthreads();
+  // (axes unrolled: a runtime index into g would move it to scratch)
   double hmax = g.h[0];
-  for (int a = 1; a < g.dim; ++a) hmax = fmax(hmax, g.h[a]);
+#pragma unroll
+  for (int a = 1; a < 3; ++a)
+    if (a < g.dim) hmax = fmax(hmax, g.h[a]);
   int R[3] = {0, 0, 0}, W[3] = {1, 1, 1};
-  for (int a = 0; a < g.dim; ++a) {
-    R[a] = (int)floor((1.5 + 0.5 * sqrt((double)g.dim)) * hmax / g.h[a]) + 1;
-    W[a] = 2 * R[a] + 1;
-  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < g.dim) {
+      R[a] = (int)floor((1.5 + 0.5 * sqrt((double)g.dim)) * hmax / g.h[a]) + 1;
+      W[a] = 2 * R[a] + 1;
+    }
   const int box = W[0] * W[1] * W[2];
   const int64_t items = (int64_t)s_n * box;
   uint32_t* words = reinterpret_cast<uint32_t*>(tags);
@@ -513,8 +518,13 @@ __global__ __launch_bounds__(256) void k_geometry(const Inst* __restrict__ insts
   double n[3] = {0.0, 0.0, 0.0}, psi = 0.0;
   bool ok = project(I.s, g.dim, x, solid, n, psi);
   if (!ok) atomicOr(&info[ii].err, kErrGeometry);
+  // Eq. delta_n with the cell's own widths
+  const int ijk[3] = {i, j, k};
   double sum = 0.0;
-  for (int a = 0; a < g.dim; ++a) sum += (n[a] / g.h[a]) * (n[a] / g.h[a]);
+  for (int a = 0; a < g.dim; ++a) {
+    const double w = width(g, a, ijk[a]);
+    sum += (n[a] / w) * (n[a] / w);
+  }
   double dn = 1.0 / sqrt(sum);
   bool ghost = false;
   if (iface) {
@@ -626,10 +636,13 @@ __global__ __launch_bounds__(256) void k_deps(const Inst* __restrict__ insts, in
   int r[3] = {1, 1, 1};
   for (int a = 0; a < 3; ++a) n[a] = g_n[a * cap + e];
   if (I.scheme == kCGC_ES || g_ext[e]) {
-    // Eq. stencil_anisotropic: r_i = max(1, ceil(2 |x_1 - x_s|_i / dx_i))
+    // Eq. stencil_anisotropic: r_i = max(1, ceil(2 |x_1 - x_s|_i / dx_i)),
+    // dx_i the ghost cell's own width
+    int gi[3];
+    unlinear(g, c, gi[0], gi[1], gi[2]);
     for (int a = 0; a < g.dim; ++a) {
       double d = psi * n[a];
-      double q = 2.0 * fabs(d) / g.h[a];
+      double q = 2.0 * fabs(d) / width(g, a, gi[a]);
       int ri = (int)ceil(q);
       r[a] = ri < 1 ? 1 : ri;
       if (r[a] > 15) {
@@ -741,8 +754,9 @@ __global__ __launch_bounds__(256) void k_finalize(
         nrm[a * cap + p] = na;
         delta[a * cap + p] = da;
         if (a < g.dim) {
-          double X = (double)(code_e(cd, a) * code_r(cd, a)) * g.h[a];
-          am[a] = fmax(0.0, da / X);
+          double Xs[3];
+          stencil_span(g, cd, g_cell[e], Xs);
+          am[a] = fmax(0.0, da / Xs[a]);
           rm[a] = code_r(cd, a);
         }
       }
@@ -863,16 +877,34 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
   const int base = scheme & ~kLayer2;
   if (base < 0 || base > 2) return GCR_E_ARG;
   int64_t ncell = 1;
+  bool stretched = false;
   for (int a = 0; a < gg.dim; ++a) {
-    if (gg.n[a] < 1 || !(gg.h[a] > 0.0) || !std::isfinite(gg.lo[a])) return GCR_E_ARG;
+    if (gg.n[a] < 1) return GCR_E_ARG;
+    if (gg.faces[a]) {
+      stretched = true;
+      for (int64_t q = 0; q < gg.n[a]; ++q)
+        if (!(gg.faces[a][q + 1] > gg.faces[a][q]) || !std::isfinite(gg.faces[a][q]) ||
+            !std::isfinite(gg.faces[a][q + 1]))
+          return GCR_E_ARG;
+    } else if (!(gg.h[a] > 0.0) || !std::isfinite(gg.lo[a])) {
+      return GCR_E_ARG;
+    }
     ncell *= gg.n[a];
     if (ncell >= (int64_t(1) << 31)) return GCR_E_UNSUPPORTED;
   }
+  if (stretched && (scheme & kLayer2)) return GCR_E_UNSUPPORTED;
   I->g.dim = gg.dim;
   for (int a = 0; a < 3; ++a) {
     I->g.n[a] = a < gg.dim ? (int)gg.n[a] : 1;
     I->g.lo[a] = a < gg.dim ? gg.lo[a] : 0.0;
     I->g.h[a] = a < gg.dim ? gg.h[a] : 1.0;
+    // a stretched axis: the caller's faces for now; build_batch puts a
+    // device copy here before the instance table is uploaded
+    I->g.face[a] = a < gg.dim ? gg.faces[a] : nullptr;
+    if (I->g.face[a]) {
+      I->g.lo[a] = gg.faces[a][0];
+      I->g.h[a] = (gg.faces[a][gg.n[a]] - gg.faces[a][0]) / (double)gg.n[a];
+    }
   }
   I->g.ncell = ncell;
   I->scheme = base;
@@ -1048,6 +1080,18 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   B->nchunks = chunks;
 
   BatchData& D = *B;
+  // stretched axes: device copies of the faces (pageable sources, consumed
+  // when each copy returns)
+  for (int i = 0; i < ninst; ++i)
+    for (int a = 0; a < 3; ++a) {
+      const double* hf = B->inst[i].g.face[a];
+      if (!hf) continue;
+      const int64_t nf = (int64_t)B->inst[i].g.n[a] + 1;
+      double* df = own<double>(D, nf);
+      if (!df) return GCR_E_NOMEM;
+      GCR_HIP(hipMemcpyAsync(df, hf, sizeof(double) * nf, hipMemcpyHostToDevice, st));
+      B->inst[i].g.face[a] = df;
+    }
   D.d_inst = own<Inst>(D, ninst);
   D.d_tags = own<int8_t>(D, cells);
   D.d_chunk_start = own<int64_t>(D, ninst + 1);

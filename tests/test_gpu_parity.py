@@ -44,7 +44,7 @@ def ghost_centres(p):
     idx = [c % g.n[0], (c // g.n[0]) % g.n[1]]
     if p.dim == 3:
         idx.append(c // (g.n[0] * g.n[1]))
-    return np.stack([g.lo[i] + (idx[i] + 0.5) * g.h[i] for i in range(p.dim)])
+    return np.stack([g.centres(i)[idx[i]] for i in range(p.dim)])
 
 
 def check_close(got, want, scale, what):
@@ -462,3 +462,58 @@ def test_second_layer_batch_mixed_flags(gcr):
     for inst, sch, bp in zip(insts, schemes, B.plans):
         op = oracle.OraclePlan(inst.grid, inst.shape, sch)
         check_plan(op, bp)
+
+
+# ---------------------------------------------------------------------------
+# stretched grids (cell faces per axis; local widths in Eq. delta_n and
+# Eq. stencil_anisotropic, centre differences as stencil spans)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["circle0", "circle1", "sphere"])
+@pytest.mark.parametrize("scheme", [CGC, CGC_ES, HGC])
+def test_stretched_plan_fill_surface(gcr, which, scheme):
+    inst = synth.sphere_stretched(seed=0) if which == "sphere" else \
+        synth.circle_stretched(seed=int(which[-1]))
+    op, gp = plan_pair(gcr, inst, scheme)
+    assert op.min_margin > 1e-9
+    check_plan(op, gp, strict_geometry=True)
+    flds = (list(inst.fields) * 2)[:2]
+    got, want, scale = run_fill(gcr, op, gp, inst, flds, [DIRICHLET, NEUMANN])
+    cs = op.cell_scale(np.nan_to_num(want), scale)
+    v, g, anc = gp.surface(dev(inst.queries.x), [dev(x) for x in got])
+    ov, og, oanc, osc = op.surface_query(inst.queries.x, want, field_scale=cs)
+    assert np.array_equal(host(anc), oanc)
+    check_close(host(v), ov, osc[:, 0], "query value")
+    check_close(host(g), og, osc[:, 1:], "query gradient")
+
+
+def test_stretched_batch_forward(gcr):
+    insts = [synth.circle_stretched(seed=s) for s in range(3)]
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * 3)
+    fields, bcv, refs = [], [], []
+    for inst, bp in zip(insts, B.plans):
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        check_plan(op, bp, strict_geometry=True)
+        f = inst.fields[0]
+        vals = synth.sample(f, inst.grid)
+        vals[op.tags != 0] = np.nan
+        S = np.stack([inst.grid.centres(a)[[op.ghost_cell % inst.grid.n[0],
+                                           op.ghost_cell // inst.grid.n[0]][a]]
+                      for a in range(2)]) + op.delta
+        b = synth.bc_values(f, S, op.normal, DIRICHLET)
+        want = op.fill(vals[None].copy(), [DIRICHLET], b[None])[0]
+        sc = op.fill_scale(np.nan_to_num(vals)[None], [DIRICHLET], b[None])[0]
+        refs.append((op, want, sc))
+        fields.append(dev(vals))
+        bcv.append(dev(b))
+    B.forward(1, fields, [DIRICHLET], bcv)
+    torch.cuda.synchronize()
+    for (op, want, sc), fld in zip(refs, fields):
+        c = op.ghost_cell
+        check_close(host(fld)[c], want[c], sc, "batched fill on a stretched grid")
+
+
+def test_stretched_second_layer_unsupported(gcr):
+    inst = synth.circle_stretched(seed=0)
+    with pytest.raises(gcr.GcrError):
+        gcr.Plan(inst.grid, inst.shape, HGC | synth.LAYER2)

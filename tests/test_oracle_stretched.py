@@ -1,9 +1,9 @@
 """Pins of the oracle on stretched grids: cell faces given per axis, cell
 centres midway between faces, and the local spacing of a cell (its width)
 in Eq. delta_n and Eq. stencil_anisotropic; stencil spans x_2 - x_1 are
-differences of cell centres.  The paper runs on grids stretched by a fixed
-ratio away from the body and applies both equations with the local spacing
-per direction (Sec. 7.1).
+differences of cell centres.  The flows of Secs. 8.1 and 8.2 run on grids
+uniform near the body and stretched by a fixed ratio toward the outer
+boundaries; Sec. 7.1 takes the spacing in both equations as the local one.
 
 Expected values come from brute force with the circle's closed-form
 distance, polynomial reproduction (exact for any spacing), the level
