@@ -257,6 +257,17 @@ void gcr_batch_destroy(gcr_batch* batch);
 gcr_status gcr_batch_plan(const gcr_batch* batch, int32_t i,
                           const gcr_plan** out);
 
+/* Foot points and normals of every ghost of a batch in one launch, as
+ * gcr_plan_foot_points gives them per plan (S = x_c + delta, Sec. 3.1),
+ * with the instances' ghosts one after another: columns g_0 .. g_0 + n_0 - 1
+ * are instance 0's in its plan's order, then instance 1's, and so on.
+ *   S, normal  device f64 [dim][n_total], n_total the sum of the plans'
+ *              n_ghost; either may be NULL.
+ * Every instance must have the same dimension (else GCR_E_UNSUPPORTED).
+ * One kernel on `stream`. */
+gcr_status gcr_batch_foot_points(const gcr_batch* batch, double* S, double* normal,
+                                 void* stream);
+
 /* Batched forward in one persistent launch: for every instance, fill its nf
  * fields, then (if nq != NULL) the force on its body from field p_field
  * (pressure) and the dim fields u_first.. (velocity).  Host arrays of device
@@ -273,18 +284,22 @@ gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
                              int32_t u_first, double mu, double* F,
                              void* stream);
 
-/* Stage timing of plan building.  When on (process-wide), gcr_plan_create
+/* Timing, process-wide.  mask: bit 0 (GCR_PROFILE_BUILD) stage timing of
+ * plan building, bit 1 (GCR_PROFILE_FORWARD) timing of the batched forward;
+ * 0 turns both off (the default: no events recorded); other bits:
+ * GCR_E_ARG.  With bit 0 set, gcr_plan_create
  * and gcr_batch_create record HIP events on their stream around each stage;
  * gcr_last_build_times copies the device times in milliseconds of the last
  * build on the calling thread into ms[11]: [0] classification, [1] interface
  * scan, [2] interface compaction, [3] geometry and ghost tags, [4] ghost
  * compaction, [5] stencils and dependencies, [6] levels and canonical order,
  * [7] finalize; [8], [9], [10] split [0] into the span pre-pass, the store
- * pass and the exact tests near the body.  Off by default (no events
- * recorded). */
-gcr_status gcr_set_profiling(int32_t on);
+ * pass and the exact tests near the body. */
+#define GCR_PROFILE_BUILD 1
+#define GCR_PROFILE_FORWARD 2
+gcr_status gcr_set_profiling(int32_t mask);
 gcr_status gcr_last_build_times(float* ms);
-/* With profiling on, each gcr_batch_forward also records HIP events around
+/* With bit 1 set, each gcr_batch_forward records HIP events around
  * its two kernels (the surface-point anchor search and the persistent fill
  * + force launch).  This call waits for the recorded work, writes the mean
  * ms of each over the calls since the last query to out[0] and out[1] and

@@ -27,7 +27,8 @@ SYMBOLS = [
     "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
     "gcr_plan_export", "gcr_plan_foot_points", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
-    "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_forward",
+    "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
+    "gcr_batch_forward",
     "gcr_set_profiling", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
 ]
 
@@ -96,6 +97,7 @@ def lib():
         L.gcr_batch_destroy.argtypes = [vp]
         L.gcr_batch_destroy.restype = None
         L.gcr_batch_plan.argtypes = [vp, i32, P(vp)]
+        L.gcr_batch_foot_points.argtypes = [vp, vp, vp, vp]
         L.gcr_set_profiling.argtypes = [i32]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_forward_times.argtypes = [vp]
@@ -313,6 +315,21 @@ class Plan:
                                       _ptr_array(lam_bc), _stream(stream)), "gcr_fill_adjoint")
 
 
+class _BatchHandle:
+    """Owner of a gcr_batch: destroyed when neither the Batch nor any of its
+    plans refers to it (plans keep it, not the Batch, so that no reference
+    cycle delays the release of the batch's device memory to the pool)."""
+
+    def __init__(self, h):
+        self.h = h
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None and not _finalizing():
+            _lib.gcr_batch_destroy(h)
+        self.h = None
+
+
 class Batch:
     """gcr_batch_create: plans of many uneven instances built together."""
 
@@ -327,20 +344,26 @@ class Batch:
         h = ctypes.c_void_p()
         _check(L.gcr_batch_create(n, G, S, sch, _stream(stream), ctypes.byref(h)),
                "gcr_batch_create")
+        self._owner = _BatchHandle(h)
         self._h = h
         self.n = n
         self.plans = []
         for i in range(n):
             ph = ctypes.c_void_p()
             _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
-            self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self))
+            self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self._owner))
 
-    def __del__(self, _finalizing=sys.is_finalizing):
-        h = getattr(self, "_h", None)
-        if h is not None and _lib is not None and not _finalizing():
-            self.plans = []
-            _lib.gcr_batch_destroy(h)
-        self._h = None
+    def foot_points(self, stream=None):
+        """gcr_batch_foot_points: (S, normal), each f64 [dim][total ghosts],
+        the instances' ghosts one after another."""
+        dev = torch.device("cuda")
+        dim = self.plans[0].dim
+        ng = sum(p.n_ghost for p in self.plans)
+        S = torch.empty((dim, ng), dtype=torch.float64, device=dev)
+        n = torch.empty((dim, ng), dtype=torch.float64, device=dev)
+        _check(lib().gcr_batch_foot_points(self._h, _dptr(S), _dptr(n), _stream(stream)),
+               "gcr_batch_foot_points")
+        return S, n
 
     def forward(self, nf, fields, bc_kind, bc_val, bc_type=None, nq=None, xq=None, nrm=None,
                 wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, stream=None):
@@ -374,8 +397,14 @@ def set_wide_layering(min_interface: int = 0):
     _check(lib().gcr_set_wide_layering(int(min_interface)), "gcr_set_wide_layering")
 
 
-def set_profiling(on: bool):
-    _check(lib().gcr_set_profiling(1 if on else 0), "gcr_set_profiling")
+PROFILE_BUILD = 1     # stage timing of plan builds
+PROFILE_FORWARD = 2   # timing of the batched forward's kernels
+
+
+def set_profiling(on):
+    """True: every timing on; False: off; an int: a mask of PROFILE_*."""
+    mask = (PROFILE_BUILD | PROFILE_FORWARD) if on is True else (0 if on is False else int(on))
+    _check(lib().gcr_set_profiling(mask), "gcr_set_profiling")
 
 
 def forward_times() -> dict:

@@ -185,9 +185,21 @@ struct BatchFwdState {
   size_t call_cap = 0;
   int32_t* d_anchor = nullptr;
   size_t anchor_cap = 0;
+  // pinned staging of the call table, two slots used in turn; a slot is
+  // rewritten only once the copy that last read it has run
+  char* h_call[2] = {nullptr, nullptr};
+  size_t h_call_cap[2] = {0, 0};
+  hipEvent_t ev_call[2] = {nullptr, nullptr};
+  bool call_pending[2] = {false, false};
+  int call_slot = 0;
   int threads = 0, grid_mul = 0;   // tuned
   std::vector<void*> owned;
   ~BatchFwdState() {
+    for (int k = 0; k < 2; ++k) {
+      if (call_pending[k]) (void)hipEventSynchronize(ev_call[k]);
+      if (ev_call[k]) (void)hipEventDestroy(ev_call[k]);
+      pinned_free(h_call[k]);
+    }
     for (void* p : owned) pool_free(p);
     for (void* p : {(void*)d_part, (void*)d_call, (void*)d_anchor})
       if (p) pool_free(p);
@@ -379,7 +391,25 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     S->part_cap = S->d_part ? np * 3 : 0;
     if (!S->d_part) return GCR_E_NOMEM;
   }
-  GCR_HIP(hipMemcpyAsync(S->d_call, h, o, hipMemcpyHostToDevice, st));
+  {
+    const int k = S->call_slot;
+    S->call_slot ^= 1;
+    if (S->call_pending[k]) {
+      GCR_HIP(hipEventSynchronize(S->ev_call[k]));
+      S->call_pending[k] = false;
+    }
+    if (S->h_call_cap[k] < o) {
+      pinned_free(S->h_call[k]);
+      S->h_call[k] = static_cast<char*>(pinned_alloc(o));
+      S->h_call_cap[k] = S->h_call[k] ? o : 0;
+      if (!S->h_call[k]) return GCR_E_NOMEM;
+    }
+    if (!S->ev_call[k]) GCR_HIP(hipEventCreateWithFlags(&S->ev_call[k], hipEventDisableTiming));
+    std::memcpy(S->h_call[k], h, o);
+    GCR_HIP(hipMemcpyAsync(S->d_call, S->h_call[k], o, hipMemcpyHostToDevice, st));
+    GCR_HIP(hipEventRecord(S->ev_call[k], st));
+    S->call_pending[k] = true;
+  }
   char* d = S->d_call;
   BCall C;
   std::memset(&C, 0, sizeof(C));
@@ -401,7 +431,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   C.aoff = nq ? reinterpret_cast<const int64_t*>(d + o_aoff) : nullptr;
   C.anchor = S->d_anchor;
   std::array<hipEvent_t, 3> ev{};
-  bool timed = profiling_on();
+  bool timed = (profiling_mask() & 2) != 0;
   for (auto& e : ev)
     if (timed && hipEventCreate(&e) != hipSuccess) timed = false;
   if (timed) (void)hipEventRecord(ev[0], st);

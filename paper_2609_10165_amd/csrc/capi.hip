@@ -285,6 +285,33 @@ __global__ void k_foot_points(GridD g, const int32_t* __restrict__ cell, const d
   }
 }
 
+// The same for every ghost of a batch, instances one after another: ghost p
+// belongs to the last instance i with g_off[i] <= p (empty instances skipped)
+__global__ void k_batch_foot_points(const Inst* __restrict__ insts, int ninst,
+                                    const int64_t* __restrict__ g_off, int64_t cap,
+                                    const int32_t* __restrict__ cell,
+                                    const double* __restrict__ delta,
+                                    const double* __restrict__ nrm_in, int dim, int64_t ng,
+                                    double* __restrict__ S, double* __restrict__ nrm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ng) return;
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g_off[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  const GridD& g = insts[lo].g;
+  int q[3];
+  unlinear(g, cell[p], q[0], q[1], q[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < dim) {
+      if (S) S[a * ng + p] = centre(g, a, q[a]) + delta[a * cap + p];
+      if (nrm) nrm[a * ng + p] = nrm_in[a * cap + p];
+    }
+}
+
 __global__ void k_export_unit(const int32_t* __restrict__ blk,
                               const int32_t* __restrict__ unit_mem, int ng,
                               int32_t* __restrict__ unit) {
@@ -599,8 +626,9 @@ void gcr_batch_destroy(gcr_batch* b) {
   delete b;
 }
 
-gcr_status gcr_set_profiling(int32_t on) {
-  set_profiling(on);
+gcr_status gcr_set_profiling(int32_t mask) {
+  if (mask < 0 || mask > 3) return GCR_E_ARG;
+  set_profiling(mask);
   return GCR_OK;
 }
 
@@ -619,6 +647,20 @@ gcr_status gcr_last_build_times(float* ms) {
 gcr_status gcr_batch_plan(const gcr_batch* b, int32_t i, const gcr_plan** out) {
   if (!b || !out || i < 0 || i >= (int)b->plans.size()) return GCR_E_ARG;
   *out = b->plans[i].get();
+  return GCR_OK;
+}
+
+gcr_status gcr_batch_foot_points(const gcr_batch* b, double* S, double* normal, void* stream) {
+  if (!b || !b->data) return GCR_E_ARG;
+  const BatchData& D = *b->data;
+  const int dim = b->plans[0]->dim;
+  for (const auto& p : b->plans)
+    if (p->dim != dim) return GCR_E_UNSUPPORTED;
+  const int64_t ng = D.ng_total;
+  if (ng == 0 || (!S && !normal)) return GCR_OK;
+  k_batch_foot_points<<<(unsigned)((ng + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+      D.d_inst, D.ninst, D.d_g_off, D.cap, D.d_cell, D.d_delta, D.d_nrm, dim, ng, S, normal);
+  GCR_HIP(hipGetLastError());
   return GCR_OK;
 }
 

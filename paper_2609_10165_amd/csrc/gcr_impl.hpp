@@ -256,8 +256,8 @@ namespace gcr {
 gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes,
                        const int32_t* schemes, hipStream_t st, std::shared_ptr<BatchData>* out);
 void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p);
-void set_profiling(int on);
-bool profiling_on();
+void set_profiling(int mask);
+int profiling_mask();   // bit 0 build stages, bit 1 batched forward
 void* plan_scratch(gcr_plan* p, int slot, size_t bytes);
 void last_build_times(float* ms);
 gcr_status status_from_err(uint32_t err);

@@ -1046,8 +1046,8 @@ struct StageEvents {
   }
 };
 
-void set_profiling(int on) { g_profiling.store(on ? 1 : 0); }
-bool profiling_on() { return g_profiling.load() != 0; }
+void set_profiling(int mask) { g_profiling.store(mask & 3); }
+int profiling_mask() { return g_profiling.load(); }
 
 static std::atomic<int64_t> g_wide_min{kWideMinInterface};
 void set_wide_layering(int64_t v) { g_wide_min.store(v > 0 ? v : kWideMinInterface); }
@@ -1142,7 +1142,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                          hipMemcpyHostToDevice, st));
   GCR_HIP(hipMemsetAsync(D.d_info, 0, sizeof(InstInfo) * ninst, st));
 
-  StageEvents T(g_profiling.load() != 0);
+  StageEvents T((g_profiling.load() & 1) != 0);
   T.mark(0, st);
   launch_classify(D.d_inst, ninst, D.d_chunk_start, chunks, D.d_span, D.d_tags, D.d_chunk_cnt,
                   D.d_band, D.d_nband, T.event(10), T.event(11), st);

@@ -244,3 +244,57 @@ def test_batch_forward_with_coupled_units(gcr):
             c = op.ghost_cell
             err = np.abs(got[c] - want[f][c])
             assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][c]), sc[f])), (i, f)
+
+
+def test_batch_foot_points(gcr):
+    """gcr_batch_foot_points: the instances' foot points and normals one
+    after another, bitwise equal to each plan's own gcr_plan_foot_points and
+    within 1e-12 of a cell width of the oracle's S = x_c + delta; instances on
+    different grids (one stretched), one of them without ghosts."""
+    insts = synth.stars64(seed=7, ninst=3, nmin=96, nmax=400) + [synth.circle_stretched(seed=1)]
+    grids = [i.grid for i in insts]
+    shapes = [i.shape for i in insts]
+    # body far outside its grid: no ghosts
+    grids.insert(2, synth.Grid(2, (40, 33, 1), (0.0, 0.0, 0.0), (0.1, 0.1, 1.0)))
+    shapes.insert(2, synth.Shape(synth.SPHERE, (50.0, 50.0, 0.0), 1.0))
+    B = gcr.Batch(grids, shapes, [HGC] * len(grids))
+    S, n = B.foot_points()
+    assert B.plans[2].n_ghost == 0
+    off = 0
+    for grid, shape, plan in zip(grids, shapes, B.plans):
+        Sp, n_p = plan.foot_points()
+        ng = plan.n_ghost
+        assert torch.equal(S[:, off:off + ng], Sp) and torch.equal(n[:, off:off + ng], n_p)
+        op = oracle.OraclePlan(grid, shape, HGC)
+        assert op.n_ghost == ng
+        c = op.ghost_cell
+        want = np.stack([grid.centres(0)[c % grid.n[0]], grid.centres(1)[c // grid.n[0]]])
+        want = want + op.delta
+        h = min(grid.widths(0).min(), grid.widths(1).min())
+        assert np.all(np.abs(host(S[:, off:off + ng]) - want) <= 1e-12 * h)
+        off += ng
+    assert S.shape == (2, off)
+
+
+def test_batch_released_without_cycle_collection(gcr):
+    """A dropped Batch is destroyed at once (its device memory goes back to
+    the pool for the next build), while a plan still held keeps the batch's
+    arrays alive."""
+    import gc
+    import weakref
+    insts = synth.stars64(seed=8, ninst=2, nmin=96, nmax=200)
+    gc.disable()
+    try:
+        B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * 2)
+        owner = weakref.ref(B._owner)
+        S0, _ = B.plans[1].foot_points()
+        keep = B.plans[1]
+        del B
+        assert owner() is not None          # the held plan keeps it
+        S1, _ = keep.foot_points()
+        torch.cuda.synchronize()
+        assert torch.equal(S0, S1)
+        del keep
+        assert owner() is None              # released without the cycle collector
+    finally:
+        gc.enable()
