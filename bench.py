@@ -6,9 +6,9 @@ each of the three ghost schemes (CGC, CGC_ES, HGC), the three built and
 applied as one batch:
   plans (classification, tags, geometry, dependency levels, canonical order)
   -> foot points and boundary data there (caller side, torch)
-  -> level-by-level fill of the 4 fields and the pressure + viscous force
-     (one persistent launch for all schemes and fields)
-  -> boundary values and gradients at 2048 surface points.
+  -> level-by-level fill of the 4 fields, their values and gradients at
+     2048 surface points and the pressure + viscous force there (one
+     persistent launch for all schemes and fields).
 Metric: ghost cells per second (sum of the three plans' ghosts per step).
 The same step done one plan at a time is timed beside it (plain_step).
 
@@ -135,14 +135,18 @@ def main():
     xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
     nqp = xq.shape[1]
     F3 = torch.zeros((len(SCHEMES), 3), dtype=torch.float64, device=dev)
+    # surface values and gradients of the 4 fields at the points, per scheme
+    sval = [torch.empty(nqp, dtype=torch.float64, device=dev) for _ in range(4 * len(SCHEMES))]
+    sgrad = [torch.empty((3, nqp), dtype=torch.float64, device=dev)
+             for _ in range(4 * len(SCHEMES))]
     F = torch.empty(3, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     seg = []
 
     def step(record=None):
         """The three schemes as one batch: shared build launches, boundary
-        data for all foot points at once, fill + force of every (scheme,
-        field) in one persistent launch, then the surface values."""
+        data for all foot points at once, then fill, surface values and
+        force of every (scheme, field) in one persistent launch."""
         B = gcr.Batch([grid] * len(SCHEMES), [shape] * len(SCHEMES), list(SCHEMES))
         if record is not None:
             record.append(gcr.last_build_times())
@@ -153,9 +157,7 @@ def main():
             off += p.n_ghost
         B.forward(4, [f for fs in fieldsets for f in fs], kinds, bcv, nq=[nqp] * len(SCHEMES),
                   xq=[xq] * len(SCHEMES), nrm=[nq] * len(SCHEMES), wq=[wq] * len(SCHEMES),
-                  p_field=3, u_first=0, mu=1.0, F=F3)
-        for p, fs in zip(B.plans, fieldsets):
-            p.surface(xq, fs)
+                  p_field=3, u_first=0, mu=1.0, F=F3, sval=sval, sgrad=sgrad)
         seg.append(B.plans[0].stats()["n_band_segments"])
         return off
 
@@ -235,13 +237,14 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                          "algorithmic_bytes": cls_bytes, "avg_ms": round(cls_ms, 5)}
-    # the step's longest kernel: the persistent fill + force launch.  Bytes
-    # it must move: per ghost and field, 2^d - 1 stencil values, the boundary
-    # datum and the result (72 B in 3D); per ghost, cell, code, unit, delta
-    # and normal once (60 B); per surface point, position, normal, weight
-    # and anchor (60 B) and 2^d values of each of p, u, v, w (256 B).
+    # the step's longest kernel: the persistent fill + surface + force
+    # launch.  Bytes it must move: per ghost and field, 2^d - 1 stencil
+    # values, the boundary datum and the result (72 B in 3D); per ghost,
+    # cell, code, unit, delta and normal once (60 B); per surface point,
+    # position, normal, weight and anchor (60 B), and per field the 2^d
+    # corner values read (64 B) and the value and gradient written (32 B).
     fwd_ms = fwd_times["forward"]
-    fwd_bytes = ng_step * (4 * 72 + 60) + len(SCHEMES) * nqp * (60 + 4 * 64)
+    fwd_bytes = ng_step * (4 * 72 + 60) + len(SCHEMES) * nqp * (60 + 4 * (64 + 32))
     fwd_gbs = fwd_bytes / (fwd_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_batch_forward", "achieved": round(fwd_gbs, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),

@@ -274,7 +274,13 @@ gcr_status gcr_batch_foot_points(const gcr_batch* batch, double* S, double* norm
  * pointers are instance-major, [ninst * nf]:
  *   fields, bc_val, bc_type (bc_type may be NULL);  bc_kind host [nf].
  *   nq host int64 [ninst]; xq, nrm, wq host [ninst] device pointers;
- *   F device f64 [ninst][3] (unused components zero). */
+ *   F device f64 [ninst][3] (unused components zero).
+ * Surface values (Sec. 6) of the filled fields at the same points, as
+ * gcr_surface gives them (NaN at a point with no ghost within two cells):
+ *   sval, sgrad  host [ninst * nf] of device pointers, or NULL (none), an
+ *                entry NULL for a field not wanted: value f64 [nq_i] and
+ *                gradient f64 [dim][nq_i] of field f of instance i.
+ *   Either needs nq (else GCR_E_ARG). */
 gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
                              double* const* fields, const int32_t* bc_kind,
                              const uint8_t* const* bc_type,
@@ -282,6 +288,7 @@ gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
                              const double* const* xq, const double* const* nrm,
                              const double* const* wq, int32_t p_field,
                              int32_t u_first, double mu, double* F,
+                             double* const* sval, double* const* sgrad,
                              void* stream);
 
 /* Timing, process-wide.  mask: bit 0 (GCR_PROFILE_BUILD) stage timing of

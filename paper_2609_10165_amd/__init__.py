@@ -103,7 +103,7 @@ def lib():
         L.gcr_forward_times.argtypes = [vp]
         L.gcr_last_build_times.argtypes = [vp]
         L.gcr_batch_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl,
-                                        vp, vp]
+                                        vp, vp, vp, vp]
         for name in SYMBOLS:
             getattr(L, name)
             if getattr(L, name).restype is ctypes.c_int and name not in ("gcr_status_str",):
@@ -366,8 +366,11 @@ class Batch:
         return S, n
 
     def forward(self, nf, fields, bc_kind, bc_val, bc_type=None, nq=None, xq=None, nrm=None,
-                wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, stream=None):
-        """gcr_batch_forward; per-instance lists are instance-major [ninst*nf]."""
+                wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, sval=None, sgrad=None,
+                stream=None):
+        """gcr_batch_forward; per-field lists are instance-major [ninst*nf]
+        (fields, bc_val, bc_type, sval, sgrad; None entries allowed in the
+        last three)."""
         L = lib()
         kinds = (ctypes.c_int32 * nf)(*[int(k) for k in bc_kind])
         bt = None
@@ -379,9 +382,17 @@ class Batch:
         if nq is not None:
             nqa = (ctypes.c_int64 * self.n)(*[int(v) for v in nq])
             xa, na, wa = _ptr_array(xq), _ptr_array(nrm), _ptr_array(wq)
+        def opt(ts):
+            if ts is None:
+                return None
+            a = (ctypes.c_void_p * len(ts))()
+            for k, t in enumerate(ts):
+                a[k] = _dptr(t) if t is not None else None
+            return a
         _check(L.gcr_batch_forward(self._h, nf, _ptr_array(fields), kinds, bt,
                                    _ptr_array(bc_val), nqa, xa, na, wa, int(p_field),
-                                   int(u_first), float(mu), _dptr(F), _stream(stream)),
+                                   int(u_first), float(mu), _dptr(F), opt(sval), opt(sgrad),
+                                   _stream(stream)),
                "gcr_batch_forward")
         return F
 

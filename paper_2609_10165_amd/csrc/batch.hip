@@ -48,6 +48,8 @@ struct BCall {
   const int32_t* order;          // [nitems] items w = i*nf + f
   const int64_t* aoff;           // [ninst + 1] first point of each instance (forces)
   const int32_t* anchor;         // [aoff[ninst]] anchor ghost of every point
+  double* const* sval;           // [ninst*nf] surface values [nq_i] (null: none)
+  double* const* sgrad;          // [ninst*nf] surface gradients [dim][nq_i] (null: none)
 };
 
 // Anchor ghost of every surface point of every instance, one group of lanes
@@ -102,11 +104,14 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
         __syncthreads();
       }
     }
-    // share of the force
+    // share of the force, and the field's value and gradient at the points
+    // (one box-polynomial evaluation serves both)
     const int vc = f - C.u_first;
     const bool isp = f == C.p_field, isu = vc >= 0 && vc < D;
+    double* const sv = C.sval ? C.sval[w] : nullptr;
+    double* const sg = C.sgrad ? C.sgrad[w] : nullptr;
     double t[3] = {0.0, 0.0, 0.0};
-    if (C.nq && (isp || isu)) {
+    if (C.nq && (isp || isu || sv || sg)) {
       const int64_t nq = C.nq[i];
       const double* xq = C.xq[i];
       const double* nr = C.nrm[i];
@@ -135,11 +140,15 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
           stencil_span(P.g, P.code[g], P.cell[g], X);
           box_eval<D>(rel, X, v, val, gr);
         }
+        if (sv) sv[q] = val;
+        if (sg)
+#pragma unroll
+          for (int a = 0; a < D; ++a) sg[a * nq + q] = gr[a];
         const double wt = wq[q];
         if (isp) {
 #pragma unroll
           for (int a = 0; a < D; ++a) t[a] += -wt * val * n[a];
-        } else {
+        } else if (isu) {
           double gn = 0.0;
 #pragma unroll
           for (int a = 0; a < D; ++a) gn += gr[a] * n[a];
@@ -311,7 +320,9 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
                                         const double* const* bc_val, const int64_t* nq,
                                         const double* const* xq, const double* const* nrm,
                                         const double* const* wq, int32_t p_field,
-                                        int32_t u_first, double mu, double* F, void* stream) {
+                                        int32_t u_first, double mu, double* F,
+                                        double* const* sval, double* const* sgrad,
+                                        void* stream) {
   if (!batch || nf < 1 || nf > kMaxFields || !fields || !bc_kind || !bc_val) return GCR_E_ARG;
   const int n = (int)batch->plans.size();
   const int dim = batch->plans[0]->dim;
@@ -323,6 +334,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     if (!fields[w] || !bc_val[w]) return GCR_E_ARG;
     if (bc_kind[w % nf] == GCR_MIXED && (!bc_type || !bc_type[w])) return GCR_E_ARG;
   }
+  if ((sval || sgrad) && !nq) return GCR_E_ARG;
   if (nq) {
     if (!xq || !nrm || !wq || !F) return GCR_E_ARG;
     for (int i = 0; i < n; ++i)
@@ -344,7 +356,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   // call table: one upload
   const size_t np = (size_t)nitems;
-  const size_t bytes = sizeof(void*) * (3 * np + 3 * n) + sizeof(int64_t) * (2 * n + 1) +
+  const size_t bytes = sizeof(void*) * (5 * np + 3 * n) + sizeof(int64_t) * (2 * n + 1) +
                        sizeof(int32_t) * np + 64;
   std::vector<char> host(bytes, 0);
   char* h = host.data();
@@ -361,6 +373,8 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   const size_t o_fields = put(fields, sizeof(void*) * np);
   const size_t o_bcv = put(bc_val, sizeof(void*) * np);
   const size_t o_bct = put(bt.data(), sizeof(void*) * np);
+  const size_t o_sval = sval ? put(sval, sizeof(void*) * np) : 0;
+  const size_t o_sgrad = sgrad ? put(sgrad, sizeof(void*) * np) : 0;
   size_t o_nq = 0, o_xq = 0, o_nrm = 0, o_wq = 0, o_aoff = 0;
   std::vector<int64_t> aoff(n + 1, 0);
   if (nq) {
@@ -430,6 +444,8 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   C.order = reinterpret_cast<const int32_t*>(d + o_order);
   C.aoff = nq ? reinterpret_cast<const int64_t*>(d + o_aoff) : nullptr;
   C.anchor = S->d_anchor;
+  C.sval = sval ? reinterpret_cast<double* const*>(d + o_sval) : nullptr;
+  C.sgrad = sgrad ? reinterpret_cast<double* const*>(d + o_sgrad) : nullptr;
   std::array<hipEvent_t, 3> ev{};
   bool timed = (profiling_mask() & 2) != 0;
   for (auto& e : ev)

@@ -581,16 +581,22 @@ __global__ __launch_bounds__(256) void k_scatter_ghosts(
 }
 
 // ghost offsets of the instances: ghosts before interface entry if_off[i]
-__global__ void k_ghost_off(const uint8_t* __restrict__ flag, const int64_t* __restrict__ blk_excl,
-                            const int64_t* __restrict__ if_off, int ninst,
-                            int64_t* __restrict__ g_off) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per offset i = 0..ninst: the ghosts before interface cell
+// if_off[i] are those of the whole 1024-flag blocks before it plus the
+// flags of its own block up to it
+__global__ __launch_bounds__(64) void k_ghost_off(const uint8_t* __restrict__ flag,
+                                                  const int64_t* __restrict__ blk_excl,
+                                                  const int64_t* __restrict__ if_off, int ninst,
+                                                  int64_t* __restrict__ g_off) {
+  const int i = blockIdx.x;
   if (i > ninst) return;
-  int64_t e = if_off[i];
-  int64_t b = e / 1024;
-  int64_t s = blk_excl[b];
-  for (int64_t q = b * 1024; q < e; ++q) s += flag[q] & 1;
-  g_off[i] = s;
+  const int64_t e = if_off[i];
+  const int64_t b = e / 1024;
+  int c = 0;
+  for (int64_t q = b * 1024 + threadIdx.x; q < e; q += 64) c += flag[q] & 1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+  if (threadIdx.x == 0) g_off[i] = blk_excl[b] + c;
 }
 
 // --------------------------------------------------------------------------
@@ -1263,7 +1269,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
     k_scatter_ghosts<<<(unsigned)nblk, 256, 0, st>>>(D.d_if_flag, nif, D.d_blkexcl, D.d_if_cell,
                                                      D.d_if_psi, D.d_if_n, cap, D.d_g_cell,
                                                      D.d_g_psi, D.d_g_n, D.d_g_ext);
-    k_ghost_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_if_flag, D.d_blkexcl, D.d_if_off, ninst,
+    k_ghost_off<<<(unsigned)(ninst + 1), 64, 0, st>>>(D.d_if_flag, D.d_blkexcl, D.d_if_off, ninst,
                                                       D.d_g_off);
     T.mark(6, st);
     // ghost count unknown on the host: launch over the interface capacity

@@ -37,7 +37,7 @@ def ghost_centres(op):
                      g.lo[1] + (c // g.n[0] + 0.5) * g.h[1]])
 
 
-def run_batch(gcr, insts, with_forces=True):
+def run_batch(gcr, insts, with_forces=True, fwd_kw=None):
     B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
     nf = 3
     ops, fields, bcv, bct, host_in, wants = [], [], [], [], [], []
@@ -66,7 +66,7 @@ def run_batch(gcr, insts, with_forces=True):
         wq = [dev(i.queries.w) for i in insts]
         F = torch.zeros((len(insts), 3), dtype=torch.float64, device="cuda")
         kw = dict(nq=nq, xq=xq, nrm=nr, wq=wq, p_field=2, u_first=0, mu=0.9, F=F)
-    B.forward(nf, fields, [2, 2, 2], bcv, bc_type=bct, **kw)
+    B.forward(nf, fields, [2, 2, 2], bcv, bc_type=bct, **kw, **(fwd_kw or {}))
     torch.cuda.synchronize()
     return B, ops, fields, wants, F
 
@@ -185,8 +185,10 @@ def test_batch_three_schemes_sphere256_full_size(gcr):
     xq, nr, wq = dev(q.x), dev(q.n), dev(q.w)
     mu = 0.7
     F = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    sv = [torch.empty(nq, dtype=torch.float64, device="cuda") for _ in range(12)]
+    sg = [torch.empty((3, nq), dtype=torch.float64, device="cuda") for _ in range(12)]
     B.forward(4, fields, kinds, bcv, nq=[nq] * 3, xq=[xq] * 3, nrm=[nr] * 3, wq=[wq] * 3,
-              p_field=3, u_first=0, mu=mu, F=F)
+              p_field=3, u_first=0, mu=mu, F=F, sval=sv, sgrad=sg)
     torch.cuda.synchronize()
     for i, (op, plan) in enumerate(zip(ops, B.plans)):
         want, sc = wants[i]
@@ -210,6 +212,11 @@ def test_batch_three_schemes_sphere256_full_size(gcr):
         assert np.array_equal(host(anc), oanc), i
         assert np.all(np.abs(host(v) - ov) <= 1e-12 * np.maximum(np.abs(ov), osc[:, 0])), i
         assert np.all(np.abs(host(gr) - og) <= 1e-12 * np.maximum(np.abs(og), osc[:, 1:])), i
+        # the same values and gradients written by the forward launch itself
+        bv = np.stack([host(sv[4 * i + f]) for f in range(4)])
+        bg = np.stack([host(sg[4 * i + f]) for f in range(4)])
+        assert np.all(np.abs(bv - ov) <= 1e-12 * np.maximum(np.abs(ov), osc[:, 0])), i
+        assert np.all(np.abs(bg - og) <= 1e-12 * np.maximum(np.abs(og), osc[:, 1:])), i
 
 
 def test_batch_forward_with_coupled_units(gcr):
@@ -298,3 +305,34 @@ def test_batch_released_without_cycle_collection(gcr):
         assert owner() is None              # released without the cycle collector
     finally:
         gc.enable()
+
+
+def test_batch_forward_surface_outputs(gcr):
+    """Values and gradients of every filled field at the instances' points,
+    written by the batched forward, against the oracle's surface query (and
+    gcr_surface on the same filled fields); outputs left out (None entries)
+    leave the others intact."""
+    insts = synth.stars64(seed=9, ninst=5, nmin=96, nmax=400)
+    nf = 3
+    nqs = [i.queries.x.shape[1] for i in insts]
+    sv = [torch.full((nq,), 7.0, dtype=torch.float64, device="cuda") for nq in nqs for _ in range(nf)]
+    sg = [torch.full((2, nq), 7.0, dtype=torch.float64, device="cuda") for nq in nqs for _ in range(nf)]
+    sv[1] = None                       # instance 0, field 1: value not wanted
+    sg[2 * nf] = None                  # instance 2, field 0: gradient not wanted
+    B, ops, fields, wants, F = run_batch(gcr, insts, fwd_kw=dict(sval=sv, sgrad=sg))
+    for i, (inst, op, plan) in enumerate(zip(insts, ops, B.plans)):
+        want, sc = wants[i]
+        cs = op.cell_scale(np.nan_to_num(want), sc)
+        ov, og, _, osc = op.surface_query(inst.queries.x, want, field_scale=cs)
+        v2, g2, _ = plan.surface(dev(inst.queries.x), fields[i * nf:(i + 1) * nf])
+        torch.cuda.synchronize()
+        for f in range(nf):
+            w = i * nf + f
+            if sv[w] is not None:
+                got = host(sv[w])
+                assert np.all(np.abs(got - ov[f]) <= 1e-12 * np.maximum(np.abs(ov[f]), osc[f, 0])), w
+                assert np.all(np.abs(got - host(v2[f])) <= 1e-14 * np.maximum(np.abs(ov[f]), osc[f, 0])), w
+            if sg[w] is not None:
+                got = host(sg[w])
+                assert np.all(np.abs(got - og[f]) <= 1e-12 * np.maximum(np.abs(og[f]), osc[f, 1:])), w
+                assert np.all(np.abs(got - host(g2[f])) <= 1e-14 * np.maximum(np.abs(og[f]), osc[f, 1:])), w
