@@ -201,9 +201,18 @@ struct BatchFwdState {
   hipEvent_t ev_call[2] = {nullptr, nullptr};
   bool call_pending[2] = {false, false};
   int call_slot = 0;
+  // pinned source of the one upload of the static tables (kept until that
+  // copy has run)
+  char* h_static = nullptr;
+  hipEvent_t ev_static = nullptr;
   int threads = 0, grid_mul = 0;   // tuned
   std::vector<void*> owned;
   ~BatchFwdState() {
+    if (ev_static) {
+      (void)hipEventSynchronize(ev_static);
+      (void)hipEventDestroy(ev_static);
+    }
+    pinned_free(h_static);
     for (int k = 0; k < 2; ++k) {
       if (call_pending[k]) (void)hipEventSynchronize(ev_call[k]);
       if (ev_call[k]) (void)hipEventDestroy(ev_call[k]);
@@ -241,21 +250,29 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
     lp[i] = b->plans[i]->d_lev_off;
     nl[i] = b->plans[i]->nlev;
   }
-  S->d_plans = static_cast<PlanD*>(pool_alloc(sizeof(PlanD) * n));
-  S->d_levp = static_cast<int32_t**>(pool_alloc(sizeof(int32_t*) * n));
-  S->d_nlev = static_cast<int32_t*>(pool_alloc(sizeof(int32_t) * n));
-  S->d_counter = static_cast<int*>(pool_alloc(sizeof(int) * n));
-  for (void* p : {(void*)S->d_plans, (void*)S->d_levp, (void*)S->d_nlev, (void*)S->d_counter})
-    S->owned.push_back(p);
-  if (!S->d_plans || !S->d_levp || !S->d_nlev || !S->d_counter) {
+  // one upload from pinned staging: plans | level-offset pointers | level
+  // counts | force counters (zero), each region 256-byte aligned
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_lp = al(sizeof(PlanD) * n), o_nl = o_lp + al(sizeof(int32_t*) * n);
+  const size_t o_ct = o_nl + al(sizeof(int32_t) * n), bytes = o_ct + al(sizeof(int) * n);
+  char* d = static_cast<char*>(pool_alloc(bytes));
+  if (d) S->owned.push_back(d);
+  S->h_static = static_cast<char*>(pinned_alloc(bytes));
+  if (!d || !S->h_static) {
     *err = GCR_E_NOMEM;
     return nullptr;
   }
-  // pageable sources: each copy has consumed its source when it returns
-  if (hipMemcpyAsync(S->d_plans, pv.data(), sizeof(PlanD) * n, hipMemcpyHostToDevice, st) ||
-      hipMemcpyAsync(S->d_levp, lp.data(), sizeof(int32_t*) * n, hipMemcpyHostToDevice, st) ||
-      hipMemcpyAsync(S->d_nlev, nl.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) ||
-      hipMemsetAsync(S->d_counter, 0, sizeof(int) * n, st)) {
+  S->d_plans = reinterpret_cast<PlanD*>(d);
+  S->d_levp = reinterpret_cast<int32_t**>(d + o_lp);
+  S->d_nlev = reinterpret_cast<int32_t*>(d + o_nl);
+  S->d_counter = reinterpret_cast<int*>(d + o_ct);
+  std::memset(S->h_static, 0, bytes);
+  std::memcpy(S->h_static, pv.data(), sizeof(PlanD) * n);
+  std::memcpy(S->h_static + o_lp, lp.data(), sizeof(int32_t*) * n);
+  std::memcpy(S->h_static + o_nl, nl.data(), sizeof(int32_t) * n);
+  if (hipMemcpyAsync(d, S->h_static, bytes, hipMemcpyHostToDevice, st) ||
+      hipEventCreateWithFlags(&S->ev_static, hipEventDisableTiming) ||
+      hipEventRecord(S->ev_static, st)) {
     *err = GCR_E_HIP;
     return nullptr;
   }

@@ -151,9 +151,26 @@ __device__ __forceinline__ void fill_single(const PlanD& P, int p, double* F, co
   const double bv = b[p];
   if (blk >= 0) return;
   const uint32_t skip = code_skip(code);
+  if (!(skip & 1u) && code_r(code, 0) == 1) {
+    // corners k and k + 1 differ by one cell along x: one 16-byte load per
+    // pair (corner 0's partner is the ghost's own slot, read and unused)
+    const int lo = code_e(code, 0) < 0 ? -1 : 0;
 #pragma unroll
-  for (int k = 1; k < (1 << D); ++k)
-    val[k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
+    for (int k = 0; k < (1 << D); k += 2) {
+      if (k & skip) {
+        val[k] = val[k + 1] = 0.0;
+        continue;
+      }
+      double two[2];
+      __builtin_memcpy(two, F + c + corner_offset(P.g, code, k) + lo, 16);
+      val[k] = lo ? two[1] : two[0];
+      val[k + 1] = lo ? two[0] : two[1];
+    }
+  } else {
+#pragma unroll
+    for (int k = 1; k < (1 << D); ++k)
+      val[k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
+  }
   double X[3];
   stencil_span(P.g, code, c, X);
   ghost_weights<D>(dl, nn, X, bc, w);

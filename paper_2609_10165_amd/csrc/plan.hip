@@ -1098,55 +1098,67 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
       GCR_HIP(hipMemcpyAsync(df, hf, sizeof(double) * nf, hipMemcpyHostToDevice, st));
       B->inst[i].g.face[a] = df;
     }
-  D.d_inst = own<Inst>(D, ninst);
+  // the small per-instance tables that cross between host and device live in
+  // one device block with the layout of the pinned staging block, so each
+  // transfer is one contiguous copy:
+  //   R1 up:   instances | chunk starts | info (zeroed)
+  //   R4 down:                            info | g_off | lev_off | unit_lev
+  //   R2 down: if_off | chunk-list and band counts | interface offsets
+  //   R3 up:   hash offsets | hash masks
+  // each region 256-byte aligned
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_inst = 0, o_cs = o_inst + al(sizeof(Inst) * ninst);
+  const size_t o_info = o_cs + al(8 * (ninst + 1));
+  const size_t o_go = o_info + al(sizeof(InstInfo) * ninst);
+  const size_t o_lo = o_go + al(8 * (ninst + 1));
+  const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
+  const size_t o_if = o_ul + al(4 * (size_t)ninst * kMaxUnits);
+  const size_t o_nl = o_if + al(8 * (ninst + 1));
+  const size_t o_io = o_nl + al(8);
+  const size_t o_ho = o_io + al(8 * (ninst + 1));
+  const size_t o_hm = o_ho + al(8 * (ninst + 1));
+  const size_t stage_bytes = o_hm + al(4 * ninst);
+  char* tb = own<char>(D, stage_bytes);
+  if (!tb) return GCR_E_NOMEM;
+  D.d_inst = reinterpret_cast<Inst*>(tb + o_inst);
+  D.d_chunk_start = reinterpret_cast<int64_t*>(tb + o_cs);
+  D.d_info = reinterpret_cast<InstInfo*>(tb + o_info);
+  D.d_g_off = reinterpret_cast<int64_t*>(tb + o_go);
+  D.d_lev_off = reinterpret_cast<int32_t*>(tb + o_lo);
+  D.d_unit_lev = reinterpret_cast<int32_t*>(tb + o_ul);
+  D.d_if_off = reinterpret_cast<int64_t*>(tb + o_if);
+  D.d_nchunk_list = reinterpret_cast<int32_t*>(tb + o_nl);
+  D.d_nband = reinterpret_cast<int32_t*>(tb + o_nl + 4);
+  D.d_iface_off = reinterpret_cast<int64_t*>(tb + o_io);
+  D.d_hoff = reinterpret_cast<int64_t*>(tb + o_ho);
+  D.d_hmask = reinterpret_cast<uint32_t*>(tb + o_hm);
   D.d_tags = own<int8_t>(D, cells);
-  D.d_chunk_start = own<int64_t>(D, ninst + 1);
   D.d_chunk_cnt = own<int32_t>(D, chunks);
   D.d_span = own<int8_t>(D, chunks * (kChunk / (64 * kSeg)));
   D.d_chunk_list = own<int32_t>(D, chunks);
-  D.d_nchunk_list = own<int32_t>(D, 1);
   D.d_band = own<int32_t>(D, chunks * (kChunk / kSeg));   // every segment at most once
-  D.d_nband = own<int32_t>(D, 1);
   D.d_chunk_excl = own<int64_t>(D, chunks + 1);
   D.d_scan_tmp = own<int64_t>(D, (chunks + kScanTile - 1) / kScanTile + 1);
-  D.d_if_off = own<int64_t>(D, ninst + 1);
-  D.d_iface_off = own<int64_t>(D, ninst + 1);
-  D.d_g_off = own<int64_t>(D, ninst + 1);
-  D.d_info = own<InstInfo>(D, ninst);
-  D.d_lev_off = own<int32_t>(D, (size_t)ninst * (kMaxLevels + 1));
   D.d_unit_mem = own<int32_t>(D, (size_t)ninst * kMaxUnits * kMaxUnit);
   D.d_unit_cnt = own<int32_t>(D, (size_t)ninst * kMaxUnits);
-  D.d_unit_lev = own<int32_t>(D, (size_t)ninst * kMaxUnits);
   D.d_reach = own<uint32_t>(D, (size_t)ninst * kMaxResidual * (kMaxResidual / 32));
-  if (!D.d_unit_lev || !D.d_reach) return GCR_E_NOMEM;
-  if (!D.d_inst || !D.d_tags || !D.d_chunk_start || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_scan_tmp || !D.d_span || !D.d_chunk_list || !D.d_nchunk_list || !D.d_band || !D.d_nband ||
-      !D.d_if_off || !D.d_iface_off || !D.d_g_off || !D.d_info || !D.d_lev_off ||
-      !D.d_unit_mem || !D.d_unit_cnt)
+  if (!D.d_tags || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_scan_tmp || !D.d_span ||
+      !D.d_chunk_list || !D.d_band || !D.d_unit_mem || !D.d_unit_cnt || !D.d_reach)
     return GCR_E_NOMEM;
-  bool any_layer2 = false;
-  for (int i = 0; i < ninst; ++i) any_layer2 = any_layer2 || D.inst[i].layer2;
-  // pinned staging: [instances | chunk starts | if_off | hoff | hmask | g_off |
-  // info | lev_off | unit_lev], each region 256-byte aligned
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t o_inst = 0, o_cs = o_inst + al(sizeof(Inst) * ninst);
-  const size_t o_if = o_cs + al(8 * (ninst + 1)), o_ho = o_if + al(8 * (ninst + 1));
-  const size_t o_hm = o_ho + al(8 * (ninst + 1)), o_go = o_hm + al(4 * ninst);
-  const size_t o_info = o_go + al(8 * (ninst + 1)), o_lo = o_info + al(sizeof(InstInfo) * ninst);
-  const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
-  const size_t o_nl = o_ul + al(4 * (size_t)ninst * kMaxUnits);
-  const size_t o_io = o_nl + al(8);
-  const size_t stage_bytes = o_io + al(8 * (ninst + 1));
+  bool any_layer2 = false, any_2d = false;
+  for (int i = 0; i < ninst; ++i) {
+    any_layer2 = any_layer2 || D.inst[i].layer2;
+    any_2d = any_2d || D.inst[i].g.dim == 2;
+  }
   PinnedStage PS;
   PS.st = st;
   PS.p = (char*)pinned_alloc(stage_bytes);
   if (!PS.p) return GCR_E_NOMEM;
   std::memcpy(PS.p + o_inst, D.inst.data(), sizeof(Inst) * ninst);
   std::memcpy(PS.p + o_cs, chunk_start.data(), 8 * (ninst + 1));
+  std::memset(PS.p + o_info, 0, o_go - o_info);
   PS.pending = true;
-  GCR_HIP(hipMemcpyAsync(D.d_inst, PS.p + o_inst, sizeof(Inst) * ninst, hipMemcpyHostToDevice, st));
-  GCR_HIP(hipMemcpyAsync(D.d_chunk_start, PS.p + o_cs, sizeof(int64_t) * (ninst + 1),
-                         hipMemcpyHostToDevice, st));
-  GCR_HIP(hipMemsetAsync(D.d_info, 0, sizeof(InstInfo) * ninst, st));
+  GCR_HIP(hipMemcpyAsync(tb, PS.p, o_go, hipMemcpyHostToDevice, st));   // R1
 
   StageEvents T((g_profiling.load() & 1) != 0);
   T.mark(0, st);
@@ -1172,14 +1184,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   T.mark(2, st);
   GCR_HIP(hipGetLastError());
   D.if_off.resize(ninst + 1);
-  GCR_HIP(hipMemcpyAsync(PS.p + o_if, D.d_if_off, sizeof(int64_t) * (ninst + 1),
-                         hipMemcpyDeviceToHost, st));
-  GCR_HIP(hipMemcpyAsync(PS.p + o_nl, D.d_nchunk_list, sizeof(int32_t), hipMemcpyDeviceToHost,
-                         st));
-  GCR_HIP(hipMemcpyAsync(PS.p + o_nl + 4, D.d_nband, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  if (any_layer2)
-    GCR_HIP(hipMemcpyAsync(PS.p + o_io, D.d_iface_off, sizeof(int64_t) * (ninst + 1),
-                           hipMemcpyDeviceToHost, st));
+  // R2 (the interface offsets only mean something with a second layer)
+  GCR_HIP(hipMemcpyAsync(PS.p + o_if, tb + o_if, o_ho - o_if, hipMemcpyDeviceToHost, st));
   GCR_HIP(hipStreamSynchronize(st));
   std::memcpy(D.if_off.data(), PS.p + o_if, 8 * (ninst + 1));
   D.iface_off = D.if_off;   // interface cells alone (second-layer candidates excluded)
@@ -1204,15 +1210,11 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
     D.hoff[i + 1] = D.hoff[i] + size;
   }
   D.d_htab = own<unsigned long long>(D, D.hoff[ninst]);
-  D.d_hoff = own<int64_t>(D, ninst + 1);
-  D.d_hmask = own<uint32_t>(D, ninst);
-  if (!D.d_htab || !D.d_hoff || !D.d_hmask) return GCR_E_NOMEM;
+  if (!D.d_htab) return GCR_E_NOMEM;
   std::memcpy(PS.p + o_ho, D.hoff.data(), 8 * (ninst + 1));
   std::memcpy(PS.p + o_hm, D.hmask.data(), 4 * ninst);
-  GCR_HIP(hipMemcpyAsync(D.d_hoff, PS.p + o_ho, sizeof(int64_t) * (ninst + 1),
-                         hipMemcpyHostToDevice, st));
-  GCR_HIP(hipMemcpyAsync(D.d_hmask, PS.p + o_hm, sizeof(uint32_t) * ninst,
-                         hipMemcpyHostToDevice, st));
+  GCR_HIP(hipMemcpyAsync(tb + o_ho, PS.p + o_ho, stage_bytes - o_ho, hipMemcpyHostToDevice,
+                         st));   // R3
   k_hash_clear<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_htab, D.hoff[ninst]);
   const int64_t nblk = (nif + 1023) / 1024;
   D.d_if_cell = own<int32_t>(D, cap);
@@ -1252,7 +1254,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
       !D.d_code || !D.d_level || !D.d_blk)
     return GCR_E_NOMEM;
   // the third normal component of 2D ghosts stays zero
-  GCR_HIP(hipMemsetAsync(D.d_if_n + 2 * cap, 0, sizeof(double) * cap, st));
+  if (any_2d) GCR_HIP(hipMemsetAsync(D.d_if_n + 2 * cap, 0, sizeof(double) * cap, st));
 
   T.mark(3, st);
   if (nif > 0) {
@@ -1336,15 +1338,9 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.g_off.resize(ninst + 1);
   D.info.resize(ninst);
   D.lev_off.resize((size_t)ninst * (kMaxLevels + 1));
-  GCR_HIP(hipMemcpyAsync(PS.p + o_go, D.d_g_off, sizeof(int64_t) * (ninst + 1),
-                         hipMemcpyDeviceToHost, st));
-  GCR_HIP(hipMemcpyAsync(PS.p + o_info, D.d_info, sizeof(InstInfo) * ninst, hipMemcpyDeviceToHost,
-                         st));
-  GCR_HIP(hipMemcpyAsync(PS.p + o_lo, D.d_lev_off, sizeof(int32_t) * ninst * (kMaxLevels + 1),
-                         hipMemcpyDeviceToHost, st));
   D.unit_lev.resize((size_t)ninst * kMaxUnits);
-  GCR_HIP(hipMemcpyAsync(PS.p + o_ul, D.d_unit_lev, sizeof(int32_t) * ninst * kMaxUnits,
-                         hipMemcpyDeviceToHost, st));
+  GCR_HIP(hipMemcpyAsync(PS.p + o_info, tb + o_info, o_if - o_info, hipMemcpyDeviceToHost,
+                         st));   // R4
   GCR_HIP(hipStreamSynchronize(st));
   PS.pending = false;
   std::memcpy(D.g_off.data(), PS.p + o_go, 8 * (ninst + 1));
