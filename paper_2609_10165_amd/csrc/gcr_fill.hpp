@@ -87,12 +87,30 @@ __device__ __forceinline__ void fill_group(const FillArgs& A, int p, int f0, boo
   }
   const uint32_t skip = code_skip(code);
   double val[kFieldGroup][8];
+  // x-adjacent corners (multiplier 1 along x, x not skipped): one 16-byte
+  // load per pair, as in fill_single
+  const bool pair = !(skip & 1u) && code_r(code, 0) == 1;
+  const int lo = code_e(code, 0) < 0 ? -1 : 0;
 #pragma unroll
   for (int j = 0; j < kFieldGroup; ++j) {
     const double* F = A.f[min(f0 + j, A.nf - 1)];
+    if (pair) {
 #pragma unroll
-    for (int k = 1; k < (1 << D); ++k)
-      val[j][k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
+      for (int k = 0; k < (1 << D); k += 2) {
+        if (k & skip) {
+          val[j][k] = val[j][k + 1] = 0.0;
+          continue;
+        }
+        double two[2];
+        __builtin_memcpy(two, F + c + corner_offset(P.g, code, k) + lo, 16);
+        val[j][k] = lo ? two[1] : two[0];
+        val[j][k + 1] = lo ? two[0] : two[1];
+      }
+    } else {
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k)
+        val[j][k] = (k & skip) ? 0.0 : F[c + corner_offset(P.g, code, k)];
+    }
   }
   double v[kFieldGroup];
 #pragma unroll

@@ -215,6 +215,9 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
   }
 }
 
+constexpr int kRelU = 4;   // ghosts per thread whose releases are issued together
+constexpr int kRelE = 4;   // their edges loaded up front (the rest, if any, one by one)
+
 template <bool InLds>
 __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   extern __shared__ uint32_t s_dyn[];
@@ -354,26 +357,52 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
       maxwidth = max(maxwidth, newly);
       if (tid == 0) lev_off[k] = placed;
       __syncthreads();
-      // ---- dependants of level k: the last edge into a node releases it
-      for (int i = tid; i < newly; i += 1024) {
-        const int g = cur[i];
-        const int ug = units ? blk_idx[lo + g] : -1;
-        const int e1 = roff[g + 1];
-        for (int e = roff[g]; e < e1; ++e) {
-          const int r = (int)(radj[e] - lo);
-          const int ur = units ? blk_idx[lo + r] : -1;
-          if (ur >= 0 && ur == ug) continue;
-          const int tgt = ur >= 0 ? (int)(unit_mem[ur * kMaxUnit] - lo) : r;
-          if (cnt_dec(cnt, tgt) != 1u) continue;
-          if (ur >= 0) {
-            unit_lev[ur] = k + 1;
-            for (int q = 0; q < unit_cnt[ur]; ++q) {
-              const int v = (int)(unit_mem[ur * kMaxUnit + q] - lo);
-              atomicOr(&bits[v >> 5], 1u << (v & 31));
-            }
-          } else {
-            atomicOr(&bits[r >> 5], 1u << (r & 31));
+      // ---- dependants of level k: the last edge into a node releases it.
+      // A thread takes kRelU ghosts of the level at a time and issues their
+      // loads together (list entry, edge range, first kRelE edges), so the
+      // dependent global round trips are paid once per group, not per ghost;
+      // the order of releases does not matter (a counter reaching zero sets
+      // a bit of the next level's bitmap)
+      auto release = [&](int rg, int ug) {
+        const int r = (int)(rg - lo);
+        const int ur = units ? blk_idx[lo + r] : -1;
+        if (ur >= 0 && ur == ug) return;
+        const int tgt = ur >= 0 ? (int)(unit_mem[ur * kMaxUnit] - lo) : r;
+        if (cnt_dec(cnt, tgt) != 1u) return;
+        if (ur >= 0) {
+          unit_lev[ur] = k + 1;
+          for (int q = 0; q < unit_cnt[ur]; ++q) {
+            const int v = (int)(unit_mem[ur * kMaxUnit + q] - lo);
+            atomicOr(&bits[v >> 5], 1u << (v & 31));
           }
+        } else {
+          atomicOr(&bits[r >> 5], 1u << (r & 31));
+        }
+      };
+      for (int i0 = tid; i0 < newly; i0 += 1024 * kRelU) {
+        int gg[kRelU], ea[kRelU], eb[kRelU], rr[kRelU][kRelE];
+#pragma unroll
+        for (int u = 0; u < kRelU; ++u) {
+          const int i = i0 + u * 1024;
+          gg[u] = i < newly ? cur[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kRelU; ++u) {
+          ea[u] = gg[u] >= 0 ? roff[gg[u]] : 0;
+          eb[u] = gg[u] >= 0 ? roff[gg[u] + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRelU; ++u)
+#pragma unroll
+          for (int q = 0; q < kRelE; ++q) rr[u][q] = ea[u] + q < eb[u] ? radj[ea[u] + q] : -1;
+#pragma unroll
+        for (int u = 0; u < kRelU; ++u) {
+          if (gg[u] < 0) continue;
+          const int ug = units ? blk_idx[lo + gg[u]] : -1;
+#pragma unroll
+          for (int q = 0; q < kRelE; ++q)
+            if (rr[u][q] >= 0) release(rr[u][q], ug);
+          for (int e = ea[u] + kRelE; e < eb[u]; ++e) release(radj[e], ug);
         }
       }
       __syncthreads();
