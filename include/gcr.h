@@ -94,8 +94,9 @@ typedef struct {
    * a, strictly increasing (copied by the library; lo[a], h[a] then
    * unused).  Cell centres lie midway between faces; Eq. delta_n and Eq.
    * stencil_anisotropic take the local cell widths; a stencil's x_2 - x_1
-   * is the difference of the two cell centres.  Not combined with
-   * GCR_LAYER2 (GCR_E_UNSUPPORTED). */
+   * is the difference of the two cell centres.  With GCR_LAYER2,
+   * (1.5 + sqrt(dim)/2) times the largest cell width over the smallest
+   * width along any axis must stay below 63 (else GCR_E_UNSUPPORTED). */
   const double* faces[3];
 } gcr_grid;
 

@@ -608,11 +608,9 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
   scheme &= ~ORC_LAYER2;
   if (scheme < 0 || scheme > 2) return ORC_E_ARG;
   int dim = g->dim;
-  int stretched = 0;
   for (int i = 0; i < dim; ++i) {
     if (g->n[i] < 1) return ORC_E_ARG;
     if (g->faces[i]) {
-      stretched = 1;
       for (int64_t k = 0; k < g->n[i]; ++k)
         if (!(g->faces[i][k + 1] > g->faces[i][k]) || !isfinite(g->faces[i][k + 1]))
           return ORC_E_ARG;
@@ -620,7 +618,6 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
       return ORC_E_ARG;
     }
   }
-  if (stretched && layer2) return ORC_E_UNSUPPORTED;
   if (s->kind == ORC_SHSTAR && dim != 3) return ORC_E_ARG;
   if ((s->kind == ORC_STAR2D || s->kind == ORC_AIRFOIL) && dim != 2) return ORC_E_ARG;
 
@@ -700,16 +697,24 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
    * here) are the solid cells with a fluid cell within R_i cells along each
    * axis i: going from x_c through its foot point S by a further half cell
    * diagonal reaches a point whose cell has a fluid centre (psi is
-   * 1-Lipschitz), at most (1.5 + sqrt(d)/2) h_max away from x_c since
-   * delta n <= h_max; hence R_i = floor((1.5 + sqrt(d)/2) h_max / h_i) + 1.
-   * Their distance to the boundary decides below. */
+   * 1-Lipschitz), at most (1.5 + sqrt(d)/2) w_max away from x_c since
+   * delta n <= w_max, the largest cell width of the grid; a displacement D
+   * along axis i crosses at most floor(D / w_min_i) + 1 cells, w_min_i the
+   * smallest width along i; hence R_i = floor((1.5 + sqrt(d)/2) w_max /
+   * w_min_i) + 1 (h_max / h_i on a uniform grid).  Their distance to the
+   * boundary decides below. */
   int64_t ncand = nif;
   if (layer2) {
-    double hmax = G->h[0];
-    for (int i = 1; i < dim; ++i) if (G->h[i] > hmax) hmax = G->h[i];
+    double wmax = 0.0, wmin[3] = {INFINITY, INFINITY, INFINITY};
+    for (int i = 0; i < dim; ++i)
+      for (int64_t k = 0; k < (G->faces[i] ? G->n[i] : 1); ++k) {
+        const double w = width(G, i, k);
+        if (w > wmax) wmax = w;
+        if (w < wmin[i]) wmin[i] = w;
+      }
     int64_t R[3] = {0, 0, 0};
     for (int i = 0; i < dim; ++i)
-      R[i] = (int64_t)floor((1.5 + 0.5 * sqrt((double)dim)) * hmax / G->h[i]) + 1;
+      R[i] = (int64_t)floor((1.5 + 0.5 * sqrt((double)dim)) * wmax / wmin[i]) + 1;
     for (int64_t c = 0; c < N; ++c) {
       if (!solid[c] || iface[c]) continue;
       int64_t ijk[3];

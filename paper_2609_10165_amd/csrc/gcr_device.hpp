@@ -56,6 +56,8 @@ struct Inst {
   ShapeD s;
   int scheme;          // kCGC, kCGC_ES, kHGC
   int layer2;          // 1: a second ghost layer (Sec. 7.1)
+  int l2r[3];          // its candidate box half-widths in cells per axis
+  int pad_;
   int64_t cell_off;    // offset of this instance in the concatenated tag array
   int64_t chunk_off;   // first classification chunk of this instance
   int64_t nchunk;

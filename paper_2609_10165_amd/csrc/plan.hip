@@ -334,11 +334,13 @@ static void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* l
 }
 
 // Second ghost layer (Sec. 7.1): the solid cells within R_i cells along each
-// axis i of a solid interface cell, R_i = floor((1.5 + sqrt(d)/2) h_max /
-// h_i) + 1, get the candidate mark 0x20.  Every cell with psi <= 1.5 delta n
-// is among them: a walk from it through its foot point reaches a fluid
-// centre within that box (delta n <= h_max, psi 1-Lipschitz), and the last
-// solid cell before it is a solid interface cell.  One workgroup per chunk
+// axis i of a solid interface cell, R_i = floor((1.5 + sqrt(d)/2) w_max /
+// w_min_i) + 1 (w_max the largest cell width, w_min_i the smallest along i;
+// h_max / h_i on a uniform grid; set per instance on the host), get the
+// candidate mark 0x20.  Every cell with psi <= 1.5 delta n is among them: a
+// walk from it through its foot point reaches a fluid centre within that
+// box (delta n <= w_max, psi 1-Lipschitz), and the last solid cell before it
+// is a solid interface cell.  One workgroup per chunk
 // of the interface chunk list (the grid covers every chunk; the rest exit):
 // the chunk's solid interface cells go to an LDS list, then the workgroup
 // walks the (cell, box offset) pairs, eight loads in flight per thread
@@ -365,18 +367,8 @@ __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts,
     if (c < g.ncell && (T[c] & 0x41) == 0x41) s_cell[atomicAdd(&s_n, 1)] = (int)c;
   }
   __syncthreads();
-  // (axes unrolled: a runtime index into g would move it to scratch)
-  double hmax = g.h[0];
-#pragma unroll
-  for (int a = 1; a < 3; ++a)
-    if (a < g.dim) hmax = fmax(hmax, g.h[a]);
-  int R[3] = {0, 0, 0}, W[3] = {1, 1, 1};
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-    if (a < g.dim) {
-      R[a] = (int)floor((1.5 + 0.5 * sqrt((double)g.dim)) * hmax / g.h[a]) + 1;
-      W[a] = 2 * R[a] + 1;
-    }
+  const int R[3] = {I.l2r[0], I.l2r[1], I.l2r[2]};   // 0 beyond the grid's dimension
+  const int W[3] = {2 * R[0] + 1, 2 * R[1] + 1, 2 * R[2] + 1};
   const int box = W[0] * W[1] * W[2];
   const int64_t items = (int64_t)s_n * box;
   uint32_t* words = reinterpret_cast<uint32_t*>(tags);
@@ -877,17 +869,17 @@ static double factorial(int n) {
   return f;
 }
 
+constexpr int kMaxL2Radius = 64;   // second-layer candidate box half-width, cells
+
 static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme, Inst* I) {
   std::memset(I, 0, sizeof(Inst));
   if (gg.dim != 2 && gg.dim != 3) return GCR_E_ARG;
   const int base = scheme & ~kLayer2;
   if (base < 0 || base > 2) return GCR_E_ARG;
   int64_t ncell = 1;
-  bool stretched = false;
   for (int a = 0; a < gg.dim; ++a) {
     if (gg.n[a] < 1) return GCR_E_ARG;
     if (gg.faces[a]) {
-      stretched = true;
       for (int64_t q = 0; q < gg.n[a]; ++q)
         if (!(gg.faces[a][q + 1] > gg.faces[a][q]) || !std::isfinite(gg.faces[a][q]) ||
             !std::isfinite(gg.faces[a][q + 1]))
@@ -898,7 +890,6 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
     ncell *= gg.n[a];
     if (ncell >= (int64_t(1) << 31)) return GCR_E_UNSUPPORTED;
   }
-  if (stretched && (scheme & kLayer2)) return GCR_E_UNSUPPORTED;
   I->g.dim = gg.dim;
   for (int a = 0; a < 3; ++a) {
     I->g.n[a] = a < gg.dim ? (int)gg.n[a] : 1;
@@ -915,6 +906,33 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
   I->g.ncell = ncell;
   I->scheme = base;
   I->layer2 = (scheme & kLayer2) ? 1 : 0;
+  if (I->layer2) {
+    // second-layer candidate box: every solid cell with psi <= 1.5 delta n
+    // has a fluid centre within (1.5 + sqrt(d)/2) w_max of its own (delta n
+    // <= w_max, the largest cell width), which lies at most
+    // floor(D / w_min_a) + 1 cells away along axis a (w_min_a the smallest
+    // width along a)
+    double wmax = 0.0, wmin[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < gg.dim; ++a) {
+      wmin[a] = gg.faces[a] ? HUGE_VAL : gg.h[a];
+      if (!gg.faces[a]) wmax = std::max(wmax, gg.h[a]);
+      else
+        for (int64_t q = 0; q < gg.n[a]; ++q) {
+          const double w = gg.faces[a][q + 1] - gg.faces[a][q];
+          wmax = std::max(wmax, w);
+          wmin[a] = std::min(wmin[a], w);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+      I->l2r[a] = 0;
+      if (a >= gg.dim) continue;
+      const double r = std::floor((1.5 + 0.5 * std::sqrt((double)gg.dim)) * wmax / wmin[a]) + 1.0;
+      // box sizes stay far inside int range; wider boxes mean a grid
+      // stretched beyond any use near the body
+      if (!(r <= (double)kMaxL2Radius)) return GCR_E_UNSUPPORTED;
+      I->l2r[a] = (int)r;
+    }
+  }
   ShapeD& s = I->s;
   s.kind = gs.kind;
   for (int a = 0; a < 3; ++a) s.c[a] = a < gg.dim ? gs.center[a] : 0.0;

@@ -513,7 +513,32 @@ def test_stretched_batch_forward(gcr):
         check_close(host(fld)[c], want[c], sc, "batched fill on a stretched grid")
 
 
-def test_stretched_second_layer_unsupported(gcr):
-    inst = synth.circle_stretched(seed=0)
+@pytest.mark.parametrize("scheme", [CGC, CGC_ES, HGC])
+@pytest.mark.parametrize("which", ["circle", "sphere"])
+def test_stretched_second_layer(gcr, which, scheme):
+    """Second ghost layer on a stretched grid (candidate box from the
+    largest and smallest cell widths): plan, fill and surface against the
+    oracle."""
+    inst = synth.sphere_stretched(seed=2) if which == "sphere" else synth.circle_stretched(seed=0)
+    op, gp = plan_pair(gcr, inst, scheme | synth.LAYER2)
+    assert op.min_margin > 1e-9
+    check_plan(op, gp, strict_geometry=True)
+    flds = (list(inst.fields) * 2)[:2]
+    got, want, scale = run_fill(gcr, op, gp, inst, flds, [DIRICHLET, NEUMANN])
+    cs = op.cell_scale(np.nan_to_num(want), scale)
+    v, g, anc = gp.surface(dev(inst.queries.x), [dev(x) for x in got])
+    ov, og, oanc, osc = op.surface_query(inst.queries.x, want, field_scale=cs)
+    assert np.array_equal(host(anc), oanc)
+    check_close(host(v), ov, osc[:, 0], "query value")
+    check_close(host(g), og, osc[:, 1:], "query gradient")
+
+
+def test_stretched_second_layer_refused_beyond_box_limit(gcr):
+    # widths growing 20 % per cell: the candidate box would exceed 64 cells
+    n = 64
+    f = synth.stretched_faces(n, -2.0, 2.0, 1.2)
+    grid = synth.Grid(2, (n, n, 1), (-2.0, -2.0, 0.0), (4.0 / n, 4.0 / n, 1.0), (f, f, None))
+    shape = synth.Shape(synth.SPHERE, (0.01, 0.02, 0.0), 0.5)
     with pytest.raises(gcr.GcrError):
-        gcr.Plan(inst.grid, inst.shape, HGC | synth.LAYER2)
+        gcr.Plan(grid, shape, HGC | synth.LAYER2)
+    gcr.Plan(grid, shape, HGC)   # the first layer alone is fine

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from synth import CGC, CGC_ES, HGC, DIRICHLET, NEUMANN
+from synth import CGC, CGC_ES, HGC, LAYER2, DIRICHLET, NEUMANN
 
 
 def ghost_centres(p):
@@ -25,7 +25,7 @@ def ghost_centres(p):
     return np.stack([g.centres(i)[idx[i]] for i in range(p.dim)])
 
 
-def brute_force_circle(grid, centre, R, scheme):
+def brute_force_circle(grid, centre, R, scheme, layer2=False):
     X, Y = grid.centres(0) - centre[0], grid.centres(1) - centre[1]
     WX, WY = grid.widths(0), grid.widths(1)
     x, y = np.meshgrid(X, Y)
@@ -46,10 +46,15 @@ def brute_force_circle(grid, centre, R, scheme):
         tags[~solid & other & (-psi < dn / 2)] = -2
     else:
         tags[solid & other] = 2
+    # second layer (Sec. 7.1): every other solid cell with psi <= 1.5 delta n,
+    # on the extended stencil
+    added = solid & (tags != 2) & (psi <= 1.5 * dn) if layer2 else np.zeros_like(solid)
+    tags[added] = 2
     r = np.ones((2,) + psi.shape, np.int64)
-    if scheme == CGC_ES:
-        for a, w in ((0, wx), (1, wy)):
-            r[a] = np.maximum(1, np.ceil(2 * np.abs(psi * n[a]) / w)).astype(np.int64)
+    ext = (tags == 2) if scheme == CGC_ES else added
+    for a, w in ((0, wx), (1, wy)):
+        q = np.maximum(1, np.ceil(2 * np.abs(psi * n[a]) / w)).astype(np.int64)
+        r[a][ext] = q[ext]
     return tags.ravel(), r.reshape(2, -1)
 
 
@@ -140,3 +145,57 @@ def test_ratio_one_is_the_uniform_grid(scheme):
     assert np.array_equal(pu.level, ps.level)
     assert np.array_equal(pu.r, ps.r)
     assert np.allclose(pu.delta, ps.delta, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme", [CGC, CGC_ES, HGC])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_stretched_second_layer_brute_force(scheme, seed):
+    """The second layer on a stretched grid: delta n and the multipliers
+    from local widths, the set by brute force over every cell."""
+    inst = synth.circle_stretched(seed=seed)
+    p = oracle.OraclePlan(inst.grid, inst.shape, scheme | LAYER2)
+    assert p.min_margin > 1e-9
+    tags, r = brute_force_circle(inst.grid, inst.shape.center, inst.shape.r0, scheme, layer2=True)
+    assert np.array_equal(p.tags, tags)
+    assert np.array_equal(p.r, r[:, p.ghost_cell])
+    p1 = oracle.OraclePlan(inst.grid, inst.shape, scheme)
+    assert p.n_ghost > p1.n_ghost
+    assert set(p1.ghost_cell.tolist()) <= set(p.ghost_cell.tolist())
+
+
+def test_stretched_second_layer_alpha_and_exactness():
+    """On the extended stencil |x_1,i - x_s,i| / (r_i dx_i) <= 1/2 with the
+    local width dx_i (the bound below Eq. stencil_anisotropic); bilinear and
+    trilinear fields reproduced to rounding; levels as longest paths."""
+    rng = np.random.default_rng(53)
+    for dim, inst in ((2, synth.circle_stretched(seed=2)), (3, synth.sphere_stretched(seed=1))):
+        g = inst.grid
+        for scheme in (CGC, HGC):
+            p = oracle.OraclePlan(g, inst.shape, scheme | LAYER2)
+            p1 = oracle.OraclePlan(g, inst.shape, scheme)
+            first = set(p1.ghost_cell.tolist())
+            ext = np.array([int(c) not in first for c in p.ghost_cell])
+            assert ext.any()
+            c = p.ghost_cell
+            idx = [c % g.n[0], (c // g.n[0]) % g.n[1]] + ([c // (g.n[0] * g.n[1])] if dim == 3 else [])
+            w = np.stack([g.widths(a)[idx[a]] for a in range(dim)])
+            alpha = np.abs(p.delta) / (p.r * w)
+            assert np.all(alpha[:, ext] <= 0.5 + 1e-15)
+            C = rng.normal(size=4 if dim == 2 else 8)
+            for bc in (DIRICHLET, NEUMANN):
+                fld = synth.polynomial_field(dim, C, bc)
+                exact = synth.sample(fld, g)
+                phi = exact.copy()
+                phi[p.tags != 0] = np.nan
+                S = ghost_centres(p) + p.delta
+                b = synth.bc_values(fld, S, p.normal, bc)[None]
+                out = p.fill(phi[None], [bc], b)[0]
+                sc = p.fill_scale(exact[None], [bc], b)[0]
+                err = np.abs(out[c] - exact[c])
+                assert np.all(err <= 1e-12 * np.maximum(sc, 1.0)), err.max()
+            pos = {int(x): k for k, x in enumerate(c)}
+            for k in range(p.n_ghost):
+                if p.unit[k] >= 0:
+                    continue
+                deps = [pos[int(x)] for x in p.stencil(k) if x >= 0 and int(x) in pos]
+                assert p.level[k] == 1 + max((p.level[d] for d in deps), default=0)
