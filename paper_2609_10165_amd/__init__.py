@@ -353,35 +353,71 @@ class Batch:
             _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
             self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self._owner))
 
-    def foot_points(self, stream=None):
+    def foot_points(self, stream=None, out=None):
         """gcr_batch_foot_points: (S, normal), each f64 [dim][total ghosts],
-        the instances' ghosts one after another."""
-        dev = torch.device("cuda")
+        the instances' ghosts one after another (into `out` = (S, normal)
+        if given)."""
         dim = self.plans[0].dim
         ng = sum(p.n_ghost for p in self.plans)
-        S = torch.empty((dim, ng), dtype=torch.float64, device=dev)
-        n = torch.empty((dim, ng), dtype=torch.float64, device=dev)
+        if out is not None:
+            S, n = out
+            if tuple(S.shape) != (dim, ng) or tuple(n.shape) != (dim, ng):
+                raise ValueError(f"out: two ({dim}, {ng}) tensors expected")
+        else:
+            dev = torch.device("cuda")
+            S = torch.empty((dim, ng), dtype=torch.float64, device=dev)
+            n = torch.empty((dim, ng), dtype=torch.float64, device=dev)
         _check(lib().gcr_batch_foot_points(self._h, _dptr(S), _dptr(n), _stream(stream)),
                "gcr_batch_foot_points")
         return S, n
 
-    def forward(self, nf, fields, bc_kind, bc_val, bc_type=None, nq=None, xq=None, nrm=None,
-                wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, sval=None, sgrad=None,
-                stream=None):
+    def forward(self, nf=None, fields=None, bc_kind=None, bc_val=None, bc_type=None, nq=None,
+                xq=None, nrm=None, wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, sval=None,
+                sgrad=None, stream=None, args=None):
         """gcr_batch_forward; per-field lists are instance-major [ninst*nf]
         (fields, bc_val, bc_type, sval, sgrad; None entries allowed in the
-        last three)."""
-        L = lib()
-        kinds = (ctypes.c_int32 * nf)(*[int(k) for k in bc_kind])
-        bt = None
+        last three).  `args`: a ForwardArgs packed once for repeated calls
+        with the same tensors, in place of the other arguments."""
+        a = args if args is not None else ForwardArgs(
+            nf, fields, bc_kind, bc_val, bc_type, nq, xq, nrm, wq, p_field, u_first, mu, F,
+            sval, sgrad)
+        if a.ninst != self.n:
+            raise ValueError(f"arguments packed for {a.ninst} instances, batch has {self.n}")
+        _check(lib().gcr_batch_forward(self._h, a.nf, a.fields, a.kinds, a.bt, a.bcv, a.nqa,
+                                       a.xa, a.na, a.wa, a.p_field, a.u_first, a.mu, a.F,
+                                       a.sval, a.sgrad, _stream(stream)),
+               "gcr_batch_forward")
+        return a.F_tensor
+
+
+class ForwardArgs:
+    """Arguments of Batch.forward checked and packed into the C-ABI's pointer
+    tables once, for repeated calls on the same tensors (the tensors are kept
+    alive here; their contents may change between calls)."""
+
+    def __init__(self, nf, fields, bc_kind, bc_val, bc_type=None, nq=None, xq=None, nrm=None,
+                 wq=None, p_field=-1, u_first=-1, mu=1.0, F=None, sval=None, sgrad=None):
+        if len(fields) % nf or len(bc_val) != len(fields):
+            raise ValueError("fields and bc_val: ninst * nf tensors each")
+        self.nf = int(nf)
+        self.ninst = len(fields) // nf
+        for name, ts, n in (("bc_type", bc_type, len(fields)), ("sval", sval, len(fields)),
+                            ("sgrad", sgrad, len(fields)), ("nq", nq, self.ninst),
+                            ("xq", xq, self.ninst), ("nrm", nrm, self.ninst),
+                            ("wq", wq, self.ninst)):
+            if ts is not None and len(ts) != n:
+                raise ValueError(f"{name}: {n} entries expected, got {len(ts)}")
+        self.kinds = (ctypes.c_int32 * nf)(*[int(k) for k in bc_kind])
+        self.bt = None
         if bc_type is not None:
-            bt = (ctypes.c_void_p * len(bc_type))()
+            self.bt = (ctypes.c_void_p * len(bc_type))()
             for i, t in enumerate(bc_type):
-                bt[i] = _dptr(t, torch.uint8) if t is not None else None
-        nqa = xa = na = wa = None
+                self.bt[i] = _dptr(t, torch.uint8) if t is not None else None
+        self.nqa = self.xa = self.na = self.wa = None
         if nq is not None:
-            nqa = (ctypes.c_int64 * self.n)(*[int(v) for v in nq])
-            xa, na, wa = _ptr_array(xq), _ptr_array(nrm), _ptr_array(wq)
+            self.nqa = (ctypes.c_int64 * len(nq))(*[int(v) for v in nq])
+            self.xa, self.na, self.wa = _ptr_array(xq), _ptr_array(nrm), _ptr_array(wq)
+
         def opt(ts):
             if ts is None:
                 return None
@@ -389,12 +425,12 @@ class Batch:
             for k, t in enumerate(ts):
                 a[k] = _dptr(t) if t is not None else None
             return a
-        _check(L.gcr_batch_forward(self._h, nf, _ptr_array(fields), kinds, bt,
-                                   _ptr_array(bc_val), nqa, xa, na, wa, int(p_field),
-                                   int(u_first), float(mu), _dptr(F), opt(sval), opt(sgrad),
-                                   _stream(stream)),
-               "gcr_batch_forward")
-        return F
+        self.fields, self.bcv = _ptr_array(fields), _ptr_array(bc_val)
+        self.sval, self.sgrad = opt(sval), opt(sgrad)
+        self.p_field, self.u_first, self.mu = int(p_field), int(u_first), float(mu)
+        self.F = _dptr(F)
+        self.F_tensor = F
+        self._keep = (fields, bc_val, bc_type, xq, nrm, wq, F, sval, sgrad)
 
 
 STAGES = ["classify", "interface_scan", "interface_compact", "geometry_tags",

@@ -336,3 +336,50 @@ def test_batch_forward_surface_outputs(gcr):
                 got = host(sg[w])
                 assert np.all(np.abs(got - og[f]) <= 1e-12 * np.maximum(np.abs(og[f]), osc[f, 1:])), w
                 assert np.all(np.abs(got - host(g2[f])) <= 1e-14 * np.maximum(np.abs(og[f]), osc[f, 1:])), w
+
+
+def test_batch_forward_packed_args(gcr):
+    """ForwardArgs packed once and reused on two fresh batches in a row: the
+    same fill, surface values and forces as the unpacked call, bitwise; a
+    pack for another number of instances is refused before any launch."""
+    insts = synth.stars64(seed=10, ninst=3, nmin=96, nmax=300)
+    nf = 3
+    base = []
+    for inst in insts:
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        vals = np.stack([synth.sample(f, inst.grid) for f in inst.fields])
+        vals[:, op.tags != 0] = np.nan
+        base += [dev(v) for v in vals]
+    grids, shapes = [i.grid for i in insts], [i.shape for i in insts]
+    B0 = gcr.Batch(grids, shapes, [HGC] * 3)
+    bcv = [dev(np.linspace(0.1, 0.9, p.n_ghost) + f) for p in B0.plans for f in range(nf)]
+    nqs = [i.queries.x.shape[1] for i in insts]
+    kw = dict(nq=nqs, xq=[dev(i.queries.x) for i in insts], nrm=[dev(i.queries.n) for i in insts],
+              wq=[dev(i.queries.w) for i in insts], p_field=2, u_first=0, mu=0.9)
+    F = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    sv = [torch.empty(n, dtype=torch.float64, device="cuda") for n in nqs for _ in range(nf)]
+    fk = [b.clone() for b in base]
+    B0.forward(nf, fk, [0] * nf, bcv, F=F, sval=sv, **kw)
+    torch.cuda.synchronize()
+    ref = ([f.clone() for f in fk], F.clone(), [v.clone() for v in sv])
+
+    def same(a, b):
+        return torch.equal(a.isnan(), b.isnan()) and torch.equal(a.nan_to_num(), b.nan_to_num())
+
+    work = [b.clone() for b in base]
+    args = gcr.ForwardArgs(nf, work, [0] * nf, bcv, F=F, sval=sv, **kw)
+    for _ in range(2):
+        for w, b in zip(work, base):
+            w.copy_(b)
+        F.zero_()
+        for v in sv:
+            v.fill_(7.0)
+        Bk = gcr.Batch(grids, shapes, [HGC] * 3)
+        Bk.forward(args=args)
+        torch.cuda.synchronize()
+        assert all(same(a, b) for a, b in zip(work, ref[0]))
+        assert torch.equal(F, ref[1])
+        assert all(same(a, b) for a, b in zip(sv, ref[2]))
+    B2 = gcr.Batch([insts[0].grid], [insts[0].shape], [HGC])
+    with pytest.raises(ValueError):
+        B2.forward(args=args)
