@@ -253,6 +253,8 @@ gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf,
 gcr_status gcr_batch_create(int32_t ninst, const gcr_grid* grids,
                             const gcr_shape* shapes, const int32_t* schemes,
                             void* stream, gcr_batch** out);
+/* Waits for the batch's gcr_batch_forward launches (on whatever stream) and
+ * releases its memory; other work on its plans must have finished. */
 void gcr_batch_destroy(gcr_batch* batch);
 /* Plan of instance i, owned by the batch (valid until gcr_batch_destroy). */
 gcr_status gcr_batch_plan(const gcr_batch* batch, int32_t i,

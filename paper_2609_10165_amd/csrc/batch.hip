@@ -205,9 +205,16 @@ struct BatchFwdState {
   // copy has run)
   char* h_static = nullptr;
   hipEvent_t ev_static = nullptr;
+  // recorded after every forward launch: the state and the batch's memory
+  // are released only once the last one has run, on whatever stream
+  hipEvent_t ev_done = nullptr;
   int threads = 0, grid_mul = 0;   // tuned
   std::vector<void*> owned;
   ~BatchFwdState() {
+    if (ev_done) {
+      (void)hipEventSynchronize(ev_done);
+      (void)hipEventDestroy(ev_done);
+    }
     if (ev_static) {
       (void)hipEventSynchronize(ev_static);
       (void)hipEventDestroy(ev_static);
@@ -549,6 +556,8 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   if (timed) (void)hipEventRecord(ev[1], st);
   const gcr_status rs =
       launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
+  if (!S->ev_done) GCR_HIP(hipEventCreateWithFlags(&S->ev_done, hipEventDisableTiming));
+  GCR_HIP(hipEventRecord(S->ev_done, st));
   if (timed) {
     (void)hipEventRecord(ev[2], st);
     std::lock_guard<std::mutex> lk(g_fwd_ev_mu);
