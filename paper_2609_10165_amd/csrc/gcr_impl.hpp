@@ -158,6 +158,7 @@ struct LevelsArgs {
   int32_t* listB;        // [cap] second level list
   int32_t* wide;         // [kWideState] completion flag, sizes of the levels
   int32_t* hist;         // [kWideLevels][cap / 256 + 1] per-tile level counts
+  int cur_cap;           // entries of a level list held in LDS (set at launch)
 };
 constexpr int kWideLevels = 128;               // deepest graph the wide layering orders
 constexpr int kWideState = kWideLevels + 8;

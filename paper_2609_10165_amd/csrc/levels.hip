@@ -218,7 +218,9 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
 constexpr int kRelU = 4;   // ghosts per thread whose releases are issued together
 constexpr int kRelE = 4;   // their edges loaded up front (the rest, if any, one by one)
 
-template <bool InLds>
+// InLds: byte counters and level bitmap in LDS; CurLds: the current level's
+// list too (it is written and read back within each level)
+template <bool InLds, bool CurLds>
 __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   extern __shared__ uint32_t s_dyn[];
   // after a finished wide layering there is nothing left to do
@@ -243,7 +245,11 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   int32_t* unit_cnt = L.unit_cnt + (int64_t)ii * kMaxUnits;
   int32_t* unit_lev = L.unit_lev + (int64_t)ii * kMaxUnits;
   uint32_t* reach = L.reach + (int64_t)ii * kMaxResidual * (kMaxResidual / 32);
-  int32_t* cur = L.listA + lo;
+  // the level list: its first cur_cap entries in LDS after the counters
+  // and bitmap (the rest, if a level is wider, in HBM)
+  int32_t* gcur = L.listA + lo;
+  int32_t* lcur = CurLds ? reinterpret_cast<int32_t*>(s_dyn + C + W) : nullptr;
+  const int ccap = CurLds ? L.cur_cap : 0;
   // instance ii owns words [(lo >> 2) + ii, + C) and [(lo >> 5) + ii, + W):
   // the next instance starts at ((lo + n) >> 2) + ii + 1 >= that end
   uint32_t* cnt = InLds ? s_dyn : L.cnt + (lo >> 2) + ii;
@@ -339,7 +345,8 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
             const int b = __ffs(word) - 1;
             word &= word - 1;
             const int g = w * 32 + b;
-            cur[pos] = g;
+            if (pos < ccap) lcur[pos] = g;
+            else gcur[pos] = g;
             perm[lo + g] = placed + pos;
             lev[lo + g] = k + 1;
             ++pos;
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
 #pragma unroll
         for (int u = 0; u < kRelU; ++u) {
           const int i = i0 + u * 1024;
-          gg[u] = i < newly ? cur[i] : -1;
+          gg[u] = i >= newly ? -1 : i < ccap ? lcur[i] : gcur[i];
         }
 #pragma unroll
         for (int u = 0; u < kRelU; ++u) {
@@ -542,7 +549,8 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
     (void)hipGetLastError();
     hipFuncAttributes fa{};
     int stat = 8192;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_levels<true>)) == hipSuccess)
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_levels<true, true>)) ==
+        hipSuccess)
       stat = (int)fa.sharedSizeBytes;
     (void)hipGetLastError();
     lds_max = std::max(0, std::max(a, b) - stat - 256);
@@ -574,16 +582,28 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
       F.wide = L.wide;
     }
   }
-  if (bytes <= lds_max) {
+  // what LDS is left holds the level list (worth it from a few thousand)
+  const int64_t cur_cap = bytes <= lds_max ? std::min<int64_t>(nn, (lds_max - bytes) / 4) : 0;
+  const int64_t bytes_cur = bytes + 4 * cur_cap;
+  F.cur_cap = (int)cur_cap;
+  if (cur_cap >= 2048) {
+    static int64_t attr = 0;
+    if (bytes_cur > attr) {
+      GCR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes_cur));
+      attr = bytes_cur;
+    }
+    k_levels<true, true><<<ninst, 1024, (size_t)bytes_cur, st>>>(F);
+  } else if (bytes <= lds_max) {
     static int64_t attr = 0;
     if (bytes > attr) {
-      GCR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true>),
+      GCR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true, false>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
       attr = bytes;
     }
-    k_levels<true><<<ninst, 1024, (size_t)bytes, st>>>(F);
+    k_levels<true, false><<<ninst, 1024, (size_t)bytes, st>>>(F);
   } else {
-    k_levels<false><<<ninst, 1024, 0, st>>>(F);
+    k_levels<false, false><<<ninst, 1024, 0, st>>>(F);
   }
   GCR_HIP(hipGetLastError());
   return GCR_OK;

@@ -720,6 +720,17 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* a, double 
   if (v > 0.0) atomicMax(a, (unsigned long long)__double_as_longlong(v));
 }
 
+// per-workgroup statistics of k_finalize, reduced per instance by
+// k_units_canonical (inst -1: the workgroup held no ghosts, or ghosts of
+// two instances, whose statistics it applied with atomics itself)
+struct FinPart {
+  double am[3];
+  int32_t rm[3];
+  int32_t fl;
+  int32_t inst;
+  int32_t pad;
+};
+
 __global__ __launch_bounds__(256) void k_finalize(
     const Inst* __restrict__ insts, int ninst, const int64_t* __restrict__ g_off, int64_t cap,
     const int32_t* __restrict__ g_cell, const double* __restrict__ g_psi,
@@ -727,7 +738,8 @@ __global__ __launch_bounds__(256) void k_finalize(
     const int32_t* __restrict__ lev, const int32_t* __restrict__ blk_idx,
     const int32_t* __restrict__ perm, int32_t* __restrict__ cell, double* __restrict__ delta,
     double* __restrict__ nrm, double* __restrict__ psi, uint32_t* __restrict__ code,
-    int32_t* __restrict__ level, int32_t* __restrict__ blk, InstInfo* __restrict__ info) {
+    int32_t* __restrict__ level, int32_t* __restrict__ blk, InstInfo* __restrict__ info,
+    FinPart* __restrict__ part) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ng_all = g_off[ninst];
   // per-thread statistics: max alpha and multiplier per axis, fluid-side count
@@ -768,6 +780,7 @@ __global__ __launch_bounds__(256) void k_finalize(
   if (threadIdx.x == 0) s_i0 = ii;
   __syncthreads();
   const bool uniform = __syncthreads_and(ii == s_i0 || ii < 0) && s_i0 >= 0;
+  if (!uniform && threadIdx.x == 0) part[blockIdx.x].inst = -1;
   if (!uniform) {
     if (ii >= 0) {
       for (int a = 0; a < 3; ++a) {
@@ -795,21 +808,70 @@ __global__ __launch_bounds__(256) void k_finalize(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int i0 = s_i0;
+    // one record per workgroup (atomics from every workgroup of an instance
+    // on its one record would serialise)
+    FinPart r;
     for (int a = 0; a < 3; ++a) {
-      atomic_max_nonneg(&info[i0].max_alpha_bits[a], s_am[a][0]);
-      if (s_rm[a][0]) atomicMax(&info[i0].rmax[a], s_rm[a][0]);
+      r.am[a] = s_am[a][0];
+      r.rm[a] = s_rm[a][0];
     }
-    if (s_fl[0]) atomicAdd(&info[i0].nfluid, s_fl[0]);
+    r.fl = s_fl[0];
+    r.inst = s_i0;
+    r.pad = 0;
+    part[blockIdx.x] = r;
   }
 }
 
-// unit members: linear-order positions -> instance-local canonical positions
-__global__ void k_units_canonical(const int32_t* __restrict__ perm,
-                                  const InstInfo* __restrict__ info,
-                                  int32_t* __restrict__ unit_mem_all,
-                                  const int32_t* __restrict__ unit_cnt_all) {
+// k_finalize's workgroup records of this instance folded into its info
+// (max, max, sum: the order does not matter), then unit members:
+// linear-order positions -> instance-local canonical positions
+__global__ __launch_bounds__(256) void k_units_canonical(const int32_t* __restrict__ perm,
+                                                         InstInfo* __restrict__ info,
+                                                         int32_t* __restrict__ unit_mem_all,
+                                                         const int32_t* __restrict__ unit_cnt_all,
+                                                         const FinPart* __restrict__ part,
+                                                         int64_t nparts) {
   const int ii = blockIdx.x;
+  {
+    double am[3] = {0.0, 0.0, 0.0};
+    int rm[3] = {0, 0, 0}, fl = 0;
+    for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
+      const FinPart& r = part[b];
+      if (r.inst != ii) continue;
+      for (int a = 0; a < 3; ++a) {
+        am[a] = fmax(am[a], r.am[a]);
+        rm[a] = max(rm[a], r.rm[a]);
+      }
+      fl += r.fl;
+    }
+    __shared__ double s_am[3][256];
+    __shared__ int s_rm[3][256], s_fl[256];
+    for (int a = 0; a < 3; ++a) {
+      s_am[a][threadIdx.x] = am[a];
+      s_rm[a][threadIdx.x] = rm[a];
+    }
+    s_fl[threadIdx.x] = fl;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) {
+        for (int a = 0; a < 3; ++a) {
+          s_am[a][threadIdx.x] = fmax(s_am[a][threadIdx.x], s_am[a][threadIdx.x + st]);
+          s_rm[a][threadIdx.x] = max(s_rm[a][threadIdx.x], s_rm[a][threadIdx.x + st]);
+        }
+        s_fl[threadIdx.x] += s_fl[threadIdx.x + st];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      InstInfo& I = info[ii];
+      for (int a = 0; a < 3; ++a) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(s_am[0 + a][0]);
+        if (bits > I.max_alpha_bits[a]) I.max_alpha_bits[a] = bits;   // non-negative: bit order
+        I.rmax[a] = max(I.rmax[a], s_rm[a][0]);
+      }
+      I.nfluid += s_fl[0];
+    }
+  }
   const int nu = info[ii].nunits;
   int32_t* um = unit_mem_all + (int64_t)ii * kMaxUnits * kMaxUnit;
   const int32_t* uc = unit_cnt_all + (int64_t)ii * kMaxUnits;
@@ -1328,6 +1390,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
       int64_t max_if = 0;
       for (int i = 0; i < ninst; ++i) max_if = std::max(max_if, D.if_off[i + 1] - D.if_off[i]);
       L.listB = L.wide = L.hist = nullptr;
+      L.cur_cap = 0;
       if (ninst == 1 && max_if >= wide_layering_min()) {
         // the reverse-edge counters are spent once the edges are filled
         L.listB = D.d_rcnt;
@@ -1339,11 +1402,17 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
       if (ls != GCR_OK) return ls;
     }
     T.mark(8, st);
-    k_finalize<<<blocks(nif, 256), 256, 0, st>>>(
-        D.d_inst, ninst, D.d_g_off, cap, D.d_g_cell, D.d_g_psi, D.d_g_n, D.d_g_code, D.d_lev,
-        D.d_blk_idx, D.d_perm, D.d_cell, D.d_delta, D.d_nrm, D.d_psi, D.d_code, D.d_level,
-        D.d_blk, D.d_info);
-    k_units_canonical<<<ninst, 256, 0, st>>>(D.d_perm, D.d_info, D.d_unit_mem, D.d_unit_cnt);
+    {
+      const unsigned nfb = blocks(nif, 256);
+      FinPart* fp = own<FinPart>(D, nfb);
+      if (!fp) return GCR_E_NOMEM;
+      k_finalize<<<nfb, 256, 0, st>>>(
+          D.d_inst, ninst, D.d_g_off, cap, D.d_g_cell, D.d_g_psi, D.d_g_n, D.d_g_code, D.d_lev,
+          D.d_blk_idx, D.d_perm, D.d_cell, D.d_delta, D.d_nrm, D.d_psi, D.d_code, D.d_level,
+          D.d_blk, D.d_info, fp);
+      k_units_canonical<<<ninst, 256, 0, st>>>(D.d_perm, D.d_info, D.d_unit_mem, D.d_unit_cnt,
+                                               fp, (int64_t)nfb);
+    }
     k_hash_remap<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_hoff, ninst, D.d_g_off, D.d_perm,
                                                               D.d_htab);
     T.mark(9, st);
