@@ -287,11 +287,15 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
           if (4 * w + q < n) v |= (uint32_t)dcnt[4 * w + q] << (8 * q);
         cnt[w] = v;
       }
-      for (int w = tid; w < W; w += 1024) {
-        uint32_t b = 0;
-        for (int q = 0; q < 32; ++q)
-          if (32 * w + q < n && dcnt[32 * w + q] == 0) b |= 1u << q;
-        bits[w] = b;
+      // level-1 bitmap: each wave reads 64 consecutive counts (one byte per
+      // lane) and writes the two words of their ballot
+      for (int g0 = tid & ~63; g0 < n; g0 += 1024) {
+        const int g = g0 + (tid & 63);
+        const unsigned long long m = __ballot(g < n && dcnt[g] == 0);
+        if ((tid & 63) == 0) {
+          bits[g0 >> 5] = (uint32_t)m;
+          if ((g0 >> 5) + 1 < W) bits[(g0 >> 5) + 1] = (uint32_t)(m >> 32);
+        }
       }
       __syncthreads();
     } else {
