@@ -77,6 +77,7 @@ def lib():
         L.orc_weights.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp, vp]
         L.orc_weights_raw.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_fill.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.orc_fresh_cells.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64]
         L.orc_fill_jacobi.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
         L.orc_fill_scale.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
         L.orc_surface_ghost.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -240,6 +241,18 @@ class OraclePlan:
         if bc_type.ndim == 1 and bc_type.size == nf:
             bc_type = np.repeat(bc_type[:, None], ng, axis=1)
         return np.ascontiguousarray(bc_type.reshape(nf, ng))
+
+    def fresh_cells(self, after):
+        """Fresh cells when the body of this plan moves to that of `after`
+        (same grid): (ascending linear indices, number uncovered)."""
+        nf, nu = ctypes.c_int64(), ctypes.c_int64()
+        st = lib().orc_fresh_cells(self._h, after._h, ctypes.byref(nf), ctypes.byref(nu), None, 0)
+        if st:
+            raise OracleError(st, "orc_fresh_cells")
+        out = np.zeros(max(nf.value, 1), np.int64)
+        lib().orc_fresh_cells(self._h, after._h, ctypes.byref(nf), ctypes.byref(nu), _vp(out),
+                              nf.value)
+        return out[:nf.value], nu.value
 
     def fill(self, fields, bc_type, bc_val):
         f = np.ascontiguousarray(np.array(fields, dtype=np.float64).reshape(-1, self.n_cells))

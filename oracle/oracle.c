@@ -582,6 +582,25 @@ void orc_plan_destroy(orc_plan* p) {
   free(p);
 }
 
+int orc_fresh_cells(const orc_plan* a, const orc_plan* b, int64_t* n_fresh,
+                    int64_t* n_uncovered, int64_t* list, int64_t cap) {
+  if (!a || !b || !n_fresh || !n_uncovered || a->dim != b->dim || a->ncell != b->ncell)
+    return ORC_E_ARG;
+  for (int i = 0; i < 3; ++i) if (a->g.n[i] != b->g.n[i]) return ORC_E_ARG;
+  int64_t nf = 0, nu = 0;
+  for (int64_t c = 0; c < a->ncell; ++c) {
+    const int was_solid = a->tag[c] == 1 || a->tag[c] == 2;
+    const int is_fluid = b->tag[c] == 0 || b->tag[c] == -2;
+    if (!(was_solid && is_fluid)) continue;
+    if (list && nf < cap) list[nf] = c;
+    ++nf;
+    if (a->tag[c] == 1) ++nu;
+  }
+  *n_fresh = nf;
+  *n_uncovered = nu;
+  return ORC_OK;
+}
+
 int64_t orc_n_cells(const orc_plan* p) { return p->ncell; }
 int64_t orc_n_ghost(const orc_plan* p) { return p->ng; }
 int64_t orc_n_interface(const orc_plan* p) { return p->nif; }

@@ -97,6 +97,17 @@ int orc_weights(const orc_plan* p, int64_t g, int bc, double* w, double* ws);
 int orc_weights_raw(int dim, int bc, const double* x2, const double* xs,
                     const double* n, double* w, double* ws);
 
+/* Fresh cells of a moved body (Sec. 7.1: moving boundaries expose fresh
+ * fluid cells, one reason for a second ghost layer).  a: the plan before the
+ * move, b: after, on the same grid.  A cell is fresh when its centre was
+ * solid in a (tag 1 or 2) and is fluid in b (tag 0 or -2); it is uncovered
+ * when it was not a ghost of a (tag 1: its value was never reconstructed).
+ * list (may be NULL) receives the fresh cells' linear indices, ascending,
+ * up to cap of them; the counts are always complete.  Returns ORC_E_ARG if
+ * the grids differ. */
+int orc_fresh_cells(const orc_plan* a, const orc_plan* b, int64_t* n_fresh,
+                    int64_t* n_uncovered, int64_t* list, int64_t cap);
+
 /* Fill.  fields: [nf][N_cells] in/out.  bc_type: [nf][N_g] (0 Dirichlet,
  * 1 Neumann).  bc_val: [nf][N_g] values at S (phi_s or dphi/dn). */
 int orc_fill(const orc_plan* p, int nf, double* fields, const int8_t* bc_type,
