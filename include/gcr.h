@@ -173,6 +173,22 @@ gcr_status gcr_plan_export(const gcr_plan* plan, int8_t* tags, int32_t* cell,
 gcr_status gcr_plan_foot_points(const gcr_plan* plan, double* S, double* normal,
                                 void* stream);
 
+/* Fresh cells of a moved body (Sec. 7.1: a moving boundary exposes fresh
+ * fluid cells, one reason for a second ghost layer).  before, after: plans
+ * of the body before and after a move, on the same grid (same sizes, origin
+ * and spacing; a stretched grid's faces must be the same too, which is not
+ * checked).  A cell is fresh when its centre was solid before (tag 1 or 2)
+ * and is fluid after (tag 0 or -2); it is uncovered when it was not a
+ * ghost before (tag 1), so no value was reconstructed there.
+ *   counts  device int64 [2]: fresh cells, uncovered fresh cells
+ *   list    device int32 [cap] or NULL: the fresh cells' linear indices,
+ *           ascending, the first cap of them
+ * Stream-ordered, no host synchronisation; uses scratch held by `after`.
+ * GCR_E_ARG if the grids differ. */
+gcr_status gcr_plan_fresh_cells(const gcr_plan* before, const gcr_plan* after,
+                                int64_t* counts, int32_t* list, int64_t cap,
+                                void* stream);
+
 /* Fill schedule.  0 = automatic (tuned), 1 = one launch per level,
  * 2 = one workgroup sweeping all levels, 3 = per-level launches captured in a
  * HIP graph and replayed.  `param` is reserved (0). */

@@ -25,7 +25,7 @@ SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
 SCHED_AUTO, SCHED_LEVELS, SCHED_WORKGROUP, SCHED_GRAPH = 0, 1, 2, 3
 SYMBOLS = [
     "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
-    "gcr_plan_export", "gcr_plan_foot_points", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
+    "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
     "gcr_batch_forward",
@@ -85,6 +85,7 @@ def lib():
         L.gcr_plan_level_offsets.argtypes = [vp, vp]
         L.gcr_plan_export.argtypes = [vp] + [vp] * 8 + [vp]
         L.gcr_plan_foot_points.argtypes = [vp, vp, vp, vp]
+        L.gcr_plan_fresh_cells.argtypes = [vp, vp, vp, vp, i64, vp]
         L.gcr_set_schedule.argtypes = [vp, i32, i32]
         L.gcr_fill.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.gcr_surface_ghost.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -249,6 +250,20 @@ class Plan:
         _check(lib().gcr_plan_foot_points(self._h, _dptr(S), _dptr(n), _stream(stream)),
                "gcr_plan_foot_points")
         return S, n
+
+    def fresh_cells(self, after: "Plan", cap: Optional[int] = None, stream=None):
+        """gcr_plan_fresh_cells: cells exposed when this plan's body moves to
+        `after`'s (same grid).  Returns (device int32 list of the first `cap`
+        fresh cells, ascending; device int64 counts [fresh, uncovered]); cap
+        None: up to every interface cell of `after`."""
+        dev = torch.device("cuda")
+        if cap is None:
+            cap = max(1, self.n_interface + after.n_interface)
+        counts = torch.empty(2, dtype=torch.int64, device=dev)
+        lst = torch.empty(cap, dtype=torch.int32, device=dev)
+        _check(lib().gcr_plan_fresh_cells(self._h, after._h, counts.data_ptr(), lst.data_ptr(),
+                                          int(cap), _stream(stream)), "gcr_plan_fresh_cells")
+        return lst, counts
 
     def fill(self, fields: Sequence[torch.Tensor], bc_kind: Sequence[int],
              bc_val: Sequence[torch.Tensor], bc_type: Optional[Sequence] = None, stream=None):

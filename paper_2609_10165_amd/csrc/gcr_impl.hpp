@@ -187,7 +187,7 @@ __device__ __forceinline__ int find_inst(const int64_t* off, int ninst, int64_t 
 
 // Schedule of the fill.
 enum { kSchedAuto = 0, kSchedLevels = 1, kSchedWorkgroup = 2, kSchedGraph = 3 };
-constexpr int kScratchSlots = 6;
+constexpr int kScratchSlots = 7;
 
 struct GraphCache;
 

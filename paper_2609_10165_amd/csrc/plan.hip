@@ -333,6 +333,106 @@ static void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* l
   k_scan_down<<<(unsigned)ntiles, 1024, 0, st>>>(cnt, n, tsum, excl, list);
 }
 
+// Fresh cells of a moved body (Sec. 7.1: a moving boundary exposes fresh
+// fluid cells): cells whose centre was solid before the move (tag 1 or 2)
+// and is fluid after it (tag 0 or -2); uncovered ones were not ghosts before
+// (tag 1), so no value was ever reconstructed there.  One workgroup per
+// chunk of 4096 cells, 16 per thread (tag arrays are 256-byte aligned).
+__global__ void k_fresh_zero(int64_t* counts) {
+  if (threadIdx.x < 2) counts[threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ uint32_t fresh_bits(const int8_t* __restrict__ a,
+                                               const int8_t* __restrict__ b, int64_t base,
+                                               int64_t n, int& unc) {
+  uint32_t m = 0;
+  unc = 0;
+  int8_t ta[kSeg], tb[kSeg];
+  if (base + kSeg <= n) {
+    *reinterpret_cast<uint4*>(ta) = *reinterpret_cast<const uint4*>(a + base);
+    *reinterpret_cast<uint4*>(tb) = *reinterpret_cast<const uint4*>(b + base);
+  } else {
+    for (int q = 0; q < kSeg; ++q) {
+      ta[q] = base + q < n ? a[base + q] : 0;
+      tb[q] = base + q < n ? b[base + q] : 0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q)
+    if ((ta[q] == 1 || ta[q] == 2) && (tb[q] == 0 || tb[q] == -2)) {
+      m |= 1u << q;
+      unc += ta[q] == 1;
+    }
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_fresh_count(const int8_t* __restrict__ a,
+                                                     const int8_t* __restrict__ b, int64_t n,
+                                                     int32_t* __restrict__ chunk_cnt,
+                                                     int64_t* __restrict__ counts) {
+  __shared__ int s_cnt, s_unc;
+  if (threadIdx.x == 0) s_cnt = s_unc = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kSeg;
+  int unc = 0;
+  const uint32_t m = base < n ? fresh_bits(a, b, base, n, unc) : 0u;
+  if (m) atomicAdd(&s_cnt, __popc(m));
+  if (unc) atomicAdd(&s_unc, unc);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    chunk_cnt[blockIdx.x] = s_cnt;
+    if (s_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(&counts[0]), (unsigned long long)s_cnt);
+    if (s_unc) atomicAdd(reinterpret_cast<unsigned long long*>(&counts[1]), (unsigned long long)s_unc);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fresh_scatter(const int8_t* __restrict__ a,
+                                                       const int8_t* __restrict__ b, int64_t n,
+                                                       const int64_t* __restrict__ excl,
+                                                       int32_t* __restrict__ list, int64_t cap) {
+  __shared__ int64_t sh[5];
+  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kSeg;
+  int unc = 0;
+  uint32_t m = base < n ? fresh_bits(a, b, base, n, unc) : 0u;
+  int64_t tot;
+  int64_t pos = excl[blockIdx.x] + block_excl_scan<256>(__popc(m), &tot, sh);
+  while (m) {
+    const int q = __ffs(m) - 1;
+    m &= m - 1;
+    if (pos < cap) list[pos] = (int32_t)(base + q);
+    ++pos;
+  }
+}
+
+extern "C" gcr_status gcr_plan_fresh_cells(const gcr_plan* a, const gcr_plan* b, int64_t* counts,
+                                           int32_t* list, int64_t cap, void* stream) {
+  if (!a || !b || !counts || cap < 0 || (cap > 0 && !list)) return GCR_E_ARG;
+  if (a->dim != b->dim || a->ncell != b->ncell) return GCR_E_ARG;
+  for (int ax = 0; ax < 3; ++ax)
+    if (a->inst.g.n[ax] != b->inst.g.n[ax] || a->inst.g.lo[ax] != b->inst.g.lo[ax] ||
+        a->inst.g.h[ax] != b->inst.g.h[ax])
+      return GCR_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = a->ncell, nch = (n + kChunk - 1) / kChunk;
+  const int64_t ntiles = (nch + kScanTile - 1) / kScanTile;
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t o_ex = al(sizeof(int32_t) * nch), o_ts = o_ex + al(sizeof(int64_t) * (nch + 1));
+  char* scr = static_cast<char*>(
+      plan_scratch(const_cast<gcr_plan*>(b), 6, o_ts + al(sizeof(int64_t) * (ntiles + 1))));
+  if (!scr) return GCR_E_NOMEM;
+  int32_t* ccnt = reinterpret_cast<int32_t*>(scr);
+  int64_t* excl = reinterpret_cast<int64_t*>(scr + o_ex);
+  int64_t* tsum = reinterpret_cast<int64_t*>(scr + o_ts);
+  k_fresh_zero<<<1, 64, 0, st>>>(counts);
+  k_fresh_count<<<(unsigned)nch, 256, 0, st>>>(a->tags, b->tags, n, ccnt, counts);
+  if (list && cap > 0) {
+    launch_scan(ccnt, nch, excl, nullptr, nullptr, tsum, st);
+    k_fresh_scatter<<<(unsigned)nch, 256, 0, st>>>(a->tags, b->tags, n, excl, list, cap);
+  }
+  GCR_HIP(hipGetLastError());
+  return GCR_OK;
+}
+
 // Second ghost layer (Sec. 7.1): the solid cells within R_i cells along each
 // axis i of a solid interface cell, R_i = floor((1.5 + sqrt(d)/2) w_max /
 // w_min_i) + 1 (w_max the largest cell width, w_min_i the smallest along i;
