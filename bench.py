@@ -24,6 +24,9 @@ Side measurements on the same GPU (reported beside the headline, never as
   fwd_bwd  384^3 grid, spherical-harmonic star, u, v, w, p, HGC: fill + drag
            forward, then the reverse-level adjoint, against the forward alone;
   layer2   the headline sphere with a second ghost layer, against HGC alone;
+  moving   that sphere moving 0.4 h per step: a plan per step, the fresh
+           cells against the previous plan (all covered by the second
+           layer), fill and force;
   large    the headline sphere on 1024^3 (classification at 1.07 GB).
 
 Prints one JSON line.  Only N=1 is supported (one GPU).
@@ -391,6 +394,7 @@ def main():
         extras["batched"] = bench_batched(gcr, torch, synth, args.extra_reps)
         extras["fwd_bwd"] = bench_fwd_bwd(gcr, torch, synth, args.extra_reps)
         extras["layer2"] = bench_layer2(gcr, torch, synth, args.extra_reps)
+        extras["moving"] = bench_moving(gcr, torch, synth, args.extra_reps)
         extras["large"] = bench_large(gcr, torch, synth, max(3, args.extra_reps // 2))
 
     cpu = None
@@ -588,6 +592,46 @@ def bench_layer2(gcr, torch, synth, reps):
         out[name] = {"ghosts": info["ghosts"], "levels": info["levels"], "step_ms": round(t, 4),
                      "ghost_cells_per_s": round(info["ghosts"] / (t * 1e-3), 1)}
     return out
+
+
+def bench_moving(gcr, torch, synth, reps):
+    """The headline sphere moving by 0.4 h per step (HGC with a second ghost
+    layer, so that the cells the move exposes were ghosts before): per step
+    a new plan at the new position, its fresh cells against the previous
+    plan, boundary data, fill of u, v, w, p and force.  Every step's fresh
+    cells must all be covered."""
+    import numpy as np
+    inst = synth.sphere256(seed=0)
+    g, h = inst.grid, inst.grid.h[0]
+    dev = torch.device("cuda")
+    fields = [_dev(torch, synth.sample(f, g), torch.float64) for f in inst.fields]
+    kinds = [DIRICHLET, DIRICHLET, DIRICHLET, NEUMANN]
+    q = inst.queries
+    xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
+    F = torch.empty(3, dtype=torch.float64, device=dev)
+    step_v = 0.4 * h * np.array([0.8, 0.48, 0.36])   # |v| = 0.4 h
+    state = {"k": 0, "prev": None, "counts": []}
+
+    def step():
+        k = state["k"]
+        state["k"] += 1
+        c = tuple(float(x) for x in np.asarray(inst.shape.center) + k * step_v)
+        plan = gcr.Plan(g, synth.Shape(inst.shape.kind, c, inst.shape.r0), 2 | 4)
+        if state["prev"] is not None:
+            _, counts = state["prev"].fresh_cells(plan)
+            state["counts"].append(counts)
+        S, nrm = plan.foot_points()
+        plan.fill(fields, kinds, list(bc_sphere_fields(S, nrm)))
+        plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
+        state["prev"] = plan
+
+    t, _ = _time(torch, step, reps)
+    counts = torch.stack(state["counts"]).cpu().numpy()
+    return {"workload": "sphere256 moving 0.4 h per step, HGC with a second ghost layer: "
+                        "plan at the new position + fresh cells against the previous plan + "
+                        "fill of u,v,w,p + force",
+            "step_ms": round(t, 4), "fresh_per_step": int(counts[:, 0].mean()),
+            "uncovered_total": int(counts[:, 1].sum()), "steps_checked": int(len(counts))}
 
 
 def bench_large(gcr, torch, synth, reps):
