@@ -213,16 +213,16 @@ struct BatchFwdState {
   ~BatchFwdState() {
     if (ev_done) {
       (void)hipEventSynchronize(ev_done);
-      (void)hipEventDestroy(ev_done);
+      event_give(ev_done);
     }
     if (ev_static) {
       (void)hipEventSynchronize(ev_static);
-      (void)hipEventDestroy(ev_static);
+      event_give(ev_static);
     }
     pinned_free(h_static);
     for (int k = 0; k < 2; ++k) {
       if (call_pending[k]) (void)hipEventSynchronize(ev_call[k]);
-      if (ev_call[k]) (void)hipEventDestroy(ev_call[k]);
+      event_give(ev_call[k]);
       pinned_free(h_call[k]);
     }
     for (void* p : owned) pool_free(p);
@@ -277,8 +277,8 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   std::memcpy(S->h_static, pv.data(), sizeof(PlanD) * n);
   std::memcpy(S->h_static + o_lp, lp.data(), sizeof(int32_t*) * n);
   std::memcpy(S->h_static + o_nl, nl.data(), sizeof(int32_t) * n);
-  if (hipMemcpyAsync(d, S->h_static, bytes, hipMemcpyHostToDevice, st) ||
-      hipEventCreateWithFlags(&S->ev_static, hipEventDisableTiming) ||
+  S->ev_static = event_take();
+  if (!S->ev_static || hipMemcpyAsync(d, S->h_static, bytes, hipMemcpyHostToDevice, st) ||
       hipEventRecord(S->ev_static, st)) {
     *err = GCR_E_HIP;
     return nullptr;
@@ -301,7 +301,29 @@ void gcr_batch_release_state(const gcr_batch* b) {
 // kernels; gcr_forward_times averages them.
 namespace {
 std::mutex g_fwd_ev_mu;
-std::vector<std::array<hipEvent_t, 3>> g_fwd_ev;
+std::vector<std::array<hipEvent_t, 3>> g_fwd_ev;    // recorded, not yet read
+std::vector<std::array<hipEvent_t, 3>> g_fwd_free;  // read, for reuse
+
+// three timing events for one forward call (reused once read)
+bool take_fwd_events(std::array<hipEvent_t, 3>* ev) {
+  {
+    std::lock_guard<std::mutex> lk(g_fwd_ev_mu);
+    if (!g_fwd_free.empty()) {
+      *ev = g_fwd_free.back();
+      g_fwd_free.pop_back();
+      return true;
+    }
+  }
+  for (auto& e : *ev) e = nullptr;
+  for (auto& e : *ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto& x : *ev)
+        if (x) (void)hipEventDestroy(x);
+      return false;
+    }
+  return true;
+}
 }  // namespace
 
 extern "C" gcr_status gcr_forward_times(float* out) {
@@ -318,7 +340,7 @@ extern "C" gcr_status gcr_forward_times(float* out) {
       f += mf;
       ++n;
     }
-    for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    g_fwd_free.push_back(e);
   }
   g_fwd_ev.clear();
   (void)hipGetLastError();
@@ -442,7 +464,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
       S->h_call_cap[k] = S->h_call[k] ? o : 0;
       if (!S->h_call[k]) return GCR_E_NOMEM;
     }
-    if (!S->ev_call[k]) GCR_HIP(hipEventCreateWithFlags(&S->ev_call[k], hipEventDisableTiming));
+    if (!S->ev_call[k] && !(S->ev_call[k] = event_take())) return GCR_E_HIP;
     std::memcpy(S->h_call[k], h, o);
     GCR_HIP(hipMemcpyAsync(S->d_call, S->h_call[k], o, hipMemcpyHostToDevice, st));
     GCR_HIP(hipEventRecord(S->ev_call[k], st));
@@ -471,9 +493,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   C.sval = sval ? reinterpret_cast<double* const*>(d + o_sval) : nullptr;
   C.sgrad = sgrad ? reinterpret_cast<double* const*>(d + o_sgrad) : nullptr;
   std::array<hipEvent_t, 3> ev{};
-  bool timed = (profiling_mask() & 2) != 0;
-  for (auto& e : ev)
-    if (timed && hipEventCreate(&e) != hipSuccess) timed = false;
+  bool timed = (profiling_mask() & 2) != 0 && take_fwd_events(&ev);
   if (timed) (void)hipEventRecord(ev[0], st);
   if (npts > 0) {
     BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
@@ -556,7 +576,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   if (timed) (void)hipEventRecord(ev[1], st);
   const gcr_status rs =
       launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
-  if (!S->ev_done) GCR_HIP(hipEventCreateWithFlags(&S->ev_done, hipEventDisableTiming));
+  if (!S->ev_done && !(S->ev_done = event_take())) return GCR_E_HIP;
   GCR_HIP(hipEventRecord(S->ev_done, st));
   if (timed) {
     (void)hipEventRecord(ev[2], st);

@@ -67,6 +67,36 @@ void pool_free(void* p) {
   g_live_blocks.erase(it);
 }
 
+// Events without timing, pooled like the memory blocks (creating one per
+// use costs more host time than a short kernel launch)
+namespace {
+std::mutex g_ev_mu;
+std::vector<hipEvent_t> g_ev_free;
+}  // namespace
+
+hipEvent_t event_take() {
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    if (!g_ev_free.empty()) {
+      hipEvent_t e = g_ev_free.back();
+      g_ev_free.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void event_give(hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  g_ev_free.push_back(e);
+}
+
 // Pinned host staging blocks (hipHostMalloc), pooled like the device blocks:
 // copies from and to them are asynchronous, so a plan build does not wait
 // for earlier work on its stream when it uploads its tables.

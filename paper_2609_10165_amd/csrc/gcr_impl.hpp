@@ -35,6 +35,9 @@ struct InstInfo {
 void* pool_alloc(size_t bytes);
 void* pinned_alloc(size_t bytes);
 void pinned_free(void* p);
+// pooled events without timing (event_give after the last wait on one)
+hipEvent_t event_take();
+void event_give(hipEvent_t e);
 
 // Pinned staging block of one plan build.  Until `pending` is cleared, an
 // exit synchronises the stream first, so no queued copy still uses the block
