@@ -279,6 +279,35 @@ def test_fill_shstar_and_airfoil(gcr):
     run_fill(gcr, op, gp, inst, inst.fields, [0, 0, 1])
 
 
+def test_airfoil4096_full_size(gcr):
+    """The airfoil workload at its full size (4096^2 cells, about 2,100
+    ghosts in chains over 100 levels deep): plans (CGC, HGC) bit-exact, the
+    HGC fill of u, v (Dirichlet) and p (Neumann), surface values at the
+    2 x 1024 quadrature points and the force, all against the oracle."""
+    inst = synth.airfoil4096(seed=0)
+    assert inst.grid.n[:2] == (4096, 4096)
+    op, gp = plan_pair(gcr, inst, CGC)
+    check_plan(op, gp)
+    op, gp = plan_pair(gcr, inst, HGC)
+    assert op.min_margin > 1e-9 and op.n_levels > 80
+    check_plan(op, gp)
+    got, want, scale = run_fill(gcr, op, gp, inst, inst.fields, [DIRICHLET, DIRICHLET, NEUMANN])
+    q = inst.queries
+    cs = op.cell_scale(np.nan_to_num(want), scale)
+    v, g, anc = gp.surface(dev(q.x), [dev(x) for x in got])
+    ov, og, oanc, osc = op.surface_query(q.x, want, field_scale=cs)
+    assert np.array_equal(host(anc), oanc)
+    check_close(host(v), ov, osc[:, 0], "query value")
+    check_close(host(g), og, osc[:, 1:], "query gradient")
+    mu = 0.3
+    F = gp.forces(dev(q.x), dev(q.n), dev(q.w), dev(got[2]), [dev(got[0]), dev(got[1])], mu)
+    Fo = op.forces(q.x, q.n, q.w, want[2], want[:2], mu)
+    _, _, _, ps = op.surface_query(q.x, want[2:3], field_scale=cs[2:3])
+    _, _, _, us = op.surface_query(q.x, want[:2], field_scale=cs[:2])
+    s = np.sum(np.abs(q.w) * (ps[0, 0] + 2 * mu * us[:, 1:].sum(axis=(0, 1))))
+    check_close(host(F), Fo, np.full(2, s), "forces")
+
+
 def test_fill_deterministic(gcr):
     inst = synth.sphere256(seed=2, n=96)
     op, gp = plan_pair(gcr, inst, HGC)
