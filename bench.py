@@ -343,6 +343,32 @@ def main():
     gcr.set_profiling(False)
     band_segments = seg[-1]
 
+    # a static body: the batch built once and forwarded repeatedly (as a
+    # solver fills every time step), level-by-level sweep against the tiled
+    # fill (tiles set up on the first call, outside the timing)
+    static = {}
+    gcr.set_profiling(gcr.PROFILE_FORWARD)
+    for mode, name in ((0, "sweep"), (2, "tiled")):
+        gcr.set_batch_tiling(mode)
+        Bs = gcr.Batch([grid] * len(SCHEMES), [shape] * len(SCHEMES), list(SCHEMES))
+        pk = buffers(tuple(p.n_ghost for p in Bs.plans))
+        bc_sphere_fields(*Bs.foot_points(out=(pk["S"], pk["n"])), out=pk["bc"])
+        for _ in range(3):
+            Bs.forward(args=pk["args"])
+        torch.cuda.synchronize()
+        gcr.forward_times()
+        t0.record(stream)
+        for _ in range(args.steps):
+            Bs.forward(args=pk["args"])
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ft = gcr.forward_times()
+        static[name] = {"ms_per_forward": round(t0.elapsed_time(t1) / args.steps, 4),
+                        "kernel_ms": round(ft["forward"], 5), "path": Bs.tiled()}
+        del Bs
+    gcr.set_batch_tiling(1)
+    gcr.set_profiling(False)
+
     # plain per-plan form of the same step, for comparison
     for _ in range(2):
         step_plain()
@@ -385,6 +411,14 @@ def main():
                 "algorithmic_bytes": fwd_bytes, "avg_ms": round(fwd_ms, 5),
                 "note": "latency-bound: 11-12 dependent levels, each a pass of dependent "
                         "loads and a barrier"}
+    for name in ("sweep", "tiled"):
+        km = static[name]["kernel_ms"]
+        gbs = fwd_bytes / (km * 1e-3) / 1e9
+        static[name]["achieved_gbs"] = round(gbs, 2)
+        static[name]["frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    static["workload"] = ("the step's batch built once, then fill + surface + force of every "
+                          "(scheme, field) repeated; kernel_ms: the fill, surface and force kernels "
+                          "of one call (tiled: k_tile_fill + k_batch_forward)")
     plain = {"ms_per_step": round(ms_plain, 4), "ghosts_per_step": ng_plain,
              "ghost_cells_per_s": round(ng_plain / (ms_plain * 1e-3), 1),
              "batched_speedup": round(ms_plain / ms_serial, 3)}
@@ -416,6 +450,7 @@ def main():
                    "ghosts_per_step": ng_step, "cells": ncell},
         "roofline": roofline,
         "roofline_classify": roofline_classify,
+        "static_forward": static,
         "plain_step": plain,
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "ms_per_step_stage_events": round(ms_step_profiled, 4),

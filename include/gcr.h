@@ -332,6 +332,26 @@ gcr_status gcr_last_build_times(float* ms);
  * their number to out[2] (-1, -1, 0 if none), and clears the record. */
 gcr_status gcr_forward_times(float* out);
 
+/* Tiled batched fill (process-wide).  Tiled, gcr_batch_forward fills the
+ * levels (Sec. 3.2) tile by tile: each instance's ghosts are grouped by the
+ * tile of cells holding them, each tile's workgroup fills the tile's ghosts
+ * and every ghost they depend on, transitively, in LDS, and writes its own;
+ * the values are those of the level-by-level sweep, bit for bit.  Finding
+ * the tiles' closures costs about as much as one sweep, so:
+ *   mode 0  always the level-by-level sweep;
+ *   mode 1  tiles from a batch's second forward call on (the default: a
+ *           batch forwarded once never pays for them);
+ *   mode 2  tiles from the first call.
+ * Batches with coupled units, graphs deeper than 128 levels or an instance
+ * of more than about 980,000 ghosts, and any batch whose tile closures would
+ * not fit, take the sweep.  Applies to batches not yet set up. */
+gcr_status gcr_set_batch_tiling(int32_t mode);
+/* Which fill a batch's forward calls use: *state = -1 the level-by-level
+ * sweep, 0 not decided yet (no forward call so far), 1 the tiled fill,
+ * 2 the sweep after the tile closures did not fit.  Synchronises the
+ * device (a diagnostic, not for the hot path). */
+gcr_status gcr_batch_tiled(const gcr_batch* batch, int32_t* state);
+
 /* Layering (Sec. 3.2) of a plan built alone: an instance with at least
  * `min_interface` interface cells is layered by the whole GPU (one grid-wide
  * round per level, then a stable counting sort by level); smaller ones, and

@@ -29,7 +29,7 @@ SYMBOLS = [
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
     "gcr_batch_forward",
-    "gcr_set_profiling", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
+    "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
 ]
 
 
@@ -100,6 +100,8 @@ def lib():
         L.gcr_batch_plan.argtypes = [vp, i32, P(vp)]
         L.gcr_batch_foot_points.argtypes = [vp, vp, vp, vp]
         L.gcr_set_profiling.argtypes = [i32]
+        L.gcr_set_batch_tiling.argtypes = [i32]
+        L.gcr_batch_tiled.argtypes = [vp, vp]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_forward_times.argtypes = [vp]
         L.gcr_last_build_times.argtypes = [vp]
@@ -368,6 +370,13 @@ class Batch:
             _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
             self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self._owner))
 
+    def tiled(self) -> int:
+        """gcr_batch_tiled: -1 sweep, 0 undecided, 1 tiled fill, 2 sweep after
+        the closures did not fit (synchronises the device)."""
+        st = ctypes.c_int32()
+        _check(lib().gcr_batch_tiled(self._h, ctypes.byref(st)), "gcr_batch_tiled")
+        return st.value
+
     def foot_points(self, stream=None, out=None):
         """gcr_batch_foot_points: (S, normal), each f64 [dim][total ghosts],
         the instances' ghosts one after another (into `out` = (S, normal)
@@ -461,6 +470,12 @@ def set_wide_layering(min_interface: int = 0):
 
 PROFILE_BUILD = 1     # stage timing of plan builds
 PROFILE_FORWARD = 2   # timing of the batched forward's kernels
+
+
+def set_batch_tiling(mode: int):
+    """Tiled batched fill: 0 off (level-by-level sweep), 1 from a batch's
+    second forward call (the default), 2 from its first."""
+    _check(lib().gcr_set_batch_tiling(int(mode)), "gcr_set_batch_tiling")
 
 
 def set_profiling(on):

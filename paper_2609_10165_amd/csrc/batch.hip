@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -50,6 +51,7 @@ struct BCall {
   const int32_t* anchor;         // [aoff[ninst]] anchor ghost of every point
   double* const* sval;           // [ninst*nf] surface values [nq_i] (null: none)
   double* const* sgrad;          // [ninst*nf] surface gradients [dim][nq_i] (null: none)
+  const int32_t* tile_flag;      // tiled fill ran when set and zero: items skip the levels
 };
 
 // Anchor ghost of every surface point of every instance, one group of lanes
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
     const uint8_t* bt = C.bct ? C.bct[w] : nullptr;
     const int kind = C.kind[f];
     const int32_t* lo_ = S.lev_off[i];
-    const int nl = S.nlev[i];
+    const int nl = (C.tile_flag && C.tile_flag[0] == 0) ? 0 : S.nlev[i];
     for (int l = 0; l < nl; ++l) {
       const int lo = lo_[l], hi = lo_[l + 1];
       for (int p = lo + (int)threadIdx.x; p < hi; p += T) fill_single<D>(P, p, F, b, bt, kind);
@@ -183,6 +185,332 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled fill.  Each instance's ghosts are grouped by the tile of cells that
+// holds them (kTileB3^3 cells in 3D, kTileB2^2 in 2D).  A tile's closure is
+// its own ghosts and every ghost they depend on, transitively; dependency
+// chains stay local, so closures are barely larger than the tiles.  One
+// workgroup per tile fills its closure level by level with the values in
+// LDS and writes only the tile's own ghosts to the fields: every value is
+// computed from the same inputs, in the same way, as by the per-level sweep,
+// each ghost is written by one workgroup, and no workgroup waits for
+// another.  The closures are found once per batch (first forward call).
+// A closure or member store that would overflow, a coupled unit or a graph
+// deeper than kTileLev levels sets a flag on the device; then the tiled fill
+// writes nothing and the per-item kernel sweeps the levels itself.
+constexpr int kTileB3 = 16, kTileB2 = 32;
+constexpr int kTileCap = 1024;   // members of one closure
+constexpr int kTileLev = 128;    // levels a closure may span
+
+struct TileArgs {
+  int ninst;
+  int tb;                        // tile extent in cells per axis
+  const int32_t* nt;             // [ninst][4] tiles per axis
+  const int64_t* slot_base;      // [ninst + 1] first tile slot of each instance
+  const int64_t* goff;           // [ninst + 1] first ghost of each instance
+  int64_t ng_total;
+  int32_t* count;                // [slots] ghosts per tile slot
+  int32_t* fillc;                // [slots] bucket fill pointers
+  const int64_t* off;            // [slots + 1] exclusive scan of count
+  const int32_t* list;           // [slots] occupied slots in order
+  const int32_t* nlist;          // [1] their number
+  int32_t* bucket;               // [ng_total] ghosts by tile
+  int32_t* mem;                  // [mcap] closure members (instance-local position | own << 31)
+  int16_t* ref;                  // [mcap][7] local index of each ghost corner, -1: not a ghost
+  int32_t* mbase;                // [tiles] first member of each closure
+  int16_t* tlev;                 // [tiles][kTileLev + 1] members before each level
+  int32_t* tinst;                // [tiles] instance of each closure
+  int32_t* mtotal;               // [1] members stored
+  int64_t mcap;
+  int32_t* flag;                 // [1] nonzero: tiled fill not usable
+};
+
+__global__ void k_tile_zero(int32_t* __restrict__ a, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] = 0;
+}
+
+__device__ __forceinline__ int tile_key(const GridD& g, const int32_t* nt, int tb, int c) {
+  int i, j, k;
+  unlinear(g, c, i, j, k);
+  return i / tb + nt[0] * (j / tb + nt[1] * (k / tb));
+}
+
+__global__ __launch_bounds__(256) void k_tile_count(BStatic S, TileArgs T, int bucket_pass) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= T.ng_total) return;
+  const int i = find_inst(T.goff, T.ninst, g);
+  const PlanD& P = S.plans[i];
+  const int p = (int)(g - T.goff[i]);
+  const int64_t slot = T.slot_base[i] + tile_key(P.g, T.nt + 4 * i, T.tb, P.cell[p]);
+  if (!bucket_pass) {
+    atomicAdd(&T.count[slot], 1);
+  } else {
+    const int at = atomicAdd(&T.fillc[slot], 1);
+    T.bucket[T.off[slot] + at] = (int32_t)g;
+  }
+}
+
+// one workgroup per occupied tile: mark the own ghosts in an LDS bitmap over
+// the instance's positions, then, from the deepest level down, the ghosts
+// the marked ones read (each level's marked positions first compacted into
+// an LDS list, one per thread); emit the marked positions in ascending order
+__device__ __forceinline__ uint32_t range_mask(int w, int a, int e) {
+  const int lo = w == (a >> 5) ? (a & 31) : 0;
+  const int hi = w == ((e - 1) >> 5) ? ((e - 1) & 31) : 31;
+  const uint32_t upto = hi == 31 ? 0xffffffffu : ((1u << (hi + 1)) - 1u);
+  return upto & ~((1u << lo) - 1u);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_closure(BStatic S, TileArgs T) {
+  extern __shared__ uint32_t s_tile[];
+  __shared__ int64_t sh[5];
+  __shared__ int32_t s_list[kTileCap];
+  __shared__ int s_m, s_base, s_bad;
+  const int b = blockIdx.x;
+  if (b >= T.nlist[0]) return;
+  const int64_t slot = T.list[b];
+  int i = 0;
+  {
+    int lo = 0, hi = T.ninst - 1;   // last instance whose first slot <= slot
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (T.slot_base[mid] <= slot) lo = mid;
+      else hi = mid - 1;
+    }
+    i = lo;
+  }
+  const PlanD& P = S.plans[i];
+  const int ng = P.ng, nl = S.nlev[i];
+  const int32_t* lof = S.lev_off[i];
+  const int W = (ng + 31) >> 5;
+  uint32_t* bits = s_tile;
+  int32_t* pre = reinterpret_cast<int32_t*>(s_tile + W);
+  const int key = (int)(slot - T.slot_base[i]);
+  const int tid = (int)threadIdx.x;
+  if (tid == 0) {
+    s_bad = (nl > kTileLev || P.nunits > 0) ? 1 : 0;
+    s_m = 0;
+  }
+  for (int w = tid; w < W; w += 256) bits[w] = 0u;
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(T.flag, 1);
+    return;
+  }
+  for (int64_t q = T.off[slot] + tid; q < T.off[slot + 1]; q += 256) {
+    const int p = (int)(T.bucket[q] - T.goff[i]);
+    atomicOr(&bits[p >> 5], 1u << (p & 31));
+  }
+  __syncthreads();
+  for (int l = nl - 1; l >= 1; --l) {   // level l + 1 reads only levels <= l
+    const int a = lof[l], e = lof[l + 1];
+    if (a >= e) continue;
+    const int wa = a >> 5, we = (e - 1) >> 5;
+    int run = 0;
+    for (int w0 = wa; w0 <= we; w0 += 256) {
+      const int w = w0 + tid;
+      uint32_t mm = w <= we ? (bits[w] & range_mask(w, a, e)) : 0u;
+      int64_t tot;
+      int pos = run + (int)block_excl_scan<256>(__popc(mm), &tot, sh);
+      while (mm) {
+        if (pos < kTileCap) s_list[pos] = (w << 5) + __ffs(mm) - 1;
+        ++pos;
+        mm &= mm - 1;
+      }
+      run += (int)tot;
+    }
+    if (run > kTileCap) {
+      if (tid == 0) atomicOr(T.flag, 2);
+      return;
+    }
+    __syncthreads();
+    for (int t = tid; t < run; t += 256) {
+      const int p = s_list[t];
+      const uint32_t code = P.code[p];
+      const uint32_t skip = code_skip(code);
+      const int c = P.cell[p];
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k) {
+        if (k & skip) continue;
+        const int qc = c + corner_offset(P.g, code, k);
+        const int8_t t8 = P.tags[qc];
+        if (t8 != 2 && t8 != -2) continue;
+        const int g2 = ghost_at(P, qc);
+        if (g2 >= 0) atomicOr(&bits[g2 >> 5], 1u << (g2 & 31));
+      }
+    }
+    __syncthreads();
+  }
+  // ranks: exclusive prefix of the word popcounts
+  int run = 0;
+  for (int w0 = 0; w0 < W; w0 += 256) {
+    const int w = w0 + tid;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<256>(w < W ? __popc(bits[w]) : 0, &tot, sh);
+    if (w < W) pre[w] = run + (int)ex;
+    run += (int)tot;
+  }
+  if (tid == 0) {
+    s_m = run;
+    if (run > kTileCap) {
+      atomicOr(T.flag, 2);
+      s_base = -1;
+    } else {
+      s_base = atomicAdd(T.mtotal, run);
+      if ((int64_t)s_base + run > T.mcap) {
+        atomicOr(T.flag, 4);
+        s_base = -1;
+      }
+    }
+  }
+  __syncthreads();
+  const int m = s_m, base = s_base;
+  if (base < 0) return;
+  auto rank = [&](int p) {
+    const int w = p >> 5;
+    return pre[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u));
+  };
+  // the members in ascending order, then one per thread
+  for (int w = tid; w < W; w += 256) {
+    uint32_t mm = bits[w];
+    int r = pre[w];
+    while (mm) {
+      s_list[r++] = (w << 5) + __ffs(mm) - 1;
+      mm &= mm - 1;
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += 256) {
+    const int p = s_list[j];
+    const uint32_t code = P.code[p];
+    const uint32_t skip = code_skip(code);
+    const int c = P.cell[p];
+    const bool own = tile_key(P.g, T.nt + 4 * i, T.tb, c) == key;
+    T.mem[base + j] = p | (own ? (int32_t)0x80000000u : 0);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      int16_t r = -1;
+      if (k < (1 << D) && !(k & skip)) {
+        const int qc = c + corner_offset(P.g, code, k);
+        const int8_t t8 = P.tags[qc];
+        if (t8 == 2 || t8 == -2) {
+          const int g2 = ghost_at(P, qc);
+          if (g2 >= 0) r = (int16_t)rank(g2);
+        }
+      }
+      T.ref[(int64_t)(base + j) * 7 + (k - 1)] = r;
+    }
+  }
+  for (int l = tid; l <= nl; l += 256) {
+    const int p = lof[l];
+    T.tlev[(int64_t)b * (kTileLev + 1) + l] = (int16_t)(p >= ng ? m : rank(p));
+  }
+  if (tid == 0) {
+    T.mbase[b] = base;
+    T.tinst[b] = i;
+  }
+}
+
+// one workgroup per closure: its members level by level, every field, with
+// the values of the closure in LDS ([member][field]); own members also to
+// the fields.  A (member, field) item reads, from HBM, only its metadata, its
+// boundary datum and the corners that are not ghosts, none of which any
+// level changes, so each thread loads its first item of the next level
+// before it computes the current one: between levels only the ghost
+// corners (LDS) remain on the path.
+template <int D>
+struct TileItem {
+  int j, f, c, bc;
+  uint32_t code;
+  int16_t ref[8];
+  double* F;
+  double bv, dl[3], nn[3], val[8];
+};
+
+template <int D>
+__device__ __forceinline__ void tile_load(const PlanD& P, const BCall& C, const TileArgs& T,
+                                          int i, int base, int j, int f, TileItem<D>& it) {
+  const int32_t mv = T.mem[base + j];
+  const int p = mv & 0x7fffffff;
+  const int w = i * C.nf + f;
+  it.j = j;
+  it.f = f;
+  it.c = P.cell[p];
+  it.code = P.code[p];
+  it.bc = C.kind[f] == 2 ? (int)C.bct[w][p] : C.kind[f];
+  it.bv = C.bcv[w][p];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    it.dl[a] = a < D ? P.dl[a][p] : 0.0;
+    it.nn[a] = a < D ? P.nn[a][p] : 0.0;
+  }
+  const uint32_t skip = code_skip(it.code);
+  it.F = C.fields[w];
+#pragma unroll
+  for (int k = 1; k < (1 << D); ++k) {
+    const int r = T.ref[(int64_t)(base + j) * 7 + (k - 1)];
+    it.ref[k] = (int16_t)r;
+    it.val[k] = ((k & skip) || r >= 0) ? 0.0 : it.F[it.c + corner_offset(P.g, it.code, k)];
+  }
+  it.j = mv < 0 ? -(j + 1) : j;   // own member: written to the field too
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_fill(BStatic S, BCall C, TileArgs T) {
+  extern __shared__ double s_val[];
+  const int b = blockIdx.x;
+  if (b >= T.nlist[0] || T.flag[0] != 0) return;
+  const int i = T.tinst[b];
+  const PlanD& P = S.plans[i];
+  const int nl = S.nlev[i], nf = C.nf;
+  const int base = T.mbase[b];
+  const int16_t* tl = T.tlev + (int64_t)b * (kTileLev + 1);
+  const int nt = (int)blockDim.x;
+  TileItem<D> cur, nxt;
+  bool have = false;
+  if (nl > 0 && (int)threadIdx.x < (tl[1] - tl[0]) * nf) {
+    const int t = tl[0] * nf + (int)threadIdx.x;
+    tile_load<D>(P, C, T, i, base, t / nf, t % nf, cur);
+    have = true;
+  }
+  for (int l = 0; l < nl; ++l) {
+    const int a = tl[l], e = tl[l + 1];
+    // first item of the next level, loaded before this level is computed
+    bool have_nxt = false;
+    if (l + 1 < nl && (int)threadIdx.x < (tl[l + 2] - e) * nf) {
+      const int t = e * nf + (int)threadIdx.x;
+      tile_load<D>(P, C, T, i, base, t / nf, t % nf, nxt);
+      have_nxt = true;
+    }
+    for (int t = a * nf + (int)threadIdx.x; t < e * nf; t += nt) {
+      TileItem<D> it;
+      if (t == a * nf + (int)threadIdx.x && have) it = cur;
+      else tile_load<D>(P, C, T, i, base, t / nf, t % nf, it);
+      const bool own = it.j < 0;
+      const int j = own ? -it.j - 1 : it.j;
+      const int f = it.f;
+      const uint32_t skip = code_skip(it.code);
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k)
+        if (!(k & skip) && it.ref[k] >= 0) it.val[k] = s_val[it.ref[k] * nf + f];
+      double X[3], wt[8];
+      stencil_span(P.g, it.code, it.c, X);
+      ghost_weights<D>(it.dl, it.nn, X, it.bc, wt);
+      double v = wt[0] * it.bv;
+#pragma unroll
+      for (int k = 1; k < (1 << D); ++k)
+        if (!(k & skip)) v += wt[k] * it.val[k];
+      s_val[j * nf + f] = v;
+      if (own) it.F[it.c] = v;
+    }
+    cur = nxt;
+    have = have_nxt;
+    __syncthreads();
+  }
+}
+
 struct BatchFwdState {
   PlanD* d_plans = nullptr;
   int32_t** d_levp = nullptr;
@@ -209,8 +537,20 @@ struct BatchFwdState {
   // are released only once the last one has run, on whatever stream
   hipEvent_t ev_done = nullptr;
   int threads = 0, grid_mul = 0;   // tuned
+  // tiled fill: 0 not set up yet, 1 set up, -1 not used for this batch
+  int tiled = 0;
+  int calls = 0;                   // forward calls so far
+  TileArgs T{};
+  int64_t tmax = 0;                // workgroups of the closure and fill launches
+  char* h_tile = nullptr;          // pinned source of the tile tables
+  hipEvent_t ev_tile = nullptr;
   std::vector<void*> owned;
   ~BatchFwdState() {
+    if (ev_tile) {
+      (void)hipEventSynchronize(ev_tile);
+      event_give(ev_tile);
+    }
+    pinned_free(h_tile);
     if (ev_done) {
       (void)hipEventSynchronize(ev_done);
       event_give(ev_done);
@@ -326,6 +666,27 @@ bool take_fwd_events(std::array<hipEvent_t, 3>* ev) {
 }
 }  // namespace
 
+extern "C" gcr_status gcr_batch_tiled(const gcr_batch* b, int32_t* state) {
+  if (!b || !state) return GCR_E_ARG;
+  BatchFwdState* S = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_bfs_mu);
+    for (auto& e : g_bfs)
+      if (e.first == b) S = e.second.get();
+  }
+  *state = 0;
+  if (!S || S->tiled == 0) return GCR_OK;
+  if (S->tiled < 0) {
+    *state = -1;
+    return GCR_OK;
+  }
+  int32_t flag = 0;
+  GCR_HIP(hipDeviceSynchronize());
+  GCR_HIP(hipMemcpy(&flag, S->T.flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+  *state = flag == 0 ? 1 : 2;
+  return GCR_OK;
+}
+
 extern "C" gcr_status gcr_forward_times(float* out) {
   if (!out) return GCR_E_ARG;
   std::lock_guard<std::mutex> lk(g_fwd_ev_mu);
@@ -350,9 +711,148 @@ extern "C" gcr_status gcr_forward_times(float* out) {
   return GCR_OK;
 }
 
+namespace {
+std::atomic<int> g_tiling{1};
+}  // namespace
+
+void gcr::set_batch_tiling(int mode) { g_tiling.store(mode < 0 ? 0 : (mode > 2 ? 2 : mode)); }
+int gcr::batch_tiling() { return g_tiling.load(); }
+
+// Tile tables and closures of a batch, on the forward stream (first forward
+// call).  false: the tiled fill is not used for this batch (switched off, a
+// coupled unit, a graph deeper than kTileLev levels, or an instance whose
+// position bitmap would not fit in LDS).
+static bool tile_setup(BatchFwdState* S, gcr_batch* b, int dim, hipStream_t st,
+                       gcr_status* err) {
+  *err = GCR_OK;
+  if (!batch_tiling()) return false;
+  const int n = (int)b->plans.size();
+  const int tb = dim == 3 ? kTileB3 : kTileB2;
+  int64_t ng_total = 0, max_ng = 0;
+  std::vector<int32_t> nt(4 * (size_t)n, 1);
+  std::vector<int64_t> sb(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const gcr_plan* p = b->plans[i].get();
+    if (p->info.nunits > 0 || p->nlev > kTileLev) return false;
+    int64_t cnt = 1;
+    for (int a = 0; a < 3; ++a) {
+      nt[4 * i + a] = (p->inst.g.n[a] + tb - 1) / tb;
+      cnt *= nt[4 * i + a];
+    }
+    sb[i + 1] = sb[i] + cnt;
+    ng_total += p->ng;
+    max_ng = std::max<int64_t>(max_ng, p->ng);
+  }
+  if (ng_total == 0) return false;
+  const size_t lds_closure = 8 * (size_t)((max_ng + 31) / 32);
+  if (lds_closure > 120 * 1024) return false;
+  const int64_t slots = sb[n], tmax = std::min<int64_t>(slots, ng_total);
+  const int64_t mcap = 4 * ng_total + 4096;
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t o_sb = al(sizeof(int32_t) * 4 * n);
+  const size_t o_cnt = o_sb + al(sizeof(int64_t) * (n + 1));
+  const size_t o_fill = o_cnt + al(sizeof(int32_t) * slots);
+  const size_t o_off = o_fill + al(sizeof(int32_t) * slots);
+  const size_t o_list = o_off + al(sizeof(int64_t) * (slots + 1));
+  const size_t o_nlist = o_list + al(sizeof(int32_t) * slots);
+  const size_t o_tsum = o_nlist + al(sizeof(int32_t) * 4);
+  const size_t o_bucket = o_tsum + al(sizeof(int64_t) * ((slots + 8191) / 8192 + 2));
+  const size_t o_mem = o_bucket + al(sizeof(int32_t) * ng_total);
+  const size_t o_ref = o_mem + al(sizeof(int32_t) * mcap);
+  const size_t o_mbase = o_ref + al(sizeof(int16_t) * 7 * mcap);
+  const size_t o_tlev = o_mbase + al(sizeof(int32_t) * tmax);
+  const size_t o_tinst = o_tlev + al(sizeof(int16_t) * (kTileLev + 1) * tmax);
+  const size_t o_small = o_tinst + al(sizeof(int32_t) * tmax);   // mtotal, flag
+  const size_t bytes = o_small + al(sizeof(int32_t) * 4);
+  char* d = static_cast<char*>(pool_alloc(bytes));
+  if (!d) {
+    *err = GCR_E_NOMEM;
+    return false;
+  }
+  S->owned.push_back(d);
+  S->h_tile = static_cast<char*>(pinned_alloc(o_cnt));
+  S->ev_tile = event_take();
+  if (!S->h_tile || !S->ev_tile) {
+    *err = GCR_E_NOMEM;
+    return false;
+  }
+  std::memcpy(S->h_tile, nt.data(), sizeof(int32_t) * 4 * n);
+  std::memcpy(S->h_tile + o_sb, sb.data(), sizeof(int64_t) * (n + 1));
+  if (hipMemcpyAsync(d, S->h_tile, o_cnt, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(S->ev_tile, st) != hipSuccess) {
+    *err = GCR_E_HIP;
+    return false;
+  }
+  TileArgs& T = S->T;
+  T.ninst = n;
+  T.tb = tb;
+  T.nt = reinterpret_cast<const int32_t*>(d);
+  T.slot_base = reinterpret_cast<const int64_t*>(d + o_sb);
+  T.goff = b->data->d_g_off;
+  T.ng_total = ng_total;
+  T.count = reinterpret_cast<int32_t*>(d + o_cnt);
+  T.fillc = reinterpret_cast<int32_t*>(d + o_fill);
+  int64_t* off = reinterpret_cast<int64_t*>(d + o_off);
+  int32_t* list = reinterpret_cast<int32_t*>(d + o_list);
+  int32_t* nlist = reinterpret_cast<int32_t*>(d + o_nlist);
+  T.off = off;
+  T.list = list;
+  T.nlist = nlist;
+  T.bucket = reinterpret_cast<int32_t*>(d + o_bucket);
+  T.mem = reinterpret_cast<int32_t*>(d + o_mem);
+  T.ref = reinterpret_cast<int16_t*>(d + o_ref);
+  T.mbase = reinterpret_cast<int32_t*>(d + o_mbase);
+  T.tlev = reinterpret_cast<int16_t*>(d + o_tlev);
+  T.tinst = reinterpret_cast<int32_t*>(d + o_tinst);
+  T.mtotal = reinterpret_cast<int32_t*>(d + o_small);
+  T.flag = reinterpret_cast<int32_t*>(d + o_small) + 1;
+  T.mcap = mcap;
+  S->tmax = tmax;
+  auto nb = [](int64_t v) { return (unsigned)((v + 255) / 256); };
+  const int64_t nz = (int64_t)(o_off - o_cnt) / 4;   // count and fillc (with padding)
+  k_tile_zero<<<nb(nz), 256, 0, st>>>(T.count, nz);
+  k_tile_zero<<<1, 256, 0, st>>>(T.mtotal, 2);
+  BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
+  k_tile_count<<<nb(ng_total), 256, 0, st>>>(bs, T, 0);
+  launch_scan(T.count, slots, off, list, nlist, reinterpret_cast<int64_t*>(d + o_tsum), st);
+  k_tile_count<<<nb(ng_total), 256, 0, st>>>(bs, T, 1);
+  const void* kc = dim == 2 ? reinterpret_cast<const void*>(&k_tile_closure<2>)
+                            : reinterpret_cast<const void*>(&k_tile_closure<3>);
+  if (lds_closure > 48 * 1024 &&
+      hipFuncSetAttribute(kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_closure) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  static bool fill_attr = false;
+  if (!fill_attr) {
+    const int mx = (int)(sizeof(double) * kTileCap * kMaxFields);
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_fill<2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_fill<3>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    fill_attr = true;
+  }
+  if (dim == 2) k_tile_closure<2><<<(unsigned)tmax, 256, lds_closure, st>>>(bs, T);
+  else k_tile_closure<3><<<(unsigned)tmax, 256, lds_closure, st>>>(bs, T);
+  if (hipGetLastError() != hipSuccess) {
+    *err = GCR_E_HIP;
+    return false;
+  }
+  return true;
+}
+
 static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int threads, int grid,
                                double* F, hipStream_t st) {
   BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
+  if (C.tile_flag) {
+    const size_t lds = sizeof(double) * kTileCap * C.nf;
+    if (dim == 2) k_tile_fill<2><<<(unsigned)S->tmax, 256, lds, st>>>(bs, C, S->T);
+    else k_tile_fill<3><<<(unsigned)S->tmax, 256, lds, st>>>(bs, C, S->T);
+  }
   if (dim == 2)
     k_batch_forward<2><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
   else
@@ -390,6 +890,18 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   gcr_status err = GCR_OK;
   BatchFwdState* S = state_of(batch, st, &err);
   if (!S) return err;
+  // tiles from the second forward call of a batch (mode 1: a batch used once
+  // does not pay for the closures), or from the first (mode 2)
+  ++S->calls;
+  if (S->tiled == 0) {
+    const int mode = batch_tiling();
+    if (mode == 0) {
+      S->tiled = -1;
+    } else if (mode == 2 || S->calls >= 2) {
+      S->tiled = tile_setup(S, batch, dim, st, &err) ? 1 : -1;
+      if (err != GCR_OK) return err;
+    }
+  }
   // items, largest first: fill work ~ ghosts, latency ~ levels, surface ~ points
   const int nitems = n * nf;
   std::vector<double> cost(nitems);
@@ -490,6 +1002,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   C.order = reinterpret_cast<const int32_t*>(d + o_order);
   C.aoff = nq ? reinterpret_cast<const int64_t*>(d + o_aoff) : nullptr;
   C.anchor = S->d_anchor;
+  C.tile_flag = S->tiled == 1 ? S->T.flag : nullptr;
   C.sval = sval ? reinterpret_cast<double* const*>(d + o_sval) : nullptr;
   C.sgrad = sgrad ? reinterpret_cast<double* const*>(d + o_sgrad) : nullptr;
   std::array<hipEvent_t, 3> ev{};
@@ -528,8 +1041,8 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     while ((int64_t(1) << b) < v) ++b;
     return b;
   };
-  const auto key = std::make_tuple(dim, nf, nq ? 1 : 0, bucket(nitems), bucket(max_ng),
-                                   bucket(max_lev));
+  const auto key = std::make_tuple(dim, nf, (nq ? 1 : 0) | (S->tiled == 1 ? 2 : 0),
+                                   bucket(nitems), bucket(max_ng), bucket(max_lev));
   if (S->threads == 0) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
     auto it = g_shape.find(key);

@@ -662,6 +662,12 @@ gcr_status gcr_set_profiling(int32_t mask) {
   return GCR_OK;
 }
 
+gcr_status gcr_set_batch_tiling(int32_t mode) {
+  if (mode < 0 || mode > 2) return GCR_E_ARG;
+  set_batch_tiling(mode);
+  return GCR_OK;
+}
+
 gcr_status gcr_set_wide_layering(int64_t min_interface) {
   if (min_interface < 0) return GCR_E_ARG;
   set_wide_layering(min_interface);

@@ -262,6 +262,15 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
 void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p);
 void set_profiling(int mask);
 int profiling_mask();   // bit 0 build stages, bit 1 batched forward
+// Exclusive scan of n counts into excl[n + 1] (total last); where list is
+// set, the indices with a nonzero count go there in order and their number
+// to nlist[0].  tsum: ceil(n / 8192) + 1 int64 of scratch (plan.hip).
+void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* list,
+                 int32_t* nlist, int64_t* tsum, hipStream_t st);
+// Tiled batched fill: 0 off, 1 from a batch's second forward call (the
+// default), 2 from its first (process-wide).
+void set_batch_tiling(int mode);
+int batch_tiling();
 void* plan_scratch(gcr_plan* p, int slot, size_t bytes);
 void last_build_times(float* ms);
 gcr_status status_from_err(uint32_t err);

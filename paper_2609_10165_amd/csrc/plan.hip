@@ -321,8 +321,8 @@ __global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ 
 
 // One workgroup up to two tiles, else the three-pass form (tsum: ntiles
 // int64 of scratch).
-static void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* list,
-                        int32_t* nlist, int64_t* tsum, hipStream_t st) {
+void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* list,
+                 int32_t* nlist, int64_t* tsum, hipStream_t st) {
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   if (ntiles <= 2 || !tsum) {
     k_scan<<<1, 1024, 0, st>>>(cnt, n, excl, list, nlist);

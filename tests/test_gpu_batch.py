@@ -383,3 +383,71 @@ def test_batch_forward_packed_args(gcr):
     B2 = gcr.Batch([insts[0].grid], [insts[0].shape], [HGC])
     with pytest.raises(ValueError):
         B2.forward(args=args)
+
+
+@pytest.mark.parametrize("case", ["stars", "spheres"])
+def test_batch_tiled_fill_equals_level_sweep(gcr, case):
+    """The tiled fill (closures of tiles in LDS) gives the level-by-level
+    sweep's fields, surface values and forces bit for bit."""
+    if case == "stars":
+        insts = synth.stars64(seed=11, ninst=6, nmin=128, nmax=900)
+        schemes, nf, kinds = [HGC] * 6, 3, [0, 0, 1]
+    else:
+        from synth import CGC, CGC_ES
+        insts = [synth.sphere256(seed=1, n=96)] * 3
+        schemes, nf, kinds = [CGC, CGC_ES, HGC], 4, [0, 0, 0, 1]
+    base = []
+    for inst, sch in zip(insts, schemes):
+        op = oracle.OraclePlan(inst.grid, inst.shape, sch)
+        vals = np.stack([synth.sample(f, inst.grid) for f in inst.fields[:nf]])
+        vals[:, op.tags != 0] = np.nan
+        base += [dev(v) for v in vals]
+    nqs = [i.queries.x.shape[1] for i in insts]
+    kw = dict(nq=nqs, xq=[dev(i.queries.x) for i in insts], nrm=[dev(i.queries.n) for i in insts],
+              wq=[dev(i.queries.w) for i in insts], p_field=nf - 1, u_first=0, mu=0.8)
+    out = []
+    for tiled in (True, False):
+        gcr.set_batch_tiling(2 if tiled else 0)
+        try:
+            B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], schemes)
+            bcv = [dev(np.cos(np.arange(p.n_ghost) * 0.37 + f)) for p in B.plans for f in range(nf)]
+            fk = [b.clone() for b in base]
+            F = torch.zeros((len(insts), 3), dtype=torch.float64, device="cuda")
+            sv = [torch.empty(n, dtype=torch.float64, device="cuda") for n in nqs for _ in range(nf)]
+            B.forward(nf, fk, kinds, bcv, F=F, sval=sv, **kw)
+            torch.cuda.synchronize()
+            assert B.tiled() == (1 if tiled else -1)
+            out.append((fk, F, sv))
+        finally:
+            gcr.set_batch_tiling(1)
+
+    def same(a, b):
+        return torch.equal(a.isnan(), b.isnan()) and torch.equal(a.nan_to_num(), b.nan_to_num())
+
+    (fa, Fa, sa), (fb, Fb, sb) = out
+    assert all(same(a, b) for a, b in zip(fa, fb))
+    assert torch.equal(Fa, Fb)
+    assert all(same(a, b) for a, b in zip(sa, sb))
+
+
+def test_batch_tiling_from_second_call(gcr):
+    """Default mode: the first forward call sweeps the levels, the second
+    sets the tiles up and uses them; both give the same fields."""
+    insts = synth.stars64(seed=12, ninst=3, nmin=128, nmax=400)
+    base = []
+    for inst in insts:
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        vals = np.stack([synth.sample(f, inst.grid) for f in inst.fields])
+        vals[:, op.tags != 0] = np.nan
+        base += [dev(v) for v in vals]
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * 3)
+    bcv = [dev(np.sin(np.arange(p.n_ghost) * 0.21 + f)) for p in B.plans for f in range(3)]
+    outs = []
+    for call in range(2):
+        fk = [b.clone() for b in base]
+        B.forward(3, fk, [0, 0, 1], bcv)
+        torch.cuda.synchronize()
+        outs.append(fk)
+        assert B.tiled() == (0 if call == 0 else 1)
+    for a, b in zip(*outs):
+        assert torch.equal(a.isnan(), b.isnan()) and torch.equal(a.nan_to_num(), b.nan_to_num())
