@@ -282,19 +282,29 @@ def main():
             e.synchronize()
         return ng
 
-    def run_pipelined_threads(nsteps):
-        """The same steps with the host work split over two threads: this
-        thread builds each step's batch (on the build stream), a second one
-        takes the built batch and enqueues its foot points, boundary data and
-        forward on the forward stream, so the next build starts while the
-        forward is being enqueued and run.  A batch is handed over only once
-        built (the build synchronises its stream), everything after that is
-        in order on the forward stream, and a batch is dropped only after its
-        forward's event."""
-        q = queue.Queue(maxsize=2)
-        err = []
+    s_build2 = torch.cuda.Stream(device=dev)
 
-        def worker():
+    def run_pipelined_threads(nsteps, nbuild=1):
+        """The same steps with the host work split over threads: `nbuild`
+        threads build batches (each on a build stream of its own), another
+        takes each built batch and enqueues its foot points, boundary data
+        and forward on the forward stream, so a build starts while earlier
+        forwards are being enqueued and run (and, with two builders, while
+        the other build waits for its read-backs).  A batch is handed over
+        only once built (the build synchronises its stream; the forward
+        stream also waits for an event recorded after it), everything after
+        that is in order on the forward stream, and a batch is dropped only
+        after its forward's event."""
+        q = queue.Queue(maxsize=2)
+        tickets = queue.Queue()
+        for _ in range(nsteps):
+            tickets.put(True)
+        for _ in range(nbuild):
+            tickets.put(None)
+        err = []
+        ng = [0]
+
+        def forwarder():
             held = collections.deque()
             t = 0
             try:
@@ -323,28 +333,40 @@ def main():
                     e.synchronize()
             except Exception as e:   # reported by the main thread
                 err.append(e)
-                while q.get() is not None:   # keep the builder from blocking
+                while q.get() is not None:   # keep the builders from blocking
                     pass
 
-        th = threading.Thread(target=worker)
-        th.start()
-        ng = 0
+        def builder(st):
+            try:
+                while tickets.get() is not None:
+                    with torch.cuda.stream(st):
+                        B = gcr.Batch([grid] * len(SCHEMES), [shape] * len(SCHEMES),
+                                      list(SCHEMES), stream=st)
+                        built = torch.cuda.Event()
+                        built.record(st)
+                    ng[0] = sum(p.n_ghost for p in B.plans)
+                    q.put((B, built))
+                    del B
+            except Exception as e:
+                err.append(e)
+                while tickets.get() is not None:   # let the other builders finish
+                    pass
+
+        fw = threading.Thread(target=forwarder)
+        fw.start()
+        bs = [threading.Thread(target=builder, args=(st,))
+              for st in (s_build, s_build2)[:nbuild]]
         try:
-            for _ in range(nsteps):
-                with torch.cuda.stream(s_build):
-                    B = gcr.Batch([grid] * len(SCHEMES), [shape] * len(SCHEMES),
-                                  list(SCHEMES), stream=s_build)
-                    built = torch.cuda.Event()
-                    built.record(s_build)
-                ng = sum(p.n_ghost for p in B.plans)
-                q.put((B, built))
-                del B
+            for b in bs:
+                b.start()
         finally:
+            for b in bs:
+                b.join()
             q.put(None)
-            th.join()
+            fw.join()
         if err:
             raise err[0]
-        return ng
+        return ng[0]
 
     def step_plain():
         """The same work one plan at a time: per-plan build, per-level fill
@@ -399,10 +421,16 @@ def main():
     ms_pipe1 = (time.perf_counter() - w0) * 1e3 / args.steps
     run_pipelined_threads(2)
     torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    run_pipelined_threads(args.steps)
+    torch.cuda.synchronize()
+    ms_pipe2 = (time.perf_counter() - w0) * 1e3 / args.steps
+    run_pipelined_threads(4, nbuild=2)
+    torch.cuda.synchronize()
     gcr.forward_times()   # drop the events of the runs before the timed one
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    ng_step = run_pipelined_threads(args.steps)
+    ng_step = run_pipelined_threads(args.steps, nbuild=2)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = wall * 1e3 / args.steps
@@ -536,6 +564,8 @@ def main():
                         "pipelined_speedup": round(ms_serial / ms_step, 3)},
         "pipelined_one_host_thread": {"ms_per_step": round(ms_pipe1, 4),
                                       "ghost_cells_per_s": round(ng_step / (ms_pipe1 * 1e-3), 1)},
+        "pipelined_one_build_thread": {"ms_per_step": round(ms_pipe2, 4),
+                                       "ghost_cells_per_s": round(ng_step / (ms_pipe2 * 1e-3), 1)},
         "wall_s": round(wall, 3),
         **extras,
         "cpu_baseline": cpu,

@@ -818,14 +818,24 @@ static bool tile_setup(BatchFwdState* S, gcr_batch* b, int dim, hipStream_t st,
   k_tile_count<<<nb(ng_total), 256, 0, st>>>(bs, T, 1);
   const void* kc = dim == 2 ? reinterpret_cast<const void*>(&k_tile_closure<2>)
                             : reinterpret_cast<const void*>(&k_tile_closure<3>);
-  if (lds_closure > 48 * 1024 &&
-      hipFuncSetAttribute(kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_closure) !=
-          hipSuccess) {
-    (void)hipGetLastError();
-    return false;
+  {
+    // the attribute only grows (per dimension), so concurrent set-ups on
+    // other host threads never leave it below a launch's size
+    static std::mutex mu;
+    static int64_t attr[2] = {48 * 1024, 48 * 1024};
+    std::lock_guard<std::mutex> lk(mu);
+    int64_t& a = attr[dim == 2 ? 0 : 1];
+    if (lds_closure > a) {
+      if (hipFuncSetAttribute(kc, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_closure) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
+      a = lds_closure;
+    }
   }
-  static bool fill_attr = false;
-  if (!fill_attr) {
+  // set once for the process (a thread-safe static), before any tiled fill
+  static const bool fill_attr = [] {
     const int mx = (int)(sizeof(double) * kTileCap * kMaxFields);
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_fill<2>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, mx) != hipSuccess ||
@@ -834,8 +844,9 @@ static bool tile_setup(BatchFwdState* S, gcr_batch* b, int dim, hipStream_t st,
       (void)hipGetLastError();
       return false;
     }
-    fill_attr = true;
-  }
+    return true;
+  }();
+  if (!fill_attr) return false;
   if (dim == 2) k_tile_closure<2><<<(unsigned)tmax, 256, lds_closure, st>>>(bs, T);
   else k_tile_closure<3><<<(unsigned)tmax, 256, lds_closure, st>>>(bs, T);
   if (hipGetLastError() != hipSuccess) {

@@ -29,6 +29,8 @@
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "gcr_impl.hpp"
 
 namespace gcr {
@@ -542,7 +544,11 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
 
 // Counters and bitmap in LDS when the largest instance fits, else in HBM.
 gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st) {
+  // device limits, taken once; the LDS attribute only grows, under the lock,
+  // so builds on several host threads never launch beyond it
+  static std::mutex mu;
   static int lds_max = -1;
+  std::unique_lock<std::mutex> lk(mu);
   if (lds_max < 0) {
     int dev = 0, a = 0, b = 0;
     (void)hipGetDevice(&dev);
@@ -559,6 +565,8 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
     (void)hipGetLastError();
     lds_max = std::max(0, std::max(a, b) - stat - 256);
   }
+  const int lds_avail = lds_max;
+  lk.unlock();
   const int64_t nn = std::max<int64_t>(max_n, 1);
   const int64_t bytes = 4 * (((nn + 3) >> 2) + ((nn + 31) >> 5));
   LevelsArgs F = L;   // the one-workgroup layering
@@ -566,6 +574,7 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
   if (L.wide && ninst == 1) {
     // grid: as many co-resident workgroups as fit, at most one per tile
     static int coop = -1;
+    lk.lock();
     if (coop < 0) {
       int dev = 0, ncu = 0, per = 0;
       (void)hipGetDevice(&dev);
@@ -577,7 +586,9 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
       (void)hipGetLastError();
       coop = std::max(0, std::min(per, 1) * ncu);
     }
-    const int64_t G = std::min<int64_t>(coop, std::max<int64_t>(1, (nn + 255) >> 8));
+    const int coop_n = coop;
+    lk.unlock();
+    const int64_t G = std::min<int64_t>(coop_n, std::max<int64_t>(1, (nn + 255) >> 8));
     if (G > 0) {
       LevelsArgs A = L;
       void* args[] = {&A};
@@ -587,24 +598,29 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
     }
   }
   // what LDS is left holds the level list (worth it from a few thousand)
-  const int64_t cur_cap = bytes <= lds_max ? std::min<int64_t>(nn, (lds_max - bytes) / 4) : 0;
+  const int64_t cur_cap =
+      bytes <= lds_avail ? std::min<int64_t>(nn, (lds_avail - bytes) / 4) : 0;
   const int64_t bytes_cur = bytes + 4 * cur_cap;
   F.cur_cap = (int)cur_cap;
   if (cur_cap >= 2048) {
     static int64_t attr = 0;
+    lk.lock();
     if (bytes_cur > attr) {
       GCR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true, true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes_cur));
       attr = bytes_cur;
     }
+    lk.unlock();
     k_levels<true, true><<<ninst, 1024, (size_t)bytes_cur, st>>>(F);
-  } else if (bytes <= lds_max) {
+  } else if (bytes <= lds_avail) {
     static int64_t attr = 0;
+    lk.lock();
     if (bytes > attr) {
       GCR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels<true, false>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
       attr = bytes;
     }
+    lk.unlock();
     k_levels<true, false><<<ninst, 1024, (size_t)bytes, st>>>(F);
   } else {
     k_levels<false, false><<<ninst, 1024, 0, st>>>(F);

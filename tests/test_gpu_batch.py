@@ -451,3 +451,76 @@ def test_batch_tiling_from_second_call(gcr):
         assert B.tiled() == (0 if call == 0 else 1)
     for a, b in zip(*outs):
         assert torch.equal(a.isnan(), b.isnan()) and torch.equal(a.nan_to_num(), b.nan_to_num())
+
+
+def test_batch_concurrent_builds_on_two_threads(gcr):
+    """Builds from two host threads at once, each on a stream of its own
+    (the library's pools, tables and launch attributes shared between them):
+    every plan equals, bit for bit, the plan of the same batch built alone,
+    and a forward run from one thread while the other builds equals the
+    forward run alone."""
+    import threading
+    from synth import CGC, CGC_ES
+    sph = synth.sphere256(seed=0)
+    stars = synth.stars64(seed=11, ninst=6, nmin=96, nmax=600)
+    cfgs = [([sph.grid] * 3, [sph.shape] * 3, [CGC, CGC_ES, HGC]),
+            ([i.grid for i in stars], [i.shape for i in stars], [HGC] * len(stars))]
+    keys = ("tags", "cell", "level", "r", "unit", "delta", "normal", "psi")
+
+    def snap(B):
+        return [(p.export(keys), p.level_offsets()) for p in B.plans]
+
+    ref = [snap(gcr.Batch(*c)) for c in cfgs]
+    # a forward on the star batch alone, then the same from a thread
+    rng = np.random.default_rng(3)
+    Bs = gcr.Batch(*cfgs[1])
+    vals = [rng.standard_normal(i.grid.n[0] * i.grid.n[1]) for i in stars]
+
+    def forward(B, st):
+        fields = [dev(v) for v in vals]
+        bcv = [torch.full((p.n_ghost,), 0.25, dtype=torch.float64, device="cuda")
+               for p in B.plans]
+        with torch.cuda.stream(st):
+            B.forward(1, fields, [0], bcv, stream=st)
+        st.synchronize()
+        return [host(f) for f in fields]
+
+    want_fwd = forward(Bs, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = [[], []]
+    fwd_got = []
+    err = []
+
+    def work(t):
+        st = torch.cuda.Stream()
+        try:
+            for r in range(6):
+                k = (t + r) % 2
+                with torch.cuda.stream(st):
+                    B = gcr.Batch(*cfgs[k], stream=st)
+                    s = snap(B)
+                st.synchronize()
+                got[t].append((k, s))
+                if t == 1 and r % 2 == 0:
+                    fwd_got.append(forward(Bs, st))
+        except Exception as e:   # noqa: BLE001 - reported below
+            err.append(e)
+
+    ths = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert not err, err
+    torch.cuda.synchronize()
+    for t in range(2):
+        assert len(got[t]) == 6
+        for k, s in got[t]:
+            for (a, la), (b, lb) in zip(s, ref[k]):
+                assert la == lb, (t, k)
+                for key in keys:
+                    assert torch.equal(a[key], b[key]), (t, k, key)
+    assert len(fwd_got) == 3
+    for fg in fwd_got:
+        for a, b in zip(fg, want_fwd):
+            assert np.array_equal(a, b, equal_nan=True)
