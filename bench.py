@@ -35,6 +35,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import gc
 import queue
 import threading
 import hashlib
@@ -57,8 +58,11 @@ DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--build-threads", type=int, default=3, choices=(1, 2, 3),
+                    help="host threads building batches in the timed steps (each on "
+                         "a stream of its own; the forwards are enqueued by another)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="oracle time budget of the CPU baseline sample")
@@ -282,7 +286,7 @@ def main():
             e.synchronize()
         return ng
 
-    s_build2 = torch.cuda.Stream(device=dev)
+    s_builds = [s_build] + [torch.cuda.Stream(device=dev) for _ in range(2)]
 
     def run_pipelined_threads(nsteps, nbuild=1):
         """The same steps with the host work split over threads: `nbuild`
@@ -355,7 +359,7 @@ def main():
         fw = threading.Thread(target=forwarder)
         fw.start()
         bs = [threading.Thread(target=builder, args=(st,))
-              for st in (s_build, s_build2)[:nbuild]]
+              for st in s_builds[:nbuild]]
         try:
             for b in bs:
                 b.start()
@@ -389,6 +393,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    gc.collect()
+    gc.freeze()   # see below
     gcr.forward_times()   # drop the warm-up calls' events
     rec = []
     t0 = torch.cuda.Event(enable_timing=True)
@@ -402,35 +408,42 @@ def main():
     t1.record(stream)
     torch.cuda.synchronize()
     ms_serial = t0.elapsed_time(t1) / args.steps
-    # the headline: the same steps pipelined over two streams, first from
-    # one host thread, then (timed for the headline) with the forward's
-    # host work on a second thread
+    # the headline: the same steps pipelined over streams, first from one
+    # host thread, then with the forward's host work on a second thread,
+    # then (timed for the headline) with `--build-threads` builders
     run_pipelined(2)
     torch.cuda.synchronize()
     use_graph = all(bc_graph(pk) is not None for pk in packs)
     if not use_graph:
         for pk in packs:
             pk["graph"] = None
-    run_pipelined(2)
+    run_pipelined(4)
     torch.cuda.synchronize()
+    # the warm-ups have grown the device-memory pools to the pipelines'
+    # depth; objects made so far are frozen out of the cycle collector's
+    # scans (a full scan of torch's objects costs milliseconds), as a
+    # long-running solver or server would
+    gc.collect()
+    gc.freeze()
     gcr.forward_times()   # drop the serial and warm-up calls' events
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     run_pipelined(args.steps)
     torch.cuda.synchronize()
     ms_pipe1 = (time.perf_counter() - w0) * 1e3 / args.steps
-    run_pipelined_threads(2)
+    run_pipelined_threads(8)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     run_pipelined_threads(args.steps)
     torch.cuda.synchronize()
     ms_pipe2 = (time.perf_counter() - w0) * 1e3 / args.steps
-    run_pipelined_threads(4, nbuild=2)
+    nbuild = args.build_threads
+    run_pipelined_threads(8 + 2 * nbuild, nbuild=nbuild)
     torch.cuda.synchronize()
     gcr.forward_times()   # drop the events of the runs before the timed one
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    ng_step = run_pipelined_threads(args.steps, nbuild=2)
+    ng_step = run_pipelined_threads(args.steps, nbuild=nbuild)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = wall * 1e3 / args.steps
@@ -550,8 +563,9 @@ def main():
         "config": {"workload": "sphere256: 256^3 grid on [-1,1]^3, sphere R=0.3 at sub-cell "
                                "offset, 4 FP64 fields (u,v,w Dirichlet, p Neumann), "
                                "CGC + CGC_ES + HGC per step as one batch, 2048 surface points; "
-                               "a step's build overlaps the previous step's forward (two streams)",
-                   "ghosts_per_step": ng_step, "cells": ncell},
+                               "steps pipelined: batches built by host threads on streams of "
+                               "their own, each step's forward on another stream",
+                   "ghosts_per_step": ng_step, "cells": ncell, "build_threads": nbuild},
         "roofline": roofline,
         "roofline_classify": roofline_classify,
         "static_forward": static,
