@@ -841,6 +841,46 @@ def bench_large(gcr, torch, synth, reps):
     c = float(np.median(cls))
     ncell = g.n[0] * g.n[1] * g.n[2]
     cbytes = ncell - 16 * nseg
+
+    # the same step as a batch of one: its forward (fill + surface + force
+    # in one launch) with the launch shape the tuner picks (for one large
+    # instance, a split sweep: many workgroups share each level), and with
+    # the per-item sweep (one workgroup per field) forced, for comparison
+    F2 = torch.zeros((1, 3), dtype=torch.float64, device=dev)
+    nqp = q.x.shape[1]
+    sv = [torch.empty(nqp, dtype=torch.float64, device=dev) for _ in range(4)]
+
+    def bstep(shape):
+        B = gcr.Batch([g], [inst.shape], [2])
+        S, nrm = B.foot_points()
+        bcv = list(bc_sphere_fields(S, nrm))
+        gcr.set_batch_shape(*shape)
+        try:
+            B.forward(4, fields, kinds, bcv, nq=[nqp], xq=[xq], nrm=[nq], wq=[wq], p_field=3,
+                      u_first=0, mu=1.0, F=F2, sval=sv)
+        finally:
+            gcr.set_batch_shape(0, 0)
+        return B
+
+    batched = {}
+    for name, shape in (("tuned", (0, 0)), ("per_item", (1024, 1))):
+        bstep(shape)
+        torch.cuda.synchronize()
+        gcr.set_profiling(gcr.PROFILE_FORWARD)
+        gcr.forward_times()
+        bt = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            bstep(shape)
+            b.record()
+            torch.cuda.synchronize()
+            bt.append(a.elapsed_time(b))
+        ft = gcr.forward_times()
+        gcr.set_profiling(False)
+        batched[name] = {"step_ms": round(float(np.median(bt)), 4),
+                         "forward_kernel_ms": round(ft["forward"], 4)}
     del fields
     torch.cuda.empty_cache()
     return {"workload": "sphere1024: 1024^3 grid on [-1,1]^3, the headline sphere, HGC, "
@@ -848,6 +888,7 @@ def bench_large(gcr, torch, synth, reps):
             "cells": ncell, "ghosts": ng, "step_ms": round(t, 4),
             "ghost_cells_per_s": round(ng / (t * 1e-3), 1),
             "classify_store_ms": round(c, 5),
+            "as_batch_of_one": batched,
             "classify_roofline": {"bound": "hbm", "kernel": "k_classify",
                                   "achieved": round(cbytes / (c * 1e-3) / 1e9, 2),
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -352,6 +352,19 @@ gcr_status gcr_set_batch_tiling(int32_t mode);
  * device (a diagnostic, not for the hot path). */
 gcr_status gcr_batch_tiled(const gcr_batch* batch, int32_t* state);
 
+/* Launch shape of the batched forward's level sweep (Sec. 3.2 fill, one
+ * level after another).  By default it is picked by timing candidates on the
+ * first call for a kind of batch and kept for the process: per-item
+ * workgroups (one (instance, field) pair each, sweeping all its levels), or
+ * a split sweep in which `-grid` workgroups per instance share each level
+ * and meet at a device-scope counter between levels.  Both give the same
+ * field values bit for bit; the force is the same bit for bit at the same
+ * `threads`.  threads = 0 and grid = 0 restore the tuned choice; otherwise
+ * threads is a power of two from 64 to 1024 and grid is 1..4 (per-item
+ * kernel on min(items, 256 grid) workgroups) or -1..-128 (split sweep; a
+ * batch with instances x -grid above 256 then fails with GCR_E_ARG).
+ * Process-wide; for tests and measurements. */
+gcr_status gcr_set_batch_shape(int32_t threads, int32_t grid);
 /* Layering (Sec. 3.2) of a plan built alone: an instance with at least
  * `min_interface` interface cells is layered by the whole GPU (one grid-wide
  * round per level, then a stable counting sort by level); smaller ones, and

@@ -29,7 +29,7 @@ SYMBOLS = [
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
     "gcr_batch_forward",
-    "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
+    "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.gcr_batch_foot_points.argtypes = [vp, vp, vp, vp]
         L.gcr_set_profiling.argtypes = [i32]
         L.gcr_set_batch_tiling.argtypes = [i32]
+        L.gcr_set_batch_shape.argtypes = [i32, i32]
         L.gcr_batch_tiled.argtypes = [vp, vp]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_forward_times.argtypes = [vp]
@@ -470,6 +471,13 @@ def set_wide_layering(min_interface: int = 0):
 
 PROFILE_BUILD = 1     # stage timing of plan builds
 PROFILE_FORWARD = 2   # timing of the batched forward's kernels
+
+
+def set_batch_shape(threads: int = 0, grid: int = 0):
+    """Launch shape of the batched forward's level sweep: (0, 0) the tuned
+    choice; else threads a power of two in 64..1024 and grid 1..4 (per-item
+    workgroups) or -1..-128 (split sweep, -grid workgroups per instance)."""
+    _check(lib().gcr_set_batch_shape(int(threads), int(grid)), "gcr_set_batch_shape")
 
 
 def set_batch_tiling(mode: int):

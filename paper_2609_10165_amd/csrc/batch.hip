@@ -10,8 +10,11 @@
 // which sum over the fields to w (-p n + mu (grad u + grad u^T) n).  The
 // last item of an instance to finish (device-scope counter, reset after use)
 // adds the shares in field order, so the result does not depend on timing.
-// Workgroup size and grid are picked by timing candidates on the first
-// call for a kind of batch and remembered for the process.
+// A batch of few large instances instead sweeps each level with many
+// workgroups of the instance together (k_batch_split: a device-scope counter
+// between levels), then does the surface items the same way.  Workgroup
+// size, grid and which of the two are picked by timing candidates on the
+// first call for a kind of batch and remembered for the process.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,6 +81,98 @@ __global__ __launch_bounds__(256) void k_batch_anchor(BStatic S, BCall C, int64_
   if (active && sub == 0) anchor[gq] = g;
 }
 
+// The surface part of item w = (instance, field), by a whole workgroup: the
+// field's value and gradient at the instance's points (one box-polynomial
+// evaluation serves both) and its share of the force, reduced over the
+// workgroup in a fixed order; the last item of the instance to finish adds
+// the shares in field order.
+template <int D>
+__device__ __forceinline__ void surface_item(const BStatic& S, const BCall& C, int w,
+                                             double (*red)[3], double* __restrict__ part,
+                                             int* __restrict__ counter,
+                                             double* __restrict__ Fout) {
+  const int T = blockDim.x;
+  const int i = w / C.nf, f = w % C.nf;
+  const PlanD& P = S.plans[i];
+  const double* F = C.fields[w];
+  // share of the force, and the field's value and gradient at the points
+  // (one box-polynomial evaluation serves both)
+  const int vc = f - C.u_first;
+  const bool isp = f == C.p_field, isu = vc >= 0 && vc < D;
+  double* const sv = C.sval ? C.sval[w] : nullptr;
+  double* const sg = C.sgrad ? C.sgrad[w] : nullptr;
+  double t[3] = {0.0, 0.0, 0.0};
+  if (C.nq && (isp || isu || sv || sg)) {
+    const int64_t nq = C.nq[i];
+    const double* xq = C.xq[i];
+    const double* nr = C.nrm[i];
+    const double* wq = C.wq[i];
+    for (int64_t q = threadIdx.x; q < nq; q += T) {
+      double x[3] = {0.0, 0.0, 0.0}, n[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        x[a] = xq[a * nq + q];
+        n[a] = nr[a * nq + q];
+      }
+      const int g = C.anchor[C.aoff[i] + q];
+      double val, gr[3];
+      if (g < 0) {
+        val = __longlong_as_double(0x7ff8000000000000LL);
+        gr[0] = gr[1] = gr[2] = val;
+      } else {
+        int ii, jj, kk;
+        unlinear(P.g, P.cell[g], ii, jj, kk);
+        const int ijk[3] = {ii, jj, kk};
+        double rel[3] = {0.0, 0.0, 0.0}, v[8];
+#pragma unroll
+        for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
+        corner_values<D>(P, g, F, v);
+        double X[3];
+        stencil_span(P.g, P.code[g], P.cell[g], X);
+        box_eval<D>(rel, X, v, val, gr);
+      }
+      if (sv) sv[q] = val;
+      if (sg)
+#pragma unroll
+        for (int a = 0; a < D; ++a) sg[a * nq + q] = gr[a];
+      const double wt = wq[q];
+      if (isp) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) t[a] += -wt * val * n[a];
+      } else if (isu) {
+        double gn = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) gn += gr[a] * n[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) t[a] += C.mu * wt * ((a == vc ? gn : 0.0) + n[vc] * gr[a]);
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) red[threadIdx.x][a] = t[a];
+  __syncthreads();
+  for (int s = T / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int a = 0; a < 3; ++a) red[threadIdx.x][a] += red[threadIdx.x + s][a];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < 3; ++a) part[(int64_t)w * 3 + a] = red[0][a];
+    __threadfence();
+    const int done = atomicAdd(&counter[i], 1);
+    if (done == C.nf - 1) {
+      __threadfence();
+      double s3[3] = {0.0, 0.0, 0.0};
+      for (int ff = 0; ff < C.nf; ++ff)
+        for (int a = 0; a < 3; ++a)
+          s3[a] += __hip_atomic_load(&part[((int64_t)i * C.nf + ff) * 3 + a], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+      for (int a = 0; a < 3; ++a) Fout[(int64_t)i * 3 + a] = s3[a];
+      atomicExch(&counter[i], 0);
+    }
+  }
+  __syncthreads();
+}
+
 template <int D>
 __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, double* __restrict__ part,
                                                         int* __restrict__ counter,
@@ -106,83 +201,76 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
         __syncthreads();
       }
     }
-    // share of the force, and the field's value and gradient at the points
-    // (one box-polynomial evaluation serves both)
-    const int vc = f - C.u_first;
-    const bool isp = f == C.p_field, isu = vc >= 0 && vc < D;
-    double* const sv = C.sval ? C.sval[w] : nullptr;
-    double* const sg = C.sgrad ? C.sgrad[w] : nullptr;
-    double t[3] = {0.0, 0.0, 0.0};
-    if (C.nq && (isp || isu || sv || sg)) {
-      const int64_t nq = C.nq[i];
-      const double* xq = C.xq[i];
-      const double* nr = C.nrm[i];
-      const double* wq = C.wq[i];
-      for (int64_t q = threadIdx.x; q < nq; q += T) {
-        double x[3] = {0.0, 0.0, 0.0}, n[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          x[a] = xq[a * nq + q];
-          n[a] = nr[a * nq + q];
-        }
-        const int g = C.anchor[C.aoff[i] + q];
-        double val, gr[3];
-        if (g < 0) {
-          val = __longlong_as_double(0x7ff8000000000000LL);
-          gr[0] = gr[1] = gr[2] = val;
-        } else {
-          int ii, jj, kk;
-          unlinear(P.g, P.cell[g], ii, jj, kk);
-          const int ijk[3] = {ii, jj, kk};
-          double rel[3] = {0.0, 0.0, 0.0}, v[8];
-#pragma unroll
-          for (int a = 0; a < D; ++a) rel[a] = x[a] - centre(P.g, a, ijk[a]);
-          corner_values<D>(P, g, F, v);
-          double X[3];
-          stencil_span(P.g, P.code[g], P.cell[g], X);
-          box_eval<D>(rel, X, v, val, gr);
-        }
-        if (sv) sv[q] = val;
-        if (sg)
-#pragma unroll
-          for (int a = 0; a < D; ++a) sg[a * nq + q] = gr[a];
-        const double wt = wq[q];
-        if (isp) {
-#pragma unroll
-          for (int a = 0; a < D; ++a) t[a] += -wt * val * n[a];
-        } else if (isu) {
-          double gn = 0.0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) gn += gr[a] * n[a];
-#pragma unroll
-          for (int a = 0; a < D; ++a) t[a] += C.mu * wt * ((a == vc ? gn : 0.0) + n[vc] * gr[a]);
-        }
-      }
-    }
-    for (int a = 0; a < 3; ++a) red[threadIdx.x][a] = t[a];
-    __syncthreads();
-    for (int s = T / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s)
-        for (int a = 0; a < 3; ++a) red[threadIdx.x][a] += red[threadIdx.x + s][a];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      for (int a = 0; a < 3; ++a) part[(int64_t)w * 3 + a] = red[0][a];
-      __threadfence();
-      const int done = atomicAdd(&counter[i], 1);
-      if (done == C.nf - 1) {
-        __threadfence();
-        double s3[3] = {0.0, 0.0, 0.0};
-        for (int ff = 0; ff < C.nf; ++ff)
-          for (int a = 0; a < 3; ++a)
-            s3[a] += __hip_atomic_load(&part[((int64_t)i * C.nf + ff) * 3 + a], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        for (int a = 0; a < 3; ++a) Fout[(int64_t)i * 3 + a] = s3[a];
-        atomicExch(&counter[i], 0);
-      }
-    }
-    __syncthreads();
+    surface_item<D>(S, C, w, red, part, counter, Fout);
   }
+}
+
+// The levels of an instance swept by G workgroups together.  Workgroup s of
+// the instance takes every G-th block of T (ghost, field) pairs of a level,
+// the fields of a ghost side by side (they share its stencil data), and the
+// G workgroups meet at a device-scope counter after each level and after
+// each level's coupled units.  Every value is computed as by the per-item
+// kernel, from the same inputs.  The grid (instances x G) is at most one
+// workgroup per compute unit, so all of an instance's workgroups become
+// resident while others wait; each wait is bounded as well, so every wave
+// ends.  The instance's workgroups then take its (instance, field) surface
+// items in turn, each computed as by the per-item kernel.  Two sets of
+// counters serve launches in turn: each launch clears the set the next one
+// uses (launches on one batch do not overlap).
+constexpr int kSpinMax = 1 << 22;
+
+__device__ __forceinline__ void inst_barrier(int* bar, int target) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();   // this workgroup's values, before its arrival
+    atomicAdd(bar, 1);
+    for (int k = 0; k < kSpinMax &&
+                    __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target;
+         ++k)
+      __builtin_amdgcn_s_sleep(1);
+    __threadfence();   // the other workgroups' values, after theirs
+  }
+  __syncthreads();
+}
+
+template <int D>
+__global__ __launch_bounds__(1024) void k_batch_split(BStatic S, BCall C, int G,
+                                                      int* __restrict__ bar, int parity,
+                                                      double* __restrict__ part,
+                                                      int* __restrict__ counter,
+                                                      double* __restrict__ Fout) {
+  __shared__ double red[1024][3];
+  __shared__ UnitWS ws[64];
+  const int T = blockDim.x;
+  const int i = (int)blockIdx.x / G, s = (int)blockIdx.x % G;
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < C.ninst; k += T) bar[(parity ^ 1) * C.ninst + k] = 0;
+  int* const cnt = bar + parity * C.ninst + i;
+  const PlanD& P = S.plans[i];
+  const int nf = C.nf;
+  const int32_t* lo_ = S.lev_off[i];
+  const int nl = (C.tile_flag && C.tile_flag[0] == 0) ? 0 : S.nlev[i];
+  int arrivals = 0;
+  for (int l = 0; l < nl; ++l) {
+    const int lo = lo_[l], n = (lo_[l + 1] - lo) * nf;
+    for (int e = s * T + (int)threadIdx.x; e < n; e += G * T) {
+      const int p = lo + e / nf, f = e % nf, w = i * nf + f;
+      fill_single<D>(P, p, C.fields[w], C.bcv[w], C.bct ? C.bct[w] : nullptr, C.kind[f]);
+    }
+    inst_barrier(cnt, G * ++arrivals);
+    if (P.nunits) {
+      if (threadIdx.x < 64)
+        for (int u = s * 64 + (int)threadIdx.x; u < P.nunits; u += G * 64)
+          if (P.unit_lev[u] == l + 1)
+            for (int f = 0; f < nf; ++f) {
+              const int w = i * nf + f;
+              fill_unit_field<D>(P, u, C.fields[w], C.bcv[w], C.bct ? C.bct[w] : nullptr,
+                                 C.kind[f], ws[threadIdx.x]);
+            }
+      inst_barrier(cnt, G * ++arrivals);
+    }
+  }
+  for (int f = s; f < nf; f += G) surface_item<D>(S, C, i * nf + f, red, part, counter, Fout);
 }
 
 // ---------------------------------------------------------------------------
@@ -516,6 +604,8 @@ struct BatchFwdState {
   int32_t** d_levp = nullptr;
   int32_t* d_nlev = nullptr;
   int* d_counter = nullptr;
+  int* d_bar = nullptr;            // [2][ninst] level counters of the split sweep
+  int bar_parity = 0;              // the set the next split launch uses
   double* d_part = nullptr;
   size_t part_cap = 0;
   char* d_call = nullptr;
@@ -598,10 +688,12 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
     nl[i] = b->plans[i]->nlev;
   }
   // one upload from pinned staging: plans | level-offset pointers | level
-  // counts | force counters (zero), each region 256-byte aligned
+  // counts | force counters and two sets of level counters (zero), each
+  // region 256-byte aligned
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t o_lp = al(sizeof(PlanD) * n), o_nl = o_lp + al(sizeof(int32_t*) * n);
-  const size_t o_ct = o_nl + al(sizeof(int32_t) * n), bytes = o_ct + al(sizeof(int) * n);
+  const size_t o_ct = o_nl + al(sizeof(int32_t) * n), o_bar = o_ct + al(sizeof(int) * n);
+  const size_t bytes = o_bar + al(sizeof(int) * 2 * n);
   char* d = static_cast<char*>(pool_alloc(bytes));
   if (d) S->owned.push_back(d);
   S->h_static = static_cast<char*>(pinned_alloc(bytes));
@@ -613,6 +705,7 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   S->d_levp = reinterpret_cast<int32_t**>(d + o_lp);
   S->d_nlev = reinterpret_cast<int32_t*>(d + o_nl);
   S->d_counter = reinterpret_cast<int*>(d + o_ct);
+  S->d_bar = reinterpret_cast<int*>(d + o_bar);
   std::memset(S->h_static, 0, bytes);
   std::memcpy(S->h_static, pv.data(), sizeof(PlanD) * n);
   std::memcpy(S->h_static + o_lp, lp.data(), sizeof(int32_t*) * n);
@@ -713,8 +806,12 @@ extern "C" gcr_status gcr_forward_times(float* out) {
 
 namespace {
 std::atomic<int> g_tiling{1};
+std::atomic<int> g_force_shape{0};   // threads << 8 | (grid & 0xff); 0: tuned
 }  // namespace
 
+void gcr::set_batch_shape(int threads, int grid) {
+  g_force_shape.store(threads ? (threads << 8) | (grid & 0xff) : 0);
+}
 void gcr::set_batch_tiling(int mode) { g_tiling.store(mode < 0 ? 0 : (mode > 2 ? 2 : mode)); }
 int gcr::batch_tiling() { return g_tiling.load(); }
 
@@ -856,7 +953,13 @@ static bool tile_setup(BatchFwdState* S, gcr_batch* b, int dim, hipStream_t st,
   return true;
 }
 
-static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int threads, int grid,
+// Workgroups per instance of the split sweep: the grid stays within one
+// workgroup per compute unit.
+constexpr int kSplitMaxGrid = 256;
+
+// gm > 0: per-item kernel over min(items, 256 gm) workgroups; gm < 0: split
+// sweep with -gm workgroups per instance.
+static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int threads, int gm,
                                double* F, hipStream_t st) {
   BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
   if (C.tile_flag) {
@@ -864,10 +967,25 @@ static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int th
     if (dim == 2) k_tile_fill<2><<<(unsigned)S->tmax, 256, lds, st>>>(bs, C, S->T);
     else k_tile_fill<3><<<(unsigned)S->tmax, 256, lds, st>>>(bs, C, S->T);
   }
-  if (dim == 2)
-    k_batch_forward<2><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
-  else
-    k_batch_forward<3><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+  if (gm < 0) {
+    const int G = -gm;
+    if ((int64_t)G * C.ninst > kSplitMaxGrid || threads > 1024) return GCR_E_ARG;
+    const int par = S->bar_parity;
+    S->bar_parity ^= 1;
+    const unsigned grid = (unsigned)(G * C.ninst);
+    if (dim == 2)
+      k_batch_split<2><<<grid, threads, 0, st>>>(bs, C, G, S->d_bar, par, S->d_part,
+                                                 S->d_counter, F);
+    else
+      k_batch_split<3><<<grid, threads, 0, st>>>(bs, C, G, S->d_bar, par, S->d_part,
+                                                 S->d_counter, F);
+  } else {
+    const int grid = std::min(C.nitems, 256 * gm);
+    if (dim == 2)
+      k_batch_forward<2><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+    else
+      k_batch_forward<3><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+  }
   GCR_HIP(hipGetLastError());
   return GCR_OK;
 }
@@ -1071,15 +1189,18 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     float best = 1e30f;
     int bt_ = 256, bg = 1;
     const int cand_t[3] = {256, 512, 1024};
-    const int cand_g[2] = {1, 4};
+    // per-item grids of 256 and 1024 workgroups; split sweeps with 4 to 128
+    // workgroups per instance (only where levels are swept)
+    const int cand_g[8] = {1, 4, -4, -8, -16, -32, -64, -128};
     for (int tt : cand_t)
       for (int gm : cand_g) {
-        const int grid = std::min(nitems, 256 * gm);
-        if (gm > 1 && grid == std::min(nitems, 256 * (gm / 4))) continue;   // same shape
-        gcr_status s = launch_batch(S, C, dim, tt, grid, Fo, st);
+        if (gm > 1 && std::min(nitems, 256 * gm) == std::min(nitems, 256 * (gm / 4)))
+          continue;   // same shape
+        if (gm < 0 && (S->tiled == 1 || (int64_t)(-gm) * n > kSplitMaxGrid)) continue;
+        gcr_status s = launch_batch(S, C, dim, tt, gm, Fo, st);
         if (s != GCR_OK) return s;
         GCR_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 3; ++r) launch_batch(S, C, dim, tt, grid, Fo, st);
+        for (int r = 0; r < 3; ++r) launch_batch(S, C, dim, tt, gm, Fo, st);
         GCR_HIP(hipEventRecord(e1, st));
         GCR_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1098,8 +1219,12 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
     g_shape[key] = {bt_, bg};
   }
   if (timed) (void)hipEventRecord(ev[1], st);
-  const gcr_status rs =
-      launch_batch(S, C, dim, S->threads, std::min(nitems, 256 * S->grid_mul), Fo, st);
+  int th = S->threads, gm = S->grid_mul;
+  if (const int fs = g_force_shape.load()) {
+    th = fs >> 8;
+    gm = (int)(int8_t)(fs & 0xff);
+  }
+  const gcr_status rs = launch_batch(S, C, dim, th, gm, Fo, st);
   if (!S->ev_done && !(S->ev_done = event_take())) return GCR_E_HIP;
   GCR_HIP(hipEventRecord(S->ev_done, st));
   if (timed) {

@@ -668,6 +668,18 @@ gcr_status gcr_set_batch_tiling(int32_t mode) {
   return GCR_OK;
 }
 
+gcr_status gcr_set_batch_shape(int32_t threads, int32_t grid) {
+  if (threads == 0 && grid == 0) {
+    set_batch_shape(0, 0);
+    return GCR_OK;
+  }
+  if (threads < 64 || threads > 1024 || (threads & (threads - 1)) || grid == 0 || grid > 4 ||
+      grid < -128)
+    return GCR_E_ARG;
+  set_batch_shape(threads, grid);
+  return GCR_OK;
+}
+
 gcr_status gcr_set_wide_layering(int64_t min_interface) {
   if (min_interface < 0) return GCR_E_ARG;
   set_wide_layering(min_interface);

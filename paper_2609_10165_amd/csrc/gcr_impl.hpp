@@ -271,6 +271,7 @@ void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* list,
 // default), 2 from its first (process-wide).
 void set_batch_tiling(int mode);
 int batch_tiling();
+void set_batch_shape(int threads, int grid);
 void* plan_scratch(gcr_plan* p, int slot, size_t bytes);
 void last_build_times(float* ms);
 gcr_status status_from_err(uint32_t err);

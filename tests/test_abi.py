@@ -49,3 +49,20 @@ def test_status_strings_and_argument_errors():
     s, keep = gcr.make_shape(type("S", (), dict(kind=0, center=(0, 0, 0), r0=1.0))())
     assert L.gcr_plan_create(ctypes.byref(g), ctypes.byref(s), 0, None, ctypes.byref(h)) == 1
     assert L.gcr_plan_create(ctypes.byref(g), ctypes.byref(s), 7, None, ctypes.byref(h)) == 1
+
+
+def test_process_wide_settings_validate_their_arguments():
+    """The process-wide switches take no device call and reject values out of
+    their documented ranges (and leave the setting as it was)."""
+    import paper_2609_10165_amd as gcr
+    if not os.path.exists(gcr.LIB_PATH):
+        pytest.skip("libgcr.so not built")
+    L = gcr.lib()
+    for bad in ((100, 1), (32, 1), (2048, 1), (256, 0), (0, 1), (256, 5), (256, -129)):
+        assert L.gcr_set_batch_shape(*bad) == 1, bad
+    for ok in ((0, 0), (64, 1), (1024, 4), (256, -1), (512, -128)):
+        assert L.gcr_set_batch_shape(*ok) == 0, ok
+    assert L.gcr_set_batch_shape(0, 0) == 0
+    assert L.gcr_set_batch_tiling(3) == 1 and L.gcr_set_batch_tiling(-1) == 1
+    assert L.gcr_set_batch_tiling(1) == 0
+    assert L.gcr_set_profiling(4) == 1 and L.gcr_set_profiling(0) == 0

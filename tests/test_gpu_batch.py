@@ -524,3 +524,103 @@ def test_batch_concurrent_builds_on_two_threads(gcr):
     for fg in fwd_got:
         for a, b in zip(fg, want_fwd):
             assert np.array_equal(a, b, equal_nan=True)
+
+
+def _bits(t):
+    return t.contiguous().view(torch.int64)
+
+
+@pytest.mark.parametrize("case", ["spheres", "units", "single"])
+def test_batch_split_sweep_equals_per_item(gcr, case):
+    """The split level sweep (several workgroups per instance meeting at a
+    device-scope counter between levels) against the per-item sweep: the
+    same field values bit for bit, and the same force, surface values and
+    gradients bit for bit at the same workgroup size; over several
+    workgroups per instance, up to the largest grid allowed, with coupled
+    units in the 'units' case.  Each launch shape is run twice in a row, so
+    both sets of level counters are used."""
+    from synth import CGC, CGC_ES
+    if case == "single":
+        inst = synth.sphere256(seed=0)
+        grids, shapes, schemes = [inst.grid], [inst.shape], [HGC]
+        kinds = [f.bc for f in inst.fields]
+        qs = [inst.queries]
+    elif case == "spheres":
+        inst = synth.sphere256(seed=0)
+        grids, shapes, schemes = [inst.grid] * 3, [inst.shape] * 3, [CGC, CGC_ES, HGC]
+        kinds = [f.bc for f in inst.fields]
+        qs = [inst.queries] * 3
+    else:
+        insts = synth.stars64(seed=0, ninst=1, nmin=96, nmax=160) + \
+            synth.stars64(seed=7, ninst=3, nmin=96, nmax=300)
+        grids, shapes = [i.grid for i in insts], [i.shape for i in insts]
+        schemes = [CGC] * len(insts)
+        kinds = [0, 1, 0]
+        qs = [i.queries for i in insts]
+    nf = len(kinds)
+    gcr.set_batch_tiling(0)
+    try:
+        B = gcr.Batch(grids, shapes, schemes)
+        if case == "units":
+            assert any(p.stats()["n_units_coupled"] > 0 for p in B.plans)
+        rng = np.random.default_rng(17)
+        clean, bcv = [], []
+        for g, p in zip(grids, B.plans):
+            ncell = int(np.prod(g.n))
+            for f in range(nf):
+                clean.append(torch.as_tensor(rng.standard_normal(ncell), device="cuda"))
+                bcv.append(torch.as_tensor(rng.standard_normal(p.n_ghost), device="cuda"))
+        nq = [q.x.shape[1] for q in qs]
+        xq, nr, wq = [dev(q.x) for q in qs], [dev(q.n) for q in qs], [dev(q.w) for q in qs]
+
+        def run(threads, grid):
+            gcr.set_batch_shape(threads, grid)   # every call on the batch after the first
+            fields = [c.clone() for c in clean]
+            F = torch.zeros((len(grids), 3), dtype=torch.float64, device="cuda")
+            sv = [torch.empty(n, dtype=torch.float64, device="cuda")
+                  for n in nq for _ in range(nf)]
+            sg = [torch.empty((grids[0].dim, n), dtype=torch.float64, device="cuda")
+                  for n in nq for _ in range(nf)]
+            B.forward(nf, fields, kinds, bcv, nq=nq, xq=xq, nrm=nr, wq=wq, p_field=nf - 1,
+                      u_first=0, mu=0.8, F=F, sval=[s for s in sv], sgrad=[s for s in sg])
+            torch.cuda.synchronize()
+            return fields, F, sv, sg
+
+        maxg = 256 // len(grids)
+        for threads in (1024, 256):
+            ref = run(threads, 1)
+            for G in sorted({2, 4, 16, min(32, maxg), min(128, maxg)}):
+                for _ in range(2):
+                    got = run(threads, -G)
+                    for a, b in zip(got[0], ref[0]):
+                        assert torch.equal(_bits(a), _bits(b)), (threads, G, "field")
+                    assert torch.equal(_bits(got[1]), _bits(ref[1])), (threads, G, "force")
+                    for a, b in zip(got[2] + got[3], ref[2] + ref[3]):
+                        assert torch.equal(_bits(a), _bits(b)), (threads, G, "surface")
+    finally:
+        gcr.set_batch_shape(0, 0)
+        gcr.set_batch_tiling(1)
+
+
+def test_batch_split_sweep_refuses_oversized_grid(gcr):
+    """A forced split shape whose grid would exceed one workgroup per compute
+    unit is refused before any launch; bad shapes are refused at once."""
+    insts = synth.stars64(seed=12, ninst=20, nmin=96, nmax=128)
+    gcr.set_batch_tiling(0)
+    try:
+        B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
+        fields = [torch.zeros(int(np.prod(i.grid.n)), dtype=torch.float64, device="cuda")
+                  for i in insts]
+        bcv = [torch.zeros(p.n_ghost, dtype=torch.float64, device="cuda") for p in B.plans]
+        gcr.set_batch_shape(256, -16)   # 20 x 16 = 320 workgroups
+        with pytest.raises(gcr.GcrError):
+            B.forward(1, fields, [0], bcv)
+        gcr.set_batch_shape(256, -8)    # 160: allowed
+        B.forward(1, fields, [0], bcv)
+        torch.cuda.synchronize()
+        for bad in ((100, 1), (256, 0), (256, 5), (256, -129), (2048, 1)):
+            with pytest.raises(gcr.GcrError):
+                gcr.set_batch_shape(*bad)
+    finally:
+        gcr.set_batch_shape(0, 0)
+        gcr.set_batch_tiling(1)
