@@ -80,9 +80,11 @@ __device__ __forceinline__ bool cell_solid(const GridD& g, const ShapeD& s, int 
 // lies wholly on one side of the boundary (0 fluid, 1 solid, -1 undecided).
 __global__ __launch_bounds__(256) void k_spans(const Inst* __restrict__ insts, int ninst,
                                                const int64_t* __restrict__ chunk_start,
-                                               int64_t nspan, int8_t* __restrict__ span) {
+                                               int64_t nspan, int8_t* __restrict__ span,
+                                               int32_t* __restrict__ nband) {
   constexpr int kSpan = 64 * kSeg, kPer = kChunk / kSpan;
   const int64_t sp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sp == 0) nband[0] = 0;   // the band list k_classify appends to starts empty
   if (sp >= nspan) return;
   const int64_t chunk = sp / kPer;
   const int ii = find_inst(chunk_start, ninst, chunk);
@@ -391,17 +393,12 @@ __global__ __launch_bounds__(64) void k_band(const Inst* __restrict__ insts, int
 }
 
 
-__global__ void k_zero_one(int32_t* __restrict__ a) {
-  if (threadIdx.x == 0) a[0] = 0;
-}
-
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
                      int8_t* span, int8_t* tags, int32_t* chunk_cnt, int32_t* band,
                      int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store, hipStream_t st) {
   const int64_t nspan = chunks * (kChunk / (64 * kSeg));
   k_spans<<<(unsigned)((nspan + 255) / 256), 256, 0, st>>>(insts, ninst, chunk_start, nspan,
-                                                           span);
-  k_zero_one<<<1, 64, 0, st>>>(nband);
+                                                           span, nband);
   if (ev_prepass) (void)hipEventRecord(ev_prepass, st);
   k_classify<<<(unsigned)chunks, 256, 0, st>>>(insts, ninst, chunk_start, span, tags, chunk_cnt,
                                                 band, nband);

@@ -550,7 +550,13 @@ __global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ 
                                                        const int32_t* __restrict__ chunk_cnt,
                                                        const int64_t* __restrict__ chunk_excl,
                                                        const int32_t* __restrict__ chunk_list,
-                                                       int32_t* __restrict__ if_cell) {
+                                                       int32_t* __restrict__ if_cell,
+                                                       unsigned long long* __restrict__ htab,
+                                                       int64_t nhash) {
+  // the cell -> ghost tables, emptied here for k_hash_build
+  for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < nhash;
+       z += (int64_t)gridDim.x * blockDim.x)
+    htab[z] = ~0ull;
   const int64_t chunk = chunk_list[blockIdx.x];   // chunks holding listed cells
   __shared__ int64_t sh[5];
   const int ii = find_inst(chunk_start, ninst, chunk);
@@ -807,11 +813,6 @@ __global__ __launch_bounds__(256) void k_rfill(const Inst* __restrict__ insts,
   }
 }
 
-__global__ void k_zero32(int32_t* __restrict__ a, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = 0;
-}
-
 // --------------------------------------------------------------------------
 // 6. canonical arrays
 // --------------------------------------------------------------------------
@@ -994,8 +995,11 @@ __global__ void k_hash_build(const int64_t* __restrict__ g_off, int ninst,
                              const int32_t* __restrict__ cell,
                              const int64_t* __restrict__ hoff,
                              const uint32_t* __restrict__ hmask,
-                             unsigned long long* __restrict__ htab) {
+                             unsigned long long* __restrict__ htab,
+                             int32_t* __restrict__ zero, int64_t nzero) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the dependency counters that the next launch fills, cleared here
+  for (int64_t z = e; z < nzero; z += (int64_t)gridDim.x * blockDim.x) zero[z] = 0;
   if (e >= g_off[ninst]) return;
   const int ii = find_inst(g_off, ninst, e);
   const int c = cell[e];
@@ -1395,7 +1399,6 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   std::memcpy(PS.p + o_hm, D.hmask.data(), 4 * ninst);
   GCR_HIP(hipMemcpyAsync(tb + o_ho, PS.p + o_ho, stage_bytes - o_ho, hipMemcpyHostToDevice,
                          st));   // R3
-  k_hash_clear<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_htab, D.hoff[ninst]);
   const int64_t nblk = (nif + 1023) / 1024;
   D.d_if_cell = own<int32_t>(D, cap);
   D.d_if_psi = own<double>(D, cap);
@@ -1440,7 +1443,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   if (nif > 0) {
     k_compact_iface<<<(unsigned)nlist, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
                                                      D.d_chunk_cnt, D.d_chunk_excl, D.d_chunk_list,
-                                                     D.d_if_cell);
+                                                     D.d_if_cell, D.d_htab, D.hoff[ninst]);
     T.mark(4, st);
     k_geometry<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_if_off, D.d_if_cell,
                                                   D.d_tags, D.d_if_psi, D.d_if_n, cap,
@@ -1456,8 +1459,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
     T.mark(6, st);
     // ghost count unknown on the host: launch over the interface capacity
     k_hash_build<<<blocks(nif, 256), 256, 0, st>>>(D.d_g_off, ninst, D.d_g_cell, D.d_hoff,
-                                                    D.d_hmask, D.d_htab);
-    k_zero32<<<blocks(2 * cap, 256), 256, 0, st>>>(D.d_rcnt, 2 * cap);   // rcnt + rfill
+                                                    D.d_hmask, D.d_htab, D.d_rcnt,
+                                                    2 * cap);   // + rcnt, rfill cleared
     k_deps<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, ninst, D.d_g_off, D.d_g_cell, D.d_g_psi,
                                               D.d_g_n, cap, D.d_g_ext, D.d_tags, D.d_htab, D.d_hoff,
                                               D.d_hmask, D.d_g_code, D.d_deps,
@@ -1517,6 +1520,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
                                                               D.d_htab);
     T.mark(9, st);
   } else {
+    k_hash_clear<<<blocks(D.hoff[ninst], 256), 256, 0, st>>>(D.d_htab, D.hoff[ninst]);
     for (int i = 4; i <= 9; ++i) T.mark(i, st);
     GCR_HIP(hipMemsetAsync(D.d_g_off, 0, sizeof(int64_t) * (ninst + 1), st));
     GCR_HIP(hipMemsetAsync(D.d_lev_off, 0, sizeof(int32_t) * ninst * (kMaxLevels + 1), st));
