@@ -122,7 +122,7 @@ def kernel_traffic(name, workload):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: measures one GPU; --gpus must be 1 (the multi-GPU layout is a design, not code)", file=sys.stderr)
         sys.exit(2)
     import torch
 
