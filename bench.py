@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--build-threads", type=int, default=3, choices=(1, 2, 3),
+    ap.add_argument("--build-threads", type=int, default=2, choices=(1, 2, 3),
                     help="host threads building batches in the timed steps (each on "
                          "a stream of its own; the forwards are enqueued by another)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -419,6 +419,19 @@ def main():
             pk["graph"] = None
     run_pipelined(4)
     torch.cuda.synchronize()
+    # grow the library's device and pinned pools to the deepest pipeline
+    # (up to three batches building, two queued, one being enqueued and
+    # three held until their forwards end): as many batches built and
+    # forwarded at once, then released, so no timed step meets an empty
+    # pool (a hipMalloc there stalls the whole pipeline)
+    with torch.cuda.stream(s_build):
+        pool_fill = [gcr.Batch([grid] * len(SCHEMES), [shape] * len(SCHEMES), list(SCHEMES),
+                               stream=s_build) for _ in range(12)]
+        pk0 = buffers_k(0, tuple(p.n_ghost for p in pool_fill[0].plans))
+        for Bp in pool_fill:
+            Bp.forward(args=pk0["args"], stream=s_build)
+    torch.cuda.synchronize()
+    del pool_fill, Bp
     # the warm-ups have grown the device-memory pools to the pipelines'
     # depth; objects made so far are frozen out of the cycle collector's
     # scans (a full scan of torch's objects costs milliseconds), as a
