@@ -88,6 +88,9 @@ def lib():
         L.orc_surface_query_adjoint.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int,
                                                 vp, vp, vp]
         L.orc_fill_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.orc_surface_query_adjoint_scale.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int,
+                                                      vp, vp, vp]
+        L.orc_fill_adjoint_scale.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.orc_shape_project.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, vp,
                                         ctypes.c_int, vp, vp, vp]
         L.orc_shape_inside.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, vp]
@@ -259,7 +262,9 @@ class OraclePlan:
         nf = f.shape[0]
         bt = self._bc(bc_type, nf, self.n_ghost)
         bv = np.ascontiguousarray(np.asarray(bc_val, dtype=np.float64).reshape(nf, self.n_ghost))
-        lib().orc_fill(self._h, nf, _vp(f), _vp(bt), _vp(bv))
+        st = lib().orc_fill(self._h, nf, _vp(f), _vp(bt), _vp(bv))
+        if st:
+            raise OracleError(st, "orc_fill")
         return f
 
     def fill_jacobi(self, fields, bc_type, bc_val, max_sweeps=1000):
@@ -276,7 +281,9 @@ class OraclePlan:
         bt = self._bc(bc_type, nf, self.n_ghost)
         bv = np.ascontiguousarray(np.asarray(bc_val, dtype=np.float64).reshape(nf, self.n_ghost))
         sc = np.zeros((nf, self.n_ghost))
-        lib().orc_fill_scale(self._h, nf, _vp(f), _vp(bt), _vp(bv), _vp(sc))
+        st = lib().orc_fill_scale(self._h, nf, _vp(f), _vp(bt), _vp(bv), _vp(sc))
+        if st:
+            raise OracleError(st, "orc_fill_scale")
         return sc
 
     def cell_scale(self, fields, ghost_scale):
@@ -341,5 +348,35 @@ class OraclePlan:
         nf = lam.shape[0]
         bt = self._bc(bc_type, nf, self.n_ghost)
         lam_bc = np.zeros((nf, self.n_ghost))
-        lib().orc_fill_adjoint(self._h, nf, _vp(lam), _vp(bt), _vp(lam_bc))
+        st = lib().orc_fill_adjoint(self._h, nf, _vp(lam), _vp(bt), _vp(lam_bc))
+        if st:
+            raise OracleError(st, "orc_fill_adjoint")
+        return lam, lam_bc
+
+    def surface_query_adjoint_scale(self, xq, gval, ggrad, lam_scale):
+        """Adds, per cell, the magnitudes of the terms that
+        surface_query_adjoint would add there (the scale of its rounding)."""
+        xq = np.ascontiguousarray(np.asarray(xq, dtype=np.float64).reshape(self.dim, -1))
+        nq = xq.shape[1]
+        lam_scale = np.ascontiguousarray(lam_scale, dtype=np.float64)
+        nf = lam_scale.reshape(-1, self.n_cells).shape[0]
+        gv = None if gval is None else np.ascontiguousarray(np.asarray(gval, np.float64).reshape(nf, nq))
+        gg = None if ggrad is None else np.ascontiguousarray(
+            np.asarray(ggrad, np.float64).reshape(nf, self.dim, nq))
+        st = lib().orc_surface_query_adjoint_scale(self._h, nq, _vp(xq), nf, _vp(gv), _vp(gg),
+                                                   _vp(lam_scale))
+        if st:
+            raise OracleError(st, "orc_surface_query_adjoint_scale")
+        return lam_scale
+
+    def fill_adjoint_scale(self, lam_scale, bc_type):
+        """Scale of every output of fill_adjoint given the scale of its input
+        (the reverse sweep on magnitudes; units by |A^-T|)."""
+        lam = np.ascontiguousarray(np.array(lam_scale, dtype=np.float64).reshape(-1, self.n_cells))
+        nf = lam.shape[0]
+        bt = self._bc(bc_type, nf, self.n_ghost)
+        lam_bc = np.zeros((nf, self.n_ghost))
+        st = lib().orc_fill_adjoint_scale(self._h, nf, _vp(lam), _vp(bt), _vp(lam_bc))
+        if st:
+            raise OracleError(st, "orc_fill_adjoint_scale")
         return lam, lam_bc

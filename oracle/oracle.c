@@ -58,7 +58,6 @@ struct orc_plan {
   double* faces[3];     /* owned copies of a stretched grid's faces */
 };
 
-#define ORC_MAX_BLOCK 8
 
 /* ------------------------------------------------------------------------- */
 /* grid helpers                                                              */
@@ -951,10 +950,8 @@ int orc_plan_create(const orc_grid* g, const orc_shape* s, int scheme,
     free(tidx); free(tlow); free(stk); free(cs); free(cit); free(onst);
     int64_t* csize = (int64_t*)calloc(ncomp ? ncomp : 1, sizeof(int64_t));
     for (int64_t j = 0; j < ng; ++j) csize[comp[j]]++;
-    for (int64_t u = 0; u < ncomp; ++u) {
+    for (int64_t u = 0; u < ncomp; ++u)
       if (csize[u] > 1) { p->nblk++; if (csize[u] > p->maxblk) p->maxblk = (int32_t)csize[u]; }
-      if (csize[u] > ORC_MAX_BLOCK) status = ORC_E_CYCLE;
-    }
     free(csize);
     if (status == ORC_OK) {
       /* Kahn on the condensed graph */
@@ -1234,6 +1231,10 @@ static int gauss(int k, double* A, double* b) {
   return ORC_OK;
 }
 
+static int32_t unit_size(const orc_plan* p, int32_t u) {
+  return p->blk_off[u + 1] - p->blk_off[u];
+}
+
 /* Coupled unit u: matrix A = I - (weights among members), and for member i
  * the external part rhs_i = sum_ext w f + w_s b (or its absolute-value
  * bound when `absval`, with f holding scales).  f == NULL: matrix only. */
@@ -1277,11 +1278,16 @@ int orc_fill(const orc_plan* p, int nf, double* fields, const int8_t* bc_type,
       if (u < 0) {
         F[p->cell[g]] = ghost_value(p, g, F, bt[g], bv[g]);
       } else if (g == p->blk_mem[p->blk_off[u]]) {
-        double A[ORC_MAX_BLOCK * ORC_MAX_BLOCK], x[ORC_MAX_BLOCK];
-        int k = unit_system(p, u, F, bt, bv, A, x, 0, NULL);
+        const int32_t k = unit_size(p, u);
+        double* A = (double*)malloc(sizeof(double) * k * (k + 1));
+        if (!A) return ORC_E_NOMEM;
+        double* x = A + (int64_t)k * k;
+        unit_system(p, u, F, bt, bv, A, x, 0, NULL);
         int st = gauss(k, A, x);
+        if (st == ORC_OK)
+          for (int i = 0; i < k; ++i) F[p->cell[p->blk_mem[p->blk_off[u] + i]]] = x[i];
+        free(A);
         if (st != ORC_OK) return st;
-        for (int i = 0; i < k; ++i) F[p->cell[p->blk_mem[p->blk_off[u] + i]]] = x[i];
       }
     }
   }
@@ -1320,6 +1326,23 @@ int orc_fill_jacobi(const orc_plan* p, int nf, double* fields,
   return result;
 }
 
+/* |A^-1| of coupled unit u (A from unit_system), row major k x k, column
+ * by column from solves against unit vectors; NULL if out of memory. */
+static double* unit_abs_inverse(const orc_plan* p, int32_t u, const int8_t* bct) {
+  const int32_t k = unit_size(p, u);
+  double* out = (double*)malloc(sizeof(double) * (2 * k * k + k));
+  if (!out) return NULL;
+  double* A = out + (int64_t)k * k;
+  double* e = A + (int64_t)k * k;
+  for (int t = 0; t < k; ++t) {
+    unit_system(p, u, NULL, bct, NULL, A, e, 0, NULL);   /* gauss overwrites A */
+    for (int q = 0; q < k; ++q) e[q] = (q == t) ? 1.0 : 0.0;
+    gauss(k, A, e);
+    for (int i = 0; i < k; ++i) out[i * k + t] = fabs(e[i]);
+  }
+  return out;
+}
+
 int orc_fill_scale(const orc_plan* p, int nf, const double* fields,
                    const int8_t* bc_type, const double* bc_val, double* scale) {
   /* s_G = sum_k |w_k| s_{P_k} + |w_s b_G|, s = |phi| on non-ghost cells;
@@ -1334,19 +1357,18 @@ int orc_fill_scale(const orc_plan* p, int nf, const double* fields,
       int32_t u = p->blk[g];
       if (u >= 0) {
         if (g != p->blk_mem[p->blk_off[u]]) continue;
-        double A[ORC_MAX_BLOCK * ORC_MAX_BLOCK], r[ORC_MAX_BLOCK];
-        int k = unit_system(p, u, F, bt, bv, A, r, 1, sc);
+        const int32_t k = unit_size(p, u);
+        double* inv = unit_abs_inverse(p, u, bt);
+        double* A = (double*)malloc(sizeof(double) * k * (k + 1));
+        if (!inv || !A) { free(inv); free(A); return ORC_E_NOMEM; }
+        double* r = A + (int64_t)k * k;
+        unit_system(p, u, F, bt, bv, A, r, 1, sc);
         for (int i = 0; i < k; ++i) {
           double acc = 0.0;
-          for (int t = 0; t < k; ++t) {
-            double B[ORC_MAX_BLOCK * ORC_MAX_BLOCK], e[ORC_MAX_BLOCK];
-            memcpy(B, A, sizeof(double) * k * k);
-            for (int q = 0; q < k; ++q) e[q] = (q == t) ? 1.0 : 0.0;
-            gauss(k, B, e);
-            acc += fabs(e[i]) * r[t];
-          }
+          for (int t = 0; t < k; ++t) acc += inv[i * k + t] * r[t];
           sc[p->blk_mem[p->blk_off[u] + i]] = acc;
         }
+        free(inv); free(A);
         continue;
       }
       double w[7], ws;
@@ -1555,9 +1577,12 @@ int orc_forces(const orc_plan* p, int64_t nq, const double* xq,
 /* adjoints: explicit transposes of the linear maps above                    */
 /* ------------------------------------------------------------------------- */
 
-int orc_surface_query_adjoint(const orc_plan* p, int64_t nq, const double* xq,
-                              int nf, const double* gval, const double* ggrad,
-                              double* lam) {
+/* lam[c] += sum_q (L_c(x_q) gval_q + grad L_c(x_q) . ggrad_q) over the
+ * corners c of each query's anchor box; with absval, the magnitude of every
+ * term is added instead (the scale of the sum). */
+static int surface_adjoint(const orc_plan* p, int64_t nq, const double* xq,
+                           int nf, const double* gval, const double* ggrad,
+                           double* lam, int absval) {
   int dim = p->dim, nc = 1 << dim;
   for (int64_t q = 0; q < nq; ++q) {
     double x[3] = {0, 0, 0};
@@ -1583,14 +1608,35 @@ int orc_surface_query_adjoint(const orc_plan* p, int64_t nq, const double* xq,
       unit[c] = 1.0;
       eval_poly(p, g, unit, rel, &uv, ug);
       for (int f = 0; f < nf; ++f) {
-        double a = gval ? uv * gval[(int64_t)f * nq + q] : 0.0;
-        if (ggrad)
-          for (int i = 0; i < dim; ++i) a += ug[i] * ggrad[((int64_t)f * dim + i) * nq + q];
+        double a;
+        if (!absval) {
+          a = gval ? uv * gval[(int64_t)f * nq + q] : 0.0;
+          if (ggrad)
+            for (int i = 0; i < dim; ++i) a += ug[i] * ggrad[((int64_t)f * dim + i) * nq + q];
+        } else {
+          a = gval ? fabs(uv * gval[(int64_t)f * nq + q]) : 0.0;
+          if (ggrad)
+            for (int i = 0; i < dim; ++i)
+              a += fabs(ug[i] * ggrad[((int64_t)f * dim + i) * nq + q]);
+        }
         lam[(int64_t)f * p->ncell + cc[c]] += a;
       }
     }
   }
   return ORC_OK;
+}
+
+int orc_surface_query_adjoint(const orc_plan* p, int64_t nq, const double* xq,
+                              int nf, const double* gval, const double* ggrad,
+                              double* lam) {
+  return surface_adjoint(p, nq, xq, nf, gval, ggrad, lam, 0);
+}
+
+int orc_surface_query_adjoint_scale(const orc_plan* p, int64_t nq,
+                                    const double* xq, int nf,
+                                    const double* gval, const double* ggrad,
+                                    double* lam_scale) {
+  return surface_adjoint(p, nq, xq, nf, gval, ggrad, lam_scale, 1);
 }
 
 int orc_fill_adjoint(const orc_plan* p, int nf, double* lam,
@@ -1619,16 +1665,19 @@ int orc_fill_adjoint(const orc_plan* p, int nf, double* lam,
         continue;
       }
       if (g != p->blk_mem[p->blk_off[u + 1] - 1]) continue;
-      int32_t k = p->blk_off[u + 1] - p->blk_off[u];
+      const int32_t k = unit_size(p, u);
       const int64_t* m = p->blk_mem + p->blk_off[u];
-      double A[ORC_MAX_BLOCK * ORC_MAX_BLOCK], AT[ORC_MAX_BLOCK * ORC_MAX_BLOCK], mu[ORC_MAX_BLOCK];
-      double dummy[ORC_MAX_BLOCK];
+      double* A = (double*)malloc(sizeof(double) * (2 * k * k + 2 * k));
+      if (!A) return ORC_E_NOMEM;
+      double* AT = A + (int64_t)k * k;
+      double* mu = AT + (int64_t)k * k;
+      double* dummy = mu + k;
       unit_system(p, u, NULL, bt, NULL, A, dummy, 0, NULL);   /* matrix only */
       for (int i = 0; i < k; ++i)
         for (int t = 0; t < k; ++t) AT[i * k + t] = A[t * k + i];
       for (int i = 0; i < k; ++i) mu[i] = L[p->cell[m[i]]];
       int st = gauss(k, AT, mu);
-      if (st != ORC_OK) return st;
+      if (st != ORC_OK) { free(A); return st; }
       for (int i = 0; i < k; ++i) L[p->cell[m[i]]] = 0.0;
       for (int i = 0; i < k; ++i) {
         double w[7], ws;
@@ -1642,6 +1691,63 @@ int orc_fill_adjoint(const orc_plan* p, int nf, double* lam,
           if (!internal) L[c] += w[j] * mu[i];
         }
       }
+      free(A);
+    }
+  }
+  return ORC_OK;
+}
+
+int orc_fill_adjoint_scale(const orc_plan* p, int nf, double* lam_scale,
+                           const int8_t* bc_type, double* lam_bc_scale) {
+  /* The reverse sweep of orc_fill_adjoint with every weight replaced by its
+   * magnitude and the unit solves by |A^-T|: each output receives the sum
+   * of the magnitudes of the terms that make it up, the scale of its
+   * rounding error.  Ghost slots end at zero, as the adjoint's do. */
+  int64_t ng = p->ng;
+  for (int f = 0; f < nf; ++f) {
+    double* L = lam_scale + (int64_t)f * p->ncell;
+    const int8_t* bt = bc_type + (int64_t)f * ng;
+    double* lb = lam_bc_scale + (int64_t)f * ng;
+    for (int64_t g = ng - 1; g >= 0; --g) {
+      int32_t u = p->blk[g];
+      if (u < 0) {
+        double w[7], ws;
+        orc_weights(p, g, bt[g], w, &ws);
+        double Lg = L[p->cell[g]];
+        lb[g] = fabs(ws) * Lg;
+        L[p->cell[g]] = 0.0;
+        for (int j = 0; j < npts(p->dim); ++j) {
+          int64_t c = p->sten[7 * g + j];
+          if (c >= 0) L[c] += fabs(w[j]) * Lg;
+        }
+        continue;
+      }
+      if (g != p->blk_mem[p->blk_off[u + 1] - 1]) continue;
+      const int32_t k = unit_size(p, u);
+      const int64_t* m = p->blk_mem + p->blk_off[u];
+      double* inv = unit_abs_inverse(p, u, bt);
+      double* mu = (double*)malloc(sizeof(double) * k);
+      if (!inv || !mu) { free(inv); free(mu); return ORC_E_NOMEM; }
+      /* |A^-T| s: entry i sums |(A^-1)_{t i}| s_t */
+      for (int i = 0; i < k; ++i) {
+        double acc = 0.0;
+        for (int t = 0; t < k; ++t) acc += inv[t * k + i] * L[p->cell[m[t]]];
+        mu[i] = acc;
+      }
+      for (int i = 0; i < k; ++i) L[p->cell[m[i]]] = 0.0;
+      for (int i = 0; i < k; ++i) {
+        double w[7], ws;
+        orc_weights(p, m[i], bt[m[i]], w, &ws);
+        lb[m[i]] = fabs(ws) * mu[i];
+        for (int j = 0; j < npts(p->dim); ++j) {
+          int64_t c = p->sten[7 * m[i] + j];
+          if (c < 0) continue;
+          int internal = 0;
+          for (int q = 0; q < k; ++q) if (p->cell[m[q]] == c) internal = 1;
+          if (!internal) L[c] += fabs(w[j]) * mu[i];
+        }
+      }
+      free(inv); free(mu);
     }
   }
   return ORC_OK;

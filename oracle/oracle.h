@@ -118,7 +118,9 @@ int orc_fill(const orc_plan* p, int nf, double* fields, const int8_t* bc_type,
 int orc_fill_jacobi(const orc_plan* p, int nf, double* fields,
                     const int8_t* bc_type, const double* bc_val,
                     int max_sweeps);
-/* Condition-aware scale of every filled ghost value: [nf][N_g]. */
+/* Condition-aware scale of every filled ghost value: [nf][N_g].  s_G sums
+ * |w_k| s_{P_k} over the stencil (s = |phi| on non-ghost cells) and
+ * |w_s b_G|; a coupled unit takes |A^-1| times its external sums. */
 int orc_fill_scale(const orc_plan* p, int nf, const double* fields,
                    const int8_t* bc_type, const double* bc_val, double* scale);
 
@@ -144,9 +146,22 @@ int orc_surface_query_adjoint(const orc_plan* p, int64_t nq, const double* xq,
                               int nf, const double* gval, const double* ggrad,
                               double* lam);
 /* lam in: dJ/d(filled field); out: dJ/d(input field) (ghost slots zeroed).
- * lam_bc out: [nf][N_g]. */
+ * lam_bc out: [nf][N_g].  Coupled units of any size are solved densely. */
 int orc_fill_adjoint(const orc_plan* p, int nf, double* lam,
                      const int8_t* bc_type, double* lam_bc);
+
+/* Condition-aware scales of the adjoints, for tolerances: the same sweeps
+ * with every coefficient replaced by its magnitude (a unit's solve by
+ * |A^-T|), so each output receives the sum of the magnitudes of the terms
+ * that make it up.  surface: adds into lam_scale [nf][N_cells] from the
+ * magnitudes of gval, ggrad; fill: lam_scale in = scale of dJ/d(filled),
+ * out = scale of dJ/d(input) (ghost slots zero); lam_bc_scale [nf][N_g]. */
+int orc_surface_query_adjoint_scale(const orc_plan* p, int64_t nq,
+                                    const double* xq, int nf,
+                                    const double* gval, const double* ggrad,
+                                    double* lam_scale);
+int orc_fill_adjoint_scale(const orc_plan* p, int nf, double* lam_scale,
+                           const int8_t* bc_type, double* lam_bc_scale);
 
 /* Geometry helpers exposed for pins. */
 int orc_shape_project(const orc_shape* s, int dim, const double* x, int solid,
