@@ -48,7 +48,7 @@ typedef enum {
   GCR_E_ARG = 1,         /* invalid argument (null, size, range, dimension) */
   GCR_E_HIP = 2,         /* a HIP runtime call failed */
   GCR_E_NOMEM = 3,       /* device or host allocation failed */
-  GCR_E_CYCLE = 4,       /* a coupled unit of the ghost graph is too large */
+  GCR_E_CYCLE = 4,       /* the ghost graph could not be layered (internal) */
   GCR_E_STENCIL = 5,     /* a stencil point leaves the grid or is a solid cell;
                             or a query point has no ghost within 2 cells */
   GCR_E_DEGENERATE = 6,  /* zero denominator in a relation */
@@ -136,9 +136,11 @@ typedef struct {
  * multipliers (Eq. stencil_anisotropic for CGC_ES), the ghost dependency
  * graph and its Kahn levels (Sec. 3.2).  Where the graph is not acyclic
  * (concave bodies), each strongly connected group of ghosts forms one unit
- * whose relations are solved together; units have at most 8 ghosts, else
- * GCR_E_CYCLE.  grid, shape: host.  Synchronises `stream` twice.  The plan owns
- * all its device memory; *out is NULL on error. */
+ * whose relations are solved together.  The library solves units of up to
+ * 8 ghosts (at most 1024 units and 1024 ghosts in cycles per instance) and
+ * reports larger ones as GCR_E_UNSUPPORTED, a capacity limit.  grid,
+ * shape: host.  Synchronises `stream` twice.  The plan owns all its device
+ * memory; *out is NULL on error. */
 gcr_status gcr_plan_create(const gcr_grid* grid, const gcr_shape* shape,
                            int32_t scheme, void* stream, gcr_plan** out);
 /* (scheme: a gcr_scheme, optionally | GCR_LAYER2; gcr_stats.n_interface

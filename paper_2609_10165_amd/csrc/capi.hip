@@ -443,7 +443,7 @@ const char* gcr_status_str(gcr_status s) {
     case GCR_E_ARG: return "invalid argument";
     case GCR_E_HIP: return "HIP runtime error";
     case GCR_E_NOMEM: return "out of memory";
-    case GCR_E_CYCLE: return "coupled ghost group too large";
+    case GCR_E_CYCLE: return "ghost graph could not be layered";
     case GCR_E_STENCIL: return "stencil leaves the grid or reaches a solid cell";
     case GCR_E_DEGENERATE: return "degenerate relation (zero denominator)";
     case GCR_E_GEOMETRY: return "closest-point projection failed";

@@ -436,8 +436,8 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
       if (left && m + pre < kMaxResidual) res[m + pre] = g;
       m += (int)tot;
     }
-    if (m > kMaxResidual) {
-      err |= kErrCycle;
+    if (m > kMaxResidual) {   // workspace capacity, not a property of the graph
+      err |= kErrUnsupported;
       break;
     }
     const int RW = (m + 31) / 32;
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
     }
     __syncthreads();
     if (s_units > kMaxUnits) {
-      err |= kErrCycle;
+      err |= kErrUnsupported;
       break;
     }
     for (int u = tid; u < m; u += 1024) {
@@ -517,8 +517,8 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
           if (v < u) ++rank;
           ++size;
         }
-      if (size > kMaxUnit) {
-        atomicOr(&L.info[ii].err, kErrCycle);
+      if (size > kMaxUnit) {   // larger than the LDS solve's workspace
+        atomicOr(&L.info[ii].err, kErrUnsupported);
         continue;
       }
       const int sl = slot[rp];
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
       }
     }
     __syncthreads();
-    if (L.info[ii].err & kErrCycle) break;
+    if (L.info[ii].err & kErrUnsupported) break;
     units = true;   // restart the layering with the units as nodes
   }
   if (tid == 0) {
