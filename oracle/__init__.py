@@ -76,6 +76,8 @@ def lib():
         L.orc_units.argtypes = [vp, vp, vp, vp]
         L.orc_weights.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp, vp]
         L.orc_weights_raw.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_weight_bounds.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp, vp]
+        L.orc_weight_bounds_raw.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_fill.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.orc_fresh_cells.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64]
         L.orc_fill_jacobi.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
@@ -172,6 +174,17 @@ def weights_raw(dim, bc, x2, xs, n):
     return w[: (3 if dim == 2 else 7)], float(ws[0])
 
 
+def weight_bounds_raw(dim, bc, x2, xs, n):
+    """Tolerance bounds of the closed-form weights (magnitude plus
+    sensitivity to the foot point and the normal)."""
+    a = [np.ascontiguousarray(np.r_[np.asarray(v, dtype=np.float64), np.zeros(3 - len(v))])
+         for v in (x2, xs, n)]
+    w = np.zeros(7)
+    ws = np.zeros(1)
+    lib().orc_weight_bounds_raw(int(dim), int(bc), *[_vp(v) for v in a], _vp(w), _vp(ws))
+    return w[: (3 if dim == 2 else 7)], float(ws[0])
+
+
 def sh_basis(l, m, v):
     v = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
     return lib().orc_sh_basis(l, m, _vp(v))
@@ -236,6 +249,12 @@ class OraclePlan:
         w = np.zeros(7)
         ws = np.zeros(1)
         lib().orc_weights(self._h, int(g), int(bc), _vp(w), _vp(ws))
+        return w[: (3 if self.dim == 2 else 7)], float(ws[0])
+
+    def weight_bounds(self, g, bc):
+        w = np.zeros(7)
+        ws = np.zeros(1)
+        lib().orc_weight_bounds(self._h, int(g), int(bc), _vp(w), _vp(ws))
         return w[: (3 if self.dim == 2 else 7)], float(ws[0])
 
     @staticmethod

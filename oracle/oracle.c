@@ -1193,6 +1193,50 @@ int orc_weights(const orc_plan* p, int64_t g, int bc, double* w, double* ws) {
   return orc_weights_raw(p->dim, bc, x2, xs, n, w, ws);
 }
 
+/* Sensitivity bounds of the weights, for tolerances: wb[k] = |w_k| + sum_i
+ * (|x2_i| |dw_k/dxs_i| + |dw_k/dn_i|), wsb likewise for w_s.  Each side of a
+ * parity comparison computes the foot point and normal by its own
+ * projection (Newton's method for star, spherical-harmonic and airfoil
+ * bodies), so x_s and n agree to a small fraction of a cell and of a unit,
+ * not bit for bit; a weight's scale is then how far it moves under a
+ * perturbation of x_s on the scale of the stencil span and of n on the scale
+ * of a unit vector.  Derivatives by central differences of the closed forms
+ * with relative steps 1e-7 (their truncation error is far below what a
+ * tolerance needs). */
+int orc_weight_bounds_raw(int dim, int bc, const double* x2, const double* xs,
+                          const double* n, double* wb, double* wsb) {
+  const int np = npts(dim);
+  double w[7], ws;
+  orc_weights_raw(dim, bc, x2, xs, n, w, &ws);
+  for (int k = 0; k < np; ++k) wb[k] = fabs(w[k]);
+  *wsb = fabs(ws);
+  for (int which = 0; which < 2; ++which) {
+    for (int i = 0; i < dim; ++i) {
+      double a[3] = {xs[0], xs[1], dim == 3 ? xs[2] : 0.0};
+      double b[3] = {n[0], n[1], dim == 3 ? n[2] : 0.0};
+      double* v = which == 0 ? a : b;
+      const double scale = which == 0 ? fabs(x2[i]) : 1.0;
+      const double eta = 1e-7 * scale;
+      const double v0 = v[i];
+      double wp[7], wsp, wm[7], wsm;
+      v[i] = v0 + eta;
+      orc_weights_raw(dim, bc, x2, a, b, wp, &wsp);
+      v[i] = v0 - eta;
+      orc_weights_raw(dim, bc, x2, a, b, wm, &wsm);
+      for (int k = 0; k < np; ++k) wb[k] += scale * fabs((wp[k] - wm[k]) / (2.0 * eta));
+      *wsb += scale * fabs((wsp - wsm) / (2.0 * eta));
+    }
+  }
+  return ORC_OK;
+}
+
+int orc_weight_bounds(const orc_plan* p, int64_t g, int bc, double* wb, double* wsb) {
+  if (g < 0 || g >= p->ng) return ORC_E_ARG;
+  double x2[3], xs[3], n[3];
+  local_coords(p, g, x2, xs, n);
+  return orc_weight_bounds_raw(p->dim, bc, x2, xs, n, wb, wsb);
+}
+
 /* one ghost value from the current field values (skipped points not read) */
 static double ghost_value(const orc_plan* p, int64_t g, const double* f, int bc,
                           double b) {
@@ -1245,10 +1289,11 @@ static int unit_system(const orc_plan* p, int32_t u, const double* f,
   const int64_t* m = p->blk_mem + p->blk_off[u];
   for (int i = 0; i < k * k; ++i) A[i] = 0.0;
   for (int i = 0; i < k; ++i) {
-    double w[7], ws;
+    double w[7], ws, wb[7], wsb;
     orc_weights(p, m[i], bct[m[i]], w, &ws);
+    if (absval) orc_weight_bounds(p, m[i], bct[m[i]], wb, &wsb);
     A[i * k + i] = 1.0;
-    rhs[i] = !bv ? 0.0 : (absval ? fabs(ws * bv[m[i]]) : ws * bv[m[i]]);
+    rhs[i] = !bv ? 0.0 : (absval ? wsb * fabs(bv[m[i]]) : ws * bv[m[i]]);
     for (int j = 0; j < npts(p->dim); ++j) {
       int64_t c = p->sten[7 * m[i] + j];
       if (c < 0) continue;
@@ -1259,7 +1304,7 @@ static int unit_system(const orc_plan* p, int32_t u, const double* f,
       if (!absval) rhs[i] += w[j] * f[c];
       else {
         double sv = (p->tag[c] == 2 || p->tag[c] == -2) ? gscale[find_ghost(p, c)] : fabs(f[c]);
-        rhs[i] += fabs(w[j]) * sv;
+        rhs[i] += wb[j] * sv;
       }
     }
   }
@@ -1345,8 +1390,9 @@ static double* unit_abs_inverse(const orc_plan* p, int32_t u, const int8_t* bct)
 
 int orc_fill_scale(const orc_plan* p, int nf, const double* fields,
                    const int8_t* bc_type, const double* bc_val, double* scale) {
-  /* s_G = sum_k |w_k| s_{P_k} + |w_s b_G|, s = |phi| on non-ghost cells;
-   * coupled units: s = |A^-1| (external bound). */
+  /* s_G = sum_k wb_k s_{P_k} + wsb_G |b_G| with the weight bounds above
+   * (|w| plus the weights' sensitivity to the geometry), s = |phi| on
+   * non-ghost cells; coupled units: s = |A^-1| (external bound). */
   int64_t ng = p->ng;
   for (int f = 0; f < nf; ++f) {
     const double* F = fields + (int64_t)f * p->ncell;
@@ -1371,16 +1417,16 @@ int orc_fill_scale(const orc_plan* p, int nf, const double* fields,
         free(inv); free(A);
         continue;
       }
-      double w[7], ws;
-      orc_weights(p, g, bt[g], w, &ws);
-      double s = fabs(ws * bv[g]);
+      double wb[7], wsb;
+      orc_weight_bounds(p, g, bt[g], wb, &wsb);
+      double s = wsb * fabs(bv[g]);
       for (int j = 0; j < npts(p->dim); ++j) {
         int64_t c = p->sten[7 * g + j];
         if (c < 0) continue;
         double sv;
         if (p->tag[c] == 2 || p->tag[c] == -2) sv = sc[find_ghost(p, c)];
         else sv = fabs(F[c]);
-        s += fabs(w[j]) * sv;
+        s += wb[j] * sv;
       }
       sc[g] = s;
     }
@@ -1700,9 +1746,9 @@ int orc_fill_adjoint(const orc_plan* p, int nf, double* lam,
 int orc_fill_adjoint_scale(const orc_plan* p, int nf, double* lam_scale,
                            const int8_t* bc_type, double* lam_bc_scale) {
   /* The reverse sweep of orc_fill_adjoint with every weight replaced by its
-   * magnitude and the unit solves by |A^-T|: each output receives the sum
-   * of the magnitudes of the terms that make it up, the scale of its
-   * rounding error.  Ghost slots end at zero, as the adjoint's do. */
+   * bound (orc_weight_bounds) and the unit solves by |A^-T|: each output
+   * receives the sum of the magnitudes of the terms that make it up, the
+   * scale of its error.  Ghost slots end at zero, as the adjoint's do. */
   int64_t ng = p->ng;
   for (int f = 0; f < nf; ++f) {
     double* L = lam_scale + (int64_t)f * p->ncell;
@@ -1711,14 +1757,14 @@ int orc_fill_adjoint_scale(const orc_plan* p, int nf, double* lam_scale,
     for (int64_t g = ng - 1; g >= 0; --g) {
       int32_t u = p->blk[g];
       if (u < 0) {
-        double w[7], ws;
-        orc_weights(p, g, bt[g], w, &ws);
+        double wb[7], wsb;
+        orc_weight_bounds(p, g, bt[g], wb, &wsb);
         double Lg = L[p->cell[g]];
-        lb[g] = fabs(ws) * Lg;
+        lb[g] = wsb * Lg;
         L[p->cell[g]] = 0.0;
         for (int j = 0; j < npts(p->dim); ++j) {
           int64_t c = p->sten[7 * g + j];
-          if (c >= 0) L[c] += fabs(w[j]) * Lg;
+          if (c >= 0) L[c] += wb[j] * Lg;
         }
         continue;
       }
@@ -1736,15 +1782,15 @@ int orc_fill_adjoint_scale(const orc_plan* p, int nf, double* lam_scale,
       }
       for (int i = 0; i < k; ++i) L[p->cell[m[i]]] = 0.0;
       for (int i = 0; i < k; ++i) {
-        double w[7], ws;
-        orc_weights(p, m[i], bt[m[i]], w, &ws);
-        lb[m[i]] = fabs(ws) * mu[i];
+        double wb[7], wsb;
+        orc_weight_bounds(p, m[i], bt[m[i]], wb, &wsb);
+        lb[m[i]] = wsb * mu[i];
         for (int j = 0; j < npts(p->dim); ++j) {
           int64_t c = p->sten[7 * m[i] + j];
           if (c < 0) continue;
           int internal = 0;
           for (int q = 0; q < k; ++q) if (p->cell[m[q]] == c) internal = 1;
-          if (!internal) L[c] += fabs(w[j]) * mu[i];
+          if (!internal) L[c] += wb[j] * mu[i];
         }
       }
       free(inv); free(mu);

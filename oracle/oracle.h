@@ -96,6 +96,14 @@ int orc_weights(const orc_plan* p, int64_t g, int bc, double* w, double* ws);
 /* Same from raw local geometry: x2 = r e dx, xs = x_s - x_1, n (all [dim]). */
 int orc_weights_raw(int dim, int bc, const double* x2, const double* xs,
                     const double* n, double* w, double* ws);
+/* Tolerance bounds of the same weights: wb[k] = |w_k| + sum_i (|x2_i|
+ * |dw_k/dxs_i| + |dw_k/dn_i|), wsb likewise for w_s: their magnitude plus
+ * how far they move when the foot point moves on the scale of the stencil
+ * span and the normal on the scale of a unit vector (each side of a parity
+ * comparison projects the body on its own). */
+int orc_weight_bounds_raw(int dim, int bc, const double* x2, const double* xs,
+                          const double* n, double* wb, double* wsb);
+int orc_weight_bounds(const orc_plan* p, int64_t g, int bc, double* wb, double* wsb);
 
 /* Fresh cells of a moved body (Sec. 7.1: moving boundaries expose fresh
  * fluid cells, one reason for a second ghost layer).  a: the plan before the
@@ -119,8 +127,9 @@ int orc_fill_jacobi(const orc_plan* p, int nf, double* fields,
                     const int8_t* bc_type, const double* bc_val,
                     int max_sweeps);
 /* Condition-aware scale of every filled ghost value: [nf][N_g].  s_G sums
- * |w_k| s_{P_k} over the stencil (s = |phi| on non-ghost cells) and
- * |w_s b_G|; a coupled unit takes |A^-1| times its external sums. */
+ * wb_k s_{P_k} over the stencil (s = |phi| on non-ghost cells) and
+ * wsb |b_G|, with the weight bounds above; a coupled unit takes |A^-1|
+ * times its external sums. */
 int orc_fill_scale(const orc_plan* p, int nf, const double* fields,
                    const int8_t* bc_type, const double* bc_val, double* scale);
 
@@ -151,9 +160,9 @@ int orc_fill_adjoint(const orc_plan* p, int nf, double* lam,
                      const int8_t* bc_type, double* lam_bc);
 
 /* Condition-aware scales of the adjoints, for tolerances: the same sweeps
- * with every coefficient replaced by its magnitude (a unit's solve by
- * |A^-T|), so each output receives the sum of the magnitudes of the terms
- * that make it up.  surface: adds into lam_scale [nf][N_cells] from the
+ * with every coefficient replaced by its magnitude (a relation's weights by
+ * their bounds, a unit's solve by |A^-T|), so each output receives the sum
+ * of the magnitudes of the terms that make it up.  surface: adds into lam_scale [nf][N_cells] from the
  * magnitudes of gval, ggrad; fill: lam_scale in = scale of dJ/d(filled),
  * out = scale of dJ/d(input) (ghost slots zero); lam_bc_scale [nf][N_g]. */
 int orc_surface_query_adjoint_scale(const orc_plan* p, int64_t nq,

@@ -1,7 +1,7 @@
 """torch.autograd front end: gradients of a drag functional through
 ghost_fill -> forces, and of surface outputs through surface(), checked
 bitwise against the direct C-ABI adjoint chain, against the oracle's
-transposes (1e-11 relative to the gradient's magnitude) and by central
+transposes (1e-12 of the oracle's per-entry adjoint scale) and by central
 differences through the autograd forward."""
 import numpy as np
 import pytest
@@ -9,6 +9,7 @@ import pytest
 import oracle
 import synth
 from synth import HGC, DIRICHLET, NEUMANN
+from tolerances import check, force_gradient
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -73,18 +74,10 @@ def test_drag_gradient_through_autograd(gcr):
     assert np.array_equal(G, np.stack([host(x) for x in lam]))
     assert np.array_equal(Gb, np.stack([host(x) for x in lam_bc]))
 
-    # the oracle's transposes
-    gval = np.zeros((nf, q.x.shape[1]))
-    ggrad = np.zeros((nf, d, q.x.shape[1]))
-    e = np.eye(d)[0]
-    gval[d] = -q.w * (e[:, None] * q.n).sum(0)
-    for i in range(d):
-        for j in range(d):
-            ggrad[i, j] = mu * q.w * (e[i] * q.n[j] + e[j] * q.n[i])
-    L0 = op.surface_query_adjoint(q.x, gval, ggrad, np.zeros((nf, op.n_cells)))
-    Go, Gbo = op.fill_adjoint(L0, kinds)
-    assert np.all(np.abs(G - Go) <= 1e-11 * np.abs(Go).max())
-    assert np.all(np.abs(Gb - Gbo) <= 1e-11 * np.abs(Gbo).max())
+    # the oracle's transposes, per-entry scales
+    Go, Gbo, So, Sbo = force_gradient(op, q, mu, np.eye(d)[0], kinds, d, list(range(d)))
+    check(G, Go, So, "gradient vs oracle")
+    check(Gb, Gbo, Sbo, "bc gradient vs oracle")
 
     # central differences (J is affine: rounding only) on 8 + 8 entries
     def J(phi, b):
@@ -126,8 +119,9 @@ def test_surface_gradient_through_autograd(gcr):
     torch.cuda.synchronize()
     got = np.stack([host(p.grad) for p in phi])
     want = op.surface_query_adjoint(inst.queries.x, gval, ggrad, np.zeros((2, op.n_cells)))
-    s = np.abs(want).max()
-    assert np.all(np.abs(got - want) <= 1e-12 * np.maximum(np.abs(want), s))
+    scale = op.surface_query_adjoint_scale(inst.queries.x, np.abs(gval), np.abs(ggrad),
+                                           np.zeros((2, op.n_cells)))
+    check(got, want, scale, "surface gradient vs oracle")
 
 
 def test_fill_rejects_non_f64(gcr):

@@ -14,6 +14,7 @@ import pytest
 import oracle
 import synth
 from synth import CGC, CGC_ES, HGC, DIRICHLET, NEUMANN
+from tolerances import force_scale
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -302,10 +303,7 @@ def test_airfoil4096_full_size(gcr):
     mu = 0.3
     F = gp.forces(dev(q.x), dev(q.n), dev(q.w), dev(got[2]), [dev(got[0]), dev(got[1])], mu)
     Fo = op.forces(q.x, q.n, q.w, want[2], want[:2], mu)
-    _, _, _, ps = op.surface_query(q.x, want[2:3], field_scale=cs[2:3])
-    _, _, _, us = op.surface_query(q.x, want[:2], field_scale=cs[:2])
-    s = np.sum(np.abs(q.w) * (ps[0, 0] + 2 * mu * us[:, 1:].sum(axis=(0, 1))))
-    check_close(host(F), Fo, np.full(2, s), "forces")
+    check_close(host(F), Fo, force_scale(op, q, want, cs, 2, [0, 1], mu), "forces")
 
 
 def test_fill_deterministic(gcr):
@@ -371,13 +369,8 @@ def test_forces(gcr, which):
     mu = 0.7
     F = gp.forces(dev(q.x), dev(q.n), dev(q.w), dev(got[p_idx]), [dev(got[i]) for i in u_idx], mu)
     Fo = op.forces(q.x, q.n, q.w, want[p_idx], np.stack([want[i] for i in u_idx]), mu)
-    # scale: sum_q |w_q| (|p| + mu * 2 * sum |grad u|) bounds every term
     cs = op.cell_scale(np.nan_to_num(want), scale)
-    _, _, _, ps = op.surface_query(q.x, want[p_idx:p_idx + 1], field_scale=cs[p_idx:p_idx + 1])
-    _, _, _, us = op.surface_query(q.x, np.stack([want[i] for i in u_idx]),
-                                   field_scale=np.stack([cs[i] for i in u_idx]))
-    s = np.sum(np.abs(q.w) * (ps[0, 0] + 2 * mu * us[:, 1:].sum(axis=(0, 1))))
-    check_close(host(F), Fo, np.full(d, s), "forces")
+    check_close(host(F), Fo, force_scale(op, q, want, cs, p_idx, u_idx, mu), "forces")
 
 
 # ---------------------------------------------------------------------------

@@ -5,10 +5,13 @@ oracle's condition-aware scale of y*.  A mistake that inflates s would
 loosen every such test without turning any red, so the scales are pinned
 here against independent recomputations in numpy:
 
-  * fill scale (propagated through the levels of Sec. 3.2 with the weights
-    of Eqs. phi_G_Dir_2d ... phi_G_Neu_3d): s_G = sum_k |w_k| s_{P_k} +
-    |w_s b_G|, s = |phi| on cells that are not ghosts, a coupled unit's
-    members |A^-1| times their external sums;
+  * weight bounds: wb_k = |w_k| + sum_i (|x2_i| |dw_k/dxs_i| + |dw_k/dn_i|)
+    (each side projects the body on its own, so the foot point and normal
+    agree to a fraction of a cell, not bit for bit), against complex-step
+    derivatives of the first row of the inverted Appendix A system;
+  * fill scale (propagated through the levels of Sec. 3.2): s_G = sum_k
+    wb_k s_{P_k} + wsb |b_G|, s = |phi| on cells that are not ghosts, a
+    coupled unit's members |A^-1| times their external sums;
   * surface scale (Sec. 6): sum over the anchor box's corners of |L_c(x)|
     (value) or |d L_c / dx_i| (gradient) times the corner scales, with the
     tensor-product Lagrange basis written out here from the box geometry;
@@ -17,8 +20,9 @@ here against independent recomputations in numpy:
 Besides equality with the recomputation, two properties that hold whatever
 the arithmetic: a scale bounds the magnitude of its value (triangle
 inequality), and, for the Dirichlet relation with every normalised distance
-|alpha_i| <= 1/2 (HGC and CGC_ES, Sec. 8), each |omega_i| <= 1, so
-sum_k |w_k| <= 2^d - 1 and |w_s| <= 2^d bound s_G by the scales it reads.
+|alpha_i| <= 1/2 (HGC and CGC_ES, Sec. 8), each |omega_i| <= 1 and
+|x2_i d omega_i / dxs_i| = 1 / (1 - alpha_i)^2 <= 4, which bounds the
+weights and their bounds by constants.
 """
 import numpy as np
 import pytest
@@ -91,23 +95,23 @@ def numpy_fill_scale(p, phi, bc, b):
             mem = units[u]
             ext = np.zeros(len(mem))
             for i, m in enumerate(mem):
-                w, ws = p.weights(m, bc)
-                ext[i] = abs(ws * b[m])
+                w, ws = p.weight_bounds(m, bc)
+                ext[i] = ws * abs(b[m])
                 for wk, c in zip(w, p.stencil(m)):
                     if c < 0:
                         continue
                     c = int(c)
                     if c in pos and pos[c] in mem:
                         continue
-                    ext[i] += abs(wk) * (s[pos[c]] if c in pos else abs(phi[c]))
+                    ext[i] += wk * (s[pos[c]] if c in pos else abs(phi[c]))
             s[mem] = np.abs(np.linalg.inv(_unit_matrix(p, mem, bc, pos))) @ ext
             continue
-        w, ws = p.weights(g, bc)
-        acc = abs(ws * b[g])
+        w, ws = p.weight_bounds(g, bc)
+        acc = ws * abs(b[g])
         for wk, c in zip(w, p.stencil(g)):
             if c >= 0:
                 c = int(c)
-                acc += abs(wk) * (s[pos[c]] if c in pos else abs(phi[c]))
+                acc += wk * (s[pos[c]] if c in pos else abs(phi[c]))
         s[g] = acc
     return s
 
@@ -133,24 +137,102 @@ def test_fill_scale_recomputed(name, scheme, bc):
 
 @pytest.mark.parametrize("name", ["circle", "sphere", "star"])
 @pytest.mark.parametrize("scheme", [CGC_ES, HGC])
-def test_fill_scale_alpha_bound(name, scheme):
-    """Dirichlet with |alpha_i| <= 1/2: |omega_i| = |alpha_i| / |1 - alpha_i|
-    <= 1, so s_G <= (2^d - 1) max_k s_{P_k} + 2^d |b_G| for every ghost that
-    is its own unit, however the weights are computed."""
+def test_weights_and_bounds_under_the_alpha_bound(name, scheme):
+    """Dirichlet with |alpha_i| <= 1/2 (Sec. 8): w_k = +-prod_{i in k}
+    omega_i with |omega_i| <= 1, so sum_k |w_k| <= 2^d - 1 and |w_s| =
+    prod |1 - omega_i| <= 2^d; with |x2_i d omega_i/dxs_i| <= 4 the bounds
+    obey wb_k <= 1 + 4 |k| (|k| the directions of P_k) and wsb <= 2^d +
+    d 4 2^(d-1), however the weights are computed."""
     inst = dict(_cases())[name]
     p = oracle.OraclePlan(inst.grid, inst.shape, scheme)
     assert np.all(p.margins["max_alpha"] <= 0.5)
-    rng = np.random.default_rng(5)
-    phi, b = _inputs(p, inst, DIRICHLET, rng)
-    s = p.fill_scale(np.nan_to_num(phi)[None], [DIRICHLET], b[None])[0]
-    pos = _ghost_index(p)
-    nc = 1 << p.dim
+    d = p.dim
+    sizes = [1, 1, 2] if d == 2 else [1, 1, 1, 2, 2, 2, 3]
     for g in range(p.n_ghost):
-        if p.unit[g] >= 0:
-            continue
-        reads = [s[pos[int(c)]] if int(c) in pos else abs(phi[c]) for c in p.stencil(g) if c >= 0]
-        bound = (nc - 1) * max(reads, default=0.0) + nc * abs(b[g])
-        assert s[g] <= bound * (1 + 1e-14), (g, s[g], bound)
+        w, ws = p.weights(g, DIRICHLET)
+        wb, wsb = p.weight_bounds(g, DIRICHLET)
+        assert np.abs(w).sum() <= (2 ** d - 1) * (1 + 1e-14) and abs(ws) <= 2 ** d * (1 + 1e-14)
+        assert np.all(wb >= np.abs(w)) and wsb >= abs(ws)
+        assert np.all(wb <= 1 + 4 * np.array(sizes) + 1e-9), (g, wb)
+        assert wsb <= 2 ** d + d * 4 * 2 ** (d - 1) + 1e-9, (g, wsb)
+
+
+def _vandermonde_row(dim, bc, x2, xs, n):
+    """First row of the inverse of the Appendix A system (complex allowed)."""
+    def basis(x):
+        if dim == 2:
+            return np.array([1.0, x[0], x[1], x[0] * x[1]], dtype=complex)
+        X, Y, Z = x
+        return np.array([1.0, X, Y, Z, X * Y, Y * Z, X * Z, X * Y * Z], dtype=complex)
+
+    def basis_dn(x, nn):
+        if dim == 2:
+            return np.array([0, nn[0], nn[1], nn[0] * x[1] + nn[1] * x[0]], dtype=complex)
+        X, Y, Z = x
+        return np.array([0, nn[0], nn[1], nn[2], nn[0] * Y + nn[1] * X, nn[1] * Z + nn[2] * Y,
+                         nn[0] * Z + nn[2] * X,
+                         nn[0] * Y * Z + nn[1] * X * Z + nn[2] * X * Y], dtype=complex)
+
+    subsets = ([(1, 0), (0, 1), (1, 1)] if dim == 2 else
+               [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (0, 1, 1), (1, 0, 1), (1, 1, 1)])
+    rows = [basis(np.array(sb) * x2) for sb in subsets]
+    rows.append(basis(xs) if bc == DIRICHLET else basis_dn(xs, n))
+    return np.linalg.inv(np.array(rows))[0]
+
+
+def _complex_step_bounds(dim, bc, x2, xs, n):
+    row = _vandermonde_row(dim, bc, x2, xs.astype(complex), n.astype(complex)).real
+    wb = np.abs(row)
+    step = 1e-30
+    for i in range(dim):
+        for which in (0, 1):
+            a = xs.astype(complex)
+            b = n.astype(complex)
+            (a if which == 0 else b)[i] += 1j * step
+            der = _vandermonde_row(dim, bc, x2, a, b).imag / step
+            wb += (abs(x2[i]) if which == 0 else 1.0) * np.abs(der)
+    return wb[:-1], wb[-1]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("bc", [DIRICHLET, NEUMANN])
+def test_weight_bounds_complex_step(dim, bc):
+    rng = np.random.default_rng(40 + dim + 10 * bc)
+    done = 0
+    for _ in range(300):
+        e = rng.choice([-1.0, 1.0], size=dim)
+        r = rng.integers(1, 3, size=dim)
+        h = rng.uniform(0.5, 2.0, size=dim)
+        x2 = e * r * h
+        n = rng.normal(size=dim)
+        n /= np.linalg.norm(n)
+        xs = rng.uniform(-0.5, 0.9) * h.min() * n
+        want, wants = _complex_step_bounds(dim, bc, x2, xs, n)
+        if not np.all(np.isfinite(want)) or max(np.abs(want).max(), abs(wants)) > 1e6:
+            continue      # near a degenerate configuration
+        got, gots = oracle.weight_bounds_raw(dim, bc, x2, xs, n)
+        assert np.allclose(got, want, rtol=1e-6, atol=1e-9 * max(1.0, np.abs(want).max()))
+        assert abs(gots - wants) <= 1e-6 * abs(wants) + 1e-9
+        done += 1
+    assert done > 100
+
+
+def test_weight_bounds_on_plan_ghosts():
+    """The bounds of actual ghosts (CGC with alpha near 1, HGC fluid side,
+    Neumann) against the complex-step values from the same local
+    geometry."""
+    inst = synth.stars64(seed=0, ninst=1, nmin=96, nmax=160)[0]
+    for scheme in (CGC, HGC):
+        p = oracle.OraclePlan(inst.grid, inst.shape, scheme)
+        h = np.asarray(inst.grid.h[:2])
+        for g in range(0, p.n_ghost, 3):
+            e = np.where(p.normal[:, g] >= 0, 1.0, -1.0)
+            x2 = e * p.r[:, g] * h
+            for bc in (DIRICHLET, NEUMANN):
+                want, wants = _complex_step_bounds(2, bc, x2, p.delta[:, g], p.normal[:, g])
+                got, gots = p.weight_bounds(g, bc)
+                assert np.allclose(got, want, rtol=1e-6, atol=1e-12 * max(1.0, np.abs(want).max()))
+                assert abs(gots - wants) <= 1e-6 * abs(wants) + 1e-12
 
 
 def _box(p, a):
@@ -215,8 +297,8 @@ def test_surface_values_within_their_scale(name):
 
 
 def numpy_adjoint_scale(p, lam_s, bc):
-    """Reverse canonical sweep on magnitudes (units by |A^-T| at their last
-    member), as the adjoint itself is ordered."""
+    """Reverse canonical sweep on weight bounds (units by |A^-T| at their
+    last member), as the adjoint itself is ordered."""
     pos = _ghost_index(p)
     units = _unit_members(p)
     L = lam_s.copy()
@@ -230,19 +312,19 @@ def numpy_adjoint_scale(p, lam_s, bc):
             mu = inv.T @ L[p.ghost_cell[mem]]
             L[p.ghost_cell[mem]] = 0.0
             for i, m in enumerate(mem):
-                w, ws = p.weights(m, bc)
-                lb[m] = abs(ws) * mu[i]
+                w, ws = p.weight_bounds(m, bc)
+                lb[m] = ws * mu[i]
                 for wk, c in zip(w, p.stencil(m)):
                     if c >= 0 and not (int(c) in pos and pos[int(c)] in mem):
-                        L[c] += abs(wk) * mu[i]
+                        L[c] += wk * mu[i]
             continue
-        w, ws = p.weights(g, bc)
+        w, ws = p.weight_bounds(g, bc)
         Lg = L[p.ghost_cell[g]]
-        lb[g] = abs(ws) * Lg
+        lb[g] = ws * Lg
         L[p.ghost_cell[g]] = 0.0
         for wk, c in zip(w, p.stencil(g)):
             if c >= 0:
-                L[c] += abs(wk) * Lg
+                L[c] += wk * Lg
     return L, lb
 
 
