@@ -53,7 +53,9 @@ typedef enum {
                             or a query point has no ghost within 2 cells */
   GCR_E_DEGENERATE = 6,  /* zero denominator in a relation */
   GCR_E_GEOMETRY = 7,    /* closest-point projection did not converge */
-  GCR_E_UNSUPPORTED = 8  /* size or combination not supported */
+  GCR_E_UNSUPPORTED = 8, /* size or combination not supported */
+  GCR_E_TIMEOUT = 9      /* a bounded wait between workgroups gave up: the
+                            outputs of the call it belongs to are not valid */
 } gcr_status;
 
 /* Ghost placement (Sec. 3.1, Sec. 7.2). */
@@ -272,7 +274,11 @@ gcr_status gcr_batch_create(int32_t ninst, const gcr_grid* grids,
                             const gcr_shape* shapes, const int32_t* schemes,
                             void* stream, gcr_batch** out);
 /* Waits for the batch's gcr_batch_forward launches (on whatever stream) and
- * releases its memory; other work on its plans must have finished. */
+ * releases its memory; other work on its plans must have finished.
+ * Forward calls on one batch may use different streams: each waits for the
+ * previous one's launches (they share the batch's scratch state), so one
+ * batch's forwards never overlap; calls from several host threads on one
+ * batch must be serialised by the caller. */
 void gcr_batch_destroy(gcr_batch* batch);
 /* Plan of instance i, owned by the batch (valid until gcr_batch_destroy). */
 gcr_status gcr_batch_plan(const gcr_batch* batch, int32_t i,
@@ -364,9 +370,26 @@ gcr_status gcr_batch_tiled(const gcr_batch* batch, int32_t* state);
  * `threads`.  threads = 0 and grid = 0 restore the tuned choice; otherwise
  * threads is a power of two from 64 to 1024 and grid is 1..4 (per-item
  * kernel on min(items, 256 grid) workgroups) or -1..-128 (split sweep; a
- * batch with instances x -grid above 256 then fails with GCR_E_ARG).
+ * batch with instances x -grid above 256 then fails with GCR_E_ARG, and one
+ * whose workgroups cannot all be resident at once with GCR_E_UNSUPPORTED:
+ * the split sweep is a cooperative launch).
  * Process-wide; for tests and measurements. */
 gcr_status gcr_set_batch_shape(int32_t threads, int32_t grid);
+
+/* Faults of the split sweep.  Its workgroups meet after every level (Sec.
+ * 3.2: a level reads only earlier levels) at a device-scope counter; each
+ * wait is bounded, and a wait that gives up (which co-residency of the
+ * cooperative launch should prevent) sets a fault word of the batch, since
+ * that call's fields, surface values and forces can then be wrong.
+ * gcr_batch_status waits for the batch's gcr_batch_forward launches and
+ * returns GCR_E_TIMEOUT if any of them gave up since the last query
+ * (clearing the word), GCR_OK otherwise; it must not run concurrently with
+ * forward calls on the same batch.  gcr_set_batch_spin sets the polls of a
+ * wait before it gives up, process-wide (0: the default, 4M polls of about
+ * 64 cycles); tests set 1 to make waits give up while every kernel still
+ * ends. */
+gcr_status gcr_batch_status(const gcr_batch* batch);
+gcr_status gcr_set_batch_spin(int32_t polls);
 /* Layering (Sec. 3.2) of a plan built alone: an instance with at least
  * `min_interface` interface cells is layered by the whole GPU (one grid-wide
  * round per level, then a stable counting sort by level); smaller ones, and

@@ -25,11 +25,14 @@ SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
 SCHED_AUTO, SCHED_LEVELS, SCHED_WORKGROUP, SCHED_GRAPH = 0, 1, 2, 3
 SYMBOLS = [
     "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
-    "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_set_schedule", "gcr_fill", "gcr_surface_ghost", "gcr_surface",
+    "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_set_schedule",
+    "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
-    "gcr_batch_forward",
-    "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering", "gcr_status_str", "gcr_version",
+    "gcr_batch_forward", "gcr_batch_status",
+    "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_set_batch_spin",
+    "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering",
+    "gcr_status_str", "gcr_version",
 ]
 
 
@@ -102,6 +105,8 @@ def lib():
         L.gcr_set_profiling.argtypes = [i32]
         L.gcr_set_batch_tiling.argtypes = [i32]
         L.gcr_set_batch_shape.argtypes = [i32, i32]
+        L.gcr_set_batch_spin.argtypes = [i32]
+        L.gcr_batch_status.argtypes = [vp]
         L.gcr_batch_tiled.argtypes = [vp, vp]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_forward_times.argtypes = [vp]
@@ -371,6 +376,12 @@ class Batch:
             _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
             self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self._owner))
 
+    def status(self):
+        """gcr_batch_status: waits for the batch's forward launches; raises
+        GcrError (GCR_E_TIMEOUT) if a split sweep's wait gave up since the
+        last query."""
+        _check(lib().gcr_batch_status(self._h), "gcr_batch_status")
+
     def tiled(self) -> int:
         """gcr_batch_tiled: -1 sweep, 0 undecided, 1 tiled fill, 2 sweep after
         the closures did not fit (synchronises the device)."""
@@ -478,6 +489,11 @@ def set_batch_shape(threads: int = 0, grid: int = 0):
     choice; else threads a power of two in 64..1024 and grid 1..4 (per-item
     workgroups) or -1..-128 (split sweep, -grid workgroups per instance)."""
     _check(lib().gcr_set_batch_shape(int(threads), int(grid)), "gcr_set_batch_shape")
+
+
+def set_batch_spin(polls: int = 0):
+    """Polls of a split sweep's wait before it gives up (0: the default)."""
+    _check(lib().gcr_set_batch_spin(int(polls)), "gcr_set_batch_spin")
 
 
 def set_batch_tiling(mode: int):

@@ -210,24 +210,29 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
 // the fields of a ghost side by side (they share its stencil data), and the
 // G workgroups meet at a device-scope counter after each level and after
 // each level's coupled units.  Every value is computed as by the per-item
-// kernel, from the same inputs.  The grid (instances x G) is at most one
-// workgroup per compute unit, so all of an instance's workgroups become
-// resident while others wait; each wait is bounded as well, so every wave
-// ends.  The instance's workgroups then take its (instance, field) surface
-// items in turn, each computed as by the per-item kernel.  Two sets of
-// counters serve launches in turn: each launch clears the set the next one
-// uses (launches on one batch do not overlap).
+// kernel, from the same inputs.  The launch is cooperative (the runtime
+// refuses it unless every workgroup can be resident at once), and each wait
+// is bounded as well, so every wave ends: a wait that gives up sets the
+// batch's fault word, which gcr_batch_status reports, since the values of
+// that call can then be wrong.  The instance's workgroups then take its
+// (instance, field) surface items in turn, each computed as by the per-item
+// kernel.  Two sets of counters serve launches in turn: each launch clears
+// the set the next one uses (launches on one batch are ordered).
 constexpr int kSpinMax = 1 << 22;
 
-__device__ __forceinline__ void inst_barrier(int* bar, int target) {
+__device__ __forceinline__ void inst_barrier(int* bar, int target, int spin, int* fault) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();   // this workgroup's values, before its arrival
     atomicAdd(bar, 1);
-    for (int k = 0; k < kSpinMax &&
-                    __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target;
-         ++k)
+    for (int k = 0;; ++k) {
+      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (k >= spin) {   // gave up: this call's values cannot be trusted
+        atomicOr(fault, 1);
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
+    }
     __threadfence();   // the other workgroups' values, after theirs
   }
   __syncthreads();
@@ -238,7 +243,8 @@ __global__ __launch_bounds__(1024) void k_batch_split(BStatic S, BCall C, int G,
                                                       int* __restrict__ bar, int parity,
                                                       double* __restrict__ part,
                                                       int* __restrict__ counter,
-                                                      double* __restrict__ Fout) {
+                                                      double* __restrict__ Fout,
+                                                      int* __restrict__ fault, int spin) {
   __shared__ double red[1024][3];
   __shared__ UnitWS ws[64];
   const int T = blockDim.x;
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(1024) void k_batch_split(BStatic S, BCall C, int G,
       const int p = lo + e / nf, f = e % nf, w = i * nf + f;
       fill_single<D>(P, p, C.fields[w], C.bcv[w], C.bct ? C.bct[w] : nullptr, C.kind[f]);
     }
-    inst_barrier(cnt, G * ++arrivals);
+    inst_barrier(cnt, G * ++arrivals, spin, fault);
     if (P.nunits) {
       if (threadIdx.x < 64)
         for (int u = s * 64 + (int)threadIdx.x; u < P.nunits; u += G * 64)
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_batch_split(BStatic S, BCall C, int G,
               fill_unit_field<D>(P, u, C.fields[w], C.bcv[w], C.bct ? C.bct[w] : nullptr,
                                  C.kind[f], ws[threadIdx.x]);
             }
-      inst_barrier(cnt, G * ++arrivals);
+      inst_barrier(cnt, G * ++arrivals, spin, fault);
     }
   }
   for (int f = s; f < nf; f += G) surface_item<D>(S, C, i * nf + f, red, part, counter, Fout);
@@ -606,6 +612,7 @@ struct BatchFwdState {
   int* d_counter = nullptr;
   int* d_bar = nullptr;            // [2][ninst] level counters of the split sweep
   int bar_parity = 0;              // the set the next split launch uses
+  int* d_fault = nullptr;          // [1] set when a split sweep's wait gave up
   double* d_part = nullptr;
   size_t part_cap = 0;
   char* d_call = nullptr;
@@ -693,7 +700,8 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t o_lp = al(sizeof(PlanD) * n), o_nl = o_lp + al(sizeof(int32_t*) * n);
   const size_t o_ct = o_nl + al(sizeof(int32_t) * n), o_bar = o_ct + al(sizeof(int) * n);
-  const size_t bytes = o_bar + al(sizeof(int) * 2 * n);
+  const size_t o_fault = o_bar + al(sizeof(int) * 2 * n);
+  const size_t bytes = o_fault + al(sizeof(int));
   char* d = static_cast<char*>(pool_alloc(bytes));
   if (d) S->owned.push_back(d);
   S->h_static = static_cast<char*>(pinned_alloc(bytes));
@@ -706,6 +714,7 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   S->d_nlev = reinterpret_cast<int32_t*>(d + o_nl);
   S->d_counter = reinterpret_cast<int*>(d + o_ct);
   S->d_bar = reinterpret_cast<int*>(d + o_bar);
+  S->d_fault = reinterpret_cast<int*>(d + o_fault);
   std::memset(S->h_static, 0, bytes);
   std::memcpy(S->h_static, pv.data(), sizeof(PlanD) * n);
   std::memcpy(S->h_static + o_lp, lp.data(), sizeof(int32_t*) * n);
@@ -957,28 +966,63 @@ static bool tile_setup(BatchFwdState* S, gcr_batch* b, int dim, hipStream_t st,
 // workgroup per compute unit.
 constexpr int kSplitMaxGrid = 256;
 
+// Polls of a split sweep's wait before it gives up (process-wide; tests
+// lower it to make the wait give up while every kernel still ends).
+static std::atomic<int> g_split_spin{kSpinMax};
+
+// Workgroups of k_batch_split<D> at `threads` that can be resident at once
+// on the device (occupancy per compute unit times compute units), found once
+// per shape.
+static int split_capacity(int dim, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> cap;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(dim, threads);
+  auto it = cap.find(key);
+  if (it != cap.end()) return it->second;
+  int dev = 0, ncu = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+  const void* k = dim == 2 ? reinterpret_cast<const void*>(&k_batch_split<2>)
+                           : reinterpret_cast<const void*>(&k_batch_split<3>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess) per = 0;
+  (void)hipGetLastError();
+  const int c = std::max(0, per * ncu);
+  cap[key] = c;
+  return c;
+}
+
 // gm > 0: per-item kernel over min(items, 256 gm) workgroups; gm < 0: split
-// sweep with -gm workgroups per instance.
+// sweep with -gm workgroups per instance, launched cooperatively (refused
+// with GCR_E_UNSUPPORTED where its workgroups cannot all be resident).
 static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int threads, int gm,
                                double* F, hipStream_t st) {
   BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
+  if (gm < 0) {
+    const int G = -gm;
+    if ((int64_t)G * C.ninst > kSplitMaxGrid || threads > 1024) return GCR_E_ARG;
+    if ((int64_t)G * C.ninst > split_capacity(dim, threads)) return GCR_E_UNSUPPORTED;
+  }
   if (C.tile_flag) {
     const size_t lds = sizeof(double) * kTileCap * C.nf;
     if (dim == 2) k_tile_fill<2><<<(unsigned)S->tmax, 256, lds, st>>>(bs, C, S->T);
     else k_tile_fill<3><<<(unsigned)S->tmax, 256, lds, st>>>(bs, C, S->T);
   }
   if (gm < 0) {
-    const int G = -gm;
-    if ((int64_t)G * C.ninst > kSplitMaxGrid || threads > 1024) return GCR_E_ARG;
-    const int par = S->bar_parity;
+    int G = -gm;
+    int par = S->bar_parity;
     S->bar_parity ^= 1;
-    const unsigned grid = (unsigned)(G * C.ninst);
-    if (dim == 2)
-      k_batch_split<2><<<grid, threads, 0, st>>>(bs, C, G, S->d_bar, par, S->d_part,
-                                                 S->d_counter, F);
-    else
-      k_batch_split<3><<<grid, threads, 0, st>>>(bs, C, G, S->d_bar, par, S->d_part,
-                                                 S->d_counter, F);
+    int spin = g_split_spin.load();
+    BCall Cc = C;
+    double* part = S->d_part;
+    int* counter = S->d_counter;
+    int* bar = S->d_bar;
+    int* fault = S->d_fault;
+    void* args[] = {&bs, &Cc, &G, &bar, &par, &part, &counter, &F, &fault, &spin};
+    const void* k = dim == 2 ? reinterpret_cast<const void*>(&k_batch_split<2>)
+                             : reinterpret_cast<const void*>(&k_batch_split<3>);
+    GCR_HIP(hipLaunchCooperativeKernel(k, dim3((unsigned)(G * C.ninst)), dim3(threads), args, 0,
+                                       st));
   } else {
     const int grid = std::min(C.nitems, 256 * gm);
     if (dim == 2)
@@ -988,6 +1032,30 @@ static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int th
   }
   GCR_HIP(hipGetLastError());
   return GCR_OK;
+}
+
+extern "C" gcr_status gcr_set_batch_spin(int32_t polls) {
+  if (polls < 0) return GCR_E_ARG;
+  g_split_spin.store(polls == 0 ? kSpinMax : polls - 1);
+  return GCR_OK;
+}
+
+extern "C" gcr_status gcr_batch_status(const gcr_batch* batch) {
+  if (!batch) return GCR_E_ARG;
+  BatchFwdState* S = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_bfs_mu);
+    for (auto& e : g_bfs)
+      if (e.first == batch) S = e.second.get();
+  }
+  if (!S) return GCR_OK;   // never forwarded
+  if (S->ev_done) GCR_HIP(hipEventSynchronize(S->ev_done));
+  int fault = 0;
+  GCR_HIP(hipMemcpy(&fault, S->d_fault, sizeof(int), hipMemcpyDeviceToHost));
+  if (!fault) return GCR_OK;
+  const int zero = 0;
+  GCR_HIP(hipMemcpy(S->d_fault, &zero, sizeof(int), hipMemcpyHostToDevice));
+  return GCR_E_TIMEOUT;
 }
 
 extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* const* fields,
@@ -1019,6 +1087,17 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   gcr_status err = GCR_OK;
   BatchFwdState* S = state_of(batch, st, &err);
   if (!S) return err;
+  // every call rewrites the batch's call table, partial sums and counters:
+  // a call on another stream than the last one waits for that one's launches
+  if (S->ev_done) GCR_HIP(hipStreamWaitEvent(st, S->ev_done, 0));
+  // a buffer that must grow is freed only once the launches that read it
+  // have run (the pool hands it to other threads at once)
+  auto retire = [&](void* p) -> bool {
+    if (!p) return true;
+    if (S->ev_done && hipEventSynchronize(S->ev_done) != hipSuccess) return false;
+    pool_free(p);
+    return true;
+  };
   // tiles from the second forward call of a batch (mode 1: a batch used once
   // does not pay for the closures), or from the first (mode 2)
   ++S->calls;
@@ -1074,20 +1153,20 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   }
   const int64_t npts = aoff[n];
   if (npts > 0 && S->anchor_cap < (size_t)npts) {
-    if (S->d_anchor) pool_free(S->d_anchor);
+    if (!retire(S->d_anchor)) return GCR_E_HIP;
     S->d_anchor = static_cast<int32_t*>(pool_alloc(sizeof(int32_t) * npts));
     S->anchor_cap = S->d_anchor ? (size_t)npts : 0;
     if (!S->d_anchor) return GCR_E_NOMEM;
   }
   const size_t o_order = put(order.data(), sizeof(int32_t) * np);
   if (S->call_cap < o) {
-    if (S->d_call) pool_free(S->d_call);
+    if (!retire(S->d_call)) return GCR_E_HIP;
     S->d_call = static_cast<char*>(pool_alloc(o));
     S->call_cap = S->d_call ? o : 0;
     if (!S->d_call) return GCR_E_NOMEM;
   }
   if (S->part_cap < np * 3) {
-    if (S->d_part) pool_free(S->d_part);
+    if (!retire(S->d_part)) return GCR_E_HIP;
     S->d_part = static_cast<double*>(pool_alloc(sizeof(double) * np * 3));
     S->part_cap = S->d_part ? np * 3 : 0;
     if (!S->d_part) return GCR_E_NOMEM;
@@ -1198,6 +1277,7 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
           continue;   // same shape
         if (gm < 0 && (S->tiled == 1 || (int64_t)(-gm) * n > kSplitMaxGrid)) continue;
         gcr_status s = launch_batch(S, C, dim, tt, gm, Fo, st);
+        if (s == GCR_E_UNSUPPORTED) continue;   // workgroups not co-resident
         if (s != GCR_OK) return s;
         GCR_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < 3; ++r) launch_batch(S, C, dim, tt, gm, Fo, st);

@@ -448,6 +448,7 @@ const char* gcr_status_str(gcr_status s) {
     case GCR_E_DEGENERATE: return "degenerate relation (zero denominator)";
     case GCR_E_GEOMETRY: return "closest-point projection failed";
     case GCR_E_UNSUPPORTED: return "unsupported size or combination";
+    case GCR_E_TIMEOUT: return "a wait between workgroups gave up; outputs not valid";
   }
   return "unknown status";
 }

@@ -648,3 +648,51 @@ def test_batch_split_sweep_refuses_oversized_grid(gcr):
     finally:
         gcr.set_batch_shape(0, 0)
         gcr.set_batch_tiling(1)
+
+
+def test_batch_split_wait_that_gives_up_is_reported(gcr):
+    """The host makes every wait of the split sweep give up after one poll
+    (gcr_set_batch_spin(1)): every kernel still ends, and gcr_batch_status
+    reports GCR_E_TIMEOUT for the call instead of letting its possibly wrong
+    values pass as valid.  With the default limit, the next calls are clean
+    again and equal the per-item sweep bit for bit."""
+    inst = synth.sphere256(seed=0, n=160)
+    kinds = [f.bc for f in inst.fields]
+    nf = len(kinds)
+    gcr.set_batch_tiling(0)
+    try:
+        B = gcr.Batch([inst.grid], [inst.shape], [HGC])
+        assert B.plans[0].n_levels >= 5
+        rng = np.random.default_rng(5)
+        clean = [torch.as_tensor(rng.standard_normal(inst.grid.n_cells), device="cuda")
+                 for _ in range(nf)]
+        bcv = [torch.as_tensor(rng.standard_normal(B.plans[0].n_ghost), device="cuda")
+               for _ in range(nf)]
+
+        def run(threads, grid):
+            gcr.set_batch_shape(threads, grid)
+            fields = [c.clone() for c in clean]
+            B.forward(nf, fields, kinds, bcv)
+            return fields
+
+        ref = run(256, 1)
+        B.status()                                   # clean so far
+        gcr.set_batch_spin(1)
+        try:
+            for _ in range(3):
+                run(256, -64)
+            with pytest.raises(gcr.GcrError) as e:
+                B.status()
+            assert e.value.code == 9                 # GCR_E_TIMEOUT
+        finally:
+            gcr.set_batch_spin(0)
+        B.status()                                   # the query cleared the word
+        got = run(256, -64)
+        B.status()
+        for a, b in zip(got, ref):
+            assert torch.equal(_bits(a), _bits(b))
+        with pytest.raises(gcr.GcrError):
+            gcr.set_batch_spin(-1)
+    finally:
+        gcr.set_batch_shape(0, 0)
+        gcr.set_batch_tiling(1)
