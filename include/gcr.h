@@ -242,6 +242,20 @@ gcr_status gcr_forces(const gcr_plan* plan, int64_t nq, const double* xq,
                       const double* const* u, double mu, double* F,
                       void* stream);
 
+/* gcr_forces for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * same computation and result, bit for bit, as gcr_forces; the per-block
+ * partial sums live in a static device array of the library (1.5 MiB per
+ * device, 65,536 blocks: up to 262,144 points in 3D and 524,288 in 2D; more
+ * gives GCR_E_UNSUPPORTED) instead of scratch the plan allocates on first
+ * use, and the call allocates nothing.  Every call on one device shares that
+ * device's array, so calls that overlap on one device (concurrent streams or
+ * host threads) race: the caller must order them. */
+gcr_status gcr_forces_noalloc(const gcr_plan* plan, int64_t nq, const double* xq,
+                              const double* nrm, const double* wq, const double* p,
+                              const double* const* u, double mu, double* F,
+                              void* stream);
+
 /* Adjoint of gcr_surface: lam[f] (device f64 [n_cells]) += (d outputs /
  * d filled field)^T (gval [nf][nq], ggrad [nf][dim][nq]; either may be NULL).
  * Deterministic. */

@@ -27,7 +27,7 @@ SYMBOLS = [
     "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
     "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_set_schedule",
     "gcr_fill", "gcr_surface_ghost", "gcr_surface",
-    "gcr_forces", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
+    "gcr_forces", "gcr_forces_noalloc", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
     "gcr_batch_forward", "gcr_batch_status",
     "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_set_batch_spin",
@@ -94,6 +94,7 @@ def lib():
         L.gcr_surface_ghost.argtypes = [vp, i32, vp, vp, vp, vp]
         L.gcr_surface.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, vp]
         L.gcr_forces.argtypes = [vp, i64, vp, vp, vp, vp, vp, dbl, vp, vp]
+        L.gcr_forces_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, dbl, vp, vp]
         L.gcr_surface_adjoint.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp]
         L.gcr_forces_adjoint.argtypes = [vp, i64, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.gcr_fill_adjoint.argtypes = [vp, i32, vp, vp, vp, vp, vp]

@@ -632,6 +632,66 @@ gcr_status gcr_forces(const gcr_plan* p, int64_t nq, const double* xq, const dou
   return GCR_OK;
 }
 
+}  // extern "C"
+
+// Force partials of gcr_forces_noalloc: a file-scope device array instead of
+// plan scratch, so the call allocates nothing.  Each device holds its own
+// copy; host code reaches it only through the address hipGetSymbolAddress
+// gives per device (the array's name on the host is a stand-in, not a
+// device address).  Every block of the force kernel writes its partial, so
+// nothing needs clearing between calls.
+namespace {
+constexpr int64_t kNoAllocForceBlocks = 65536;   // 1.5 MiB of partials
+static __device__ __align__(256) double scratch[3 * kNoAllocForceBlocks];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the array, looked up once per device.
+gcr_status device_scratch(double** out) {
+  int dev = 0;
+  GCR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return GCR_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    GCR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return GCR_E_HIP;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return GCR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gcr_status gcr_forces_noalloc(const gcr_plan* p, int64_t nq, const double* xq,
+                              const double* nrm, const double* wq, const double* pf,
+                              const double* const* u, double mu, double* F, void* stream) {
+  if (!p || nq < 0 || !F || !pf || !u) return GCR_E_ARG;
+  if (nq > 0 && (!xq || !nrm || !wq)) return GCR_E_ARG;
+  for (int a = 0; a < p->dim; ++a)
+    if (!u[a]) return GCR_E_ARG;
+  const int64_t nb = force_blocks(p->dim, nq);
+  if (nb > kNoAllocForceBlocks) return GCR_E_UNSUPPORTED;
+  double* part = nullptr;
+  const gcr_status s = device_scratch(&part);
+  if (s != GCR_OK) return s;
+  ForceArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.nq = nq;
+  A.xq = xq;
+  A.nrm = nrm;
+  A.wq = wq;
+  A.p = pf;
+  for (int a = 0; a < p->dim; ++a) A.u[a] = u[a];
+  A.mu = mu;
+  launch_forces(plan_view(p), A, part, F, (hipStream_t)stream);
+  GCR_HIP(hipGetLastError());
+  return GCR_OK;
+}
+
 gcr_status gcr_batch_create(int32_t ninst, const gcr_grid* grids, const gcr_shape* shapes,
                             const int32_t* schemes, void* stream, gcr_batch** out) {
   if (!out) return GCR_E_ARG;
