@@ -26,7 +26,7 @@ struct InstInfo {
   int32_t maxwidth;
   int32_t nfluid;
   int32_t rmax[3];      // largest stencil multiplier per axis
-  int32_t pad;
+  int32_t layered;      // set when the LDS layering finished the instance
   unsigned long long max_alpha_bits[3];
 };
 

@@ -217,6 +217,471 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Layering in LDS.  One workgroup per instance keeps the byte counters of
+// unplaced ghosts read, each ghost's level and a Kahn queue in LDS, and the
+// instance's reverse edges too when they fit: level k is the queue segment
+// its predecessor level released, so a level costs one pass over its own
+// ghosts' reverse edges and one barrier.
+//
+// If the queue runs dry with ghosts left, those read a cycle directly or
+// through others.  The ghosts that no unplaced ghost reads are trimmed
+// away, repeatedly, leaving the cycles (and any ghost between two); their
+// strongly connected groups (transitive closure, as in k_levels) become
+// coupled units.  The unplaced ghosts and units are then placed in
+// dependency order, each at 1 + the highest level it reads (the level of
+// Sec. 3.2: the longest dependency path, units as single nodes).
+//
+// The canonical order (level, linear index) comes from a stable counting
+// sort: per-wave level counts over contiguous ranges of the linear order,
+// level offsets from their totals, a scan over the waves per level, and each
+// ghost's rank among its wave's ghosts of the same level by ballots.  An
+// instance that does not fit, is deeper than kFastLevels or whose units
+// exceed the solver's limits is left to k_levels, launched right after,
+// which skips the instances finished here (InstInfo::layered).
+constexpr int kFastLevels = 256;
+constexpr int kFastWaves = 16;     // 1024 threads
+constexpr uint16_t kTrimmed = 0xffff;
+
+// Appends v to list[base + ...] (length counter *size) for the lanes with p
+// set, one atomic per wave; entries at or beyond cap are dropped (a node
+// enters a queue once, so it never holds more than the instance's ghosts;
+// the check keeps LDS writes in bounds regardless).
+__device__ __forceinline__ void wave_push16(bool p, int v, uint16_t* list, int base,
+                                            int* size, int cap) {
+  const unsigned long long m = __ballot(p);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int at = 0;
+  if (lane == leader) at = atomicAdd(size, __popcll(m));
+  at = __shfl(at, leader);
+  const int idx = base + at + __popcll(m & ((1ull << lane) - 1ull));
+  if (p && idx < cap) list[idx] = (uint16_t)v;
+}
+
+__global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_bytes) {
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ int s_off[kFastLevels + 2];
+  __shared__ int s_tot[kFastLevels + 1];
+  __shared__ int s_cnt[3];
+  __shared__ int64_t sh[17];
+  __shared__ int s_flag, s_units, s_maxunit, s_maxlev, s_placed, s_bad;
+  const int ii = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t lo = L.g_off[ii];
+  const int n = (int)(L.g_off[ii + 1] - lo);
+  if (n > 65535) return;   // 16-bit ids in the queue
+  const int np = (1 << L.insts[ii].g.dim) - 1;
+  const int64_t cap = L.cap;
+  const int32_t* __restrict__ deps = L.deps;
+  const int32_t* __restrict__ roff = L.roff + lo;
+  const int32_t* __restrict__ radj = L.radj;
+  const uint8_t* __restrict__ dcnt = L.dcnt + lo;
+  int32_t* __restrict__ blk_idx = L.blk_idx;      // global linear ids
+  int32_t* unit_mem = L.unit_mem + (int64_t)ii * kMaxUnits * kMaxUnit;
+  int32_t* unit_cnt = L.unit_cnt + (int64_t)ii * kMaxUnits;
+  int32_t* unit_lev = L.unit_lev + (int64_t)ii * kMaxUnits;
+  const int64_t e0 = roff[0];
+  const int E = (int)(roff[n] - e0);
+  auto al = [](int64_t b) { return (b + 15) & ~int64_t(15); };
+  char* base = reinterpret_cast<char*>(s_dyn);
+  int64_t o = 0;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + o);
+  o += al(4 * (int64_t)((n + 3) >> 2));
+  uint16_t* lvl = reinterpret_cast<uint16_t*>(base + o);
+  o += al(2 * (int64_t)n);
+  uint16_t* que = reinterpret_cast<uint16_t*>(base + o);
+  o += al(2 * (int64_t)n);
+  // [kFastWaves][kFastLevels] rank counts; before that the cycle search's
+  // residual list, representatives and unit slots (3 x kMaxResidual)
+  int32_t* tab = reinterpret_cast<int32_t*>(base + o);
+  o += 4 * (int64_t)kFastWaves * kFastLevels;
+  if (o > lds_bytes) return;   // every thread leaves alike
+  int32_t* eoff = reinterpret_cast<int32_t*>(base + o);
+  const int64_t o_adj = o + al(4 * ((int64_t)n + 1));
+  uint16_t* eadj = reinterpret_cast<uint16_t*>(base + o_adj);
+  const bool elds = o_adj + al(2 * (int64_t)E) <= lds_bytes;
+  auto edge_range = [&](int g, int& ea, int& eb) {
+    ea = elds ? eoff[g] : (int)(roff[g] - e0);
+    eb = elds ? eoff[g + 1] : (int)(roff[g + 1] - e0);
+  };
+  auto dependant = [&](int e) { return elds ? (int)eadj[e] : (int)(radj[e0 + e] - lo); };
+  auto dep = [&](int g, int q) { return deps[(int64_t)q * cap + lo + g]; };   // global id / -1
+
+  const int C = (n + 3) >> 2;
+  for (int w = tid; w < C; w += 1024) {
+    uint32_t v = 0;
+    for (int q = 0; q < 4; ++q)
+      if (4 * w + q < n) v |= (uint32_t)dcnt[4 * w + q] << (8 * q);
+    cnt[w] = v;
+  }
+  for (int g = tid; g < n; g += 1024) {
+    lvl[g] = 0;
+    blk_idx[lo + g] = -1;
+  }
+  if (elds) {
+    for (int g = tid; g <= n; g += 1024) eoff[g] = (int)(roff[g] - e0);
+    for (int e = tid; e < E; e += 1024) eadj[e] = (uint16_t)(radj[e0 + e] - lo);
+  }
+  if (tid < 3) s_cnt[tid] = 0;
+  if (tid == 0) {
+    s_units = 0;
+    s_maxunit = 0;
+    s_bad = 0;
+  }
+  __syncthreads();
+  // level 1: ghosts that read no ghost
+  for (int g = tid; g < n; g += 1024) {
+    const bool p = dcnt[g] == 0;
+    if (p) lvl[g] = 1;
+    wave_push16(p, g, que, 0, &s_cnt[0], n);
+  }
+  __syncthreads();
+  int a = 0, b = s_cnt[0], k = 0;
+  // iteration k: level k (queue[a, b)) releases level k + 1 into queue[b,
+  // ...), its length accumulating in s_cnt[k % 3].  The counter of the next
+  // iteration, s_cnt[(k + 1) % 3], was last read after the barrier that
+  // ended iteration k - 2, which every thread has passed since, so thread 0
+  // clears it now.
+  while (a < b) {
+    ++k;
+    if (k > kFastLevels) return;   // uniform: every thread counts the same levels
+    if (tid == 0) s_cnt[(k + 1) % 3] = 0;
+    int* const tail = &s_cnt[k % 3];
+    for (int i = a + tid; i < b; i += 1024) {
+      const int g = que[i];
+      int ea, eb;
+      edge_range(g, ea, eb);
+      for (int e = ea; e < eb; ++e) {
+        const int q = dependant(e);
+        const bool rel = cnt_dec(cnt, q) == 1u;
+        if (rel) lvl[q] = (uint16_t)(k + 1);
+        wave_push16(rel, q, que, b, tail, n);
+      }
+    }
+    __syncthreads();
+    a = b;
+    b += *tail;
+    if (b > n) return;   // cannot happen (each ghost released once)
+  }
+  if (tid == 0) {
+    s_maxlev = k;
+    s_placed = b;
+  }
+
+  if (b < n) {
+    // ---- the ghosts left read a cycle.  Trim those that no unplaced ghost
+    // reads (counters: unplaced readers), repeatedly.
+    for (int w = tid; w < C; w += 1024) cnt[w] = 0;
+    __syncthreads();
+    for (int g = tid; g < n; g += 1024) {
+      if (lvl[g] != 0) continue;
+      int ea, eb;
+      edge_range(g, ea, eb);
+      uint32_t c = 0;
+      for (int e = ea; e < eb; ++e) c += lvl[dependant(e)] == 0 ? 1u : 0u;
+      if (c) cnt_add(cnt, g, c);
+    }
+    if (tid < 3) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int g = tid; g < n; g += 1024) {
+      const bool p = lvl[g] == 0 && cnt_get(cnt, g) == 0;
+      if (p) lvl[g] = kTrimmed;
+      wave_push16(p, g, que, b, &s_cnt[0], n);
+    }
+    __syncthreads();
+    {
+      int ta = b, tb = b + s_cnt[0], r = 0;
+      while (ta < tb) {
+        ++r;
+        if (tid == 0) s_cnt[(r + 1) % 3] = 0;
+        int* const tail = &s_cnt[r % 3];
+        for (int i = ta + tid; i < tb; i += 1024) {
+          const int u = que[i];
+          for (int q = 0; q < np; ++q) {
+            const int32_t d = dep(u, q);
+            bool rel = false;
+            int dl = 0;
+            if (d >= 0) {
+              dl = (int)(d - lo);
+              if (lvl[dl] == 0 && cnt_dec(cnt, dl) == 1u) {
+                rel = true;
+                lvl[dl] = kTrimmed;
+              }
+            }
+            wave_push16(rel, dl, que, tb, tail, n);
+          }
+        }
+        __syncthreads();
+        ta = tb;
+        tb += *tail;
+        if (tb > n) return;
+      }
+    }
+    // ---- strongly connected groups of the untrimmed ghosts (ascending)
+    int32_t* res = tab;
+    int32_t* rep = tab + kMaxResidual;
+    int32_t* slot = tab + 2 * kMaxResidual;
+    int m = 0;
+    for (int b0 = 0; b0 < n; b0 += 1024) {
+      const int g = b0 + tid;
+      const bool left = g < n && lvl[g] == 0;
+      int64_t tot;
+      const int64_t pre = block_excl_scan<1024>(left ? 1 : 0, &tot, sh);
+      if (left && m + pre < kMaxResidual) res[m + pre] = g;
+      m += (int)tot;
+    }
+    if (m == 0 || m > kMaxResidual) return;
+    uint32_t* reach = L.reach + (int64_t)ii * kMaxResidual * (kMaxResidual / 32);
+    const int RW = (m + 31) / 32;
+    for (int t = tid; t < m * RW; t += 1024) reach[t] = 0;
+    __threadfence_block();
+    __syncthreads();
+    for (int u = tid; u < m; u += 1024)
+      for (int q = 0; q < np; ++q) {
+        const int32_t d = dep(res[u], q);
+        if (d < 0 || lvl[d - lo] != 0) continue;
+        const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
+        if (v >= 0) reach[u * RW + (v >> 5)] |= 1u << (v & 31);
+      }
+    __threadfence_block();
+    __syncthreads();
+    do {
+      if (tid == 0) s_flag = 0;
+      __syncthreads();
+      int changed = 0;
+      for (int u = tid; u < m; u += 1024)
+        for (int q = 0; q < np; ++q) {
+          const int32_t d = dep(res[u], q);
+          if (d < 0 || lvl[d - lo] != 0) continue;
+          const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
+          if (v < 0) continue;
+          for (int w = 0; w < RW; ++w) {
+            const uint32_t ow = reach[u * RW + w], nw = ow | reach[v * RW + w];
+            if (nw != ow) {
+              reach[u * RW + w] = nw;
+              changed = 1;
+            }
+          }
+        }
+      if (changed) s_flag = 1;
+      __threadfence_block();
+      __syncthreads();
+    } while (s_flag);
+    // representative: smallest member of the group; -1 off cycles
+    for (int u = tid; u < m; u += 1024) {
+      int rp = -1;
+      if ((reach[u * RW + (u >> 5)] >> (u & 31)) & 1u)
+        for (int v = 0; v < m; ++v)
+          if (((reach[u * RW + (v >> 5)] >> (v & 31)) & 1u) &&
+              ((reach[v * RW + (u >> 5)] >> (u & 31)) & 1u)) {
+            rp = v;
+            break;
+          }
+      rep[u] = rp;
+    }
+    __syncthreads();
+    {
+      int off = 0;
+      for (int b0 = 0; b0 < m; b0 += 1024) {
+        const int u = b0 + tid;
+        const bool isrep = u < m && rep[u] == u;
+        int64_t tot;
+        const int64_t pre = block_excl_scan<1024>(isrep ? 1 : 0, &tot, sh);
+        if (isrep) slot[u] = off + (int)pre;
+        off += (int)tot;
+      }
+      if (tid == 0) s_units = off;
+    }
+    __syncthreads();
+    if (s_units > kMaxUnits) return;
+    for (int u = tid; u < m; u += 1024) {
+      const int rp = rep[u];
+      if (rp < 0) continue;
+      int rank = 0, size = 0;
+      for (int v = 0; v < m; ++v)
+        if (rep[v] == rp) {
+          if (v < u) ++rank;
+          ++size;
+        }
+      if (size > kMaxUnit) {   // larger than the LDS solve's workspace
+        s_bad = 1;
+        continue;
+      }
+      const int sl = slot[rp];
+      unit_mem[sl * kMaxUnit + rank] = (int32_t)(lo + res[u]);
+      blk_idx[lo + res[u]] = sl;
+      if (u == rp) {
+        unit_cnt[sl] = size;
+        atomicMax(&s_maxunit, size);
+      }
+    }
+    for (int g = tid; g < n; g += 1024)
+      if (lvl[g] == kTrimmed) lvl[g] = 0;
+    __threadfence_block();
+    __syncthreads();
+    if (s_bad) return;
+
+    // ---- the unplaced ghosts and units in dependency order, each at 1 +
+    // the highest level it reads (internal edges of a unit excluded)
+    auto head_of = [&](int g) {
+      const int u = blk_idx[lo + g];
+      return u >= 0 ? (int)(unit_mem[u * kMaxUnit] - lo) : g;
+    };
+    auto place = [&](int t) {   // level of node t, given to its members
+      const int u = blk_idx[lo + t];
+      const int sz = u >= 0 ? unit_cnt[u] : 1;
+      int mx = 0;
+      for (int j = 0; j < sz; ++j) {
+        const int gm = u >= 0 ? (int)(unit_mem[u * kMaxUnit + j] - lo) : t;
+        for (int q = 0; q < np; ++q) {
+          const int32_t d = dep(gm, q);
+          if (d < 0 || (u >= 0 && blk_idx[d] == u)) continue;
+          mx = max(mx, (int)lvl[d - lo]);
+        }
+      }
+      for (int j = 0; j < sz; ++j) {
+        const int gm = u >= 0 ? (int)(unit_mem[u * kMaxUnit + j] - lo) : t;
+        lvl[gm] = (uint16_t)(mx + 1);
+      }
+      if (u >= 0) unit_lev[u] = mx + 1;
+      atomicAdd(&s_placed, sz);
+      atomicMax(&s_maxlev, mx + 1);
+    };
+    for (int w = tid; w < C; w += 1024) cnt[w] = 0;
+    __syncthreads();
+    for (int g = tid; g < n; g += 1024) {
+      if (lvl[g] != 0) continue;
+      const int u = blk_idx[lo + g];
+      uint32_t c = 0;
+      for (int q = 0; q < np; ++q) {
+        const int32_t d = dep(g, q);
+        if (d < 0 || lvl[d - lo] != 0 || (u >= 0 && blk_idx[d] == u)) continue;
+        ++c;
+      }
+      if (c) cnt_add(cnt, head_of(g), c);
+    }
+    if (tid < 3) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int g = tid; g < n; g += 1024) {
+      bool p = false;
+      if (lvl[g] == 0 && head_of(g) == g && cnt_get(cnt, g) == 0) p = true;
+      if (p) place(g);
+      wave_push16(p, g, que, b, &s_cnt[0], n);
+    }
+    __threadfence_block();
+    __syncthreads();
+    int ra = b, rb = b + s_cnt[0], r = 0;
+    while (ra < rb) {
+      ++r;
+      if (tid == 0) s_cnt[(r + 1) % 3] = 0;
+      int* const tail = &s_cnt[r % 3];
+      for (int i = ra + tid; i < rb; i += 1024) {
+        const int t = que[i];
+        const int u = blk_idx[lo + t];
+        const int sz = u >= 0 ? unit_cnt[u] : 1;
+        for (int j = 0; j < sz; ++j) {
+          const int gm = u >= 0 ? (int)(unit_mem[u * kMaxUnit + j] - lo) : t;
+          int ea, eb;
+          edge_range(gm, ea, eb);
+          for (int e = ea; e < eb; ++e) {
+            const int q = dependant(e);
+            bool rel = false;
+            int tq = 0;
+            if (lvl[q] == 0) {   // members of t's own unit are placed already
+              const int uq = blk_idx[lo + q];
+              tq = uq >= 0 ? (int)(unit_mem[uq * kMaxUnit] - lo) : q;
+              if (cnt_dec(cnt, tq) == 1u) {
+                rel = true;
+                place(tq);
+              }
+            }
+            wave_push16(rel, tq, que, rb, tail, n);
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+      ra = rb;
+      rb += *tail;
+      if (rb > n) return;
+    }
+  }
+  __syncthreads();
+  if (s_placed != n || s_maxlev > kFastLevels) return;   // k_levels does it
+  const int nlev = s_maxlev;
+
+  // ---- stable counting sort by level: wave w takes linear positions
+  // [w R, (w + 1) R)
+  const int R = ((((n + kFastWaves - 1) / kFastWaves) + 63) / 64) * 64;
+  const int wv = tid >> 6, lane = tid & 63;
+  for (int t = tid; t < kFastWaves * nlev; t += 1024) tab[t] = 0;
+  __syncthreads();
+  const int r0 = wv * R, r1 = min(n, r0 + R);
+  for (int g = r0 + lane; g < r1; g += 64) atomicAdd(&tab[wv * nlev + lvl[g] - 1], 1);
+  __syncthreads();
+  for (int l = tid; l < nlev; l += 1024) {
+    int t = 0;
+    for (int w = 0; w < kFastWaves; ++w) t += tab[w * nlev + l];
+    s_tot[l] = t;
+  }
+  __syncthreads();
+  {
+    const int v = tid < nlev ? s_tot[tid] : 0;
+    int64_t tot;
+    const int64_t pre = block_excl_scan<1024>(v, &tot, sh);
+    if (tid < nlev) s_off[tid] = (int)pre;
+    if (tid == 0) s_off[nlev] = (int)tot;
+  }
+  __syncthreads();
+  for (int l = tid; l < nlev; l += 1024) {
+    int run = s_off[l];
+    for (int w = 0; w < kFastWaves; ++w) {
+      const int t = tab[w * nlev + l];
+      tab[w * nlev + l] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  int32_t* __restrict__ lev = L.lev + lo;
+  int32_t* __restrict__ perm = L.perm + lo;
+  for (int c = r0; c < r1; c += 64) {
+    const int g = c + lane;
+    const bool valid = g < r1;
+    const int l = valid ? (int)lvl[g] - 1 : -1;
+    unsigned long long rem = __ballot(valid);
+    int pos = 0;
+    while (rem) {
+      const int leader = __ffsll((long long)rem) - 1;
+      const int l0 = __shfl(l, leader);
+      const bool same = valid && l == l0;
+      const unsigned long long mk = __ballot(same);
+      const int at = tab[wv * nlev + l0];
+      if (same) pos = at + __popcll(mk & ((1ull << lane) - 1ull));
+      __builtin_amdgcn_wave_barrier();
+      if (lane == leader) tab[wv * nlev + l0] = at + __popcll(mk);
+      __builtin_amdgcn_wave_barrier();
+      rem &= ~mk;
+    }
+    if (valid) {
+      lev[g] = l + 1;
+      perm[g] = pos;
+    }
+  }
+  int32_t* lev_off = L.lev_off + (int64_t)ii * (kMaxLevels + 1);
+  for (int l = tid; l <= nlev; l += 1024) lev_off[l] = s_off[l];
+  if (tid == 0) {
+    int maxw = 0;
+    for (int l = 0; l < nlev; ++l) maxw = max(maxw, s_tot[l]);
+    L.info[ii].nlev = nlev;
+    L.info[ii].maxwidth = maxw;
+    L.info[ii].nunits = s_units;
+    L.info[ii].maxunit = s_maxunit;
+    L.info[ii].layered = 1;
+  }
+}
+
 constexpr int kRelU = 4;   // ghosts per thread whose releases are issued together
 constexpr int kRelE = 4;   // their edges loaded up front (the rest, if any, one by one)
 
@@ -225,9 +690,10 @@ constexpr int kRelE = 4;   // their edges loaded up front (the rest, if any, one
 template <bool InLds, bool CurLds>
 __global__ __launch_bounds__(1024) void k_levels(LevelsArgs L) {
   extern __shared__ uint32_t s_dyn[];
-  // after a finished wide layering there is nothing left to do
+  // after a finished wide or LDS layering there is nothing left to do
   if (L.wide && L.wide[0] == 1) return;
   const int ii = blockIdx.x;
+  if (L.info[ii].layered) return;
   const int tid = threadIdx.x;
   const int np = (1 << L.insts[ii].g.dim) - 1;
   const int64_t lo = L.g_off[ii];
@@ -571,6 +1037,34 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
   const int64_t bytes = 4 * (((nn + 3) >> 2) + ((nn + 31) >> 5));
   LevelsArgs F = L;   // the one-workgroup layering
   F.wide = nullptr;
+  if (!(L.wide && ninst == 1)) {
+    // the LDS layering first; k_levels below skips what it finished
+    static int fast_lds = -1;
+    lk.lock();
+    if (fast_lds < 0) {
+      int dev = 0, a = 0, b = 0;
+      (void)hipGetDevice(&dev);
+      if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        a = 0;
+      if (hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
+        b = 0;
+      hipFuncAttributes fa{};
+      int stat = 4096;
+      if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_levels_fast)) == hipSuccess)
+        stat = (int)fa.sharedSizeBytes;
+      (void)hipGetLastError();
+      int v = std::max(0, std::max(a, b) - stat - 256) & ~255;
+      if (v > 0 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_levels_fast),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) {
+        (void)hipGetLastError();
+        v = 0;
+      }
+      fast_lds = v;
+    }
+    const int fl = fast_lds;
+    lk.unlock();
+    if (fl > 0) k_levels_fast<<<ninst, 1024, (size_t)fl, st>>>(L, fl);
+  }
   if (L.wide && ninst == 1) {
     // grid: as many co-resident workgroups as fit, at most one per tile
     static int coop = -1;
