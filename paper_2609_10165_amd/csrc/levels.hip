@@ -298,16 +298,41 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
   int32_t* tab = reinterpret_cast<int32_t*>(base + o);
   o += 4 * (int64_t)kFastWaves * kFastLevels;
   if (o > lds_bytes) return;   // every thread leaves alike
+  // reverse edges, then (used only after a stall) the forward dependencies
+  // as local ids and each ghost's unit slot, each where LDS is left
   int32_t* eoff = reinterpret_cast<int32_t*>(base + o);
   const int64_t o_adj = o + al(4 * ((int64_t)n + 1));
   uint16_t* eadj = reinterpret_cast<uint16_t*>(base + o_adj);
-  const bool elds = o_adj + al(2 * (int64_t)E) <= lds_bytes;
+  const int64_t o_eend = o_adj + al(2 * (int64_t)E);
+  const bool elds = o_eend <= lds_bytes;
+  const int64_t o_dep = elds ? o_eend : o;
+  uint16_t* fdep = reinterpret_cast<uint16_t*>(base + o_dep);
+  const int64_t o_slot = o_dep + al(2 * (int64_t)np * n);
+  uint16_t* uslot = reinterpret_cast<uint16_t*>(base + o_slot);
+  const bool dlds = o_slot + al(2 * (int64_t)n) <= lds_bytes;
+  __shared__ uint16_t s_uhead[kMaxUnits];   // head (smallest member) of each unit
+  __shared__ uint8_t s_usize[kMaxUnits];
   auto edge_range = [&](int g, int& ea, int& eb) {
     ea = elds ? eoff[g] : (int)(roff[g] - e0);
     eb = elds ? eoff[g + 1] : (int)(roff[g + 1] - e0);
   };
   auto dependant = [&](int e) { return elds ? (int)eadj[e] : (int)(radj[e0 + e] - lo); };
-  auto dep = [&](int g, int q) { return deps[(int64_t)q * cap + lo + g]; };   // global id / -1
+  // dependency q of ghost g as a local id, -1 if it reads no ghost there
+  auto dep = [&](int g, int q) -> int {
+    if (dlds) {
+      const int v = fdep[q * n + g];
+      return v == 0xffff ? -1 : v;
+    }
+    const int32_t d = deps[(int64_t)q * cap + lo + g];
+    return d < 0 ? -1 : (int)(d - lo);
+  };
+  auto slot_of = [&](int g) -> int {
+    if (dlds) {
+      const int v = uslot[g];
+      return v == 0xffff ? -1 : v;
+    }
+    return blk_idx[lo + g];
+  };
 
   const int C = (n + 3) >> 2;
   for (int w = tid; w < C; w += 1024) {
@@ -373,6 +398,14 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
   if (b < n) {
     // ---- the ghosts left read a cycle.  Trim those that no unplaced ghost
     // reads (counters: unplaced readers), repeatedly.
+    if (dlds) {
+      for (int t = tid; t < np * n; t += 1024) {
+        const int q = t / n, g = t - q * n;
+        const int32_t d = deps[(int64_t)q * cap + lo + g];
+        fdep[t] = d < 0 ? (uint16_t)0xffff : (uint16_t)(d - lo);
+      }
+      for (int g = tid; g < n; g += 1024) uslot[g] = 0xffff;
+    }
     for (int w = tid; w < C; w += 1024) cnt[w] = 0;
     __syncthreads();
     for (int g = tid; g < n; g += 1024) {
@@ -400,15 +433,11 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
         for (int i = ta + tid; i < tb; i += 1024) {
           const int u = que[i];
           for (int q = 0; q < np; ++q) {
-            const int32_t d = dep(u, q);
+            const int dl = dep(u, q);
             bool rel = false;
-            int dl = 0;
-            if (d >= 0) {
-              dl = (int)(d - lo);
-              if (lvl[dl] == 0 && cnt_dec(cnt, dl) == 1u) {
-                rel = true;
-                lvl[dl] = kTrimmed;
-              }
+            if (dl >= 0 && lvl[dl] == 0 && cnt_dec(cnt, dl) == 1u) {
+              rel = true;
+              lvl[dl] = kTrimmed;
             }
             wave_push16(rel, dl, que, tb, tail, n);
           }
@@ -440,9 +469,9 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
     __syncthreads();
     for (int u = tid; u < m; u += 1024)
       for (int q = 0; q < np; ++q) {
-        const int32_t d = dep(res[u], q);
-        if (d < 0 || lvl[d - lo] != 0) continue;
-        const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
+        const int d = dep(res[u], q);
+        if (d < 0 || lvl[d] != 0) continue;
+        const int v = (int)find_sorted(res, 0, m, d);
         if (v >= 0) reach[u * RW + (v >> 5)] |= 1u << (v & 31);
       }
     __threadfence_block();
@@ -453,9 +482,9 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
       int changed = 0;
       for (int u = tid; u < m; u += 1024)
         for (int q = 0; q < np; ++q) {
-          const int32_t d = dep(res[u], q);
-          if (d < 0 || lvl[d - lo] != 0) continue;
-          const int v = (int)find_sorted(res, 0, m, (int)(d - lo));
+          const int d = dep(res[u], q);
+          if (d < 0 || lvl[d] != 0) continue;
+          const int v = (int)find_sorted(res, 0, m, d);
           if (v < 0) continue;
           for (int w = 0; w < RW; ++w) {
             const uint32_t ow = reach[u * RW + w], nw = ow | reach[v * RW + w];
@@ -512,8 +541,11 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
       const int sl = slot[rp];
       unit_mem[sl * kMaxUnit + rank] = (int32_t)(lo + res[u]);
       blk_idx[lo + res[u]] = sl;
+      if (dlds) uslot[res[u]] = (uint16_t)sl;
       if (u == rp) {
         unit_cnt[sl] = size;
+        s_uhead[sl] = (uint16_t)res[u];
+        s_usize[sl] = (uint8_t)size;
         atomicMax(&s_maxunit, size);
       }
     }
@@ -526,19 +558,19 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
     // ---- the unplaced ghosts and units in dependency order, each at 1 +
     // the highest level it reads (internal edges of a unit excluded)
     auto head_of = [&](int g) {
-      const int u = blk_idx[lo + g];
-      return u >= 0 ? (int)(unit_mem[u * kMaxUnit] - lo) : g;
+      const int u = slot_of(g);
+      return u >= 0 ? (int)s_uhead[u] : g;
     };
     auto place = [&](int t) {   // level of node t, given to its members
-      const int u = blk_idx[lo + t];
-      const int sz = u >= 0 ? unit_cnt[u] : 1;
+      const int u = slot_of(t);
+      const int sz = u >= 0 ? (int)s_usize[u] : 1;
       int mx = 0;
       for (int j = 0; j < sz; ++j) {
         const int gm = u >= 0 ? (int)(unit_mem[u * kMaxUnit + j] - lo) : t;
         for (int q = 0; q < np; ++q) {
-          const int32_t d = dep(gm, q);
-          if (d < 0 || (u >= 0 && blk_idx[d] == u)) continue;
-          mx = max(mx, (int)lvl[d - lo]);
+          const int d = dep(gm, q);
+          if (d < 0 || (u >= 0 && slot_of(d) == u)) continue;
+          mx = max(mx, (int)lvl[d]);
         }
       }
       for (int j = 0; j < sz; ++j) {
@@ -553,11 +585,11 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
     __syncthreads();
     for (int g = tid; g < n; g += 1024) {
       if (lvl[g] != 0) continue;
-      const int u = blk_idx[lo + g];
+      const int u = slot_of(g);
       uint32_t c = 0;
       for (int q = 0; q < np; ++q) {
-        const int32_t d = dep(g, q);
-        if (d < 0 || lvl[d - lo] != 0 || (u >= 0 && blk_idx[d] == u)) continue;
+        const int d = dep(g, q);
+        if (d < 0 || lvl[d] != 0 || (u >= 0 && slot_of(d) == u)) continue;
         ++c;
       }
       if (c) cnt_add(cnt, head_of(g), c);
@@ -579,8 +611,8 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
       int* const tail = &s_cnt[r % 3];
       for (int i = ra + tid; i < rb; i += 1024) {
         const int t = que[i];
-        const int u = blk_idx[lo + t];
-        const int sz = u >= 0 ? unit_cnt[u] : 1;
+        const int u = slot_of(t);
+        const int sz = u >= 0 ? (int)s_usize[u] : 1;
         for (int j = 0; j < sz; ++j) {
           const int gm = u >= 0 ? (int)(unit_mem[u * kMaxUnit + j] - lo) : t;
           int ea, eb;
@@ -590,8 +622,7 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
             bool rel = false;
             int tq = 0;
             if (lvl[q] == 0) {   // members of t's own unit are placed already
-              const int uq = blk_idx[lo + q];
-              tq = uq >= 0 ? (int)(unit_mem[uq * kMaxUnit] - lo) : q;
+              tq = head_of(q);
               if (cnt_dec(cnt, tq) == 1u) {
                 rel = true;
                 place(tq);
