@@ -195,6 +195,7 @@ class BatchStep:
         self.sgrad = [torch.empty((self.dim, n), dtype=torch.float64, device=dev)
                       for n in self.nq for _ in range(self.nf)]
         self.p_field, self.u_first = p_field, u_first
+        self.spec = gcr.BatchSpec(grids, shapes, schemes)   # packed once
         self.bc_fn = bc_fn                   # (pk) -> writes pk["bc"] (and pk["bt"])
         self.packs = [{}, {}]
         self.bc_graph_ok = None
@@ -202,7 +203,7 @@ class BatchStep:
         self.band_segments = 0
 
     def batch(self, stream=None):
-        return self.gcr.Batch(self.grids, self.shapes, self.schemes, stream=stream)
+        return self.gcr.Batch(spec=self.spec, stream=stream)
 
     def pack(self, k, counts):
         pk = self.packs[k]
@@ -292,12 +293,11 @@ class BatchStep:
         B = self.batch()
         if record is not None:
             record.append(self.gcr.last_build_times())
-        pk = self.pack(k, tuple(p.n_ghost for p in B.plans))
+        pk = self.pack(k, B.counts())
         B.foot_points(out=(pk["S"], pk["n"]))
         self.boundary_data(pk)
         B.forward(args=pk["args"])
         self.ghosts = sum(pk["counts"])
-        self.band_segments = B.plans[0].stats()["n_band_segments"]
         return B
 
     def run_threads(self, nsteps, s_fwd, s_builds, nbuild):
@@ -328,7 +328,7 @@ class BatchStep:
                     B, built = item
                     with torch.cuda.stream(s_fwd):
                         s_fwd.wait_event(built)
-                        pk = self.pack(t & 1, tuple(p.n_ghost for p in B.plans))
+                        pk = self.pack(t & 1, B.counts())
                         B.foot_points(stream=s_fwd, out=(pk["S"], pk["n"]))
                         self.boundary_data(pk)
                         B.forward(args=pk["args"], stream=s_fwd)
@@ -381,7 +381,7 @@ class BatchStep:
         torch = self.torch
         with torch.cuda.stream(s_build):
             held = [self.batch(stream=s_build) for _ in range(count)]
-            pk = self.pack(0, tuple(p.n_ghost for p in held[0].plans))
+            pk = self.pack(0, held[0].counts())
             for B in held:
                 B.forward(args=pk["args"], stream=s_build)
         torch.cuda.synchronize()
@@ -475,6 +475,7 @@ def measure_batched(gcr, torch, W, args, s_fwd, s_builds, extra=True):
     torch.cuda.synchronize()
     gcr.set_profiling(False)
     stage_ms = {k: float(np.mean([r[k] for r in rec])) for k in rec[0]}
+    W.band_segments = W.batch().plans[0].stats()["n_band_segments"]
     out = {"ms_per_step": ms_step, "ms_serial": ms_serial, "wall_s": wall,
            "ghosts": W.ghosts, "fwd_ms": fwd_times["forward"], "anchor_ms": fwd_times["anchor"],
            "stage_ms": stage_ms, "band_segments": W.band_segments, "nbuild": nbuild}
@@ -493,14 +494,14 @@ def measure_batched(gcr, torch, W, args, s_fwd, s_builds, extra=True):
 
 def roofline_of(W, m, cells):
     """The step's longest kernel among the batched forward (library events
-    around the launch in the timed steps), the classification store pass and
-    the layering (stage events around each launch), against its
-    algorithmic bytes."""
+    around the launch in the timed steps), the classification store pass
+    (1 byte per cell written) and the layering (stage events around each
+    launch), against its algorithmic bytes."""
     d = W.dim
     npts = sum(W.nq)
     cands = {
         "k_batch_forward": (m["fwd_ms"], forward_bytes(d, W.nf, m["ghosts"], npts)),
-        "k_classify": (m["stage_ms"]["classify_store"], cells - 16 * m["band_segments"]),
+        "k_classify": (m["stage_ms"]["classify_store"], cells),
         "k_levels": (m["stage_ms"]["levels_order"], levels_bytes(d, m["ghosts"])),
     }
     out = {}
@@ -737,7 +738,7 @@ def bench_static(gcr, torch, W, steps):
     for mode, name in ((0, "sweep"), (2, "tiled")):
         gcr.set_batch_tiling(mode)
         B = W.batch()
-        pk = W.pack(0, tuple(p.n_ghost for p in B.plans))
+        pk = W.pack(0, B.counts())
         B.foot_points(out=(pk["S"], pk["n"]))
         W.bc_fn(pk)
         for _ in range(3):
@@ -876,7 +877,7 @@ def bench_large(gcr, torch, synth, reps):
     t = float(np.median(ts))
     c = float(np.median(cls))
     ncell = g.n[0] * g.n[1] * g.n[2]
-    cbytes = ncell - 16 * info["seg"]
+    cbytes = ncell   # the store pass writes every cell's tag
     del fields
     torch.cuda.empty_cache()
     return {"workload": "sphere1024: 1024^3 grid on [-1,1]^3, the 256^3 workload's sphere, HGC, "

@@ -297,6 +297,11 @@ void gcr_batch_destroy(gcr_batch* batch);
 /* Plan of instance i, owned by the batch (valid until gcr_batch_destroy). */
 gcr_status gcr_batch_plan(const gcr_batch* batch, int32_t i,
                           const gcr_plan** out);
+/* Sizes of every instance's plan at once (host copies, no synchronisation):
+ * n_ghost host int64 [ninst] ghosts, n_levels host int32 [ninst] levels of
+ * the dependency graph (Sec. 3.2); either may be NULL. */
+gcr_status gcr_batch_counts(const gcr_batch* batch, int64_t* n_ghost,
+                            int32_t* n_levels);
 
 /* Foot points and normals of every ghost of a batch in one launch, as
  * gcr_plan_foot_points gives them per plan (S = x_c + delta, Sec. 3.1),

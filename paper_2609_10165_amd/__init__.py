@@ -28,7 +28,8 @@ SYMBOLS = [
     "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_set_schedule",
     "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_forces_noalloc", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
-    "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_foot_points",
+    "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_counts",
+    "gcr_batch_foot_points",
     "gcr_batch_forward", "gcr_batch_status",
     "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_set_batch_spin",
     "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering",
@@ -102,6 +103,7 @@ def lib():
         L.gcr_batch_destroy.argtypes = [vp]
         L.gcr_batch_destroy.restype = None
         L.gcr_batch_plan.argtypes = [vp, i32, P(vp)]
+        L.gcr_batch_counts.argtypes = [vp, vp, vp]
         L.gcr_batch_foot_points.argtypes = [vp, vp, vp, vp]
         L.gcr_set_profiling.argtypes = [i32]
         L.gcr_set_batch_tiling.argtypes = [i32]
@@ -354,28 +356,57 @@ class _BatchHandle:
         self.h = None
 
 
-class Batch:
-    """gcr_batch_create: plans of many uneven instances built together."""
+class BatchSpec:
+    """The instances of a batch packed once into the C-ABI's host structs,
+    for building the same kind of batch repeatedly (a static or moving body
+    rebuilt every step) without converting every grid and shape again."""
 
-    def __init__(self, grids, shapes, schemes, stream=None):
-        L = lib()
+    def __init__(self, grids, shapes, schemes):
         n = len(grids)
-        gs = [make_grid(g) for g in grids]   # keeps stretched faces alive for the call
-        G = (_Grid * n)(*gs)
-        keep = [make_shape(s) for s in shapes]
-        S = (_Shape * n)(*[k[0] for k in keep])
-        sch = (ctypes.c_int32 * n)(*[int(s) for s in schemes])
+        self.n = n
+        gs = [make_grid(g) for g in grids]   # keeps stretched faces alive
+        self._keep = ([getattr(g, "_keep", None) for g in gs],
+                      [make_shape(s) for s in shapes])
+        self.G = (_Grid * n)(*gs)
+        self.S = (_Shape * n)(*[k[0] for k in self._keep[1]])
+        self.sch = (ctypes.c_int32 * n)(*[int(s) for s in schemes])
+
+
+class Batch:
+    """gcr_batch_create: plans of many uneven instances built together.
+    `spec` (a BatchSpec) replaces grids, shapes and schemes."""
+
+    def __init__(self, grids=None, shapes=None, schemes=None, stream=None, spec=None):
+        L = lib()
+        if spec is None:
+            spec = BatchSpec(grids, shapes, schemes)
         h = ctypes.c_void_p()
-        _check(L.gcr_batch_create(n, G, S, sch, _stream(stream), ctypes.byref(h)),
-               "gcr_batch_create")
+        _check(L.gcr_batch_create(spec.n, spec.G, spec.S, spec.sch, _stream(stream),
+                                  ctypes.byref(h)), "gcr_batch_create")
         self._owner = _BatchHandle(h)
         self._h = h
-        self.n = n
-        self.plans = []
-        for i in range(n):
-            ph = ctypes.c_void_p()
-            _check(L.gcr_batch_plan(h, i, ctypes.byref(ph)), "gcr_batch_plan")
-            self.plans.append(Plan(None, None, 0, _handle=ph, _owner=self._owner))
+        self.n = spec.n
+        self.dim = int(spec.G[0].dim)
+        self._plans = None
+
+    @property
+    def plans(self):
+        """Plan of every instance (wrappers made on first use)."""
+        if self._plans is None:
+            L = lib()
+            plans = []
+            for i in range(self.n):
+                ph = ctypes.c_void_p()
+                _check(L.gcr_batch_plan(self._h, i, ctypes.byref(ph)), "gcr_batch_plan")
+                plans.append(Plan(None, None, 0, _handle=ph, _owner=self._owner))
+            self._plans = plans
+        return self._plans
+
+    def counts(self):
+        """gcr_batch_counts: ghosts per instance, a tuple of ints."""
+        buf = (ctypes.c_int64 * self.n)()
+        _check(lib().gcr_batch_counts(self._h, buf, None), "gcr_batch_counts")
+        return tuple(buf)
 
     def status(self):
         """gcr_batch_status: waits for the batch's forward launches; raises
@@ -394,8 +425,7 @@ class Batch:
         """gcr_batch_foot_points: (S, normal), each f64 [dim][total ghosts],
         the instances' ghosts one after another (into `out` = (S, normal)
         if given)."""
-        dim = self.plans[0].dim
-        ng = sum(p.n_ghost for p in self.plans)
+        dim, ng = self.dim, sum(self.counts())
         if out is not None:
             S, n = out
             if tuple(S.shape) != (dim, ng) or tuple(n.shape) != (dim, ng):

@@ -759,6 +759,16 @@ gcr_status gcr_batch_plan(const gcr_batch* b, int32_t i, const gcr_plan** out) {
   return GCR_OK;
 }
 
+gcr_status gcr_batch_counts(const gcr_batch* b, int64_t* n_ghost, int32_t* n_levels) {
+  if (!b) return GCR_E_ARG;
+  const int n = (int)b->plans.size();
+  for (int i = 0; i < n; ++i) {
+    if (n_ghost) n_ghost[i] = b->plans[i]->ng;
+    if (n_levels) n_levels[i] = b->plans[i]->nlev;
+  }
+  return GCR_OK;
+}
+
 gcr_status gcr_batch_foot_points(const gcr_batch* b, double* S, double* normal, void* stream) {
   if (!b || !b->data) return GCR_E_ARG;
   const BatchData& D = *b->data;

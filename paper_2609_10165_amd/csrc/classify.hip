@@ -4,10 +4,13 @@
 //
 // Three launches: a pre-pass settles whole 1024-cell spans from bounds on
 // the body (a radial bound, or a Lipschitz bound on the star radius); the
-// store pass writes every settled 16-cell row segment as constant stores and
-// the cells of unsettled segments away from the body, and lists the segments
-// that need an exact test of every cell; the band pass runs those, one wave
-// per segment.
+// store pass writes every cell's solid bit, settling 16-cell row segments
+// by the same bounds where it can and testing the cells of the others (the
+// band) exactly; the interface pass marks the band cells that have a face
+// neighbour of the other class.
+//
+// (Band segments are counted for statistics in kBandStripes counters 64
+// bytes apart, nband[16 s]; their sum is the count.)
 #include <hip/hip_runtime.h>
 
 #include "gcr_impl.hpp"
@@ -33,13 +36,16 @@ __device__ __forceinline__ int star_box(const ShapeD& s, int dim, const double l
   }
   const double rc = sqrt(rc2), hd = sqrt(hd2);
   if (!(rc > 2.0 * hd)) return -1;
-  const double D = asin(hd / rc) * (1.0 + 1e-12) + 1e-15;
+  // D bounds the angle the box subtends, asin(hd / rc): asin(x) / x grows
+  // with x, so below x = 1/2 asin(x) <= x asin(1/2) / (1/2) = (pi / 3) x
+  const double inv = 1.0 / rc;
+  const double D = hd * inv * 1.0472 * (1.0 + 1e-12) + 1e-15;
   double r;
   if (s.kind == kStar2D) {
     double r1;
-    star_r(s, xc[0] / rc, xc[1] / rc, r, r1);
+    star_r(s, xc[0] * inv, xc[1] * inv, r, r1);
   } else {
-    const double u[3] = {xc[0] / rc, xc[1] / rc, xc[2] / rc};
+    const double u[3] = {xc[0] * inv, xc[1] * inv, xc[2] * inv};
     double gr[3];
     sh_r(s, u, r, gr);
   }
@@ -49,10 +55,10 @@ __device__ __forceinline__ int star_box(const ShapeD& s, int dim, const double l
   return -1;
 }
 
-// Whether every point of the box [lo, hi] lies on one side of the boundary:
-// 0 fluid, 1 solid, -1 undecided (radial bounds, then the Lipschitz test).
-__device__ __forceinline__ int box_settled(const ShapeD& s, int dim, const double lo[3],
-                                           const double hi[3]) {
+// Whether every point of the box [lo, hi] lies on one side of the boundary
+// by the radial bounds alone: 0 fluid, 1 solid, -1 undecided.
+__device__ __forceinline__ int box_radial(const ShapeD& s, int dim, const double lo[3],
+                                          const double hi[3]) {
   double dmin2 = 0.0, dmax2 = 0.0;
   for (int a = 0; a < dim; ++a) {
     const double c = s.cull_c[a];
@@ -61,8 +67,18 @@ __device__ __forceinline__ int box_settled(const ShapeD& s, int dim, const doubl
     dmin2 += dl * dl;
     dmax2 += df * df;
   }
-  if (sqrt(dmin2) > s.rmax * (1.0 + 1e-9) + 1e-300) return 0;
-  if (sqrt(dmax2) < s.rmin * (1.0 - 1e-9)) return 1;
+  // on squares: the 1e-9 relative margins dwarf the rounding of either form
+  const double rhi = s.rmax * (1.0 + 1e-9), rlo = s.rmin * (1.0 - 1e-9);
+  if (dmin2 > rhi * rhi + 1e-300) return 0;
+  if (rlo > 0.0 && dmax2 < rlo * rlo) return 1;
+  return -1;
+}
+
+// The same, then the Lipschitz test for star and SH bodies.
+__device__ __forceinline__ int box_settled(const ShapeD& s, int dim, const double lo[3],
+                                           const double hi[3]) {
+  const int r = box_radial(s, dim, lo, hi);
+  if (r >= 0) return r;
   if (s.kind == kStar2D || s.kind == kShStar) return star_box(s, dim, lo, hi);
   return -1;
 }
@@ -81,13 +97,17 @@ __device__ __forceinline__ bool cell_solid(const GridD& g, const ShapeD& s, int 
 __global__ __launch_bounds__(256) void k_spans(const Inst* __restrict__ insts, int ninst,
                                                const int64_t* __restrict__ chunk_start,
                                                int64_t nspan, int8_t* __restrict__ span,
+                                               int32_t* __restrict__ chunk_inst,
                                                int32_t* __restrict__ nband) {
   constexpr int kSpan = 64 * kSeg, kPer = kChunk / kSpan;
   const int64_t sp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sp == 0) nband[0] = 0;   // the band list k_classify appends to starts empty
+  if (sp < kBandStripes) nband[sp * 16] = 0;   // k_band_iface counts from zero
   if (sp >= nspan) return;
   const int64_t chunk = sp / kPer;
   const int ii = find_inst(chunk_start, ninst, chunk);
+  // the chunk's instance, for the passes after this one (one load instead
+  // of a search at the start of each of their workgroups)
+  if (sp % kPer == 0) chunk_inst[chunk] = ii;
   const Inst& I = insts[ii];
   const GridD& g = I.g;
   const int64_t base = (chunk - I.chunk_off) * kChunk + (sp % kPer) * kSpan;
@@ -118,292 +138,248 @@ __global__ __launch_bounds__(256) void k_spans(const Inst* __restrict__ insts, i
   span[sp] = r;
 }
 
-__global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts, int ninst,
-                                                  const int64_t* __restrict__ chunk_start,
+// Whether the nvalid cells of the row segment starting at cell `base` and
+// their face neighbours lie on one side of the boundary (0 fluid, 1 solid,
+// -1 undecided); full: with the Lipschitz test, else radial bounds only.  A
+// segment within one row is one box; one that crosses a row end (or is cut
+// by the grid end) is the tail of its first row and the head of its second,
+// each boxed with its face neighbours, both of which must agree.
+__device__ __forceinline__ int seg_settled(const GridD& g, const ShapeD& S, int base, int nvalid,
+                                           bool full) {
+  int i0, j, k;
+  unlinear(g, base, i0, j, k);
+  if (nvalid == kSeg && i0 + kSeg - 1 < g.n[0]) {
+    double lo[3], hi[3];
+    lo[0] = centre_below(g, 0, i0);
+    hi[0] = centre_above(g, 0, i0 + kSeg - 1);
+    lo[1] = centre_below(g, 1, j);
+    hi[1] = centre_above(g, 1, j);
+    lo[2] = hi[2] = 0.0;
+    if (g.dim == 3) {
+      lo[2] = centre_below(g, 2, k);
+      hi[2] = centre_above(g, 2, k);
+    }
+    return full ? box_settled(S, g.dim, lo, hi) : box_radial(S, g.dim, lo, hi);
+  }
+  // (with rows of 16 cells or more a segment meets at most two rows)
+  if (g.n[0] < kSeg) return -1;
+  int p1[3];
+  unlinear(g, base + nvalid - 1, p1[0], p1[1], p1[2]);
+  const bool one_row = p1[1] == j && p1[2] == k;
+  double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+  const int seg_a[3] = {i0, j, k}, seg_b[3] = {one_row ? p1[0] : g.n[0] - 1, j, k};
+  // (axes unrolled: a runtime index into g would move it to scratch)
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < g.dim) {
+      lo[a] = centre_below(g, a, seg_a[a]);
+      hi[a] = centre_above(g, a, seg_b[a]);
+    }
+  int sa = full ? box_settled(S, g.dim, lo, hi) : box_radial(S, g.dim, lo, hi);
+  if (!one_row && sa >= 0) {
+    const int c0[3] = {0, p1[1], p1[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (a < g.dim) {
+        lo[a] = centre_below(g, a, c0[a]);
+        hi[a] = centre_above(g, a, p1[a]);
+      }
+    const int sb = full ? box_settled(S, g.dim, lo, hi) : box_radial(S, g.dim, lo, hi);
+    if (sb != sa) sa = -1;
+  }
+  return sa;
+}
+
+// nvalid tags of value v (0 or 1) from cell `dst` on
+__device__ __forceinline__ void store_const(int8_t* dst, int nvalid, int v) {
+  if (nvalid == kSeg) {
+    const uint32_t w = v ? 0x01010101u : 0u;
+    *reinterpret_cast<uint4*>(dst) = make_uint4(w, w, w, w);
+  } else {
+    for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)v;
+  }
+}
+
+// The store pass, one workgroup per chunk of kChunk cells, a 16-cell row
+// segment per thread.  A wave whose span the pre-pass settled only stores.
+// Otherwise the work is done densely in three rounds, so that no wave runs
+// an expensive test for a few of its lanes: each lane's segment first meets
+// the radial bounds (cheap); the segments they leave undecided are listed
+// in LDS and, for star and SH bodies, their Lipschitz tests run one segment
+// per thread; the segments still undecided form the chunk's band, whose
+// cells are tested exactly one cell per thread.  Band cells get their solid
+// bit here and their interface mark (a face neighbour of the other class)
+// from k_band_iface; settled segments have none, since their boxes include
+// the face neighbours.  The chunk's band is recorded as a 256-bit mask.
+__global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts,
+                                                  const int32_t* __restrict__ chunk_inst,
                                                   const int8_t* __restrict__ span,
                                                   int8_t* __restrict__ tags,
                                                   int32_t* __restrict__ chunk_cnt,
-                                                  int32_t* __restrict__ band,
-                                                  int32_t* __restrict__ nband) {
+                                                  uint64_t* __restrict__ bandmask) {
   const int64_t chunk = blockIdx.x;
-  const int ii = find_inst(chunk_start, ninst, chunk);
+  const int ii = chunk_inst[chunk];
   const Inst& I = insts[ii];
   const GridD g = I.g;
   const int64_t chunk_off = I.chunk_off, cell_off = I.cell_off;
-  __shared__ int s_cnt, s_band, s_base;
   __shared__ ShapeD sh_s;
+  __shared__ int s_na, s_nb;
+  __shared__ uint8_t s_la[256], s_lb[256];
+  __shared__ unsigned long long s_mask[4];
   static_assert(sizeof(ShapeD) % 8 == 0, "ShapeD copied as doubles");
   constexpr int kSpans = kChunk / (64 * kSeg);
+  const int tid = (int)threadIdx.x;
+  const int64_t cbase = (chunk - chunk_off) * kChunk;
   // a workgroup whose spans are all whole and settled only stores: one round
   // of flag loads, no barrier (most workgroups of a large grid)
   bool need_shape = false;
   int8_t fl[kSpans];
   for (int q = 0; q < kSpans; ++q) {
     fl[q] = span[chunk * kSpans + q];
-    need_shape |= (chunk - chunk_off) * kChunk + (int64_t)(q + 1) * 64 * kSeg > g.ncell ||
-                  fl[q] < 0;
+    need_shape |= cbase + (int64_t)(q + 1) * 64 * kSeg > g.ncell || fl[q] < 0;
   }
   if (!need_shape) {
-    const int8_t f = fl[threadIdx.x >> 6];
-    const uint32_t v = f ? 0x01010101u : 0u;
-    *reinterpret_cast<uint4*>(tags + cell_off + (chunk - chunk_off) * kChunk +
-                              (int64_t)threadIdx.x * kSeg) = make_uint4(v, v, v, v);
-    if (threadIdx.x == 0) chunk_cnt[chunk] = 0;
+    store_const(tags + cell_off + cbase + (int64_t)tid * kSeg, kSeg, fl[tid >> 6]);
+    if (tid < 4) bandmask[chunk * 4 + tid] = 0ull;
+    if (tid == 0) chunk_cnt[chunk] = 0;
     return;
   }
   {
     const double* src = reinterpret_cast<const double*>(&I.s);
     double* dst = reinterpret_cast<double*>(&sh_s);
-    for (int q = (int)threadIdx.x; q < (int)(sizeof(ShapeD) / 8); q += 256) dst[q] = src[q];
+    for (int q = tid; q < (int)(sizeof(ShapeD) / 8); q += 256) dst[q] = src[q];
   }
-  if (threadIdx.x == 0) {
-    s_cnt = 0;
-    s_band = 0;
+  if (tid == 0) {
+    s_na = 0;
+    s_nb = 0;
   }
+  if (tid < 4) s_mask[tid] = 0ull;
   __syncthreads();
   const ShapeD& S = sh_s;
-  const int64_t base64 = (chunk - chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
-  int cnt = 0;
-  // a wave whose span the pre-pass settled only stores (full spans only:
-  // the last, partial span of an instance takes the per-segment path)
-  const int64_t wbase = base64 - (int64_t)(threadIdx.x & 63) * kSeg;
-  const int wset = wbase + 64 * kSeg <= g.ncell ? (int)span[chunk * (kChunk / (64 * kSeg)) +
-                                                             (threadIdx.x >> 6)]
-                                                : -1;
-  int mode = 0;   // 0 no cells or stored here, 1 settled segment, 2 band, 3 cell by cell
+  const bool lip = S.kind == kStar2D || S.kind == kShStar;
+  const int64_t base64 = cbase + (int64_t)tid * kSeg;
+  const int64_t wbase = base64 - (int64_t)(tid & 63) * kSeg;
+  const int wset = wbase + 64 * kSeg <= g.ncell ? (int)fl[tid >> 6] : -1;
+  const bool valid = base64 < g.ncell;
+  const int nvalid = valid ? (int)min((int64_t)kSeg, g.ncell - base64) : 0;
+  // round 1: the wave's span settled, else this lane's radial bounds
   if (wset >= 0) {
-    const uint32_t v = wset ? 0x01010101u : 0u;
-    *reinterpret_cast<uint4*>(tags + cell_off + base64) = make_uint4(v, v, v, v);
-  } else {
-    // per lane: 1 row segment settled by its box, 2 row segment near the
-    // boundary (tested by k_band), 3 segment crossing a row end or the grid
-    // end (cell by cell)
-    const bool valid = base64 < g.ncell;
-    const int base = valid ? (int)base64 : 0;
-    const int nvalid = valid ? (int)min((int64_t)kSeg, g.ncell - base64) : 0;
-    int i0 = 0, j = 0, k = 0, settled = -1;
-    if (valid) {
-      unlinear(g, base, i0, j, k);
-      if (nvalid == kSeg && i0 + kSeg - 1 < g.n[0]) {
-        // radial culling on the segment's box (face neighbours included)
-        double lo[3], hi[3];
-        lo[0] = centre_below(g, 0, i0);
-        hi[0] = centre_above(g, 0, i0 + kSeg - 1);
-        lo[1] = centre_below(g, 1, j);
-        hi[1] = centre_above(g, 1, j);
-        lo[2] = hi[2] = 0.0;
-        if (g.dim == 3) {
-          lo[2] = centre_below(g, 2, k);
-          hi[2] = centre_above(g, 2, k);
-        }
-        settled = box_settled(S, g.dim, lo, hi);
-        mode = settled >= 0 ? 1 : 2;
-      } else {
-        // a segment crossing a row end (or cut by the grid end): the tail of
-        // its first row and the head of its second, each boxed with its
-        // face neighbours, usually settle it too (both sides must agree)
-        int p1[3];
-        unlinear(g, base + nvalid - 1, p1[0], p1[1], p1[2]);
-        const bool one_row = p1[1] == j && p1[2] == k;
-        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
-        int seg_a[3] = {i0, j, k}, seg_b[3] = {one_row ? p1[0] : g.n[0] - 1, j, k};
-        // (axes unrolled: a runtime index into g would move it to scratch)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-          if (a < g.dim) {
-            lo[a] = centre_below(g, a, seg_a[a]);
-            hi[a] = centre_above(g, a, seg_b[a]);
-          }
-        // (with rows of 16 cells or more a segment meets at most two rows)
-        int sa = g.n[0] >= kSeg ? box_settled(S, g.dim, lo, hi) : -1;
-        if (!one_row && sa >= 0) {
-          const int c0[3] = {0, p1[1], p1[2]};
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-            if (a < g.dim) {
-              lo[a] = centre_below(g, a, c0[a]);
-              hi[a] = centre_above(g, a, p1[a]);
-            }
-          if (box_settled(S, g.dim, lo, hi) != sa) sa = -1;
-        }
-        settled = sa;
-        mode = settled >= 0 ? 1 : 3;
-      }
-    }
-    if (valid) {
-      uint8_t t[kSeg];
-      if (mode == 1) {
-        for (int b = 0; b < nvalid; ++b) t[b] = (uint8_t)settled;
-      } else if (mode == 2) {
-        for (int b = 0; b < kSeg; ++b) t[b] = 0;   // written by k_band
-      } else {
-        for (int b = 0; b < nvalid; ++b) {
-          int c = base + b, i, jj, kk;
-          unlinear(g, c, i, jj, kk);
-          bool sd = cell_solid(g, S, i, jj, kk);
-          bool iface = false;
-          int q[3] = {i, jj, kk};
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-            for (int sg = -1; sg <= 1 && a < g.dim && !iface; sg += 2) {
-              int qq[3] = {q[0], q[1], q[2]};
-              qq[a] += sg;
-              if (qq[a] < 0 || qq[a] >= g.n[a]) continue;
-              if (cell_solid(g, S, qq[0], qq[1], qq[2]) != sd) {
-                iface = true;
-                break;
-              }
-            }
-          t[b] = (uint8_t)((sd ? 1 : 0) | (iface ? 0x40 : 0));
-          cnt += iface;
-        }
-      }
-      int8_t* dst = tags + cell_off + base;
-      if (mode == 2) {
-        // k_band writes these 16 cells
-      } else if (nvalid == kSeg) {
-        uint4 w;
-        w.x = t[0] | (t[1] << 8) | (t[2] << 16) | ((uint32_t)t[3] << 24);
-        w.y = t[4] | (t[5] << 8) | (t[6] << 16) | ((uint32_t)t[7] << 24);
-        w.z = t[8] | (t[9] << 8) | (t[10] << 16) | ((uint32_t)t[11] << 24);
-        w.w = t[12] | (t[13] << 8) | (t[14] << 16) | ((uint32_t)t[15] << 24);
-        *reinterpret_cast<uint4*>(dst) = w;
-      } else {
-        for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)t[b];
-      }
+    store_const(tags + cell_off + base64, kSeg, wset);
+  } else if (valid) {
+    const int r = seg_settled(g, S, (int)base64, nvalid, false);
+    if (r >= 0) store_const(tags + cell_off + base64, nvalid, r);
+    else if (lip) s_la[atomicAdd(&s_na, 1)] = (uint8_t)tid;
+    else s_lb[atomicAdd(&s_nb, 1)] = (uint8_t)tid;
+  }
+  __syncthreads();
+  // round 2: the Lipschitz tests of the undecided segments, one per thread
+  for (int t = tid; t < s_na; t += 256) {
+    const int l = s_la[t];
+    const int64_t b = cbase + (int64_t)l * kSeg;
+    const int nv = (int)min((int64_t)kSeg, g.ncell - b);
+    const int r = seg_settled(g, S, (int)b, nv, true);
+    if (r >= 0) store_const(tags + cell_off + b, nv, r);
+    else s_lb[atomicAdd(&s_nb, 1)] = (uint8_t)l;
+  }
+  __syncthreads();
+  // round 3: every cell of the band segments, one per thread (solid bit)
+  const int nb = s_nb;
+  for (int t = tid; t < nb * kSeg; t += 256) {
+    const int l = s_lb[t / kSeg], o = t % kSeg;
+    const int64_t c = cbase + (int64_t)l * kSeg + o;
+    if (o == 0) atomicOr(&s_mask[l >> 6], 1ull << (l & 63));
+    if (c >= g.ncell) continue;
+    int i, j, k;
+    unlinear(g, (int)c, i, j, k);
+    tags[cell_off + c] = cell_solid(g, S, i, j, k) ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid < 4) bandmask[chunk * 4 + tid] = s_mask[tid];
+  if (tid == 0) chunk_cnt[chunk] = 0;
+}
+
+// Interface marks of the band cells, one workgroup per chunk (chunks
+// without band segments leave at once): a band cell is marked when a face
+// neighbour in the grid has the other solid bit; the chunk's count goes to
+// chunk_cnt, and its band segments to one of the striped counters.
+__global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ insts,
+                                                    const int32_t* __restrict__ chunk_inst,
+                                                    const uint64_t* __restrict__ bandmask,
+                                                    int8_t* __restrict__ tags,
+                                                    int32_t* __restrict__ chunk_cnt,
+                                                    int32_t* __restrict__ nband) {
+  const int64_t chunk = blockIdx.x;
+  unsigned long long m[4];
+  int tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    m[w] = bandmask[chunk * 4 + w];
+    tot += __popcll(m[w]);
+  }
+  if (tot == 0) return;
+  const int tid = (int)threadIdx.x;
+  __shared__ uint8_t s_l[256];
+  __shared__ int s_cnt;
+  {
+    // rank of this thread's segment among the chunk's band segments
+    const int w = tid >> 6, b = tid & 63;
+    if ((m[w] >> b) & 1ull) {
+      int pos = __popcll(m[w] & ((1ull << b) - 1ull));
+      for (int q = 0; q < w; ++q) pos += __popcll(m[q]);
+      s_l[pos] = (uint8_t)tid;
     }
   }
-  // near-boundary row segments go to the band list (k_band tests them with
-  // a whole wave each): positions within the workgroup from an LDS counter,
-  // one global atomic per workgroup; every thread reaches the barriers
-  {
-    const uint64_t bm = __ballot(mode == 2);
-    const int lane = (int)(threadIdx.x & 63);
-    int wofs = 0;
-    if (bm && lane == 0) wofs = atomicAdd(&s_band, __popcll(bm));
-    wofs = __shfl(wofs, 0);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_band > 0) s_base = atomicAdd(nband, s_band);
-    __syncthreads();
-    if (mode == 2)
-      band[s_base + wofs + __popcll(bm & ((1ull << lane) - 1))] =
-          (int32_t)(chunk * (kChunk / kSeg) + threadIdx.x);
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+  const int ii = chunk_inst[chunk];
+  const Inst& I = insts[ii];
+  const GridD g = I.g;
+  const int64_t cell_off = I.cell_off;
+  const int64_t cbase = (chunk - I.chunk_off) * kChunk;
+  const int8_t* T = tags + cell_off;   // written below too (own cell only)
+  int cnt = 0;
+  for (int t = tid; t < tot * kSeg; t += 256) {
+    const int64_t c = cbase + (int64_t)s_l[t / kSeg] * kSeg + t % kSeg;
+    if (c >= g.ncell) continue;
+    int i, j, k;
+    unlinear(g, (int)c, i, j, k);
+    const int self = T[c] & 1;
+    bool iface = false;
+    if (i > 0) iface |= (T[c - 1] & 1) != self;
+    if (i + 1 < g.n[0]) iface |= (T[c + 1] & 1) != self;
+    const int64_t sy = g.n[0];
+    if (j > 0) iface |= (T[c - sy] & 1) != self;
+    if (j + 1 < g.n[1]) iface |= (T[c + sy] & 1) != self;
+    if (g.dim == 3) {
+      const int64_t sz = sy * g.n[1];
+      if (k > 0) iface |= (T[c - sz] & 1) != self;
+      if (k + 1 < g.n[2]) iface |= (T[c + sz] & 1) != self;
+    }
+    if (iface) {
+      tags[cell_off + c] = (int8_t)(self | 0x40);
+      ++cnt;
+    }
   }
   if (cnt) atomicAdd(&s_cnt, cnt);
   __syncthreads();
-  if (threadIdx.x == 0) chunk_cnt[chunk] = s_cnt;
-}
-
-constexpr unsigned kBandWaves = 16384;   // workgroups of k_band (one wave each)
-
-// Near-boundary row segments listed by k_classify, one wave each: the 82
-// cells a segment needs (own row with both ends, rows j-1, j+1, k-1, k+1)
-// spread over the lanes (t = 0..17 own row from i0 - 1, t = 18 + 16 r + o row
-// r at i0 + o), two ballots, then lane 0 forms the segment's tags and
-// interface marks.  Cells off the grid read as fluid in the own row; a whole
-// neighbour row off the grid stands for the segment itself, since a face
-// without a neighbour cannot make an interface.  Every wave leaves its loop
-// once the list is exhausted.
-__global__ __launch_bounds__(64) void k_band(const Inst* __restrict__ insts, int ninst,
-                                             const int64_t* __restrict__ chunk_start,
-                                             const int32_t* __restrict__ band,
-                                             const int32_t* __restrict__ nband,
-                                             int8_t* __restrict__ tags,
-                                             int32_t* __restrict__ chunk_cnt) {
-  __shared__ ShapeD sh_s;
-  static_assert(sizeof(ShapeD) % 8 == 0, "ShapeD copied as doubles");
-  const int lane = (int)threadIdx.x;
-  const int nb = nband[0];
-  int cached = -1;
-  for (int b = (int)blockIdx.x; b < nb; b += (int)gridDim.x) {
-    const int32_t seg = band[b];
-    const int64_t chunk = seg / (kChunk / kSeg);
-    const int ii = find_inst(chunk_start, ninst, chunk);
-    const Inst& I = insts[ii];
-    if (ii != cached) {   // uniform: one wave per workgroup
-      __syncthreads();
-      const double* src = reinterpret_cast<const double*>(&I.s);
-      double* dst = reinterpret_cast<double*>(&sh_s);
-      for (int q = lane; q < (int)(sizeof(ShapeD) / 8); q += 64) dst[q] = src[q];
-      __syncthreads();
-      cached = ii;
-    }
-    const ShapeD& S = sh_s;
-    const GridD g = I.g;
-    const int64_t cell_off = I.cell_off;
-    const int base = (int)((chunk - I.chunk_off) * kChunk + (int64_t)(seg % (kChunk / kSeg)) * kSeg);
-    int i0, j, k;
-    unlinear(g, base, i0, j, k);
-    bool r[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int t = lane + 64 * q;
-      bool v = false;
-      if (t < kSeg + 2 + 4 * kSeg) {
-        int ci = i0, cj = j, ck = k, rr = -1;
-        if (t < kSeg + 2) {
-          ci = i0 - 1 + t;
-        } else {
-          rr = (t - (kSeg + 2)) / kSeg;
-          ci = i0 + (t - (kSeg + 2)) % kSeg;
-          if (rr == 0) cj = j - 1;
-          else if (rr == 1) cj = j + 1;
-          else if (rr == 2) ck = k - 1;
-          else ck = k + 1;
-        }
-        const bool in = ci >= 0 && ci < g.n[0] && cj >= 0 && cj < g.n[1] &&
-                        (g.dim == 3 ? (ck >= 0 && ck < g.n[2]) : rr < 2);
-        if (in) v = cell_solid(g, S, ci, cj, ck);
-      }
-      r[q] = v;
-    }
-    const uint64_t m0 = __ballot(r[0]), m1 = __ballot(r[1]);
-    if (lane == 0) {
-      constexpr uint32_t M = (1u << kSeg) - 1;
-      uint32_t row = (uint32_t)(m0 & ((1ull << (kSeg + 2)) - 1));   // i0-1 .. i0+16
-      if (i0 == 0) row = (row & ~1u) | ((row >> 1) & 1u);
-      if (i0 + kSeg >= g.n[0]) row = (row & ~(1u << (kSeg + 1))) | (((row >> kSeg) & 1u) << (kSeg + 1));
-      const uint32_t self = (row >> 1) & M;
-      uint32_t diff = (self ^ (row & M)) | (self ^ ((row >> 2) & M));
-      uint32_t rjm = (uint32_t)(m0 >> 18) & M, rjp = (uint32_t)(m0 >> 34) & M;
-      uint32_t rkm = (uint32_t)((m0 >> 50) | (m1 << 14)) & M, rkp = (uint32_t)(m1 >> 2) & M;
-      if (j - 1 < 0) rjm = self;
-      if (j + 1 >= g.n[1]) rjp = self;
-      diff |= (self ^ rjm) | (self ^ rjp);
-      if (g.dim == 3) {
-        if (k - 1 < 0) rkm = self;
-        if (k + 1 >= g.n[2]) rkp = self;
-        diff |= (self ^ rkm) | (self ^ rkp);
-      }
-      uint32_t w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-          const int c = 4 * q + bb;
-          v |= (((self >> c) & 1u) | (((diff >> c) & 1u) << 6)) << (8 * bb);
-        }
-        w[q] = v;
-      }
-      *reinterpret_cast<uint4*>(tags + cell_off + base) = make_uint4(w[0], w[1], w[2], w[3]);
-      if (diff) atomicAdd(&chunk_cnt[chunk], __popc(diff));
-    }
+  if (tid == 0) {
+    chunk_cnt[chunk] += s_cnt;
+    atomicAdd(&nband[(chunk % kBandStripes) * 16], tot);
   }
 }
 
 
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
-                     int8_t* span, int8_t* tags, int32_t* chunk_cnt, int32_t* band,
-                     int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store, hipStream_t st) {
+                     int8_t* span, int32_t* chunk_inst, int8_t* tags, int32_t* chunk_cnt,
+                     int32_t* band, int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store,
+                     hipStream_t st) {
   const int64_t nspan = chunks * (kChunk / (64 * kSeg));
+  uint64_t* mask = reinterpret_cast<uint64_t*>(band);   // [chunks][4]
   k_spans<<<(unsigned)((nspan + 255) / 256), 256, 0, st>>>(insts, ninst, chunk_start, nspan,
-                                                           span, nband);
+                                                           span, chunk_inst, nband);
   if (ev_prepass) (void)hipEventRecord(ev_prepass, st);
-  k_classify<<<(unsigned)chunks, 256, 0, st>>>(insts, ninst, chunk_start, span, tags, chunk_cnt,
-                                                band, nband);
+  k_classify<<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask);
   if (ev_store) (void)hipEventRecord(ev_store, st);
-  k_band<<<kBandWaves, 64, 0, st>>>(insts, ninst, chunk_start, band, nband, tags, chunk_cnt);
+  k_band_iface<<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt, nband);
 }
 
 }  // namespace gcr

@@ -16,6 +16,9 @@ constexpr int kMaxUnits = 1024;   // coupled units per instance
 constexpr int kMaxLevels = 1024;  // levels per instance
 constexpr int kChunk = 4096;      // cells per classification workgroup
 constexpr int kSeg = 16;          // cells per classification thread
+// the band-segment count (statistics) accumulates in this many counters, one
+// per 64-byte line, so that chunks add to different addresses
+constexpr int kBandStripes = 64;
 constexpr int kMaxResidual = 1024;// ghosts left after plain Kahn layering
 
 // error bits, reported per instance

@@ -78,7 +78,8 @@ struct BatchData {
   int8_t* d_span = nullptr;          // [chunks * 4] settled flag of each wave's span
   int32_t* d_chunk_list = nullptr;   // chunks holding interface cells, ascending
   int32_t* d_nchunk_list = nullptr;
-  int32_t* d_band = nullptr;         // near-boundary row segments (k_band)
+  int32_t* d_band = nullptr;         // band masks of the chunks (classification scratch)
+  int32_t* d_chunk_inst = nullptr;   // instance of each chunk
   int32_t* d_nband = nullptr;        // their number
   int64_t* d_scan_tmp = nullptr;     // tile totals of the long chunk scan
   int64_t* d_iface_off = nullptr;    // interface cells per instance (second layer)
@@ -171,12 +172,14 @@ int64_t wide_layering_min();
 gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
 
 // Classification of every cell of a batch into tags (0 fluid, 1 solid, 0x40
-// interface mark) and per-chunk interface counts.  ev_prepass / ev_store
+// interface mark) and per-chunk interface counts; chunk_inst [chunks]
+// receives each chunk's instance, band [chunks][8] is scratch.  ev_prepass / ev_store
 // (either may be null) are recorded after the span pre-pass and after the
 // store pass.
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
-                     int8_t* span, int8_t* tags, int32_t* chunk_cnt, int32_t* band,
-                     int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store, hipStream_t st);
+                     int8_t* span, int32_t* chunk_inst, int8_t* tags, int32_t* chunk_cnt,
+                     int32_t* band, int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store,
+                     hipStream_t st);
 
 // instance holding global index x of a batch: the last i with off[i] <= x
 __device__ __forceinline__ int find_inst(const int64_t* off, int ninst, int64_t x) {

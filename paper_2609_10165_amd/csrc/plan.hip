@@ -544,8 +544,8 @@ __global__ void k_gather_off(const int64_t* __restrict__ excl, const int64_t* __
   if (i <= n) off[i] = excl[start[i]];
 }
 
-__global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ insts, int ninst,
-                                                       const int64_t* __restrict__ chunk_start,
+__global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ insts,
+                                                       const int32_t* __restrict__ chunk_inst,
                                                        const int8_t* __restrict__ tags,
                                                        const int32_t* __restrict__ chunk_cnt,
                                                        const int64_t* __restrict__ chunk_excl,
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(256) void k_compact_iface(const Inst* __restrict__ 
     htab[z] = ~0ull;
   const int64_t chunk = chunk_list[blockIdx.x];   // chunks holding listed cells
   __shared__ int64_t sh[5];
-  const int ii = find_inst(chunk_start, ninst, chunk);
+  const int ii = chunk_inst[chunk];
   const Inst& I = insts[ii];
   const int64_t base64 = (chunk - I.chunk_off) * kChunk + (int64_t)threadIdx.x * kSeg;
   uint32_t mask = 0;
@@ -1297,8 +1297,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   const size_t o_lo = o_go + al(8 * (ninst + 1));
   const size_t o_ul = o_lo + al(4 * (size_t)ninst * (kMaxLevels + 1));
   const size_t o_if = o_ul + al(4 * (size_t)ninst * kMaxUnits);
-  const size_t o_nl = o_if + al(8 * (ninst + 1));
-  const size_t o_io = o_nl + al(8);
+  const size_t o_nl = o_if + al(8 * (ninst + 1));   // chunk-list count, band stripes
+  const size_t o_io = o_nl + al(64 + 64 * kBandStripes);
   const size_t o_ho = o_io + al(8 * (ninst + 1));
   const size_t o_hm = o_ho + al(8 * (ninst + 1));
   const size_t stage_bytes = o_hm + al(4 * ninst);
@@ -1312,7 +1312,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_unit_lev = reinterpret_cast<int32_t*>(tb + o_ul);
   D.d_if_off = reinterpret_cast<int64_t*>(tb + o_if);
   D.d_nchunk_list = reinterpret_cast<int32_t*>(tb + o_nl);
-  D.d_nband = reinterpret_cast<int32_t*>(tb + o_nl + 4);
+  D.d_nband = reinterpret_cast<int32_t*>(tb + o_nl + 64);
   D.d_iface_off = reinterpret_cast<int64_t*>(tb + o_io);
   D.d_hoff = reinterpret_cast<int64_t*>(tb + o_ho);
   D.d_hmask = reinterpret_cast<uint32_t*>(tb + o_hm);
@@ -1320,14 +1320,16 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_chunk_cnt = own<int32_t>(D, chunks);
   D.d_span = own<int8_t>(D, chunks * (kChunk / (64 * kSeg)));
   D.d_chunk_list = own<int32_t>(D, chunks);
-  D.d_band = own<int32_t>(D, chunks * (kChunk / kSeg));   // every segment at most once
+  D.d_band = own<int32_t>(D, chunks * 8);   // band mask of each chunk (4 x 64 bits)
+  D.d_chunk_inst = own<int32_t>(D, chunks);
   D.d_chunk_excl = own<int64_t>(D, chunks + 1);
   D.d_scan_tmp = own<int64_t>(D, (chunks + kScanTile - 1) / kScanTile + 1);
   D.d_unit_mem = own<int32_t>(D, (size_t)ninst * kMaxUnits * kMaxUnit);
   D.d_unit_cnt = own<int32_t>(D, (size_t)ninst * kMaxUnits);
   D.d_reach = own<uint32_t>(D, (size_t)ninst * kMaxResidual * (kMaxResidual / 32));
   if (!D.d_tags || !D.d_chunk_cnt || !D.d_chunk_excl || !D.d_scan_tmp || !D.d_span ||
-      !D.d_chunk_list || !D.d_band || !D.d_unit_mem || !D.d_unit_cnt || !D.d_reach)
+      !D.d_chunk_list || !D.d_band || !D.d_chunk_inst || !D.d_unit_mem || !D.d_unit_cnt ||
+      !D.d_reach)
     return GCR_E_NOMEM;
   bool any_layer2 = false, any_2d = false;
   for (int i = 0; i < ninst; ++i) {
@@ -1346,8 +1348,8 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
 
   StageEvents T((g_profiling.load() & 1) != 0);
   T.mark(0, st);
-  launch_classify(D.d_inst, ninst, D.d_chunk_start, chunks, D.d_span, D.d_tags, D.d_chunk_cnt,
-                  D.d_band, D.d_nband, T.event(10), T.event(11), st);
+  launch_classify(D.d_inst, ninst, D.d_chunk_start, chunks, D.d_span, D.d_chunk_inst, D.d_tags,
+                  D.d_chunk_cnt, D.d_band, D.d_nband, T.event(10), T.event(11), st);
   T.mark(1, st);
   launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
               D.d_scan_tmp, st);
@@ -1376,7 +1378,11 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   if (any_layer2) std::memcpy(D.iface_off.data(), PS.p + o_io, 8 * (ninst + 1));
   int32_t nlist = 0, nband = 0;
   std::memcpy(&nlist, PS.p + o_nl, sizeof(int32_t));
-  std::memcpy(&nband, PS.p + o_nl + 4, sizeof(int32_t));
+  for (int q = 0; q < kBandStripes; ++q) {
+    int32_t v = 0;
+    std::memcpy(&v, PS.p + o_nl + 64 + 64 * q, sizeof(int32_t));
+    nband += v;
+  }
   D.nband = nband;
   const int64_t nif = D.if_off[ninst];
   const int64_t cap = std::max<int64_t>(nif, 1);
@@ -1441,7 +1447,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
 
   T.mark(3, st);
   if (nif > 0) {
-    k_compact_iface<<<(unsigned)nlist, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
+    k_compact_iface<<<(unsigned)nlist, 256, 0, st>>>(D.d_inst, D.d_chunk_inst, D.d_tags,
                                                      D.d_chunk_cnt, D.d_chunk_excl, D.d_chunk_list,
                                                      D.d_if_cell, D.d_htab, D.hoff[ninst]);
     T.mark(4, st);
