@@ -792,10 +792,14 @@ def bench_layer2(gcr, torch, synth, reps):
 
 def bench_moving(gcr, torch, synth, reps):
     """The 256^3 sphere moving by 0.4 h per step (HGC with a second ghost
-    layer, so that the cells the move exposes were ghosts before): per step
-    a new plan at the new position, its fresh cells against the previous
-    plan, boundary data, fill of u, v, w, p and force.  Every step's fresh
-    cells must all be covered."""
+    layer, so that the cells the move exposes were ghosts before), two ways:
+    full, a new plan at each position; incremental, two plans updated in
+    turn (gcr_plan_update, each from two positions back), which classify
+    again only the chunks the move can change.  Per step: the plan, its
+    fresh cells against the previous position's plan, boundary data, fill
+    of u, v, w, p and force.  Every step's fresh cells must be covered.
+    Then the re-plan alone (plan + fresh cells) on the 1024^3 grid, where
+    the classification of every cell is bandwidth-scale."""
     inst = synth.sphere256(seed=0)
     g, h = inst.grid, inst.grid.h[0]
     fields = [_dev(torch, synth.sample(f, g), torch.float64) for f in inst.fields]
@@ -804,28 +808,73 @@ def bench_moving(gcr, torch, synth, reps):
     xq, nq, wq = (_dev(torch, a) for a in (q.x, q.n, q.w))
     F = torch.empty(3, dtype=torch.float64, device="cuda")
     step_v = 0.4 * h * np.array([0.8, 0.48, 0.36])   # |v| = 0.4 h
-    state = {"k": 0, "prev": None, "counts": []}
+    scheme = 2 | 4
 
-    def step():
-        k = state["k"]
-        state["k"] += 1
-        c = tuple(float(x) for x in np.asarray(inst.shape.center) + k * step_v)
-        plan = gcr.Plan(g, synth.Shape(inst.shape.kind, c, inst.shape.r0), 2 | 4)
-        if state["prev"] is not None:
-            _, counts = state["prev"].fresh_cells(plan)
-            state["counts"].append(counts)
-        S, nrm = plan.foot_points()
-        plan.fill(fields, kinds, list(bc_sphere_fields(S, nrm)))
-        plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
-        state["prev"] = plan
+    def shape_at(sh, k, v):
+        c = tuple(float(x) for x in np.asarray(sh.center) + k * v)
+        return synth.Shape(sh.kind, c, sh.r0)
 
-    t, _, _ = timed_steps(torch, step, reps)
-    counts = torch.stack(state["counts"]).cpu().numpy()
-    return {"workload": "sphere256 moving 0.4 h per step, HGC with a second ghost layer: "
-                        "plan at the new position + fresh cells against the previous plan + "
-                        "fill of u,v,w,p + force",
-            "step_ms": round(t, 4), "fresh_per_step": int(counts[:, 0].mean()),
-            "uncovered_total": int(counts[:, 1].sum()), "steps_checked": int(len(counts))}
+    def run(mode, grid, sh, v, physics, nsteps):
+        state = {"k": 0, "plans": [], "counts": []}
+        replan = []
+
+        def step():
+            k = state["k"]
+            state["k"] += 1
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            if mode == "full" or len(state["plans"]) < 2:
+                plan = gcr.Plan(grid, shape_at(sh, k, v), scheme)
+                state["plans"].append(plan)
+            else:
+                plan = state["plans"][-2].update(shape_at(sh, k, v))
+                state["plans"].append(plan)
+            prev = state["plans"][-2] if len(state["plans"]) > 1 else None
+            if prev is not None:
+                _, counts = prev.fresh_cells(plan)
+                state["counts"].append(counts)
+            t1.record()
+            del state["plans"][:-2]
+            if physics:
+                S, nrm = plan.foot_points()
+                plan.fill(fields, kinds, list(bc_sphere_fields(S, nrm)))
+                plan.forces(xq, nq, wq, fields[3], fields[:3], 1.0, out=F)
+            replan.append((t0, t1))
+
+        for _ in range(2):   # both plans of the turn exist before timing
+            step()
+        replan.clear()
+        t, p10, p90 = timed_steps(torch, step, nsteps)
+        torch.cuda.synchronize()
+        rp = float(np.median([a.elapsed_time(b) for a, b in replan]))
+        counts = torch.stack(state["counts"][1:]).cpu().numpy()
+        return {"step_ms": round(t, 4), "step_p10_ms": round(p10, 4),
+                "step_p90_ms": round(p90, 4), "replan_ms": round(rp, 4),
+                "fresh_per_step": int(counts[:, 0].mean()),
+                "uncovered_total": int(counts[:, 1].sum()), "steps": int(len(counts))}
+
+    out = {"workload": "sphere256 moving 0.4 h per step, HGC with a second ghost layer: "
+                       "plan at the new position (full build, or an update of the plan two "
+                       "positions back) + fresh cells against the previous position's plan + "
+                       "boundary data + fill of u,v,w,p + force; replan_ms: plan + fresh "
+                       "cells alone"}
+    for mode in ("full", "incremental"):
+        out[mode] = run(mode, g, inst.shape, step_v, True, reps)
+    out["incremental_over_full"] = round(out["full"]["step_ms"] / out["incremental"]["step_ms"], 3)
+    del fields
+    big = synth.sphere256(seed=0, n=1024)
+    hb = big.grid.h[0]
+    vb = 0.4 * hb * np.array([0.8, 0.48, 0.36])
+    out["sphere1024"] = {"workload": "sphere1024 (1.07e9 cells) moving 0.4 h per step, HGC with "
+                                     "a second ghost layer: plan + fresh cells"}
+    for mode in ("full", "incremental"):
+        r = run(mode, big.grid, big.shape, vb, False, max(4, reps // 2))
+        out["sphere1024"][mode] = {k: r[k] for k in ("replan_ms", "fresh_per_step",
+                                                      "uncovered_total", "steps")}
+    out["sphere1024"]["incremental_over_full"] = round(
+        out["sphere1024"]["full"]["replan_ms"] / out["sphere1024"]["incremental"]["replan_ms"], 3)
+    return out
 
 
 def bench_large(gcr, torch, synth, reps):

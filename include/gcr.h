@@ -149,6 +149,29 @@ gcr_status gcr_plan_create(const gcr_grid* grid, const gcr_shape* shape,
  * then still counts interface cells only.) */
 void gcr_plan_destroy(gcr_plan* plan);
 
+/* Re-plan after the body moved (Sec. 7.1: a moving boundary; the plan of
+ * Secs. 3.1-3.2 at the new position).  plan: made by gcr_plan_create (a
+ * plan of a batch: GCR_E_UNSUPPORTED); shape: the body at its new position
+ * or of a new form, any kind valid on the plan's grid; grid, scheme and
+ * second layer stay.  The result equals gcr_plan_create with the same grid,
+ * shape and scheme, array for array.  The plan's tag array is updated in
+ * place: a chunk of 4096 cells is classified again only when one of its
+ * 1024-cell spans was not settled on one side of the old boundary, is not
+ * settled on one side of the new one, or changed side, or when it holds a
+ * ghost of the old plan; every other chunk keeps its tags (its cells and
+ * their face neighbours lie on the same side of both boundaries).  Ghosts,
+ * dependencies, levels, units and the lookup tables are rebuilt from the
+ * new tags; caches of the old plan (ghost weights, adjoint stencils, tuned
+ * schedule) are dropped.  Synchronises `stream` twice, as gcr_plan_create;
+ * work on other streams that reads the plan must be complete.  For the
+ * fresh cells of a move keep the plan of the previous position alive: two
+ * plans updated in turn, each from two positions back, give
+ * gcr_plan_fresh_cells(previous, updated).  On error the plan is as it was
+ * before the call (rebuilt at the old position if the update had begun),
+ * except if that rebuild fails too (GCR_E_NOMEM): then every call on it
+ * but gcr_plan_destroy returns GCR_E_ARG. */
+gcr_status gcr_plan_update(gcr_plan* plan, const gcr_shape* shape, void* stream);
+
 /* Host copy of the plan's sizes and statistics. */
 gcr_status gcr_plan_stats(const gcr_plan* plan, gcr_stats* out);
 

@@ -25,7 +25,8 @@ SPHERE, STAR2D, SHSTAR, AIRFOIL = 0, 1, 2, 3
 SCHED_AUTO, SCHED_LEVELS, SCHED_WORKGROUP, SCHED_GRAPH = 0, 1, 2, 3
 SYMBOLS = [
     "gcr_plan_create", "gcr_plan_destroy", "gcr_plan_stats", "gcr_plan_level_offsets",
-    "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_set_schedule",
+    "gcr_plan_export", "gcr_plan_foot_points", "gcr_plan_fresh_cells", "gcr_plan_update",
+    "gcr_set_schedule",
     "gcr_fill", "gcr_surface_ghost", "gcr_surface",
     "gcr_forces", "gcr_forces_noalloc", "gcr_surface_adjoint", "gcr_forces_adjoint", "gcr_fill_adjoint",
     "gcr_batch_create", "gcr_batch_destroy", "gcr_batch_plan", "gcr_batch_counts",
@@ -90,6 +91,7 @@ def lib():
         L.gcr_plan_export.argtypes = [vp] + [vp] * 8 + [vp]
         L.gcr_plan_foot_points.argtypes = [vp, vp, vp, vp]
         L.gcr_plan_fresh_cells.argtypes = [vp, vp, vp, vp, i64, vp]
+        L.gcr_plan_update.argtypes = [vp, P(_Shape), vp]
         L.gcr_set_schedule.argtypes = [vp, i32, i32]
         L.gcr_fill.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.gcr_surface_ghost.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -205,11 +207,25 @@ class Plan:
             self._h = h
         st = _Stats()
         _check(L.gcr_plan_stats(self._h, ctypes.byref(st)), "gcr_plan_stats")
+        self._sizes(st)
+
+    def _sizes(self, st):
         self.dim = st.dim
         self.n_cells = st.n_cells
         self.n_ghost = st.n_ghost
         self.n_levels = st.n_levels
         self.n_interface = st.n_interface
+
+    def update(self, shape, stream=None):
+        """gcr_plan_update: the plan re-made in place for the body `shape`
+        (same grid and scheme), classifying again only the chunks the move
+        can change."""
+        s, keep = make_shape(shape)
+        _check(lib().gcr_plan_update(self._h, ctypes.byref(s), _stream(stream)), "gcr_plan_update")
+        st = _Stats()
+        _check(lib().gcr_plan_stats(self._h, ctypes.byref(st)), "gcr_plan_stats")
+        self._sizes(st)
+        return self
 
     def __del__(self, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)

@@ -619,7 +619,7 @@ extern "C" {
 gcr_status gcr_surface_adjoint(const gcr_plan* plan, int64_t nq, const double* xq, int32_t nf,
                                const double* gval, const double* ggrad, double* const* lam,
                                void* stream) {
-  if (!plan || nq < 0 || (nq > 0 && !xq) || !nonnull(nf, (const void* const*)lam))
+  if (!plan_ok(plan) || nq < 0 || (nq > 0 && !xq) || !nonnull(nf, (const void* const*)lam))
     return GCR_E_ARG;
   if (nq >= (int64_t(1) << 31)) return GCR_E_UNSUPPORTED;
   return surface_adjoint_impl(const_cast<gcr_plan*>(plan), nq, xq, nf, gval, ggrad, lam,
@@ -629,7 +629,7 @@ gcr_status gcr_surface_adjoint(const gcr_plan* plan, int64_t nq, const double* x
 gcr_status gcr_forces_adjoint(const gcr_plan* plan, int64_t nq, const double* xq,
                               const double* nrm, const double* wq, double mu, const double* gF,
                               double* lam_p, double* const* lam_u, void* stream) {
-  if (!plan || nq < 0 || !gF || !lam_p || !lam_u) return GCR_E_ARG;
+  if (!plan_ok(plan) || nq < 0 || !gF || !lam_p || !lam_u) return GCR_E_ARG;
   if (nq > 0 && (!xq || !nrm || !wq)) return GCR_E_ARG;
   const int d = plan->dim;
   for (int a = 0; a < d; ++a)
@@ -651,7 +651,7 @@ gcr_status gcr_forces_adjoint(const gcr_plan* plan, int64_t nq, const double* xq
 gcr_status gcr_fill_adjoint(const gcr_plan* plan, int32_t nf, double* const* lam,
                             const int32_t* bc_kind, const uint8_t* const* bc_type,
                             double* const* lam_bc, void* stream) {
-  if (!plan || !nonnull(nf, (const void* const*)lam) || !bc_kind ||
+  if (!plan_ok(plan) || !nonnull(nf, (const void* const*)lam) || !bc_kind ||
       !nonnull(nf, (const void* const*)lam_bc))
     return GCR_E_ARG;
   gcr_plan* p = const_cast<gcr_plan*>(plan);

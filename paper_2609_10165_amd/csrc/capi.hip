@@ -475,8 +475,46 @@ void gcr_plan_destroy(gcr_plan* plan) {
   delete plan;
 }
 
+gcr_status gcr_plan_update(gcr_plan* p, const gcr_shape* shape, void* stream) {
+  if (!plan_ok(p) || !shape) return GCR_E_ARG;
+  // a plan made alone, not a view of a batch (whose other plans share its arrays)
+  if (!p->batch || p->batch->ninst != 1 || p->batch.use_count() != 1) return GCR_E_UNSUPPORTED;
+  const hipStream_t st = (hipStream_t)stream;
+  std::shared_ptr<BatchData> nb;
+  gcr_status s = build_update(*p->batch, *shape, true, st, &nb);
+  const gcr_status result = s;
+  if (s != GCR_OK) {
+    if (p->batch->d_tags) return s;   // failed before the tags were taken: plan unchanged
+    // the previous tags are partly rewritten: build the plan as it was
+    s = build_update(*p->batch, p->inst.s, false, st, &nb);
+    if (s != GCR_OK) {
+      p->dead = true;
+      p->batch.reset();
+      return result;
+    }
+  }
+  // the build synchronised the stream: the previous plan's arrays are idle
+  // on it.  Caches derived from the ghosts go with them.
+  for (int i = 0; i < kScratchSlots; ++i) {
+    if (p->scr[i]) pool_free(p->scr[i]);
+    p->scr[i] = nullptr;
+    p->scr_bytes[i] = 0;
+  }
+  if (p->sup) pool_free(p->sup);
+  p->sup = nullptr;
+  p->sup_bound = 0;
+  p->sup_hmask = 0;
+  if (p->wts) pool_free(p->wts);
+  p->wts = nullptr;
+  p->wts_ok[0] = p->wts_ok[1] = false;
+  p->graph.reset();
+  p->tuned = -1;
+  make_plan_view(nb, 0, p);
+  return result;
+}
+
 gcr_status gcr_plan_stats(const gcr_plan* p, gcr_stats* out) {
-  if (!p || !out) return GCR_E_ARG;
+  if (!plan_ok(p) || !out) return GCR_E_ARG;
   std::memset(out, 0, sizeof(*out));
   out->dim = p->dim;
   out->n_levels = p->nlev;
@@ -499,7 +537,7 @@ gcr_status gcr_plan_stats(const gcr_plan* p, gcr_stats* out) {
 }
 
 gcr_status gcr_plan_level_offsets(const gcr_plan* p, int32_t* out) {
-  if (!p || !out) return GCR_E_ARG;
+  if (!plan_ok(p) || !out) return GCR_E_ARG;
   std::memcpy(out, p->lev_off.data(), sizeof(int32_t) * (p->nlev + 1));
   return GCR_OK;
 }
@@ -507,7 +545,7 @@ gcr_status gcr_plan_level_offsets(const gcr_plan* p, int32_t* out) {
 gcr_status gcr_plan_export(const gcr_plan* p, int8_t* tags, int32_t* cell, int32_t* level,
                            double* delta, double* normal, double* psi, int32_t* r,
                            int32_t* unit, void* stream) {
-  if (!p) return GCR_E_ARG;
+  if (!plan_ok(p)) return GCR_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t ng = p->ng;
   if (tags) GCR_HIP(hipMemcpyAsync(tags, p->tags, p->ncell, hipMemcpyDeviceToDevice, st));
@@ -530,7 +568,7 @@ gcr_status gcr_plan_export(const gcr_plan* p, int8_t* tags, int32_t* cell, int32
 }
 
 gcr_status gcr_plan_foot_points(const gcr_plan* p, double* S, double* normal, void* stream) {
-  if (!p) return GCR_E_ARG;
+  if (!plan_ok(p)) return GCR_E_ARG;
   if (p->ng == 0 || (!S && !normal)) return GCR_OK;
   const int ng = (int)p->ng;
   const double* d2 = p->dim == 3 ? p->delta[2] : p->delta[0];
@@ -542,7 +580,7 @@ gcr_status gcr_plan_foot_points(const gcr_plan* p, double* S, double* normal, vo
 }
 
 gcr_status gcr_set_schedule(gcr_plan* p, int32_t schedule, int32_t param) {
-  if (!p || schedule < 0 || schedule > 3 || param != 0) return GCR_E_ARG;
+  if (!plan_ok(p) || schedule < 0 || schedule > 3 || param != 0) return GCR_E_ARG;
   p->schedule = schedule;
   return GCR_OK;
 }
@@ -550,7 +588,7 @@ gcr_status gcr_set_schedule(gcr_plan* p, int32_t schedule, int32_t param) {
 gcr_status gcr_fill(const gcr_plan* plan, int32_t nf, double* const* fields,
                     const int32_t* bc_kind, const uint8_t* const* bc_type,
                     const double* const* bc_val, void* stream) {
-  if (!plan) return GCR_E_ARG;
+  if (!plan_ok(plan)) return GCR_E_ARG;
   FillArgs A;
   gcr_status s = make_fill_args(plan, nf, fields, bc_kind, bc_type, bc_val, &A);
   if (s != GCR_OK) return s;
@@ -575,7 +613,7 @@ gcr_status gcr_fill(const gcr_plan* plan, int32_t nf, double* const* fields,
 
 gcr_status gcr_surface_ghost(const gcr_plan* p, int32_t nf, const double* const* fields,
                              double* val, double* grad, void* stream) {
-  if (!p || !check_fields(nf, (const void* const*)fields)) return GCR_E_ARG;
+  if (!plan_ok(p) || !check_fields(nf, (const void* const*)fields)) return GCR_E_ARG;
   SurfArgs S;
   std::memset(&S, 0, sizeof(S));
   S.P = plan_view(p);
@@ -591,7 +629,7 @@ gcr_status gcr_surface_ghost(const gcr_plan* p, int32_t nf, const double* const*
 gcr_status gcr_surface(const gcr_plan* p, int64_t nq, const double* xq, int32_t nf,
                        const double* const* fields, double* val, double* grad, int32_t* anchor,
                        void* stream) {
-  if (!p || nq < 0 || (nq > 0 && !xq) || !check_fields(nf, (const void* const*)fields))
+  if (!plan_ok(p) || nq < 0 || (nq > 0 && !xq) || !check_fields(nf, (const void* const*)fields))
     return GCR_E_ARG;
   if (nq >= (int64_t(1) << 31)) return GCR_E_UNSUPPORTED;
   SurfArgs S;
@@ -610,7 +648,7 @@ gcr_status gcr_surface(const gcr_plan* p, int64_t nq, const double* xq, int32_t 
 gcr_status gcr_forces(const gcr_plan* p, int64_t nq, const double* xq, const double* nrm,
                       const double* wq, const double* pf, const double* const* u, double mu,
                       double* F, void* stream) {
-  if (!p || nq < 0 || !F || !pf || !u) return GCR_E_ARG;
+  if (!plan_ok(p) || nq < 0 || !F || !pf || !u) return GCR_E_ARG;
   if (nq > 0 && (!xq || !nrm || !wq)) return GCR_E_ARG;
   for (int a = 0; a < p->dim; ++a)
     if (!u[a]) return GCR_E_ARG;
@@ -669,7 +707,7 @@ extern "C" {
 gcr_status gcr_forces_noalloc(const gcr_plan* p, int64_t nq, const double* xq,
                               const double* nrm, const double* wq, const double* pf,
                               const double* const* u, double mu, double* F, void* stream) {
-  if (!p || nq < 0 || !F || !pf || !u) return GCR_E_ARG;
+  if (!plan_ok(p) || nq < 0 || !F || !pf || !u) return GCR_E_ARG;
   if (nq > 0 && (!xq || !nrm || !wq)) return GCR_E_ARG;
   for (int a = 0; a < p->dim; ++a)
     if (!u[a]) return GCR_E_ARG;

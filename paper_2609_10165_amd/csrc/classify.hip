@@ -13,6 +13,8 @@
 // bytes apart, nband[16 s]; their sum is the count.)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gcr_impl.hpp"
 
 namespace gcr {
@@ -211,13 +213,12 @@ __device__ __forceinline__ void store_const(int8_t* dst, int nvalid, int v) {
 // bit here and their interface mark (a face neighbour of the other class)
 // from k_band_iface; settled segments have none, since their boxes include
 // the face neighbours.  The chunk's band is recorded as a 256-bit mask.
-__global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts,
-                                                  const int32_t* __restrict__ chunk_inst,
-                                                  const int8_t* __restrict__ span,
-                                                  int8_t* __restrict__ tags,
-                                                  int32_t* __restrict__ chunk_cnt,
-                                                  uint64_t* __restrict__ bandmask) {
-  const int64_t chunk = blockIdx.x;
+__device__ __forceinline__ void classify_chunk(int64_t chunk, const Inst* __restrict__ insts,
+                                               const int32_t* __restrict__ chunk_inst,
+                                               const int8_t* __restrict__ span,
+                                               int8_t* __restrict__ tags,
+                                               int32_t* __restrict__ chunk_cnt,
+                                               uint64_t* __restrict__ bandmask) {
   const int ii = chunk_inst[chunk];
   const Inst& I = insts[ii];
   const GridD g = I.g;
@@ -298,17 +299,38 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
   if (tid == 0) chunk_cnt[chunk] = 0;
 }
 
+// One workgroup per chunk, or (List) workgroups striding over the chunks
+// listed in list[0, *nlist) (an incremental re-plan's dirty chunks).
+template <bool List>
+__global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts,
+                                                  const int32_t* __restrict__ chunk_inst,
+                                                  const int8_t* __restrict__ span,
+                                                  int8_t* __restrict__ tags,
+                                                  int32_t* __restrict__ chunk_cnt,
+                                                  uint64_t* __restrict__ bandmask,
+                                                  const int32_t* __restrict__ list,
+                                                  const int32_t* __restrict__ nlist) {
+  if (!List) {
+    classify_chunk(blockIdx.x, insts, chunk_inst, span, tags, chunk_cnt, bandmask);
+    return;
+  }
+  const int nit = nlist[0];
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    classify_chunk(list[it], insts, chunk_inst, span, tags, chunk_cnt, bandmask);
+    __syncthreads();   // the LDS lists are reused by the next chunk
+  }
+}
+
 // Interface marks of the band cells, one workgroup per chunk (chunks
 // without band segments leave at once): a band cell is marked when a face
 // neighbour in the grid has the other solid bit; the chunk's count goes to
 // chunk_cnt, and its band segments to one of the striped counters.
-__global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ insts,
-                                                    const int32_t* __restrict__ chunk_inst,
-                                                    const uint64_t* __restrict__ bandmask,
-                                                    int8_t* __restrict__ tags,
-                                                    int32_t* __restrict__ chunk_cnt,
-                                                    int32_t* __restrict__ nband) {
-  const int64_t chunk = blockIdx.x;
+__device__ __forceinline__ void band_iface_chunk(int64_t chunk, const Inst* __restrict__ insts,
+                                                 const int32_t* __restrict__ chunk_inst,
+                                                 const uint64_t* __restrict__ bandmask,
+                                                 int8_t* __restrict__ tags,
+                                                 int32_t* __restrict__ chunk_cnt,
+                                                 int32_t* __restrict__ nband) {
   unsigned long long m[4];
   int tot = 0;
   for (int w = 0; w < 4; ++w) {
@@ -367,19 +389,98 @@ __global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ ins
   }
 }
 
+template <bool List>
+__global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ insts,
+                                                    const int32_t* __restrict__ chunk_inst,
+                                                    const uint64_t* __restrict__ bandmask,
+                                                    int8_t* __restrict__ tags,
+                                                    int32_t* __restrict__ chunk_cnt,
+                                                    int32_t* __restrict__ nband,
+                                                    const int32_t* __restrict__ list,
+                                                    const int32_t* __restrict__ nlist) {
+  if (!List) {
+    band_iface_chunk(blockIdx.x, insts, chunk_inst, bandmask, tags, chunk_cnt, nband);
+    return;
+  }
+  const int nit = nlist[0];
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    band_iface_chunk(list[it], insts, chunk_inst, bandmask, tags, chunk_cnt, nband);
+    __syncthreads();   // s_l and s_cnt are reused by the next chunk
+  }
+}
+
+// --------------------------------------------------------------------------
+// 2. incremental re-plan of a moved body
+// --------------------------------------------------------------------------
+
+// A chunk keeps its tags across a move when each of its spans was settled
+// before and is settled to the same class after: then every cell of it and
+// every face neighbour lies on that side of both boundaries, so the cell's
+// class is unchanged and it is no interface cell either time.  Those tags
+// are its settled value unless a ghost of the previous plan lies there (a
+// second-layer ghost can sit in a settled solid span), which
+// k_dirty_ghosts catches.  One thread per chunk: dirty[c] = 1 for a chunk
+// to classify again; a clean chunk gets no interface cells and no band.
+__global__ __launch_bounds__(256) void k_dirty(const int8_t* __restrict__ span0,
+                                               const int8_t* __restrict__ span1, int64_t chunks,
+                                               int32_t* __restrict__ dirty,
+                                               int32_t* __restrict__ chunk_cnt,
+                                               uint64_t* __restrict__ bandmask) {
+  constexpr int kPer = kChunk / (64 * kSeg);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= chunks) return;
+  bool d = false;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int8_t a = span0[c * kPer + q], b = span1[c * kPer + q];
+    d = d || b < 0 || a != b;
+  }
+  dirty[c] = d ? 1 : 0;
+  if (!d) {
+    chunk_cnt[c] = 0;
+    for (int w = 0; w < 4; ++w) bandmask[c * 4 + w] = 0ull;
+  }
+}
+
+// the chunks of the previous plan's ghosts (a single instance from chunk 0)
+__global__ __launch_bounds__(256) void k_dirty_ghosts(const int32_t* __restrict__ cell,
+                                                      int64_t ng, int32_t* __restrict__ dirty) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ng) dirty[cell[e] / kChunk] = 1;   // every writer stores 1
+}
+
 
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
                      int8_t* span, int32_t* chunk_inst, int8_t* tags, int32_t* chunk_cnt,
                      int32_t* band, int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store,
-                     hipStream_t st) {
+                     hipStream_t st, const ClassifyUpdate* U) {
   const int64_t nspan = chunks * (kChunk / (64 * kSeg));
   uint64_t* mask = reinterpret_cast<uint64_t*>(band);   // [chunks][4]
   k_spans<<<(unsigned)((nspan + 255) / 256), 256, 0, st>>>(insts, ninst, chunk_start, nspan,
                                                            span, chunk_inst, nband);
   if (ev_prepass) (void)hipEventRecord(ev_prepass, st);
-  k_classify<<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask);
+  if (!U) {
+    k_classify<false><<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt,
+                                                        mask, nullptr, nullptr);
+    if (ev_store) (void)hipEventRecord(ev_store, st);
+    k_band_iface<false><<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, mask, tags,
+                                                          chunk_cnt, nband, nullptr, nullptr);
+    return;
+  }
+  // a re-plan: the dirty chunks, listed in ascending order, are classified
+  // by a grid that strides over the list (its length stays on the device)
+  k_dirty<<<(unsigned)((chunks + 255) / 256), 256, 0, st>>>(U->span_prev, span, chunks, U->dirty,
+                                                            chunk_cnt, mask);
+  if (U->ng_prev > 0)
+    k_dirty_ghosts<<<(unsigned)((U->ng_prev + 255) / 256), 256, 0, st>>>(U->ghost_prev,
+                                                                         U->ng_prev, U->dirty);
+  launch_scan(U->dirty, chunks, U->scan_excl, U->list, U->nlist, U->scan_tmp, st);
+  const unsigned G = (unsigned)std::min<int64_t>(chunks, kListGrid);
+  k_classify<true><<<G, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask, U->list,
+                                      U->nlist);
   if (ev_store) (void)hipEventRecord(ev_store, st);
-  k_band_iface<<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt, nband);
+  k_band_iface<true><<<G, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt, nband, U->list,
+                                        U->nlist);
 }
 
 }  // namespace gcr

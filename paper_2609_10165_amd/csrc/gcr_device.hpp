@@ -374,6 +374,26 @@ __device__ __forceinline__ void star_r(const ShapeD& s, double ux, double uy, do
   r1 = s.r0 * d;
 }
 
+// The same with r'' (d^2 r / d theta^2 = -r0 sum k^2 (A_k cos k theta +
+// B_k sin k theta)).
+__device__ __forceinline__ void star_r2(const ShapeD& s, double ux, double uy, double& r,
+                                        double& r1, double& r2) {
+  double ck = 1.0, sk = 0.0, sum = 1.0, d = 0.0, dd = 0.0;
+  for (int k = 0; k < s.ncoef; ++k) {
+    double A = s.coef[2 * k], B = s.coef[2 * k + 1];
+    sum += A * ck + B * sk;
+    d += (double)k * (B * ck - A * sk);
+    dd -= (double)(k * k) * (A * ck + B * sk);
+    double nc = ck * ux - sk * uy;
+    double ns = ck * uy + sk * ux;
+    ck = nc;
+    sk = ns;
+  }
+  r = s.r0 * sum;
+  r1 = s.r0 * d;
+  r2 = s.r0 * dd;
+}
+
 // SH radius and its gradient on the unit sphere (tangential) at direction u.
 // Y_lm = N_lm P~_l^|m|(u_z) {Re,Im}((u_x + i u_y)^|m|) with P~_l^m = d^m P_l/dt^m;
 // coef[] holds a_lm N_lm.

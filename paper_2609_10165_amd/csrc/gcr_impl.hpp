@@ -81,6 +81,9 @@ struct BatchData {
   int32_t* d_band = nullptr;         // band masks of the chunks (classification scratch)
   int32_t* d_chunk_inst = nullptr;   // instance of each chunk
   int32_t* d_nband = nullptr;        // their number
+  int32_t* d_dirty = nullptr;        // re-plan: chunks classified again (flags, then list)
+  int32_t* d_dirty_list = nullptr;
+  int32_t* d_ndirty = nullptr;
   int64_t* d_scan_tmp = nullptr;     // tile totals of the long chunk scan
   int64_t* d_iface_off = nullptr;    // interface cells per instance (second layer)
   int64_t* d_chunk_excl = nullptr;
@@ -176,10 +179,28 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
 // receives each chunk's instance, band [chunks][8] is scratch.  ev_prepass / ev_store
 // (either may be null) are recorded after the span pre-pass and after the
 // store pass.
+//
+// With U (a re-plan of a single instance whose tags hold the previous
+// plan's): only the chunks the move can change are classified again, those
+// with a span unsettled now or settled differently before, and those
+// holding a ghost of the previous plan; they are listed in U->list[0,
+// *U->nlist), ascending, and flagged in U->dirty [chunks].
+struct ClassifyUpdate {
+  const int8_t* span_prev;     // [chunks * 4] the previous plan's span flags
+  const int32_t* ghost_prev;   // [ng_prev] the previous plan's ghost cells
+  int64_t ng_prev;
+  int32_t* dirty;              // [chunks]
+  int32_t* list;               // [chunks]
+  int32_t* nlist;              // [1]
+  int64_t* scan_excl;          // [chunks + 1] scan scratch
+  int64_t* scan_tmp;           // scan tile totals
+};
+constexpr int kListGrid = 2048;   // workgroups striding over a chunk list
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
                      int8_t* span, int32_t* chunk_inst, int8_t* tags, int32_t* chunk_cnt,
                      int32_t* band, int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store,
-                     hipStream_t st);
+                     hipStream_t st, const ClassifyUpdate* U = nullptr);
+
 
 // instance holding global index x of a batch: the last i with off[i] <= x
 __device__ __forceinline__ int find_inst(const int64_t* off, int ninst, int64_t x) {
@@ -211,6 +232,7 @@ struct gcr_plan {
   std::vector<int32_t> lev_off;   // host [nlev+1]
   // device views
   int8_t* tags = nullptr;
+  const int8_t* span = nullptr;     // span flags of the plan's chunks (4 a chunk)
   int32_t* cell = nullptr;
   double* delta[3] = {nullptr, nullptr, nullptr};
   double* nrm[3] = {nullptr, nullptr, nullptr};
@@ -241,8 +263,13 @@ struct gcr_plan {
   int64_t sup_bound = 0;
   uint32_t sup_hmask = 0;
   std::unique_ptr<gcr::GraphCache> graph;
+  // set when a re-plan failed and the plan could not be rebuilt as it was:
+  // every call but destroy then returns GCR_E_ARG
+  bool dead = false;
   ~gcr_plan();
 };
+
+inline bool plan_ok(const gcr_plan* p) { return p && !p->dead; }
 
 namespace gcr {
 // Cached ghost weights of plan p for the kinds used (capi.hip).
@@ -262,6 +289,14 @@ namespace gcr {
 
 gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes,
                        const int32_t* schemes, hipStream_t st, std::shared_ptr<BatchData>* out);
+// A plan of prev's single instance (same grid, scheme and second layer) for
+// the body `shape`.  incremental: prev's tags are taken over (prev is left
+// without them, so it can no longer serve a plan) and only the chunks the
+// move can change are classified again; else a full build.
+gcr_status build_update(BatchData& prev, const gcr_shape& shape, bool incremental,
+                        hipStream_t st, std::shared_ptr<BatchData>* out);
+gcr_status build_update(BatchData& prev, const ShapeD& shape, bool incremental, hipStream_t st,
+                        std::shared_ptr<BatchData>* out);
 void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p);
 void set_profiling(int mask);
 int profiling_mask();   // bit 0 build stages, bit 1 batched forward

@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
   __shared__ int64_t sh[8];
   __shared__ int s_hist[kWideLevels];
   __shared__ int s_wc[4][kWideLevels];
+  if (L.info[0].layered) return;   // the LDS layering finished it (every workgroup leaves)
 
   // counters of ghosts read, four per word; no ghost is in a unit
   for (int64_t w = gt; w < C; w += GT) {
@@ -219,8 +220,9 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
 
 // ---------------------------------------------------------------------------
 // Layering in LDS.  One workgroup per instance keeps the byte counters of
-// unplaced ghosts read, each ghost's level and a Kahn queue in LDS, and the
-// instance's reverse edges too when they fit: level k is the queue segment
+// unplaced ghosts read, each ghost's level and a Kahn queue in LDS (the
+// queue in HBM when only the rest fits), and the instance's reverse edges
+// too when they fit: level k is the queue segment
 // its predecessor level released, so a level costs one pass over its own
 // ghosts' reverse edges and one barrier.
 //
@@ -291,12 +293,18 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
   o += al(4 * (int64_t)((n + 3) >> 2));
   uint16_t* lvl = reinterpret_cast<uint16_t*>(base + o);
   o += al(2 * (int64_t)n);
-  uint16_t* que = reinterpret_cast<uint16_t*>(base + o);
-  o += al(2 * (int64_t)n);
+  // the release queue: in LDS when it fits beside the rank table, else in the
+  // instance's slice of listA (HBM, 2 bytes a ghost of its 4), which leaves
+  // 3 bytes a ghost in LDS
+  constexpr int64_t kTab = 4 * (int64_t)kFastWaves * kFastLevels;
+  const bool qlds = o + al(2 * (int64_t)n) + kTab <= lds_bytes;
+  uint16_t* que = qlds ? reinterpret_cast<uint16_t*>(base + o)
+                       : reinterpret_cast<uint16_t*>(L.listA + lo);
+  if (qlds) o += al(2 * (int64_t)n);
   // [kFastWaves][kFastLevels] rank counts; before that the cycle search's
   // residual list, representatives and unit slots (3 x kMaxResidual)
   int32_t* tab = reinterpret_cast<int32_t*>(base + o);
-  o += 4 * (int64_t)kFastWaves * kFastLevels;
+  o += kTab;
   if (o > lds_bytes) return;   // every thread leaves alike
   // reverse edges, then (used only after a stall) the forward dependencies
   // as local ids and each ghost's unit slot, each where LDS is left
@@ -1068,8 +1076,10 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
   const int64_t bytes = 4 * (((nn + 3) >> 2) + ((nn + 31) >> 5));
   LevelsArgs F = L;   // the one-workgroup layering
   F.wide = nullptr;
-  if (!(L.wide && ninst == 1)) {
-    // the LDS layering first; k_levels below skips what it finished
+  {
+    // the LDS layering first (an instance that fits it is layered there even
+    // when the wide layering is armed); k_levels_wide and k_levels below
+    // skip what it finished
     static int fast_lds = -1;
     lk.lock();
     if (fast_lds < 0) {

@@ -80,6 +80,34 @@ __device__ bool project(const ShapeD& s, int dim, const double x[3], bool solid,
     double q0 = w0[0] + a * t0[0], q1 = w0[1] + a * t0[1];
     double nv = sqrt(q0 * q0 + q1 * q1);
     double u0 = q0 / nv, u1 = q1 / nv, r, r1;
+    if (!ok) {
+      // Gauss-Newton leaves out the curvature term, so it crawls (or
+      // wanders) where the point is nearly as deep as the boundary's radius
+      // of curvature: a second-layer candidate inside a tight bend.  Newton
+      // on the polar angle from where it stopped, with that term (f = |X -
+      // x|^2 / 2, f' = R.X', f'' = X'.X' + R.X''), taking the Gauss-Newton
+      // step wherever f'' is not positive.
+      double th = atan2(u1, u0);
+      good = 0;
+      last = 1.0;
+      for (int it = 0; it < 60 && good < 2; ++it) {
+        double sn, cs, r2;
+        sincos(th, &sn, &cs);
+        star_r2(s, cs, sn, r, r1, r2);
+        const double D1x = r1 * cs - r * sn, D1y = r1 * sn + r * cs;
+        const double D2x = (r2 - r) * cs - 2.0 * r1 * sn, D2y = (r2 - r) * sn + 2.0 * r1 * cs;
+        const double Rx = s.c[0] + r * cs - x[0], Ry = s.c[1] + r * sn - x[1];
+        const double g1 = Rx * D1x + Ry * D1y;
+        double g2 = D1x * D1x + D1y * D1y + Rx * D2x + Ry * D2y;
+        if (!(g2 > 0.0)) g2 = D1x * D1x + D1y * D1y;
+        const double dth = -g1 / g2;
+        th += dth;
+        last = fabs(dth);
+        good = last < 1e-15 ? good + 1 : 0;
+      }
+      ok = good >= 2 || last < 1e-13;
+      sincos(th, &u1, &u0);
+    }
     star_r(s, u0, u1, r, r1);
     S[0] = s.c[0] + r * u0;
     S[1] = s.c[1] + r * u1;
@@ -337,7 +365,10 @@ void launch_scan(const int32_t* cnt, int64_t n, int64_t* excl, int32_t* list,
 // fluid cells): cells whose centre was solid before the move (tag 1 or 2)
 // and is fluid after it (tag 0 or -2); uncovered ones were not ghosts before
 // (tag 1), so no value was ever reconstructed there.  One workgroup per
-// chunk of 4096 cells, 16 per thread (tag arrays are 256-byte aligned).
+// chunk of 4096 cells, 16 per thread (tag arrays are 256-byte aligned).  A
+// chunk whose spans both plans settled to the same class holds no fresh
+// cell (each of its cells lies on that side of both boundaries) and is
+// skipped on its span flags alone.
 __global__ void k_fresh_zero(int64_t* counts) {
   if (threadIdx.x < 2) counts[threadIdx.x] = 0;
 }
@@ -366,11 +397,29 @@ __device__ __forceinline__ uint32_t fresh_bits(const int8_t* __restrict__ a,
   return m;
 }
 
+__device__ __forceinline__ bool spans_agree(const int8_t* __restrict__ sa,
+                                            const int8_t* __restrict__ sb, int64_t chunk) {
+  constexpr int kPer = kChunk / (64 * kSeg);
+  bool same = true;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int8_t x = sa[chunk * kPer + q];
+    same = same && x >= 0 && x == sb[chunk * kPer + q];
+  }
+  return same;
+}
+
 __global__ __launch_bounds__(256) void k_fresh_count(const int8_t* __restrict__ a,
-                                                     const int8_t* __restrict__ b, int64_t n,
+                                                     const int8_t* __restrict__ b,
+                                                     const int8_t* __restrict__ sa,
+                                                     const int8_t* __restrict__ sb, int64_t n,
                                                      int32_t* __restrict__ chunk_cnt,
                                                      int64_t* __restrict__ counts) {
   __shared__ int s_cnt, s_unc;
+  if (spans_agree(sa, sb, blockIdx.x)) {   // uniform over the workgroup
+    if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = 0;
+    return;
+  }
   if (threadIdx.x == 0) s_cnt = s_unc = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kSeg;
@@ -387,10 +436,13 @@ __global__ __launch_bounds__(256) void k_fresh_count(const int8_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_fresh_scatter(const int8_t* __restrict__ a,
-                                                       const int8_t* __restrict__ b, int64_t n,
+                                                       const int8_t* __restrict__ b,
+                                                       const int8_t* __restrict__ sa,
+                                                       const int8_t* __restrict__ sb, int64_t n,
                                                        const int64_t* __restrict__ excl,
                                                        int32_t* __restrict__ list, int64_t cap) {
   __shared__ int64_t sh[5];
+  if (spans_agree(sa, sb, blockIdx.x)) return;   // no fresh cell here
   const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kSeg;
   int unc = 0;
   uint32_t m = base < n ? fresh_bits(a, b, base, n, unc) : 0u;
@@ -406,7 +458,7 @@ __global__ __launch_bounds__(256) void k_fresh_scatter(const int8_t* __restrict_
 
 extern "C" gcr_status gcr_plan_fresh_cells(const gcr_plan* a, const gcr_plan* b, int64_t* counts,
                                            int32_t* list, int64_t cap, void* stream) {
-  if (!a || !b || !counts || cap < 0 || (cap > 0 && !list)) return GCR_E_ARG;
+  if (!plan_ok(a) || !plan_ok(b) || !counts || cap < 0 || (cap > 0 && !list)) return GCR_E_ARG;
   if (a->dim != b->dim || a->ncell != b->ncell) return GCR_E_ARG;
   for (int ax = 0; ax < 3; ++ax)
     if (a->inst.g.n[ax] != b->inst.g.n[ax] || a->inst.g.lo[ax] != b->inst.g.lo[ax] ||
@@ -424,10 +476,12 @@ extern "C" gcr_status gcr_plan_fresh_cells(const gcr_plan* a, const gcr_plan* b,
   int64_t* excl = reinterpret_cast<int64_t*>(scr + o_ex);
   int64_t* tsum = reinterpret_cast<int64_t*>(scr + o_ts);
   k_fresh_zero<<<1, 64, 0, st>>>(counts);
-  k_fresh_count<<<(unsigned)nch, 256, 0, st>>>(a->tags, b->tags, n, ccnt, counts);
+  k_fresh_count<<<(unsigned)nch, 256, 0, st>>>(a->tags, b->tags, a->span, b->span, n, ccnt,
+                                               counts);
   if (list && cap > 0) {
     launch_scan(ccnt, nch, excl, nullptr, nullptr, tsum, st);
-    k_fresh_scatter<<<(unsigned)nch, 256, 0, st>>>(a->tags, b->tags, n, excl, list, cap);
+    k_fresh_scatter<<<(unsigned)nch, 256, 0, st>>>(a->tags, b->tags, a->span, b->span, n, excl,
+                                                   list, cap);
   }
   GCR_HIP(hipGetLastError());
   return GCR_OK;
@@ -449,7 +503,10 @@ __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts,
                                                  const int64_t* __restrict__ chunk_start,
                                                  const int32_t* __restrict__ chunk_list,
                                                  const int32_t* __restrict__ nlist,
-                                                 int8_t* __restrict__ tags) {
+                                                 int8_t* __restrict__ tags,
+                                                 int32_t* __restrict__ dirty,
+                                                 int32_t* __restrict__ dlist,
+                                                 int32_t* __restrict__ ndirty) {
   __shared__ int s_cell[kChunk];
   __shared__ int s_n;
   if ((int)blockIdx.x >= nlist[0]) return;
@@ -471,7 +528,6 @@ __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts,
   const int W[3] = {2 * R[0] + 1, 2 * R[1] + 1, 2 * R[2] + 1};
   const int box = W[0] * W[1] * W[2];
   const int64_t items = (int64_t)s_n * box;
-  uint32_t* words = reinterpret_cast<uint32_t*>(tags);
   constexpr int kFly = 8;
   for (int64_t i0 = threadIdx.x; i0 < items; i0 += 256 * kFly) {
     int64_t at[kFly];
@@ -499,21 +555,30 @@ __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts,
         }
       }
     }
+    // plain solid, not yet marked: a byte store, as every writer of a cell
+    // here stores the same value (1 -> 0x21) and no other kernel runs
 #pragma unroll
     for (int u = 0; u < kFly; ++u)
-      if (at[u] >= 0 && v[u] == 1)   // plain solid, not yet marked
-        // the tag array is padded to 256 bytes, so its last word is whole
-        atomicOr(&words[at[u] >> 2], 0x20u << (8 * (int)(at[u] & 3)));
+      if (at[u] >= 0 && v[u] == 1) {
+        tags[at[u]] = 0x21;
+        if (dirty) {
+          // a re-plan counts marks in the listed chunks only: list this one
+          const int64_t ch = I.chunk_off + (at[u] - I.cell_off) / kChunk;
+          if (dirty[ch] == 0 && atomicExch(&dirty[ch], 1) == 0)
+            dlist[atomicAdd(ndirty, 1)] = (int32_t)ch;
+        }
+      }
   }
 }
 
-// per chunk: cells with an interface or candidate mark (every chunk)
-__global__ __launch_bounds__(256) void k_count_marks(const Inst* __restrict__ insts, int ninst,
-                                                     const int64_t* __restrict__ chunk_start,
-                                                     const int8_t* __restrict__ tags,
-                                                     int32_t* __restrict__ chunk_cnt) {
+// per chunk: cells with an interface or candidate mark (every chunk, or
+// (List) the chunks of list[0, *nlist), the others holding none)
+__device__ __forceinline__ void count_marks_chunk(int64_t chunk, const Inst* __restrict__ insts,
+                                                  int ninst,
+                                                  const int64_t* __restrict__ chunk_start,
+                                                  const int8_t* __restrict__ tags,
+                                                  int32_t* __restrict__ chunk_cnt) {
   __shared__ int s;
-  const int64_t chunk = blockIdx.x;
   const int ii = find_inst(chunk_start, ninst, chunk);
   const Inst& I = insts[ii];
   if (threadIdx.x == 0) s = 0;
@@ -535,6 +600,24 @@ __global__ __launch_bounds__(256) void k_count_marks(const Inst* __restrict__ in
   if (n) atomicAdd(&s, n);
   __syncthreads();
   if (threadIdx.x == 0) chunk_cnt[chunk] = s;
+}
+
+template <bool List>
+__global__ __launch_bounds__(256) void k_count_marks(const Inst* __restrict__ insts, int ninst,
+                                                     const int64_t* __restrict__ chunk_start,
+                                                     const int8_t* __restrict__ tags,
+                                                     int32_t* __restrict__ chunk_cnt,
+                                                     const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ nlist) {
+  if (!List) {
+    count_marks_chunk(blockIdx.x, insts, ninst, chunk_start, tags, chunk_cnt);
+    return;
+  }
+  const int nit = nlist[0];
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    count_marks_chunk(list[it], insts, ninst, chunk_start, tags, chunk_cnt);
+    __syncthreads();   // s is reused by the next chunk
+  }
 }
 
 // off[i] = excl[start[i]] for the instance boundaries
@@ -1037,6 +1120,8 @@ static double factorial(int n) {
 
 constexpr int kMaxL2Radius = 64;   // second-layer candidate box half-width, cells
 
+static gcr_status make_shape(const gcr_shape& gs, int dim, ShapeD* out);
+
 static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme, Inst* I) {
   std::memset(I, 0, sizeof(Inst));
   if (gg.dim != 2 && gg.dim != 3) return GCR_E_ARG;
@@ -1099,16 +1184,23 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
       I->l2r[a] = (int)r;
     }
   }
-  ShapeD& s = I->s;
+  return make_shape(gs, gg.dim, &I->s);
+}
+
+// The device description of body gs in dim dimensions (Sec. 7: the bodies
+// of the test cases), with its culling bounds.
+static gcr_status make_shape(const gcr_shape& gs, int dim, ShapeD* out) {
+  ShapeD s;
+  std::memset(&s, 0, sizeof(s));
   s.kind = gs.kind;
-  for (int a = 0; a < 3; ++a) s.c[a] = a < gg.dim ? gs.center[a] : 0.0;
+  for (int a = 0; a < 3; ++a) s.c[a] = a < dim ? gs.center[a] : 0.0;
   s.r0 = gs.r0;
   if (gs.kind == kSphere) {
     if (!(gs.r0 > 0.0)) return GCR_E_ARG;
     for (int a = 0; a < 3; ++a) s.cull_c[a] = s.c[a];
     s.rmin = s.rmax = gs.r0;
   } else if (gs.kind == kStar2D) {
-    if (gg.dim != 2 || !(gs.r0 > 0.0) || gs.ncoef < 0 || 2 * gs.ncoef > kMaxCoef) return GCR_E_ARG;
+    if (dim != 2 || !(gs.r0 > 0.0) || gs.ncoef < 0 || 2 * gs.ncoef > kMaxCoef) return GCR_E_ARG;
     if (gs.ncoef > 0 && !gs.coef) return GCR_E_ARG;
     s.ncoef = gs.ncoef;
     double sa = 0.0;
@@ -1126,7 +1218,7 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
     s.lip = gs.r0 * lip;
   } else if (gs.kind == kShStar) {
     int L = (int)std::lround(std::sqrt((double)gs.ncoef)) - 1;
-    if (gg.dim != 3 || !(gs.r0 > 0.0) || L < 0 || (L + 1) * (L + 1) != gs.ncoef || L > 8 ||
+    if (dim != 3 || !(gs.r0 > 0.0) || L < 0 || (L + 1) * (L + 1) != gs.ncoef || L > 8 ||
         !gs.coef)
       return GCR_E_ARG;
     s.ncoef = gs.ncoef;
@@ -1149,7 +1241,7 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
       for (int m = -l; m <= l; ++m) lip += (double)l * std::fabs(gs.coef[l * l + l + m]);
     s.lip = gs.r0 * lip;
   } else if (gs.kind == kAirfoil) {
-    if (gg.dim != 2 || !(gs.chord > 0.0) || !(gs.thickness > 0.0) || gs.thickness > 0.5)
+    if (dim != 2 || !(gs.chord > 0.0) || !(gs.thickness > 0.0) || gs.thickness > 0.5)
       return GCR_E_ARG;
     s.chord = gs.chord;
     s.thick = gs.thickness;
@@ -1163,6 +1255,7 @@ static gcr_status make_inst(const gcr_grid& gg, const gcr_shape& gs, int scheme,
   } else {
     return GCR_E_ARG;
   }
+  *out = s;
   return GCR_OK;
 }
 
@@ -1246,17 +1339,80 @@ void last_build_times(float* ms) {
   for (int s = 0; s < kStages; ++s) ms[s] = g_stage_ms[s];
 }
 
+template <class T>
+static T* own_solo(BatchData& B, size_t n) {
+  // a pool allocation of its own (so that a re-plan can take it over)
+  T* p = static_cast<T*>(pool_alloc(sizeof(T) * (n ? n : 1)));
+  if (p) B.owned.push_back(p);
+  return p;
+}
+
+static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st,
+                             BatchData* prev, std::shared_ptr<BatchData>* out);
+
 gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes,
                        const int32_t* schemes, hipStream_t st, std::shared_ptr<BatchData>* out) {
   if (ninst < 1 || !grids || !shapes || !schemes || !out) return GCR_E_ARG;
   auto B = std::make_shared<BatchData>();
   B->ninst = ninst;
   B->inst.resize(ninst);
-  std::vector<int64_t> chunk_start(ninst + 1);
-  int64_t cells = 0, chunks = 0;
   for (int i = 0; i < ninst; ++i) {
     gcr_status s = make_inst(grids[i], shapes[i], schemes[i], &B->inst[i]);
     if (s != GCR_OK) return s;
+  }
+  // stretched axes: device copies of the faces (pageable sources, consumed
+  // when each copy returns)
+  for (int i = 0; i < ninst; ++i)
+    for (int a = 0; a < 3; ++a) {
+      const double* hf = B->inst[i].g.face[a];
+      if (!hf) continue;
+      const int64_t nf = (int64_t)B->inst[i].g.n[a] + 1;
+      double* df = own<double>(*B, nf);
+      if (!df) return GCR_E_NOMEM;
+      GCR_HIP(hipMemcpyAsync(df, hf, sizeof(double) * nf, hipMemcpyHostToDevice, st));
+      B->inst[i].g.face[a] = df;
+    }
+  return build_core(B, st, nullptr, out);
+}
+
+gcr_status build_update(BatchData& prev, const gcr_shape& shape, bool incremental,
+                        hipStream_t st, std::shared_ptr<BatchData>* out) {
+  if (prev.ninst != 1 || !out) return GCR_E_UNSUPPORTED;
+  ShapeD sd;
+  const gcr_status s = make_shape(shape, prev.inst[0].g.dim, &sd);
+  if (s != GCR_OK) return s;
+  return build_update(prev, sd, incremental, st, out);
+}
+
+gcr_status build_update(BatchData& prev, const ShapeD& shape, bool incremental, hipStream_t st,
+                        std::shared_ptr<BatchData>* out) {
+  if (prev.ninst != 1 || !out) return GCR_E_UNSUPPORTED;
+  auto B = std::make_shared<BatchData>();
+  B->ninst = 1;
+  B->inst.resize(1);
+  Inst I = prev.inst[0];
+  I.s = shape;
+  // the stretched faces: device copies of the previous plan's
+  for (int a = 0; a < 3; ++a) {
+    if (!I.g.face[a]) continue;
+    const int64_t nf = (int64_t)I.g.n[a] + 1;
+    double* df = own<double>(*B, nf);
+    if (!df) return GCR_E_NOMEM;
+    GCR_HIP(hipMemcpyAsync(df, I.g.face[a], sizeof(double) * nf, hipMemcpyDeviceToDevice, st));
+    I.g.face[a] = df;
+  }
+  B->inst[0] = I;
+  return build_core(B, st, incremental ? &prev : nullptr, out);
+}
+
+// The build proper: B holds its instances (device faces in place); with
+// prev, a re-plan of prev's single instance that takes over its tags.
+static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st,
+                             BatchData* prev, std::shared_ptr<BatchData>* out) {
+  const int ninst = B->ninst;
+  std::vector<int64_t> chunk_start(ninst + 1);
+  int64_t cells = 0, chunks = 0;
+  for (int i = 0; i < ninst; ++i) {
     Inst& I = B->inst[i];
     I.cell_off = cells;
     cells += (I.g.ncell + 255) / 256 * 256;
@@ -1268,20 +1424,7 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   chunk_start[ninst] = chunks;
   B->ncells_total = cells;
   B->nchunks = chunks;
-
   BatchData& D = *B;
-  // stretched axes: device copies of the faces (pageable sources, consumed
-  // when each copy returns)
-  for (int i = 0; i < ninst; ++i)
-    for (int a = 0; a < 3; ++a) {
-      const double* hf = B->inst[i].g.face[a];
-      if (!hf) continue;
-      const int64_t nf = (int64_t)B->inst[i].g.n[a] + 1;
-      double* df = own<double>(D, nf);
-      if (!df) return GCR_E_NOMEM;
-      GCR_HIP(hipMemcpyAsync(df, hf, sizeof(double) * nf, hipMemcpyHostToDevice, st));
-      B->inst[i].g.face[a] = df;
-    }
   // the small per-instance tables that cross between host and device live in
   // one device block with the layout of the pinned staging block, so each
   // transfer is one contiguous copy:
@@ -1316,7 +1459,23 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
   D.d_iface_off = reinterpret_cast<int64_t*>(tb + o_io);
   D.d_hoff = reinterpret_cast<int64_t*>(tb + o_ho);
   D.d_hmask = reinterpret_cast<uint32_t*>(tb + o_hm);
-  D.d_tags = own<int8_t>(D, cells);
+  if (prev) {
+    // the previous plan's tags, which the classification below updates
+    if (prev->ninst != 1 || prev->nchunks != chunks || !prev->d_tags) return GCR_E_UNSUPPORTED;
+    auto it = std::find(prev->owned.begin(), prev->owned.end(), (void*)prev->d_tags);
+    if (it == prev->owned.end()) return GCR_E_UNSUPPORTED;
+    prev->owned.erase(it);
+    D.owned.push_back(prev->d_tags);
+    D.d_tags = prev->d_tags;
+    prev->d_tags = nullptr;
+    D.d_dirty = own<int32_t>(D, chunks);
+    D.d_dirty_list = own<int32_t>(D, chunks);
+    D.d_ndirty = own<int32_t>(D, 1);
+    if (!D.d_dirty || !D.d_dirty_list || !D.d_ndirty) return GCR_E_NOMEM;
+  } else {
+    // a single instance's tags on their own, for a later re-plan to take over
+    D.d_tags = ninst == 1 ? own_solo<int8_t>(D, cells) : own<int8_t>(D, cells);
+  }
   D.d_chunk_cnt = own<int32_t>(D, chunks);
   D.d_span = own<int8_t>(D, chunks * (kChunk / (64 * kSeg)));
   D.d_chunk_list = own<int32_t>(D, chunks);
@@ -1348,8 +1507,20 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
 
   StageEvents T((g_profiling.load() & 1) != 0);
   T.mark(0, st);
+  ClassifyUpdate U{};
+  if (prev) {
+    U.span_prev = prev->d_span;
+    U.ghost_prev = prev->d_g_cell;
+    U.ng_prev = prev->d_g_cell ? prev->g_off[1] : 0;
+    U.dirty = D.d_dirty;
+    U.list = D.d_dirty_list;
+    U.nlist = D.d_ndirty;
+    U.scan_excl = D.d_chunk_excl;
+    U.scan_tmp = D.d_scan_tmp;
+  }
   launch_classify(D.d_inst, ninst, D.d_chunk_start, chunks, D.d_span, D.d_chunk_inst, D.d_tags,
-                  D.d_chunk_cnt, D.d_band, D.d_nband, T.event(10), T.event(11), st);
+                  D.d_chunk_cnt, D.d_band, D.d_nband, T.event(10), T.event(11), st,
+                  prev ? &U : nullptr);
   T.mark(1, st);
   launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
               D.d_scan_tmp, st);
@@ -1359,9 +1530,15 @@ gcr_status build_batch(int ninst, const gcr_grid* grids, const gcr_shape* shapes
     k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
                                                        D.d_iface_off);
     k_l2_mark<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start,
-                                                D.d_chunk_list, D.d_nchunk_list, D.d_tags);
-    k_count_marks<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags,
-                                                    D.d_chunk_cnt);
+                                                D.d_chunk_list, D.d_nchunk_list, D.d_tags,
+                                                D.d_dirty, D.d_dirty_list, D.d_ndirty);
+    if (prev)   // the dirty chunks and those the marks reached
+      k_count_marks<true><<<(unsigned)std::min<int64_t>(chunks, kListGrid), 256, 0, st>>>(
+          D.d_inst, ninst, D.d_chunk_start, D.d_tags, D.d_chunk_cnt, D.d_dirty_list,
+          D.d_ndirty);
+    else
+      k_count_marks<false><<<(unsigned)chunks, 256, 0, st>>>(
+          D.d_inst, ninst, D.d_chunk_start, D.d_tags, D.d_chunk_cnt, nullptr, nullptr);
     launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
                 D.d_scan_tmp, st);
   }
@@ -1571,6 +1748,7 @@ void make_plan_view(const std::shared_ptr<BatchData>& B, int i, gcr_plan* p) {
   p->lev_off.assign(D.lev_off.begin() + (size_t)i * (kMaxLevels + 1),
                     D.lev_off.begin() + (size_t)i * (kMaxLevels + 1) + p->nlev + 1);
   p->tags = D.d_tags + p->inst.cell_off;
+  p->span = D.d_span + p->inst.chunk_off * (kChunk / (64 * kSeg));
   const int64_t o = p->goff;
   if (D.d_cell) {
     p->cell = D.d_cell + o;
