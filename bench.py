@@ -93,7 +93,8 @@ def kernel_traffic(name, workload):
     """HBM bytes per launch of kernel `name` on `workload` from the committed
     byte-counter summary, or None when it is absent or the kernel's sources
     changed since."""
-    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
+    key = name.replace(" + ", "+")
+    path = os.path.join(ROOT, "profiles", f"{key}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -494,14 +495,16 @@ def measure_batched(gcr, torch, W, args, s_fwd, s_builds, extra=True):
 
 def roofline_of(W, m, cells):
     """The step's longest kernel among the batched forward (library events
-    around the launch in the timed steps), the classification store pass
-    (1 byte per cell written) and the layering (stage events around each
-    launch), against its algorithmic bytes."""
+    around the launch in the timed steps), the classification (the span
+    pass, which stores settled spans, and the store pass over the chunks it
+    leaves: 1 byte per cell written) and the layering (stage events around
+    each launch), against its algorithmic bytes."""
     d = W.dim
     npts = sum(W.nq)
     cands = {
         "k_batch_forward": (m["fwd_ms"], forward_bytes(d, W.nf, m["ghosts"], npts)),
-        "k_classify": (m["stage_ms"]["classify_store"], cells),
+        "k_spans + k_classify": (m["stage_ms"]["classify_prepass"] + m["stage_ms"]["classify_store"],
+                                 cells),
         "k_levels": (m["stage_ms"]["levels_order"], levels_bytes(d, m["ghosts"])),
     }
     out = {}
@@ -921,12 +924,12 @@ def bench_large(gcr, torch, synth, reps):
         b.record()
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))
-        cls.append(info["times"]["classify_store"])
+        cls.append(info["times"]["classify_prepass"] + info["times"]["classify_store"])
     gcr.set_profiling(False)
     t = float(np.median(ts))
     c = float(np.median(cls))
     ncell = g.n[0] * g.n[1] * g.n[2]
-    cbytes = ncell   # the store pass writes every cell's tag
+    cbytes = ncell   # the span and store passes write every cell's tag
     del fields
     torch.cuda.empty_cache()
     return {"workload": "sphere1024: 1024^3 grid on [-1,1]^3, the 256^3 workload's sphere, HGC, "
@@ -934,7 +937,7 @@ def bench_large(gcr, torch, synth, reps):
             "cells": ncell, "ghosts": info["ng"], "step_ms": round(t, 4),
             "ghost_cells_per_s": round(info["ng"] / (t * 1e-3), 1),
             "classify_store_ms": round(c, 5),
-            "classify_roofline": {"bound": "hbm", "kernel": "k_classify",
+            "classify_roofline": {"bound": "hbm", "kernel": "k_spans + k_classify",
                                   "achieved": round(cbytes / (c * 1e-3) / 1e9, 2),
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": round(cbytes / (c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

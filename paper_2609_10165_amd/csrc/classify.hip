@@ -2,12 +2,15 @@
 // inside test at the cell centre (psi >= 0 solid) and the interface mark
 // (a face neighbour of the other class).
 //
-// Three launches: a pre-pass settles whole 1024-cell spans from bounds on
-// the body (a radial bound, or a Lipschitz bound on the star radius); the
-// store pass writes every cell's solid bit, settling 16-cell row segments
-// by the same bounds where it can and testing the cells of the others (the
-// band) exactly; the interface pass marks the band cells that have a face
-// neighbour of the other class.
+// A span pass settles whole 1024-cell spans from bounds on the body (a
+// radial bound, or a Lipschitz bound on the star radius) and stores them at
+// once; the chunks of 4096 cells it leaves are listed, and the store pass
+// writes their cells' solid bits, settling 16-cell row segments by the same
+// bounds where it can and testing the cells of the others (the band)
+// exactly; the interface pass marks the band cells that have a face
+// neighbour of the other class.  The list keeps the heavy store pass (its
+// FP64 tests hold many registers) off the chunks that only take a constant.
+// A re-plan lists the chunks a move can change instead (section 2).
 //
 // (Band segments are counted for statistics in kBandStripes counters 64
 // bytes apart, nband[16 s]; their sum is the count.)
@@ -93,51 +96,98 @@ __device__ __forceinline__ bool cell_solid(const GridD& g, const ShapeD& s, int 
   return inside(s, g.dim, x);
 }
 
-// One thread per span of 64 * kSeg cells (one classification wave): whether
-// the box of the span's cells and their face neighbours, in index space,
-// lies wholly on one side of the boundary (0 fluid, 1 solid, -1 undecided).
+// nvalid tags of value v (0 or 1) from cell `dst` on
+__device__ __forceinline__ void store_const(int8_t* dst, int nvalid, int v) {
+  if (nvalid == kSeg) {
+    const uint32_t w = v ? 0x01010101u : 0u;
+    *reinterpret_cast<uint4*>(dst) = make_uint4(w, w, w, w);
+  } else {
+    for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)v;
+  }
+}
+
+// The span pass, kSpanChunks chunks (4 spans each) per workgroup: one lane
+// per span of 64 * kSeg cells tests whether the box of the span's cells and
+// their face neighbours, in index space, lies wholly on one side of the
+// boundary (0 fluid, 1 solid, -1 undecided); then (tags set) every wave
+// stores whole settled spans, 1 KB each, with 16-byte stores.  need[c] = 1
+// for a chunk with a span left (undecided, or cut by the grid end), the
+// chunks the store pass visits; every chunk's interface count and band mask
+// start at zero.
+constexpr int kSpanChunks = 8;
 __global__ __launch_bounds__(256) void k_spans(const Inst* __restrict__ insts, int ninst,
                                                const int64_t* __restrict__ chunk_start,
-                                               int64_t nspan, int8_t* __restrict__ span,
+                                               int64_t chunks, int8_t* __restrict__ span,
                                                int32_t* __restrict__ chunk_inst,
+                                               int32_t* __restrict__ need,
+                                               int32_t* __restrict__ chunk_cnt,
+                                               uint64_t* __restrict__ bandmask,
+                                               int8_t* __restrict__ tags,
                                                int32_t* __restrict__ nband) {
-  constexpr int kSpan = 64 * kSeg, kPer = kChunk / kSpan;
-  const int64_t sp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sp < kBandStripes) nband[sp * 16] = 0;   // k_band_iface counts from zero
-  if (sp >= nspan) return;
-  const int64_t chunk = sp / kPer;
-  const int ii = find_inst(chunk_start, ninst, chunk);
-  // the chunk's instance, for the passes after this one (one load instead
-  // of a search at the start of each of their workgroups)
-  if (sp % kPer == 0) chunk_inst[chunk] = ii;
-  const Inst& I = insts[ii];
-  const GridD& g = I.g;
-  const int64_t base = (chunk - I.chunk_off) * kChunk + (sp % kPer) * kSpan;
-  int8_t r = -1;
-  if (base < g.ncell) {
-    int p0[3], p1[3], mn[3], mx[3];
-    unlinear(g, (int)base, p0[0], p0[1], p0[2]);
-    unlinear(g, (int)min(base + kSpan, g.ncell) - 1, p1[0], p1[1], p1[2]);
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = p0[a];
-      mx[a] = p1[a];
+  constexpr int kSpan = 64 * kSeg, kPer = kChunk / kSpan, kSpans = kSpanChunks * kPer;
+  static_assert(kSpans <= 64, "one wave tests the workgroup's spans");
+  __shared__ int8_t s_flag[kSpans];
+  __shared__ int64_t s_base[kSpans];   // tag offset of a whole settled span, else -1
+  const int tid = (int)threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kSpanChunks;
+  if (blockIdx.x == 0 && tid < kBandStripes) nband[tid * 16] = 0;   // k_band_iface counts from zero
+  if (tid < kSpans) {
+    const int64_t chunk = c0 + tid / kPer;
+    int8_t r = -1;
+    int64_t whole = -1;
+    if (chunk < chunks) {
+      const int ii = find_inst(chunk_start, ninst, chunk);
+      // the chunk's instance, for the passes after this one (one load instead
+      // of a search at the start of each of their workgroups)
+      if (tid % kPer == 0) {
+        chunk_inst[chunk] = ii;
+        chunk_cnt[chunk] = 0;
+      }
+      bandmask[chunk * 4 + tid % kPer] = 0ull;
+      const Inst& I = insts[ii];
+      const GridD& g = I.g;
+      const int64_t base = (chunk - I.chunk_off) * kChunk + (tid % kPer) * kSpan;
+      if (base < g.ncell) {
+        int p0[3], p1[3], mn[3], mx[3];
+        unlinear(g, (int)base, p0[0], p0[1], p0[2]);
+        unlinear(g, (int)min(base + kSpan, g.ncell) - 1, p1[0], p1[1], p1[2]);
+        for (int a = 0; a < 3; ++a) {
+          mn[a] = p0[a];
+          mx[a] = p1[a];
+        }
+        if (p0[2] != p1[2]) {
+          mn[0] = mn[1] = 0;
+          mx[0] = g.n[0] - 1;
+          mx[1] = g.n[1] - 1;
+        } else if (p0[1] != p1[1]) {
+          mn[0] = 0;
+          mx[0] = g.n[0] - 1;
+        }
+        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < g.dim; ++a) {
+          lo[a] = centre_below(g, a, mn[a]);
+          hi[a] = centre_above(g, a, mx[a]);
+        }
+        r = (int8_t)box_settled(I.s, g.dim, lo, hi);
+        if (r >= 0 && base + kSpan <= g.ncell) whole = I.cell_off + base;
+      }
+      span[chunk * kPer + tid % kPer] = r;
     }
-    if (p0[2] != p1[2]) {
-      mn[0] = mn[1] = 0;
-      mx[0] = g.n[0] - 1;
-      mx[1] = g.n[1] - 1;
-    } else if (p0[1] != p1[1]) {
-      mn[0] = 0;
-      mx[0] = g.n[0] - 1;
-    }
-    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < g.dim; ++a) {
-      lo[a] = centre_below(g, a, mn[a]);
-      hi[a] = centre_above(g, a, mx[a]);
-    }
-    r = (int8_t)box_settled(I.s, g.dim, lo, hi);
+    s_flag[tid] = r;
+    s_base[tid] = whole;
   }
-  span[sp] = r;
+  __syncthreads();
+  if (tid < kSpanChunks && c0 + tid < chunks) {
+    bool nd = false;
+    for (int q = 0; q < kPer; ++q) nd = nd || s_base[tid * kPer + q] < 0;
+    need[c0 + tid] = nd ? 1 : 0;
+  }
+  if (!tags) return;
+  const int wv = tid >> 6, lane = tid & 63;
+  for (int q = wv; q < kSpans; q += 4) {
+    const int64_t b = s_base[q];
+    if (b >= 0) store_const(tags + b + lane * kSeg, kSeg, s_flag[q]);
+  }
 }
 
 // Whether the nvalid cells of the row segment starting at cell `base` and
@@ -192,16 +242,6 @@ __device__ __forceinline__ int seg_settled(const GridD& g, const ShapeD& S, int 
   return sa;
 }
 
-// nvalid tags of value v (0 or 1) from cell `dst` on
-__device__ __forceinline__ void store_const(int8_t* dst, int nvalid, int v) {
-  if (nvalid == kSeg) {
-    const uint32_t w = v ? 0x01010101u : 0u;
-    *reinterpret_cast<uint4*>(dst) = make_uint4(w, w, w, w);
-  } else {
-    for (int b = 0; b < nvalid; ++b) dst[b] = (int8_t)v;
-  }
-}
-
 // The store pass, one workgroup per chunk of kChunk cells, a 16-cell row
 // segment per thread.  A wave whose span the pre-pass settled only stores.
 // Otherwise the work is done densely in three rounds, so that no wave runs
@@ -213,13 +253,11 @@ __device__ __forceinline__ void store_const(int8_t* dst, int nvalid, int v) {
 // bit here and their interface mark (a face neighbour of the other class)
 // from k_band_iface; settled segments have none, since their boxes include
 // the face neighbours.  The chunk's band is recorded as a 256-bit mask.
-__device__ __forceinline__ void classify_chunk(int64_t chunk, const Inst* __restrict__ insts,
-                                               const int32_t* __restrict__ chunk_inst,
+__device__ __forceinline__ void classify_chunk(int64_t chunk, int ii, const Inst* __restrict__ insts,
                                                const int8_t* __restrict__ span,
                                                int8_t* __restrict__ tags,
                                                int32_t* __restrict__ chunk_cnt,
                                                uint64_t* __restrict__ bandmask) {
-  const int ii = chunk_inst[chunk];
   const Inst& I = insts[ii];
   const GridD g = I.g;
   const int64_t chunk_off = I.chunk_off, cell_off = I.cell_off;
@@ -300,7 +338,8 @@ __device__ __forceinline__ void classify_chunk(int64_t chunk, const Inst* __rest
 }
 
 // One workgroup per chunk, or (List) workgroups striding over the chunks
-// listed in list[0, *nlist) (an incremental re-plan's dirty chunks).
+// listed in list[0, *nlist).  (Two instances: the loop costs registers, and
+// so occupancy, that the one-chunk form does without.)
 template <bool List>
 __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts,
                                                   const int32_t* __restrict__ chunk_inst,
@@ -311,12 +350,13 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
                                                   const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ nlist) {
   if (!List) {
-    classify_chunk(blockIdx.x, insts, chunk_inst, span, tags, chunk_cnt, bandmask);
+    classify_chunk(blockIdx.x, chunk_inst[blockIdx.x], insts, span, tags, chunk_cnt, bandmask);
     return;
   }
   const int nit = nlist[0];
   for (int it = blockIdx.x; it < nit; it += gridDim.x) {
-    classify_chunk(list[it], insts, chunk_inst, span, tags, chunk_cnt, bandmask);
+    const int64_t chunk = list[it];
+    classify_chunk(chunk, chunk_inst[chunk], insts, span, tags, chunk_cnt, bandmask);
     __syncthreads();   // the LDS lists are reused by the next chunk
   }
 }
@@ -331,6 +371,7 @@ __device__ __forceinline__ void band_iface_chunk(int64_t chunk, const Inst* __re
                                                  int8_t* __restrict__ tags,
                                                  int32_t* __restrict__ chunk_cnt,
                                                  int32_t* __restrict__ nband) {
+  const int ii = chunk_inst[chunk];   // loaded beside the masks
   unsigned long long m[4];
   int tot = 0;
   for (int w = 0; w < 4; ++w) {
@@ -352,7 +393,6 @@ __device__ __forceinline__ void band_iface_chunk(int64_t chunk, const Inst* __re
   }
   if (tid == 0) s_cnt = 0;
   __syncthreads();
-  const int ii = chunk_inst[chunk];
   const Inst& I = insts[ii];
   const GridD g = I.g;
   const int64_t cell_off = I.cell_off;
@@ -389,7 +429,6 @@ __device__ __forceinline__ void band_iface_chunk(int64_t chunk, const Inst* __re
   }
 }
 
-template <bool List>
 __global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ insts,
                                                     const int32_t* __restrict__ chunk_inst,
                                                     const uint64_t* __restrict__ bandmask,
@@ -398,7 +437,7 @@ __global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ ins
                                                     int32_t* __restrict__ nband,
                                                     const int32_t* __restrict__ list,
                                                     const int32_t* __restrict__ nlist) {
-  if (!List) {
+  if (!list) {
     band_iface_chunk(blockIdx.x, insts, chunk_inst, bandmask, tags, chunk_cnt, nband);
     return;
   }
@@ -420,12 +459,10 @@ __global__ __launch_bounds__(256) void k_band_iface(const Inst* __restrict__ ins
 // are its settled value unless a ghost of the previous plan lies there (a
 // second-layer ghost can sit in a settled solid span), which
 // k_dirty_ghosts catches.  One thread per chunk: dirty[c] = 1 for a chunk
-// to classify again; a clean chunk gets no interface cells and no band.
+// to classify again.
 __global__ __launch_bounds__(256) void k_dirty(const int8_t* __restrict__ span0,
                                                const int8_t* __restrict__ span1, int64_t chunks,
-                                               int32_t* __restrict__ dirty,
-                                               int32_t* __restrict__ chunk_cnt,
-                                               uint64_t* __restrict__ bandmask) {
+                                               int32_t* __restrict__ dirty) {
   constexpr int kPer = kChunk / (64 * kSeg);
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= chunks) return;
@@ -436,10 +473,6 @@ __global__ __launch_bounds__(256) void k_dirty(const int8_t* __restrict__ span0,
     d = d || b < 0 || a != b;
   }
   dirty[c] = d ? 1 : 0;
-  if (!d) {
-    chunk_cnt[c] = 0;
-    for (int w = 0; w < 4; ++w) bandmask[c * 4 + w] = 0ull;
-  }
 }
 
 // the chunks of the previous plan's ghosts (a single instance from chunk 0)
@@ -453,34 +486,43 @@ __global__ __launch_bounds__(256) void k_dirty_ghosts(const int32_t* __restrict_
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
                      int8_t* span, int32_t* chunk_inst, int8_t* tags, int32_t* chunk_cnt,
                      int32_t* band, int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store,
-                     hipStream_t st, const ClassifyUpdate* U) {
-  const int64_t nspan = chunks * (kChunk / (64 * kSeg));
+                     hipStream_t st, const ClassifyWork& W, const ClassifyUpdate* U) {
   uint64_t* mask = reinterpret_cast<uint64_t*>(band);   // [chunks][4]
-  k_spans<<<(unsigned)((nspan + 255) / 256), 256, 0, st>>>(insts, ninst, chunk_start, nspan,
-                                                           span, chunk_inst, nband);
+  // Where chunks are rows of a 2D grid, about every other one meets the
+  // body and the store pass takes them all (the settled ones with one
+  // store each); elsewhere the span pass stores settled spans at once and
+  // the store pass takes the chunks left.  A re-plan keeps the previous
+  // plan's tags outside the chunks a move can change.
+  const bool every = !U && W.every_chunk;
+  k_spans<<<(unsigned)((chunks + kSpanChunks - 1) / kSpanChunks), 256, 0, st>>>(
+      insts, ninst, chunk_start, chunks, span, chunk_inst, W.flag, chunk_cnt, mask,
+      U || every ? nullptr : tags, nband);
   if (ev_prepass) (void)hipEventRecord(ev_prepass, st);
-  if (!U) {
+  if (every) {
     k_classify<false><<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt,
                                                         mask, nullptr, nullptr);
     if (ev_store) (void)hipEventRecord(ev_store, st);
-    k_band_iface<false><<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, mask, tags,
-                                                          chunk_cnt, nband, nullptr, nullptr);
+    k_band_iface<<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt,
+                                                   nband, nullptr, nullptr);
     return;
   }
-  // a re-plan: the dirty chunks, listed in ascending order, are classified
-  // by a grid that strides over the list (its length stays on the device)
-  k_dirty<<<(unsigned)((chunks + 255) / 256), 256, 0, st>>>(U->span_prev, span, chunks, U->dirty,
-                                                            chunk_cnt, mask);
-  if (U->ng_prev > 0)
-    k_dirty_ghosts<<<(unsigned)((U->ng_prev + 255) / 256), 256, 0, st>>>(U->ghost_prev,
-                                                                         U->ng_prev, U->dirty);
-  launch_scan(U->dirty, chunks, U->scan_excl, U->list, U->nlist, U->scan_tmp, st);
+  if (U) {
+    // a re-plan: the chunks the move can change, instead of those left
+    k_dirty<<<(unsigned)((chunks + 255) / 256), 256, 0, st>>>(U->span_prev, span, chunks,
+                                                              W.flag);
+    if (U->ng_prev > 0)
+      k_dirty_ghosts<<<(unsigned)((U->ng_prev + 255) / 256), 256, 0, st>>>(
+          U->ghost_prev, U->ng_prev, W.flag);
+  }
+  // the flagged chunks, listed in ascending order, are classified by a grid
+  // that strides over the list (its length stays on the device)
+  launch_scan(W.flag, chunks, W.scan_excl, W.list, W.nlist, W.scan_tmp, st);
   const unsigned G = (unsigned)std::min<int64_t>(chunks, kListGrid);
-  k_classify<true><<<G, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask, U->list,
-                                      U->nlist);
+  k_classify<true><<<G, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask, W.list,
+                                      W.nlist);
   if (ev_store) (void)hipEventRecord(ev_store, st);
-  k_band_iface<true><<<G, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt, nband, U->list,
-                                        U->nlist);
+  k_band_iface<<<G, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt, nband, W.list,
+                                  W.nlist);
 }
 
 }  // namespace gcr

@@ -81,7 +81,7 @@ struct BatchData {
   int32_t* d_band = nullptr;         // band masks of the chunks (classification scratch)
   int32_t* d_chunk_inst = nullptr;   // instance of each chunk
   int32_t* d_nband = nullptr;        // their number
-  int32_t* d_dirty = nullptr;        // re-plan: chunks classified again (flags, then list)
+  int32_t* d_dirty = nullptr;        // chunks the store pass classifies (flags, then list)
   int32_t* d_dirty_list = nullptr;
   int32_t* d_ndirty = nullptr;
   int64_t* d_scan_tmp = nullptr;     // tile totals of the long chunk scan
@@ -180,26 +180,31 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
 // (either may be null) are recorded after the span pre-pass and after the
 // store pass.
 //
-// With U (a re-plan of a single instance whose tags hold the previous
-// plan's): only the chunks the move can change are classified again, those
-// with a span unsettled now or settled differently before, and those
-// holding a ghost of the previous plan; they are listed in U->list[0,
-// *U->nlist), ascending, and flagged in U->dirty [chunks].
-struct ClassifyUpdate {
-  const int8_t* span_prev;     // [chunks * 4] the previous plan's span flags
-  const int32_t* ghost_prev;   // [ng_prev] the previous plan's ghost cells
-  int64_t ng_prev;
-  int32_t* dirty;              // [chunks]
+// The chunks the span pass leaves (or, with U, those a move can change)
+// are flagged in W.flag [chunks] and listed in W.list[0, *W.nlist),
+// ascending.  With U (a re-plan of a single instance whose tags hold the
+// previous plan's): only the chunks the move can change are classified
+// again, those with a span unsettled now or settled differently before,
+// and those holding a ghost of the previous plan.
+struct ClassifyWork {
+  int32_t* flag;               // [chunks]
   int32_t* list;               // [chunks]
   int32_t* nlist;              // [1]
   int64_t* scan_excl;          // [chunks + 1] scan scratch
   int64_t* scan_tmp;           // scan tile totals
+  bool every_chunk;            // full build: the store pass takes every chunk (2D grids)
 };
-constexpr int kListGrid = 2048;   // workgroups striding over a chunk list
+struct ClassifyUpdate {
+  const int8_t* span_prev;     // [chunks * 4] the previous plan's span flags
+  const int32_t* ghost_prev;   // [ng_prev] the previous plan's ghost cells
+  int64_t ng_prev;
+};
+constexpr int kListGrid = 32768;   // workgroups striding over a chunk list (one entry each below)
 void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, int64_t chunks,
                      int8_t* span, int32_t* chunk_inst, int8_t* tags, int32_t* chunk_cnt,
                      int32_t* band, int32_t* nband, hipEvent_t ev_prepass, hipEvent_t ev_store,
-                     hipStream_t st, const ClassifyUpdate* U = nullptr);
+                     hipStream_t st, const ClassifyWork& W,
+                     const ClassifyUpdate* U = nullptr);
 
 
 // instance holding global index x of a batch: the last i with off[i] <= x

@@ -571,8 +571,9 @@ __global__ __launch_bounds__(256) void k_l2_mark(const Inst* __restrict__ insts,
   }
 }
 
-// per chunk: cells with an interface or candidate mark (every chunk, or
-// (List) the chunks of list[0, *nlist), the others holding none)
+// per chunk: cells with an interface or candidate mark, for every chunk
+// (list null) or the chunks of list[0, *nlist) (the classified ones and
+// those a candidate mark reached; the others hold none)
 __device__ __forceinline__ void count_marks_chunk(int64_t chunk, const Inst* __restrict__ insts,
                                                   int ninst,
                                                   const int64_t* __restrict__ chunk_start,
@@ -602,14 +603,13 @@ __device__ __forceinline__ void count_marks_chunk(int64_t chunk, const Inst* __r
   if (threadIdx.x == 0) chunk_cnt[chunk] = s;
 }
 
-template <bool List>
 __global__ __launch_bounds__(256) void k_count_marks(const Inst* __restrict__ insts, int ninst,
                                                      const int64_t* __restrict__ chunk_start,
                                                      const int8_t* __restrict__ tags,
                                                      int32_t* __restrict__ chunk_cnt,
                                                      const int32_t* __restrict__ list,
                                                      const int32_t* __restrict__ nlist) {
-  if (!List) {
+  if (!list) {   // every chunk, one workgroup each
     count_marks_chunk(blockIdx.x, insts, ninst, chunk_start, tags, chunk_cnt);
     return;
   }
@@ -1468,15 +1468,15 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
     D.owned.push_back(prev->d_tags);
     D.d_tags = prev->d_tags;
     prev->d_tags = nullptr;
-    D.d_dirty = own<int32_t>(D, chunks);
-    D.d_dirty_list = own<int32_t>(D, chunks);
-    D.d_ndirty = own<int32_t>(D, 1);
-    if (!D.d_dirty || !D.d_dirty_list || !D.d_ndirty) return GCR_E_NOMEM;
   } else {
     // a single instance's tags on their own, for a later re-plan to take over
     D.d_tags = ninst == 1 ? own_solo<int8_t>(D, cells) : own<int8_t>(D, cells);
   }
   D.d_chunk_cnt = own<int32_t>(D, chunks);
+  D.d_dirty = own<int32_t>(D, chunks);
+  D.d_dirty_list = own<int32_t>(D, chunks);
+  D.d_ndirty = own<int32_t>(D, 1);
+  if (!D.d_dirty || !D.d_dirty_list || !D.d_ndirty) return GCR_E_NOMEM;
   D.d_span = own<int8_t>(D, chunks * (kChunk / (64 * kSeg)));
   D.d_chunk_list = own<int32_t>(D, chunks);
   D.d_band = own<int32_t>(D, chunks * 8);   // band mask of each chunk (4 x 64 bits)
@@ -1490,10 +1490,11 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
       !D.d_chunk_list || !D.d_band || !D.d_chunk_inst || !D.d_unit_mem || !D.d_unit_cnt ||
       !D.d_reach)
     return GCR_E_NOMEM;
-  bool any_layer2 = false, any_2d = false;
+  bool any_layer2 = false, any_2d = false, any_3d = false;
   for (int i = 0; i < ninst; ++i) {
     any_layer2 = any_layer2 || D.inst[i].layer2;
     any_2d = any_2d || D.inst[i].g.dim == 2;
+    any_3d = any_3d || D.inst[i].g.dim == 3;
   }
   PinnedStage PS;
   PS.st = st;
@@ -1507,19 +1508,16 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
 
   StageEvents T((g_profiling.load() & 1) != 0);
   T.mark(0, st);
+  ClassifyWork W{D.d_dirty, D.d_dirty_list, D.d_ndirty, D.d_chunk_excl, D.d_scan_tmp,
+                 !any_3d};
   ClassifyUpdate U{};
   if (prev) {
     U.span_prev = prev->d_span;
     U.ghost_prev = prev->d_g_cell;
     U.ng_prev = prev->d_g_cell ? prev->g_off[1] : 0;
-    U.dirty = D.d_dirty;
-    U.list = D.d_dirty_list;
-    U.nlist = D.d_ndirty;
-    U.scan_excl = D.d_chunk_excl;
-    U.scan_tmp = D.d_scan_tmp;
   }
   launch_classify(D.d_inst, ninst, D.d_chunk_start, chunks, D.d_span, D.d_chunk_inst, D.d_tags,
-                  D.d_chunk_cnt, D.d_band, D.d_nband, T.event(10), T.event(11), st,
+                  D.d_chunk_cnt, D.d_band, D.d_nband, T.event(10), T.event(11), st, W,
                   prev ? &U : nullptr);
   T.mark(1, st);
   launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
@@ -1529,16 +1527,15 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
     // join the list: mark, recount every chunk, scan again
     k_gather_off<<<blocks(ninst + 1, 64), 64, 0, st>>>(D.d_chunk_excl, D.d_chunk_start, ninst,
                                                        D.d_iface_off);
-    k_l2_mark<<<(unsigned)chunks, 256, 0, st>>>(D.d_inst, ninst, D.d_chunk_start,
-                                                D.d_chunk_list, D.d_nchunk_list, D.d_tags,
-                                                D.d_dirty, D.d_dirty_list, D.d_ndirty);
-    if (prev)   // the dirty chunks and those the marks reached
-      k_count_marks<true><<<(unsigned)std::min<int64_t>(chunks, kListGrid), 256, 0, st>>>(
-          D.d_inst, ninst, D.d_chunk_start, D.d_tags, D.d_chunk_cnt, D.d_dirty_list,
-          D.d_ndirty);
-    else
-      k_count_marks<false><<<(unsigned)chunks, 256, 0, st>>>(
-          D.d_inst, ninst, D.d_chunk_start, D.d_tags, D.d_chunk_cnt, nullptr, nullptr);
+    // with a chunk list, marks outside it extend it, and the count covers
+    // the list; else every chunk is counted
+    const bool listed = prev || !W.every_chunk;
+    k_l2_mark<<<(unsigned)chunks, 256, 0, st>>>(
+        D.d_inst, ninst, D.d_chunk_start, D.d_chunk_list, D.d_nchunk_list, D.d_tags,
+        listed ? D.d_dirty : nullptr, D.d_dirty_list, D.d_ndirty);
+    k_count_marks<<<(unsigned)(listed ? std::min<int64_t>(chunks, kListGrid) : chunks), 256, 0,
+                    st>>>(D.d_inst, ninst, D.d_chunk_start, D.d_tags, D.d_chunk_cnt,
+                          listed ? D.d_dirty_list : nullptr, D.d_ndirty);
     launch_scan(D.d_chunk_cnt, chunks, D.d_chunk_excl, D.d_chunk_list, D.d_nchunk_list,
                 D.d_scan_tmp, st);
   }
