@@ -209,7 +209,8 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
 // the instance takes every G-th block of T (ghost, field) pairs of a level,
 // the fields of a ghost side by side (they share its stencil data), and the
 // G workgroups meet at a device-scope counter after each level and after
-// each level's coupled units.  Every value is computed as by the per-item
+// each level's coupled units (G = 1: the workgroup's own barrier, which
+// orders its values for its own waves).  Every value is computed as by the per-item
 // kernel, from the same inputs.  The launch is cooperative (the runtime
 // refuses it unless every workgroup can be resident at once), and each wait
 // is bounded as well, so every wave ends: a wait that gives up sets the
@@ -220,7 +221,11 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
 // the set the next one uses (launches on one batch are ordered).
 constexpr int kSpinMax = 1 << 22;
 
-__device__ __forceinline__ void inst_barrier(int* bar, int target, int spin, int* fault) {
+__device__ __forceinline__ void inst_barrier(int* bar, int target, int spin, int* fault, int G) {
+  if (G == 1) {   // the instance's only workgroup: its own barrier orders its values
+    __syncthreads();
+    return;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();   // this workgroup's values, before its arrival
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(1024) void k_batch_split(BStatic S, BCall C, int G,
       const int p = lo + e / nf, f = e % nf, w = i * nf + f;
       fill_single<D>(P, p, C.fields[w], C.bcv[w], C.bct ? C.bct[w] : nullptr, C.kind[f]);
     }
-    inst_barrier(cnt, G * ++arrivals, spin, fault);
+    inst_barrier(cnt, G * ++arrivals, spin, fault, G);
     if (P.nunits) {
       if (threadIdx.x < 64)
         for (int u = s * 64 + (int)threadIdx.x; u < P.nunits; u += G * 64)
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_batch_split(BStatic S, BCall C, int G,
               fill_unit_field<D>(P, u, C.fields[w], C.bcv[w], C.bct ? C.bct[w] : nullptr,
                                  C.kind[f], ws[threadIdx.x]);
             }
-      inst_barrier(cnt, G * ++arrivals, spin, fault);
+      inst_barrier(cnt, G * ++arrivals, spin, fault, G);
     }
   }
   for (int f = s; f < nf; f += G) surface_item<D>(S, C, i * nf + f, red, part, counter, Fout);
