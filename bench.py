@@ -93,7 +93,7 @@ def kernel_traffic(name, workload):
     """HBM bytes per launch of kernel `name` on `workload` from the committed
     byte-counter summary, or None when it is absent or the kernel's sources
     changed since."""
-    key = name.replace(" + ", "+")
+    key = name.split("<")[0].replace(" + ", "+")
     path = os.path.join(ROOT, "profiles", f"{key}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -202,6 +202,7 @@ class BatchStep:
         self.bc_graph_ok = None
         self.ghosts = 0
         self.band_segments = 0
+        self.shape = (0, 0)   # the forward's launch shape (threads, grid)
 
     def batch(self, stream=None):
         return self.gcr.Batch(spec=self.spec, stream=stream)
@@ -298,6 +299,7 @@ class BatchStep:
         B.foot_points(out=(pk["S"], pk["n"]))
         self.boundary_data(pk)
         B.forward(args=pk["args"])
+        self.shape = B.shape()
         self.ghosts = sum(pk["counts"])
         return B
 
@@ -501,8 +503,11 @@ def roofline_of(W, m, cells):
     each launch), against its algorithmic bytes."""
     d = W.dim
     npts = sum(W.nq)
+    # the forward's kernel: the split sweep for a negative grid, else the
+    # per-item kernel
+    fwd = f"k_batch_split<{d}>" if W.shape[1] < 0 else f"k_batch_forward<{d}>"
     cands = {
-        "k_batch_forward": (m["fwd_ms"], forward_bytes(d, W.nf, m["ghosts"], npts)),
+        fwd: (m["fwd_ms"], forward_bytes(d, W.nf, m["ghosts"], npts)),
         "k_spans + k_classify": (m["stage_ms"]["classify_prepass"] + m["stage_ms"]["classify_store"],
                                  cells),
         "k_levels": (m["stage_ms"]["levels_order"], levels_bytes(d, m["ghosts"])),

@@ -402,6 +402,13 @@ gcr_status gcr_set_batch_tiling(int32_t mode);
  * device (a diagnostic, not for the hot path). */
 gcr_status gcr_batch_tiled(const gcr_batch* batch, int32_t* state);
 
+/* The launch shape a batch's forward calls use (see gcr_set_batch_shape):
+ * *threads per workgroup and *grid, > 0 one workgroup per (instance, field)
+ * item times grid (k_batch_forward), < 0 the split sweep with -grid
+ * workgroups per instance (k_batch_split); both 0 before the first forward
+ * call.  Host only, no synchronisation. */
+gcr_status gcr_batch_shape(const gcr_batch* batch, int32_t* threads, int32_t* grid);
+
 /* Launch shape of the batched forward's level sweep (Sec. 3.2 fill, one
  * level after another).  By default it is picked by timing candidates on the
  * first call for a kind of batch and kept for the process: per-item

@@ -33,7 +33,7 @@ SYMBOLS = [
     "gcr_batch_foot_points",
     "gcr_batch_forward", "gcr_batch_status",
     "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_set_batch_spin",
-    "gcr_batch_tiled", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering",
+    "gcr_batch_tiled", "gcr_batch_shape", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering",
     "gcr_status_str", "gcr_version",
 ]
 
@@ -113,6 +113,7 @@ def lib():
         L.gcr_set_batch_spin.argtypes = [i32]
         L.gcr_batch_status.argtypes = [vp]
         L.gcr_batch_tiled.argtypes = [vp, vp]
+        L.gcr_batch_shape.argtypes = [vp, vp, vp]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_forward_times.argtypes = [vp]
         L.gcr_last_build_times.argtypes = [vp]
@@ -436,6 +437,15 @@ class Batch:
         st = ctypes.c_int32()
         _check(lib().gcr_batch_tiled(self._h, ctypes.byref(st)), "gcr_batch_tiled")
         return st.value
+
+    def shape(self):
+        """gcr_batch_shape: (threads, grid) of the forward's launches; grid < 0
+        the split sweep (k_batch_split), > 0 per-item workgroups
+        (k_batch_forward); (0, 0) before the first forward call."""
+        t, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gcr_batch_shape(self._h, ctypes.byref(t), ctypes.byref(g)),
+               "gcr_batch_shape")
+        return t.value, g.value
 
     def foot_points(self, stream=None, out=None):
         """gcr_batch_foot_points: (S, normal), each f64 [dim][total ghosts],

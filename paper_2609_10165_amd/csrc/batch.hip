@@ -773,6 +773,19 @@ bool take_fwd_events(std::array<hipEvent_t, 3>* ev) {
 }
 }  // namespace
 
+extern "C" gcr_status gcr_batch_shape(const gcr_batch* b, int32_t* threads, int32_t* grid) {
+  if (!b || !threads || !grid) return GCR_E_ARG;
+  *threads = 0;
+  *grid = 0;
+  std::lock_guard<std::mutex> lk(g_bfs_mu);
+  for (auto& e : g_bfs)
+    if (e.first == b) {
+      *threads = e.second->threads;
+      *grid = e.second->grid_mul;
+    }
+  return GCR_OK;
+}
+
 extern "C" gcr_status gcr_batch_tiled(const gcr_batch* b, int32_t* state) {
   if (!b || !state) return GCR_E_ARG;
   BatchFwdState* S = nullptr;
