@@ -439,14 +439,26 @@ gcr_status gcr_set_batch_shape(int32_t threads, int32_t grid);
  * ends. */
 gcr_status gcr_batch_status(const gcr_batch* batch);
 gcr_status gcr_set_batch_spin(int32_t polls);
-/* Layering (Sec. 3.2) of a plan built alone: an instance with at least
- * `min_interface` interface cells is layered by the whole GPU (one grid-wide
- * round per level, then a stable counting sort by level); smaller ones, and
- * every instance of a batch, by one workgroup.  A cycle or a graph deeper
- * than 126 levels hands the instance to the one-workgroup layering, so the
- * result never depends on this setting.  0 restores the default (65536).
- * Process-wide; applies to plans built afterwards. */
+/* Layering (Sec. 3.2).  Every instance is first layered by one workgroup
+ * holding its counters and levels in LDS (up to about 47,000 ghosts).  A
+ * plan built alone that does not fit there and has at least
+ * `min_interface` interface cells is layered by the whole GPU (one
+ * grid-wide round per level, then a stable counting sort by level); the
+ * rest, and instances beyond either, by one workgroup with its state in
+ * HBM.  A cycle or a graph deeper than 126 levels hands an instance from
+ * the whole-GPU layering to the one-workgroup one, so the result never
+ * depends on this setting.  0 restores the default (65536).  Process-wide;
+ * applies to plans built afterwards. */
 gcr_status gcr_set_wide_layering(int64_t min_interface);
+
+/* When the Kahn layering of an instance stalls (its remaining ghosts read a
+ * cycle), a remainder of at most `max_ghosts` ghosts is resolved by one
+ * wave (closure by repeated squaring in registers, no workgroup barrier),
+ * a larger one by the workgroup (trimming, closure, placement rounds).
+ * Both give the same levels and units.  0..64, default 64 (0: always the
+ * workgroup); else GCR_E_ARG.  Process-wide; applies to plans built
+ * afterwards. */
+gcr_status gcr_set_wave_residual(int32_t max_ghosts);
 
 const char* gcr_status_str(gcr_status s);
 const char* gcr_version(void);

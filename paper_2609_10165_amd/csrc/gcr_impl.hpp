@@ -166,12 +166,16 @@ struct LevelsArgs {
   int32_t* wide;         // [kWideState] completion flag, sizes of the levels
   int32_t* hist;         // [kWideLevels][cap / 256 + 1] per-tile level counts
   int cur_cap;           // entries of a level list held in LDS (set at launch)
+  int wave_res;          // residuals up to this size go to the one-wave solver
 };
 constexpr int kWideLevels = 128;               // deepest graph the wide layering orders
 constexpr int kWideState = kWideLevels + 8;
 constexpr int64_t kWideMinInterface = 65536;   // default; smaller instances: one workgroup
 void set_wide_layering(int64_t min_interface);   // 0: the default
 int64_t wide_layering_min();
+constexpr int kWaveResidual = 64;   // most ghosts left by Kahn that one wave resolves
+void set_wave_residual(int max_ghosts);
+int wave_residual();
 gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
 
 // Classification of every cell of a batch into tags (0 fluid, 1 solid, 0x40

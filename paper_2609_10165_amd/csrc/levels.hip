@@ -403,7 +403,163 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
     s_placed = b;
   }
 
-  if (b < n) {
+  if (b < n && n - b <= L.wave_res) {   // (wave_res <= 64)
+    // ---- at most 64 ghosts left (they read a cycle): one wave finds the
+    // cycles and places them, with no workgroup barrier.  Lane u holds
+    // residual ghost res[u] and the set A of residual ghosts it reads; the
+    // closure R = A+ comes from repeated squaring (R |= R o R), the group of
+    // a ghost on a cycle (u in R[u]) is R[u] & {v : u in R[v]}, whose
+    // smallest member is its representative, and the groups' slots follow
+    // their representatives' order.  Then every residual ghost or group is
+    // placed, in dependency order, at 1 + the highest level it reads outside
+    // its group.  The result is the one of the general path below, which
+    // trims ghosts off the cycles first: a ghost on a cycle is never trimmed,
+    // and the levels are the same longest-path levels.
+    if (tid < 64) {
+      const int lane = tid;
+      int32_t* res = tab;          // [64] residual ghosts, ascending
+      int32_t* s_L = tab + 64;     // [64] their levels (0: not placed yet)
+      int32_t* s_c = tab + 128;    // [64] this round's candidates (-1: not ready)
+      int m = 0;
+      for (int g0 = 0; g0 < n; g0 += 64) {
+        const int g = g0 + lane;
+        const bool left = g < n && lvl[g] == 0;
+        const unsigned long long bm = __ballot(left);
+        if (left) res[m + __popcll(bm & ((1ull << lane) - 1ull))] = g;
+        m += __popcll(bm);
+      }
+      s_L[lane] = 0;
+      __builtin_amdgcn_wave_barrier();
+      // dependency q of ghost g as a local id, -1 if it reads no ghost there
+      auto gdep = [&](int g, int q) -> int {
+        const int32_t d = deps[(int64_t)q * cap + lo + g];
+        return d < 0 ? -1 : (int)(d - lo);
+      };
+      // the residual ghosts each lane reads (A) and the highest level among
+      // the ghosts it reads that the layering placed (ext), read once
+      const int g = lane < m ? res[lane] : -1;
+      unsigned long long A = 0ull;
+      int ext = 0;
+      if (lane < m)
+        for (int q = 0; q < np; ++q) {
+          const int d = gdep(g, q);
+          if (d < 0) continue;
+          if (lvl[d] != 0) {
+            ext = max(ext, (int)lvl[d]);
+            continue;
+          }
+          const int v = (int)find_sorted(res, 0, m, d);
+          if (v >= 0) A |= 1ull << v;
+        }
+      unsigned long long R = A;
+      for (int it = 0; it < 7; ++it) {   // 2^7 > 64: paths of every length
+        unsigned long long Rn = R;
+        for (int v = 0; v < m; ++v) {
+          const unsigned long long Rv = __shfl(R, v);
+          if ((R >> v) & 1ull) Rn |= Rv;
+        }
+        const bool grew = Rn != R;
+        R = Rn;
+        if (__ballot(grew) == 0ull) break;
+      }
+      unsigned long long T = 0ull;   // {v : lane in R[v]}
+      for (int u = 0; u < m; ++u) {
+        const unsigned long long col = __ballot(lane < m && ((R >> u) & 1ull));
+        if (lane == u) T = col;
+      }
+      const bool oncyc = lane < m && ((R >> lane) & 1ull);
+      const unsigned long long M = oncyc ? (R & T) : (lane < m ? (1ull << lane) : 0ull);
+      const int rep = oncyc ? __ffsll((long long)M) - 1 : -1;
+      const int size = __popcll(M);
+      const unsigned long long reps = __ballot(oncyc && rep == lane);
+      const int nunits = __popcll(reps);
+      const bool bad = __ballot(oncyc && size > kMaxUnit) != 0ull;
+      int slot = -1;
+      if (oncyc) slot = __popcll(reps & ((1ull << rep) - 1ull));
+      if (!bad && oncyc) {
+        unit_mem[slot * kMaxUnit + __popcll(M & ((1ull << lane) - 1ull))] = (int32_t)(lo + g);
+        blk_idx[lo + g] = slot;
+        if (rep == lane) unit_cnt[slot] = size;
+      }
+      // placement rounds: a ghost (group) is ready once every residual ghost
+      // it reads outside its group is placed; each round places at least
+      // one.  The indices a lane reads each round sit in registers (at most
+      // np residual ghosts read, kMaxUnit group members), so a round's loads
+      // go out together.
+      int dv[7], mv[kMaxUnit];
+      {
+        unsigned long long w = A & ~M;   // read outside the lane's group
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+          dv[q] = w ? __ffsll((long long)w) - 1 : -1;
+          w &= w ? w - 1ull : 0ull;
+        }
+        w = bad ? 0ull : M;
+#pragma unroll
+        for (int j = 0; j < kMaxUnit; ++j) {
+          mv[j] = w ? __ffsll((long long)w) - 1 : -1;
+          w &= w ? w - 1ull : 0ull;
+        }
+      }
+      int Lown = 0;
+      for (int round = 0; !bad && round <= m; ++round) {
+        int c = -1;
+        if (lane < m && Lown == 0) {
+          int lv[7];
+#pragma unroll
+          for (int q = 0; q < 7; ++q) lv[q] = dv[q] >= 0 ? s_L[dv[q]] : 1;
+          c = ext;
+#pragma unroll
+          for (int q = 0; q < 7; ++q)
+            if (dv[q] >= 0) c = (c < 0 || lv[q] == 0) ? -1 : max(c, lv[q]);
+        }
+        s_c[lane] = c;
+        __builtin_amdgcn_wave_barrier();
+        int nl = 0;
+        if (lane < m && Lown == 0) {
+          int cw[kMaxUnit];
+#pragma unroll
+          for (int j = 0; j < kMaxUnit; ++j) cw[j] = mv[j] >= 0 ? s_c[mv[j]] : 0;
+          int mx = 0;
+          bool ok = true;
+#pragma unroll
+          for (int j = 0; j < kMaxUnit; ++j) {
+            ok = ok && cw[j] >= 0;
+            mx = max(mx, cw[j]);
+          }
+          if (ok) nl = mx + 1;
+        }
+        if (nl) {
+          Lown = nl;
+          s_L[lane] = nl;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (__ballot(lane < m && Lown == 0) == 0ull) break;
+      }
+      if (bad) {
+        if (lane == 0) s_bad = 1;
+      } else {
+        const int L = lane < m ? Lown : 0;
+        if (lane < m && L > 0) lvl[g] = (uint16_t)L;
+        if (oncyc && rep == lane) unit_lev[slot] = L;
+        int mxl = L, mxs = oncyc ? size : 0, done = lane < m && L > 0 ? 1 : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          mxl = max(mxl, __shfl_xor(mxl, o));
+          mxs = max(mxs, __shfl_xor(mxs, o));
+          done += __shfl_xor(done, o);
+        }
+        if (lane == 0) {
+          s_units = nunits;
+          s_maxunit = mxs;
+          s_maxlev = max(s_maxlev, mxl);
+          s_placed += done;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_bad) return;
+  } else if (b < n) {
     // ---- the ghosts left read a cycle.  Trim those that no unplaced ghost
     // reads (counters: unplaced readers), repeatedly.
     if (dlds) {

@@ -1335,6 +1335,9 @@ int profiling_mask() { return g_profiling.load(); }
 static std::atomic<int64_t> g_wide_min{kWideMinInterface};
 void set_wide_layering(int64_t v) { g_wide_min.store(v > 0 ? v : kWideMinInterface); }
 int64_t wide_layering_min() { return g_wide_min.load(); }
+static std::atomic<int> g_wave_res{kWaveResidual};
+void set_wave_residual(int v) { g_wave_res.store(v < 0 ? 0 : (v > kWaveResidual ? kWaveResidual : v)); }
+int wave_residual() { return g_wave_res.load(); }
 void last_build_times(float* ms) {
   for (int s = 0; s < kStages; ++s) ms[s] = g_stage_ms[s];
 }
@@ -1674,6 +1677,7 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
       for (int i = 0; i < ninst; ++i) max_if = std::max(max_if, D.if_off[i + 1] - D.if_off[i]);
       L.listB = L.wide = L.hist = nullptr;
       L.cur_cap = 0;
+      L.wave_res = wave_residual();
       if (ninst == 1 && max_if >= wide_layering_min()) {
         // the reverse-edge counters are spent once the edges are filled
         L.listB = D.d_rcnt;

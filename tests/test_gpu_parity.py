@@ -564,3 +564,37 @@ def test_stretched_second_layer_refused_beyond_box_limit(gcr):
     with pytest.raises(gcr.GcrError):
         gcr.Plan(grid, shape, HGC | synth.LAYER2)
     gcr.Plan(grid, shape, HGC)   # the first layer alone is fine
+
+
+# ---------------------------------------------------------------------------
+# cycles: the remainder of a stalled Kahn layering resolved by one wave or
+# by the workgroup (Sec. 3.2: coupled units, levels by longest path)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", [0, 32, 33, 63, "small"])
+def test_cycle_remainder_wave_and_workgroup_agree(gcr, which):
+    """Instances whose layering stalls on cycles (four of the 64-star
+    workload, and a small star): built with the one-wave remainder solver
+    and with the workgroup path, every exported array bit for bit the same,
+    and both equal to the oracle (levels, order, units)."""
+    if which == "small":
+        inst, scheme = synth.stars64(seed=0, ninst=1, nmin=96, nmax=160)[0], CGC
+    else:
+        inst, scheme = synth.stars64(seed=0)[which], HGC
+    op = oracle.OraclePlan(inst.grid, inst.shape, scheme)
+    exports = []
+    try:
+        for limit in (64, 0):
+            gcr.set_wave_residual(limit)
+            gp = gcr.Plan(inst.grid, inst.shape, scheme)
+            exports.append((check_plan(op, gp), gp.stats()))
+    finally:
+        gcr.set_wave_residual(64)
+    (a, sa), (b, sb) = exports
+    for k in a:
+        assert np.array_equal(host(a[k]), host(b[k]), equal_nan=True), k
+    for k in ("n_units_coupled", "max_unit", "n_levels", "max_level_width"):
+        assert sa[k] == sb[k], k
+    assert sa["n_units_coupled"] >= 1 or op.n_units_coupled == 0
+    with pytest.raises(gcr.GcrError):
+        gcr.set_wave_residual(65)
