@@ -366,11 +366,14 @@ gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf,
  * GCR_E_ARG.  With bit 0 set, gcr_plan_create
  * and gcr_batch_create record HIP events on their stream around each stage;
  * gcr_last_build_times copies the device times in milliseconds of the last
- * build on the calling thread into ms[11]: [0] classification, [1] interface
+ * build on the calling thread into ms[13]: [0] classification, [1] interface
  * scan, [2] interface compaction, [3] geometry and ghost tags, [4] ghost
  * compaction, [5] stencils and dependencies, [6] levels and canonical order,
- * [7] finalize; [8], [9], [10] split [0] into the span pre-pass, the store
- * pass and the exact tests near the body. */
+ * [7] finalize; [8], [9], [10] split [0] into the span pass, the store pass
+ * and the interface marks; [11] the stream's wait for the host between the
+ * two halves of the build (the first synchronisation and the sizing of the
+ * ghost arrays); [12] the host time of the whole call (both
+ * synchronisations included). */
 #define GCR_PROFILE_BUILD 1
 #define GCR_PROFILE_FORWARD 2
 gcr_status gcr_set_profiling(int32_t mask);

@@ -530,7 +530,7 @@ class ForwardArgs:
 
 STAGES = ["classify", "interface_scan", "interface_compact", "geometry_tags",
           "ghost_compact", "dependencies", "levels_order", "finalize",
-          "classify_prepass", "classify_store", "classify_band"]
+          "classify_prepass", "classify_store", "classify_band", "sizing_wait", "call_host"]
 
 
 def set_wave_residual(max_ghosts: int = 64):

@@ -14,7 +14,7 @@
 
 namespace gcr {
 
-constexpr int kStages = 11;   // plan-build stages timed by gcr_last_build_times
+constexpr int kStages = 13;   // plan-build stages timed by gcr_last_build_times
 
 
 // Per-instance results of plan building, written by the device.

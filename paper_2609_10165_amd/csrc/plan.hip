@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -1311,13 +1312,17 @@ struct StageEvents {
     if (on) (void)hipEventRecord(ev[i], st);
   }
   hipEvent_t event(int i) const { return on ? ev[i] : nullptr; }
-  void collect() {
+  void collect(double call_ms) {
     if (!on) return;
-    // stages 0..7 as documented; 8..10 split stage 0 into the span pre-pass,
-    // the store pass (k_classify) and the band tests (k_band)
-    const int a[kStages] = {0, 1, 3, 4, 5, 6, 7, 8, 0, 10, 11};
-    const int b[kStages] = {1, 2, 4, 5, 6, 7, 8, 9, 10, 11, 1};
-    for (int s = 0; s < kStages; ++s) {
+    // stages 0..7 as documented; 8..10 split stage 0 into the span pass,
+    // the store pass (k_classify) and the interface marks (k_band_iface);
+    // 11 is the stream's wait for the host between the two halves (the
+    // first synchronisation and the sizing); 12 the call's host time
+    constexpr int kEv = kStages - 1;
+    const int a[kEv] = {0, 1, 3, 4, 5, 6, 7, 8, 0, 10, 11, 2};
+    const int b[kEv] = {1, 2, 4, 5, 6, 7, 8, 9, 10, 11, 1, 3};
+    g_stage_ms[kEv] = (float)call_ms;
+    for (int s = 0; s < kEv; ++s) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[a[s]], ev[b[s]]) != hipSuccess) ms = -1.f;
       g_stage_ms[s] = ms;
@@ -1412,6 +1417,7 @@ gcr_status build_update(BatchData& prev, const ShapeD& shape, bool incremental, 
 // prev, a re-plan of prev's single instance that takes over its tags.
 static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st,
                              BatchData* prev, std::shared_ptr<BatchData>* out) {
+  const auto t_call = std::chrono::steady_clock::now();
   const int ninst = B->ninst;
   std::vector<int64_t> chunk_start(ninst + 1);
   int64_t cells = 0, chunks = 0;
@@ -1722,7 +1728,8 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
   std::memcpy(D.info.data(), PS.p + o_info, sizeof(InstInfo) * ninst);
   std::memcpy(D.lev_off.data(), PS.p + o_lo, 4 * (size_t)ninst * (kMaxLevels + 1));
   std::memcpy(D.unit_lev.data(), PS.p + o_ul, 4 * (size_t)ninst * kMaxUnits);
-  T.collect();
+  T.collect(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call)
+                .count());
   D.ng_total = D.g_off[ninst];
   for (int i = 0; i < ninst; ++i) {
     gcr_status s = status_from_err(D.info[i].err);
