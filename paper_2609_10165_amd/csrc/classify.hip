@@ -243,9 +243,10 @@ __device__ __forceinline__ int seg_settled(const GridD& g, const ShapeD& S, int 
 }
 
 // The store pass, one workgroup per chunk of kChunk cells, a 16-cell row
-// segment per thread.  A wave whose span the pre-pass settled only stores.
-// Otherwise the work is done densely in three rounds, so that no wave runs
-// an expensive test for a few of its lanes: each lane's segment first meets
+// segment per thread.  A wave whose span the span pass settled only stores
+// it (nothing, when the span pass stored it already).  Otherwise the work
+// is done densely in three rounds, so that no wave runs an expensive test
+// for a few of its lanes: each lane's segment first meets
 // the radial bounds (cheap); the segments they leave undecided are listed
 // in LDS and, for star and SH bodies, their Lipschitz tests run one segment
 // per thread; the segments still undecided form the chunk's band, whose
@@ -257,7 +258,8 @@ __device__ __forceinline__ void classify_chunk(int64_t chunk, int ii, const Inst
                                                const int8_t* __restrict__ span,
                                                int8_t* __restrict__ tags,
                                                int32_t* __restrict__ chunk_cnt,
-                                               uint64_t* __restrict__ bandmask) {
+                                               uint64_t* __restrict__ bandmask,
+                                               bool spans_stored) {
   const Inst& I = insts[ii];
   const GridD g = I.g;
   const int64_t chunk_off = I.chunk_off, cell_off = I.cell_off;
@@ -301,9 +303,10 @@ __device__ __forceinline__ void classify_chunk(int64_t chunk, int ii, const Inst
   const int wset = wbase + 64 * kSeg <= g.ncell ? (int)fl[tid >> 6] : -1;
   const bool valid = base64 < g.ncell;
   const int nvalid = valid ? (int)min((int64_t)kSeg, g.ncell - base64) : 0;
-  // round 1: the wave's span settled, else this lane's radial bounds
+  // round 1: the wave's span settled (stored here unless the span pass
+  // stored it), else this lane's radial bounds
   if (wset >= 0) {
-    store_const(tags + cell_off + base64, kSeg, wset);
+    if (!spans_stored) store_const(tags + cell_off + base64, kSeg, wset);
   } else if (valid) {
     const int r = seg_settled(g, S, (int)base64, nvalid, false);
     if (r >= 0) store_const(tags + cell_off + base64, nvalid, r);
@@ -337,10 +340,13 @@ __device__ __forceinline__ void classify_chunk(int64_t chunk, int ii, const Inst
   if (tid == 0) chunk_cnt[chunk] = 0;
 }
 
-// One workgroup per chunk, or (List) workgroups striding over the chunks
-// listed in list[0, *nlist).  (Two instances: the loop costs registers, and
-// so occupancy, that the one-chunk form does without.)
-template <bool List>
+// Mode 0: one workgroup per chunk.  Mode 1: one workgroup per entry of
+// list[first, *nlist), up to the grid's size.  Mode 2: workgroups striding
+// over the entries of list[first, *nlist) (first: the grid of a mode-1
+// launch before it).  The loop of mode 2 costs registers, and so occupancy,
+// that the one-chunk forms do without, so a list is taken by a mode-1 grid
+// and a small mode-2 launch after it for whatever that grid left.
+template <int Mode>
 __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts,
                                                   const int32_t* __restrict__ chunk_inst,
                                                   const int8_t* __restrict__ span,
@@ -348,15 +354,27 @@ __global__ __launch_bounds__(256) void k_classify(const Inst* __restrict__ insts
                                                   int32_t* __restrict__ chunk_cnt,
                                                   uint64_t* __restrict__ bandmask,
                                                   const int32_t* __restrict__ list,
-                                                  const int32_t* __restrict__ nlist) {
-  if (!List) {
-    classify_chunk(blockIdx.x, chunk_inst[blockIdx.x], insts, span, tags, chunk_cnt, bandmask);
+                                                  const int32_t* __restrict__ nlist,
+                                                  bool spans_stored, int first) {
+  if (Mode == 0) {
+    classify_chunk(blockIdx.x, chunk_inst[blockIdx.x], insts, span, tags, chunk_cnt, bandmask,
+                   false);
     return;
   }
   const int nit = nlist[0];
-  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+  if (Mode == 1) {
+    const int it = first + (int)blockIdx.x;
+    if (it < nit) {
+      const int64_t chunk = list[it];
+      classify_chunk(chunk, chunk_inst[chunk], insts, span, tags, chunk_cnt, bandmask,
+                     spans_stored);
+    }
+    return;
+  }
+  for (int it = first + (int)blockIdx.x; it < nit; it += gridDim.x) {
     const int64_t chunk = list[it];
-    classify_chunk(chunk, chunk_inst[chunk], insts, span, tags, chunk_cnt, bandmask);
+    classify_chunk(chunk, chunk_inst[chunk], insts, span, tags, chunk_cnt, bandmask,
+                   spans_stored);
     __syncthreads();   // the LDS lists are reused by the next chunk
   }
 }
@@ -499,8 +517,8 @@ void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, i
       U || every ? nullptr : tags, nband);
   if (ev_prepass) (void)hipEventRecord(ev_prepass, st);
   if (every) {
-    k_classify<false><<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt,
-                                                        mask, nullptr, nullptr);
+    k_classify<0><<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask,
+                                                    nullptr, nullptr, false, 0);
     if (ev_store) (void)hipEventRecord(ev_store, st);
     k_band_iface<<<(unsigned)chunks, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt,
                                                    nband, nullptr, nullptr);
@@ -514,12 +532,17 @@ void launch_classify(const Inst* insts, int ninst, const int64_t* chunk_start, i
       k_dirty_ghosts<<<(unsigned)((U->ng_prev + 255) / 256), 256, 0, st>>>(
           U->ghost_prev, U->ng_prev, W.flag);
   }
-  // the flagged chunks, listed in ascending order, are classified by a grid
-  // that strides over the list (its length stays on the device)
+  // the flagged chunks, listed in ascending order, are classified one
+  // workgroup per entry, and entries beyond that grid (a list longer than
+  // kListGrid) by a striding launch; the list's length stays on the device
   launch_scan(W.flag, chunks, W.scan_excl, W.list, W.nlist, W.scan_tmp, st);
   const unsigned G = (unsigned)std::min<int64_t>(chunks, kListGrid);
-  k_classify<true><<<G, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask, W.list,
-                                      W.nlist);
+  // (a full build's span pass stored the whole settled spans already)
+  k_classify<1><<<G, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask, W.list,
+                                   W.nlist, U == nullptr, 0);
+  if ((int64_t)G < chunks)   // entries beyond the first grid, if any
+    k_classify<2><<<256, 256, 0, st>>>(insts, chunk_inst, span, tags, chunk_cnt, mask, W.list,
+                                       W.nlist, U == nullptr, (int)G);
   if (ev_store) (void)hipEventRecord(ev_store, st);
   k_band_iface<<<G, 256, 0, st>>>(insts, chunk_inst, mask, tags, chunk_cnt, nband, W.list,
                                   W.nlist);
