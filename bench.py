@@ -148,23 +148,26 @@ def bc_star_fields(S, n, cen, beta, out, kinds):
     cos 3y, v = cos(x + 2y), p = exp(x/2) sin y) at the foot points S with
     normals n: field f is Dirichlet where cos(theta_S - beta_f) >= 0 (theta_S
     the angle of S about its body's centre, cen [2][ng]), else Neumann; out
-    [3][ng] the values, kinds [3][ng] uint8 the kinds."""
+    [3][ng] the values, kinds [3][ng] uint8 the kinds.  The three fields go
+    as [3][ng] stacks, so each step is one launch for all of them."""
     import torch
     x, y = S[0], S[1]
     th = torch.atan2(y - cen[1], x - cen[0])
-    s2x, c2x, s3y, c3y = torch.sin(2 * x), torch.cos(2 * x), torch.sin(3 * y), torch.cos(3 * y)
-    a = x + 2 * y
-    sa, ca = torch.sin(a), torch.cos(a)
+    # arguments 2x, 3y, x + 2y, y: their sines and cosines in one launch each
+    arg = torch.stack((x, y, x, y))
+    arg[0].mul_(2.0)
+    arg[1].mul_(3.0)
+    arg[2].add_(y, alpha=2.0)
+    sn, cs = torch.sin(arg), torch.cos(arg)
     e = torch.exp(0.5 * x)
-    sy, cy = torch.sin(y), torch.cos(y)
-    vals = (s2x * c3y, ca, e * sy)
-    dns = (2 * c2x * c3y * n[0] - 3 * s2x * s3y * n[1],
-           -sa * n[0] - 2 * sa * n[1],
-           0.5 * e * sy * n[0] + e * cy * n[1])
-    for f in range(3):
-        dirichlet = torch.cos(th - beta[f]) >= 0
-        kinds[f].copy_(torch.logical_not(dirichlet))
-        torch.where(dirichlet, vals[f], dns[f], out=out[f])
+    n0, n1 = n[0], n[1]
+    vals = torch.stack((sn[0] * cs[1], cs[2], e * sn[3]))
+    dns = torch.stack((2 * cs[0] * cs[1] * n0 - 3 * sn[0] * sn[1] * n1,
+                       -sn[2] * (n0 + 2 * n1),
+                       e * (0.5 * sn[3] * n0 + cs[3] * n1)))
+    dirichlet = torch.cos(th.unsqueeze(0) - beta) >= 0
+    torch.logical_not(dirichlet, out=kinds)
+    torch.where(dirichlet, vals, dns, out=out)
 
 
 # ---------------------------------------------------------------------------
