@@ -881,6 +881,44 @@ __global__ __launch_bounds__(1024) void k_rscan(const int32_t* __restrict__ cnt,
   block_scan_i32(cnt, g_off[ninst], off, sh);
 }
 
+// The same for long inputs, in three passes (tile totals; their scan,
+// k_scan_top; tiles again from their offsets), tiles of kScanTile values.
+// The counts past the ghost count are zero, so scanning the interface
+// capacity gives the same offsets up to the ghost count.
+__global__ __launch_bounds__(1024) void k_iscan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                       int64_t* __restrict__ tsum) {
+  __shared__ int64_t sh[17];
+  const int64_t b = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanT;
+  int64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanT; ++q) sum += b + q < n ? in[b + q] : 0;
+  int64_t tot;
+  (void)block_excl_scan<1024>(sum, &tot, sh);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_iscan_down(const int32_t* __restrict__ in, int64_t n,
+                                                     const int64_t* __restrict__ toff,
+                                                     int32_t* __restrict__ out) {
+  __shared__ int64_t sh[17];
+  const int64_t b = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanT;
+  int v[kScanT];
+  int64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanT; ++q) {
+    v[q] = b + q < n ? in[b + q] : 0;
+    sum += v[q];
+  }
+  int64_t tot;
+  int64_t run = toff[blockIdx.x] + block_excl_scan<1024>(sum, &tot, sh);
+#pragma unroll
+  for (int q = 0; q < kScanT; ++q) {
+    if (b + q < n) out[b + q] = (int32_t)run;
+    run += v[q];
+  }
+  if (b < n && b + kScanT >= n) out[n] = (int32_t)run;   // the thread holding the last value
+}
+
 __global__ __launch_bounds__(256) void k_rfill(const Inst* __restrict__ insts,
                                                const int64_t* __restrict__ g_off, int ninst,
                                                int64_t cap, const int32_t* __restrict__ deps,
@@ -1654,7 +1692,20 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
                                               D.d_g_n, cap, D.d_g_ext, D.d_tags, D.d_htab, D.d_hoff,
                                               D.d_hmask, D.d_g_code, D.d_deps,
                                               D.d_rcnt, D.d_dcnt, D.d_info);
-    k_rscan<<<1, 1024, 0, st>>>(D.d_rcnt, D.d_g_off, ninst, D.d_roff);
+    {
+      // reverse-edge offsets: one workgroup up to two tiles, else three passes
+      // over the interface capacity
+      const int64_t ntiles = (cap + kScanTile - 1) / kScanTile;
+      if (ntiles <= 2) {
+        k_rscan<<<1, 1024, 0, st>>>(D.d_rcnt, D.d_g_off, ninst, D.d_roff);
+      } else {
+        int64_t* tsum = own<int64_t>(D, ntiles + 1);
+        if (!tsum) return GCR_E_NOMEM;
+        k_iscan_reduce<<<(unsigned)ntiles, 1024, 0, st>>>(D.d_rcnt, cap, tsum);
+        k_scan_top<<<1, 1024, 0, st>>>(tsum, ntiles, tsum + ntiles, nullptr);
+        k_iscan_down<<<(unsigned)ntiles, 1024, 0, st>>>(D.d_rcnt, cap, tsum, D.d_roff);
+      }
+    }
     k_rfill<<<blocks(nif, 256), 256, 0, st>>>(D.d_inst, D.d_g_off, ninst, cap, D.d_deps,
                                                D.d_roff, D.d_rcnt + cap, D.d_radj);
     T.mark(7, st);
