@@ -442,17 +442,27 @@ gcr_status gcr_set_batch_shape(int32_t threads, int32_t grid);
  * ends. */
 gcr_status gcr_batch_status(const gcr_batch* batch);
 gcr_status gcr_set_batch_spin(int32_t polls);
-/* Layering (Sec. 3.2).  Every instance is first layered by one workgroup
- * holding its counters and levels in LDS (up to about 47,000 ghosts).  A
- * plan built alone that does not fit there and has at least
- * `min_interface` interface cells is layered by the whole GPU (one
+/* Layering (Sec. 3.2).  At the default setting every instance is first
+ * layered by one workgroup holding its counters and levels in LDS (up to
+ * about 47,000 ghosts); a plan built alone that does not fit there and has
+ * at least 65,536 interface cells is layered by the whole GPU (one
  * grid-wide round per level, then a stable counting sort by level); the
- * rest, and instances beyond either, by one workgroup with its state in
- * HBM.  A cycle or a graph deeper than 126 levels hands an instance from
- * the whole-GPU layering to the one-workgroup one, so the result never
- * depends on this setting.  0 restores the default (65536).  Process-wide;
- * applies to plans built afterwards. */
+ * rest by one workgroup with its state in HBM.  A threshold set here
+ * (`min_interface` > 0) sends every plan built alone with at least that
+ * many interface cells to the whole GPU first, fitting LDS or not (for
+ * tests and measurements).  A cycle or a graph deeper than 126 levels
+ * hands an instance from the whole-GPU layering to the one-workgroup one,
+ * so the result never depends on this setting.  0 restores the default.
+ * Process-wide; applies to plans built afterwards. */
 gcr_status gcr_set_wide_layering(int64_t min_interface);
+
+/* The whole-GPU layering collects each round's newly placed ghosts in a
+ * per-workgroup LDS buffer of `entries` slots (1..4096, default 4096; 0
+ * restores it) and appends the overflow straight to the level's list.  The
+ * result does not depend on it; a small buffer exercises the overflow (for
+ * tests).  Else GCR_E_ARG.  Process-wide; applies to plans built
+ * afterwards. */
+gcr_status gcr_set_wide_buffer(int32_t entries);
 
 /* When the Kahn layering of an instance stalls (its remaining ghosts read a
  * cycle), a remainder of at most `max_ghosts` ghosts is resolved by one

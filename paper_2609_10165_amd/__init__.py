@@ -34,7 +34,7 @@ SYMBOLS = [
     "gcr_batch_forward", "gcr_batch_status",
     "gcr_set_profiling", "gcr_set_batch_tiling", "gcr_set_batch_shape", "gcr_set_batch_spin",
     "gcr_batch_tiled", "gcr_batch_shape", "gcr_last_build_times", "gcr_forward_times", "gcr_set_wide_layering",
-    "gcr_set_wave_residual",
+    "gcr_set_wave_residual", "gcr_set_wide_buffer",
     "gcr_status_str", "gcr_version",
 ]
 
@@ -117,6 +117,7 @@ def lib():
         L.gcr_batch_shape.argtypes = [vp, vp, vp]
         L.gcr_set_wide_layering.argtypes = [ctypes.c_int64]
         L.gcr_set_wave_residual.argtypes = [i32]
+        L.gcr_set_wide_buffer.argtypes = [i32]
         L.gcr_forward_times.argtypes = [vp]
         L.gcr_last_build_times.argtypes = [vp]
         L.gcr_batch_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl,
@@ -537,6 +538,12 @@ def set_wave_residual(max_ghosts: int = 64):
     """Largest remainder of a stalled Kahn layering (ghosts reading a cycle)
     that one wave resolves; larger ones go to the workgroup (0..64)."""
     _check(lib().gcr_set_wave_residual(int(max_ghosts)), "gcr_set_wave_residual")
+
+
+def set_wide_buffer(entries: int = 0):
+    """Slots of the whole-GPU layering's per-workgroup release buffer
+    (1..4096; 0 the default)."""
+    _check(lib().gcr_set_wide_buffer(int(entries)), "gcr_set_wide_buffer")
 
 
 def set_wide_layering(min_interface: int = 0):

@@ -785,6 +785,12 @@ gcr_status gcr_set_wide_layering(int64_t min_interface) {
   return GCR_OK;
 }
 
+gcr_status gcr_set_wide_buffer(int32_t entries) {
+  if (entries < 0 || entries > kWideBuf) return GCR_E_ARG;
+  set_wide_buffer(entries);
+  return GCR_OK;
+}
+
 gcr_status gcr_set_wave_residual(int32_t max_ghosts) {
   if (max_ghosts < 0 || max_ghosts > kWaveResidual) return GCR_E_ARG;
   set_wave_residual(max_ghosts);

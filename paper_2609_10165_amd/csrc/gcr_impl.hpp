@@ -167,7 +167,9 @@ struct LevelsArgs {
   int32_t* hist;         // [kWideLevels][cap / 256 + 1] per-tile level counts
   int cur_cap;           // entries of a level list held in LDS (set at launch)
   int wave_res;          // residuals up to this size go to the one-wave solver
+  int wide_cap;          // entries of the wide layering's per-workgroup release buffer
 };
+constexpr int kWideBuf = 4096;   // its LDS capacity
 constexpr int kWideLevels = 128;               // deepest graph the wide layering orders
 constexpr int kWideState = kWideLevels + 8;
 constexpr int64_t kWideMinInterface = 65536;   // default; smaller instances: one workgroup
@@ -176,6 +178,9 @@ int64_t wide_layering_min();
 constexpr int kWaveResidual = 64;   // most ghosts left by Kahn that one wave resolves
 void set_wave_residual(int max_ghosts);
 int wave_residual();
+void set_wide_buffer(int entries);   // 0: the default (kWideBuf)
+int wide_buffer();
+bool wide_layering_forced();         // a threshold set explicitly
 gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStream_t st);
 
 // Classification of every cell of a batch into tags (0 fluid, 1 solid, 0x40

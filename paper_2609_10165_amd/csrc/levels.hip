@@ -72,8 +72,37 @@ __device__ __forceinline__ void wave_push(bool p, int v, int32_t* list, int32_t*
   if (p) list[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
 }
 
+// Appends v for the lanes with p set to a workgroup's LDS buffer buf (fill
+// count *s_n, capacity cap), one LDS atomic per wave; entries beyond the
+// capacity go straight to the global list glist (length *gsize), one global
+// atomic per wave that has any.  *s_n keeps counting past cap.
+__device__ __forceinline__ void wave_push_buf(bool p, int v, int32_t* buf, int* s_n, int cap,
+                                              int32_t* glist, int32_t* gsize) {
+  const unsigned long long m = __ballot(p);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(s_n, __popcll(m));
+  base = __shfl(base, leader);
+  const int idx = base + __popcll(m & lt);
+  const bool spill = p && idx >= cap;
+  if (p && !spill) buf[idx] = v;
+  const unsigned long long ms = __ballot(spill);
+  if (ms == 0ull) return;
+  const int ls = __ffsll((long long)ms) - 1;
+  int gb = 0;
+  if (lane == ls) gb = atomicAdd(gsize, __popcll(ms));
+  gb = __shfl(gb, ls);
+  if (spill) glist[gb + __popcll(ms & lt)] = v;
+}
+
 // Wide layering of instance 0.  wide[0] = 1 when it finished (levels,
 // canonical order, level offsets and info final), wide[r] = size of level r.
+// Each round's releases collect in the workgroup's LDS buffer and join the
+// next level's list with one global atomic per workgroup (the order inside
+// a level's list is free: the counting sort orders the level).
 __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
@@ -95,6 +124,9 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
   __shared__ int64_t sh[8];
   __shared__ int s_hist[kWideLevels];
   __shared__ int s_wc[4][kWideLevels];
+  __shared__ int32_t s_buf[kWideBuf];
+  __shared__ int s_n, s_base;
+  const int wcap = min(max(L.wide_cap, 1), kWideBuf);
   if (L.info[0].layered) return;   // the LDS layering finished it (every workgroup leaves)
 
   // counters of ghosts read, four per word; no ghost is in a unit
@@ -108,12 +140,22 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
   if (blockIdx.x == 0)
     for (int r = tid; r < kWideState; r += 256) size[r] = 0;
   grid.sync();
-  // level 1: ghosts that read no ghost
+  // level 1: ghosts that read no ghost (through the workgroup's buffer,
+  // flushed as after each round)
+  if (tid == 0) s_n = 0;
+  __syncthreads();
   for (int64_t g0 = (int64_t)blockIdx.x * 256; g0 < n; g0 += GT) {
     const int g = (int)(g0 + tid);
     const bool p = g < n && dcnt[g] == 0;
     if (p) lev[g] = 1;
-    wave_push(p, g, lists[1], &size[1]);
+    wave_push_buf(p, g, s_buf, &s_n, wcap, lists[1], &size[1]);
+  }
+  __syncthreads();
+  {
+    const int mcount = min(s_n, wcap);
+    if (tid == 0 && mcount > 0) s_base = atomicAdd(&size[1], mcount);
+    __syncthreads();
+    for (int k = tid; k < mcount; k += 256) lists[1][s_base + k] = s_buf[k];
   }
   grid.sync();
 
@@ -132,6 +174,8 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
     }
     const int32_t* __restrict__ cur = lists[r & 1];
     int32_t* __restrict__ nxt = lists[(r + 1) & 1];
+    if (tid == 0) s_n = 0;
+    __syncthreads();
     for (int64_t i = gt; i < sz; i += GT) {
       const int g = cur[i];
       const int e1 = roff[g + 1];
@@ -139,8 +183,15 @@ __global__ __launch_bounds__(256) void k_levels_wide(LevelsArgs L) {
         const int q = (int)(radj[e] - lo);
         const bool rel = cnt_dec(cnt, q) == 1u;
         if (rel) lev[q] = r + 1;
-        wave_push(rel, q, nxt, &size[r + 1]);
+        wave_push_buf(rel, q, s_buf, &s_n, wcap, nxt, &size[r + 1]);
       }
+    }
+    __syncthreads();
+    {
+      const int mcount = min(s_n, wcap);
+      if (tid == 0 && mcount > 0) s_base = atomicAdd(&size[r + 1], mcount);
+      __syncthreads();
+      for (int k = tid; k < mcount; k += 256) nxt[s_base + k] = s_buf[k];
     }
     ++r;
     grid.sync();
@@ -1232,10 +1283,10 @@ gcr_status launch_levels(const LevelsArgs& L, int ninst, int64_t max_n, hipStrea
   const int64_t bytes = 4 * (((nn + 3) >> 2) + ((nn + 31) >> 5));
   LevelsArgs F = L;   // the one-workgroup layering
   F.wide = nullptr;
-  {
+  if (!(L.wide && ninst == 1 && wide_layering_forced())) {
     // the LDS layering first (an instance that fits it is layered there even
-    // when the wide layering is armed); k_levels_wide and k_levels below
-    // skip what it finished
+    // when the wide layering is armed, unless a threshold set explicitly
+    // forces it); k_levels_wide and k_levels below skip what it finished
     static int fast_lds = -1;
     lk.lock();
     if (fast_lds < 0) {

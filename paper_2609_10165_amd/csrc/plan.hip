@@ -1381,6 +1381,10 @@ int64_t wide_layering_min() { return g_wide_min.load(); }
 static std::atomic<int> g_wave_res{kWaveResidual};
 void set_wave_residual(int v) { g_wave_res.store(v < 0 ? 0 : (v > kWaveResidual ? kWaveResidual : v)); }
 int wave_residual() { return g_wave_res.load(); }
+static std::atomic<int> g_wide_buf{kWideBuf};
+void set_wide_buffer(int v) { g_wide_buf.store(v <= 0 || v > kWideBuf ? kWideBuf : v); }
+int wide_buffer() { return g_wide_buf.load(); }
+bool wide_layering_forced() { return g_wide_min.load() != kWideMinInterface; }
 void last_build_times(float* ms) {
   for (int s = 0; s < kStages; ++s) ms[s] = g_stage_ms[s];
 }
@@ -1735,6 +1739,7 @@ static gcr_status build_core(const std::shared_ptr<BatchData>& B, hipStream_t st
       L.listB = L.wide = L.hist = nullptr;
       L.cur_cap = 0;
       L.wave_res = wave_residual();
+      L.wide_cap = wide_buffer();
       if (ninst == 1 && max_if >= wide_layering_min()) {
         // the reverse-edge counters are spent once the edges are filled
         L.listB = D.d_rcnt;

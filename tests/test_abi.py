@@ -66,3 +66,7 @@ def test_process_wide_settings_validate_their_arguments():
     assert L.gcr_set_batch_tiling(3) == 1 and L.gcr_set_batch_tiling(-1) == 1
     assert L.gcr_set_batch_tiling(1) == 0
     assert L.gcr_set_profiling(4) == 1 and L.gcr_set_profiling(0) == 0
+    assert L.gcr_set_wave_residual(65) == 1 and L.gcr_set_wave_residual(-1) == 1
+    assert L.gcr_set_wave_residual(64) == 0
+    assert L.gcr_set_wide_buffer(4097) == 1 and L.gcr_set_wide_buffer(-1) == 1
+    assert L.gcr_set_wide_buffer(0) == 0

@@ -187,11 +187,15 @@ def test_plan_airfoil(gcr):
     check_plan(op, gp)
 
 
-@pytest.fixture
-def wide(gcr):
-    gcr.set_wide_layering(1)   # every plan built alone is layered grid-wide
+@pytest.fixture(params=[0, 1])
+def wide(gcr, request):
+    # every plan built alone is layered grid-wide; with a release buffer of
+    # one slot per workgroup nearly every placed ghost takes the overflow
+    gcr.set_wide_layering(1)
+    gcr.set_wide_buffer(request.param)
     yield
     gcr.set_wide_layering(0)
+    gcr.set_wide_buffer(0)
 
 
 def _layering_case(case):
@@ -231,6 +235,15 @@ def test_plan_shstar384_full_size(gcr):
     assert op.n_interface >= 65536
     assert op.min_margin > 1e-9
     check_plan(op, gp)
+
+
+def test_plan_beyond_lds_layering(gcr):
+    # 74,006 ghosts: more than the one-workgroup LDS layering holds, so the
+    # default takes the grid-wide layering (17 levels)
+    inst = synth.sphere256(seed=0, n=512)
+    op, gp = plan_pair(gcr, inst, HGC)
+    assert op.n_ghost > 50000 and op.n_interface >= 65536
+    check_plan(op, gp, strict_geometry=True)
 
 
 # ---------------------------------------------------------------------------
