@@ -173,12 +173,142 @@ __device__ __forceinline__ void surface_item(const BStatic& S, const BCall& C, i
   __syncthreads();
 }
 
+// The levels of a 2D item, swept in LDS.  A prologue takes every ghost of
+// the item at once: its weights (as fill_single computes them), the term of
+// its boundary value, and per stencil corner either the product of weight
+// and fluid value or, for a corner that is a ghost, the weight and that
+// ghost's position, into a record of kRecWords doubles (bit 63 of the last
+// word marks a member of a coupled unit).  The levels then read only LDS,
+// the first word of each record becoming the ghost's value once computed;
+// the terms are added in corner order, as fill_single adds them, and each
+// level's coupled units are solved as fill_unit_field solves them, so the
+// values are the same bits.  An epilogue stores the values into the field.
+constexpr int kRecWords = 5;
+constexpr int kRecUnitWS = 8;   // unit workspaces after the records
+constexpr uint32_t kRecFluid = 0xffffu, kRecSkip = 0xfffeu;
+constexpr uint64_t kRecMember = 1ull << 63;
+
+// Coupled unit u of an LDS sweep: (I - W_int) phi = W_ext phi_ext + w0 b,
+// assembled from the members' records in fill_unit_field's order.
+__device__ __forceinline__ void unit_lds2(const PlanD& P, int u, double* rec, UnitWS& ws) {
+  const int k = P.unit_cnt[u];
+  for (int i = 0; i < k; ++i) ws.mem[i] = P.unit_mem[u * kMaxUnit + i];
+  for (int i = 0; i < k; ++i) {
+    const double* r = rec + (int64_t)kRecWords * ws.mem[i];
+    const uint64_t pk = (uint64_t)__double_as_longlong(r[4]);
+    for (int t = 0; t < k; ++t) ws.M[i * k + t] = (t == i) ? 1.0 : 0.0;
+    double rr = r[0];
+    for (int c = 1; c < 4; ++c) {
+      const uint32_t id = (uint32_t)(pk >> (16 * (c - 1))) & 0xffffu;
+      if (id == kRecSkip) continue;
+      if (id == kRecFluid) {
+        rr += r[c];
+        continue;
+      }
+      int t = -1;
+      for (int s = 0; s < k; ++s)
+        if (ws.mem[s] == (int)id) t = s;
+      if (t >= 0) ws.M[i * k + t] -= r[c];
+      else rr += r[c] * rec[(int64_t)kRecWords * id];
+    }
+    ws.rhs[i] = rr;
+  }
+  ws_solve(ws, k);
+  for (int i = 0; i < k; ++i) rec[(int64_t)kRecWords * ws.mem[i]] = ws.rhs[i];
+}
+__device__ __forceinline__ void sweep_lds2(const PlanD& P, const int32_t* __restrict__ lev_off,
+                                           int nl, double* __restrict__ F,
+                                           const double* __restrict__ b,
+                                           const uint8_t* __restrict__ bt, int kind,
+                                           double* rec, int rec_cap) {
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int ng = P.ng;
+  for (int p = tid; p < ng; p += T) {
+    const int c = P.cell[p];
+    const uint32_t code = P.code[p];
+    double dl[3] = {P.dl[0][p], P.dl[1][p], 0.0}, nn[3] = {P.nn[0][p], P.nn[1][p], 0.0}, w[8];
+    const bool member = P.blk[p] >= 0;
+    const int bc = kind == 2 ? (int)bt[p] : kind;
+    const double bv = b[p];
+    double X[3];
+    stencil_span(P.g, code, c, X);
+    ghost_weights<2>(dl, nn, X, bc, w);
+    const uint32_t skip = code_skip(code);
+    double* r = rec + (int64_t)kRecWords * p;
+    r[0] = w[0] * bv;
+    // the corners' tags and values in one round of loads (a skipped corner
+    // reads the ghost's own cell, unused); only ghost corners (tag +-2)
+    // search the lookup table
+    int q[4];
+    int8_t tg[4];
+    double fv[4];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) q[k] = (k & skip) ? c : c + corner_offset(P.g, code, k);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      tg[k] = P.tags[q[k]];
+      fv[k] = F[q[k]];
+    }
+    uint64_t pk = member ? kRecMember : 0ull;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      uint64_t id = kRecSkip;
+      double t = 0.0;
+      if (!(k & skip)) {
+        const int g = (tg[k] == 2 || tg[k] == -2) ? ghost_at(P, q[k]) : -1;
+        if (g >= 0) {
+          id = (uint64_t)g;
+          t = w[k];
+        } else {
+          id = kRecFluid;
+          t = w[k] * fv[k];
+        }
+      }
+      r[k] = t;
+      pk |= id << (16 * (k - 1));
+    }
+    r[4] = __longlong_as_double((long long)pk);
+  }
+  __syncthreads();
+  for (int l = 0; l < nl; ++l) {
+    const int lo = lev_off[l], hi = lev_off[l + 1];
+    for (int p = lo + tid; p < hi; p += T) {
+      double* r = rec + (int64_t)kRecWords * p;
+      const uint64_t pk = (uint64_t)__double_as_longlong(r[4]);
+      if (pk & kRecMember) continue;   // solved with its unit below
+      double v = r[0];
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+        const uint32_t id = (uint32_t)(pk >> (16 * (k - 1))) & 0xffffu;
+        if (id == kRecSkip) continue;
+        v += id == kRecFluid ? r[k] : r[k] * rec[(int64_t)kRecWords * id];
+      }
+      r[0] = v;
+    }
+    __syncthreads();
+    if (P.nunits) {
+      UnitWS* ws = reinterpret_cast<UnitWS*>(rec + (int64_t)kRecWords * rec_cap);
+      if (tid < kRecUnitWS)
+        for (int s = tid; s < P.nunits; s += kRecUnitWS)
+          if (P.unit_lev[s] == l + 1) unit_lds2(P, s, rec, ws[tid]);
+      __syncthreads();
+    }
+  }
+  for (int p = tid; p < ng; p += T) F[P.cell[p]] = rec[(int64_t)kRecWords * p];
+  __syncthreads();
+}
+
+// (LDS, dynamic: the surface part's reduction rows, the coupled units'
+// workspaces and the 2D sweep records share it; the records of an item are
+// dead before the rows are used, and the sweep's unit workspaces follow the
+// records.  rec_cap: the largest item, in ghosts, the records may hold.)
 template <int D>
 __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, double* __restrict__ part,
                                                         int* __restrict__ counter,
-                                                        double* __restrict__ Fout) {
-  __shared__ double red[1024][3];
-  __shared__ UnitWS ws[64];
+                                                        double* __restrict__ Fout, int rec_cap) {
+  extern __shared__ double s_lds[];
+  double(*red)[3] = reinterpret_cast<double(*)[3]>(s_lds);
+  UnitWS* ws = reinterpret_cast<UnitWS*>(s_lds);
   const int T = blockDim.x;
   for (int it = blockIdx.x; it < C.nitems; it += gridDim.x) {
     const int w = C.order[it];
@@ -190,6 +320,11 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
     const int kind = C.kind[f];
     const int32_t* lo_ = S.lev_off[i];
     const int nl = (C.tile_flag && C.tile_flag[0] == 0) ? 0 : S.nlev[i];
+    if (D == 2 && nl > 0 && P.ng <= rec_cap) {
+      sweep_lds2(P, lo_, nl, F, b, bt, kind, s_lds, rec_cap);
+      surface_item<D>(S, C, w, red, part, counter, Fout);
+      continue;
+    }
     for (int l = 0; l < nl; ++l) {
       const int lo = lo_[l], hi = lo_[l + 1];
       for (int p = lo + (int)threadIdx.x; p < hi; p += T) fill_single<D>(P, p, F, b, bt, kind);
@@ -639,6 +774,7 @@ struct BatchFwdState {
   // are released only once the last one has run, on whatever stream
   hipEvent_t ev_done = nullptr;
   int threads = 0, grid_mul = 0;   // tuned
+  int rec_ng = 0;                  // ghosts of the largest 2D instance
   // tiled fill: 0 not set up yet, 1 set up, -1 not used for this batch
   int tiled = 0;
   int calls = 0;                   // forward calls so far
@@ -698,6 +834,7 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
     pv[i] = plan_view(b->plans[i].get());
     lp[i] = b->plans[i]->d_lev_off;
     nl[i] = b->plans[i]->nlev;
+    if (pv[i].g.dim == 2) S->rec_ng = std::max(S->rec_ng, pv[i].ng);
   }
   // one upload from pinned staging: plans | level-offset pointers | level
   // counts | force counters and two sets of level counters (zero), each
@@ -1010,6 +1147,30 @@ static int split_capacity(int dim, int threads) {
   return c;
 }
 
+// Ghosts a workgroup's LDS can hold as sweep records (k_batch_forward), from
+// the device's largest dynamic LDS, which the forward kernels are allowed
+// once; 0 where that fails.
+static int forward_rec_cap() {
+  static std::mutex mu;
+  static int cap = -1;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cap >= 0) return cap;
+  int dev = 0, a = 0, o = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) a = 0;
+  if (hipDeviceGetAttribute(&o, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) o = 0;
+  const int v = std::max(a, o) & ~255;
+  bool ok = v > (int)(kRecUnitWS * sizeof(UnitWS));
+  for (const void* k : {reinterpret_cast<const void*>(&k_batch_forward<2>),
+                        reinterpret_cast<const void*>(&k_batch_forward<3>)})
+    ok = ok && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
+  (void)hipGetLastError();
+  cap = ok ? std::min<int>((v - (int)(kRecUnitWS * sizeof(UnitWS))) / (kRecWords * (int)sizeof(double)),
+                           (int)kRecSkip - 1)
+           : 0;
+  return cap;
+}
+
 // gm > 0: per-item kernel over min(items, 256 gm) workgroups; gm < 0: split
 // sweep with -gm workgroups per instance, launched cooperatively (refused
 // with GCR_E_UNSUPPORTED where its workgroups cannot all be resident).
@@ -1043,10 +1204,18 @@ static gcr_status launch_batch(BatchFwdState* S, const BCall& C, int dim, int th
                                        st));
   } else {
     const int grid = std::min(C.nitems, 256 * gm);
+    // LDS: the reduction rows, the unit workspaces, or (2D) the sweep records
+    // of the largest item that takes them, whichever is largest
+    const int rcap = forward_rec_cap();
+    const int rec = dim == 2 && S->rec_ng <= rcap ? S->rec_ng : 0;
+    const size_t lds =
+        std::max({(size_t)threads * 3 * sizeof(double), 64 * sizeof(UnitWS),
+                  rec ? (size_t)rec * kRecWords * sizeof(double) + kRecUnitWS * sizeof(UnitWS) : 0});
+    if (rcap == 0 && lds > 64 * 1024) return GCR_E_UNSUPPORTED;
     if (dim == 2)
-      k_batch_forward<2><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+      k_batch_forward<2><<<grid, threads, lds, st>>>(bs, C, S->d_part, S->d_counter, F, rec);
     else
-      k_batch_forward<3><<<grid, threads, 0, st>>>(bs, C, S->d_part, S->d_counter, F);
+      k_batch_forward<3><<<grid, threads, lds, st>>>(bs, C, S->d_part, S->d_counter, F, rec);
   }
   GCR_HIP(hipGetLastError());
   return GCR_OK;
