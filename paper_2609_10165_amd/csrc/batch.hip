@@ -230,39 +230,25 @@ __device__ __forceinline__ void sweep_lds2(const PlanD& P, const int32_t* __rest
     const bool member = P.blk[p] >= 0;
     const int bc = kind == 2 ? (int)bt[p] : kind;
     const double bv = b[p];
+    int gi[4];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) gi[k] = P.cgi[(int64_t)(k - 1) * ng + p];
     double X[3];
     stencil_span(P.g, code, c, X);
     ghost_weights<2>(dl, nn, X, bc, w);
-    const uint32_t skip = code_skip(code);
     double* r = rec + (int64_t)kRecWords * p;
     r[0] = w[0] * bv;
-    // the corners' tags and values in one round of loads (a skipped corner
-    // reads the ghost's own cell, unused); only ghost corners (tag +-2)
-    // search the lookup table
-    int q[4];
-    int8_t tg[4];
-    double fv[4];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) q[k] = (k & skip) ? c : c + corner_offset(P.g, code, k);
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      tg[k] = P.tags[q[k]];
-      fv[k] = F[q[k]];
-    }
     uint64_t pk = member ? kRecMember : 0ull;
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
       uint64_t id = kRecSkip;
       double t = 0.0;
-      if (!(k & skip)) {
-        const int g = (tg[k] == 2 || tg[k] == -2) ? ghost_at(P, q[k]) : -1;
-        if (g >= 0) {
-          id = (uint64_t)g;
-          t = w[k];
-        } else {
-          id = kRecFluid;
-          t = w[k] * fv[k];
-        }
+      if (gi[k] >= 0) {
+        id = (uint64_t)gi[k];
+        t = w[k];
+      } else if (gi[k] == -1) {
+        id = kRecFluid;
+        t = w[k] * F[c + corner_offset(P.g, code, k)];
       }
       r[k] = t;
       pk |= id << (16 * (k - 1));
@@ -320,7 +306,7 @@ __global__ __launch_bounds__(1024) void k_batch_forward(BStatic S, BCall C, doub
     const int kind = C.kind[f];
     const int32_t* lo_ = S.lev_off[i];
     const int nl = (C.tile_flag && C.tile_flag[0] == 0) ? 0 : S.nlev[i];
-    if (D == 2 && nl > 0 && P.ng <= rec_cap) {
+    if (D == 2 && nl > 0 && P.ng <= rec_cap && P.cgi) {
       sweep_lds2(P, lo_, nl, F, b, bt, kind, s_lds, rec_cap);
       surface_item<D>(S, C, w, red, part, counter, Fout);
       continue;
@@ -775,6 +761,7 @@ struct BatchFwdState {
   hipEvent_t ev_done = nullptr;
   int threads = 0, grid_mul = 0;   // tuned
   int rec_ng = 0;                  // ghosts of the largest 2D instance
+  int32_t* d_cgi = nullptr;        // corners' ghosts of the 2D plans (PlanD::cgi)
   // tiled fill: 0 not set up yet, 1 set up, -1 not used for this batch
   int tiled = 0;
   int calls = 0;                   // forward calls so far
@@ -821,6 +808,26 @@ std::mutex g_bfs_mu;
 // the device pool they return memory to may already be gone by then
 auto& g_bfs = *new std::vector<std::pair<const gcr_batch*, std::unique_ptr<BatchFwdState>>>();
 
+// The corners' ghosts of the batch's 2D plans, once per batch: one thread
+// per ghost (flattened over the plans, off[i] the first of plan i), corner
+// k + 1 of ghost p at cgi[3 off[i] + k ng + p]: the ghost's position from
+// the lookup table, -1 for a fluid corner, -2 for a skipped one.
+__global__ __launch_bounds__(256) void k_corner_ghosts(const PlanD* __restrict__ plans,
+                                                       const int64_t* __restrict__ off, int n,
+                                                       int32_t* __restrict__ cgi) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= off[n]) return;
+  const int i = find_inst(off, n, e);
+  const PlanD& P = plans[i];
+  const int p = (int)(e - off[i]);
+  const int c = P.cell[p];
+  const uint32_t code = P.code[p];
+  const uint32_t skip = code_skip(code);
+  int32_t* out = cgi + 3 * off[i];
+  for (int k = 1; k < 4; ++k)
+    out[(int64_t)(k - 1) * P.ng + p] = (k & skip) ? -2 : ghost_at(P, c + corner_offset(P.g, code, k));
+}
+
 BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   std::lock_guard<std::mutex> lk(g_bfs_mu);
   for (auto& e : g_bfs)
@@ -830,11 +837,23 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   std::vector<PlanD> pv(n);
   std::vector<int32_t*> lp(n);
   std::vector<int32_t> nl(n);
+  std::vector<int64_t> coff(n + 1, 0);   // ghosts of the 2D plans before plan i
   for (int i = 0; i < n; ++i) {
     pv[i] = plan_view(b->plans[i].get());
     lp[i] = b->plans[i]->d_lev_off;
     nl[i] = b->plans[i]->nlev;
     if (pv[i].g.dim == 2) S->rec_ng = std::max(S->rec_ng, pv[i].ng);
+    coff[i + 1] = coff[i] + (pv[i].g.dim == 2 ? pv[i].ng : 0);
+  }
+  if (coff[n] > 0) {
+    S->d_cgi = static_cast<int32_t*>(pool_alloc(sizeof(int32_t) * 3 * coff[n]));
+    if (!S->d_cgi) {
+      *err = GCR_E_NOMEM;
+      return nullptr;
+    }
+    S->owned.push_back(S->d_cgi);
+    for (int i = 0; i < n; ++i)
+      if (pv[i].g.dim == 2) pv[i].cgi = S->d_cgi + 3 * coff[i];
   }
   // one upload from pinned staging: plans | level-offset pointers | level
   // counts | force counters and two sets of level counters (zero), each
@@ -843,7 +862,8 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   const size_t o_lp = al(sizeof(PlanD) * n), o_nl = o_lp + al(sizeof(int32_t*) * n);
   const size_t o_ct = o_nl + al(sizeof(int32_t) * n), o_bar = o_ct + al(sizeof(int) * n);
   const size_t o_fault = o_bar + al(sizeof(int) * 2 * n);
-  const size_t bytes = o_fault + al(sizeof(int));
+  const size_t o_coff = o_fault + al(sizeof(int));
+  const size_t bytes = o_coff + al(sizeof(int64_t) * (n + 1));
   char* d = static_cast<char*>(pool_alloc(bytes));
   if (d) S->owned.push_back(d);
   S->h_static = static_cast<char*>(pinned_alloc(bytes));
@@ -861,9 +881,16 @@ BatchFwdState* state_of(gcr_batch* b, hipStream_t st, gcr_status* err) {
   std::memcpy(S->h_static, pv.data(), sizeof(PlanD) * n);
   std::memcpy(S->h_static + o_lp, lp.data(), sizeof(int32_t*) * n);
   std::memcpy(S->h_static + o_nl, nl.data(), sizeof(int32_t) * n);
+  std::memcpy(S->h_static + o_coff, coff.data(), sizeof(int64_t) * (n + 1));
   S->ev_static = event_take();
-  if (!S->ev_static || hipMemcpyAsync(d, S->h_static, bytes, hipMemcpyHostToDevice, st) ||
-      hipEventRecord(S->ev_static, st)) {
+  if (!S->ev_static || hipMemcpyAsync(d, S->h_static, bytes, hipMemcpyHostToDevice, st)) {
+    *err = GCR_E_HIP;
+    return nullptr;
+  }
+  if (coff[n] > 0)
+    k_corner_ghosts<<<(unsigned)((coff[n] + 255) / 256), 256, 0, st>>>(
+        S->d_plans, reinterpret_cast<const int64_t*>(d + o_coff), n, S->d_cgi);
+  if (hipGetLastError() != hipSuccess || hipEventRecord(S->ev_static, st)) {
     *err = GCR_E_HIP;
     return nullptr;
   }

@@ -163,6 +163,7 @@ PlanD plan_view(const gcr_plan* p) {
   P.hmask = p->hmask;
   P.nunits = p->info.nunits;
   P.unit_lev = p->unit_lev;
+  P.cgi = nullptr;
   return P;
 }
 

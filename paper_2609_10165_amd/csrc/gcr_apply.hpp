@@ -27,6 +27,9 @@ struct PlanD {
   unsigned hmask;
   int nunits;                  // coupled units
   const int32_t* unit_lev;     // their levels (1-based)
+  // batched forward, 2D: [3][ng] the position of corner k + 1's ghost, -1 for
+  // a fluid corner, -2 for a skipped one (null elsewhere)
+  const int32_t* cgi;
 };
 
 constexpr unsigned long long kHashEmpty = ~0ull;
