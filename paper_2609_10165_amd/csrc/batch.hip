@@ -59,20 +59,33 @@ struct BCall {
 
 // Anchor ghost of every surface point of every instance, one group of lanes
 // per point (the search is geometry only, so the fields' items share it).
+// With a row of workgroups per instance (gridDim.y = instances) a workgroup
+// knows its instance; otherwise (one row) each point searches the offsets.
 template <int D>
 __global__ __launch_bounds__(256) void k_batch_anchor(BStatic S, BCall C, int64_t npts,
                                                       int32_t* __restrict__ anchor) {
   constexpr int NL = anchor_lanes<D>();
   constexpr int PPB = 256 / NL;
   const int sub = (int)threadIdx.x % NL;
-  const int64_t gq = (int64_t)blockIdx.x * PPB + (int)threadIdx.x / NL;
-  const bool active = gq < npts;
+  const int64_t pb = (int64_t)blockIdx.x * PPB + (int)threadIdx.x / NL;
   int i = 0;
-  int64_t q = 0;
+  int64_t q = 0, gq = 0;
+  bool active;
+  if (gridDim.y > 1) {
+    i = (int)blockIdx.y;
+    q = pb;
+    active = q < C.nq[i];
+    gq = C.aoff[i] + q;
+  } else {
+    gq = pb;
+    active = gq < npts;
+    if (active) {
+      i = find_inst(C.aoff, C.ninst, gq);
+      q = gq - C.aoff[i];
+    }
+  }
   double x[3] = {0.0, 0.0, 0.0};
   if (active) {
-    i = find_inst(C.aoff, C.ninst, gq);
-    q = gq - C.aoff[i];
     const int64_t nq = C.nq[i];
 #pragma unroll
     for (int a = 0; a < D; ++a) x[a] = C.xq[i][a * nq + q];
@@ -1334,6 +1347,21 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   std::vector<int32_t> order(nitems);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  // (the sort keeps an instance's nf items adjacent: their costs are equal)
+  // Workgroups go to the eight XCDs in turn, each with its own L2: the items
+  // of one instance, which read the same plan data, are placed 8 apart, so
+  // that with a workgroup per item they share an XCD.  Instances are taken
+  // in groups of eight by rank, which keeps the order largest first by group.
+  if (nf > 1 && n >= 8) {
+    std::vector<int32_t> x(nitems);
+    const int full = n / 8 * 8;
+    for (int r = 0; r < n; ++r)
+      for (int f = 0; f < nf; ++f) {
+        const int src = r * nf + f;
+        x[r < full ? (r / 8) * 8 * nf + 8 * f + r % 8 : src] = order[src];
+      }
+    order.swap(x);
+  }
   // call table: one upload
   const size_t np = (size_t)nitems;
   const size_t bytes = sizeof(void*) * (5 * np + 3 * n) + sizeof(int64_t) * (2 * n + 1) +
@@ -1432,15 +1460,19 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   if (timed) (void)hipEventRecord(ev[0], st);
   if (npts > 0) {
     BStatic bs{S->d_plans, S->d_levp, S->d_nlev};
-    if (dim == 2) {
-      constexpr int ppb = 256 / anchor_lanes<2>();
-      k_batch_anchor<2><<<(unsigned)((npts + ppb - 1) / ppb), 256, 0, st>>>(bs, C, npts,
-                                                                           S->d_anchor);
-    } else {
-      constexpr int ppb = 256 / anchor_lanes<3>();
-      k_batch_anchor<3><<<(unsigned)((npts + ppb - 1) / ppb), 256, 0, st>>>(bs, C, npts,
-                                                                           S->d_anchor);
-    }
+    // a row of workgroups per instance, unless the rows' lengths are so
+    // uneven that the grid would be more than twice the points' blocks
+    const int64_t ppb = 256 / (dim == 2 ? anchor_lanes<2>() : anchor_lanes<3>());
+    int64_t rowb = 0;
+    for (int i = 0; i < n; ++i) rowb = std::max<int64_t>(rowb, (nq[i] + ppb - 1) / ppb);
+    const int64_t flat = (npts + ppb - 1) / ppb;
+    const dim3 grid = n > 1 && n <= 65535 && rowb * n <= 2 * flat
+                          ? dim3((unsigned)rowb, (unsigned)n)
+                          : dim3((unsigned)flat);
+    if (dim == 2)
+      k_batch_anchor<2><<<grid, 256, 0, st>>>(bs, C, npts, S->d_anchor);
+    else
+      k_batch_anchor<3><<<grid, 256, 0, st>>>(bs, C, npts, S->d_anchor);
     GCR_HIP(hipGetLastError());
   }
   double* Fo = F;
