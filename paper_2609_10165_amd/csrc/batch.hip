@@ -197,6 +197,14 @@ __device__ __forceinline__ void surface_item(const BStatic& S, const BCall& C, i
 // level's coupled units are solved as fill_unit_field solves them, so the
 // values are the same bits.  An epilogue stores the values into the field.
 constexpr int kRecWords = 5;
+
+// A load through a global-address-space pointer (the plan's and the
+// field's arrays are device memory): a flat load would also count against
+// the LDS wait counter that every LDS access of the sweep waits on.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
 constexpr int kRecUnitWS = 8;   // unit workspaces after the records
 constexpr uint32_t kRecFluid = 0xffffu, kRecSkip = 0xfffeu;
 constexpr uint64_t kRecMember = 1ull << 63;
@@ -237,15 +245,16 @@ __device__ __forceinline__ void sweep_lds2(const PlanD& P, const int32_t* __rest
   const int T = blockDim.x, tid = threadIdx.x;
   const int ng = P.ng;
   for (int p = tid; p < ng; p += T) {
-    const int c = P.cell[p];
-    const uint32_t code = P.code[p];
-    double dl[3] = {P.dl[0][p], P.dl[1][p], 0.0}, nn[3] = {P.nn[0][p], P.nn[1][p], 0.0}, w[8];
-    const bool member = P.blk[p] >= 0;
-    const int bc = kind == 2 ? (int)bt[p] : kind;
-    const double bv = b[p];
+    const int c = gload(P.cell + p);
+    const uint32_t code = gload(P.code + p);
+    double dl[3] = {gload(P.dl[0] + p), gload(P.dl[1] + p), 0.0},
+           nn[3] = {gload(P.nn[0] + p), gload(P.nn[1] + p), 0.0}, w[8];
+    const bool member = gload(P.blk + p) >= 0;
+    const int bc = kind == 2 ? (int)gload(bt + p) : kind;
+    const double bv = gload(b + p);
     int gi[4];
 #pragma unroll
-    for (int k = 1; k < 4; ++k) gi[k] = P.cgi[(int64_t)(k - 1) * ng + p];
+    for (int k = 1; k < 4; ++k) gi[k] = gload(P.cgi + (int64_t)(k - 1) * ng + p);
     double X[3];
     stencil_span(P.g, code, c, X);
     ghost_weights<2>(dl, nn, X, bc, w);
@@ -261,7 +270,7 @@ __device__ __forceinline__ void sweep_lds2(const PlanD& P, const int32_t* __rest
         t = w[k];
       } else if (gi[k] == -1) {
         id = kRecFluid;
-        t = w[k] * F[c + corner_offset(P.g, code, k)];
+        t = w[k] * gload(F + c + corner_offset(P.g, code, k));
       }
       r[k] = t;
       pk |= id << (16 * (k - 1));
@@ -269,31 +278,65 @@ __device__ __forceinline__ void sweep_lds2(const PlanD& P, const int32_t* __rest
     r[4] = __longlong_as_double((long long)pk);
   }
   __syncthreads();
+  // (read once: after a barrier every level would load it again)
+  const int nunits = P.nunits;
+  int unext = 0x7fffffff;
+  if (tid < kRecUnitWS)
+    for (int s = tid; s < nunits; s += kRecUnitWS) unext = min(unext, gload(P.unit_lev + s));
+  // level offsets 64 at a time, lane j holding lev_off[base + j]: a level
+  // reads its bounds from registers instead of memory
+  const int lane = tid & 63;
+  int vlev = 0, vnext = 0;
   for (int l = 0; l < nl; ++l) {
-    const int lo = lev_off[l], hi = lev_off[l + 1];
+    if ((l & 63) == 0) {
+      vlev = l + lane <= nl ? gload(lev_off + l + lane) : 0;
+      vnext = l + 64 <= nl ? gload(lev_off + l + 64) : 0;
+    }
+    const int lo = __builtin_amdgcn_readlane(vlev, l & 63);
+    const int hi = (l & 63) == 63 ? __builtin_amdgcn_readfirstlane(vnext)
+                                  : __builtin_amdgcn_readlane(vlev, (l & 63) + 1);
     for (int p = lo + tid; p < hi; p += T) {
+      // the record's words, then the three corners' ghost values, each
+      // group read at once; the terms are added in corner order as before
       double* r = rec + (int64_t)kRecWords * p;
-      const uint64_t pk = (uint64_t)__double_as_longlong(r[4]);
-      if (pk & kRecMember) continue;   // solved with its unit below
-      double v = r[0];
+      double w[kRecWords];
 #pragma unroll
-      for (int k = 1; k < 4; ++k) {
-        const uint32_t id = (uint32_t)(pk >> (16 * (k - 1))) & 0xffffu;
-        if (id == kRecSkip) continue;
-        v += id == kRecFluid ? r[k] : r[k] * rec[(int64_t)kRecWords * id];
+      for (int k = 0; k < kRecWords; ++k) w[k] = r[k];
+      const uint64_t pk = (uint64_t)__double_as_longlong(w[4]);
+      if (pk & kRecMember) continue;   // solved with its unit below
+      uint32_t id[3];
+      double gv[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        id[k] = (uint32_t)(pk >> (16 * k)) & 0xffffu;
+        gv[k] = rec[(int64_t)kRecWords * (id[k] < kRecSkip ? (int)id[k] : p)];
+      }
+      double v = w[0];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double t = id[k] == kRecFluid ? w[k + 1] : w[k + 1] * gv[k];
+        v = id[k] == kRecSkip ? v : v + t;
       }
       r[0] = v;
     }
     __syncthreads();
-    if (P.nunits) {
-      UnitWS* ws = reinterpret_cast<UnitWS*>(rec + (int64_t)kRecWords * rec_cap);
-      if (tid < kRecUnitWS)
-        for (int s = tid; s < P.nunits; s += kRecUnitWS)
-          if (P.unit_lev[s] == l + 1) unit_lds2(P, s, rec, ws[tid]);
+    if (nunits) {
+      // thread s < kRecUnitWS takes units s, s + kRecUnitWS, ...; unext is
+      // the lowest level among those not solved yet
+      if (unext == l + 1) {
+        UnitWS* ws = reinterpret_cast<UnitWS*>(rec + (int64_t)kRecWords * rec_cap);
+        unext = 0x7fffffff;
+        for (int s = tid; s < nunits; s += kRecUnitWS) {
+          const int ul = gload(P.unit_lev + s);
+          if (ul == l + 1) unit_lds2(P, s, rec, ws[tid]);
+          else if (ul > l + 1) unext = min(unext, ul);
+        }
+      }
       __syncthreads();
     }
   }
-  for (int p = tid; p < ng; p += T) F[P.cell[p]] = rec[(int64_t)kRecWords * p];
+  for (int p = tid; p < ng; p += T)
+    *(__attribute__((address_space(1))) double*)(F + gload(P.cell + p)) = rec[(int64_t)kRecWords * p];
   __syncthreads();
 }
 
