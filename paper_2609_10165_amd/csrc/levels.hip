@@ -458,7 +458,7 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
     // ---- at most 64 ghosts left (they read a cycle): one wave finds the
     // cycles and places them, with no workgroup barrier.  Lane u holds
     // residual ghost res[u] and the set A of residual ghosts it reads; the
-    // closure R = A+ comes from repeated squaring (R |= R o R), the group of
+    // closure R = A+ comes from Warshall's pass over its lanes, the group of
     // a ghost on a cycle (u in R[u]) is R[u] & {v : u in R[v]}, whose
     // smallest member is its representative, and the groups' slots follow
     // their representatives' order.  Then every residual ghost or group is
@@ -502,16 +502,15 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
           const int v = (int)find_sorted(res, 0, m, d);
           if (v >= 0) A |= 1ull << v;
         }
+      // closure R = A+ by Warshall's pass: after step v, R[u] holds every
+      // ghost u reaches through intermediates among the first v + 1; row v
+      // is read from its lane with readlane (v is uniform), no LDS
       unsigned long long R = A;
-      for (int it = 0; it < 7; ++it) {   // 2^7 > 64: paths of every length
-        unsigned long long Rn = R;
-        for (int v = 0; v < m; ++v) {
-          const unsigned long long Rv = __shfl(R, v);
-          if ((R >> v) & 1ull) Rn |= Rv;
-        }
-        const bool grew = Rn != R;
-        R = Rn;
-        if (__ballot(grew) == 0ull) break;
+      const int mu = __builtin_amdgcn_readfirstlane(m);   // (the same in every lane)
+      for (int v = 0; v < mu; ++v) {
+        const uint32_t rlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)R, v);
+        const uint32_t rhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(R >> 32), v);
+        if ((R >> v) & 1ull) R |= ((unsigned long long)rhi << 32) | rlo;
       }
       unsigned long long T = 0ull;   // {v : lane in R[v]}
       for (int u = 0; u < m; ++u) {
