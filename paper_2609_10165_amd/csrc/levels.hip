@@ -469,8 +469,7 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
     if (tid < 64) {
       const int lane = tid;
       int32_t* res = tab;          // [64] residual ghosts, ascending
-      int32_t* s_L = tab + 64;     // [64] their levels (0: not placed yet)
-      int32_t* s_c = tab + 128;    // [64] this round's candidates (-1: not ready)
+      int32_t* s_c = tab + 128;    // [64] the placement order
       int m = 0;
       for (int g0 = 0; g0 < n; g0 += 64) {
         const int g = g0 + lane;
@@ -479,7 +478,6 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
         if (left) res[m + __popcll(bm & ((1ull << lane) - 1ull))] = g;
         m += __popcll(bm);
       }
-      s_L[lane] = 0;
       __builtin_amdgcn_wave_barrier();
       // dependency q of ghost g as a local id, -1 if it reads no ghost there
       auto gdep = [&](int g, int q) -> int {
@@ -531,60 +529,39 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
         blk_idx[lo + g] = slot;
         if (rep == lane) unit_cnt[slot] = size;
       }
-      // placement rounds: a ghost (group) is ready once every residual ghost
-      // it reads outside its group is placed; each round places at least
-      // one.  The indices a lane reads each round sit in registers (at most
-      // np residual ghosts read, kMaxUnit group members), so a round's loads
-      // go out together.
-      int dv[7], mv[kMaxUnit];
-      {
-        unsigned long long w = A & ~M;   // read outside the lane's group
-#pragma unroll
-        for (int q = 0; q < 7; ++q) {
-          dv[q] = w ? __ffsll((long long)w) - 1 : -1;
-          w &= w ? w - 1ull : 0ull;
-        }
-        w = bad ? 0ull : M;
-#pragma unroll
-        for (int j = 0; j < kMaxUnit; ++j) {
-          mv[j] = w ? __ffsll((long long)w) - 1 : -1;
-          w &= w ? w - 1ull : 0ull;
-        }
-      }
+      // placement in dependency order, in one pass in registers.  Ghost u
+      // reading ghost w of another group has a larger key 2 |R[u]| + (u not
+      // on a cycle) than w: R[u] holds R[w], and u itself (u on a cycle) or
+      // w's own group (w on a cycle) or w (neither) besides.  So the order
+      // of (key, lane) places every group after all it reads; a group's
+      // members share R and sit together.  c: the highest level the lane
+      // reads outside its group (ext to start with), final when its group's
+      // turn comes; the group's level is 1 + the highest c of its members.
       int Lown = 0;
-      for (int round = 0; !bad && round <= m; ++round) {
-        int c = -1;
-        if (lane < m && Lown == 0) {
-          int lv[7];
-#pragma unroll
-          for (int q = 0; q < 7; ++q) lv[q] = dv[q] >= 0 ? s_L[dv[q]] : 1;
-          c = ext;
-#pragma unroll
-          for (int q = 0; q < 7; ++q)
-            if (dv[q] >= 0) c = (c < 0 || lv[q] == 0) ? -1 : max(c, lv[q]);
+      if (!bad) {
+        const int key = lane < m ? 2 * __popcll(R) + (oncyc ? 0 : 1) : 0x7fffffff;
+        int rank = 0;
+        for (int v = 0; v < mu; ++v) {
+          const int kv = __builtin_amdgcn_readlane(key, v);
+          rank += (kv < key || (kv == key && v < lane)) ? 1 : 0;
         }
-        s_c[lane] = c;
+        if (lane < m) s_c[rank] = lane;
         __builtin_amdgcn_wave_barrier();
-        int nl = 0;
-        if (lane < m && Lown == 0) {
-          int cw[kMaxUnit];
-#pragma unroll
-          for (int j = 0; j < kMaxUnit; ++j) cw[j] = mv[j] >= 0 ? s_c[mv[j]] : 0;
+        const int ord = lane < m ? s_c[lane] : 0;
+        const unsigned long long outside = A & ~M;
+        int c = ext;
+        for (int pos = 0; pos < mu; ++pos) {
+          const int v = __builtin_amdgcn_readlane(ord, pos);
+          if (__builtin_amdgcn_readlane(Lown, v) != 0) continue;   // placed with its group
+          const unsigned long long Mv =
+              ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(M >> 32), v) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)M, v);
           int mx = 0;
-          bool ok = true;
-#pragma unroll
-          for (int j = 0; j < kMaxUnit; ++j) {
-            ok = ok && cw[j] >= 0;
-            mx = max(mx, cw[j]);
-          }
-          if (ok) nl = mx + 1;
+          for (unsigned long long w = Mv; w; w &= w - 1ull)
+            mx = max(mx, __builtin_amdgcn_readlane(c, __ffsll((long long)w) - 1));
+          if ((Mv >> lane) & 1ull) Lown = mx + 1;
+          if (outside & Mv) c = max(c, mx + 1);
         }
-        if (nl) {
-          Lown = nl;
-          s_L[lane] = nl;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (__ballot(lane < m && Lown == 0) == 0ull) break;
       }
       if (bad) {
         if (lane == 0) s_bad = 1;
