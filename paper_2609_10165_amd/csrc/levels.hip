@@ -868,27 +868,27 @@ __global__ __launch_bounds__(1024) void k_levels_fast(LevelsArgs L, int lds_byte
   __syncthreads();
   int32_t* __restrict__ lev = L.lev + lo;
   int32_t* __restrict__ perm = L.perm + lo;
+  static_assert(kFastLevels <= 256, "a level index fits 8 ballots");
   for (int c = r0; c < r1; c += 64) {
     const int g = c + lane;
     const bool valid = g < r1;
     const int l = valid ? (int)lvl[g] - 1 : -1;
-    unsigned long long rem = __ballot(valid);
-    int pos = 0;
-    while (rem) {
-      const int leader = __ffsll((long long)rem) - 1;
-      const int l0 = __shfl(l, leader);
-      const bool same = valid && l == l0;
-      const unsigned long long mk = __ballot(same);
-      const int at = tab[wv * nlev + l0];
-      if (same) pos = at + __popcll(mk & ((1ull << lane) - 1ull));
-      __builtin_amdgcn_wave_barrier();
-      if (lane == leader) tab[wv * nlev + l0] = at + __popcll(mk);
-      __builtin_amdgcn_wave_barrier();
-      rem &= ~mk;
+    // the lanes of this lane's level: those that agree with it on every bit
+    // of the level index, one ballot a bit
+    unsigned long long mk = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (l >> bit) & 1;
+      const unsigned long long bb = __ballot(valid && on);
+      mk &= on ? bb : ~bb;
     }
+    const int at = valid ? tab[wv * nlev + l] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && lane == __ffsll((long long)mk) - 1) tab[wv * nlev + l] = at + __popcll(mk);
+    __builtin_amdgcn_wave_barrier();
     if (valid) {
       lev[g] = l + 1;
-      perm[g] = pos;
+      perm[g] = at + __popcll(mk & ((1ull << lane) - 1ull));
     }
   }
   int32_t* lev_off = L.lev_off + (int64_t)ii * (kMaxLevels + 1);
