@@ -2,6 +2,8 @@
 shared launches, and the persistent batched forward (fill of several fields
 with mixed Dirichlet/Neumann data + force), against the oracle per instance
 and against the single-instance path."""
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 
@@ -100,6 +102,57 @@ def test_batch_forward_matches_oracle(gcr):
         Fo = op.forces(q.x, q.n, q.w, want[2], want[:2], 0.9)
         cs = op.cell_scale(np.nan_to_num(want), sc)
         check(host(F[i])[:2], Fo, force_scale(op, q, want, cs, 2, [0, 1], 0.9), f"force {i}")
+
+
+def test_batch_forward_uneven_points(gcr):
+    """Surface points spread unevenly over the instances (256, 8, 0, 24, 8,
+    8: the anchor search runs as one row of workgroups, each point finding
+    its instance) and evenly (24 each: a row of workgroups per instance).
+    Surface values, gradients and forces against the oracle's at 1e-12 of
+    its propagated scales, both times."""
+    insts = synth.stars64(seed=3, ninst=6, nmin=96, nmax=400)
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
+    nf, mu = 3, 0.8
+    ops, fields, bcv, bct, wants = [], [], [], [], []
+    for inst in insts:
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        ops.append(op)
+        S = ghost_centres(op) + op.delta
+        kinds = np.stack([synth.mixed_kinds(S, inst.shape.center, b) for b in inst.mixed_beta])
+        vals = np.stack([synth.sample(f, inst.grid) for f in inst.fields])
+        vals[:, op.tags != 0] = np.nan
+        b = np.stack([synth.bc_values(f, S, op.normal, k) for f, k in zip(inst.fields, kinds)])
+        want = op.fill(vals.copy(), kinds, b)
+        sc = op.fill_scale(np.nan_to_num(vals), kinds, b)
+        wants.append((want, op.cell_scale(np.nan_to_num(want), sc)))
+        for f in range(nf):
+            fields.append(dev(vals[f]))
+            bcv.append(dev(b[f]))
+            bct.append(dev(kinds[f], torch.uint8))
+    for counts in ([256, 8, 0, 24, 8, 8], [24] * 6):
+        qs = [(i.queries.x[:, :k], i.queries.n[:, :k], i.queries.w[:k]) for i, k in zip(insts, counts)]
+        F = torch.zeros((len(insts), 3), dtype=torch.float64, device="cuda")
+        sv = [torch.empty(k, dtype=torch.float64, device="cuda") for k in counts for _ in range(nf)]
+        sg = [torch.empty((2, k), dtype=torch.float64, device="cuda") for k in counts for _ in range(nf)]
+        B.forward(nf, fields, [2, 2, 2], bcv, bc_type=bct, nq=counts,
+                  xq=[dev(x) for x, _, _ in qs], nrm=[dev(n) for _, n, _ in qs],
+                  wq=[dev(w) for _, _, w in qs], p_field=2, u_first=0, mu=mu, F=F,
+                  sval=sv, sgrad=sg)
+        torch.cuda.synchronize()
+        for i, (op, (want, cs)) in enumerate(zip(ops, wants)):
+            x, n, w = qs[i]
+            if counts[i] == 0:
+                assert np.all(host(F[i]) == 0), (counts, i)
+                continue
+            ov, og, oanc, osc = op.surface_query(x, want, field_scale=cs)
+            bv = np.stack([host(sv[i * nf + f]) for f in range(nf)])
+            bg = np.stack([host(sg[i * nf + f]) for f in range(nf)])
+            check(bv, ov, osc[:, 0], f"{counts} surface values {i}")
+            check(bg, og, osc[:, 1:], f"{counts} surface gradients {i}")
+            Fo = op.forces(x, n, w, want[2], want[:2], mu)
+            q = SimpleNamespace(x=x, n=n, w=w)
+            check(host(F[i])[:2], Fo, force_scale(op, q, want, cs, 2, [0, 1], mu),
+                  f"{counts} force {i}")
 
 
 def test_batch_forward_full_size(gcr):
