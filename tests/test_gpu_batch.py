@@ -88,8 +88,12 @@ def test_batch_plans_match_single_plans(gcr):
         assert bp.level_offsets() == sp.level_offsets()
 
 
-def test_batch_forward_matches_oracle(gcr):
-    insts = synth.stars64(seed=6, ninst=8, nmin=96, nmax=500)
+@pytest.mark.parametrize("seed,ninst", [(6, 8), (9, 11)])
+def test_batch_forward_matches_oracle(gcr, seed, ninst):
+    """Fills and forces of every instance against the oracle.  With 11
+    instances the launch's item order places eight instances' field items
+    8 workgroups apart and leaves the last three in place."""
+    insts = synth.stars64(seed=seed, ninst=ninst, nmin=96, nmax=500)
     B, ops, fields, wants, F = run_batch(gcr, insts)
     nf = 3
     for i, (op, (want, sc)) in enumerate(zip(ops, wants)):
