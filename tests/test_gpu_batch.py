@@ -611,17 +611,24 @@ def _bits(t):
     return t.contiguous().view(torch.int64)
 
 
-@pytest.mark.parametrize("case", ["spheres", "units", "single"])
+@pytest.mark.parametrize("case", ["spheres", "units", "single", "deep"])
 def test_batch_split_sweep_equals_per_item(gcr, case):
     """The split level sweep (several workgroups per instance meeting at a
     device-scope counter between levels) against the per-item sweep: the
     same field values bit for bit, and the same force, surface values and
     gradients bit for bit at the same workgroup size; over several
     workgroups per instance, up to the largest grid allowed, with coupled
-    units in the 'units' case.  Each launch shape is run twice in a row, so
-    both sets of level counters are used."""
+    units in the 'units' case.  In the 'deep' case (a 2D airfoil of more
+    than 64 levels) the per-item sweep runs from LDS records and reloads its
+    level offsets past level 64.  Each launch shape is run twice in a row,
+    so both sets of level counters are used."""
     from synth import CGC, CGC_ES
-    if case == "single":
+    if case == "deep":
+        inst = synth.airfoil4096(seed=0)
+        grids, shapes, schemes = [inst.grid], [inst.shape], [HGC]
+        kinds = [0, 0, 1]
+        qs = [inst.queries]
+    elif case == "single":
         inst = synth.sphere256(seed=0)
         grids, shapes, schemes = [inst.grid], [inst.shape], [HGC]
         kinds = [f.bc for f in inst.fields]
@@ -644,6 +651,8 @@ def test_batch_split_sweep_equals_per_item(gcr, case):
         B = gcr.Batch(grids, shapes, schemes)
         if case == "units":
             assert any(p.stats()["n_units_coupled"] > 0 for p in B.plans)
+        if case == "deep":
+            assert len(B.plans[0].level_offsets()) - 1 > 64 and B.plans[0].n_ghost < 3968
         rng = np.random.default_rng(17)
         clean, bcv = [], []
         for g, p in zip(grids, B.plans):
