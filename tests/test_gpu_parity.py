@@ -611,3 +611,25 @@ def test_cycle_remainder_wave_and_workgroup_agree(gcr, which):
     assert sa["n_units_coupled"] >= 1 or op.n_units_coupled == 0
     with pytest.raises(gcr.GcrError):
         gcr.set_wave_residual(65)
+
+
+def test_canonical_order_of_a_deep_plan(gcr):
+    """The canonical ghost order, level then linear index, on a plan deeper
+    than 128 levels (the airfoil on a 7168^2 grid: 141 levels, the thin
+    trailing edge being a long dependency chain), so that a ghost's rank
+    among those of its level uses every bit of the level index: levels
+    ascend, cells ascend within a level, and the level offsets count them."""
+    inst = synth.airfoil4096(seed=0, n=7168)
+    p = gcr.Plan(inst.grid, inst.shape, HGC)
+    ex = p.export(("cell", "level"))
+    torch.cuda.synchronize()
+    lev = ex["level"].cpu().numpy().astype(np.int64)
+    cell = ex["cell"].cpu().numpy().astype(np.int64)
+    off = np.asarray(p.level_offsets())
+    nl = len(off) - 1
+    print(f"airfoil n=7168: {cell.size} ghosts, {nl} levels", flush=True)
+    assert 128 < nl <= 256
+    assert lev[0] == 1 and np.all(np.diff(lev) >= 0)
+    same = np.diff(lev) == 0
+    assert np.all(np.diff(cell)[same] > 0)
+    assert np.array_equal(np.searchsorted(lev, np.arange(1, nl + 2)), off)
