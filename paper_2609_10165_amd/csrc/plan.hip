@@ -32,14 +32,20 @@ namespace gcr {
 // closest point and normal
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void naca_point(double t, double s, double C[2], double D[2]) {
+// The contour point C(s) = (s^2, +-y_t(s^2)) (s >= 0 upper, s < 0 lower
+// surface), its derivative D and second derivative E in s.
+__device__ __forceinline__ void naca_point(double t, double s, double C[2], double D[2],
+                                           double E[2]) {
   double s2 = s * s, sg = s < 0.0 ? -1.0 : 1.0;
   double poly = 0.1260 * s2 + 0.3516 * s2 * s2 - 0.2843 * s2 * s2 * s2 + 0.1036 * s2 * s2 * s2 * s2;
   double dpoly = s * (2.0 * 0.1260 + s2 * (4.0 * 0.3516 + s2 * (-6.0 * 0.2843 + s2 * 8.0 * 0.1036)));
+  double d2poly = 2.0 * 0.1260 + s2 * (12.0 * 0.3516 + s2 * (-30.0 * 0.2843 + s2 * 56.0 * 0.1036));
   C[0] = s2;
   C[1] = 5.0 * t * (0.2969 * s - sg * poly);
   D[0] = 2.0 * s;
   D[1] = 5.0 * t * (0.2969 - sg * dpoly);
+  E[0] = 2.0;
+  E[1] = -5.0 * t * sg * d2poly;
 }
 
 __device__ bool project(const ShapeD& s, int dim, const double x[3], bool solid, double n[3],
@@ -194,27 +200,32 @@ __device__ bool project(const ShapeD& s, int dim, const double x[3], bool solid,
       double sv = br == 0 ? sp : -sp;
       if (sv == 0.0) sv = br == 0 ? 1e-3 : -1e-3;
       double last = 1.0;
-      // Gauss-Newton on the contour parameter, clamped to the branch
+      // Newton on the squared distance along the contour parameter, clamped
+      // to the branch; the Gauss-Newton step where the curvature term makes
+      // the second derivative non-positive
       for (int it = 0; it < 200 && last > 1e-15; ++it) {
-        double C[2], D[2];
-        naca_point(s.thick, sv, C, D);
-        double ds = -((C[0] - b0) * D[0] + (C[1] - b1) * D[1]) / (D[0] * D[0] + D[1] * D[1]);
-        double ns = sv + ds;
+        double C[2], D[2], E[2];
+        naca_point(s.thick, sv, C, D, E);
+        const double r0 = C[0] - b0, r1 = C[1] - b1;
+        const double dd = D[0] * D[0] + D[1] * D[1];
+        double h = dd + r0 * E[0] + r1 * E[1];
+        if (!(h > 0.0)) h = dd;
+        double ns = sv - (r0 * D[0] + r1 * D[1]) / h;
         ns = ns < lo ? lo : (ns > hi ? hi : ns);
         last = fabs(ns - sv);
         sv = ns;
       }
       if (last > 1e-12) ok = false;
-      double C[2], D[2];
-      naca_point(s.thick, sv, C, D);
+      double C[2], D[2], E[2];
+      naca_point(s.thick, sv, C, D, E);
       double d2 = (C[0] - b0) * (C[0] - b0) + (C[1] - b1) * (C[1] - b1);
       if (d2 < best) {
         best = d2;
         bs = sv;
       }
     }
-    double C[2], D[2], nb[2];
-    naca_point(s.thick, bs, C, D);
+    double C[2], D[2], E[2], nb[2];
+    naca_point(s.thick, bs, C, D, E);
     if (fabs(bs) >= 1.0) {
       // trailing-edge corner: the normal is the direction from the corner
       double e0 = b0 - C[0], e1 = b1 - C[1];

@@ -187,6 +187,18 @@ def test_plan_airfoil(gcr):
     check_plan(op, gp)
 
 
+@pytest.mark.parametrize("n", [5120, 8192])
+def test_plan_airfoil_fine_grids(gcr, n):
+    """The airfoil on grids where a first-order (Gauss-Newton) projection
+    along the contour had not converged in its iteration limit for some
+    cells: the plan against the oracle's (tags, ghost order and levels bit
+    for bit, foot points and normals within tolerance)."""
+    inst = synth.airfoil4096(seed=0, n=n, m=64)
+    op, gp = plan_pair(gcr, inst, HGC)
+    assert op.min_margin > 1e-9
+    check_plan(op, gp)
+
+
 @pytest.fixture(params=[0, 1])
 def wide(gcr, request):
     # every plan built alone is layered grid-wide; with a release buffer of
