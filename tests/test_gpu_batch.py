@@ -108,6 +108,27 @@ def test_batch_forward_matches_oracle(gcr, seed, ninst):
         check(host(F[i])[:2], Fo, force_scale(op, q, want, cs, 2, [0, 1], 0.9), f"force {i}")
 
 
+def test_batch_forward_plan_beyond_lds_records(gcr):
+    """A 2D batch whose largest plan (a star on 4096^2, about 4,300 ghosts)
+    has more ghosts than a workgroup's LDS holds records for: its items
+    sweep their levels from HBM, one ghost per thread.  Fills and forces of
+    every instance against the oracle."""
+    insts = synth.stars64(seed=0, ninst=1, nmin=4096, nmax=4096) + \
+        synth.stars64(seed=2, ninst=2, nmin=96, nmax=300)
+    B, ops, fields, wants, F = run_batch(gcr, insts)
+    assert ops[0].n_ghost > 3968
+    nf = 3
+    for i, (op, (want, sc)) in enumerate(zip(ops, wants)):
+        for f in range(nf):
+            got = host(fields[i * nf + f])
+            err = np.abs(got[op.ghost_cell] - want[f][op.ghost_cell])
+            assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][op.ghost_cell]), sc[f])), (i, f)
+        q = insts[i].queries
+        Fo = op.forces(q.x, q.n, q.w, want[2], want[:2], 0.9)
+        cs = op.cell_scale(np.nan_to_num(want), sc)
+        check(host(F[i])[:2], Fo, force_scale(op, q, want, cs, 2, [0, 1], 0.9), f"force {i}")
+
+
 def test_batch_forward_uneven_points(gcr):
     """Surface points spread unevenly over the instances (256, 8, 0, 24, 8,
     8: the anchor search runs as one row of workgroups, each point finding
