@@ -342,6 +342,10 @@ gcr_status gcr_batch_foot_points(const gcr_batch* batch, double* S, double* norm
  * (pressure) and the dim fields u_first.. (velocity).  Host arrays of device
  * pointers are instance-major, [ninst * nf]:
  *   fields, bc_val, bc_type (bc_type may be NULL);  bc_kind host [nf].
+ *   An instance whose plan has no ghosts reads no boundary data: its
+ *   bc_val (and bc_type) entries may be NULL; every other NULL entry of
+ *   fields, bc_val, or bc_type where its field's kind is GCR_MIXED, is
+ *   GCR_E_ARG.
  *   nq host int64 [ninst]; xq, nrm, wq host [ninst] device pointers;
  *   F device f64 [ninst][3] (unused components zero).
  * Surface values (Sec. 6) of the filled fields at the same points, as

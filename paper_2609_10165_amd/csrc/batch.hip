@@ -1344,8 +1344,10 @@ extern "C" gcr_status gcr_batch_forward(gcr_batch* batch, int32_t nf, double* co
   for (int f = 0; f < nf; ++f)
     if (bc_kind[f] < 0 || bc_kind[f] > 2) return GCR_E_ARG;
   for (int w = 0; w < n * nf; ++w) {
-    if (!fields[w] || !bc_val[w]) return GCR_E_ARG;
-    if (bc_kind[w % nf] == GCR_MIXED && (!bc_type || !bc_type[w])) return GCR_E_ARG;
+    // (a plan without ghosts reads no boundary data)
+    const bool reads_bc = batch->plans[w / nf]->ng > 0;
+    if (!fields[w] || (reads_bc && !bc_val[w])) return GCR_E_ARG;
+    if (reads_bc && bc_kind[w % nf] == GCR_MIXED && (!bc_type || !bc_type[w])) return GCR_E_ARG;
   }
   if ((sval || sgrad) && !nq) return GCR_E_ARG;
   if (nq) {

@@ -355,6 +355,63 @@ def test_batch_forward_with_coupled_units(gcr):
             assert np.all(err <= 1e-12 * np.maximum(np.abs(want[f][c]), sc[f])), (i, f)
 
 
+def test_batch_forward_with_an_empty_plan(gcr):
+    """The batched forward over instances of which one has no ghosts (its
+    body far outside its grid) and one sits on a stretched grid: the other
+    instances' fills and forces against the oracle, the empty one's field
+    untouched and its force zero."""
+    insts = synth.stars64(seed=4, ninst=2, nmin=96, nmax=300) + [synth.circle_stretched(seed=1)]
+    grids = [i.grid for i in insts]
+    shapes = [i.shape for i in insts]
+    grids.insert(1, synth.Grid(2, (40, 33, 1), (0.0, 0.0, 0.0), (0.1, 0.1, 1.0)))
+    shapes.insert(1, synth.Shape(synth.SPHERE, (50.0, 50.0, 0.0), 1.0))
+    B = gcr.Batch(grids, shapes, [HGC] * len(grids))
+    assert B.plans[1].n_ghost == 0
+    nf, mu = 3, 0.6
+    rng = np.random.default_rng(5)
+    ops, fields, bcv, wants, qs, before = [], [], [], [], [], []
+    for k, (grid, shape) in enumerate(zip(grids, shapes)):
+        op = oracle.OraclePlan(grid, shape, HGC)
+        ops.append(op)
+        vals = rng.standard_normal((nf, op.n_cells))
+        vals[:, op.tags != 0] = np.nan
+        b = rng.standard_normal((nf, op.n_ghost))
+        kinds = np.zeros((nf, op.n_ghost), np.int8)
+        kinds[1] = 1
+        if op.n_ghost:
+            want = op.fill(vals.copy(), kinds, b)
+            sc = op.fill_scale(np.nan_to_num(vals), kinds, b)
+            wants.append((want, op.cell_scale(np.nan_to_num(want), sc), sc))
+        else:
+            wants.append(None)
+        before.append(vals)
+        for f in range(nf):
+            fields.append(dev(vals[f]))
+            bcv.append(dev(b[f]))
+        # (the empty instance gets no surface points)
+        q = insts[k if k < 1 else k - 1].queries
+        qs.append(q if op.n_ghost else SimpleNamespace(x=q.x[:, :0], n=q.n[:, :0], w=q.w[:0]))
+    F = torch.full((len(grids), 3), 7.0, dtype=torch.float64, device="cuda")
+    B.forward(nf, fields, [0, 1, 0], bcv, nq=[q.x.shape[1] for q in qs],
+              xq=[dev(q.x) for q in qs], nrm=[dev(q.n) for q in qs], wq=[dev(q.w) for q in qs],
+              p_field=2, u_first=0, mu=mu, F=F)
+    torch.cuda.synchronize()
+    for k, op in enumerate(ops):
+        got = np.stack([host(fields[k * nf + f]) for f in range(nf)])
+        if wants[k] is None:
+            assert np.array_equal(np.isnan(got), np.isnan(before[k]))
+            assert np.array_equal(np.nan_to_num(got), np.nan_to_num(before[k]))
+            assert np.all(host(F[k]) == 0), k
+            continue
+        want, cs, sc = wants[k]
+        c = op.ghost_cell
+        for f in range(nf):
+            check(got[f][c], want[f][c], sc[f], f"fill {k} field {f}")
+        q = qs[k]
+        Fo = op.forces(q.x, q.n, q.w, want[2], want[:2], mu)
+        check(host(F[k])[:2], Fo, force_scale(op, q, want, cs, 2, [0, 1], mu), f"force {k}")
+
+
 def test_batch_foot_points(gcr):
     """gcr_batch_foot_points: the instances' foot points and normals one
     after another, bitwise equal to each plan's own gcr_plan_foot_points and
