@@ -229,7 +229,10 @@ gcr_status gcr_set_schedule(gcr_plan* plan, int32_t schedule, int32_t param);
  *   bc_type  host array [nf] of device uint8 [n_ghost] (0/1), read only for
  *            fields with GCR_MIXED; may be NULL if no field is mixed.
  *   bc_val   host array [nf] of device f64 [n_ghost]: phi at S (Dirichlet) or
- *            dphi/dn at S (Neumann), canonical ghost order. */
+ *            dphi/dn at S (Neumann), canonical ghost order.
+ * A plan with no ghosts reads no boundary data: its bc_val and bc_type
+ * entries may be NULL.  Otherwise a NULL field, bc_val, or bc_type of a
+ * GCR_MIXED field, is GCR_E_ARG. */
 gcr_status gcr_fill(const gcr_plan* plan, int32_t nf, double* const* fields,
                     const int32_t* bc_kind, const uint8_t* const* bc_type,
                     const double* const* bc_val, void* stream);

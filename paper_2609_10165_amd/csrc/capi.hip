@@ -360,19 +360,21 @@ static bool check_fields(int32_t nf, const void* const* f) {
 static gcr_status make_fill_args(const gcr_plan* p, int32_t nf, double* const* fields,
                                  const int32_t* bc_kind, const uint8_t* const* bc_type,
                                  const double* const* bc_val, FillArgs* A) {
-  if (!check_fields(nf, (const void* const*)fields) || !bc_kind ||
-      !check_fields(nf, (const void* const*)bc_val))
+  // (a plan without ghosts reads no boundary data)
+  const bool reads_bc = p->ng > 0;
+  if (!check_fields(nf, (const void* const*)fields) || !bc_kind || (reads_bc && !bc_val) ||
+      (reads_bc && !check_fields(nf, (const void* const*)bc_val)))
     return GCR_E_ARG;
   std::memset(A, 0, sizeof(FillArgs));
   A->P = plan_view(p);
   A->nf = nf;
   for (int f = 0; f < nf; ++f) {
     if (bc_kind[f] < 0 || bc_kind[f] > 2) return GCR_E_ARG;
-    if (bc_kind[f] == GCR_MIXED && (!bc_type || !bc_type[f])) return GCR_E_ARG;
+    if (reads_bc && bc_kind[f] == GCR_MIXED && (!bc_type || !bc_type[f])) return GCR_E_ARG;
     A->kind[f] = bc_kind[f];
     A->f[f] = fields[f];
-    A->b[f] = bc_val[f];
-    A->bt[f] = bc_kind[f] == GCR_MIXED ? bc_type[f] : nullptr;
+    A->b[f] = bc_val ? bc_val[f] : nullptr;
+    A->bt[f] = bc_kind[f] == GCR_MIXED && bc_type ? bc_type[f] : nullptr;
   }
   return GCR_OK;
 }

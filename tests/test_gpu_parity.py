@@ -645,3 +645,20 @@ def test_canonical_order_of_a_deep_plan(gcr):
     same = np.diff(lev) == 0
     assert np.all(np.diff(cell)[same] > 0)
     assert np.array_equal(np.searchsorted(lev, np.arange(1, nl + 2)), off)
+
+
+def test_fill_of_a_plan_without_ghosts(gcr):
+    """A body far outside its grid: no ghosts, no levels.  Its fill reads no
+    boundary data (zero-size tensors, null pointers, are accepted) and
+    leaves the field as it was."""
+    grid = synth.Grid(2, (40, 33, 1), (0.0, 0.0, 0.0), (0.1, 0.1, 1.0))
+    shape = synth.Shape(synth.SPHERE, (50.0, 50.0, 0.0), 1.0)
+    p = gcr.Plan(grid, shape, HGC)
+    assert p.n_ghost == 0 and p.level_offsets() == [0]
+    u = torch.as_tensor(np.random.default_rng(3).standard_normal(40 * 33), device="cuda")
+    before = u.clone()
+    empty = torch.empty(0, dtype=torch.float64, device="cuda")
+    p.fill([u], [DIRICHLET], [empty])
+    p.fill([u], [2], [empty], bc_type=[torch.empty(0, dtype=torch.uint8, device="cuda")])
+    torch.cuda.synchronize()
+    assert torch.equal(u, before)
