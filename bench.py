@@ -458,8 +458,15 @@ def measure_batched(gcr, torch, W, args, s_fwd, s_builds, extra=True):
     W.capture()
     nbuild = args.build_threads
     W.grow_pools(s_builds[0])
+    # pipelined warm-up steps, for at least 0.3 s: the first process on a
+    # fresh machine runs its host code slowly at first (pages of the
+    # libraries still coming in), which a few steps do not cover
+    w0 = time.perf_counter()
     W.run_threads(4 + 2 * nbuild, s_fwd, s_builds, nbuild)
     torch.cuda.synchronize()
+    while time.perf_counter() - w0 < 0.3:
+        W.run_threads(16, s_fwd, s_builds, nbuild)
+        torch.cuda.synchronize()
     # the warm-ups have grown the pools to the pipeline's depth; objects made
     # so far are frozen out of the cycle collector's scans (a full scan of
     # torch's objects costs milliseconds), as a long-running solver would
