@@ -129,6 +129,37 @@ def test_batch_forward_plan_beyond_lds_records(gcr):
         check(host(F[i])[:2], Fo, force_scale(op, q, want, cs, 2, [0, 1], 0.9), f"force {i}")
 
 
+def test_batch_forward_eight_fields(gcr):
+    """The most fields a call takes (8) over 9 instances: the launch's item
+    order places eight instances' 8 field items 8 workgroups apart and
+    leaves the ninth instance's in place.  Dirichlet and Neumann fields in
+    turn, no force; every fill against the oracle."""
+    insts = synth.stars64(seed=11, ninst=9, nmin=96, nmax=260)
+    B = gcr.Batch([i.grid for i in insts], [i.shape for i in insts], [HGC] * len(insts))
+    nf = 8
+    kinds = [f % 2 for f in range(nf)]
+    rng = np.random.default_rng(8)
+    ops, fields, bcv, wants = [], [], [], []
+    for inst in insts:
+        op = oracle.OraclePlan(inst.grid, inst.shape, HGC)
+        ops.append(op)
+        vals = rng.standard_normal((nf, op.n_cells))
+        vals[:, op.tags != 0] = np.nan
+        b = rng.standard_normal((nf, op.n_ghost))
+        kk = np.repeat(np.asarray(kinds, np.int8)[:, None], op.n_ghost, axis=1)
+        wants.append((op.fill(vals.copy(), kk, b), op.fill_scale(np.nan_to_num(vals), kk, b)))
+        for f in range(nf):
+            fields.append(dev(vals[f]))
+            bcv.append(dev(b[f]))
+    B.forward(nf, fields, kinds, bcv)
+    torch.cuda.synchronize()
+    for i, (op, (want, sc)) in enumerate(zip(ops, wants)):
+        c = op.ghost_cell
+        for f in range(nf):
+            got = host(fields[i * nf + f])
+            check(got[c], want[f][c], sc[f], f"instance {i} field {f}")
+
+
 def test_batch_forward_uneven_points(gcr):
     """Surface points spread unevenly over the instances (256, 8, 0, 24, 8,
     8: the anchor search runs as one row of workgroups, each point finding
